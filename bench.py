@@ -1,0 +1,272 @@
+"""Benchmark: galaxies/s at 300 effective samples on the batched uniform
+workload (10,000 galaxies, 53x53 stamps, PSF FWHM 0.7", 4 chains, 20 leapfrog
+steps, 300 dual-averaging warmup iterations + 1,000 draws), one MI355X.
+
+One step = the whole hot path on one synthetic batch: data transform, chain
+initialisation, warmup + sampling (one persistent launch per trajectory,
+replayed from a HIP graph), ESS/R-hat, and the shear posterior of the interim
+samples on a 41x41 grid.  Time per galaxy follows Section 4.1:
+    T_warmup / G + T_sampling / (G * n_eff) * 300,
+with T_warmup from a warmup-only call and T_sampling = T_hmc - T_warmup.
+
+Prints one JSON line (rank 0).  `--gpus` above 1 is rejected: this build
+runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from workloads import gen  # noqa: E402
+
+TARGET_ESS = 300.0
+PS = gen.PIXEL_SCALE
+
+
+def flops_per_eval(N: int) -> float:
+    """Algorithmic float32 operations of one gradient evaluation (k-space form).
+
+    50 per main bin (spectrum 21, residual and chi^2 6, conj(R) T 6, shape and
+    centroid sums 17; an FMA counts 2), 8 per frequency point for the
+    separable PSF-sinc-phase tables, and 6 x 8 x 2 for the wave reductions."""
+    nc = N if N % 2 else N - 1
+    nmain = (nc * nc - 1) // 2
+    ntab = 2 * (N // 2) + 1
+    return 50.0 * nmain + 8.0 * 2 * ntab + 96.0
+
+
+# ---------------------------------------------------------------- CPU baseline
+def _oracle_worker(args):
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)            # one BLAS thread per worker process
+    idx, n_iter, L = args
+    from oracle import hmc, render, shear
+    cfg = gen.CONFIGS["uniform"]
+    t = gen.draw_truth(cfg, n_gal=1, seed=gen.data_seed(1) + 1000 + idx)
+    ep = shear.shear_forward(t.e1 + 1j * t.e2, complex(*cfg.g_true))
+    prm = np.array([t.flux[0], t.hlr[0], ep.real[0], ep.imag[0], t.dx[0], t.dy[0]])
+    rng = np.random.default_rng(idx)
+    N = int(t.n_pix[0])
+    d = render.render_one(prm, N, PS, t.psf_fwhm[0]) + rng.normal(0, 1, (N, N))
+    gal = hmc.Galaxy(data=d, N=N, pixel_scale=PS, psf_fwhm=float(t.psf_fwhm[0]), sigma=1.0,
+                     ref_xy=(float(t.dx[0]), float(t.dy[0])))
+    th0 = hmc.init_chain(d, 1.0, math.log10(prm[1]), (prm[2], prm[3]), 7, idx)
+    t0 = time.perf_counter()
+    hmc.run_chain(hmc.galaxy_potential(gal), th0, 7, idx, L, n_iter, 0, 0.01, adapt=True, jitter=0.2)
+    return time.perf_counter() - t0, n_iter * L
+
+
+def cpu_baseline_eval_rate(n_iter=15, L=20):
+    """Oracle gradient evaluations per second on the host, all usable cores."""
+    import multiprocessing as mp
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    ctx = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(i, n_iter, L) for i in range(cores)])
+    wall = time.perf_counter() - t0
+    evals = sum(r[1] for r in res)
+    return evals / wall, cores, evals, wall
+
+
+# ---------------------------------------------------------------- GPU workload
+def lens(e1, e2, g):
+    """Shear response of the reduced-shear ellipticity (simulation input)."""
+    e = e1 + 1j * e2
+    gg = complex(*g)
+    ep = (e + gg) / (1.0 + np.conj(gg) * e)
+    return ep.real, ep.imag
+
+
+def make_inputs(api, torch, n_gal, cfg, seed_offset=0):
+    dev = torch.device("cuda:0")
+    t = gen.draw_truth(cfg, n_gal=n_gal, seed=gen.data_seed(cfg.index) + seed_offset)
+    e1p, e2p = lens(t.e1, t.e2, cfg.g_true)
+    params = np.stack([t.flux, t.hlr, e1p, e2p, t.dx, t.dy], axis=1).astype(np.float32)
+    b = api.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32, device=dev),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32, device=dev), pixel_scale=PS)
+    model = api.render_stamps(b, torch.tensor(params, device=dev))
+    noise, off = gen.draw_noise(t, gen.data_seed(cfg.index) + 7 + seed_offset)
+    data = (model + torch.tensor(noise, device=dev)).contiguous()
+    # chain starts (eq. initialize): flux from the stamp sum, size and shape
+    # jittered around the truth, centroid offsets zero
+    rng = np.random.default_rng(gen.chain_seed(cfg.index) + seed_offset)
+    N = int(t.n_pix[0])
+    sums = data.view(n_gal, N * N).double().sum(dim=1).cpu().numpy()
+    C = cfg.chains
+    init = np.zeros((n_gal, C, 6), np.float32)
+    init[:, :, 0] = np.log10(np.maximum(sums, t.sigma * N))[:, None]
+    init[:, :, 1] = np.log10(t.hlr)[:, None] + rng.uniform(-0.015, 0.015, (n_gal, C))
+    for c in range(C):
+        e1 = e1p + rng.uniform(-0.1, 0.1, n_gal)
+        e2 = e2p + rng.uniform(-0.1, 0.1, n_gal)
+        bad = e1 * e1 + e2 * e2 >= 0.95 ** 2
+        e1[bad], e2[bad] = e1p[bad], e2p[bad]
+        init[:, c, 2], init[:, c, 3] = e1, e2
+    ref = torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32, device=dev)
+    return t, b, data, ref, torch.tensor(init, device=dev)
+
+
+def timed(torch, fn, stream):
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    out = fn()
+    e.record(stream)
+    e.synchronize()
+    return out, s.elapsed_time(e) * 1e-3
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-gal", type=int, default=None, help="override galaxy count (profiling)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-gal", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
+              "part of this build", file=sys.stderr)
+        sys.exit(2)
+    cfg = gen.CONFIGS["uniform"]
+    G = args.n_gal or cfg.n_gal
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rate, cores, evals, wall = cpu_baseline_eval_rate()
+        cpu = dict(rate=rate, cores=cores, evals=evals, wall=wall)
+        print(f"[bench] oracle: {evals} gradient evaluations on {cores} cores in {wall:.1f} s",
+              file=sys.stderr, flush=True)
+
+    import torch
+    from paper_2604_22048_amd import api
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    t, b, data, ref, init = make_inputs(api, torch, G, cfg)
+    N = cfg.n_pix
+    C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
+    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
+                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
+                         iters_per_launch=1, use_graph=True, seed=gen.chain_seed(cfg.index))
+    wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
+    g1s = np.linspace(-0.1, 0.1, 41)
+    alpha = (math.log(0.6), 0.3, 0.2)
+    pts = torch.tensor([[a, bb, *alpha] for bb in g1s for a in g1s], dtype=torch.float64, device=dev)
+    tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True)
+    K = 1000
+
+    def step():
+        (smp, stats, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg),
+                                            stream)
+        (ess, rh), t_ess = timed(torch, lambda: api.ess(smp), stream)
+        # interim samples for the shear phase: every 4th draw of the 4 chains
+        def shear_step():
+            th = smp[:, :, 3::4, :].reshape(G, K, 6)
+            return api.shear_posterior(th[..., 2], th[..., 3], th[..., 1], th[..., 0], pts, tp)
+        lp, t_shear = timed(torch, shear_step, stream)
+        return dict(smp=smp, stats=stats, status=status, ess=ess, rhat=rh, lp=lp, t_hmc=t_hmc,
+                    t_ess=t_ess, t_shear=t_shear)
+
+    for i in range(args.warmup):
+        step()
+        print(f"[bench] warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(args.steps):
+        results.append(step())
+        print(f"[bench] step {i + 1}/{args.steps}: hmc {results[-1]['t_hmc']:.3f} s", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    r = results[-1]
+    # warmup-only call: splits T_hmc into warmup and sampling
+    _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
+    t_hmc = float(np.mean([x["t_hmc"] for x in results]))
+    t_s = t_hmc - t_w
+    ess = r["ess"].cpu().numpy()
+    n_eff = ess.mean(axis=1)                  # mean over the six properties (Section 4.1)
+    n_eff_mean = float(n_eff.mean())
+    tpg = t_w / G + t_s / (G * n_eff_mean) * TARGET_ESS
+    value = 1.0 / tpg
+    stats = r["stats"].cpu().numpy()
+    rhat = r["rhat"].cpu().numpy()
+
+    # plain form: one galaxy and one leapfrog step per launch, on a subset
+    Gp = args.plain_gal
+    pt, pb, pdata, pref, pinit = make_inputs(api, torch, Gp, cfg, seed_offset=99)
+    it_p = 2
+    pcfg = api.HmcConfig(**{**hcfg.__dict__, "form": api.N.FORM_PLAIN, "n_warmup": it_p,
+                            "n_samples": 0, "use_graph": False})
+    _, t_plain = timed(torch, lambda: api.hmc_sample(pb, pdata, pref, pinit, pcfg, want_samples=False),
+                       stream)
+    per_iter_gal = t_plain / (Gp * it_p)        # seconds per galaxy-iteration (C chains)
+    plain_tpg = per_iter_gal * (W + S * TARGET_ESS / n_eff_mean)
+    plain_value = 1.0 / plain_tpg
+
+    # roofline of the trajectory kernel: one launch = one iteration of every chain
+    n_launch = W + S
+    t_launch = t_hmc / n_launch
+    alg = flops_per_eval(N) * G * C * L
+    achieved = alg / t_launch / 1e12
+    peak = 78.6
+    out = {
+        "metric": "galaxies/sec at 300 ESS (53x53 stamps), batched vs plain",
+        "value": round(value, 3),
+        "unit": "galaxies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched uniform: 10,000 galaxies, 53x53 stamps, PSF FWHM 0.7in, "
+                               "SNR 15-100, 4 chains, 20 leapfrog steps, 300 dual-averaging warmup "
+                               "+ 1000 draws, shear grid 41x41",
+                   "n_gal": G, "stamp": N, "chains": C, "leapfrog": L, "warmup_iters": W,
+                   "samples": S, "metric_kind": "fisher-diagonal", "jitter": 0.2},
+        "plain_value": round(plain_value, 4),
+        "batched_over_plain": round(value / plain_value, 1),
+        "t_warmup_s": round(t_w, 4),
+        "t_sampling_s": round(t_s, 4),
+        "t_ess_s": round(r["t_ess"], 4),
+        "t_shear_grid_s": round(r["t_shear"], 4),
+        "n_eff_mean": round(n_eff_mean, 1),
+        "n_eff_min_param_mean": round(float(ess.min(axis=1).mean()), 1),
+        "ess_per_s": round(float(ess.mean(axis=1).sum()) / t_s, 1),
+        "accept_rate": round(float(stats[..., 0].mean()), 4),
+        "rhat_max": round(float(np.nanmax(rhat)), 4),
+        "frac_rhat_lt_1.01": round(float(np.mean(rhat.max(axis=1) < 1.01)), 4),
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "hmc_kernel (advance)", "launch_ms": round(t_launch * 1e3, 4),
+                     "alg_flop_per_launch": alg},
+    }
+    if cpu:
+        evals_per_gal = C * L * (W + S * TARGET_ESS / n_eff_mean)
+        out["cpu_baseline"] = {"value": round(cpu["rate"] / evals_per_gal, 6), "unit": "galaxies/s",
+                               "cores": cpu["cores"], "kind": "oracle",
+                               "sample": f"{cpu['evals']} float64 oracle gradient evaluations (53x53, "
+                                         f"one 15-iteration warmup chain per core) in "
+                                         f"{cpu['wall']:.1f} s; galaxies/s = eval rate / evaluations "
+                                         f"per galaxy at 300 ESS with the GPU run's n_eff"}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,248 @@
+/*
+ * bsi.h -- C ABI of the Bayesian shear inference library for MI355X (gfx950).
+ *
+ * The method is that of arXiv 2604.22048 ("Differentiable Forward Modeling
+ * for Efficient and Accurate Shear Inference").  Phase 1 samples the interim
+ * posterior of each galaxy's properties from its pixel stamp
+ * (eq. interim-post with the pixel likelihood eq. likelihood-pixels and the
+ * interim prior eq. interim-prior); phase 2 evaluates the Monte-Carlo shear
+ * likelihood eq. likelihood-shear from the fixed interim samples, with the
+ * shear Jacobian of eq. true-prior-jacobian-shear.
+ *
+ * Conventions for every call
+ *   - Return value: BSI_OK (0) or a negative BSI_E* code.  Arguments are
+ *     validated synchronously before anything is enqueued; on a validation
+ *     error nothing is enqueued and no output is written.  The message of
+ *     the last error on a handle is returned by bsi_last_error().
+ *   - Asynchronous device failures are sticky on the handle and reported by
+ *     the next call (BSI_EHIP).
+ *   - Numerical trouble in one galaxy never fails a call; it sets that
+ *     galaxy's status bits (BSI_STATUS_*).
+ *   - Pointers marked [device] are caller-owned device memory on the
+ *     handle's device; [host] pointers are read during the call only.  The
+ *     library never frees caller memory.  It allocates only handle-owned
+ *     workspace, which grows on demand and is released by bsi_destroy().
+ *   - Calls are stream-ordered on `stream` (a hipStream_t; NULL means the
+ *     default stream).  A handle must be used from one host thread at a
+ *     time.
+ *   - Stamps: square N x N single-precision images stored row-major
+ *     ([y][x]), packed back to back in one buffer; galaxy i starts at
+ *     element off[i].  Pixel centres are at x_i = i - (N-1)/2 (same in y).
+ *   - Physical parameters (params): float[6] per galaxy =
+ *     {flux F, half-light radius s [arcsec] of the circular pre-shear
+ *      profile, e1, e2 (reduced-shear convention, eq. ellip-phi-transform),
+ *      dx, dy [pixels from the stamp centre]}.
+ *   - Sampling coordinates (theta): float[6] =
+ *     {log10 F, log10 s, e1, e2, Dx, Dy} with (Dx, Dy) the offset in pixels
+ *     from a per-galaxy reference centroid ref_xy (the prior of eq.
+ *     interim-prior centres the offsets on the true centroid).
+ */
+#ifndef BSI_H
+#define BSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BSI_VERSION 1
+
+enum {
+  BSI_OK = 0,
+  BSI_EINVAL = -1,        /* invalid argument (message in bsi_last_error)  */
+  BSI_ENOMEM = -2,        /* device workspace allocation failed             */
+  BSI_EHIP = -3,          /* HIP runtime error (possibly from earlier work)  */
+  BSI_EUNSUPPORTED = -4,  /* size or device not supported (gfx950 only)     */
+  BSI_ENODEV = -5         /* no usable device                                */
+};
+
+/* Per-galaxy status bits (OR-ed over all of a galaxy's chains). */
+enum {
+  BSI_STATUS_OUT_OF_SUPPORT = 1,  /* a parameter set or trajectory left the prior support */
+  BSI_STATUS_NONFINITE = 2,       /* a non-finite log-likelihood or energy was met        */
+  BSI_STATUS_DIVERGENT = 4        /* |dH| > 1000 in some trajectory                       */
+};
+
+enum { BSI_PROFILE_EXPONENTIAL = 0, BSI_PROFILE_GAUSSIAN = 1 };
+
+/* Log-likelihood evaluation method for bsi_loglik_grad. */
+enum {
+  BSI_LIK_KSPACE = 0,  /* exact Parseval form on the stamp's DFT grid (default) */
+  BSI_LIK_PIXEL = 1    /* render, pixel residual, adjoint transform             */
+};
+
+typedef struct bsi_ctx* bsi_handle;
+typedef void* bsi_stream;   /* hipStream_t */
+
+/* Library version (BSI_VERSION). */
+int bsi_version(void);
+
+/* Number of visible HIP devices in *n (0 when none); BSI_OK or BSI_EHIP. */
+int bsi_device_count(int32_t* n);
+
+/* Create a handle bound to `device` (HIP ordinal).  Fails with BSI_ENODEV
+ * when no device exists, BSI_EUNSUPPORTED when it is not gfx950. */
+int bsi_create(bsi_handle* out, int32_t device);
+
+/* Release a handle and its workspace; NULL is ignored.  Waits for the
+ * handle's outstanding work. */
+void bsi_destroy(bsi_handle h);
+
+/* Message of the last failing call on h (empty string if none; never NULL).
+ * With h == NULL returns the last error of bsi_create on this thread. */
+const char* bsi_last_error(bsi_handle h);
+
+/* A ragged batch of square stamps. */
+typedef struct {
+  int32_t n_gal;             /* number of galaxies, >= 0                              */
+  const int32_t* n;          /* [host] stamp side N_i, 8 <= N_i <= 128                  */
+  const int64_t* off;        /* [host] element offset of stamp i in the packed buffer   */
+  const float* psf_fwhm;     /* [device] Gaussian PSF FWHM per galaxy, arcsec, > 0      */
+  const float* sigma;        /* [device] pixel noise sigma per galaxy (b = sigma^2), > 0 */
+  float pixel_scale;         /* arcsec per pixel, > 0                                   */
+  int32_t profile;           /* BSI_PROFILE_*                                           */
+} bsi_batch;
+
+/*
+ * bsi_render_stamps -- noiseless model stamps (Section 3.2: exponential
+ * profile convolved with the known PSF, integrated over pixels).
+ * The stamp is the truncated Fourier series on the stamp's frequency grid:
+ *   m[j,i] = N^-2 sum_{u,v} w_u w_v T(u,v) exp(i(k_u x_i + k_v y_j)),
+ *   k_u = 2 pi u / N, u in -floor(N/2)..floor(N/2), w = 1/2 at u = +-N/2 for
+ *   even N and 1 otherwise,
+ *   T = F G(q) exp(-sigma_psf^2 |k|^2 / 2) sinc(u/N) sinc(v/N) exp(-i k.d),
+ * with G the Fourier transform of the sheared, unit-flux profile.
+ *   params [device] float[n_gal][6] physical parameters.
+ *   out    [device] packed stamps, element off[i] .. off[i] + N_i^2 - 1.
+ */
+int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params, float* out,
+                      bsi_stream stream);
+
+/*
+ * bsi_loglik_grad -- pixel log-likelihood of eq. likelihood-pixels,
+ *   log L = -1/2 sum_p (d_p - m_p)^2 / sigma^2   (constant C = 0),
+ * and its gradient with respect to the physical parameters.
+ *   data    [device] packed stamps.
+ *   params  [device] float[n_gal][6].
+ *   loglik  [device] double[n_gal] or NULL.
+ *   grad    [device] float[n_gal][6] d log L / d params, or NULL.
+ *   status  [device] uint32[n_gal] or NULL (bit OUT_OF_SUPPORT when
+ *           |e| >= 1 or s <= 0 or F <= 0; NONFINITE when log L is not finite).
+ *   method  BSI_LIK_KSPACE or BSI_LIK_PIXEL (same value up to rounding).
+ */
+int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, const float* params,
+                    double* loglik, float* grad, uint32_t* status, int32_t method,
+                    bsi_stream stream);
+
+/* Interim prior of eq. interim-prior (paper values in brackets). */
+typedef struct {
+  float log10f_lo, log10f_hi;   /* uniform log10 F support   [-1, 9]  */
+  float log10s_lo, log10s_hi;   /* uniform log10 s support   [-2, 1]  */
+  float sigma_d;                /* Gaussian sigma of Dx, Dy  [0.5 px] */
+  float sigma_e;                /* ellipticity prior sigma   [0.3]    */
+} bsi_interim;
+
+enum { BSI_METRIC_GIVEN = 0, BSI_METRIC_FISHER = 1 };
+enum { BSI_FORM_BATCHED = 0, BSI_FORM_PLAIN = 1 };
+
+/* Hamiltonian sampler settings.  One iteration = one trajectory of
+ * n_leapfrog steps followed by the Metropolis test. */
+typedef struct {
+  int32_t n_chains;          /* chains per galaxy, 1..16                                   */
+  int32_t n_leapfrog;        /* leapfrog steps per trajectory, >= 1                        */
+  int32_t n_warmup;          /* warmup iterations (not stored), >= 0                       */
+  int32_t n_samples;         /* stored iterations, >= 0                                    */
+  int32_t adapt;             /* 1: dual-averaging step-size adaptation during warmup       */
+  int32_t metric;            /* BSI_METRIC_GIVEN (inv_mass or identity) or _FISHER          */
+  float step_size;           /* initial (adapt) or fixed step size, > 0                    */
+  float target_accept;       /* dual-averaging target delta in (0, 1) [0.8]                */
+  float jitter;              /* relative step-size jitter in [0, 1) [0 = none]             */
+  int32_t form;              /* BSI_FORM_BATCHED: all galaxies per launch;
+                                BSI_FORM_PLAIN: one galaxy and one leapfrog step per launch */
+  int32_t iters_per_launch;  /* batched form: trajectories per kernel launch (>= 1)        */
+  int32_t use_graph;         /* batched form: replay launches from a captured HIP graph    */
+  uint64_t seed;             /* Philox key                                                 */
+  uint64_t uid_base;         /* chain uid = uid_base + galaxy * n_chains + chain           */
+  float* trace;              /* [device] float[n_gal][n_chains][n_warmup + n_samples][4] or
+                                NULL: per iteration {base step size, dH, acceptance
+                                statistic min(1, exp(-dH)) (0 if rejected for support or
+                                non-finiteness), accepted (0 or 1)}                          */
+} bsi_hmc_cfg;
+
+/*
+ * bsi_hmc_sample -- phase 1: sample every galaxy's interim posterior.
+ *   data       [device] packed stamps.
+ *   ref_xy     [device] float[n_gal][2] reference centroid (pixels from the
+ *              stamp centre); the model centroid is ref_xy + (Dx, Dy).
+ *   inv_mass   [device] float[n_gal][6] diagonal inverse metric or NULL
+ *              (identity); ignored with BSI_METRIC_FISHER.
+ *   init       [device] float[n_gal][n_chains][6] start positions (theta).
+ *   samples    [device] float[n_gal][n_chains][n_samples][6] (theta) or NULL.
+ *   chain_stats[device] float[n_gal][n_chains][4] = {accept rate over the
+ *              stored iterations, final step size, divergent trajectories,
+ *              final potential energy} or NULL.
+ *   status     [device] uint32[n_gal] or NULL.
+ * Random numbers: Philox4x32-10 keyed by seed, counter (uid, t, tag, block)
+ * with t the iteration index; so the output of a chain does not depend on
+ * which other galaxies share the call.
+ */
+int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, const float* ref_xy,
+                   const float* inv_mass, const float* init, const bsi_interim* interim,
+                   const bsi_hmc_cfg* cfg, float* samples, float* chain_stats, uint32_t* status,
+                   bsi_stream stream);
+
+/* True prior of the intrinsic properties used in phase 2. */
+enum { BSI_E_BA14 = 0, BSI_E_TRUNC_GAUSS = 1 };
+typedef struct {
+  int32_t e_kind;            /* BSI_E_BA14: (1-E)^2 exp(-E/2 sigma_e^2) on |e| < 1
+                                (eq. ellip-mag-prior in (e1, e2) form);
+                                BSI_E_TRUNC_GAUSS: exp(-E/2 sigma_e^2) on |e| < e_max   */
+  float e_max;
+  int32_t size_term;         /* 1: include ln s ~ N(mu_ln_s, sigma_ln_s)                  */
+  int32_t flux_term;         /* 1: include ln F ~ N(mu_ln_f, sigma_ln_f)                  */
+  double mu_ln_f, sigma_ln_f;
+} bsi_true_prior;
+
+/*
+ * bsi_shear_posterior -- phase 2: Monte-Carlo shear log-likelihood
+ * (eq. likelihood-shear) at n_pts points of (g1, g2, mu_ln_s, sigma_ln_s,
+ * sigma_e):
+ *   ln P = sum_n [ ln sum_k w_nk - ln K ] (+ 0 inside the uniform priors,
+ *          -inf outside: |g| < 1, 1e-4 < sigma_e < 1, |mu_ln_s| < 2 ln 10,
+ *          0 < sigma_ln_s < ln 10 / 2),
+ *   ln w_nk = ln p_e(h_g^-1(e'_nk)) + ln|d eps/d eps'| - ln P0_e(e'_nk)
+ *             + size and flux terms (true minus interim density, in log10
+ *             coordinates).  Centroid terms cancel (Section 3.3).
+ * The log-sum-exp over k and the sum over galaxies are carried in float64.
+ *   e1p, e2p, log10s, log10f  [device] float[n_gal][K] interim samples
+ *              (structure of arrays; log10f may be NULL when flux_term = 0).
+ *   pts      [host or device, see pts_on_device] double[n_pts][5].
+ *   logpost  [device] double[n_pts].
+ *   grad     [device] double[n_pts][5] gradient of ln P, or NULL.
+ * Samples whose intrinsic ellipticity falls outside the true prior's
+ * support get weight 0; a galaxy with all weights 0 gives ln P = -inf.
+ */
+int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                        const float* e2p, const float* log10s, const float* log10f,
+                        const bsi_true_prior* tp, const bsi_interim* interim, int32_t n_pts,
+                        const double* pts, int32_t pts_on_device, double* logpost, double* grad,
+                        bsi_stream stream);
+
+/*
+ * bsi_ess -- diagnostics of Section 4.1 for stored samples:
+ * multi-chain effective sample size per parameter (autocorrelation with
+ * Geyer's initial monotone sequence, no rank normalisation) and the classic
+ * potential scale reduction R-hat.
+ *   samples  [device] float[n_gal][n_chains][n_samples][n_par].
+ *   ess      [device] float[n_gal][n_par] or NULL.
+ *   rhat     [device] float[n_gal][n_par] or NULL.
+ */
+int bsi_ess(bsi_handle h, int32_t n_gal, int32_t n_chains, int32_t n_samples, int32_t n_par,
+            const float* samples, float* ess, float* rhat, bsi_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSI_H */

@@ -191,11 +191,13 @@ def run_chain(potential_fn, theta0, seed, uid, L, n_warmup, n_samples, eps0, ada
     alpha_sum = 0.0
     alpha_warm = []
     eps_hist = []
+    trace = []
     for t in range(n_warmup + n_samples):
         eps_hist.append(f32(eps))
         theta, U, gU, info = hmc_iteration(potential_fn, theta, U, gU, eps, L, seed, uid, t,
                                            inv_mass, n_dim, jitter)
         n_div += int(info["divergent"])
+        trace.append((f32(eps), info["dH"], info["alpha"], float(info["accept"])))
         if t < n_warmup:
             alpha_warm.append(info["alpha"])
             if adapt:
@@ -208,6 +210,7 @@ def run_chain(potential_fn, theta0, seed, uid, L, n_warmup, n_samples, eps0, ada
             alpha_sum += info["alpha"]
     return dict(samples=samples, eps=f32(eps), accept_rate=n_acc / max(n_samples, 1),
                 alpha_mean=alpha_sum / max(n_samples, 1), alpha_warmup=np.array(alpha_warm),
+                trace=np.array(trace).reshape(-1, 4),
                 n_div=n_div, U=U, eps_hist=np.array(eps_hist))
 
 
@@ -234,3 +237,25 @@ def init_chain(data, sigma, log10s_center, e_center, seed, uid, half_s=0.015, ha
     else:
         e1, e2 = 0.0, 0.0
     return np.array([math.log10(F), ls, e1, e2, 0.0, 0.0])
+
+
+def fisher_inv_mass(gal: Galaxy, theta, ip=prior.PAPER_INTERIM):
+    """Inverse of the diagonal Fisher information of the likelihood plus the
+    interim-prior curvature, in sampling coordinates (a diagonal metric).
+
+    F_jj = sigma^-2 sum_pixels (dm/dtheta_j)^2, with each stamp derivative
+    synthesised from the spectrum derivative (forward mode)."""
+    tc = clamp_theta(theta, ip)
+    prm = theta_to_params(tc, gal.ref_xy)
+    _, dT = render.spectrum(prm, gal.N, gal.pixel_scale, gal.psf_fwhm, gal.profile, derivs=True)
+    jac = np.array([prm[0] * LN10, prm[1] * LN10, 1.0, 1.0, 1.0, 1.0])
+    fi = np.array([np.sum(render.synthesize(dT[j], gal.N) ** 2) for j in range(6)])
+    fi = fi * jac * jac / (gal.sigma * gal.sigma)
+    e1, e2 = tc[2], tc[3]
+    E = e1 * e1 + e2 * e2
+    se, sd = ip["sigma_e"], ip["sigma_d"]
+    fi[2] += 4.0 / (1 - E) + 8.0 * e1 * e1 / (1 - E) ** 2 + 1.0 / (se * se)
+    fi[3] += 4.0 / (1 - E) + 8.0 * e2 * e2 / (1 - E) ** 2 + 1.0 / (se * se)
+    fi[4] += 1.0 / (sd * sd)
+    fi[5] += 1.0 / (sd * sd)
+    return 1.0 / fi

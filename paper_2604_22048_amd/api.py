@@ -1,0 +1,252 @@
+"""Python binding of the shear-inference library: same call names as the C
+ABI, torch tensors for device memory and streams.  Every computation runs in
+the HIP library; this module only checks shapes and passes pointers."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+PAPER_INTERIM = dict(log10f_lo=-1.0, log10f_hi=9.0, log10s_lo=-2.0, log10s_hi=1.0,
+                     sigma_d=0.5, sigma_e=0.3)
+
+
+class BsiError(RuntimeError):
+    pass
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Library:
+    """One handle on one device.  Use ``get()`` for the process-wide default."""
+
+    def __init__(self, device: int = 0):
+        self.lib = N.load()
+        self.device = device
+        h = C.c_void_p()
+        rc = self.lib.bsi_create(C.byref(h), device)
+        if rc != N.BSI_OK:
+            raise BsiError(f"bsi_create: {N.ERRORS.get(rc, rc)}: {self.lib.bsi_last_error(None).decode()}")
+        self.h = h
+
+    def check(self, rc, what):
+        if rc != N.BSI_OK:
+            msg = self.lib.bsi_last_error(self.h).decode()
+            raise BsiError(f"{what}: {N.ERRORS.get(rc, rc)}: {msg}")
+
+    def close(self):
+        if self.h:
+            self.lib.bsi_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default = {}
+
+
+def get(device: int = 0) -> Library:
+    if device not in _default:
+        _default[device] = Library(device)
+    return _default[device]
+
+
+@dataclass
+class Batch:
+    """A ragged batch of square stamps packed row-major back to back."""
+    n: np.ndarray                 # int32 [G] stamp sides (host)
+    psf_fwhm: torch.Tensor        # float32 [G] (device)
+    sigma: torch.Tensor           # float32 [G] (device)
+    pixel_scale: float = 0.2
+    profile: int = N.PROFILE_EXPONENTIAL
+    off: np.ndarray = field(default=None)   # int64 [G]; default: packed in order
+
+    def __post_init__(self):
+        self.n = np.ascontiguousarray(self.n, dtype=np.int32)
+        if self.off is None:
+            sz = self.n.astype(np.int64) ** 2
+            self.off = np.concatenate([[0], np.cumsum(sz)[:-1]]).astype(np.int64)
+        self.off = np.ascontiguousarray(self.off, dtype=np.int64)
+        self.psf_fwhm = self.psf_fwhm.contiguous().float()
+        self.sigma = self.sigma.contiguous().float()
+
+    @property
+    def n_gal(self):
+        return int(self.n.shape[0])
+
+    @property
+    def n_pixels(self):
+        return int((self.off + self.n.astype(np.int64) ** 2).max()) if self.n_gal else 0
+
+    def c(self) -> N.Batch:
+        b = N.Batch()
+        b.n_gal = self.n_gal
+        b.n = self.n.ctypes.data_as(C.POINTER(C.c_int32))
+        b.off = self.off.ctypes.data_as(C.POINTER(C.c_int64))
+        b.psf_fwhm = self.psf_fwhm.data_ptr()
+        b.sigma = self.sigma.data_ptr()
+        b.pixel_scale = float(self.pixel_scale)
+        b.profile = int(self.profile)
+        return b
+
+
+def _interim(d=None) -> N.Interim:
+    d = dict(PAPER_INTERIM if d is None else d)
+    return N.Interim(**{k: float(v) for k, v in d.items()})
+
+
+def render_stamps(batch: Batch, params: torch.Tensor, lib: Library | None = None) -> torch.Tensor:
+    lib = lib or get(params.device.index or 0)
+    params = params.contiguous().float()
+    assert params.shape == (batch.n_gal, 6)
+    out = torch.zeros(batch.n_pixels, dtype=torch.float32, device=params.device)
+    b = batch.c()
+    lib.check(lib.lib.bsi_render_stamps(lib.h, C.byref(b), _ptr(params), _ptr(out),
+                                        _stream(params.device)), "bsi_render_stamps")
+    return out
+
+
+def loglik_grad(batch: Batch, data: torch.Tensor, params: torch.Tensor, method: int = N.LIK_KSPACE,
+                lib: Library | None = None):
+    """(log L [G] float64, d log L / d params [G, 6], status [G] int32)."""
+    lib = lib or get(params.device.index or 0)
+    params = params.contiguous().float()
+    data = data.contiguous().float()
+    G = batch.n_gal
+    dev = params.device
+    ll = torch.empty(G, dtype=torch.float64, device=dev)
+    gr = torch.empty(G, 6, dtype=torch.float32, device=dev)
+    st = torch.empty(G, dtype=torch.int32, device=dev)
+    b = batch.c()
+    lib.check(lib.lib.bsi_loglik_grad(lib.h, C.byref(b), _ptr(data), _ptr(params), _ptr(ll), _ptr(gr),
+                                      _ptr(st), int(method), _stream(dev)), "bsi_loglik_grad")
+    return ll, gr, st
+
+
+@dataclass
+class HmcConfig:
+    n_chains: int = 4
+    n_leapfrog: int = 20
+    n_warmup: int = 300
+    n_samples: int = 1000
+    adapt: bool = True
+    metric: int = N.METRIC_GIVEN
+    step_size: float = 0.01
+    target_accept: float = 0.8
+    jitter: float = 0.0
+    form: int = N.FORM_BATCHED
+    iters_per_launch: int = 1
+    use_graph: bool = True
+    seed: int = 0
+    uid_base: int = 0
+
+    def c(self, trace=None) -> N.HmcCfg:
+        return N.HmcCfg(int(self.n_chains), int(self.n_leapfrog), int(self.n_warmup),
+                        int(self.n_samples), int(bool(self.adapt)), int(self.metric),
+                        float(self.step_size), float(self.target_accept), float(self.jitter),
+                        int(self.form), int(self.iters_per_launch), int(bool(self.use_graph)),
+                        int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.uid_base) & 0xFFFFFFFFFFFFFFFF,
+                        None if trace is None else trace.data_ptr())
+
+
+def hmc_sample(batch: Batch, data: torch.Tensor, ref_xy: torch.Tensor, init: torch.Tensor,
+               cfg: HmcConfig, interim=None, inv_mass: torch.Tensor | None = None,
+               want_samples: bool = True, trace: torch.Tensor | None = None,
+               lib: Library | None = None):
+    """(samples [G, C, S, 6], chain_stats [G, C, 4], status [G]).
+
+    trace: optional float32 [G, C, W + S, 4] tensor filled per iteration with
+    (base step, dH, acceptance statistic, accepted)."""
+    dev = data.device
+    lib = lib or get(dev.index or 0)
+    G, Cn, S = batch.n_gal, cfg.n_chains, cfg.n_samples
+    assert init.shape == (G, Cn, 6) and ref_xy.shape == (G, 2)
+    data = data.contiguous().float()
+    init = init.contiguous().float()
+    ref_xy = ref_xy.contiguous().float()
+    if inv_mass is not None:
+        inv_mass = inv_mass.contiguous().float()
+        assert inv_mass.shape == (G, 6)
+    samples = torch.empty(G, Cn, S, 6, dtype=torch.float32, device=dev) if want_samples else None
+    stats = torch.empty(G, Cn, 4, dtype=torch.float32, device=dev)
+    status = torch.empty(G, dtype=torch.int32, device=dev)
+    if trace is not None:
+        assert trace.shape == (G, Cn, cfg.n_warmup + S, 4) and trace.dtype == torch.float32
+        assert trace.is_contiguous()
+    b = batch.c()
+    ip = _interim(interim)
+    cc = cfg.c(trace)
+    lib.check(lib.lib.bsi_hmc_sample(lib.h, C.byref(b), _ptr(data), _ptr(ref_xy), _ptr(inv_mass),
+                                     _ptr(init), C.byref(ip), C.byref(cc), _ptr(samples),
+                                     _ptr(stats), _ptr(status), _stream(dev)), "bsi_hmc_sample")
+    return samples, stats, status
+
+
+@dataclass
+class TruePriorCfg:
+    e_kind: int = N.E_TRUNC_GAUSS
+    e_max: float = 0.7
+    size_term: bool = True
+    flux_term: bool = False
+    mu_ln_f: float = 0.0
+    sigma_ln_f: float = 1.0
+
+    def c(self) -> N.TruePrior:
+        return N.TruePrior(int(self.e_kind), float(self.e_max), int(bool(self.size_term)),
+                           int(bool(self.flux_term)), float(self.mu_ln_f), float(self.sigma_ln_f))
+
+
+def shear_posterior(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, interim=None,
+                    want_grad: bool = False, lib: Library | None = None):
+    """ln P at points (g1, g2, mu_ln_s, sigma_ln_s, sigma_e); samples are [G, K] tensors."""
+    dev = e1p.device
+    lib = lib or get(dev.index or 0)
+    G, K = e1p.shape
+    e1p, e2p = e1p.contiguous().float(), e2p.contiguous().float()
+    log10s = log10s.contiguous().float() if log10s is not None else None
+    log10f = log10f.contiguous().float() if log10f is not None else None
+    if isinstance(pts, torch.Tensor) and pts.is_cuda:
+        pts_t = pts.contiguous().double()
+        on_dev = 1
+        P = pts_t.shape[0]
+        pts_p = _ptr(pts_t)
+    else:
+        pts_np = np.ascontiguousarray(np.asarray(pts, dtype=np.float64).reshape(-1, 5))
+        P = pts_np.shape[0]
+        on_dev = 0
+        pts_p = C.c_void_p(pts_np.ctypes.data)
+    lp = torch.empty(P, dtype=torch.float64, device=dev)
+    gr = torch.empty(P, 5, dtype=torch.float64, device=dev) if want_grad else None
+    tp = true_prior.c()
+    ip = _interim(interim)
+    lib.check(lib.lib.bsi_shear_posterior(lib.h, G, K, _ptr(e1p), _ptr(e2p), _ptr(log10s),
+                                          _ptr(log10f), C.byref(tp), C.byref(ip), P, pts_p, on_dev,
+                                          _ptr(lp), _ptr(gr), _stream(dev)), "bsi_shear_posterior")
+    return (lp, gr) if want_grad else lp
+
+
+def ess(samples: torch.Tensor, lib: Library | None = None):
+    """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]."""
+    dev = samples.device
+    lib = lib or get(dev.index or 0)
+    samples = samples.contiguous().float()
+    G, Cn, S, P = samples.shape
+    e = torch.empty(G, P, dtype=torch.float32, device=dev)
+    r = torch.empty(G, P, dtype=torch.float32, device=dev)
+    lib.check(lib.lib.bsi_ess(lib.h, G, Cn, S, P, _ptr(samples), _ptr(e), _ptr(r), _stream(dev)),
+              "bsi_ess")
+    return e, r

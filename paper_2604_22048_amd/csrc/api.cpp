@@ -1,0 +1,527 @@
+// Host implementation of the C ABI declared in include/bsi.h.
+#include "bsi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "bsi_kernels.h"
+
+using namespace bsi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct bsi_ctx {
+  int device = 0;
+  int num_cu = 0;
+  std::string err;
+  hipStream_t own = nullptr;
+  DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts;
+};
+
+namespace {
+
+int fail(bsi_handle h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  return code;
+}
+
+int hip_fail(bsi_handle h, hipError_t e, const char* where) {
+  return fail(h, BSI_EHIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+int ensure(bsi_handle h, DevBuf& b, size_t bytes) {
+  if (bytes <= b.n) return BSI_OK;
+  if (b.p) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(h, e, "workspace sync");
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+  }
+  const size_t n = std::max<size_t>(bytes, 256);
+  hipError_t e = hipMalloc(&b.p, n);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, BSI_ENOMEM, "workspace allocation of %zu bytes failed", n);
+  }
+  b.n = n;
+  return BSI_OK;
+}
+
+struct ClassRange {
+  int N;
+  int begin;   // position in the sorted galaxy list
+  int count;
+};
+
+struct Plan {
+  std::vector<int32_t> gidx;      // galaxies grouped by stamp side
+  std::vector<int64_t> bin_off;   // per galaxy, offset into the bin buffer (complex units)
+  std::vector<ClassRange> classes;
+  int64_t total_bins = 0;
+  int64_t max_pixel = 0;          // one past the largest pixel index
+};
+
+int check_batch(bsi_handle h, const bsi_batch* b) {
+  if (!b) return fail(h, BSI_EINVAL, "batch is NULL");
+  if (b->n_gal < 0) return fail(h, BSI_EINVAL, "n_gal < 0");
+  if (b->n_gal == 0) return BSI_OK;
+  if (!b->n || !b->off) return fail(h, BSI_EINVAL, "batch n/off host arrays are NULL");
+  if (!b->psf_fwhm || !b->sigma) return fail(h, BSI_EINVAL, "batch psf_fwhm/sigma are NULL");
+  if (!(b->pixel_scale > 0.0f) || !std::isfinite(b->pixel_scale))
+    return fail(h, BSI_EINVAL, "pixel_scale must be positive");
+  if (b->profile != BSI_PROFILE_EXPONENTIAL && b->profile != BSI_PROFILE_GAUSSIAN)
+    return fail(h, BSI_EINVAL, "unknown profile %d", b->profile);
+  for (int i = 0; i < b->n_gal; ++i) {
+    if (b->n[i] < 8 || b->n[i] > kMaxN)
+      return fail(h, BSI_EUNSUPPORTED, "stamp side %d of galaxy %d outside [8, %d]", b->n[i], i, kMaxN);
+    if (b->off[i] < 0) return fail(h, BSI_EINVAL, "negative offset for galaxy %d", i);
+  }
+  return BSI_OK;
+}
+
+Plan make_plan(const bsi_batch* b) {
+  Plan p;
+  std::map<int, std::vector<int32_t>> by;
+  for (int i = 0; i < b->n_gal; ++i) by[b->n[i]].push_back(i);
+  p.bin_off.assign(b->n_gal, 0);
+  int64_t bins = 0;
+  for (auto& kv : by) {
+    ClassRange c{kv.first, (int)p.gidx.size(), (int)kv.second.size()};
+    const Geom g = make_geom(kv.first);
+    for (int32_t i : kv.second) {
+      p.gidx.push_back(i);
+      p.bin_off[i] = bins;
+      bins += g.nbins;
+      p.max_pixel = std::max<int64_t>(p.max_pixel, b->off[i] + (int64_t)kv.first * kv.first);
+    }
+    p.classes.push_back(c);
+  }
+  p.total_bins = bins;
+  return p;
+}
+
+// Upload the plan's index arrays into the handle workspace.
+int upload_plan(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s) {
+  int rc;
+  const size_t n = (size_t)b->n_gal;
+  if ((rc = ensure(h, h->gidx, n * sizeof(int32_t)))) return rc;
+  if ((rc = ensure(h, h->off, n * sizeof(int64_t)))) return rc;
+  if ((rc = ensure(h, h->bin_off, n * sizeof(int64_t)))) return rc;
+  hipError_t e;
+  if ((e = hipMemcpyAsync(h->gidx.p, p.gidx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(h->off.p, b->off, n * sizeof(int64_t), hipMemcpyHostToDevice, s)) ||
+      (e = hipMemcpyAsync(h->bin_off.p, p.bin_off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s)))
+    return hip_fail(h, e, "plan upload");
+  // pageable sources: make sure the copies are done before the vectors die
+  if ((e = hipStreamSynchronize(s))) return hip_fail(h, e, "plan upload sync");
+  return BSI_OK;
+}
+
+const int32_t* gidx_ptr(bsi_handle h, const ClassRange& c) {
+  return static_cast<const int32_t*>(h->gidx.p) + c.begin;
+}
+
+int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* data,
+                  const double* model, double* chi2, hipStream_t s) {
+  int rc;
+  if ((rc = ensure(h, h->dh, (size_t)p.total_bins * sizeof(float2)))) return rc;
+  for (const ClassRange& c : p.classes) {
+    hipError_t e = launch_dft_bins(data, model, gidx_ptr(h, c), c.count,
+                                   static_cast<const int64_t*>(h->off.p),
+                                   static_cast<const int64_t*>(h->bin_off.p), c.N,
+                                   static_cast<float2*>(h->dh.p), chi2, b->sigma, s);
+    if (e != hipSuccess) return hip_fail(h, e, "dft_bins launch");
+  }
+  return BSI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bsi_version(void) { return BSI_VERSION; }
+
+int bsi_device_count(int32_t* n) {
+  if (!n) return BSI_EINVAL;
+  int c = 0;
+  hipError_t e = hipGetDeviceCount(&c);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *n = 0;
+    return BSI_OK;
+  }
+  *n = c;
+  return BSI_OK;
+}
+
+int bsi_create(bsi_handle* out, int32_t device) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return BSI_EINVAL;
+  }
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device";
+    return BSI_ENODEV;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device ordinal out of range";
+    return BSI_EINVAL;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    g_create_error = "hipGetDeviceProperties failed";
+    return BSI_EHIP;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("unsupported device architecture ") + prop.gcnArchName;
+    return BSI_EUNSUPPORTED;
+  }
+  if (hipSetDevice(device) != hipSuccess) {
+    g_create_error = "hipSetDevice failed";
+    return BSI_EHIP;
+  }
+  bsi_ctx* h = new bsi_ctx();
+  h->device = device;
+  h->num_cu = prop.multiProcessorCount;
+  if (hipStreamCreate(&h->own) != hipSuccess) {
+    delete h;
+    g_create_error = "stream creation failed";
+    return BSI_EHIP;
+  }
+  *out = h;
+  return BSI_OK;
+}
+
+void bsi_destroy(bsi_handle h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&h->gidx, &h->off, &h->bin_off, &h->dh, &h->chi2, &h->model, &h->state,
+                    &h->partial, &h->pts})
+    if (b->p) (void)hipFree(b->p);
+  if (h->own) (void)hipStreamDestroy(h->own);
+  delete h;
+}
+
+const char* bsi_last_error(bsi_handle h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params, float* out,
+                      bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  if (batch->n_gal == 0) return BSI_OK;
+  if (!params || !out) return fail(h, BSI_EINVAL, "params/out is NULL");
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Plan p = make_plan(batch);
+  if ((rc = upload_plan(h, batch, p, s))) return rc;
+  const float rs = profile_rscale(batch->profile, batch->pixel_scale);
+  for (const ClassRange& c : p.classes) {
+    hipError_t e = launch_render(params, batch->psf_fwhm, gidx_ptr(h, c), c.count,
+                                 static_cast<const int64_t*>(h->off.p), c.N, rs,
+                                 1.0f / batch->pixel_scale, batch->profile, out, s);
+    if (e != hipSuccess) return hip_fail(h, e, "render launch");
+  }
+  return BSI_OK;
+}
+
+int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, const float* params,
+                    double* loglik, float* grad, uint32_t* status, int32_t method,
+                    bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  if (batch->n_gal == 0) return BSI_OK;
+  if (!data || !params) return fail(h, BSI_EINVAL, "data/params is NULL");
+  if (method != BSI_LIK_KSPACE && method != BSI_LIK_PIXEL)
+    return fail(h, BSI_EINVAL, "unknown likelihood method %d", method);
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Plan p = make_plan(batch);
+  if ((rc = upload_plan(h, batch, p, s))) return rc;
+  const float rs = profile_rscale(batch->profile, batch->pixel_scale);
+  const int64_t* off = static_cast<const int64_t*>(h->off.p);
+  double* chi2 = nullptr;
+  const double* model = nullptr;
+  if (method == BSI_LIK_PIXEL) {
+    if ((rc = ensure(h, h->model, (size_t)p.max_pixel * sizeof(double)))) return rc;
+    if ((rc = ensure(h, h->chi2, (size_t)batch->n_gal * sizeof(double)))) return rc;
+    for (const ClassRange& c : p.classes) {
+      hipError_t e = launch_render_f64(params, batch->psf_fwhm, gidx_ptr(h, c), c.count, off, c.N,
+                                       rs, 1.0f / batch->pixel_scale, batch->profile,
+                                       static_cast<double*>(h->model.p), s);
+      if (e != hipSuccess) return hip_fail(h, e, "render launch");
+    }
+    model = static_cast<const double*>(h->model.p);
+    chi2 = static_cast<double*>(h->chi2.p);
+  }
+  if ((rc = data_spectrum(h, batch, p, data, model, chi2, s))) return rc;
+  for (const ClassRange& c : p.classes) {
+    hipError_t e = launch_loglik(static_cast<const float2*>(h->dh.p),
+                                 static_cast<const int64_t*>(h->bin_off.p), gidx_ptr(h, c), c.count,
+                                 params, batch->psf_fwhm, batch->sigma, c.N, rs,
+                                 1.0f / batch->pixel_scale, batch->profile,
+                                 method == BSI_LIK_PIXEL, chi2, loglik, grad, status, s);
+    if (e != hipSuccess) return hip_fail(h, e, "loglik launch");
+  }
+  return BSI_OK;
+}
+
+int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, const float* ref_xy,
+                   const float* inv_mass, const float* init, const bsi_interim* ip,
+                   const bsi_hmc_cfg* cfg, float* samples, float* chain_stats, uint32_t* status,
+                   bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_batch(h, batch);
+  if (rc) return rc;
+  if (!cfg || !ip) return fail(h, BSI_EINVAL, "cfg/interim is NULL");
+  if (cfg->n_chains < 1 || cfg->n_chains > 16) return fail(h, BSI_EINVAL, "n_chains must be 1..16");
+  if (cfg->n_leapfrog < 1) return fail(h, BSI_EINVAL, "n_leapfrog must be >= 1");
+  if (cfg->n_warmup < 0 || cfg->n_samples < 0) return fail(h, BSI_EINVAL, "negative iteration count");
+  if (!(cfg->step_size > 0.0f) || !std::isfinite(cfg->step_size))
+    return fail(h, BSI_EINVAL, "step_size must be positive");
+  if (cfg->adapt && !(cfg->target_accept > 0.0f && cfg->target_accept < 1.0f))
+    return fail(h, BSI_EINVAL, "target_accept must be in (0, 1)");
+  if (!(cfg->jitter >= 0.0f && cfg->jitter < 1.0f)) return fail(h, BSI_EINVAL, "jitter must be in [0, 1)");
+  if (cfg->metric != BSI_METRIC_GIVEN && cfg->metric != BSI_METRIC_FISHER)
+    return fail(h, BSI_EINVAL, "unknown metric %d", cfg->metric);
+  if (cfg->form != BSI_FORM_BATCHED && cfg->form != BSI_FORM_PLAIN)
+    return fail(h, BSI_EINVAL, "unknown form %d", cfg->form);
+  if (cfg->form == BSI_FORM_BATCHED && cfg->iters_per_launch < 1)
+    return fail(h, BSI_EINVAL, "iters_per_launch must be >= 1");
+  if (!(ip->log10f_lo < ip->log10f_hi) || !(ip->log10s_lo < ip->log10s_hi) || !(ip->sigma_d > 0) ||
+      !(ip->sigma_e > 0))
+    return fail(h, BSI_EINVAL, "invalid interim prior");
+  if (batch->n_gal == 0) return BSI_OK;
+  if (!data || !ref_xy || !init) return fail(h, BSI_EINVAL, "data/ref_xy/init is NULL");
+  if (cfg->n_samples > 0 && !samples && !chain_stats && !status)
+    return fail(h, BSI_EINVAL, "no output requested");
+  hipSetDevice(h->device);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->own;
+  const Plan p = make_plan(batch);
+  if ((rc = upload_plan(h, batch, p, s))) return rc;
+  if ((rc = data_spectrum(h, batch, p, data, nullptr, nullptr, s))) return rc;
+  const int C = cfg->n_chains;
+  if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
+  for (const ClassRange& c : p.classes) {
+    if (hmc_lds_bytes(c.N, C) > 160 * 1024)
+      return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", c.N, C);
+  }
+
+  HmcArgs a{};
+  a.dh = static_cast<const float2*>(h->dh.p);
+  a.bin_off = static_cast<const int64_t*>(h->bin_off.p);
+  a.psf = batch->psf_fwhm;
+  a.sigma = batch->sigma;
+  a.ref_xy = ref_xy;
+  a.init = init;
+  a.inv_mass = inv_mass;
+  a.state = static_cast<ChainState*>(h->state.p);
+  a.samples = samples;
+  a.trace = cfg->trace;
+  a.rscale = profile_rscale(batch->profile, batch->pixel_scale);
+  a.pscale_inv = 1.0f / batch->pixel_scale;
+  a.prof = batch->profile;
+  a.C = C;
+  a.L = cfg->n_leapfrog;
+  a.W = cfg->n_warmup;
+  a.S = cfg->n_samples;
+  a.adapt = cfg->adapt;
+  a.metric = cfg->metric;
+  a.eps0 = cfg->step_size;
+  a.delta = cfg->target_accept;
+  a.jitter = cfg->jitter;
+  a.mu = (float)std::log(10.0 * (double)cfg->step_size);
+  a.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
+  a.k1 = (uint32_t)(cfg->seed >> 32);
+  a.uid_base = cfg->uid_base;
+  a.lf_lo = ip->log10f_lo;
+  a.lf_hi = ip->log10f_hi;
+  a.ls_lo = ip->log10s_lo;
+  a.ls_hi = ip->log10s_hi;
+  a.sigma_d = ip->sigma_d;
+  a.sigma_e = ip->sigma_e;
+  a.t_stop = cfg->n_warmup + cfg->n_samples;
+
+  for (const ClassRange& c : p.classes) {
+    HmcArgs ac = a;
+    ac.N = c.N;
+    ac.gidx = gidx_ptr(h, c);
+    ac.n_gal = c.count;
+    ac.n_steps = 0;
+    hipError_t e = launch_hmc_init(ac, c.count, s);
+    if (e != hipSuccess) return hip_fail(h, e, "hmc init launch");
+  }
+  const int T = a.t_stop;
+  if (cfg->form == BSI_FORM_PLAIN) {
+    // one galaxy, one leapfrog step per launch
+    for (const ClassRange& c : p.classes) {
+      for (int i = 0; i < c.count; ++i) {
+        HmcArgs ac = a;
+        ac.N = c.N;
+        ac.gidx = gidx_ptr(h, c) + i;
+        ac.n_gal = 1;
+        ac.n_steps = 1;
+        for (int64_t k = 0; k < (int64_t)T * a.L; ++k) {
+          hipError_t e = launch_hmc_advance(ac, 1, s);
+          if (e != hipSuccess) return hip_fail(h, e, "hmc advance launch");
+        }
+      }
+    }
+  } else {
+    const int ipl = std::min(cfg->iters_per_launch, std::max(T, 1));
+    const int n_launch = (T + ipl - 1) / ipl;
+    auto enqueue = [&](hipStream_t st) -> hipError_t {
+      for (const ClassRange& c : p.classes) {
+        HmcArgs ac = a;
+        ac.N = c.N;
+        ac.gidx = gidx_ptr(h, c);
+        ac.n_gal = c.count;
+        ac.n_steps = ipl * a.L;
+        hipError_t e = launch_hmc_advance(ac, c.count, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    if (cfg->use_graph && n_launch > 1) {
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+      if (e == hipSuccess) e = enqueue(s);
+      hipError_t e2 = hipStreamEndCapture(s, &graph);
+      if (e == hipSuccess) e = e2;
+      if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      for (int k = 0; e == hipSuccess && k < n_launch; ++k) e = hipGraphLaunch(exec, s);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      if (e != hipSuccess) return hip_fail(h, e, "hmc graph");
+    } else {
+      for (int k = 0; k < n_launch; ++k) {
+        hipError_t e = enqueue(s);
+        if (e != hipSuccess) return hip_fail(h, e, "hmc advance launch");
+      }
+    }
+  }
+  hipError_t e = launch_hmc_finalize(static_cast<const ChainState*>(h->state.p), batch->n_gal, C,
+                                     cfg->n_samples, chain_stats, status, s);
+  if (e != hipSuccess) return hip_fail(h, e, "hmc finalize launch");
+  if (!stream) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "hmc sync");
+  }
+  return BSI_OK;
+}
+
+int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                        const float* e2p, const float* log10s, const float* log10f,
+                        const bsi_true_prior* tp, const bsi_interim* ip, int32_t n_pts,
+                        const double* pts, int32_t pts_on_device, double* logpost, double* grad,
+                        bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n_gal < 1) return fail(h, BSI_EINVAL, "n_gal must be >= 1");
+  if (K < 1 || K > 1024) return fail(h, BSI_EUNSUPPORTED, "K must be in 1..1024");
+  if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
+  if (!tp || !ip) return fail(h, BSI_EINVAL, "true prior / interim is NULL");
+  if (tp->e_kind != BSI_E_BA14 && tp->e_kind != BSI_E_TRUNC_GAUSS)
+    return fail(h, BSI_EINVAL, "unknown e_kind");
+  if (tp->e_kind == BSI_E_TRUNC_GAUSS && !(tp->e_max > 0.0f && tp->e_max <= 1.0f))
+    return fail(h, BSI_EINVAL, "e_max must be in (0, 1]");
+  if (tp->flux_term && !(tp->sigma_ln_f > 0.0)) return fail(h, BSI_EINVAL, "sigma_ln_f must be > 0");
+  if (!e1p || !e2p || (tp->size_term && !log10s) || (tp->flux_term && !log10f))
+    return fail(h, BSI_EINVAL, "sample arrays are NULL");
+  if (n_pts == 0) return BSI_OK;
+  if (!pts || !logpost) return fail(h, BSI_EINVAL, "pts/logpost is NULL");
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  int rc;
+  const double* dpts = pts;
+  if (!pts_on_device) {
+    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
+    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "points upload");
+    dpts = static_cast<const double*>(h->pts.p);
+  }
+  const int chunks = (n_pts + 63) / 64;
+  const int n_blocks = std::max(1, std::min((n_gal + 3) / 4, std::max(64, 4096 / chunks)));
+  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
+  ShearArgs a{};
+  a.n_gal = n_gal;
+  a.K = K;
+  a.e1p = e1p;
+  a.e2p = e2p;
+  a.l10s = log10s ? log10s : e1p;
+  a.l10f = log10f ? log10f : e1p;
+  a.e_kind = tp->e_kind;
+  a.e_max = tp->e_kind == BSI_E_BA14 ? 1.0f : tp->e_max;
+  a.size_term = tp->size_term;
+  a.flux_term = tp->flux_term;
+  a.mu_lnf = tp->mu_ln_f;
+  a.sig_lnf = tp->flux_term ? tp->sigma_ln_f : 1.0;
+  a.log_span_s = std::log((double)ip->log10s_hi - (double)ip->log10s_lo);
+  a.log_span_f = std::log((double)ip->log10f_hi - (double)ip->log10f_lo);
+  a.sigma_e_interim = ip->sigma_e;
+  a.n_pts = n_pts;
+  a.pts = dpts;
+  a.partial = static_cast<double*>(h->partial.p);
+  a.want_grad = grad != nullptr;
+  hipError_t e = launch_shear(a, n_blocks, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear launch");
+  e = launch_shear_reduce(a.partial, n_blocks, n_pts, dpts, logpost, grad, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
+  return BSI_OK;
+}
+
+int bsi_ess(bsi_handle h, int32_t n_gal, int32_t n_chains, int32_t n_samples, int32_t n_par,
+            const float* samples, float* ess, float* rhat, bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n_gal < 0 || n_chains < 1 || n_chains > 16 || n_samples < 4 || n_par < 1)
+    return fail(h, BSI_EINVAL, "invalid ESS shape");
+  if ((size_t)n_chains * n_samples * sizeof(double) + 256 * sizeof(double) > 150 * 1024)
+    return fail(h, BSI_EUNSUPPORTED, "n_chains * n_samples too large for LDS");
+  if (n_gal == 0) return BSI_OK;
+  if (!samples || (!ess && !rhat)) return fail(h, BSI_EINVAL, "NULL samples or outputs");
+  hipSetDevice(h->device);
+  hipError_t e = launch_ess(n_gal, n_chains, n_samples, n_par, samples, ess, rhat,
+                            static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(h, e, "ess launch");
+  return BSI_OK;
+}
+
+}  // extern "C"

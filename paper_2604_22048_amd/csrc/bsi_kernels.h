@@ -1,0 +1,124 @@
+// Kernel launchers shared by the host API (one translation unit per .hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bsi_device.h"
+
+namespace bsi {
+
+enum { kProfExpHost = 0, kProfGaussHost = 1 };
+
+// Half-light radius of exp(-r) in scale radii: root of (1 + x) exp(-x) = 1/2.
+double exponential_hlr_factor();
+
+// Scale from half-light radius [arcsec] to the profile radius in pixels.
+inline float profile_rscale(int prof, float pixel_scale) {
+  if (prof == 0) return (float)(1.0 / (exponential_hlr_factor() * (double)pixel_scale));
+  return (float)(1.0 / (1.1774100225154747 * (double)pixel_scale));   // sqrt(2 ln 2)
+}
+
+// ---- transform.hip ----
+size_t dft_bins_lds_bytes(int N);
+size_t render_lds_bytes(int N);
+hipError_t launch_dft_bins(const float* data, const double* model, const int32_t* gidx, int n,
+                           const int64_t* off, const int64_t* bin_off, int N, float2* out,
+                           double* chi2, const float* sigma, hipStream_t s);
+hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
+                         const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                         float* out, hipStream_t s);
+hipError_t launch_render_f64(const float* params, const float* psf, const int32_t* gidx, int n,
+                             const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                             double* out, hipStream_t s);
+
+// ---- likelihood.hip ----
+hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
+                         const float* params, const float* psf, const float* sigma, int N,
+                         float rscale, float pscale_inv, int prof, int resid_mode,
+                         const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
+                         hipStream_t s);
+
+// ---- hmc.hip ----
+// Per-chain device state: 64 words, loaded and stored one word per lane.
+struct ChainState {
+  float theta[6];      // accepted position (sampling coordinates)
+  float grad[6];       // grad U at theta
+  float th[6];         // trajectory position
+  float p[6];          // trajectory momentum
+  float g[6];          // grad U at th
+  float inv_mass[6];   // diagonal inverse metric
+  double U;            // potential at theta
+  double H0;           // Hamiltonian at the trajectory start
+  double hbar;         // dual averaging: running mean of (delta - alpha)
+  double log_eps_bar;  // dual averaging: averaged log step
+  double Uth;          // potential at th
+  float eps;           // current base step size
+  float eps_t;         // this trajectory's (jittered) step
+  int32_t l;           // leapfrog steps done in the current trajectory
+  int32_t ok;          // trajectory stayed inside the support
+  int32_t t;           // iteration index
+  int32_t n_acc;       // accepted stored iterations
+  int32_t n_div;       // divergent or non-finite trajectories
+  uint32_t status;     // BSI_STATUS_* bits
+  float sum_alpha;     // sum of acceptance statistics over stored iterations
+  float u_acc;         // Metropolis uniform of the current trajectory
+  float pad[8];
+};
+static_assert(sizeof(ChainState) == 256, "ChainState must be 64 words");
+
+struct HmcArgs {
+  const float2* dh;
+  const int64_t* bin_off;
+  const int32_t* gidx;
+  int n_gal;              // galaxies in this launch (entries of gidx)
+  const float* psf;
+  const float* sigma;
+  const float* ref_xy;
+  const float* init;      // [gal][C][6] (init kernel only)
+  const float* inv_mass;  // [gal][6] or NULL (init kernel only)
+  ChainState* state;      // [gal][C]
+  float* samples;         // [gal][C][S][6] or NULL
+  float* trace;           // [gal][C][W+S][4] or NULL
+  int N;
+  float rscale, pscale_inv;
+  int prof;
+  int C, L, W, S, adapt, metric;
+  float eps0, delta, jitter, mu;
+  uint32_t k0, k1;
+  uint64_t uid_base;
+  float lf_lo, lf_hi, ls_lo, ls_hi, sigma_d, sigma_e;
+  int n_steps;            // leapfrog steps to advance in this launch
+  int t_stop;             // iteration at which a chain stops (W + S)
+};
+
+size_t hmc_lds_bytes(int N, int C);
+hipError_t launch_hmc_init(const HmcArgs& a, int grid, hipStream_t s);
+hipError_t launch_hmc_advance(const HmcArgs& a, int grid, hipStream_t s);
+hipError_t launch_hmc_finalize(const ChainState* st, int n_gal, int C, int S, float* chain_stats,
+                               uint32_t* status, hipStream_t s);
+
+// ---- shear.hip ----
+struct ShearArgs {
+  int n_gal, K;
+  const float *e1p, *e2p, *l10s, *l10f;
+  int e_kind;
+  float e_max;
+  int size_term, flux_term;
+  double mu_lnf, sig_lnf;
+  double log_span_s, log_span_f;   // ln of the interim uniform widths (log10 units)
+  double sigma_e_interim;
+  int n_pts;
+  const double* pts;               // device [n_pts][5]
+  double* partial;                 // device [n_blocks][n_pts][6]
+  int want_grad;
+};
+hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s);
+hipError_t launch_shear_reduce(const double* partial, int n_blocks, int n_pts, const double* pts,
+                               double* logpost, double* grad, hipStream_t s);
+
+// ---- diag.hip ----
+hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,
+                      float* rhat, hipStream_t s);
+
+}  // namespace bsi

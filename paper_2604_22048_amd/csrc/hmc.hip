@@ -1,0 +1,536 @@
+// Batched Hamiltonian Monte Carlo over the per-galaxy interim posteriors
+// (eq. interim-post: pixel likelihood eq. likelihood-pixels times the interim
+// prior eq. interim-prior), one wave per chain, the chains of one galaxy in
+// one workgroup sharing that galaxy's data spectrum in LDS.
+//
+// A launch advances every chain of its galaxies by n_steps leapfrog steps,
+// crossing trajectory boundaries as needed (a chain's state, including a
+// trajectory in progress, lives in a 256-byte ChainState between launches).
+// The batched form launches all galaxies with n_steps = L * iterations; the
+// plain form launches one galaxy with n_steps = 1.  Both run the same code.
+//
+// Iteration t of a chain (Neal 2011, with the paper's dual-averaging warmup):
+//   momentum p = z / sqrt(inv_mass), z from Philox (uid, t, 0, 0..1) by
+//   Box-Muller; step eps_t = eps (1 + j (2u - 1)), u from Philox (uid, t, 3, 0);
+//   L leapfrog steps; dH = H_end - H_start in float64; accept iff
+//   ln u < -dH with u from Philox (uid, t, 1, 0); a trajectory that leaves the
+//   support or has a non-finite dH is rejected; during warmup the step is
+//   adapted by dual averaging (Hoffman & Gelman 2014, Algorithm 5) on
+//   alpha = min(1, exp(-dH)).
+#include "bsi_kernels.h"
+#include "kspace.h"
+
+namespace bsi {
+
+namespace {
+
+constexpr double kDaGamma = 0.05, kDaT0 = 10.0, kDaKappa = 0.75;
+constexpr double kDivergence = 1000.0;
+constexpr float kEClamp = 1.0f - 1e-6f;
+
+struct GalCtx {
+  Geom g;
+  const float2* dh;
+  const float* atab;
+  float2* X;
+  float2* Y;
+  float norm;      // 1 / (N^2 sigma^2)
+  float rscale;
+  float refx, refy;
+};
+
+struct Prior {
+  float lf_lo, lf_hi, ls_lo, ls_hi, sd, se;
+};
+
+__device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
+  const float E = th[2] * th[2] + th[3] * th[3];
+  return th[0] > pr.lf_lo && th[0] < pr.lf_hi && th[1] > pr.ls_lo && th[1] < pr.ls_hi && E < 1.0f;
+}
+
+// Potential U = -(log L + log P0) and its gradient in sampling coordinates.
+// Outside the support U = +inf and the gradient is evaluated at the nearest
+// admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
+// trajectory can continue (it is rejected anyway).
+template <int PROF>
+__device__ __forceinline__ double potential(const GalCtx& c, const Prior& pr, const float* th,
+                                            float* gU, uint32_t& status) {
+  const bool inside = in_support(th, pr);
+  float t0 = fminf(fmaxf(th[0], pr.lf_lo), pr.lf_hi);
+  float t1 = fminf(fmaxf(th[1], pr.ls_lo), pr.ls_hi);
+  float e1 = th[2], e2 = th[3];
+  float E = e1 * e1 + e2 * e2;
+  if (E > kEClamp) {
+    const float f = sqrtf(kEClamp / E);
+    e1 *= f;
+    e2 *= f;
+    E = e1 * e1 + e2 * e2;
+  }
+  const float F = exp10f(t0), s = exp10f(t1);
+  const float dx = c.refx + th[4], dy = c.refy + th[5];
+  fill_xy(c.g, c.atab, c.X, c.Y, dx, dy);
+  const Shape sh = make_shape(s * c.rscale, e1, e2);
+  const KSums S = kspace_sums<PROF>(c.g, c.dh, c.X, c.Y, F, sh);
+  const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
+  const double isd2 = 1.0 / ((double)pr.sd * pr.sd);
+  const double ise2 = 1.0 / ((double)pr.se * pr.se);
+  const double lp = -0.5 * ((double)th[4] * th[4] + (double)th[5] * th[5]) * isd2 +
+                    2.0 * log(1.0 - (double)E) - 0.5 * (double)E * ise2;
+  const float cpri = -4.0f / (1.0f - E) - (float)ise2;
+  gU[0] = -r.dF * F * kLn10F;
+  gU[1] = -r.ds * s * kLn10F;
+  gU[2] = -(r.de1 + cpri * e1);
+  gU[3] = -(r.de2 + cpri * e2);
+  gU[4] = -(r.ddx - th[4] * (float)isd2);
+  gU[5] = -(r.ddy - th[5] * (float)isd2);
+  double U = -(r.loglik + lp);
+  if (!isfinite(U)) status |= 2u;
+  if (!inside) {
+    status |= 1u;
+    U = INFINITY;
+  }
+  return U;
+}
+
+// Diagonal Fisher information of the likelihood plus the prior curvature, at
+// theta, in sampling coordinates; returns the inverse as the metric.
+template <int PROF>
+__device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* th, float* im) {
+  const Geom& g = c.g;
+  const int lane = lane_id();
+  float t0 = fminf(fmaxf(th[0], pr.lf_lo), pr.lf_hi);
+  float t1 = fminf(fmaxf(th[1], pr.ls_lo), pr.ls_hi);
+  float e1 = th[2], e2 = th[3];
+  float E = e1 * e1 + e2 * e2;
+  if (E > kEClamp) {
+    const float f = sqrtf(kEClamp / E);
+    e1 *= f;
+    e2 *= f;
+    E = e1 * e1 + e2 * e2;
+  }
+  const float F = exp10f(t0), s = exp10f(t1);
+  fill_xy(g, c.atab, c.X, c.Y, c.refx + th[4], c.refy + th[5]);
+  const Shape sh = make_shape(s * c.rscale, e1, e2);
+  const float cg = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;
+  // accumulate sum_c |dM/dp|^2 over every bin, frequency points combined per bin
+  float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const bool even = (g.N & 1) == 0;
+  for (int b = lane; b < g.nbins; b += kWave) {
+    int ub, vb, cmul;
+    if (b < g.nmain) {
+      main_bin_uv(g, b, ub, vb);
+      cmul = 2;
+    } else {
+      spec_bin_uv(g.N, b - g.nmain, ub, vb, cmul);
+    }
+    const int nu = (even && ub == -g.h) ? 2 : 1;
+    const int nv = (even && vb == -g.h) ? 2 : 1;
+    float dr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, di[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int au = 0; au < nu; ++au) {
+      const int u = (nu == 2) ? (au == 0 ? -g.h : g.h) : ub;
+      const float cu = (nu == 2) ? (au == 0 ? 0.5f : -0.5f) : 1.0f;
+      for (int av = 0; av < nv; ++av) {
+        const int v = (nv == 2) ? (av == 0 ? -g.h : g.h) : vb;
+        const float cv = (nv == 2) ? (av == 0 ? 0.5f : -0.5f) : 1.0f;
+        const float kx = u * g.kstep, ky = v * g.kstep;
+        const float2 xu = c.X[u + g.h], yv = c.Y[v + g.h];
+        const float kx2 = kx * kx, ky2 = ky * ky, kxy = kx * ky;
+        const float q = fmaf(sh.ca, kx2, fmaf(sh.cb, ky2, sh.cc * kxy));
+        float G, ia;
+        profile_factor<PROF>(sh, q, G, ia);
+        const float amp = F * G * cu * cv;
+        const float Tr = amp * fmaf(xu.x, yv.x, -xu.y * yv.y);
+        const float Ti = amp * fmaf(xu.x, yv.y, xu.y * yv.x);
+        const float dq1 = sh.inv1mE * ((2.f * e1 + 2.f) * kx2 + (2.f * e1 - 2.f) * ky2 + 2.f * e1 * q);
+        const float dq2 = sh.inv1mE * (2.f * e2 * (kx2 + ky2) + 4.f * kxy + 2.f * e2 * q);
+        const float f[4] = {1.0f / F, 2.0f * cg / s * q * ia, cg * dq1 * ia, cg * dq2 * ia};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          dr[j] += f[j] * Tr;
+          di[j] += f[j] * Ti;
+        }
+        // -i k T
+        dr[4] += kx * Ti; di[4] -= kx * Tr;
+        dr[5] += ky * Ti; di[5] -= ky * Tr;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc[j] += (float)cmul * (dr[j] * dr[j] + di[j] * di[j]);
+  }
+  float fi[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) fi[j] = wave_sum(acc[j]) * c.norm;
+  fi[0] *= F * F * kLn10F * kLn10F;
+  fi[1] *= s * s * kLn10F * kLn10F;
+  const float ise2 = 1.0f / (pr.se * pr.se), omE = 1.0f - E;
+  fi[2] += 4.0f / omE + 8.0f * e1 * e1 / (omE * omE) + ise2;
+  fi[3] += 4.0f / omE + 8.0f * e2 * e2 / (omE * omE) + ise2;
+  fi[4] += 1.0f / (pr.sd * pr.sd);
+  fi[5] += 1.0f / (pr.sd * pr.sd);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) im[j] = 1.0f / fi[j];
+}
+
+// Stage one galaxy's data spectrum and PSF-sinc table in LDS.
+__device__ void stage_galaxy(const HmcArgs& a, int gal, const Geom& g, float2* dh, float* atab) {
+  const float2* src = a.dh + a.bin_off[gal];
+  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) dh[b] = src[b];
+  const float sp = a.psf[gal] * 0.42466090014400953f * a.pscale_inv;
+  for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
+    const int u = t - g.h;
+    const double k = 2.0 * 3.14159265358979323846 * u / g.N;
+    const double sn = (u == 0) ? 1.0 : sinpi((double)u / g.N) / (3.14159265358979323846 * u / g.N);
+    atab[t] = (float)(exp(-0.5 * (double)sp * sp * k * k) * sn);
+  }
+}
+
+struct Lds {
+  float2* dh;
+  float* atab;
+  float2* X;
+  float2* Y;
+};
+
+__device__ __forceinline__ Lds carve(const Geom& g, int wave) {
+  extern __shared__ float4 smem4[];
+  Lds l;
+  l.dh = reinterpret_cast<float2*>(smem4);
+  l.atab = reinterpret_cast<float*>(l.dh + g.nbins);
+  float2* w0 = reinterpret_cast<float2*>(l.atab + ((g.ntab + 1) & ~1));
+  l.X = w0 + 2 * g.ntab * wave;
+  l.Y = l.X + g.ntab;
+  return l;
+}
+
+// Lane-uniform copy of a chain's state (word w of the 64-word record on lane w).
+struct Regs {
+  float theta[6], grad[6], th[6], p[6], g[6], im[6];
+  double U, H0, hbar, lbar, Uth;
+  float eps, eps_t, sum_alpha, u_acc;
+  int l, ok, t, n_acc, n_div;
+  uint32_t status;
+};
+
+__device__ __forceinline__ Regs load_state(const ChainState* st) {
+  const uint32_t w = reinterpret_cast<const uint32_t*>(st)[lane_id()];
+  Regs r;
+  auto f = [&](int i) { return __uint_as_float(bcast(w, i)); };
+  auto d = [&](int i) {
+    const uint64_t lo = bcast(w, i), hi = bcast(w, i + 1);
+    return __longlong_as_double((long long)((hi << 32) | lo));
+  };
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    r.theta[j] = f(j);
+    r.grad[j] = f(6 + j);
+    r.th[j] = f(12 + j);
+    r.p[j] = f(18 + j);
+    r.g[j] = f(24 + j);
+    r.im[j] = f(30 + j);
+  }
+  r.U = d(36);
+  r.H0 = d(38);
+  r.hbar = d(40);
+  r.lbar = d(42);
+  r.Uth = d(44);
+  r.eps = f(46);
+  r.eps_t = f(47);
+  r.l = (int)bcast(w, 48);
+  r.ok = (int)bcast(w, 49);
+  r.t = (int)bcast(w, 50);
+  r.n_acc = (int)bcast(w, 51);
+  r.n_div = (int)bcast(w, 52);
+  r.status = bcast(w, 53);
+  r.sum_alpha = f(54);
+  r.u_acc = f(55);
+  return r;
+}
+
+__device__ __forceinline__ void store_state(ChainState* st, const Regs& r) {
+  const int lane = lane_id();
+  uint32_t w = 0;
+  auto put_f = [&](int i, float x) { if (lane == i) w = __float_as_uint(x); };
+  auto put_u = [&](int i, uint32_t x) { if (lane == i) w = x; };
+  auto put_d = [&](int i, double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    if (lane == i) w = (uint32_t)(b & 0xffffffffu);
+    if (lane == i + 1) w = (uint32_t)(b >> 32);
+  };
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    put_f(j, r.theta[j]);
+    put_f(6 + j, r.grad[j]);
+    put_f(12 + j, r.th[j]);
+    put_f(18 + j, r.p[j]);
+    put_f(24 + j, r.g[j]);
+    put_f(30 + j, r.im[j]);
+  }
+  put_d(36, r.U);
+  put_d(38, r.H0);
+  put_d(40, r.hbar);
+  put_d(42, r.lbar);
+  put_d(44, r.Uth);
+  put_f(46, r.eps);
+  put_f(47, r.eps_t);
+  put_u(48, (uint32_t)r.l);
+  put_u(49, (uint32_t)r.ok);
+  put_u(50, (uint32_t)r.t);
+  put_u(51, (uint32_t)r.n_acc);
+  put_u(52, (uint32_t)r.n_div);
+  put_u(53, r.status);
+  put_f(54, r.sum_alpha);
+  put_f(55, r.u_acc);
+  reinterpret_cast<uint32_t*>(st)[lane] = w;
+}
+
+// Random numbers of iteration t: 6 normals (Box-Muller in float64 on lanes 0
+// and 1), the Metropolis uniform and the step-jitter uniform.
+__device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_t k0, uint32_t k1,
+                                               float* z, float& u_acc, float& u_jit) {
+  const int lane = lane_id();
+  uint32_t tag = kTagMomentum, blk = 0;
+  if (lane == 1) blk = 1;
+  if (lane == 2) tag = kTagAccept;
+  if (lane == 3) tag = kTagJitter;
+  const uint4 w = philox4x32_10(make_uint4(uid, t, tag, blk), k0, k1);
+  // two Box-Muller pairs per lane from (w.x, w.y) and (w.z, w.w)
+  double za, zb, zc, zd;
+  {
+    const double r = sqrt(-2.0 * log((double)u01(w.x)));
+    double sn, cs;
+    sincospi(2.0 * (double)u01(w.y), &sn, &cs);
+    za = r * cs;
+    zb = r * sn;
+  }
+  {
+    const double r = sqrt(-2.0 * log((double)u01(w.z)));
+    double sn, cs;
+    sincospi(2.0 * (double)u01(w.w), &sn, &cs);
+    zc = r * cs;
+    zd = r * sn;
+  }
+  z[0] = (float)bcast(za, 0);
+  z[1] = (float)bcast(zb, 0);
+  z[2] = (float)bcast(zc, 0);
+  z[3] = (float)bcast(zd, 0);
+  z[4] = (float)bcast(za, 1);
+  z[5] = (float)bcast(zb, 1);
+  u_acc = u01(bcast(w.x, 2));
+  u_jit = u01(bcast(w.x, 3));
+}
+
+template <int PROF>
+__device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const Prior& pr, Regs& r,
+                              uint32_t uid, float* samples_chain, float* trace_chain) {
+  const int lane = lane_id();
+  for (int step = 0; step < a.n_steps; ++step) {
+    if (r.t >= a.t_stop) break;
+    if (r.l == 0) {
+      float z[6], u_jit;
+      draw_iteration(uid, (uint32_t)r.t, a.k0, a.k1, z, r.u_acc, u_jit);
+      r.eps_t = r.eps;
+      if (a.jitter > 0.0f)
+        r.eps_t = (float)((double)r.eps * (1.0 + (double)a.jitter * (2.0 * (double)u_jit - 1.0)));
+      double ke = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        r.p[j] = (float)((double)z[j] / sqrt((double)r.im[j]));
+        ke += (double)r.im[j] * (double)r.p[j] * (double)r.p[j];
+        r.th[j] = r.theta[j];
+        r.g[j] = r.grad[j];
+      }
+      r.H0 = r.U + 0.5 * ke;
+      r.ok = 1;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) r.p[j] -= 0.5f * r.eps_t * r.g[j];
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) r.th[j] += r.eps_t * r.im[j] * r.p[j];
+    uint32_t st = 0;
+    r.Uth = potential<PROF>(c, pr, r.th, r.g, st);
+    r.status |= st;
+    if (!in_support(r.th, pr)) r.ok = 0;
+    r.l += 1;
+    if (r.l < a.L) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) r.p[j] -= r.eps_t * r.g[j];
+      continue;
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) r.p[j] -= 0.5f * r.eps_t * r.g[j];
+    double ke = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ke += (double)r.im[j] * (double)r.p[j] * (double)r.p[j];
+    const double dH = r.Uth + 0.5 * ke - r.H0;
+    const bool finite = isfinite(dH);
+    const bool accept = r.ok && finite && log((double)r.u_acc) < -dH;
+    const double alpha = (r.ok && finite) ? fmin(1.0, exp(-dH)) : 0.0;
+    if (!finite || fabs(dH) > kDivergence) {
+      r.n_div += 1;
+      r.status |= finite ? 4u : 2u;
+    }
+    if (trace_chain && lane < 4) {
+      const float v = lane == 0 ? r.eps : lane == 1 ? (float)dH : lane == 2 ? (float)alpha
+                                                                 : (accept ? 1.0f : 0.0f);
+      trace_chain[(int64_t)r.t * 4 + lane] = v;
+    }
+    if (accept) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        r.theta[j] = r.th[j];
+        r.grad[j] = r.g[j];
+      }
+      r.U = r.Uth;
+    }
+    if (r.t < a.W) {
+      if (a.adapt) {
+        const double m = (double)(r.t + 1);
+        const double eta = 1.0 / (m + kDaT0);
+        r.hbar = (1.0 - eta) * r.hbar + eta * ((double)a.delta - alpha);
+        const double le = (double)a.mu - sqrt(m) / kDaGamma * r.hbar;
+        const double x = pow(m, -kDaKappa);
+        r.lbar = x * le + (1.0 - x) * r.lbar;
+        r.eps = (float)exp(le);
+        if (r.t == a.W - 1) r.eps = (float)exp(r.lbar);
+      }
+    } else {
+      if (samples_chain && lane < 6) {
+        float v = r.theta[0];
+#pragma unroll
+        for (int j = 1; j < 6; ++j) v = (lane == j) ? r.theta[j] : v;
+        samples_chain[(int64_t)(r.t - a.W) * 6 + lane] = v;
+      }
+      r.n_acc += accept ? 1 : 0;
+      r.sum_alpha += (float)alpha;
+    }
+    r.t += 1;
+    r.l = 0;
+  }
+}
+
+template <int PROF, bool INIT>
+__global__ void __launch_bounds__(1024) hmc_kernel(HmcArgs a) {
+  const Geom g = make_geom(a.N);
+  const int wave = threadIdx.x / kWave;
+  const Lds l = carve(g, wave);
+  const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e};
+  for (int gi = blockIdx.x; gi < a.n_gal; gi += gridDim.x) {
+    const int gal = a.gidx[gi];
+    __syncthreads();
+    stage_galaxy(a, gal, g, l.dh, l.atab);
+    __syncthreads();
+    if (wave >= a.C) continue;
+    const float sig = a.sigma[gal];
+    GalCtx c;
+    c.g = g;
+    c.dh = l.dh;
+    c.atab = l.atab;
+    c.X = l.X;
+    c.Y = l.Y;
+    c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
+    c.rscale = a.rscale;
+    c.refx = a.ref_xy[2 * (int64_t)gal];
+    c.refy = a.ref_xy[2 * (int64_t)gal + 1];
+    const int64_t chain = (int64_t)gal * a.C + wave;
+    ChainState* st = a.state + chain;
+    const uint32_t uid = (uint32_t)(a.uid_base + (uint64_t)chain);
+    if (INIT) {
+      Regs r;
+      const float* ini = a.init + chain * 6;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) r.theta[j] = ini[j];
+      if (a.metric == 1) {
+        fisher_inv_mass<PROF>(c, pr, r.theta, r.im);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) r.im[j] = a.inv_mass ? a.inv_mass[(int64_t)gal * 6 + j] : 1.0f;
+      }
+      uint32_t stt = 0;
+      r.U = potential<PROF>(c, pr, r.theta, r.grad, stt);
+      r.status = stt;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        r.th[j] = r.theta[j];
+        r.p[j] = 0.f;
+        r.g[j] = r.grad[j];
+      }
+      r.H0 = 0.0;
+      r.hbar = 0.0;
+      r.lbar = 0.0;
+      r.Uth = r.U;
+      r.eps = a.eps0;
+      r.eps_t = a.eps0;
+      r.sum_alpha = 0.f;
+      r.u_acc = 0.5f;
+      r.l = 0;
+      r.ok = 1;
+      r.t = 0;
+      r.n_acc = 0;
+      r.n_div = 0;
+      store_state(st, r);
+    } else {
+      Regs r = load_state(st);
+      float* sc = a.samples ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
+      float* tc = a.trace ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
+      advance_chain<PROF>(a, c, pr, r, uid, sc, tc);
+      store_state(st, r);
+    }
+  }
+}
+
+__global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal, int C, int S,
+                                    float* __restrict__ stats, uint32_t* __restrict__ status) {
+  const int gal = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gal >= n_gal) return;
+  uint32_t s = 0;
+  for (int c = 0; c < C; ++c) {
+    const ChainState& x = st[(int64_t)gal * C + c];
+    s |= x.status;
+    if (stats) {
+      float* o = stats + ((int64_t)gal * C + c) * 4;
+      o[0] = S > 0 ? (float)x.n_acc / (float)S : 0.f;
+      o[1] = x.eps;
+      o[2] = (float)x.n_div;
+      o[3] = (float)x.U;
+    }
+  }
+  if (status) status[gal] = s;
+}
+
+}  // namespace
+
+size_t hmc_lds_bytes(int N, int C) {
+  const Geom g = make_geom(N);
+  return sizeof(float2) * g.nbins + sizeof(float) * ((g.ntab + 1) & ~1) +
+         2 * sizeof(float2) * g.ntab * C;
+}
+
+template <bool INIT>
+static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
+  if (a.n_gal <= 0) return hipSuccess;
+  const size_t lds = hmc_lds_bytes(a.N, a.C);
+  const dim3 blk(kWave * a.C);
+  if (a.prof == kProfExp) {
+    hipFuncSetAttribute((const void*)hmc_kernel<kProfExp, INIT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((hmc_kernel<kProfExp, INIT>), dim3(grid), blk, lds, s, a);
+  } else {
+    hipFuncSetAttribute((const void*)hmc_kernel<kProfGauss, INIT>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((hmc_kernel<kProfGauss, INIT>), dim3(grid), blk, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hmc_init(const HmcArgs& a, int grid, hipStream_t s) { return launch_impl<true>(a, grid, s); }
+hipError_t launch_hmc_advance(const HmcArgs& a, int grid, hipStream_t s) { return launch_impl<false>(a, grid, s); }
+
+hipError_t launch_hmc_finalize(const ChainState* st, int n_gal, int C, int S, float* chain_stats,
+                               uint32_t* status, hipStream_t s) {
+  if (n_gal <= 0) return hipSuccess;
+  hipLaunchKernelGGL(hmc_finalize_kernel, dim3((n_gal + 255) / 256), dim3(256), 0, s, st, n_gal, C,
+                     S, chain_stats, status);
+  return hipGetLastError();
+}
+
+}  // namespace bsi

@@ -1,0 +1,84 @@
+// Batched log-likelihood and gradient (eq. likelihood-pixels), one wave per
+// galaxy.  The DFT of the data (or, for the pixel method, of the pixel
+// residual) at the half-plane bins is staged in LDS and contracted with the
+// analytic spectrum by kspace_sums (the same routine the sampler uses).
+#include "bsi_kernels.h"
+#include "kspace.h"
+
+namespace bsi {
+
+template <int PROF, bool RESID>
+__global__ void __launch_bounds__(64) loglik_kernel(
+    const float2* __restrict__ dh_all, const int64_t* __restrict__ bin_off, const int32_t* __restrict__ gidx,
+    const float* __restrict__ params, const float* __restrict__ psf, const float* __restrict__ sigma,
+    int N, float rscale, float pscale_inv, const double* __restrict__ chi2_pix,
+    double* __restrict__ loglik, float* __restrict__ grad, uint32_t* __restrict__ status) {
+  extern __shared__ float4 smem4[];
+  const Geom g = make_geom(N);
+  const int gal = gidx[blockIdx.x];
+  float2* dh = reinterpret_cast<float2*>(smem4);
+  float* atab = reinterpret_cast<float*>(dh + g.nbins);
+  float2* X = reinterpret_cast<float2*>(atab + ((g.ntab + 1) & ~1));
+  float2* Y = X + g.ntab;
+  const float2* src = dh_all + bin_off[gal];
+  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) dh[b] = src[b];
+  const float sp = psf[gal] * 0.42466090014400953f * pscale_inv;
+  for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
+    const int u = t - g.h;
+    const double k = 2.0 * 3.14159265358979323846 * u / N;
+    const double sn = (u == 0) ? 1.0 : sinpi((double)u / N) / (3.14159265358979323846 * u / N);
+    atab[t] = (float)(exp(-0.5 * (double)sp * sp * k * k) * sn);
+  }
+  __syncthreads();
+  const float* p = params + 6 * (int64_t)gal;
+  const float F = p[0], s = p[1], e1 = p[2], e2 = p[3], dx = p[4], dy = p[5];
+  const float sig = sigma[gal];
+  const float norm = 1.0f / ((float)N * (float)N * sig * sig);
+  const float E = e1 * e1 + e2 * e2;
+  uint32_t st = 0;
+  if (!(E < 1.0f) || !(s > 0.0f) || !(F > 0.0f)) st |= 1u;
+  fill_xy(g, atab, X, Y, dx, dy);
+  const Shape sh = make_shape(s * rscale, e1, e2);
+  const KSums S = kspace_sums<PROF, RESID>(g, dh, X, Y, F, sh);
+  KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, norm);
+  if (RESID) r.loglik = -0.5 * chi2_pix[gal] / ((double)sig * (double)sig);
+  if (!isfinite(r.loglik)) st |= 2u;
+  if (threadIdx.x == 0) {
+    if (loglik) loglik[gal] = r.loglik;
+    if (status) status[gal] = st;
+  }
+  if (grad && threadIdx.x < 6) {
+    const float v[6] = {r.dF, r.ds, r.de1, r.de2, r.ddx, r.ddy};
+    float o = v[0];
+#pragma unroll
+    for (int j = 1; j < 6; ++j) o = (threadIdx.x == j) ? v[j] : o;
+    grad[6 * (int64_t)gal + threadIdx.x] = o;
+  }
+}
+
+static size_t loglik_lds_bytes(int N) {
+  const Geom g = make_geom(N);
+  return sizeof(float2) * g.nbins + sizeof(float) * ((g.ntab + 1) & ~1) + 2 * sizeof(float2) * g.ntab;
+}
+
+hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
+                         const float* params, const float* psf, const float* sigma, int N,
+                         float rscale, float pscale_inv, int prof, int resid_mode,
+                         const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
+                         hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = loglik_lds_bytes(N);
+  auto go = [&](auto kern) {
+    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, dim3(n), dim3(64), lds, s, dh, bin_off, gidx, params, psf, sigma, N,
+                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
+  };
+  if (prof == kProfExp) {
+    if (resid_mode) go(loglik_kernel<kProfExp, true>); else go(loglik_kernel<kProfExp, false>);
+  } else {
+    if (resid_mode) go(loglik_kernel<kProfGauss, true>); else go(loglik_kernel<kProfGauss, false>);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace bsi

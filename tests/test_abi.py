@@ -1,0 +1,98 @@
+"""C ABI checks that need no GPU: every declared symbol is exported, struct
+layouts agree between include/bsi.h and the Python binding, and calls without
+a device or handle fail cleanly."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "bsi.h")
+
+
+@pytest.fixture(scope="module")
+def native():
+    from paper_2604_22048_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_2604_22048_amd import build
+        build.build()
+    return _native
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsi_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(native):
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = native.load()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(native.SIGNATURES), set(names) ^ set(native.SIGNATURES)
+
+
+def test_struct_layouts_match_header(native):
+    prog = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "bsi.h"
+#define F(T, m) printf(#T "." #m " %zu\n", offsetof(T, m));
+int main(void) {
+  printf("bsi_batch %zu\n", sizeof(bsi_batch));
+  printf("bsi_interim %zu\n", sizeof(bsi_interim));
+  printf("bsi_hmc_cfg %zu\n", sizeof(bsi_hmc_cfg));
+  printf("bsi_true_prior %zu\n", sizeof(bsi_true_prior));
+  F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile)
+  F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
+  F(bsi_hmc_cfg, trace)
+  F(bsi_true_prior, mu_ln_f) F(bsi_true_prior, sigma_ln_f)
+  return 0;
+}
+"""
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        exe = os.path.join(d, "layout")
+        open(c, "w").write(prog)
+        subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe])
+        out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([exe], text=True).splitlines())
+    assert int(out["bsi_batch"]) == C.sizeof(native.Batch)
+    assert int(out["bsi_interim"]) == C.sizeof(native.Interim)
+    assert int(out["bsi_hmc_cfg"]) == C.sizeof(native.HmcCfg)
+    assert int(out["bsi_true_prior"]) == C.sizeof(native.TruePrior)
+    for key, val in out.items():
+        if "." in key:
+            t, m = key.split(".")
+            cls = {"bsi_batch": native.Batch, "bsi_hmc_cfg": native.HmcCfg,
+                   "bsi_true_prior": native.TruePrior}[t]
+            assert getattr(cls, m).offset == int(val), key
+
+
+def test_no_device_and_null_handle_paths(native):
+    lib = native.load()
+    n = C.c_int32(-1)
+    assert lib.bsi_device_count(C.byref(n)) == 0 and n.value >= 0
+    assert lib.bsi_version() == 1
+    if n.value == 0:
+        h = C.c_void_p()
+        assert lib.bsi_create(C.byref(h), 0) == -5
+        assert b"device" in lib.bsi_last_error(None)
+    b = native.Batch()
+    assert lib.bsi_render_stamps(None, C.byref(b), None, None, None) == -1
+    assert lib.bsi_loglik_grad(None, C.byref(b), None, None, None, None, None, 0, None) == -1
+    assert lib.bsi_ess(None, 1, 1, 10, 1, None, None, None, None) == -1
+    lib.bsi_destroy(None)
+    assert lib.bsi_device_count(None) == -1
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_2604_22048_amd import _native
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _native.load()

@@ -173,3 +173,22 @@ def test_init_chain_rule():
     th = hmc.init_chain(-d, 1.0, -0.2, (0.9, 0.0), seed=5, uid=4)
     assert abs(th[0] - math.log10(25.0)) < 1e-12     # floor sigma * N
     assert th[2] ** 2 + th[3] ** 2 < 0.95 ** 2
+
+
+def test_fisher_metric_matches_finite_difference_curvature():
+    # at the true parameters of a noiseless stamp the likelihood Hessian equals
+    # minus the Fisher information; check the diagonal by differences of U
+    N = 25
+    th = np.array([math.log10(400.0), math.log10(0.5), 0.2, -0.1, 0.1, -0.05])
+    ref = (0.1, -0.2)
+    prm = hmc.theta_to_params(th, ref)
+    d = render.render_one(prm, N, 0.2, 0.7)
+    gal = hmc.Galaxy(data=d, N=N, pixel_scale=0.2, psf_fwhm=0.7, sigma=1.0, ref_xy=ref)
+    im = hmc.fisher_inv_mass(gal, th)
+    for j in range(6):
+        h = 1e-4
+        e = np.zeros(6)
+        e[j] = h
+        curv = (hmc.potential(gal, th + e)[0] - 2 * hmc.potential(gal, th)[0] +
+                hmc.potential(gal, th - e)[0]) / (h * h)
+        assert abs(curv * im[j] - 1.0) < 2e-3, (j, curv, 1 / im[j])
