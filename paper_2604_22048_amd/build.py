@@ -27,9 +27,9 @@ FLAGS = [
 ]
 
 
-def _compile(src: str, bdir: str) -> str:
+def _compile(src: str, bdir: str, defines=()) -> str:
     obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -38,20 +38,21 @@ def _compile(src: str, bdir: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    bdir = os.path.join(PKG, "_build")
+def build(verbose: bool = False, out: str = OUT, bdir: str | None = None, defines=()) -> str:
+    """Compile every source and link `out`; `defines` are extra -D macros."""
+    bdir = bdir or os.path.join(PKG, "_build")
     os.makedirs(bdir, exist_ok=True)
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, bdir), SOURCES))
-    tmp = OUT + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, bdir, defines), SOURCES))
+    tmp = out + ".tmp"
     r = subprocess.run([HIPCC, "-shared", "--offload-arch=gfx950", "-Wl,-z,defs", "-o", tmp, *objs],
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
     if verbose:
-        print("built", OUT)
-    return OUT
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

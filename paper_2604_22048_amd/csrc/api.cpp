@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "bsi_kernels.h"
+#include "kspace.h"
 
 using namespace bsi;
 
@@ -110,11 +111,11 @@ Plan make_plan(const bsi_batch* b) {
   int64_t bins = 0;
   for (auto& kv : by) {
     ClassRange c{kv.first, (int)p.gidx.size(), (int)kv.second.size()};
-    const Geom g = make_geom(kv.first);
+    const SlotPlan sp = make_slot_plan(kv.first);
     for (int32_t i : kv.second) {
       p.gidx.push_back(i);
       p.bin_off[i] = bins;
-      bins += g.nbins;
+      bins += sp.nbins;
       p.max_pixel = std::max<int64_t>(p.max_pixel, b->off[i] + (int64_t)kv.first * kv.first);
     }
     p.classes.push_back(c);

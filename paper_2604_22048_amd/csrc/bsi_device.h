@@ -118,6 +118,45 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Wave-wide sums with DPP row shifts and row broadcasts (no LDS traffic): an
+// inclusive prefix sum within each row of 16 lanes, then rows combined by
+// broadcasting lanes 15 and 31; lane 63 ends with the total, which is read
+// back as a wave-uniform value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_shift_add(float x) {
+  return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, false));
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_shift_add(double x) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(v & 0xffffffffll), CTRL, ROW_MASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(v >> 32), CTRL, ROW_MASK, 0xf, false);
+  return x + __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_sum_dpp(T x) {
+  x = dpp_shift_add<0x111, 0xf>(x);   // row_shr:1
+  x = dpp_shift_add<0x112, 0xf>(x);   // row_shr:2
+  x = dpp_shift_add<0x114, 0xf>(x);   // row_shr:4
+  x = dpp_shift_add<0x118, 0xf>(x);   // row_shr:8
+  x = dpp_shift_add<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_shift_add<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return x;                           // total on lane 63
+}
+
+__device__ __forceinline__ float wave_total(float x) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(wave_sum_dpp(x)), 63));
+}
+
+__device__ __forceinline__ double wave_total(double x) {
+  const long long v = __double_as_longlong(wave_sum_dpp(x));
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 __device__ __forceinline__ float wave_max(float x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));

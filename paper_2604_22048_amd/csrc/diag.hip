@@ -99,7 +99,7 @@ hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, floa
                       float* rhat, hipStream_t s) {
   if (n_gal <= 0) return hipSuccess;
   const size_t lds = sizeof(double) * ((size_t)C * S + 256);
-  hipFuncSetAttribute((const void*)ess_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute((const void*)ess_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(ess_kernel, dim3(n_gal * P), dim3(256), lds, s, C, S, P, samples, ess, rhat);
   return hipGetLastError();
 }

@@ -30,14 +30,34 @@ constexpr float kEClamp = 1.0f - 1e-6f;
 
 struct GalCtx {
   Geom g;
+  SlotPlan sp;
   const float2* dh;
   const float* atab;
-  float2* X;
-  float2* Y;
+  float2* X;       // per-wave tables (see fill_tables); the Fisher metric reuses
+  float2* Ym;      // X and Ym as full x and y tables
+  float2* Yf;
   float norm;      // 1 / (N^2 sigma^2)
   float rscale;
   float refx, refy;
 };
+
+// Plain separable tables over the full frequency range (Fisher metric only):
+// X[u+h] = a(u) exp(-i k_u dx), Y[v+h] = a(v) exp(-i k_v dy).
+__device__ __forceinline__ void fill_xy_full(const Geom& g, const float* __restrict__ atab, float2* X,
+                                             float2* Y, float dx, float dy) {
+  const int lane = lane_id();
+  const float two_over_n = 2.0f / (float)g.N;
+  for (int t = lane; t < g.ntab; t += kWave) {
+    const float u = (float)(t - g.h);
+    const float a = atab[t];
+    float s, c;
+    sincospif(u * dx * two_over_n, &s, &c);
+    X[t] = make_float2(a * c, -a * s);
+    sincospif(u * dy * two_over_n, &s, &c);
+    Y[t] = make_float2(a * c, -a * s);
+  }
+  wave_lds_sync();
+}
 
 struct Prior {
   float lf_lo, lf_hi, ls_lo, ls_hi, sd, se;
@@ -52,9 +72,9 @@ __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
 // Outside the support U = +inf and the gradient is evaluated at the nearest
 // admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
 // trajectory can continue (it is rejected anyway).
-template <int PROF>
-__device__ __forceinline__ double potential(const GalCtx& c, const Prior& pr, const float* th,
-                                            float* gU, uint32_t& status) {
+template <int PROF, int P>
+__device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& lc, const Prior& pr,
+                                            const float* th, float* gU, uint32_t& status) {
   const bool inside = in_support(th, pr);
   float t0 = fminf(fmaxf(th[0], pr.lf_lo), pr.lf_hi);
   float t1 = fminf(fmaxf(th[1], pr.ls_lo), pr.ls_hi);
@@ -68,14 +88,14 @@ __device__ __forceinline__ double potential(const GalCtx& c, const Prior& pr, co
   }
   const float F = exp10f(t0), s = exp10f(t1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
-  fill_xy(c.g, c.atab, c.X, c.Y, dx, dy);
+  fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
   const Shape sh = make_shape(s * c.rscale, e1, e2);
-  const KSums S = kspace_sums<PROF>(c.g, c.dh, c.X, c.Y, F, sh);
+  const KSums S = kspace_sums<PROF, P>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
   const double isd2 = 1.0 / ((double)pr.sd * pr.sd);
   const double ise2 = 1.0 / ((double)pr.se * pr.se);
   const double lp = -0.5 * ((double)th[4] * th[4] + (double)th[5] * th[5]) * isd2 +
-                    2.0 * log(1.0 - (double)E) - 0.5 * (double)E * ise2;
+                    (double)(2.0f * __logf(1.0f - E)) - 0.5 * (double)E * ise2;
   const float cpri = -4.0f / (1.0f - E) - (float)ise2;
   gU[0] = -r.dF * F * kLn10F;
   gU[1] = -r.ds * s * kLn10F;
@@ -109,7 +129,8 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
     E = e1 * e1 + e2 * e2;
   }
   const float F = exp10f(t0), s = exp10f(t1);
-  fill_xy(g, c.atab, c.X, c.Y, c.refx + th[4], c.refy + th[5]);
+  float2* Y = c.Ym;   // the per-wave region holds 2 ntab + ymax entries
+  fill_xy_full(g, c.atab, c.X, Y, c.refx + th[4], c.refy + th[5]);
   const Shape sh = make_shape(s * c.rscale, e1, e2);
   const float cg = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;
   // accumulate sum_c |dM/dp|^2 over every bin, frequency points combined per bin
@@ -133,7 +154,7 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
         const int v = (nv == 2) ? (av == 0 ? -g.h : g.h) : vb;
         const float cv = (nv == 2) ? (av == 0 ? 0.5f : -0.5f) : 1.0f;
         const float kx = u * g.kstep, ky = v * g.kstep;
-        const float2 xu = c.X[u + g.h], yv = c.Y[v + g.h];
+        const float2 xu = c.X[u + g.h], yv = Y[v + g.h];
         const float kx2 = kx * kx, ky2 = ky * ky, kxy = kx * ky;
         const float q = fmaf(sh.ca, kx2, fmaf(sh.cb, ky2, sh.cc * kxy));
         float G, ia;
@@ -159,7 +180,7 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
   }
   float fi[6];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) fi[j] = wave_sum(acc[j]) * c.norm;
+  for (int j = 0; j < 6; ++j) fi[j] = wave_total(acc[j]) * c.norm;
   fi[0] *= F * F * kLn10F * kLn10F;
   fi[1] *= s * s * kLn10F * kLn10F;
   const float ise2 = 1.0f / (pr.se * pr.se), omE = 1.0f - E;
@@ -172,33 +193,48 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
 }
 
 // Stage one galaxy's data spectrum and PSF-sinc table in LDS.
-__device__ void stage_galaxy(const HmcArgs& a, int gal, const Geom& g, float2* dh, float* atab) {
-  const float2* src = a.dh + a.bin_off[gal];
-  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) dh[b] = src[b];
-  const float sp = a.psf[gal] * 0.42466090014400953f * a.pscale_inv;
+__device__ void stage_galaxy(const HmcArgs& a, int gal, const Geom& g, const SlotPlan& sp,
+                             float2* dh, float* atab) {
+  const float4* src = reinterpret_cast<const float4*>(a.dh + a.bin_off[gal]);
+  float4* d4 = reinterpret_cast<float4*>(dh);
+  for (int b = threadIdx.x; b < sp.nbins / 2; b += blockDim.x) d4[b] = src[b];
+  if ((sp.nbins & 1) && threadIdx.x == 0) dh[sp.nbins - 1] = a.dh[a.bin_off[gal] + sp.nbins - 1];
+  const float spsf = a.psf[gal] * 0.42466090014400953f * a.pscale_inv;
   for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
     const int u = t - g.h;
     const double k = 2.0 * 3.14159265358979323846 * u / g.N;
     const double sn = (u == 0) ? 1.0 : sinpi((double)u / g.N) / (3.14159265358979323846 * u / g.N);
-    atab[t] = (float)(exp(-0.5 * (double)sp * sp * k * k) * sn);
+    atab[t] = (float)(exp(-0.5 * (double)spsf * spsf * k * k) * sn);
   }
 }
 
 struct Lds {
   float2* dh;
   float* atab;
+  float4* cols;       // per-slot column table (shared)
+  ChainState* cs;     // this wave's chain record
   float2* X;
-  float2* Y;
+  float2* Ym;
+  float2* Yf;
 };
 
-__device__ __forceinline__ Lds carve(const Geom& g, int wave) {
+__device__ __forceinline__ int wave_table_len(const Geom& g, const SlotPlan& sp) {
+  return 2 * g.ntab + sp.ymax;
+}
+
+// LDS: [data spectrum | atab | column table | C chain records | C table sets]
+__device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave, int C) {
   extern __shared__ float4 smem4[];
   Lds l;
   l.dh = reinterpret_cast<float2*>(smem4);
-  l.atab = reinterpret_cast<float*>(l.dh + g.nbins);
-  float2* w0 = reinterpret_cast<float2*>(l.atab + ((g.ntab + 1) & ~1));
-  l.X = w0 + 2 * g.ntab * wave;
-  l.Y = l.X + g.ntab;
+  l.atab = reinterpret_cast<float*>(l.dh + ((sp.nbins + 1) & ~1));
+  l.cols = reinterpret_cast<float4*>(l.atab + ((g.ntab + 3) & ~3));
+  ChainState* cs0 = reinterpret_cast<ChainState*>(l.cols + sp.P * 64);
+  l.cs = cs0 + wave;
+  float2* w0 = reinterpret_cast<float2*>(cs0 + C);
+  l.X = w0 + wave_table_len(g, sp) * wave;
+  l.Ym = l.X + g.ntab;
+  l.Yf = l.Ym + sp.ymax;
   return l;
 }
 
@@ -319,114 +355,181 @@ __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_
   u_jit = u01(bcast(w.x, 3));
 }
 
-template <int PROF>
-__device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const Prior& pr, Regs& r,
-                              uint32_t uid, float* samples_chain, float* trace_chain) {
+// Values the leapfrog touches every step stay in registers; the rest of the
+// chain state lives in the wave's LDS record and is read and written (by
+// lane 0) only at trajectory boundaries.
+struct Hot {
+  float th[6], p[6], g[6], im[6];
+  double Uth;
+  float eps_t;
+  int l, ok, t;
+  uint32_t status;
+};
+
+__device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
+
+template <int PROF, int P>
+__device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
+                              const Prior& pr, ChainState* cs, uint32_t uid, float* samples_chain,
+                              float* trace_chain) {
   const int lane = lane_id();
+  Hot h;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    h.th[j] = cs->th[j];
+    h.p[j] = cs->p[j];
+    h.g[j] = cs->g[j];
+    h.im[j] = cs->inv_mass[j];
+  }
+  h.Uth = cs->Uth;
+  h.eps_t = cs->eps_t;
+  h.l = cs->l;
+  h.ok = cs->ok;
+  h.t = cs->t;
+  h.status = cs->status;
   for (int step = 0; step < a.n_steps; ++step) {
-    if (r.t >= a.t_stop) break;
-    if (r.l == 0) {
-      float z[6], u_jit;
-      draw_iteration(uid, (uint32_t)r.t, a.k0, a.k1, z, r.u_acc, u_jit);
-      r.eps_t = r.eps;
+    if (h.t >= a.t_stop) break;
+    if (h.l == 0) {
+      float z[6], u_acc, u_jit;
+      draw_iteration(uid, (uint32_t)h.t, a.k0, a.k1, z, u_acc, u_jit);
+      const float eps = cs->eps;
+      h.eps_t = eps;
       if (a.jitter > 0.0f)
-        r.eps_t = (float)((double)r.eps * (1.0 + (double)a.jitter * (2.0 * (double)u_jit - 1.0)));
+        h.eps_t = (float)((double)eps * (1.0 + (double)a.jitter * (2.0 * (double)u_jit - 1.0)));
       double ke = 0.0;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        r.p[j] = (float)((double)z[j] / sqrt((double)r.im[j]));
-        ke += (double)r.im[j] * (double)r.p[j] * (double)r.p[j];
-        r.th[j] = r.theta[j];
-        r.g[j] = r.grad[j];
+        h.p[j] = (float)((double)z[j] / sqrt((double)h.im[j]));
+        ke += (double)h.im[j] * (double)h.p[j] * (double)h.p[j];
+        h.th[j] = cs->theta[j];
+        h.g[j] = cs->grad[j];
       }
-      r.H0 = r.U + 0.5 * ke;
-      r.ok = 1;
+      const double H0 = cs->U + 0.5 * ke;
+      lane0_sync();
+      if (lane == 0) {
+        cs->H0 = H0;
+        cs->u_acc = u_acc;
+      }
+      lane0_sync();
+      h.ok = 1;
 #pragma unroll
-      for (int j = 0; j < 6; ++j) r.p[j] -= 0.5f * r.eps_t * r.g[j];
+      for (int j = 0; j < 6; ++j) h.p[j] -= 0.5f * h.eps_t * h.g[j];
     }
 #pragma unroll
-    for (int j = 0; j < 6; ++j) r.th[j] += r.eps_t * r.im[j] * r.p[j];
+    for (int j = 0; j < 6; ++j) h.th[j] += h.eps_t * h.im[j] * h.p[j];
     uint32_t st = 0;
-    r.Uth = potential<PROF>(c, pr, r.th, r.g, st);
-    r.status |= st;
-    if (!in_support(r.th, pr)) r.ok = 0;
-    r.l += 1;
-    if (r.l < a.L) {
+    h.Uth = potential<PROF, P>(c, lc, pr, h.th, h.g, st);
+    h.status |= st;
+    if (!in_support(h.th, pr)) h.ok = 0;
+    h.l += 1;
+    if (h.l < a.L) {
 #pragma unroll
-      for (int j = 0; j < 6; ++j) r.p[j] -= r.eps_t * r.g[j];
+      for (int j = 0; j < 6; ++j) h.p[j] -= h.eps_t * h.g[j];
       continue;
     }
+    // end of trajectory: Metropolis test, adaptation, output
 #pragma unroll
-    for (int j = 0; j < 6; ++j) r.p[j] -= 0.5f * r.eps_t * r.g[j];
+    for (int j = 0; j < 6; ++j) h.p[j] -= 0.5f * h.eps_t * h.g[j];
     double ke = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) ke += (double)r.im[j] * (double)r.p[j] * (double)r.p[j];
-    const double dH = r.Uth + 0.5 * ke - r.H0;
+    for (int j = 0; j < 6; ++j) ke += (double)h.im[j] * (double)h.p[j] * (double)h.p[j];
+    const double dH = h.Uth + 0.5 * ke - cs->H0;
     const bool finite = isfinite(dH);
-    const bool accept = r.ok && finite && log((double)r.u_acc) < -dH;
-    const double alpha = (r.ok && finite) ? fmin(1.0, exp(-dH)) : 0.0;
-    if (!finite || fabs(dH) > kDivergence) {
-      r.n_div += 1;
-      r.status |= finite ? 4u : 2u;
-    }
+    const bool accept = h.ok && finite && log((double)cs->u_acc) < -dH;
+    const double alpha = (h.ok && finite) ? fmin(1.0, exp(-dH)) : 0.0;
+    if (!finite || fabs(dH) > kDivergence) h.status |= finite ? 4u : 2u;
+    const float eps_used = cs->eps;
     if (trace_chain && lane < 4) {
-      const float v = lane == 0 ? r.eps : lane == 1 ? (float)dH : lane == 2 ? (float)alpha
-                                                                 : (accept ? 1.0f : 0.0f);
-      trace_chain[(int64_t)r.t * 4 + lane] = v;
+      const float v = lane == 0 ? eps_used : lane == 1 ? (float)dH : lane == 2 ? (float)alpha
+                                                                    : (accept ? 1.0f : 0.0f);
+      trace_chain[(int64_t)h.t * 4 + lane] = v;
     }
-    if (accept) {
+    lane0_sync();
+    if (lane == 0) {
+      if (!finite || fabs(dH) > kDivergence) cs->n_div += 1;
+      if (accept) {
 #pragma unroll
-      for (int j = 0; j < 6; ++j) {
-        r.theta[j] = r.th[j];
-        r.grad[j] = r.g[j];
+        for (int j = 0; j < 6; ++j) {
+          cs->theta[j] = h.th[j];
+          cs->grad[j] = h.g[j];
+        }
+        cs->U = h.Uth;
       }
-      r.U = r.Uth;
+      if (h.t < a.W) {
+        if (a.adapt) {
+          const double m = (double)(h.t + 1);
+          const double eta = 1.0 / (m + kDaT0);
+          const double hbar = (1.0 - eta) * cs->hbar + eta * ((double)a.delta - alpha);
+          const double le = (double)a.mu - sqrt(m) / kDaGamma * hbar;
+          const double x = pow(m, -kDaKappa);
+          const double lbar = x * le + (1.0 - x) * cs->log_eps_bar;
+          cs->hbar = hbar;
+          cs->log_eps_bar = lbar;
+          cs->eps = (h.t == a.W - 1) ? (float)exp(lbar) : (float)exp(le);
+        }
+      } else {
+        cs->n_acc += accept ? 1 : 0;
+        cs->sum_alpha += (float)alpha;
+      }
     }
-    if (r.t < a.W) {
-      if (a.adapt) {
-        const double m = (double)(r.t + 1);
-        const double eta = 1.0 / (m + kDaT0);
-        r.hbar = (1.0 - eta) * r.hbar + eta * ((double)a.delta - alpha);
-        const double le = (double)a.mu - sqrt(m) / kDaGamma * r.hbar;
-        const double x = pow(m, -kDaKappa);
-        r.lbar = x * le + (1.0 - x) * r.lbar;
-        r.eps = (float)exp(le);
-        if (r.t == a.W - 1) r.eps = (float)exp(r.lbar);
-      }
-    } else {
-      if (samples_chain && lane < 6) {
-        float v = r.theta[0];
+    lane0_sync();
+    if (h.t >= a.W && samples_chain && lane < 6) {
+      float v = cs->theta[0];
 #pragma unroll
-        for (int j = 1; j < 6; ++j) v = (lane == j) ? r.theta[j] : v;
-        samples_chain[(int64_t)(r.t - a.W) * 6 + lane] = v;
-      }
-      r.n_acc += accept ? 1 : 0;
-      r.sum_alpha += (float)alpha;
+      for (int j = 1; j < 6; ++j) v = (lane == j) ? cs->theta[j] : v;
+      samples_chain[(int64_t)(h.t - a.W) * 6 + lane] = v;
     }
-    r.t += 1;
-    r.l = 0;
+    h.t += 1;
+    h.l = 0;
   }
+  lane0_sync();
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      cs->th[j] = h.th[j];
+      cs->p[j] = h.p[j];
+      cs->g[j] = h.g[j];
+    }
+    cs->Uth = h.Uth;
+    cs->eps_t = h.eps_t;
+    cs->l = h.l;
+    cs->ok = h.ok;
+    cs->t = h.t;
+    cs->status = h.status;
+  }
+  lane0_sync();
 }
 
-template <int PROF, bool INIT>
-__global__ void __launch_bounds__(1024) hmc_kernel(HmcArgs a) {
+// Minimum resident waves per SIMD requested from the register allocator for
+// the trajectory kernel (occupancy against instruction-level parallelism).
+#ifndef BSI_HMC_WAVES_PER_EU
+#define BSI_HMC_WAVES_PER_EU 2
+#endif
+
+template <int PROF, bool INIT, int P, int MAXT>
+__global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   const Geom g = make_geom(a.N);
+  const SlotPlan sp = make_slot_plan(a.N);
   const int wave = threadIdx.x / kWave;
-  const Lds l = carve(g, wave);
+  const Lds l = carve(g, sp, wave, a.C);
+  build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e};
   for (int gi = blockIdx.x; gi < a.n_gal; gi += gridDim.x) {
     const int gal = a.gidx[gi];
     __syncthreads();
-    stage_galaxy(a, gal, g, l.dh, l.atab);
+    stage_galaxy(a, gal, g, sp, l.dh, l.atab);
     __syncthreads();
     if (wave >= a.C) continue;
+    const LaneCols<P> lc = lane_cols<P>(l.cols);
     const float sig = a.sigma[gal];
     GalCtx c;
     c.g = g;
+    c.sp = sp;
     c.dh = l.dh;
     c.atab = l.atab;
     c.X = l.X;
-    c.Y = l.Y;
+    c.Ym = l.Ym;
+    c.Yf = l.Yf;
     c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
     c.rscale = a.rscale;
     c.refx = a.ref_xy[2 * (int64_t)gal];
@@ -446,7 +549,7 @@ __global__ void __launch_bounds__(1024) hmc_kernel(HmcArgs a) {
         for (int j = 0; j < 6; ++j) r.im[j] = a.inv_mass ? a.inv_mass[(int64_t)gal * 6 + j] : 1.0f;
       }
       uint32_t stt = 0;
-      r.U = potential<PROF>(c, pr, r.theta, r.grad, stt);
+      r.U = potential<PROF, P>(c, lc, pr, r.theta, r.grad, stt);
       r.status = stt;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
@@ -469,11 +572,13 @@ __global__ void __launch_bounds__(1024) hmc_kernel(HmcArgs a) {
       r.n_div = 0;
       store_state(st, r);
     } else {
-      Regs r = load_state(st);
+      uint32_t* csw = reinterpret_cast<uint32_t*>(l.cs);
+      csw[lane_id()] = reinterpret_cast<const uint32_t*>(st)[lane_id()];
+      wave_lds_sync();
       float* sc = a.samples ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = a.trace ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF>(a, c, pr, r, uid, sc, tc);
-      store_state(st, r);
+      advance_chain<PROF, P>(a, c, lc, pr, l.cs, uid, sc, tc);
+      reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
     }
   }
 }
@@ -501,24 +606,47 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 size_t hmc_lds_bytes(int N, int C) {
   const Geom g = make_geom(N);
-  return sizeof(float2) * g.nbins + sizeof(float) * ((g.ntab + 1) & ~1) +
-         2 * sizeof(float2) * g.ntab * C;
+  const SlotPlan sp = make_slot_plan(N);
+  return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
+         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C +
+         sizeof(float2) * (2 * g.ntab + sp.ymax) * C;
+}
+
+template <int PROF, bool INIT, int P>
+static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  const dim3 blk(kWave * a.C);
+  if (a.C <= 4) {
+    auto k = hmc_kernel<PROF, INIT, P, 256>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
+  } else {
+    auto k = hmc_kernel<PROF, INIT, P, 1024>;
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
+  }
+}
+
+template <int PROF, bool INIT>
+static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  switch (make_slot_plan(a.N).P) {
+    case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
+    case 2: launch_p<PROF, INIT, 2>(a, grid, lds, s); break;
+    case 3: launch_p<PROF, INIT, 3>(a, grid, lds, s); break;
+    case 4: launch_p<PROF, INIT, 4>(a, grid, lds, s); break;
+    case 5: launch_p<PROF, INIT, 5>(a, grid, lds, s); break;
+    case 6: launch_p<PROF, INIT, 6>(a, grid, lds, s); break;
+    default: launch_p<PROF, INIT, 8>(a, grid, lds, s); break;
+  }
 }
 
 template <bool INIT>
 static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   if (a.n_gal <= 0) return hipSuccess;
   const size_t lds = hmc_lds_bytes(a.N, a.C);
-  const dim3 blk(kWave * a.C);
-  if (a.prof == kProfExp) {
-    hipFuncSetAttribute((const void*)hmc_kernel<kProfExp, INIT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((hmc_kernel<kProfExp, INIT>), dim3(grid), blk, lds, s, a);
-  } else {
-    hipFuncSetAttribute((const void*)hmc_kernel<kProfGauss, INIT>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((hmc_kernel<kProfGauss, INIT>), dim3(grid), blk, lds, s, a);
-  }
+  if (a.prof == kProfExp)
+    launch_prof<kProfExp, INIT>(a, grid, lds, s);
+  else
+    launch_prof<kProfGauss, INIT>(a, grid, lds, s);
   return hipGetLastError();
 }
 

@@ -14,6 +14,21 @@
 // dT/ds = -3 r0^2 q / (s (1 + r0^2 q)) T, dT/de = -3/2 r0^2 (dq/de) /
 // (1 + r0^2 q) T (exponential profile), dT/d(dx, dy) = -i (k_x, k_y) T, so
 // every gradient component is a weighted sum of Re or Im of conj(R) T.
+//
+// Work layout ("slot plan"): the odd core of the grid, |u|, |v| <= hc, is
+// walked as rows v = 0..hc.  Row 0 is taken whole with weight 1 (it holds
+// each mirror pair once and the DC bin), rows v > 0 with weight 2 (their
+// mirrors, v < 0, are not stored).  R consecutive rows form a super-row of
+// R * nc slots, spread over P iterations of the 64 lanes: lane l in iteration
+// i owns slot s = l + 64 i, i.e. row offset s / nc and column s % nc, the
+// same for every super-row.  Column quantities (k_x, the x factor of the
+// spectrum) are therefore lane constants, and the data spectrum is stored in
+// slot order so that each bin is one LDS read at a fixed offset.  Slots past
+// R * nc and rows past hc carry zero data and a zero spectrum factor, and
+// row 0 carries a 1/sqrt(2) factor in both, so the loop is branch-free and
+// every sum is doubled at the end.  (R, P) is chosen per N to minimise the
+// number of slots (lane utilisation 85-97 % for the stamp sizes in use).
+// The Nyquist bins of an even N follow the slots as "special" bins.
 #pragma once
 
 #include "bsi_device.h"
@@ -22,9 +37,65 @@ namespace bsi {
 
 enum { kProfExp = 0, kProfGauss = 1 };
 
+// Supported iterations per super-row (template instances of the bin loop).
+constexpr int kPlanP[] = {1, 2, 3, 4, 5, 6, 8};
+
+struct SlotPlan {
+  int R, P, nsr;      // rows per super-row, iterations per super-row, super-rows
+  int nslots;         // nsr * P * 64
+  int ymax;           // nsr * R rows covered (>= hc + 1)
+  int nspec;          // special (Nyquist) bins after the slots: N + 1 for even N, else 0
+  int nbins;          // nslots + nspec: length of the stored data spectrum
+};
+
+__host__ __device__ inline SlotPlan make_slot_plan(int N) {
+  const int nc = (N & 1) ? N : N - 1;
+  const int rows = (nc - 1) / 2 + 1;
+  SlotPlan best{0, 0, 0, 1 << 30, 0, 0, 0};
+  for (int k = 0; k < 7; ++k) {
+    const int P = kPlanP[k];
+#ifdef BSI_PLAN_P
+    if (P != BSI_PLAN_P) continue;
+#endif
+    const int R = (64 * P) / nc;
+    if (R < 1) continue;
+    const int Rr = R < rows ? R : rows;
+    const int nsr = (rows + Rr - 1) / Rr;
+    const int slots = nsr * P * 64;
+    if (slots < best.nslots) best = SlotPlan{Rr, P, nsr, slots, nsr * Rr, 0, 0};
+  }
+  best.nspec = (N & 1) ? 0 : N + 1;
+  best.nbins = best.nslots + best.nspec;
+  return best;
+}
+
+// Slot -> (u, v) or invalid.  Row 0 data are stored scaled by 1/sqrt(2).
+__host__ __device__ inline bool slot_uv(int N, const SlotPlan& sp, int slot, int& u, int& v) {
+  const int nc = (N & 1) ? N : N - 1;
+  const int hc = (nc - 1) / 2;
+  const int per = sp.P * 64;
+  const int sr = slot / per, s = slot - sr * per;
+  if (s >= sp.R * nc) return false;
+  const int ro = s / nc;
+  v = sr * sp.R + ro;
+  u = s - ro * nc - hc;
+  return v <= hc;
+}
+
+// Special (Nyquist) bin i of an even N -> DFT bin (u_b, v_b), Nyquist bins
+// at frequency -N/2, and its multiplicity c in a full-grid sum.
+__host__ __device__ inline void nyq_bin_uv(int N, int i, int& u, int& v, int& c) {
+  const int h = N / 2;
+  if (i == 0) { u = -h; v = 0; c = 1; return; }
+  if (i == 1) { u = 0; v = -h; c = 1; return; }
+  if (i < h + 1) { u = i - 1; v = -h; c = 2; return; }        // u = 1..h-1
+  if (i == h + 1) { u = -h; v = -h; c = 1; return; }
+  u = -h; v = i - (h + 1); c = 2;                               // v = 1..h-1
+}
+
 struct KSums {
   double chi2;                                    // sum over the full grid of |D - M|^2
-  float sF, sxx, syy, sxy, sq, sdx, sdy;          // weighted Re/Im sums (see below)
+  float sF, sxx, syy, sxy, sq, sdx, sdy;          // weighted Re/Im sums
 };
 
 struct KResult {
@@ -63,75 +134,157 @@ __device__ __forceinline__ void profile_factor(const Shape& sh, float q, float& 
   }
 }
 
-// Fill this wave's separable factor tables: X[u+h] = a(u) exp(-i k_u dx),
-// Y[v+h] = a(v) exp(-i k_v dy), a(u) = PSF(k_u) sinc(u/N).
-__device__ __forceinline__ void fill_xy(const Geom& g, const float* __restrict__ atab, float2* X,
-                                        float2* Y, float dx, float dy) {
+// Geometry of one stamp size: grid sizes, slot plan and this lane's columns.
+template <int P>
+struct LaneCols {
+  float kx[P];       // k_x of the lane's column in iteration i (0 if unused)
+  float rok[P];      // row offset * kstep
+  int xi[P];         // index into the X table (u + h), or -1 if the slot is unused
+  int yo[P];         // row offset within the super-row
+};
+
+// Per-slot column table shared by the workgroup: entry (i, lane) =
+// {k_x, row offset * kstep, X index (-1 if unused), row offset}.
+__device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& sp, float4* tab) {
+  for (int t = threadIdx.x; t < sp.P * 64; t += blockDim.x) {
+    float4 e = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(0));
+    if (t < sp.R * g.nc) {
+      const int ro = t / g.nc;
+      const int u = t - ro * g.nc - g.hc;
+      e = make_float4((float)u * g.kstep, (float)ro * g.kstep, __int_as_float(u + g.h),
+                      __int_as_float(ro));
+    }
+    tab[t] = e;
+  }
+}
+
+template <int P>
+__device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
+  LaneCols<P> c;
+  const int lane = lane_id();
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const float4 e = tab[lane + 64 * i];
+    c.kx[i] = e.x;
+    c.rok[i] = e.y;
+    c.xi[i] = __float_as_int(e.z);
+    c.yo[i] = __float_as_int(e.w);
+  }
+  return c;
+}
+
+// Per-wave LDS tables of one evaluation.
+//   X [ntab]  : F a(u) exp(-i k_u dx),   u = -h..h
+//   Ym[ymax]  : a(v) exp(-i k_v dy) for rows v = 0..ymax-1 (row 0 / sqrt 2, rows > hc zero)
+//   Yf[ntab]  : a(v) exp(-i k_v dy),     v = -h..h (even N only, for the Nyquist bins)
+// with a(u) = PSF(k_u) sinc(u/N) from atab.
+__device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
+                                            const float* __restrict__ atab, float2* X, float2* Ym,
+                                            float2* Yf, float F, float dx, float dy) {
   const int lane = lane_id();
   const float two_over_n = 2.0f / (float)g.N;
   for (int t = lane; t < g.ntab; t += kWave) {
     const float u = (float)(t - g.h);
-    const float a = atab[t];
+    const float a = F * atab[t];
     float s, c;
     sincospif(u * dx * two_over_n, &s, &c);
     X[t] = make_float2(a * c, -a * s);
-    sincospif(u * dy * two_over_n, &s, &c);
-    Y[t] = make_float2(a * c, -a * s);
+  }
+  const bool even = (g.N & 1) == 0;
+  for (int v = lane; v < sp.ymax; v += kWave) {
+    float2 y = make_float2(0.f, 0.f);
+    if (v <= g.hc) {
+      const float a = atab[v + g.h] * (v == 0 ? 0.70710678118654752f : 1.0f);
+      float s, c;
+      sincospif((float)v * dy * two_over_n, &s, &c);
+      y = make_float2(a * c, -a * s);
+    }
+    Ym[v] = y;
+  }
+  if (even) {
+    for (int t = lane; t < g.ntab; t += kWave) {
+      const float v = (float)(t - g.h);
+      const float a = atab[t];
+      float s, c;
+      sincospif(v * dy * two_over_n, &s, &c);
+      Yf[t] = make_float2(a * c, -a * s);
+    }
   }
   wave_lds_sync();
 }
 
-// Accumulate the k-space sums of one wave.  dh: DFT of the data at the bins
-// (main bins then special bins), or with RESID the DFT of the pixel
-// residual d - m itself.  F: flux.  Result is lane-uniform.
-template <int PROF, bool RESID = false>
-__device__ KSums kspace_sums(const Geom& g, const float2* __restrict__ dh, const float2* X,
-                             const float2* Y, float F, const Shape& sh) {
+// Accumulate the k-space sums of one wave.  dh: the data spectrum (or, with
+// RESID, the spectrum of the pixel residual d - m) in slot order followed by
+// the Nyquist bins.  The X table already contains the flux.  Result is
+// lane-uniform.
+template <int PROF, int P, bool RESID = false>
+__device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P>& lc,
+                             const float2* __restrict__ dh, const float2* X, const float2* Ym,
+                             const float2* Yf, const Shape& sh) {
   const int lane = lane_id();
-  double chi2 = 0.0;
-  float sF = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f, sq = 0.f, sdx = 0.f, sdy = 0.f;
-  const float ks = g.kstep;
-  const int h = g.h;
-
-  // Main bins: one frequency point each, multiplicity 2.
-  for (int b = lane; b < g.nmain; b += kWave) {
-    int u, v;
-    main_bin_uv(g, b, u, v);
-    const float kx = (float)u * ks, ky = (float)v * ks;
-    const float2 D = dh[b];
-    const float2 xu = X[u + h], yv = Y[v + h];
-    const float pr = fmaf(xu.x, yv.x, -xu.y * yv.y);
-    const float pi = fmaf(xu.x, yv.y, xu.y * yv.x);
-    const float kx2 = kx * kx, ky2 = ky * ky, kxy = kx * ky;
-    const float q = fmaf(sh.ca, kx2, fmaf(sh.cb, ky2, sh.cc * kxy));
-    float G, ia;
-    profile_factor<PROF>(sh, q, G, ia);
-    const float amp = F * G;
-    const float Tr = amp * pr, Ti = amp * pi;
-    const float Rr = RESID ? D.x : D.x - Tr, Ri = RESID ? D.y : D.y - Ti;
-    chi2 += (double)fmaf(Rr, Rr, Ri * Ri);
-    const float zr = fmaf(Rr, Tr, Ri * Ti);
-    const float zi = fmaf(Rr, Ti, -Ri * Tr);
-    sF += zr;
-    const float wq = zr * ia;
-    sxx = fmaf(kx2, wq, sxx);
-    syy = fmaf(ky2, wq, syy);
-    sxy = fmaf(kxy, wq, sxy);
-    sq = fmaf(q, wq, sq);
-    sdx = fmaf(kx, zi, sdx);
-    sdy = fmaf(ky, zi, sdy);
+  float xr[P], xim[P], A[P], Cc[P], kx2[P];
+  const float2* yp[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const float2 x = lc.xi[i] >= 0 ? X[lc.xi[i]] : make_float2(0.f, 0.f);
+    xr[i] = x.x;
+    xim[i] = x.y;
+    kx2[i] = lc.kx[i] * lc.kx[i];
+    A[i] = sh.ca * kx2[i];
+    Cc[i] = sh.cc * lc.kx[i];
+    yp[i] = Ym + lc.yo[i];
   }
+  double chi2 = 0.0;
+  float sF = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f, sdx = 0.f, sdy = 0.f;
+  float wky[P];                       // per column: sum of k_y w (times k_x at the end)
+#pragma unroll
+  for (int i = 0; i < P; ++i) wky[i] = 0.f;
+  const float2* dp = dh + lane;
+  for (int sr = 0; sr < sp.nsr; ++sr) {
+    const float v0k = (float)(sr * sp.R) * g.kstep;
+    float c2 = 0.f;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const float2 D = dp[i * 64];
+      const float2 y = yp[i][sr * sp.R];
+      const float ky = lc.rok[i] + v0k;
+      const float ky2 = ky * ky;
+      const float q = fmaf(Cc[i], ky, fmaf(sh.cb, ky2, A[i]));
+      float G, ia;
+      profile_factor<PROF>(sh, q, G, ia);
+      const float pr = fmaf(xr[i], y.x, -xim[i] * y.y);
+      const float pi = fmaf(xr[i], y.y, xim[i] * y.x);
+      const float Tr = G * pr, Ti = G * pi;
+      const float Rr = RESID ? D.x : D.x - Tr, Ri = RESID ? D.y : D.y - Ti;
+      c2 = fmaf(Rr, Rr, fmaf(Ri, Ri, c2));
+      const float zr = fmaf(Rr, Tr, Ri * Ti);
+      const float zi = fmaf(Rr, Ti, -Ri * Tr);
+      sF += zr;
+      const float wq = zr * ia;
+      sxx = fmaf(kx2[i], wq, sxx);
+      syy = fmaf(ky2, wq, syy);
+      wky[i] = fmaf(ky, wq, wky[i]);
+      sdx = fmaf(lc.kx[i], zi, sdx);
+      sdy = fmaf(ky, zi, sdy);
+    }
+    chi2 += (double)c2;
+    dp += P * 64;
+  }
+#pragma unroll
+  for (int i = 0; i < P; ++i) sxy = fmaf(lc.kx[i], wky[i], sxy);
   chi2 *= 2.0;
-  sF *= 2.f; sxx *= 2.f; syy *= 2.f; sxy *= 2.f; sq *= 2.f; sdx *= 2.f; sdy *= 2.f;
+  sF *= 2.f; sxx *= 2.f; syy *= 2.f; sxy *= 2.f; sdx *= 2.f; sdy *= 2.f;
 
-  // Special bins: DC (all N) and the Nyquist bins of an even N.
-  const bool even = (g.N & 1) == 0;
-  for (int i = lane; i < g.nspec; i += kWave) {
+  // Nyquist bins of an even N: each combines the frequency points +-N/2
+  // (weights 1/2, sign -1 on +N/2) on its Nyquist axis or axes.
+  const int h = g.h;
+  const float ks = g.kstep;
+  for (int i = lane; i < sp.nspec; i += kWave) {
     int ub, vb, c;
-    spec_bin_uv(g.N, i, ub, vb, c);
-    const float2 D = dh[g.nmain + i];
-    const int nu = (even && ub == -h) ? 2 : 1;
-    const int nv = (even && vb == -h) ? 2 : 1;
+    nyq_bin_uv(g.N, i, ub, vb, c);
+    const float2 D = dh[sp.nslots + i];
+    const int nu = (ub == -h) ? 2 : 1;
+    const int nv = (vb == -h) ? 2 : 1;
     float Mr = 0.f, Mi = 0.f;
     for (int au = 0; au < nu; ++au) {
       const int u = (nu == 2) ? (au == 0 ? -h : h) : ub;
@@ -140,11 +293,11 @@ __device__ KSums kspace_sums(const Geom& g, const float2* __restrict__ dh, const
         const int v = (nv == 2) ? (av == 0 ? -h : h) : vb;
         const float cv = (nv == 2) ? (av == 0 ? 0.5f : -0.5f) : 1.0f;
         const float kx = (float)u * ks, ky = (float)v * ks;
-        const float2 xu = X[u + h], yv = Y[v + h];
+        const float2 xu = X[u + h], yv = Yf[v + h];
         const float q = fmaf(sh.ca, kx * kx, fmaf(sh.cb, ky * ky, sh.cc * kx * ky));
         float G, ia;
         profile_factor<PROF>(sh, q, G, ia);
-        const float amp = F * G * cu * cv;
+        const float amp = G * cu * cv;
         Mr += amp * fmaf(xu.x, yv.x, -xu.y * yv.y);
         Mi += amp * fmaf(xu.x, yv.y, xu.y * yv.x);
       }
@@ -159,23 +312,21 @@ __device__ KSums kspace_sums(const Geom& g, const float2* __restrict__ dh, const
         const int v = (nv == 2) ? (av == 0 ? -h : h) : vb;
         const float cv = (nv == 2) ? (av == 0 ? 0.5f : -0.5f) : 1.0f;
         const float kx = (float)u * ks, ky = (float)v * ks;
-        const float2 xu = X[u + h], yv = Y[v + h];
-        const float kx2 = kx * kx, ky2 = ky * ky, kxy = kx * ky;
-        const float q = fmaf(sh.ca, kx2, fmaf(sh.cb, ky2, sh.cc * kxy));
+        const float2 xu = X[u + h], yv = Yf[v + h];
+        const float kx2b = kx * kx, ky2b = ky * ky, kxy = kx * ky;
+        const float q = fmaf(sh.ca, kx2b, fmaf(sh.cb, ky2b, sh.cc * kxy));
         float G, ia;
         profile_factor<PROF>(sh, q, G, ia);
-        const float amp = F * G;
-        const float Tr = amp * fmaf(xu.x, yv.x, -xu.y * yv.y);
-        const float Ti = amp * fmaf(xu.x, yv.y, xu.y * yv.x);
+        const float Tr = G * fmaf(xu.x, yv.x, -xu.y * yv.y);
+        const float Ti = G * fmaf(xu.x, yv.y, xu.y * yv.x);
         const float w = cf * cu * cv;
         const float zr = w * fmaf(Rr, Tr, Ri * Ti);
         const float zi = w * fmaf(Rr, Ti, -Ri * Tr);
         sF += zr;
         const float wq = zr * ia;
-        sxx = fmaf(kx2, wq, sxx);
-        syy = fmaf(ky2, wq, syy);
+        sxx = fmaf(kx2b, wq, sxx);
+        syy = fmaf(ky2b, wq, syy);
         sxy = fmaf(kxy, wq, sxy);
-        sq = fmaf(q, wq, sq);
         sdx = fmaf(kx, zi, sdx);
         sdy = fmaf(ky, zi, sdy);
       }
@@ -183,19 +334,21 @@ __device__ KSums kspace_sums(const Geom& g, const float2* __restrict__ dh, const
   }
 
   KSums s;
-  s.chi2 = wave_sum(chi2);
-  s.sF = wave_sum(sF);
-  s.sxx = wave_sum(sxx);
-  s.syy = wave_sum(syy);
-  s.sxy = wave_sum(sxy);
-  s.sq = wave_sum(sq);
-  s.sdx = wave_sum(sdx);
-  s.sdy = wave_sum(sdy);
+  s.chi2 = wave_total(chi2);
+  s.sF = wave_total(sF);
+  s.sxx = wave_total(sxx);
+  s.syy = wave_total(syy);
+  s.sxy = wave_total(sxy);
+  // q is linear in (kx^2, ky^2, kx ky), so sum q w = ca Sxx + cb Syy + cc Sxy
+  s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
+  s.sdx = wave_total(sdx);
+  s.sdy = wave_total(sdy);
   return s;
 }
 
 // Turn the sums into log L and d log L / d(F, s, e1, e2, dx, dy).
-// norm = 1 / (N^2 sigma^2); s_arcsec is the half-light radius.
+// norm = 1 / (N^2 sigma^2); s_arcsec is the half-light radius.  The X table
+// carried the flux, so sF = sum Re(conj R T) and dT/dF = T / F.
 template <int PROF>
 __device__ __forceinline__ KResult kspace_finish(const KSums& S, const Shape& sh, float F,
                                                  float s_arcsec, float e1, float e2, float norm) {

@@ -7,7 +7,7 @@
 
 namespace bsi {
 
-template <int PROF, bool RESID>
+template <int PROF, bool RESID, int P>
 __global__ void __launch_bounds__(64) loglik_kernel(
     const float2* __restrict__ dh_all, const int64_t* __restrict__ bin_off, const int32_t* __restrict__ gidx,
     const float* __restrict__ params, const float* __restrict__ psf, const float* __restrict__ sigma,
@@ -15,19 +15,24 @@ __global__ void __launch_bounds__(64) loglik_kernel(
     double* __restrict__ loglik, float* __restrict__ grad, uint32_t* __restrict__ status) {
   extern __shared__ float4 smem4[];
   const Geom g = make_geom(N);
+  const SlotPlan sp = make_slot_plan(N);
   const int gal = gidx[blockIdx.x];
   float2* dh = reinterpret_cast<float2*>(smem4);
-  float* atab = reinterpret_cast<float*>(dh + g.nbins);
+  float* atab = reinterpret_cast<float*>(dh + sp.nbins);
   float2* X = reinterpret_cast<float2*>(atab + ((g.ntab + 1) & ~1));
-  float2* Y = X + g.ntab;
+  float2* Ym = X + g.ntab;
+  float2* Yf = Ym + sp.ymax;
+  float4* cols = reinterpret_cast<float4*>(Yf + g.ntab + 1);
+  cols = reinterpret_cast<float4*>((reinterpret_cast<uintptr_t>(cols) + 15) & ~uintptr_t(15));
+  build_col_table(g, sp, cols);
   const float2* src = dh_all + bin_off[gal];
-  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) dh[b] = src[b];
-  const float sp = psf[gal] * 0.42466090014400953f * pscale_inv;
+  for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) dh[b] = src[b];
+  const float spsf = psf[gal] * 0.42466090014400953f * pscale_inv;
   for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
     const int u = t - g.h;
     const double k = 2.0 * 3.14159265358979323846 * u / N;
     const double sn = (u == 0) ? 1.0 : sinpi((double)u / N) / (3.14159265358979323846 * u / N);
-    atab[t] = (float)(exp(-0.5 * (double)sp * sp * k * k) * sn);
+    atab[t] = (float)(exp(-0.5 * (double)spsf * spsf * k * k) * sn);
   }
   __syncthreads();
   const float* p = params + 6 * (int64_t)gal;
@@ -37,9 +42,10 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   const float E = e1 * e1 + e2 * e2;
   uint32_t st = 0;
   if (!(E < 1.0f) || !(s > 0.0f) || !(F > 0.0f)) st |= 1u;
-  fill_xy(g, atab, X, Y, dx, dy);
+  fill_tables(g, sp, atab, X, Ym, Yf, F, dx, dy);
   const Shape sh = make_shape(s * rscale, e1, e2);
-  const KSums S = kspace_sums<PROF, RESID>(g, dh, X, Y, F, sh);
+  const LaneCols<P> lc = lane_cols<P>(cols);
+  const KSums S = kspace_sums<PROF, P, RESID>(g, sp, lc, dh, X, Ym, Yf, sh);
   KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, norm);
   if (RESID) r.loglik = -0.5 * chi2_pix[gal] / ((double)sig * (double)sig);
   if (!isfinite(r.loglik)) st |= 2u;
@@ -58,7 +64,31 @@ __global__ void __launch_bounds__(64) loglik_kernel(
 
 static size_t loglik_lds_bytes(int N) {
   const Geom g = make_geom(N);
-  return sizeof(float2) * g.nbins + sizeof(float) * ((g.ntab + 1) & ~1) + 2 * sizeof(float2) * g.ntab;
+  const SlotPlan sp = make_slot_plan(N);
+  return sizeof(float2) * sp.nbins + sizeof(float) * ((g.ntab + 1) & ~1) +
+         sizeof(float2) * (2 * g.ntab + sp.ymax + 1) + 16 + sizeof(float4) * sp.P * 64;
+}
+
+template <int PROF, bool RESID>
+static void launch_loglik_p(int P, dim3 grid, size_t lds, hipStream_t s, const float2* dh,
+                            const int64_t* bin_off, const int32_t* gidx, const float* params,
+                            const float* psf, const float* sigma, int N, float rscale,
+                            float pscale_inv, const double* chi2_pix, double* loglik, float* grad,
+                            uint32_t* status) {
+  auto go = [&](auto kern) {
+    (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(kern, grid, dim3(64), lds, s, dh, bin_off, gidx, params, psf, sigma, N,
+                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
+  };
+  switch (P) {
+    case 1: go(loglik_kernel<PROF, RESID, 1>); break;
+    case 2: go(loglik_kernel<PROF, RESID, 2>); break;
+    case 3: go(loglik_kernel<PROF, RESID, 3>); break;
+    case 4: go(loglik_kernel<PROF, RESID, 4>); break;
+    case 5: go(loglik_kernel<PROF, RESID, 5>); break;
+    case 6: go(loglik_kernel<PROF, RESID, 6>); break;
+    default: go(loglik_kernel<PROF, RESID, 8>); break;
+  }
 }
 
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
@@ -68,15 +98,22 @@ hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = loglik_lds_bytes(N);
-  auto go = [&](auto kern) {
-    hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(kern, dim3(n), dim3(64), lds, s, dh, bin_off, gidx, params, psf, sigma, N,
-                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
-  };
+  const int P = make_slot_plan(N).P;
+  const dim3 grid(n);
   if (prof == kProfExp) {
-    if (resid_mode) go(loglik_kernel<kProfExp, true>); else go(loglik_kernel<kProfExp, false>);
+    if (resid_mode)
+      launch_loglik_p<kProfExp, true>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
+                                      rscale, pscale_inv, chi2_pix, loglik, grad, status);
+    else
+      launch_loglik_p<kProfExp, false>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
+                                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
   } else {
-    if (resid_mode) go(loglik_kernel<kProfGauss, true>); else go(loglik_kernel<kProfGauss, false>);
+    if (resid_mode)
+      launch_loglik_p<kProfGauss, true>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
+                                        rscale, pscale_inv, chi2_pix, loglik, grad, status);
+    else
+      launch_loglik_p<kProfGauss, false>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma,
+                                         N, rscale, pscale_inv, chi2_pix, loglik, grad, status);
   }
   return hipGetLastError();
 }

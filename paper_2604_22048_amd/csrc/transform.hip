@@ -74,15 +74,22 @@ __global__ void __launch_bounds__(256) dft_bins_kernel(
     Q[r * N + i] = make_float2(ar, ai);
   }
   __syncthreads();
-  // pass 2 (along x) at every bin
+  // pass 2 (along x) at every stored bin: the slot layout of the k-space
+  // loop (row 0 scaled by 1/sqrt 2, unused slots zero), then the Nyquist bins
+  const SlotPlan sp = make_slot_plan(N);
   float2* dst = out + bin_off[gal];
-  for (int b = threadIdx.x; b < g.nbins; b += blockDim.x) {
+  for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) {
     int u, v;
-    if (b < g.nmain) {
-      main_bin_uv(g, b, u, v);
+    float scale = 1.0f;
+    if (b < sp.nslots) {
+      if (!slot_uv(N, sp, b, u, v)) {
+        dst[b] = make_float2(0.f, 0.f);
+        continue;
+      }
+      if (v == 0) scale = 0.70710678118654752f;
     } else {
       int c;
-      spec_bin_uv(N, b - g.nmain, u, v, c);
+      nyq_bin_uv(N, b - sp.nslots, u, v, c);
     }
     const int r = (v < 0) ? g.h : v;
     const float2* q = Q + r * N;
@@ -97,7 +104,7 @@ __global__ void __launch_bounds__(256) dft_bins_kernel(
       m += step;
       if (m >= 2 * N) m -= 2 * N;
     }
-    dst[b] = make_float2(ar, ai);
+    dst[b] = make_float2(scale * ar, scale * ai);
   }
 }
 
@@ -210,7 +217,7 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
   (void)sigma;
   if (n <= 0) return hipSuccess;
   const size_t lds = dft_bins_lds_bytes(N);
-  hipFuncSetAttribute((const void*)dft_bins_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)dft_bins_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(dft_bins_kernel, dim3(n), dim3(256), lds, s, data, model, gidx, off, bin_off,
                      N, out, chi2);
@@ -223,7 +230,7 @@ static hipError_t render_impl(const float* params, const float* psf, const int32
                               OutT* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = render_lds_bytes(N);
-  hipFuncSetAttribute((const void*)render_kernel<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
+  (void)hipFuncSetAttribute((const void*)render_kernel<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(render_kernel<OutT>, dim3(n), dim3(256), lds, s, params, psf, gidx, off, N,
                      rscale, pscale_inv, prof, out);
