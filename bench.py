@@ -35,13 +35,17 @@ PS = gen.PIXEL_SCALE
 def flops_per_eval(N: int) -> float:
     """Algorithmic float32 operations of one gradient evaluation (k-space form).
 
-    50 per main bin (spectrum 21, residual and chi^2 6, conj(R) T 6, shape and
-    centroid sums 17; an FMA counts 2), 8 per frequency point for the
-    separable PSF-sinc-phase tables, and 6 x 8 x 2 for the wave reductions."""
-    nc = N if N % 2 else N - 1
-    nmain = (nc * nc - 1) // 2
+    Per half-plane DFT bin ((N^2 + 1) / 2 for odd N, N^2 / 2 + 2 for even N):
+    43 (an FMA counts 2): spectrum 15 (k_y, q, 1 + r0^2 q, rsqrt, G, X Y, G X Y),
+    residual and |R|^2 6, conj(R) T 6, and the six weighted sums 16 (F, k_x^2,
+    k_y^2, k_x k_y, k_x, k_y).  Per frequency point 12 for the separable
+    PSF-sinc-phase tables, and 100 for the per-evaluation shape constants,
+    reductions and the gradient assembly.  Slots that only pad the lane
+    layout are not counted."""
+    nbins = (N * N + 1) // 2 if N % 2 else N * N // 2 + 2
     ntab = 2 * (N // 2) + 1
-    return 50.0 * nmain + 8.0 * 2 * ntab + 96.0
+    rows = (N if N % 2 else N - 1) // 2 + 1
+    return 43.0 * nbins + 12.0 * (ntab + rows) + 100.0
 
 
 # ---------------------------------------------------------------- CPU baseline

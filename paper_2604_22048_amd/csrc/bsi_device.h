@@ -25,6 +25,7 @@ constexpr int kMaxN = 128;
 constexpr float kPiF = 3.14159265358979323846f;
 constexpr double kLn10 = 2.30258509299404568402;
 constexpr float kLn10F = 2.30258509299404568402f;
+constexpr float kLn2F = 0.69314718055994530942f;
 
 struct Geom {
   int N, h, nc, hc;
@@ -155,6 +156,29 @@ __device__ __forceinline__ double wave_total(double x) {
   const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), 63);
   const int hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Seven wave-wide float sums at once through a per-wave LDS scratch of
+// 64 x 8 words: each lane writes its eight partials (slot 7 unused), lane l
+// then adds the partials of value l / 8 held by lanes 8 (l % 8) .. 8 (l % 8) + 7,
+// and a three-step DPP prefix sum inside each group of eight lanes finishes
+// the sum on lane 8 v + 7.  scratch must be 16-byte aligned, 2 KiB per wave.
+__device__ __forceinline__ void wave_total7(float* v, float* scratch) {
+  const int lane = lane_id();
+  float4* s4 = reinterpret_cast<float4*>(scratch);
+  s4[2 * lane] = make_float4(v[0], v[1], v[2], v[3]);
+  s4[2 * lane + 1] = make_float4(v[4], v[5], v[6], 0.f);
+  wave_lds_sync();
+  const int val = lane >> 3, grp = lane & 7;
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += scratch[(8 * grp + k) * 8 + val];
+  acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
+  acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
+  acc = dpp_shift_add<0x114, 0xf>(acc);   // row_shr:4
+#pragma unroll
+  for (int j = 0; j < 7; ++j) v[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 8 * j + 7));
+  wave_lds_sync();
 }
 
 __device__ __forceinline__ float wave_max(float x) {

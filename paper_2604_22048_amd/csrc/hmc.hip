@@ -36,6 +36,7 @@ struct GalCtx {
   float2* X;       // per-wave tables (see fill_tables); the Fisher metric reuses
   float2* Ym;      // X and Ym as full x and y tables
   float2* Yf;
+  float* red;      // per-wave reduction scratch (2 KiB)
   float norm;      // 1 / (N^2 sigma^2)
   float rscale;
   float refx, refy;
@@ -46,15 +47,13 @@ struct GalCtx {
 __device__ __forceinline__ void fill_xy_full(const Geom& g, const float* __restrict__ atab, float2* X,
                                              float2* Y, float dx, float dy) {
   const int lane = lane_id();
-  const float two_over_n = 2.0f / (float)g.N;
+  const float rx = dx / (float)g.N, ry = dy / (float)g.N;
   for (int t = lane; t < g.ntab; t += kWave) {
-    const float u = (float)(t - g.h);
     const float a = atab[t];
-    float s, c;
-    sincospif(u * dx * two_over_n, &s, &c);
-    X[t] = make_float2(a * c, -a * s);
-    sincospif(u * dy * two_over_n, &s, &c);
-    Y[t] = make_float2(a * c, -a * s);
+    const float2 wx = cis_neg_rev((float)(t - g.h) * rx);
+    const float2 wy = cis_neg_rev((float)(t - g.h) * ry);
+    X[t] = make_float2(a * wx.x, a * wx.y);
+    Y[t] = make_float2(a * wy.x, a * wy.y);
   }
   wave_lds_sync();
 }
@@ -86,11 +85,13 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& 
     e2 *= f;
     E = e1 * e1 + e2 * e2;
   }
-  const float F = exp10f(t0), s = exp10f(t1);
+  // F = 10^t0 and s = 10^t1 in one lane-parallel evaluation
+  const float e10 = exp10f(lane_id() == 0 ? t0 : t1);
+  const float F = bcast(e10, 0), s = bcast(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
   fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
   const Shape sh = make_shape(s * c.rscale, e1, e2);
-  const KSums S = kspace_sums<PROF, P>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh);
+  const KSums S = kspace_sums<PROF, P>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh, c.red);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
   const double isd2 = 1.0 / ((double)pr.sd * pr.sd);
   const double ise2 = 1.0 / ((double)pr.se * pr.se);
@@ -213,6 +214,7 @@ struct Lds {
   float* atab;
   float4* cols;       // per-slot column table (shared)
   ChainState* cs;     // this wave's chain record
+  float* red;         // this wave's reduction scratch (64 x 8 floats)
   float2* X;
   float2* Ym;
   float2* Yf;
@@ -222,7 +224,8 @@ __device__ __forceinline__ int wave_table_len(const Geom& g, const SlotPlan& sp)
   return 2 * g.ntab + sp.ymax;
 }
 
-// LDS: [data spectrum | atab | column table | C chain records | C table sets]
+// LDS: [data spectrum | atab | column table | C chain records | C reduction
+// scratches | C table sets]
 __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave, int C) {
   extern __shared__ float4 smem4[];
   Lds l;
@@ -231,7 +234,9 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave
   l.cols = reinterpret_cast<float4*>(l.atab + ((g.ntab + 3) & ~3));
   ChainState* cs0 = reinterpret_cast<ChainState*>(l.cols + sp.P * 64);
   l.cs = cs0 + wave;
-  float2* w0 = reinterpret_cast<float2*>(cs0 + C);
+  float* red0 = reinterpret_cast<float*>(cs0 + C);
+  l.red = red0 + 512 * wave;
+  float2* w0 = reinterpret_cast<float2*>(red0 + 512 * C);
   l.X = w0 + wave_table_len(g, sp) * wave;
   l.Ym = l.X + g.ntab;
   l.Yf = l.Ym + sp.ymax;
@@ -319,8 +324,9 @@ __device__ __forceinline__ void store_state(ChainState* st, const Regs& r) {
   reinterpret_cast<uint32_t*>(st)[lane] = w;
 }
 
-// Random numbers of iteration t: 6 normals (Box-Muller in float64 on lanes 0
-// and 1), the Metropolis uniform and the step-jitter uniform.
+// Random numbers of iteration t: 6 normals (Box-Muller on lanes 0 and 1,
+// float hardware log/sqrt/sin/cos: relative error ~1e-7), the Metropolis
+// uniform and the step-jitter uniform.
 __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_t k0, uint32_t k1,
                                                float* z, float& u_acc, float& u_jit) {
   const int lane = lane_id();
@@ -330,27 +336,17 @@ __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_
   if (lane == 3) tag = kTagJitter;
   const uint4 w = philox4x32_10(make_uint4(uid, t, tag, blk), k0, k1);
   // two Box-Muller pairs per lane from (w.x, w.y) and (w.z, w.w)
-  double za, zb, zc, zd;
-  {
-    const double r = sqrt(-2.0 * log((double)u01(w.x)));
-    double sn, cs;
-    sincospi(2.0 * (double)u01(w.y), &sn, &cs);
-    za = r * cs;
-    zb = r * sn;
-  }
-  {
-    const double r = sqrt(-2.0 * log((double)u01(w.z)));
-    double sn, cs;
-    sincospi(2.0 * (double)u01(w.w), &sn, &cs);
-    zc = r * cs;
-    zd = r * sn;
-  }
-  z[0] = (float)bcast(za, 0);
-  z[1] = (float)bcast(zb, 0);
-  z[2] = (float)bcast(zc, 0);
-  z[3] = (float)bcast(zd, 0);
-  z[4] = (float)bcast(za, 1);
-  z[5] = (float)bcast(zb, 1);
+  const float r1 = sqrtf(-2.0f * kLn2F * __builtin_amdgcn_logf(u01(w.x)));
+  const float r2 = sqrtf(-2.0f * kLn2F * __builtin_amdgcn_logf(u01(w.z)));
+  const float a1 = u01(w.y), a2 = u01(w.w);       // angles in revolutions
+  const float za = r1 * __builtin_amdgcn_cosf(a1), zb = r1 * __builtin_amdgcn_sinf(a1);
+  const float zc = r2 * __builtin_amdgcn_cosf(a2), zd = r2 * __builtin_amdgcn_sinf(a2);
+  z[0] = bcast(za, 0);
+  z[1] = bcast(zb, 0);
+  z[2] = bcast(zc, 0);
+  z[3] = bcast(zd, 0);
+  z[4] = bcast(za, 1);
+  z[5] = bcast(zb, 1);
   u_acc = u01(bcast(w.x, 2));
   u_jit = u01(bcast(w.x, 3));
 }
@@ -399,8 +395,8 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
       double ke = 0.0;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        h.p[j] = (float)((double)z[j] / sqrt((double)h.im[j]));
-        ke += (double)h.im[j] * (double)h.p[j] * (double)h.p[j];
+        h.p[j] = z[j] * __builtin_amdgcn_rsqf(h.im[j]);
+        ke += (double)(h.im[j] * h.p[j] * h.p[j]);
         h.th[j] = cs->theta[j];
         h.g[j] = cs->grad[j];
       }
@@ -432,7 +428,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     for (int j = 0; j < 6; ++j) h.p[j] -= 0.5f * h.eps_t * h.g[j];
     double ke = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) ke += (double)h.im[j] * (double)h.p[j] * (double)h.p[j];
+    for (int j = 0; j < 6; ++j) ke += (double)(h.im[j] * h.p[j] * h.p[j]);
     const double dH = h.Uth + 0.5 * ke - cs->H0;
     const bool finite = isfinite(dH);
     const bool accept = h.ok && finite && log((double)cs->u_acc) < -dH;
@@ -461,7 +457,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
           const double eta = 1.0 / (m + kDaT0);
           const double hbar = (1.0 - eta) * cs->hbar + eta * ((double)a.delta - alpha);
           const double le = (double)a.mu - sqrt(m) / kDaGamma * hbar;
-          const double x = pow(m, -kDaKappa);
+          const double x = (double)exp2f(-(float)kDaKappa * log2f((float)m));   // m^-kappa
           const double lbar = x * le + (1.0 - x) * cs->log_eps_bar;
           cs->hbar = hbar;
           cs->log_eps_bar = lbar;
@@ -530,6 +526,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.X = l.X;
     c.Ym = l.Ym;
     c.Yf = l.Yf;
+    c.red = l.red;
     c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
     c.rscale = a.rscale;
     c.refx = a.ref_xy[2 * (int64_t)gal];
@@ -608,7 +605,7 @@ size_t hmc_lds_bytes(int N, int C) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan(N);
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
-         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C +
+         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C + sizeof(float) * 512 * C +
          sizeof(float2) * (2 * g.ntab + sp.ymax) * C;
 }
 

@@ -174,53 +174,55 @@ __device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
 }
 
 // Per-wave LDS tables of one evaluation.
-//   X [ntab]  : F a(u) exp(-i k_u dx),   u = -h..h
+//   X [ntab]  : F a(u) exp(-i k_u dx),   u = -h..h  (k_u dx = 2 pi u dx / N)
 //   Ym[ymax]  : a(v) exp(-i k_v dy) for rows v = 0..ymax-1 (row 0 / sqrt 2, rows > hc zero)
 //   Yf[ntab]  : a(v) exp(-i k_v dy),     v = -h..h (even N only, for the Nyquist bins)
 // with a(u) = PSF(k_u) sinc(u/N) from atab.
+// exp(-2 pi i r) for r in revolutions with the hardware sin/cos (input in
+// revolutions; measured max abs error 1.3e-7 for |r| <= 3).
+__device__ __forceinline__ float2 cis_neg_rev(float r) {
+  return make_float2(__builtin_amdgcn_cosf(r), -__builtin_amdgcn_sinf(r));
+}
+
 __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
                                             const float* __restrict__ atab, float2* X, float2* Ym,
                                             float2* Yf, float F, float dx, float dy) {
   const int lane = lane_id();
-  const float two_over_n = 2.0f / (float)g.N;
+  const float rx = dx / (float)g.N, ry = dy / (float)g.N;   // revolutions per unit frequency
   for (int t = lane; t < g.ntab; t += kWave) {
-    const float u = (float)(t - g.h);
     const float a = F * atab[t];
-    float s, c;
-    sincospif(u * dx * two_over_n, &s, &c);
-    X[t] = make_float2(a * c, -a * s);
+    const float2 w = cis_neg_rev((float)(t - g.h) * rx);
+    X[t] = make_float2(a * w.x, a * w.y);
   }
   const bool even = (g.N & 1) == 0;
   for (int v = lane; v < sp.ymax; v += kWave) {
     float2 y = make_float2(0.f, 0.f);
     if (v <= g.hc) {
       const float a = atab[v + g.h] * (v == 0 ? 0.70710678118654752f : 1.0f);
-      float s, c;
-      sincospif((float)v * dy * two_over_n, &s, &c);
-      y = make_float2(a * c, -a * s);
+      const float2 w = cis_neg_rev((float)v * ry);
+      y = make_float2(a * w.x, a * w.y);
     }
     Ym[v] = y;
   }
   if (even) {
     for (int t = lane; t < g.ntab; t += kWave) {
-      const float v = (float)(t - g.h);
       const float a = atab[t];
-      float s, c;
-      sincospif(v * dy * two_over_n, &s, &c);
-      Yf[t] = make_float2(a * c, -a * s);
+      const float2 w = cis_neg_rev((float)(t - g.h) * ry);
+      Yf[t] = make_float2(a * w.x, a * w.y);
     }
   }
   wave_lds_sync();
 }
 
-// Accumulate the k-space sums of one wave.  dh: the data spectrum (or, with
+// Accumulate the k-space sums of one wave (red: this wave's 2 KiB reduction
+// scratch in LDS).  dh: the data spectrum (or, with
 // RESID, the spectrum of the pixel residual d - m) in slot order followed by
 // the Nyquist bins.  The X table already contains the flux.  Result is
 // lane-uniform.
 template <int PROF, int P, bool RESID = false>
 __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P>& lc,
                              const float2* __restrict__ dh, const float2* X, const float2* Ym,
-                             const float2* Yf, const Shape& sh) {
+                             const float2* Yf, const Shape& sh, float* red) {
   const int lane = lane_id();
   float xr[P], xim[P], A[P], Cc[P], kx2[P];
   const float2* yp[P];
@@ -335,14 +337,16 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
 
   KSums s;
   s.chi2 = wave_total(chi2);
-  s.sF = wave_total(sF);
-  s.sxx = wave_total(sxx);
-  s.syy = wave_total(syy);
-  s.sxy = wave_total(sxy);
+  float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
+  wave_total7(v, red);
+  s.sF = v[0];
+  s.sxx = v[1];
+  s.syy = v[2];
+  s.sxy = v[3];
+  s.sdx = v[4];
+  s.sdy = v[5];
   // q is linear in (kx^2, ky^2, kx ky), so sum q w = ca Sxx + cb Syy + cc Sxy
   s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
-  s.sdx = wave_total(sdx);
-  s.sdy = wave_total(sdy);
   return s;
 }
 

@@ -24,6 +24,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   float2* Yf = Ym + sp.ymax;
   float4* cols = reinterpret_cast<float4*>(Yf + g.ntab + 1);
   cols = reinterpret_cast<float4*>((reinterpret_cast<uintptr_t>(cols) + 15) & ~uintptr_t(15));
+  float* red = reinterpret_cast<float*>(cols + sp.P * 64);
   build_col_table(g, sp, cols);
   const float2* src = dh_all + bin_off[gal];
   for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) dh[b] = src[b];
@@ -45,7 +46,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   fill_tables(g, sp, atab, X, Ym, Yf, F, dx, dy);
   const Shape sh = make_shape(s * rscale, e1, e2);
   const LaneCols<P> lc = lane_cols<P>(cols);
-  const KSums S = kspace_sums<PROF, P, RESID>(g, sp, lc, dh, X, Ym, Yf, sh);
+  const KSums S = kspace_sums<PROF, P, RESID>(g, sp, lc, dh, X, Ym, Yf, sh, red);
   KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, norm);
   if (RESID) r.loglik = -0.5 * chi2_pix[gal] / ((double)sig * (double)sig);
   if (!isfinite(r.loglik)) st |= 2u;
@@ -66,7 +67,8 @@ static size_t loglik_lds_bytes(int N) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan(N);
   return sizeof(float2) * sp.nbins + sizeof(float) * ((g.ntab + 1) & ~1) +
-         sizeof(float2) * (2 * g.ntab + sp.ymax + 1) + 16 + sizeof(float4) * sp.P * 64;
+         sizeof(float2) * (2 * g.ntab + sp.ymax + 1) + 16 + sizeof(float4) * sp.P * 64 +
+         sizeof(float) * 64 * 8;
 }
 
 template <int PROF, bool RESID>
