@@ -15,6 +15,8 @@ runs on one GPU.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import math
 import os
@@ -48,6 +50,28 @@ def flops_per_eval(N: int) -> float:
     return 43.0 * nbins + 12.0 * (ntab + rows) + 100.0
 
 
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_22048_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(f).encode())
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per trajectory launch from the committed counter summary, or
+    None when the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hmc_kernel_uniform53.txt")
+    try:
+        kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
+    except OSError:
+        return None
+    if kv.get("source_sha256", "").strip() != kernel_source_hash():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 # ---------------------------------------------------------------- CPU baseline
 def _oracle_worker(args):
     from threadpoolctl import threadpool_limits
@@ -69,7 +93,7 @@ def _oracle_worker(args):
     return time.perf_counter() - t0, n_iter * L
 
 
-def cpu_baseline_eval_rate(n_iter=15, L=20):
+def cpu_baseline_eval_rate(n_iter=40, L=20):
     """Oracle gradient evaluations per second on the host, all usable cores."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
@@ -138,7 +162,17 @@ def main():
     ap.add_argument("--n-gal", type=int, default=None, help="override galaxy count (profiling)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain-gal", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda:0")
+        for _ in range(4):
+            b = a.clone()
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 4}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
               "part of this build", file=sys.stderr)
@@ -257,7 +291,8 @@ def main():
         "rhat_max": round(float(np.nanmax(rhat)), 4),
         "frac_rhat_lt_1.01": round(float(np.mean(rhat.max(axis=1) < 1.01)), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": recorded_traffic(),
                      "kernel": "hmc_kernel (advance)", "launch_ms": round(t_launch * 1e3, 4),
                      "alg_flop_per_launch": alg},
     }
@@ -266,7 +301,7 @@ def main():
         out["cpu_baseline"] = {"value": round(cpu["rate"] / evals_per_gal, 6), "unit": "galaxies/s",
                                "cores": cpu["cores"], "kind": "oracle",
                                "sample": f"{cpu['evals']} float64 oracle gradient evaluations (53x53, "
-                                         f"one 15-iteration warmup chain per core) in "
+                                         f"one 40-iteration warmup chain per core) in "
                                          f"{cpu['wall']:.1f} s; galaxies/s = eval rate / evaluations "
                                          f"per galaxy at 300 ESS with the GPU run's n_eff"}
     print(json.dumps(out), flush=True)
