@@ -229,6 +229,48 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
                         const double* pts, int32_t pts_on_device, double* logpost, double* grad,
                         bsi_stream stream);
 
+/* Shear-level sampler settings (the per-galaxy sampler's scheme on the five
+ * population parameters). */
+typedef struct {
+  int32_t n_chains;          /* chains, 1..64 (evaluated together in one pass)            */
+  int32_t n_leapfrog;        /* leapfrog steps per trajectory, >= 1                        */
+  int32_t n_warmup;          /* warmup iterations (not stored), >= 0                       */
+  int32_t n_samples;         /* stored iterations, >= 0                                    */
+  int32_t adapt;             /* 1: dual-averaging step-size adaptation during warmup       */
+  float step_size;           /* initial (adapt) or fixed step size, > 0                    */
+  float target_accept;       /* dual-averaging target delta in (0, 1) [0.8]                */
+  float jitter;              /* relative step-size jitter in [0, 1)                        */
+  double inv_mass[5];        /* diagonal inverse metric, every entry > 0                   */
+  uint64_t seed;             /* Philox key                                                 */
+  uint64_t uid_base;         /* chain uid = uid_base + chain                               */
+  int32_t use_graph;         /* replay each trajectory from a captured HIP graph           */
+  float* trace;              /* [device] float[n_chains][n_warmup + n_samples][4] or NULL,
+                                as in bsi_hmc_cfg                                          */
+} bsi_shear_hmc_cfg;
+
+/*
+ * bsi_shear_hmc -- phase 2 sampling: Hamiltonian Monte Carlo on
+ * x = (g1, g2, mu_ln_s, sigma_ln_s, sigma_e) with potential
+ * U(x) = -ln P(g, alpha | d) of bsi_shear_posterior (Section 3.4 samples the
+ * shear and population parameters from this posterior; its gradient is the
+ * softmax-weighted closed-form derivative of the log importance weights).
+ * The iteration is that of bsi_hmc_sample (Philox4x32-10 momenta with the
+ * same counters, float64 energies and Metropolis test, dual-averaging
+ * warmup); position, momentum and energies are float64.  Every leapfrog step
+ * evaluates all chains in one pass over the interim samples; the chain state
+ * stays on the device for the whole call.
+ *   e1p .. log10f, tp, interim   as for bsi_shear_posterior.
+ *   init        [host] double[n_chains][5] start points (inside the support).
+ *   samples     [device] double[n_chains][n_samples][5] or NULL.
+ *   chain_stats [device] double[n_chains][4] = {accept rate over the stored
+ *               iterations, final step size, divergent trajectories, ln P at
+ *               the final position} or NULL.
+ */
+int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
+                  const float* log10s, const float* log10f, const bsi_true_prior* tp,
+                  const bsi_interim* interim, const bsi_shear_hmc_cfg* cfg, const double* init,
+                  double* samples, double* chain_stats, bsi_stream stream);
+
 /*
  * bsi_ess -- diagnostics of Section 4.1 for stored samples:
  * multi-chain effective sample size per parameter (autocorrelation with

@@ -228,3 +228,18 @@ def grid_posterior(S, g1s, g2s, alpha, tp, ip):
     w = np.exp(lp - mx)
     G1, G2 = np.meshgrid(g1s, g2s)
     return lp, float(np.sum(w * G1) / np.sum(w)), float(np.sum(w * G2) / np.sum(w))
+
+
+def hyper_potential(S, tp, ip):
+    """Potential of the shear-level sampler (Section 3.4 samples P(g, alpha | d)):
+    x = (g1, g2, mu_ln_s, sigma_ln_s, sigma_e) -> (U, grad U) with
+    U = -ln P(g, alpha | d); outside the hyper-prior support U = +inf and the
+    gradient is undefined (NaN): a trajectory that gets there is rejected.  Combined
+    with ``hmc.run_chain`` (n_dim = 5) this is the oracle shear-level HMC."""
+    def fn(x):
+        g, alpha = complex(x[0], x[1]), (x[2], x[3], x[4])
+        if not in_hyper_support(g, alpha):
+            return math.inf, np.full(5, np.nan)
+        lp, gr = log_posterior_grad(S, g, alpha, tp, ip)
+        return -lp, -np.asarray(gr, dtype=np.float64)
+    return fn

@@ -50,6 +50,14 @@ class TruePrior(C.Structure):
                 ("flux_term", C.c_int32), ("mu_ln_f", C.c_double), ("sigma_ln_f", C.c_double)]
 
 
+class ShearHmcCfg(C.Structure):
+    _fields_ = [("n_chains", C.c_int32), ("n_leapfrog", C.c_int32), ("n_warmup", C.c_int32),
+                ("n_samples", C.c_int32), ("adapt", C.c_int32), ("step_size", C.c_float),
+                ("target_accept", C.c_float), ("jitter", C.c_float), ("inv_mass", C.c_double * 5),
+                ("seed", C.c_uint64), ("uid_base", C.c_uint64), ("use_graph", C.c_int32),
+                ("trace", C.c_void_p)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "bsi_version": (C.c_int, []),
@@ -67,6 +75,10 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
                                       C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bsi_shear_hmc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p, C.POINTER(TruePrior), C.POINTER(Interim),
+                                C.POINTER(ShearHmcCfg), C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.c_void_p]),
     "bsi_ess": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p]),
 }

@@ -239,6 +239,61 @@ def shear_posterior(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, int
     return (lp, gr) if want_grad else lp
 
 
+@dataclass
+class ShearHmcConfig:
+    n_chains: int = 4
+    n_leapfrog: int = 10
+    n_warmup: int = 500
+    n_samples: int = 3000
+    adapt: bool = True
+    step_size: float = 1e-3
+    target_accept: float = 0.8
+    jitter: float = 0.0
+    inv_mass: tuple = (1.0, 1.0, 1.0, 1.0, 1.0)
+    seed: int = 0
+    uid_base: int = 0
+    use_graph: bool = True
+
+    def c(self, trace=None) -> N.ShearHmcCfg:
+        return N.ShearHmcCfg(int(self.n_chains), int(self.n_leapfrog), int(self.n_warmup),
+                             int(self.n_samples), int(bool(self.adapt)), float(self.step_size),
+                             float(self.target_accept), float(self.jitter),
+                             (C.c_double * 5)(*[float(v) for v in self.inv_mass]),
+                             int(self.seed) & 0xFFFFFFFFFFFFFFFF,
+                             int(self.uid_base) & 0xFFFFFFFFFFFFFFFF, int(bool(self.use_graph)),
+                             None if trace is None else trace.data_ptr())
+
+
+def shear_hmc(e1p, e2p, log10s, log10f, true_prior: TruePriorCfg, cfg: ShearHmcConfig, init,
+              interim=None, trace: torch.Tensor | None = None, want_samples: bool = True,
+              lib: Library | None = None):
+    """(samples [C, S, 5] float64, chain_stats [C, 4] float64) of the shear-level sampler.
+
+    init: start points [C, 5] (host array).  trace: optional float32
+    [C, W + S, 4] tensor (base step, dH, acceptance statistic, accepted)."""
+    dev = e1p.device
+    lib = lib or get(dev.index or 0)
+    G, K = e1p.shape
+    e1p, e2p = e1p.contiguous().float(), e2p.contiguous().float()
+    log10s = log10s.contiguous().float() if log10s is not None else None
+    log10f = log10f.contiguous().float() if log10f is not None else None
+    Cn, S = cfg.n_chains, cfg.n_samples
+    init_np = np.ascontiguousarray(np.asarray(init, dtype=np.float64).reshape(Cn, 5))
+    samples = torch.empty(Cn, S, 5, dtype=torch.float64, device=dev) if want_samples else None
+    stats = torch.empty(Cn, 4, dtype=torch.float64, device=dev)
+    if trace is not None:
+        assert trace.shape == (Cn, cfg.n_warmup + S, 4) and trace.dtype == torch.float32
+        assert trace.is_contiguous()
+    tp = true_prior.c()
+    ip = _interim(interim)
+    cc = cfg.c(trace)
+    lib.check(lib.lib.bsi_shear_hmc(lib.h, G, K, _ptr(e1p), _ptr(e2p), _ptr(log10s), _ptr(log10f),
+                                    C.byref(tp), C.byref(ip), C.byref(cc),
+                                    C.c_void_p(init_np.ctypes.data), _ptr(samples), _ptr(stats),
+                                    _stream(dev)), "bsi_shear_hmc")
+    return samples, stats
+
+
 def ess(samples: torch.Tensor, lib: Library | None = None):
     """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]."""
     dev = samples.device

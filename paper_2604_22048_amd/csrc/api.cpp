@@ -33,7 +33,7 @@ struct bsi_ctx {
   int num_cu = 0;
   std::string err;
   hipStream_t own = nullptr;
-  DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts;
+  DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts, shear_state;
 };
 
 namespace {
@@ -224,7 +224,7 @@ void bsi_destroy(bsi_handle h) {
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&h->gidx, &h->off, &h->bin_off, &h->dh, &h->chi2, &h->model, &h->state,
-                    &h->partial, &h->pts})
+                    &h->partial, &h->pts, &h->shear_state})
     if (b->p) (void)hipFree(b->p);
   if (h->own) (void)hipStreamDestroy(h->own);
   delete h;
@@ -446,41 +446,39 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   return BSI_OK;
 }
 
-int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
-                        const float* e2p, const float* log10s, const float* log10f,
-                        const bsi_true_prior* tp, const bsi_interim* ip, int32_t n_pts,
-                        const double* pts, int32_t pts_on_device, double* logpost, double* grad,
-                        bsi_stream stream) {
-  if (!h) return BSI_EINVAL;
-  h->err.clear();
+}  // extern "C"
+
+namespace {
+
+int check_shear_inputs(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
+                       const float* log10s, const float* log10f, const bsi_true_prior* tp,
+                       const bsi_interim* ip) {
   if (n_gal < 1) return fail(h, BSI_EINVAL, "n_gal must be >= 1");
   if (K < 1 || K > 1024) return fail(h, BSI_EUNSUPPORTED, "K must be in 1..1024");
-  if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
   if (!tp || !ip) return fail(h, BSI_EINVAL, "true prior / interim is NULL");
   if (tp->e_kind != BSI_E_BA14 && tp->e_kind != BSI_E_TRUNC_GAUSS)
     return fail(h, BSI_EINVAL, "unknown e_kind");
   if (tp->e_kind == BSI_E_TRUNC_GAUSS && !(tp->e_max > 0.0f && tp->e_max <= 1.0f))
     return fail(h, BSI_EINVAL, "e_max must be in (0, 1]");
   if (tp->flux_term && !(tp->sigma_ln_f > 0.0)) return fail(h, BSI_EINVAL, "sigma_ln_f must be > 0");
+  if (!(ip->log10f_lo < ip->log10f_hi) || !(ip->log10s_lo < ip->log10s_hi) || !(ip->sigma_e > 0))
+    return fail(h, BSI_EINVAL, "invalid interim prior");
   if (!e1p || !e2p || (tp->size_term && !log10s) || (tp->flux_term && !log10f))
     return fail(h, BSI_EINVAL, "sample arrays are NULL");
-  if (n_pts == 0) return BSI_OK;
-  if (!pts || !logpost) return fail(h, BSI_EINVAL, "pts/logpost is NULL");
-  hipSetDevice(h->device);
-  hipStream_t s = static_cast<hipStream_t>(stream);
-  int rc;
-  const double* dpts = pts;
-  if (!pts_on_device) {
-    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
-    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "points upload");
-    dpts = static_cast<const double*>(h->pts.p);
-  }
+  return BSI_OK;
+}
+
+// Blocks of one evaluation pass over n_gal galaxies at n_pts points (four
+// galaxies per block and pass, at most 4096 blocks over all point chunks).
+int shear_blocks(int n_gal, int n_pts) {
   const int chunks = (n_pts + 63) / 64;
-  const int n_blocks = std::max(1, std::min((n_gal + 3) / 4, std::max(64, 4096 / chunks)));
-  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
+  return std::max(1, std::min((n_gal + 3) / 4, std::max(64, 4096 / chunks)));
+}
+
+ShearArgs shear_args(int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
+                     const float* log10s, const float* log10f, const bsi_true_prior* tp,
+                     const bsi_interim* ip, int n_pts, const double* dpts, double* partial,
+                     int want_grad) {
   ShearArgs a{};
   a.n_gal = n_gal;
   a.K = K;
@@ -499,12 +497,143 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
   a.sigma_e_interim = ip->sigma_e;
   a.n_pts = n_pts;
   a.pts = dpts;
-  a.partial = static_cast<double*>(h->partial.p);
-  a.want_grad = grad != nullptr;
+  a.partial = partial;
+  a.want_grad = want_grad;
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                        const float* e2p, const float* log10s, const float* log10f,
+                        const bsi_true_prior* tp, const bsi_interim* ip, int32_t n_pts,
+                        const double* pts, int32_t pts_on_device, double* logpost, double* grad,
+                        bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_shear_inputs(h, n_gal, K, e1p, e2p, log10s, log10f, tp, ip);
+  if (rc) return rc;
+  if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
+  if (n_pts == 0) return BSI_OK;
+  if (!pts || !logpost) return fail(h, BSI_EINVAL, "pts/logpost is NULL");
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* dpts = pts;
+  if (!pts_on_device) {
+    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
+    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "points upload");
+    dpts = static_cast<const double*>(h->pts.p);
+  }
+  const int n_blocks = shear_blocks(n_gal, n_pts);
+  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
+  const ShearArgs a = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, n_pts, dpts,
+                                 static_cast<double*>(h->partial.p), grad != nullptr);
   hipError_t e = launch_shear(a, n_blocks, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear launch");
   e = launch_shear_reduce(a.partial, n_blocks, n_pts, dpts, logpost, grad, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
+  return BSI_OK;
+}
+
+int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
+                  const float* log10s, const float* log10f, const bsi_true_prior* tp,
+                  const bsi_interim* ip, const bsi_shear_hmc_cfg* cfg, const double* init,
+                  double* samples, double* chain_stats, bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_shear_inputs(h, n_gal, K, e1p, e2p, log10s, log10f, tp, ip);
+  if (rc) return rc;
+  if (!cfg || !init) return fail(h, BSI_EINVAL, "cfg/init is NULL");
+  const int C = cfg->n_chains;
+  if (C < 1 || C > 64) return fail(h, BSI_EINVAL, "n_chains must be 1..64");
+  if (cfg->n_leapfrog < 1) return fail(h, BSI_EINVAL, "n_leapfrog must be >= 1");
+  if (cfg->n_warmup < 0 || cfg->n_samples < 0) return fail(h, BSI_EINVAL, "negative iteration count");
+  if (!(cfg->step_size > 0.0f) || !std::isfinite(cfg->step_size))
+    return fail(h, BSI_EINVAL, "step_size must be positive");
+  if (cfg->adapt && !(cfg->target_accept > 0.0f && cfg->target_accept < 1.0f))
+    return fail(h, BSI_EINVAL, "target_accept must be in (0, 1)");
+  if (!(cfg->jitter >= 0.0f && cfg->jitter < 1.0f)) return fail(h, BSI_EINVAL, "jitter must be in [0, 1)");
+  for (int j = 0; j < 5; ++j)
+    if (!(cfg->inv_mass[j] > 0.0) || !std::isfinite(cfg->inv_mass[j]))
+      return fail(h, BSI_EINVAL, "inv_mass entries must be positive");
+  hipSetDevice(h->device);
+  hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->own;
+  const int n_blocks = shear_blocks(n_gal, C);
+  if ((rc = ensure(h, h->pts, (size_t)C * 5 * sizeof(double)))) return rc;
+  if ((rc = ensure(h, h->partial, (size_t)n_blocks * C * 6 * sizeof(double)))) return rc;
+  if ((rc = ensure(h, h->shear_state, (size_t)C * sizeof(ShearChain)))) return rc;
+  hipError_t e = hipMemcpyAsync(h->pts.p, init, (size_t)C * 5 * sizeof(double),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "start points upload");
+
+  double* dpts = static_cast<double*>(h->pts.p);
+  const ShearArgs sa = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, C, dpts,
+                                  static_cast<double*>(h->partial.p), 1);
+  ShearHmcArgs a{};
+  a.state = static_cast<ShearChain*>(h->shear_state.p);
+  a.pts = dpts;
+  a.partial = sa.partial;
+  a.n_blocks = n_blocks;
+  a.C = C;
+  a.L = cfg->n_leapfrog;
+  a.W = cfg->n_warmup;
+  a.S = cfg->n_samples;
+  a.t_stop = cfg->n_warmup + cfg->n_samples;
+  a.adapt = cfg->adapt;
+  for (int j = 0; j < 5; ++j) a.im[j] = cfg->inv_mass[j];
+  a.eps0 = cfg->step_size;
+  a.delta = cfg->target_accept;
+  a.jitter = cfg->jitter;
+  a.mu = std::log(10.0 * (double)cfg->step_size);
+  a.k0 = (uint32_t)(cfg->seed & 0xffffffffu);
+  a.k1 = (uint32_t)(cfg->seed >> 32);
+  a.uid_base = cfg->uid_base;
+  a.samples = samples;
+  a.trace = cfg->trace;
+
+  // the potential at the start points, then one trajectory per iteration
+  e = launch_shear(sa, n_blocks, s);
+  if (e == hipSuccess) e = launch_shear_hmc_update(a, 1, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear hmc init");
+  auto trajectory = [&](hipStream_t st) -> hipError_t {
+    for (int l = 0; l < a.L; ++l) {
+      hipError_t x = launch_shear(sa, n_blocks, st);
+      if (x == hipSuccess) x = launch_shear_hmc_update(a, 0, st);
+      if (x != hipSuccess) return x;
+    }
+    return hipSuccess;
+  };
+  const int T = a.t_stop;
+  if (cfg->use_graph && T > 1) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) e = trajectory(s);
+    hipError_t e2 = hipStreamEndCapture(s, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    for (int k = 0; e == hipSuccess && k < T; ++k) e = hipGraphLaunch(exec, s);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(h, e, "shear hmc graph");
+  } else {
+    for (int k = 0; k < T; ++k) {
+      e = trajectory(s);
+      if (e != hipSuccess) return hip_fail(h, e, "shear hmc launch");
+    }
+  }
+  e = launch_shear_hmc_stats(a.state, C, a.S, chain_stats, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear hmc stats");
+  if (!stream) {
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "shear hmc sync");
+  }
   return BSI_OK;
 }
 

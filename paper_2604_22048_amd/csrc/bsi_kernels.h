@@ -117,6 +117,40 @@ hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s);
 hipError_t launch_shear_reduce(const double* partial, int n_blocks, int n_pts, const double* pts,
                                double* logpost, double* grad, hipStream_t s);
 
+// Shear-level sampler state per chain (float64 except the step sizes, which
+// are carried in float like the per-galaxy sampler's).
+struct ShearChain {
+  double x[5];     // trajectory position (g1, g2, mu_ln_s, sigma_ln_s, sigma_e)
+  double p[5];     // trajectory momentum
+  double x0[5];    // accepted position
+  double g0[5];    // grad U at x0
+  double U0;       // U at x0
+  double H0;       // Hamiltonian at the trajectory start
+  double hbar, lbar;
+  double u_acc;
+  double sum_alpha;
+  float eps, eps_t;
+  int32_t l, t, ok, n_acc, n_div;
+  uint32_t status;
+};
+
+struct ShearHmcArgs {
+  ShearChain* state;   // [C]
+  double* pts;         // [C][5] points of the next evaluation (read by shear_kernel)
+  const double* partial;
+  int n_blocks;        // blocks of the evaluation pass
+  int C, L, W, S, t_stop, adapt;
+  double im[5];        // diagonal inverse metric
+  float eps0, delta, jitter;
+  double mu;
+  uint32_t k0, k1;
+  uint64_t uid_base;
+  double* samples;     // [C][S][5] or NULL
+  float* trace;        // [C][W+S][4] or NULL
+};
+hipError_t launch_shear_hmc_update(const ShearHmcArgs& a, int init, hipStream_t s);
+hipError_t launch_shear_hmc_stats(const ShearChain* st, int C, int S, double* stats, hipStream_t s);
+
 // ---- diag.hip ----
 hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,
                       float* rhat, hipStream_t s);

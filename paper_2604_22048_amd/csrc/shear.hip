@@ -196,23 +196,216 @@ __global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
   }
 }
 
-__global__ void shear_reduce_kernel(const double* __restrict__ partial, int n_blocks, int n_pts,
-                                    const double* __restrict__ pts, double* __restrict__ logpost,
-                                    double* __restrict__ grad) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= n_pts) return;
-  double v[6] = {0, 0, 0, 0, 0, 0};
-  for (int b = 0; b < n_blocks; ++b)
+constexpr int kRedThreads = 256;
+
+// Sum of the per-block partials of point p, in a fixed order: thread i adds
+// blocks i, i + 256, ..., then a pairwise tree over the threads.  The total
+// is returned on thread 0 (bitwise reproducible for a given n_blocks).
+__device__ __forceinline__ void reduce_point(const double* __restrict__ partial, int n_blocks,
+                                             int n_pts, int p, double (*red)[6], double* v) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < n_blocks; b += kRedThreads)
 #pragma unroll
-    for (int j = 0; j < 6; ++j) v[j] += partial[((int64_t)b * n_pts + p) * 6 + j];
-  const double* q = pts + 5 * (int64_t)p;
+    for (int j = 0; j < 6; ++j) acc[j] += partial[((int64_t)b * n_pts + p) * 6 + j];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) red[threadIdx.x][j] = acc[j];
+  __syncthreads();
+  for (int w = kRedThreads / 2; w >= 1; w >>= 1) {
+    if ((int)threadIdx.x < w)
+#pragma unroll
+      for (int j = 0; j < 6; ++j) red[threadIdx.x][j] += red[threadIdx.x + w][j];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 6; ++j) v[j] = red[0][j];
+}
+
+// Support of the uniform hyper-priors (|g| < 1, 1e-4 < sigma_e < 1,
+// |mu_ln_s| < 2 ln 10, 0 < sigma_ln_s < ln 10 / 2).
+__device__ __forceinline__ bool hyper_inside(const double* q) {
   const double gg = q[0] * q[0] + q[1] * q[1];
-  const bool inside = gg < 1.0 && q[4] > 1e-4 && q[4] < 1.0 && fabs(q[2]) < 2.0 * kLn10 &&
-                      q[3] > 0.0 && q[3] < 0.5 * kLn10;
-  logpost[p] = inside ? v[0] : -INFINITY;
+  return gg < 1.0 && q[4] > 1e-4 && q[4] < 1.0 && fabs(q[2]) < 2.0 * kLn10 && q[3] > 0.0 &&
+         q[3] < 0.5 * kLn10;
+}
+
+// One block per point.
+__global__ void __launch_bounds__(kRedThreads)
+shear_reduce_kernel(const double* __restrict__ partial, int n_blocks, int n_pts,
+                    const double* __restrict__ pts, double* __restrict__ logpost,
+                    double* __restrict__ grad) {
+  __shared__ double red[kRedThreads][6];
+  const int p = blockIdx.x;
+  double v[6];
+  reduce_point(partial, n_blocks, n_pts, p, red, v);
+  if (threadIdx.x != 0) return;
+  logpost[p] = hyper_inside(pts + 5 * (int64_t)p) ? v[0] : -INFINITY;
   if (grad)
 #pragma unroll
     for (int j = 0; j < 5; ++j) grad[5 * (int64_t)p + j] = v[1 + j];
+}
+
+// ---- shear-level HMC -----------------------------------------------------
+// The sampler of the per-galaxy phase (fixed-length HMC, Philox momenta,
+// float64 energies, dual-averaging warmup) run on x = (g1, g2, mu_ln_s,
+// sigma_ln_s, sigma_e) with U = -ln P(g, alpha | d).  Each evaluation of U is
+// one pass of shear_kernel over all interim samples at the n_chains current
+// points; shear_hmc_update_kernel (one block per chain) reduces that pass and
+// moves its chain to the next point, so one leapfrog step is two launches and
+// no state leaves the device.  Box-Muller, the energy and the adaptation run
+// in float64 on one thread per chain.
+
+constexpr double kDaGamma = 0.05, kDaT0 = 10.0, kDaKappa = 0.75;
+constexpr double kDivergence = 1000.0;
+
+__device__ void shear_begin_iteration(const ShearHmcArgs& a, ShearChain& c, uint32_t uid,
+                                      double* pt) {
+  const uint32_t t = (uint32_t)c.t;
+  const uint4 w0 = philox4x32_10(make_uint4(uid, t, kTagMomentum, 0), a.k0, a.k1);
+  const uint4 w1 = philox4x32_10(make_uint4(uid, t, kTagMomentum, 1), a.k0, a.k1);
+  const uint4 wa = philox4x32_10(make_uint4(uid, t, kTagAccept, 0), a.k0, a.k1);
+  const uint32_t wu[6] = {w0.x, w0.y, w0.z, w0.w, w1.x, w1.y};
+  double z[6];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double r = sqrt(-2.0 * log((double)u01(wu[2 * k])));
+    const double ang = 2.0 * 3.14159265358979323846 * (double)u01(wu[2 * k + 1]);
+    z[2 * k] = r * cos(ang);
+    z[2 * k + 1] = r * sin(ang);
+  }
+  c.u_acc = (double)u01(wa.x);
+  float eps_t = c.eps;
+  if (a.jitter > 0.0f) {
+    const uint4 wj = philox4x32_10(make_uint4(uid, t, kTagJitter, 0), a.k0, a.k1);
+    eps_t = (float)((double)c.eps * (1.0 + (double)a.jitter * (2.0 * (double)u01(wj.x) - 1.0)));
+  }
+  c.eps_t = eps_t;
+  double ke = 0.0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    c.p[j] = z[j] / sqrt(a.im[j]);
+    ke += a.im[j] * c.p[j] * c.p[j];
+  }
+  c.H0 = c.U0 + 0.5 * ke;
+  c.ok = 1;
+  c.l = 0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    c.p[j] -= 0.5 * (double)eps_t * c.g0[j];
+    c.x[j] = c.x0[j] + (double)eps_t * a.im[j] * c.p[j];
+    pt[j] = c.x[j];
+  }
+}
+
+__global__ void __launch_bounds__(kRedThreads) shear_hmc_update_kernel(ShearHmcArgs a, int init) {
+  __shared__ double red[kRedThreads][6];
+  const int chain = blockIdx.x;
+  double v[6];
+  reduce_point(a.partial, a.n_blocks, a.C, chain, red, v);
+  if (threadIdx.x != 0) return;
+  ShearChain c = a.state[chain];
+  double* pt = a.pts + 5 * (int64_t)chain;
+  const uint32_t uid = (uint32_t)(a.uid_base + (uint64_t)chain);
+  const double U = hyper_inside(pt) ? -v[0] : INFINITY;
+  double gU[5];
+#pragma unroll
+  for (int j = 0; j < 5; ++j) gU[j] = -v[1 + j];
+  if (init) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      c.x0[j] = pt[j];
+      c.g0[j] = gU[j];
+    }
+    c.U0 = U;
+    c.eps = a.eps0;
+    c.hbar = 0.0;
+    c.lbar = 0.0;
+    c.t = 0;
+    c.n_acc = 0;
+    c.n_div = 0;
+    c.status = isfinite(U) ? 0u : 1u;
+    c.sum_alpha = 0.0;
+    if (a.t_stop > 0) shear_begin_iteration(a, c, uid, pt);
+    a.state[chain] = c;
+    return;
+  }
+  if (c.t >= a.t_stop) return;
+  c.l += 1;
+  if (!isfinite(U)) c.ok = 0;
+  const double e = (double)c.eps_t;
+  if (c.l < a.L) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      c.p[j] -= e * gU[j];
+      c.x[j] += e * a.im[j] * c.p[j];
+      pt[j] = c.x[j];
+    }
+    a.state[chain] = c;
+    return;
+  }
+  double ke = 0.0;
+#pragma unroll
+  for (int j = 0; j < 5; ++j) {
+    c.p[j] -= 0.5 * e * gU[j];
+    ke += a.im[j] * c.p[j] * c.p[j];
+  }
+  const double dH = U + 0.5 * ke - c.H0;
+  const bool finite = isfinite(dH);
+  const bool accept = c.ok && finite && log(c.u_acc) < -dH;
+  const double alpha = (c.ok && finite) ? fmin(1.0, exp(-dH)) : 0.0;
+  if (!finite || fabs(dH) > kDivergence) {
+    c.n_div += 1;
+    c.status |= finite ? 4u : 2u;
+  }
+  if (!c.ok) c.status |= 1u;
+  if (a.trace) {
+    float* tr = a.trace + ((int64_t)chain * a.t_stop + c.t) * 4;
+    tr[0] = c.eps;
+    tr[1] = (float)dH;
+    tr[2] = (float)alpha;
+    tr[3] = accept ? 1.0f : 0.0f;
+  }
+  if (accept) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      c.x0[j] = c.x[j];
+      c.g0[j] = gU[j];
+    }
+    c.U0 = U;
+  }
+  if (c.t < a.W) {
+    if (a.adapt) {
+      const double m = (double)(c.t + 1);
+      const double eta = 1.0 / (m + kDaT0);
+      c.hbar = (1.0 - eta) * c.hbar + eta * ((double)a.delta - alpha);
+      const double le = a.mu - sqrt(m) / kDaGamma * c.hbar;
+      const double xw = pow(m, -kDaKappa);
+      c.lbar = xw * le + (1.0 - xw) * c.lbar;
+      c.eps = (c.t == a.W - 1) ? (float)exp(c.lbar) : (float)exp(le);
+    }
+  } else {
+    c.n_acc += accept ? 1 : 0;
+    c.sum_alpha += alpha;
+    if (a.samples) {
+      double* o = a.samples + ((int64_t)chain * a.S + (c.t - a.W)) * 5;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) o[j] = c.x0[j];
+    }
+  }
+  c.t += 1;
+  c.l = 0;
+  if (c.t < a.t_stop) shear_begin_iteration(a, c, uid, pt);
+  a.state[chain] = c;
+}
+
+__global__ void shear_hmc_stats_kernel(const ShearChain* __restrict__ st, int C, int S,
+                                       double* __restrict__ stats) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= C) return;
+  const ShearChain& x = st[c];
+  stats[4 * c + 0] = S > 0 ? (double)x.n_acc / (double)S : 0.0;
+  stats[4 * c + 1] = (double)x.eps;
+  stats[4 * c + 2] = (double)x.n_div;
+  stats[4 * c + 3] = -x.U0;
 }
 
 }  // namespace
@@ -227,8 +420,20 @@ hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s) {
 hipError_t launch_shear_reduce(const double* partial, int n_blocks, int n_pts, const double* pts,
                                double* logpost, double* grad, hipStream_t s) {
   if (n_pts <= 0) return hipSuccess;
-  hipLaunchKernelGGL(shear_reduce_kernel, dim3((n_pts + 127) / 128), dim3(128), 0, s, partial,
-                     n_blocks, n_pts, pts, logpost, grad);
+  hipLaunchKernelGGL(shear_reduce_kernel, dim3(n_pts), dim3(kRedThreads), 0, s, partial, n_blocks,
+                     n_pts, pts, logpost, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_shear_hmc_update(const ShearHmcArgs& a, int init, hipStream_t s) {
+  if (a.C <= 0) return hipSuccess;
+  hipLaunchKernelGGL(shear_hmc_update_kernel, dim3(a.C), dim3(kRedThreads), 0, s, a, init);
+  return hipGetLastError();
+}
+
+hipError_t launch_shear_hmc_stats(const ShearChain* st, int C, int S, double* stats, hipStream_t s) {
+  if (C <= 0 || !stats) return hipSuccess;
+  hipLaunchKernelGGL(shear_hmc_stats_kernel, dim3(1), dim3(64), 0, s, st, C, S, stats);
   return hipGetLastError();
 }
 

@@ -50,3 +50,26 @@ def init_positions(t, params, data, off, C, seed):
             out[i, c] = hmc.init_chain(d, float(t.sigma[i]), math.log10(params[i, 1]), es, seed,
                                        i * C + c)
     return out
+
+
+def interim_population(G, K, seed, g=(0.02, 0.0), sig_e=0.2, e_max=0.7, mu_ln_s=math.log(0.6),
+                       sig_ln_s=0.3, noise_e=0.05, noise_ln_s=0.05):
+    """Stand-in interim samples with a population behind them: galaxy n has an
+    intrinsic ellipticity from a circular Gaussian truncated at e_max, lensed
+    by g with the oracle's shear map, and a lognormal size; its K samples
+    scatter around those with measurement-like noise (ellipticities kept
+    inside |e| < 0.95).  Returns float32 (e1', e2', log10 s, log10 F), each
+    [G, K]."""
+    rng = np.random.default_rng(seed)
+    e = np.empty(0, complex)
+    while e.size < G:
+        z = rng.normal(0, sig_e, 2 * G) + 1j * rng.normal(0, sig_e, 2 * G)
+        e = np.concatenate([e, z[np.abs(z) < e_max]])
+    ep = shear.shear_forward(e[:G], complex(*g))
+    ln_s = rng.normal(mu_ln_s, sig_ln_s, G)
+    smp = ep[:, None] + rng.normal(0, noise_e, (G, K)) + 1j * rng.normal(0, noise_e, (G, K))
+    r = np.abs(smp)
+    smp = np.where(r < 0.95, smp, smp * 0.9 / np.maximum(r, 1e-12))
+    l10s = (ln_s[:, None] + rng.normal(0, noise_ln_s, (G, K))) / math.log(10.0)
+    l10f = rng.normal(3.0, 0.1, (G, K))
+    return [a.astype(np.float32) for a in (smp.real, smp.imag, l10s, l10f)]

@@ -48,10 +48,13 @@ int main(void) {
   printf("bsi_interim %zu\n", sizeof(bsi_interim));
   printf("bsi_hmc_cfg %zu\n", sizeof(bsi_hmc_cfg));
   printf("bsi_true_prior %zu\n", sizeof(bsi_true_prior));
+  printf("bsi_shear_hmc_cfg %zu\n", sizeof(bsi_shear_hmc_cfg));
   F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile)
   F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
   F(bsi_hmc_cfg, trace)
   F(bsi_true_prior, mu_ln_f) F(bsi_true_prior, sigma_ln_f)
+  F(bsi_shear_hmc_cfg, jitter) F(bsi_shear_hmc_cfg, inv_mass) F(bsi_shear_hmc_cfg, seed)
+  F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)
   return 0;
 }
 """
@@ -65,11 +68,12 @@ int main(void) {
     assert int(out["bsi_interim"]) == C.sizeof(native.Interim)
     assert int(out["bsi_hmc_cfg"]) == C.sizeof(native.HmcCfg)
     assert int(out["bsi_true_prior"]) == C.sizeof(native.TruePrior)
+    assert int(out["bsi_shear_hmc_cfg"]) == C.sizeof(native.ShearHmcCfg)
     for key, val in out.items():
         if "." in key:
             t, m = key.split(".")
             cls = {"bsi_batch": native.Batch, "bsi_hmc_cfg": native.HmcCfg,
-                   "bsi_true_prior": native.TruePrior}[t]
+                   "bsi_true_prior": native.TruePrior, "bsi_shear_hmc_cfg": native.ShearHmcCfg}[t]
             assert getattr(cls, m).offset == int(val), key
 
 
@@ -86,6 +90,8 @@ def test_no_device_and_null_handle_paths(native):
     assert lib.bsi_render_stamps(None, C.byref(b), None, None, None) == -1
     assert lib.bsi_loglik_grad(None, C.byref(b), None, None, None, None, None, 0, None) == -1
     assert lib.bsi_ess(None, 1, 1, 10, 1, None, None, None, None) == -1
+    assert lib.bsi_shear_hmc(None, 1, 1, None, None, None, None, None, None, None, None, None,
+                             None, None) == -1
     lib.bsi_destroy(None)
     assert lib.bsi_device_count(None) == -1
 

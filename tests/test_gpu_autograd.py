@@ -1,0 +1,91 @@
+"""torch.autograd wrappers over the library's hand-written adjoints.
+
+LogLik: on 256 parameter sets drawn like the 32 x 32 plain-method workload,
+the backward pass equals grad_out times the oracle's forward-mode gradient
+(tolerance 1e-4 of |g| + sqrt(F_jj), as for bsi_loglik_grad), and log L
+matches to 1e-6 relative.  ShearLogPost: backward equals grad_out times the
+oracle's softmax-weighted derivative of the log importance weights.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import render, shear                            # noqa: E402
+from workloads import gen                                    # noqa: E402
+from tests import synth                                      # noqa: E402
+
+PS = gen.PIXEL_SCALE
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods(device):
+    from paper_2604_22048_amd import api, autograd
+    return api, autograd
+
+
+def test_loglik_autograd_on_256_parameter_sets(mods):
+    import torch
+    api, ag = mods
+    _log("autograd LogLik 256 sets")
+    G, N = 256, 32
+    tr = gen.draw_truth(gen.CONFIGS["tiny"], n_gal=G, seed=4242)
+    rng = np.random.default_rng(4244)
+    truth = np.stack([tr.flux, tr.hlr, tr.e1, tr.e2, tr.dx, tr.dy], axis=1)
+    data = np.concatenate([(render.render_one(truth[i], N, PS, tr.psf_fwhm[i]) +
+                            rng.normal(0, 1, (N, N))).ravel() for i in range(G)]).astype(np.float32)
+    params = truth * np.c_[rng.uniform(0.9, 1.1, G), rng.uniform(0.9, 1.1, G), np.ones((G, 4))]
+    params[:, 2:4] += rng.uniform(-0.05, 0.05, (G, 2))
+    params[:, 4:6] += rng.uniform(-0.2, 0.2, (G, 2))
+    p32 = params.astype(np.float32)
+    b = api.Batch(n=np.full(G, N), psf_fwhm=torch.tensor(tr.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.ones(G, device="cuda"), pixel_scale=PS)
+    pt = torch.tensor(p32, device="cuda", requires_grad=True)
+    ll = ag.loglik(pt, torch.tensor(data).cuda(), b)
+    w = torch.tensor(rng.uniform(-2, 2, G), dtype=torch.float64, device="cuda")
+    (w * ll).sum().backward()
+    got = pt.grad.cpu().numpy()
+    llv = ll.detach().cpu().numpy()
+    wv = w.cpu().numpy()
+    for i in range(G):
+        d = data[i * N * N:(i + 1) * N * N].reshape(N, N).astype(np.float64)
+        p = p32[i].astype(np.float64)
+        psf = float(np.float32(tr.psf_fwhm[i]))
+        rll, rg = render.loglik_grad(d, p, N, PS, psf, 1.0)
+        assert abs(llv[i] - rll) <= 1e-6 * abs(rll), (i, llv[i], rll)
+        _, dT = render.spectrum(p, N, PS, psf, derivs=True)
+        sc = np.array([math.sqrt(np.sum(render.synthesize(dT[j], N) ** 2)) for j in range(6)])
+        assert np.all(np.abs(got[i] - wv[i] * rg) <= 1e-4 * abs(wv[i]) * (np.abs(rg) + sc)), \
+            (i, got[i], wv[i] * rg, sc)
+
+
+def test_shear_logpost_autograd(mods):
+    import torch
+    api, ag = mods
+    _log("autograd ShearLogPost")
+    S = synth.interim_population(48, 200, 60)
+    St = [torch.tensor(a).cuda() for a in S]
+    Sd = [a.astype(np.float64) for a in S]
+    pts0 = np.array([[0.02, -0.01, math.log(0.6), 0.3, 0.2], [-0.03, 0.04, -0.4, 0.25, 0.18],
+                     [0.0, 0.0, -0.6, 0.35, 0.22]])
+    pts = torch.tensor(pts0, dtype=torch.float64, device="cuda", requires_grad=True)
+    tpg = api.TruePriorCfg(e_kind=1, e_max=0.95)
+    lp = ag.shear_logpost(pts, St[0], St[1], St[2], St[3], tpg)
+    w = torch.tensor([1.0, -0.5, 2.0], dtype=torch.float64, device="cuda")
+    (w * lp).sum().backward()
+    got = pts.grad.cpu().numpy()
+    tpo = shear.TruePrior(e_kind=1, e_max=0.95)
+    for j in range(3):
+        rl, rg = shear.log_posterior_grad(Sd, complex(*pts0[j, :2]), tuple(pts0[j, 2:]), tpo,
+                                          shear.Interim())
+        assert abs(lp[j].item() - rl) <= 1e-6 * (abs(rl) + 48)
+        assert np.all(np.abs(got[j] - w[j].item() * rg) <= 1e-4 * abs(w[j].item()) *
+                      (np.abs(rg) + math.sqrt(48.0) * 5.0)), (j, got[j], rg)

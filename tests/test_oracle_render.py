@@ -166,3 +166,33 @@ def test_loglik_perfect_model_is_zero():
     assert render.loglik(m, p, 25, PS, 0.7, 1.0) == 0.0
     ll, g = render.loglik_grad(m, p, 25, PS, 0.7, 1.0)
     assert np.all(np.abs(g) < 1e-9)
+
+
+def test_gradient_central_differences_on_256_parameter_sets():
+    """The analytic gradient against plain central differences (relative step
+    1e-4) on 256 parameter sets drawn like the 32 x 32 plain-method workload,
+    each evaluated on its own noisy stamp at a perturbed position."""
+    from workloads import gen
+    cfg = gen.CONFIGS["tiny"]
+    tr = gen.draw_truth(cfg, n_gal=256, seed=4242)
+    rng = np.random.default_rng(4243)
+    N = 32
+    worst = 0.0
+    for i in range(256):
+        t = np.array([tr.flux[i], tr.hlr[i], tr.e1[i], tr.e2[i], tr.dx[i], tr.dy[i]])
+        d = render.render_one(t, N, PS, tr.psf_fwhm[i]) + rng.normal(0, 1, (N, N))
+        p = t * [rng.uniform(0.9, 1.1), rng.uniform(0.9, 1.1), 1, 1, 1, 1] + \
+            np.r_[0, 0, rng.uniform(-0.05, 0.05, 2), rng.uniform(-0.2, 0.2, 2)]
+        _, g = render.loglik_grad(d, p, N, PS, tr.psf_fwhm[i], 1.0)
+        _, dT = render.spectrum(p, N, PS, tr.psf_fwhm[i], derivs=True)
+        scale = [math.sqrt(np.sum(render.synthesize(dT[j], N) ** 2)) for j in range(6)]
+        f = lambda q: render.loglik(d, q, N, PS, tr.psf_fwhm[i], 1.0)
+        for j in range(6):
+            h = 1e-4 * max(1.0, abs(p[j]))
+            e = np.zeros(6)
+            e[j] = h
+            fd = (f(p + e) - f(p - e)) / (2 * h)
+            err = abs(fd - g[j]) / (abs(g[j]) + scale[j])
+            worst = max(worst, err)
+            assert err <= 1e-5, (i, j, fd, g[j], scale[j])
+    assert worst > 0.0

@@ -144,3 +144,54 @@ def test_exact_ellipticities_recover_shear_on_grid():
     # exact intrinsic shapes: the posterior centre is g plus the shape-noise mean
     assert abs(m1 - 0.02) < 4 * s1 and abs(m2) < 4 * s1
     assert 0.001 < s1 < 0.01
+
+
+def test_shear_level_hmc_against_importance_sampling():
+    """Shear-level HMC (the per-galaxy sampler on the five population
+    parameters) against an estimate built without it: self-normalised
+    importance sampling of the posterior from a widened Gaussian around the
+    mode (quasi-Newton optimum, finite-difference Hessian).  Chain means and
+    standard deviations agree within their Monte-Carlo errors."""
+    from scipy.optimize import minimize
+    from oracle import diagnostics, hmc
+    from tests import synth
+    S = [a.astype(np.float64) for a in synth.interim_population(40, 64, 11)]
+    tp = shear.TruePrior(e_kind=shear.E_KIND_TRUNC_GAUSS, e_max=0.95)
+    ip = shear.Interim()
+    pot = shear.hyper_potential(S, tp, ip)
+    x0 = np.array([0.0, 0.0, math.log(0.6), 0.3, 0.25])
+    res = minimize(lambda x: pot(x)[0], x0, jac=lambda x: pot(x)[1], method="L-BFGS-B",
+                   bounds=[(-0.5, 0.5), (-0.5, 0.5), (-2.0, 1.0), (0.05, 1.0), (0.05, 0.9)],
+                   options=dict(gtol=1e-9, ftol=1e-14))
+    xm = res.x
+    H = np.zeros((5, 5))
+    for j in range(5):
+        e = np.zeros(5)
+        e[j] = 1e-5
+        H[j] = (pot(xm + e)[1] - pot(xm - e)[1]) / 2e-5
+    cov = np.linalg.inv(0.5 * (H + H.T))
+    sd = np.sqrt(np.diag(cov))
+    # importance sampling from N(xm, 1.5^2 cov)
+    rng = np.random.default_rng(12)
+    n_is = 3000
+    Lc = np.linalg.cholesky(2.25 * cov)
+    z = rng.normal(size=(n_is, 5))
+    xs = xm + z @ Lc.T
+    lq = -0.5 * np.sum(z * z, axis=1)
+    lp = np.array([shear.log_posterior(S, complex(x[0], x[1]), tuple(x[2:]), tp, ip) for x in xs])
+    lw = lp - lq
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    n_is_eff = 1.0 / np.sum(w * w)
+    assert n_is_eff > 500
+    m_is = w @ xs
+    s_is = np.sqrt(w @ (xs - m_is) ** 2)
+    out = hmc.run_chain(pot, xm, seed=99, uid=3, L=6, n_warmup=80, n_samples=240,
+                        eps0=0.5, adapt=True, inv_mass=sd ** 2, jitter=0.1)
+    x = out["samples"]
+    assert out["accept_rate"] > 0.5
+    for j in range(5):
+        n_eff = max(diagnostics.ess(x[None, :, j]), 20.0)
+        se = math.sqrt(s_is[j] ** 2 / n_eff + s_is[j] ** 2 / n_is_eff)
+        assert abs(x[:, j].mean() - m_is[j]) < 4 * se, (j, x[:, j].mean(), m_is[j], se)
+        assert 0.7 < x[:, j].std() / s_is[j] < 1.4, (j, x[:, j].std(), s_is[j])
