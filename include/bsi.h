@@ -271,6 +271,93 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
                   const bsi_interim* interim, const bsi_shear_hmc_cfg* cfg, const double* init,
                   double* samples, double* chain_stats, bsi_stream stream);
 
+/* ---- Request serving: slot-based continuous batching of phase 1 ----------
+ *
+ * A server keeps the chains of many independent galaxy-fit requests resident
+ * on the device.  Requests of any of the configured stamp sizes are admitted
+ * while their device footprint fits in the server's HBM budget (a fixed part
+ * per request -- chain states and stored samples -- plus the stamp and its
+ * spectrum, carved from an arena); each bsi_slots_advance moves every
+ * resident request forward by a number of HMC iterations, one launch per
+ * stamp size, the sizes running concurrently; a request that has run
+ * n_warmup + n_samples iterations is finished and is returned by
+ * bsi_slots_harvest, which frees its slot and memory for new admissions.
+ * Chain c of request `id` uses Philox counter uid id * n_chains + c, and the
+ * iteration is exactly that of bsi_hmc_sample, so a request's samples do not
+ * depend on which other requests share the device: with
+ * uid_base = id * n_chains a one-galaxy bsi_hmc_sample call gives the same
+ * samples.  A server is used from one host thread, with its handle, and
+ * orders all its work on the stream given at creation. */
+typedef struct bsi_slots_s* bsi_slots;
+
+typedef struct {
+  int32_t n_sizes;             /* number of stamp sizes served, 1..16                     */
+  const int32_t* sizes;        /* [host] the stamp sides, 8..128, distinct                  */
+  int64_t hbm_budget;          /* device bytes held by the server for request state, > 0    */
+  int32_t max_slots;           /* resident-request limit; 0 = as many as the budget allows  */
+  bsi_hmc_cfg hmc;             /* n_chains, n_leapfrog, n_warmup, n_samples, adapt, metric,
+                                  step_size, target_accept, jitter and seed are used; form,
+                                  iters_per_launch, use_graph, uid_base and trace are not   */
+  bsi_interim interim;
+  float pixel_scale;
+  int32_t profile;             /* BSI_PROFILE_*                                             */
+} bsi_slots_cfg;
+
+typedef struct {
+  uint64_t id;                 /* request id (chain uids id * n_chains + c)                 */
+  int32_t n;                   /* stamp side, one of the configured sizes                   */
+  const float* stamp;          /* [device] N * N floats, row-major; copied by the next
+                                  bsi_slots_advance, so it must stay valid and unchanged
+                                  until that call's work has run on the server's stream     */
+  float psf_fwhm, sigma;       /* PSF FWHM [arcsec] and pixel noise sigma, > 0              */
+  float ref_x, ref_y;          /* reference centroid, pixels from the stamp centre          */
+  const float* init;           /* [host] float[n_chains][6] start positions (theta)         */
+} bsi_request;
+
+typedef struct {
+  int32_t resident;            /* requests holding a slot (running or finished)             */
+  int32_t finished;            /* of which finished and not yet harvested                   */
+  int32_t pending;             /* admitted since the last bsi_slots_advance                 */
+  int32_t max_slots;
+  int64_t budget;              /* bytes held (per-request arrays plus arena)                */
+  int64_t slot_fixed_bytes;    /* per-request bytes independent of the stamp size           */
+  int64_t arena_bytes, arena_free, arena_largest_free;
+} bsi_slots_info;
+
+/* Create a server on handle h (which must outlive it).  BSI_EINVAL when the
+ * budget cannot hold one request of the largest size; BSI_EUNSUPPORTED when
+ * a size with n_chains chains does not fit in LDS. */
+int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, bsi_slots* out);
+
+/* Wait for the server's work and release its device memory; NULL is ignored. */
+void bsi_slots_destroy(bsi_slots s);
+
+/* Device bytes request of side n would hold (fixed part plus stamp-dependent part). */
+int bsi_slots_footprint(bsi_slots s, int32_t n, int64_t* bytes);
+
+/* Admit request r if a slot is free and its footprint fits; *admitted = 1 if
+ * so, 0 if the server is full (nothing changes then).  The request starts
+ * running at the next bsi_slots_advance. */
+int bsi_slots_admit(bsi_slots s, const bsi_request* r, int32_t* admitted);
+
+/* Enqueue n_iter >= 1 HMC iterations for every resident, unfinished request
+ * (admitted requests are first initialised: data spectrum, metric, start
+ * potential).  Returns without waiting for the device. */
+int bsi_slots_advance(bsi_slots s, int32_t n_iter);
+
+/* Wait for the enqueued work, then hand out up to max finished requests in
+ * the order they finished and free their slots:
+ *   ids          [host] uint64[max]
+ *   samples      [device] float[max][n_chains][n_samples][6] (theta) or NULL
+ *   chain_stats  [device] float[max][n_chains][4] as in bsi_hmc_sample, or NULL
+ *   status       [device] uint32[max] (BSI_STATUS_* bits) or NULL
+ * *n_out receives the number handed out.  Outputs are complete on return. */
+int bsi_slots_harvest(bsi_slots s, int32_t max, uint64_t* ids, float* samples,
+                      float* chain_stats, uint32_t* status, int32_t* n_out);
+
+/* Occupancy and memory of the server. */
+int bsi_slots_get_info(bsi_slots s, bsi_slots_info* info);
+
 /*
  * bsi_ess -- diagnostics of Section 4.1 for stored samples:
  * multi-chain effective sample size per parameter (autocorrelation with

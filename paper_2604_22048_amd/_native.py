@@ -58,6 +58,25 @@ class ShearHmcCfg(C.Structure):
                 ("trace", C.c_void_p)]
 
 
+class SlotsCfg(C.Structure):
+    _fields_ = [("n_sizes", C.c_int32), ("sizes", C.POINTER(C.c_int32)), ("hbm_budget", C.c_int64),
+                ("max_slots", C.c_int32), ("hmc", HmcCfg), ("interim", Interim),
+                ("pixel_scale", C.c_float), ("profile", C.c_int32)]
+
+
+class Request(C.Structure):
+    _fields_ = [("id", C.c_uint64), ("n", C.c_int32), ("stamp", C.c_void_p), ("psf_fwhm", C.c_float),
+                ("sigma", C.c_float), ("ref_x", C.c_float), ("ref_y", C.c_float),
+                ("init", C.POINTER(C.c_float))]
+
+
+class SlotsInfo(C.Structure):
+    _fields_ = [("resident", C.c_int32), ("finished", C.c_int32), ("pending", C.c_int32),
+                ("max_slots", C.c_int32), ("budget", C.c_int64), ("slot_fixed_bytes", C.c_int64),
+                ("arena_bytes", C.c_int64), ("arena_free", C.c_int64),
+                ("arena_largest_free", C.c_int64)]
+
+
 # exported symbol -> (restype, argtypes)
 SIGNATURES = {
     "bsi_version": (C.c_int, []),
@@ -79,6 +98,14 @@ SIGNATURES = {
                                 C.c_void_p, C.POINTER(TruePrior), C.POINTER(Interim),
                                 C.POINTER(ShearHmcCfg), C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p]),
+    "bsi_slots_create": (C.c_int, [C.c_void_p, C.POINTER(SlotsCfg), C.c_void_p, C.POINTER(C.c_void_p)]),
+    "bsi_slots_destroy": (None, [C.c_void_p]),
+    "bsi_slots_footprint": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
+    "bsi_slots_admit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int32)]),
+    "bsi_slots_advance": (C.c_int, [C.c_void_p, C.c_int32]),
+    "bsi_slots_harvest": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64), C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+    "bsi_slots_get_info": (C.c_int, [C.c_void_p, C.POINTER(SlotsInfo)]),
     "bsi_ess": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p]),
 }

@@ -4,6 +4,7 @@ the HIP library; this module only checks shapes and passes pointers."""
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -292,6 +293,81 @@ def shear_hmc(e1p, e2p, log10s, log10f, true_prior: TruePriorCfg, cfg: ShearHmcC
                                     C.c_void_p(init_np.ctypes.data), _ptr(samples), _ptr(stats),
                                     _stream(dev)), "bsi_shear_hmc")
     return samples, stats
+
+
+class Slots:
+    """Request server (bsi_slots_*): admit galaxy-fit requests while their
+    device footprint fits, advance all resident chains, harvest finished
+    requests.  Work is ordered on the stream current at creation."""
+
+    def __init__(self, sizes, cfg: HmcConfig, hbm_budget: int, max_slots: int = 0, interim=None,
+                 pixel_scale: float = 0.2, profile: int = N.PROFILE_EXPONENTIAL,
+                 device: int = 0, lib: Library | None = None):
+        self.lib = lib or get(device)
+        self.device = torch.device("cuda", device)
+        self.cfg = cfg
+        self._sizes = (C.c_int32 * len(sizes))(*[int(x) for x in sizes])
+        c = N.SlotsCfg(len(sizes), C.cast(self._sizes, C.POINTER(C.c_int32)), int(hbm_budget),
+                       int(max_slots), cfg.c(), _interim(interim), float(pixel_scale), int(profile))
+        self._stream = torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        self.lib.check(self.lib.lib.bsi_slots_create(self.lib.h, C.byref(c),
+                                                     C.c_void_p(self._stream.cuda_stream),
+                                                     C.byref(h)), "bsi_slots_create")
+        self.h = h
+        self._keep = []          # stamps referenced by not yet advanced admissions
+
+    def footprint(self, n: int) -> int:
+        b = C.c_int64()
+        self.lib.check(self.lib.lib.bsi_slots_footprint(self.h, int(n), C.byref(b)), "bsi_slots_footprint")
+        return int(b.value)
+
+    def admit(self, rid: int, stamp: torch.Tensor, psf_fwhm: float, sigma: float, ref_xy, init) -> bool:
+        n = int(round(math.sqrt(stamp.numel())))
+        assert stamp.is_cuda and stamp.dtype == torch.float32 and stamp.is_contiguous()
+        ini = np.ascontiguousarray(np.asarray(init, dtype=np.float32).reshape(self.cfg.n_chains, 6))
+        r = N.Request(int(rid), n, stamp.data_ptr(), float(psf_fwhm), float(sigma), float(ref_xy[0]),
+                      float(ref_xy[1]), ini.ctypes.data_as(C.POINTER(C.c_float)))
+        ok = C.c_int32(0)
+        self.lib.check(self.lib.lib.bsi_slots_admit(self.h, C.byref(r), C.byref(ok)), "bsi_slots_admit")
+        if ok.value:
+            self._keep.append(stamp)
+        return bool(ok.value)
+
+    def advance(self, n_iter: int):
+        self.lib.check(self.lib.lib.bsi_slots_advance(self.h, int(n_iter)), "bsi_slots_advance")
+        self._keep_prev, self._keep = self._keep, []
+
+    def harvest(self, max_n: int, want_samples: bool = True):
+        """(ids [n] uint64 numpy, samples [n, C, S, 6], chain_stats [n, C, 4], status [n])."""
+        Cn, S = self.cfg.n_chains, self.cfg.n_samples
+        smp = torch.empty(max_n, Cn, S, 6, dtype=torch.float32, device=self.device) if want_samples else None
+        st = torch.empty(max_n, Cn, 4, dtype=torch.float32, device=self.device)
+        stat = torch.empty(max_n, dtype=torch.int32, device=self.device)
+        ids = (C.c_uint64 * max(max_n, 1))()
+        n = C.c_int32(0)
+        self.lib.check(self.lib.lib.bsi_slots_harvest(self.h, int(max_n), ids, _ptr(smp), _ptr(st),
+                                                      _ptr(stat), C.byref(n)), "bsi_slots_harvest")
+        k = n.value
+        self._keep_prev = []
+        out_ids = np.array(ids[:k], dtype=np.uint64)
+        return out_ids, (smp[:k] if smp is not None else None), st[:k], stat[:k]
+
+    def info(self) -> dict:
+        i = N.SlotsInfo()
+        self.lib.check(self.lib.lib.bsi_slots_get_info(self.h, C.byref(i)), "bsi_slots_get_info")
+        return {f: getattr(i, f) for f, _ in N.SlotsInfo._fields_}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lib.bsi_slots_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ess(samples: torch.Tensor, lib: Library | None = None):

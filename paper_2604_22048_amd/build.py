@@ -15,7 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbsi.so")
-SOURCES = ["transform.hip", "likelihood.hip", "hmc.hip", "shear.hip", "diag.hip", "api.cpp"]
+SOURCES = ["transform.hip", "likelihood.hip", "hmc.hip", "shear.hip", "diag.hip", "slots.hip", "api.cpp",
+           "slots.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -28,7 +29,7 @@ FLAGS = [
 
 
 def _compile(src: str, bdir: str, defines=()) -> str:
-    obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
+    obj = os.path.join(bdir, src.replace(".", "_") + ".o")
     cmd = [HIPCC, *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     if src.endswith(".cpp"):
         cmd[1:1] = ["-x", "hip"]

@@ -13,63 +13,16 @@
 #include <vector>
 
 #include "bsi_kernels.h"
+#include "ctx.h"
 #include "kspace.h"
 
 using namespace bsi;
 
+using namespace bsi_host;
+
 namespace {
 
 thread_local std::string g_create_error;
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t n = 0;
-};
-
-}  // namespace
-
-struct bsi_ctx {
-  int device = 0;
-  int num_cu = 0;
-  std::string err;
-  hipStream_t own = nullptr;
-  DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts, shear_state;
-};
-
-namespace {
-
-int fail(bsi_handle h, int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof(buf), fmt, ap);
-  va_end(ap);
-  if (h) h->err = buf;
-  return code;
-}
-
-int hip_fail(bsi_handle h, hipError_t e, const char* where) {
-  return fail(h, BSI_EHIP, "%s: %s", where, hipGetErrorString(e));
-}
-
-int ensure(bsi_handle h, DevBuf& b, size_t bytes) {
-  if (bytes <= b.n) return BSI_OK;
-  if (b.p) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(h, e, "workspace sync");
-    (void)hipFree(b.p);
-    b.p = nullptr;
-    b.n = 0;
-  }
-  const size_t n = std::max<size_t>(bytes, 256);
-  hipError_t e = hipMalloc(&b.p, n);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(h, BSI_ENOMEM, "workspace allocation of %zu bytes failed", n);
-  }
-  b.n = n;
-  return BSI_OK;
-}
 
 struct ClassRange {
   int N;
@@ -210,9 +163,15 @@ int bsi_create(bsi_handle* out, int32_t device) {
   bsi_ctx* h = new bsi_ctx();
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
-  if (hipStreamCreate(&h->own) != hipSuccess) {
-    delete h;
-    g_create_error = "stream creation failed";
+  bool ok = hipStreamCreate(&h->own) == hipSuccess &&
+            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; ok && i < kAuxStreams; ++i)
+    ok = hipStreamCreate(&h->aux[i]) == hipSuccess &&
+         hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    bsi_destroy(h);
+    g_create_error = "stream or event creation failed";
     return BSI_EHIP;
   }
   *out = h;
@@ -227,6 +186,11 @@ void bsi_destroy(bsi_handle h) {
                     &h->partial, &h->pts, &h->shear_state})
     if (b->p) (void)hipFree(b->p);
   if (h->own) (void)hipStreamDestroy(h->own);
+  for (int i = 0; i < kAuxStreams; ++i) {
+    if (h->aux[i]) (void)hipStreamDestroy(h->aux[i]);
+    if (h->ev_join[i]) (void)hipEventDestroy(h->ev_join[i]);
+  }
+  if (h->ev_fork) (void)hipEventDestroy(h->ev_fork);
   delete h;
 }
 
@@ -406,16 +370,15 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     const int ipl = std::min(cfg->iters_per_launch, std::max(T, 1));
     const int n_launch = (T + ipl - 1) / ipl;
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-      for (const ClassRange& c : p.classes) {
+      return fork_join(h, st, (int)p.classes.size(), [&](int i, hipStream_t sc) {
+        const ClassRange& c = p.classes[i];
         HmcArgs ac = a;
         ac.N = c.N;
         ac.gidx = gidx_ptr(h, c);
         ac.n_gal = c.count;
         ac.n_steps = ipl * a.L;
-        hipError_t e = launch_hmc_advance(ac, c.count, st);
-        if (e != hipSuccess) return e;
-      }
-      return hipSuccess;
+        return launch_hmc_advance(ac, c.count, sc);
+      });
     };
     if (cfg->use_graph && n_launch > 1) {
       hipGraph_t graph = nullptr;

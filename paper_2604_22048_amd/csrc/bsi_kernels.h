@@ -63,7 +63,8 @@ struct ChainState {
   uint32_t status;     // BSI_STATUS_* bits
   float sum_alpha;     // sum of acceptance statistics over stored iterations
   float u_acc;         // Metropolis uniform of the current trajectory
-  float pad[8];
+  uint32_t uid;        // Philox counter word 0 of this chain
+  float pad[7];
 };
 static_assert(sizeof(ChainState) == 256, "ChainState must be 64 words");
 
@@ -77,6 +78,7 @@ struct HmcArgs {
   const float* ref_xy;
   const float* init;      // [gal][C][6] (init kernel only)
   const float* inv_mass;  // [gal][6] or NULL (init kernel only)
+  const uint64_t* uid_gal;  // [gal] chain-uid base or NULL: uid_base + gal * C (init kernel only)
   ChainState* state;      // [gal][C]
   float* samples;         // [gal][C][S][6] or NULL
   float* trace;           // [gal][C][W+S][4] or NULL
@@ -150,6 +152,35 @@ struct ShearHmcArgs {
 };
 hipError_t launch_shear_hmc_update(const ShearHmcArgs& a, int init, hipStream_t s);
 hipError_t launch_shear_hmc_stats(const ShearChain* st, int C, int S, double* stats, hipStream_t s);
+
+// ---- slots.hip ----
+// One admitted request: where its slot's scalars go and where its stamp is
+// copied from and to (arena offsets are in floats for the stamp and in
+// complex bins for the data spectrum).
+struct SlotRecord {
+  int32_t slot, N;
+  float psf, sigma, refx, refy;
+  uint64_t uid;       // chain uid base of the request
+  uint64_t src;       // device address of the caller's stamp
+  int64_t off;        // stamp copy, floats from the arena start
+  int64_t bin_off;    // data spectrum, complex bins from the arena start
+};
+
+// Per-slot device arrays of the request server.
+struct SlotArrays {
+  int64_t* off;
+  int64_t* bin_off;
+  float* psf;
+  float* sigma;
+  float* ref_xy;      // [slot][2]
+  uint64_t* uid;
+  float* init;        // [slot][C][6]
+};
+hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C,
+                                const SlotArrays& sa, float* arena, hipStream_t s);
+hipError_t launch_slots_gather(const int32_t* list, int n, int C, int S, const ChainState* st,
+                               const float* samples, float* out, float* stats, uint32_t* status,
+                               hipStream_t s);
 
 // ---- diag.hip ----
 hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,

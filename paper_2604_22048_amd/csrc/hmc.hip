@@ -249,7 +249,7 @@ struct Regs {
   double U, H0, hbar, lbar, Uth;
   float eps, eps_t, sum_alpha, u_acc;
   int l, ok, t, n_acc, n_div;
-  uint32_t status;
+  uint32_t status, uid;
 };
 
 __device__ __forceinline__ Regs load_state(const ChainState* st) {
@@ -284,6 +284,7 @@ __device__ __forceinline__ Regs load_state(const ChainState* st) {
   r.status = bcast(w, 53);
   r.sum_alpha = f(54);
   r.u_acc = f(55);
+  r.uid = bcast(w, 56);
   return r;
 }
 
@@ -321,6 +322,7 @@ __device__ __forceinline__ void store_state(ChainState* st, const Regs& r) {
   put_u(53, r.status);
   put_f(54, r.sum_alpha);
   put_f(55, r.u_acc);
+  put_u(56, r.uid);
   reinterpret_cast<uint32_t*>(st)[lane] = w;
 }
 
@@ -366,9 +368,10 @@ __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
 template <int PROF, int P>
 __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
-                              const Prior& pr, ChainState* cs, uint32_t uid, float* samples_chain,
+                              const Prior& pr, ChainState* cs, float* samples_chain,
                               float* trace_chain) {
   const int lane = lane_id();
+  const uint32_t uid = cs->uid;
   Hot h;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -533,7 +536,6 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.refy = a.ref_xy[2 * (int64_t)gal + 1];
     const int64_t chain = (int64_t)gal * a.C + wave;
     ChainState* st = a.state + chain;
-    const uint32_t uid = (uint32_t)(a.uid_base + (uint64_t)chain);
     if (INIT) {
       Regs r;
       const float* ini = a.init + chain * 6;
@@ -567,6 +569,8 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       r.t = 0;
       r.n_acc = 0;
       r.n_div = 0;
+      r.uid = (uint32_t)((a.uid_gal ? a.uid_gal[gal] : a.uid_base + (uint64_t)gal * a.C) +
+                         (uint64_t)wave);
       store_state(st, r);
     } else {
       uint32_t* csw = reinterpret_cast<uint32_t*>(l.cs);
@@ -574,7 +578,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       wave_lds_sync();
       float* sc = a.samples ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = a.trace ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P>(a, c, lc, pr, l.cs, uid, sc, tc);
+      advance_chain<PROF, P>(a, c, lc, pr, l.cs, sc, tc);
       reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
     }
   }

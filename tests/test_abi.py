@@ -49,12 +49,19 @@ int main(void) {
   printf("bsi_hmc_cfg %zu\n", sizeof(bsi_hmc_cfg));
   printf("bsi_true_prior %zu\n", sizeof(bsi_true_prior));
   printf("bsi_shear_hmc_cfg %zu\n", sizeof(bsi_shear_hmc_cfg));
+  printf("bsi_slots_cfg %zu\n", sizeof(bsi_slots_cfg));
+  printf("bsi_request %zu\n", sizeof(bsi_request));
+  printf("bsi_slots_info %zu\n", sizeof(bsi_slots_info));
   F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile)
   F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
   F(bsi_hmc_cfg, trace)
   F(bsi_true_prior, mu_ln_f) F(bsi_true_prior, sigma_ln_f)
   F(bsi_shear_hmc_cfg, jitter) F(bsi_shear_hmc_cfg, inv_mass) F(bsi_shear_hmc_cfg, seed)
   F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)
+  F(bsi_slots_cfg, hbm_budget) F(bsi_slots_cfg, hmc) F(bsi_slots_cfg, interim)
+  F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile)
+  F(bsi_request, stamp) F(bsi_request, psf_fwhm) F(bsi_request, ref_y) F(bsi_request, init)
+  F(bsi_slots_info, budget) F(bsi_slots_info, arena_largest_free)
   return 0;
 }
 """
@@ -69,11 +76,16 @@ int main(void) {
     assert int(out["bsi_hmc_cfg"]) == C.sizeof(native.HmcCfg)
     assert int(out["bsi_true_prior"]) == C.sizeof(native.TruePrior)
     assert int(out["bsi_shear_hmc_cfg"]) == C.sizeof(native.ShearHmcCfg)
+    assert int(out["bsi_slots_cfg"]) == C.sizeof(native.SlotsCfg)
+    assert int(out["bsi_request"]) == C.sizeof(native.Request)
+    assert int(out["bsi_slots_info"]) == C.sizeof(native.SlotsInfo)
     for key, val in out.items():
         if "." in key:
             t, m = key.split(".")
             cls = {"bsi_batch": native.Batch, "bsi_hmc_cfg": native.HmcCfg,
-                   "bsi_true_prior": native.TruePrior, "bsi_shear_hmc_cfg": native.ShearHmcCfg}[t]
+                   "bsi_true_prior": native.TruePrior, "bsi_shear_hmc_cfg": native.ShearHmcCfg,
+                   "bsi_slots_cfg": native.SlotsCfg, "bsi_request": native.Request,
+                   "bsi_slots_info": native.SlotsInfo}[t]
             assert getattr(cls, m).offset == int(val), key
 
 
@@ -92,6 +104,10 @@ def test_no_device_and_null_handle_paths(native):
     assert lib.bsi_ess(None, 1, 1, 10, 1, None, None, None, None) == -1
     assert lib.bsi_shear_hmc(None, 1, 1, None, None, None, None, None, None, None, None, None,
                              None, None) == -1
+    assert lib.bsi_slots_create(None, None, None, None) == -1
+    assert lib.bsi_slots_advance(None, 1) == -1
+    assert lib.bsi_slots_get_info(None, None) == -1
+    lib.bsi_slots_destroy(None)
     lib.bsi_destroy(None)
     assert lib.bsi_device_count(None) == -1
 

@@ -1,0 +1,131 @@
+"""The request server (bsi_slots_*): each request's samples are identical
+whether it runs alone or in a changing mix of other requests of other stamp
+sizes (bitwise: a chain's arithmetic and random numbers depend only on its
+own data and uid), admission follows the device footprint, and every
+admitted request is handed back exactly once."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from tests import synth                                      # noqa: E402
+from workloads import gen                                    # noqa: E402
+
+PS = gen.PIXEL_SCALE
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsi(device):
+    from paper_2604_22048_amd import api
+    return api
+
+
+def _requests(n, sizes, seed):
+    t, params, data, off = synth.make_population("uneven", n_gal=n, seed=seed, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, 1, seed)[:, 0]
+    return t, params, data, off, init
+
+
+CFG = dict(n_chains=1, n_leapfrog=6, n_warmup=12, n_samples=15, adapt=True, metric=1,
+           step_size=0.05, jitter=0.2, seed=9)
+
+
+def test_slots_alone_equals_mix_bitwise(bsi):
+    import torch
+    _log("slots alone vs mix")
+    rng = np.random.default_rng(70)
+    n = 20
+    sizes = rng.choice([25, 41, 53], n)
+    t, params, data, off, init = _requests(n, sizes, 71)
+    dev = torch.tensor(data).cuda()
+    cfg = bsi.HmcConfig(**CFG)
+    srv = bsi.Slots([25, 41, 53], cfg, hbm_budget=64 << 20, max_slots=6)
+    ids = 1000 + np.arange(n)
+    queue = list(range(n))
+    got = {}
+    ticks = 0
+    while len(got) < n:
+        while queue:
+            i = queue[0]
+            N = int(t.n_pix[i])
+            ok = srv.admit(int(ids[i]), dev[off[i]:off[i] + N * N], float(t.psf_fwhm[i]),
+                           float(t.sigma[i]), (params[i, 4], params[i, 5]), init[i])
+            if not ok:
+                break
+            queue.pop(0)
+        inf = srv.info()
+        assert inf["resident"] <= 6
+        srv.advance(int(rng.integers(2, 9)))
+        ticks += 1
+        hid, smp, st, status = srv.harvest(n)
+        for k, rid in enumerate(hid):
+            assert int(rid) not in got
+            got[int(rid)] = (smp[k].cpu().numpy(), st[k].cpu().numpy())
+        assert ticks < 200
+    inf = srv.info()
+    assert inf["resident"] == 0 and inf["arena_free"] == inf["arena_bytes"]
+    assert ticks > 4          # requests overlapped and queued
+    # alone: a one-galaxy bsi_hmc_sample with the request's chain uid
+    for i in [0, 3, 7, 12, 19]:
+        N = int(t.n_pix[i])
+        b = bsi.Batch(n=np.array([N]), psf_fwhm=torch.tensor([t.psf_fwhm[i]], dtype=torch.float32).cuda(),
+                      sigma=torch.tensor([t.sigma[i]], dtype=torch.float32).cuda(), pixel_scale=PS)
+        ref = torch.tensor([[params[i, 4], params[i, 5]]], dtype=torch.float32).cuda()
+        ini = torch.tensor(init[i][None, None, :], dtype=torch.float32).cuda()
+        c1 = bsi.HmcConfig(uid_base=int(ids[i]), **CFG)
+        smp, st, _ = bsi.hmc_sample(b, dev[off[i]:off[i] + N * N].contiguous(), ref, ini, c1)
+        assert np.array_equal(smp[0].cpu().numpy(), got[int(ids[i])][0]), i
+        assert np.array_equal(st[0].cpu().numpy(), got[int(ids[i])][1]), i
+    # alone in the server too
+    srv1 = bsi.Slots([53, 25, 41], cfg, hbm_budget=16 << 20)
+    i = 5
+    N = int(t.n_pix[i])
+    assert srv1.admit(int(ids[i]), dev[off[i]:off[i] + N * N], float(t.psf_fwhm[i]), float(t.sigma[i]),
+                      (params[i, 4], params[i, 5]), init[i])
+    srv1.advance(CFG["n_warmup"] + CFG["n_samples"])
+    hid, smp, st, _ = srv1.harvest(4)
+    assert list(hid) == [ids[i]]
+    assert np.array_equal(smp[0].cpu().numpy(), got[int(ids[i])][0])
+    srv.close()
+    srv1.close()
+
+
+def test_slots_admission_by_footprint(bsi):
+    import torch
+    _log("slots admission")
+    cfg = bsi.HmcConfig(**CFG)
+    n = 8
+    t, params, data, off, init = _requests(n, [53] * n, 72)
+    dev = torch.tensor(data).cuda()
+    probe = bsi.Slots([53], cfg, hbm_budget=16 << 20)
+    fp = probe.footprint(53)
+    probe.close()
+    # room for exactly three 53-pixel requests
+    srv = bsi.Slots([53], cfg, hbm_budget=4 * fp, max_slots=3)
+    assert srv.footprint(53) == fp
+    adm = []
+    for i in range(n):
+        N = 53
+        adm.append(srv.admit(i, dev[off[i]:off[i] + N * N], float(t.psf_fwhm[i]), float(t.sigma[i]),
+                             (params[i, 4], params[i, 5]), init[i]))
+    assert adm == [True] * 3 + [False] * (n - 3)
+    inf = srv.info()
+    assert inf["resident"] == 3 and inf["pending"] == 3
+    srv.advance(CFG["n_warmup"] + CFG["n_samples"])
+    hid, smp, st, status = srv.harvest(2)
+    assert list(hid) == [0, 1]
+    assert np.all(np.isfinite(smp.cpu().numpy()))
+    assert srv.info()["resident"] == 1
+    assert srv.admit(3, dev[off[3]:off[3] + 2809], float(t.psf_fwhm[3]), float(t.sigma[3]),
+                     (params[3, 4], params[3, 5]), init[3])
+    with pytest.raises(Exception):
+        srv.admit(4, dev[:25 * 25], 0.7, 1.0, (0, 0), init[4])     # size not served
+    srv.close()
