@@ -115,9 +115,12 @@ def lens(e1, e2, g):
     return ep.real, ep.imag
 
 
-def make_inputs(api, torch, n_gal, cfg, seed_offset=0):
+def make_inputs(api, torch, n_gal, cfg, seed_offset=0, sizes=None, chains=None):
+    """Seeded synthetic galaxies of workload cfg rendered on the device, with
+    pixel noise, reference centroids and chain starts (eq. initialize)."""
     dev = torch.device("cuda:0")
-    t = gen.draw_truth(cfg, n_gal=n_gal, seed=gen.data_seed(cfg.index) + seed_offset)
+    t = gen.draw_truth(cfg, n_gal=n_gal, seed=gen.data_seed(cfg.index) + seed_offset,
+                       size_override=sizes)
     e1p, e2p = lens(t.e1, t.e2, cfg.g_true)
     params = np.stack([t.flux, t.hlr, e1p, e2p, t.dx, t.dy], axis=1).astype(np.float32)
     b = api.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32, device=dev),
@@ -128,11 +131,15 @@ def make_inputs(api, torch, n_gal, cfg, seed_offset=0):
     # chain starts (eq. initialize): flux from the stamp sum, size and shape
     # jittered around the truth, centroid offsets zero
     rng = np.random.default_rng(gen.chain_seed(cfg.index) + seed_offset)
-    N = int(t.n_pix[0])
-    sums = data.view(n_gal, N * N).double().sum(dim=1).cpu().numpy()
-    C = cfg.chains
+    npix = t.n_pix.astype(np.int64)
+    cs = torch.cumsum(data.double(), 0)
+    end = torch.tensor(off + npix * npix - 1, device=dev)
+    start = torch.tensor(off - 1, device=dev)
+    sums = (cs[end] - torch.where(start >= 0, cs[start.clamp(min=0)], torch.zeros_like(cs[end])))
+    sums = sums.cpu().numpy()
+    C = cfg.chains if chains is None else chains
     init = np.zeros((n_gal, C, 6), np.float32)
-    init[:, :, 0] = np.log10(np.maximum(sums, t.sigma * N))[:, None]
+    init[:, :, 0] = np.log10(np.maximum(sums, t.sigma * npix))[:, None]
     init[:, :, 1] = np.log10(t.hlr)[:, None] + rng.uniform(-0.015, 0.015, (n_gal, C))
     for c in range(C):
         e1 = e1p + rng.uniform(-0.1, 0.1, n_gal)
@@ -154,6 +161,157 @@ def timed(torch, fn, stream):
     return out, s.elapsed_time(e) * 1e-3
 
 
+def shear_leg(api, torch, stream, smp, G, K, seed):
+    """Shear-level HMC over (g1, g2, mu_ln_s, sigma_ln_s, sigma_e) on the
+    interim samples of the uniform step (every 4th draw of the 4 chains: K =
+    1000 per galaxy, 10^7 in all): 4 chains, 10 leapfrog steps, 500 warmup +
+    3000 draws, and the HBM roofline of one evaluation pass."""
+    dev = torch.device("cuda:0")
+    th = smp[:, :, 3::4, :].reshape(G, K, 6)
+    e1p, e2p, l10s = th[..., 2].contiguous(), th[..., 3].contiguous(), th[..., 1].contiguous()
+    tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True)
+    dcfg = gen.CONFIGS["diff"].extra
+    Cs = 4
+    rng = np.random.default_rng(seed)
+    x0 = np.array([0.0, 0.0, math.log(0.6), 0.3, 0.2]) + rng.normal(0, 0.003, (Cs, 5))
+    cfg = api.ShearHmcConfig(n_chains=Cs, n_leapfrog=dcfg["shear_leapfrog"],
+                             n_warmup=dcfg["shear_warmup"], n_samples=dcfg["shear_samples"],
+                             adapt=True, step_size=1e-3, jitter=0.1, seed=seed)
+    (ss, sst), t_tot = timed(torch, lambda: api.shear_hmc(e1p, e2p, l10s, None, tp, cfg, x0), stream)
+    n_eval = 1 + (cfg.n_warmup + cfg.n_samples) * cfg.n_leapfrog
+    e, rh = api.ess(ss.float()[None])
+    ssn = ss.cpu().numpy()
+    # one evaluation pass at the chains' final points, timed alone
+    pts = torch.tensor(ssn[:, -1, :], dtype=torch.float64, device=dev)
+    api.shear_posterior(e1p, e2p, l10s, None, pts, tp, want_grad=True)
+    reps = 20
+    _, t_pass = timed(torch, lambda: [api.shear_posterior(e1p, e2p, l10s, None, pts, tp, want_grad=True)
+                                      for _ in range(reps)], stream)
+    t_pass /= reps
+    bytes_pass = G * K * 12.0                  # e1', e2', log10 s as float32
+    gbs = bytes_pass / t_pass / 1e9
+    return {"n_gal": G, "K": K, "chains": Cs, "leapfrog": cfg.n_leapfrog, "warmup": cfg.n_warmup,
+            "samples": cfg.n_samples, "t_s": round(t_tot, 4), "n_eval": n_eval,
+            "us_per_eval": round(t_tot / n_eval * 1e6, 2),
+            "g_mean": [round(float(ssn[..., 0].mean()), 5), round(float(ssn[..., 1].mean()), 5)],
+            "g_sd": [round(float(ssn[..., 0].std()), 5), round(float(ssn[..., 1].std()), 5)],
+            "g_true": list(gen.CONFIGS["uniform"].g_true),
+            "ess_g": [round(float(e[0, 0]), 1), round(float(e[0, 1]), 1)],
+            "rhat_max": round(float(rh.max()), 4),
+            "accept_rate": round(float(sst[:, 0].mean()), 4),
+            "eval_pass_us": round(t_pass * 1e6, 2),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(gbs / 8000.0, 4), "traffic": None,
+                         "kernel": "shear_kernel + shear_reduce_kernel (4 points, with gradient)",
+                         "alg_bytes_per_pass": bytes_pass}}
+
+
+SERVING_SIZES = gen.SIZE_CLASSES
+
+
+def make_request_pool(api, torch, per_size, seed_offset=0):
+    """Device-resident request payloads per stamp size (serving workload)."""
+    from paper_2604_22048_amd import serve
+    cfg = gen.CONFIGS["serving"]
+    P = {k: {} for k in ("stamps", "psf", "sigma", "ref", "init")}
+    for N in SERVING_SIZES:
+        t, b, data, ref, init = make_inputs(api, torch, per_size, cfg, seed_offset=seed_offset + N,
+                                            sizes=np.full(per_size, N), chains=1)
+        P["stamps"][N] = data.view(per_size, N * N)
+        P["psf"][N] = t.psf_fwhm.astype(np.float32)
+        P["sigma"][N] = t.sigma.astype(np.float32)
+        P["ref"][N] = ref.cpu().numpy()
+        P["init"][N] = np.ascontiguousarray(init.cpu().numpy())
+    return serve.RequestPool(**P)
+
+
+def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, iters_per_tick=30,
+                budget=4 << 30, extra_rates=(), log=None):
+    """Poisson request stream at `rate` for `window_s` seconds of arrivals
+    (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
+    warmup + n_draws iterations of 20 leapfrog steps each), then the capacity:
+    cap_requests requests all present at the start."""
+    from paper_2604_22048_amd import serve
+    cfg = gen.CONFIGS["serving"]
+    hc = api.HmcConfig(n_chains=1, n_leapfrog=cfg.leapfrog, n_warmup=cfg.warmup, n_samples=n_draws,
+                       adapt=True, metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8,
+                       jitter=0.2, seed=gen.chain_seed(cfg.index))
+    pool = make_request_pool(api, torch, 512)
+    w = np.array(cfg.extra["size_weights"])
+    rng = np.random.default_rng(seed)
+
+    def run(arr, tag, ess):
+        sizes = rng.choice(np.array(SERVING_SIZES), size=arr.shape[0], p=w)
+        srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget)
+        r = serve.serve(srv, pool, arr, sizes, iters_per_tick, ess=ess, progress=log)
+        srv.close()
+        if log:
+            log(f"[serve] {tag}: {r.n_done} requests in {r.wall:.2f} s")
+        return r, sizes
+
+    def lat_stats(r):
+        lat = r.latency[np.isfinite(r.latency)]
+        return {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+                "mean_ms": round(float(lat.mean()) * 1e3, 2)}
+
+    # warm the kernels and the allocator
+    run(np.zeros(64), "warm", False)
+    n_req = int(rate * window_s)
+    arr = gen.draw_requests(n_req, rate, gen.data_seed(cfg.index))
+    r, sizes = run(arr, f"{rate:.0f}/s", True)
+    em = r.ess_mean[np.isfinite(r.ess_mean)]
+    out = {"rate_req_per_s": rate, "window_s": window_s, "n_requests": n_req, "completed": r.n_done,
+           "galaxies_per_s": round(r.n_done / r.wall, 1), **lat_stats(r),
+           "max_resident": r.max_resident, "ticks": r.ticks, "iters_per_tick": iters_per_tick,
+           "warmup": cfg.warmup, "draws": n_draws, "leapfrog": cfg.leapfrog,
+           "ess_mean_median": round(float(np.median(em)), 1),
+           "frac_ess_ge_300": round(float(np.mean(em >= 300.0)), 4),
+           "p50_ms_by_size": {int(N): round(float(np.nanpercentile(r.latency[sizes == N], 50)) * 1e3, 2)
+                              for N in SERVING_SIZES}}
+    rc, _ = run(np.zeros(cap_requests), "capacity", False)
+    cap = rc.n_done / rc.wall
+    out["capacity_req_per_s"] = round(cap, 1)
+    out["capacity_requests"] = cap_requests
+    for frac in extra_rates:
+        rr = frac * cap
+        n2 = int(rr * window_s)
+        r2, _ = run(gen.draw_requests(n2, rr, gen.data_seed(cfg.index) + 1), f"{frac:.1f}x capacity", False)
+        out[f"at_{frac:.1f}x_capacity"] = {"rate_req_per_s": round(rr, 1), "n_requests": n2,
+                                           "galaxies_per_s": round(r2.n_done / r2.wall, 1),
+                                           **lat_stats(r2)}
+    return out
+
+
+def uneven_leg(api, torch, stream, n_gal, log=None):
+    """Batched uneven workload: n_gal galaxies, stamp side from the size rule
+    (25-101), PSF FWHM ~ U(0.6, 0.9), SNR 10-200, 4 chains, 20 leapfrog
+    steps, 300 warmup + 1000 draws; the size classes launch concurrently."""
+    cfg = gen.CONFIGS["uneven"]
+    t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
+    C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
+    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
+                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
+                         use_graph=True, seed=gen.chain_seed(cfg.index))
+    wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
+    api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
+    (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
+    (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
+    _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
+    n_eff = float(e.mean(dim=1).mean())
+    t_s = t_hmc - t_w
+    tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
+    counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
+    flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
+    return {"n_gal": n_gal, "size_counts": counts, "t_hmc_s": round(t_hmc, 4),
+            "t_warmup_s": round(t_w, 4), "n_eff_mean": round(n_eff, 1),
+            "galaxies_per_s": round(1.0 / tpg, 1),
+            "achieved_tflops": round(flop / t_hmc / 1e12, 3),
+            "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4),
+            "accept_rate": round(float(st[..., 0].mean()), 4),
+            "status_nonzero": int((status != 0).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -164,6 +322,12 @@ def main():
     ap.add_argument("--plain-gal", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
+    ap.add_argument("--workload", choices=["uniform", "uneven", "serving"], default="uniform",
+                    help="uniform: the headline line (with shear-level HMC and serving legs); "
+                         "uneven / serving: the mixed-size batch or the extended serving study")
+    ap.add_argument("--no-legs", action="store_true", help="uniform workload without the shear and "
+                    "serving legs (profiling)")
+    ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -177,6 +341,32 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
               "part of this build", file=sys.stderr)
         sys.exit(2)
+    log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.workload != "uniform":
+        import torch
+        from paper_2604_22048_amd import api
+        torch.cuda.init()
+        stream = torch.cuda.current_stream(torch.device("cuda:0"))
+        if args.workload == "uneven":
+            G = args.n_gal or gen.CONFIGS["uneven"].n_gal
+            res = uneven_leg(api, torch, stream, G, log)
+            out = {"metric": "galaxies/sec at 300 ESS (uneven stamps 25-101 px)",
+                   "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "batched uneven: stamp side from the size rule, PSF FWHM "
+                                          "U(0.6, 0.9)in, SNR 10-200, 4 chains, 20 leapfrog steps, "
+                                          "300 warmup + 1000 draws"}, **res}
+        else:
+            res = serving_leg(api, torch, 2000.0, args.serve_window, 60000, 5, extra_rates=(0.5, 0.9),
+                              log=log)
+            out = {"metric": "p50/p99 fit latency and galaxies/s, Poisson requests",
+                   "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "serving: Poisson arrivals at 2000 req/s, stamp sizes "
+                                          "25/41/53/73/101 (weights .3/.3/.2/.15/.05), 1 chain, 20 "
+                                          "leapfrog steps, 300 warmup + 600 draws"}, **res}
+        print(json.dumps(out), flush=True)
+        return
     cfg = gen.CONFIGS["uniform"]
     G = args.n_gal or cfg.n_gal
 
@@ -260,8 +450,14 @@ def main():
     alg = flops_per_eval(N) * G * C * L
     achieved = alg / t_launch / 1e12
     peak = 78.6
+    legs = {}
+    if not args.no_legs:
+        legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
+        log(f"[bench] shear-level HMC: {legs['shear_hmc']['t_s']} s")
+        del results, r["smp"]
+        legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log)
     out = {
-        "metric": "galaxies/sec at 300 ESS (53x53 stamps), batched vs plain",
+        "metric": "galaxies/sec at 300 ESS (53x53 stamps), batched vs plain; p50/p99 fit latency",
         "value": round(value, 3),
         "unit": "galaxies/s",
         "n_gpus": 1,
@@ -295,6 +491,7 @@ def main():
                      "traffic": recorded_traffic(),
                      "kernel": "hmc_kernel (advance)", "launch_ms": round(t_launch * 1e3, 4),
                      "alg_flop_per_launch": alg},
+        **legs,
     }
     if cpu:
         evals_per_gal = C * L * (W + S * TARGET_ESS / n_eff_mean)

@@ -161,7 +161,9 @@ typedef struct {
   int32_t form;              /* BSI_FORM_BATCHED: all galaxies per launch;
                                 BSI_FORM_PLAIN: one galaxy and one leapfrog step per launch */
   int32_t iters_per_launch;  /* batched form: trajectories per kernel launch (>= 1)        */
-  int32_t use_graph;         /* batched form: replay launches from a captured HIP graph    */
+  int32_t use_graph;         /* batched form: replay launches from a captured HIP graph
+                                (batches of one stamp size; a batch of several sizes
+                                launches its per-size branches directly)                   */
   uint64_t seed;             /* Philox key                                                 */
   uint64_t uid_base;         /* chain uid = uid_base + galaxy * n_chains + chain           */
   float* trace;              /* [device] float[n_gal][n_chains][n_warmup + n_samples][4] or
@@ -339,6 +341,12 @@ int bsi_slots_footprint(bsi_slots s, int32_t n, int64_t* bytes);
  * so, 0 if the server is full (nothing changes then).  The request starts
  * running at the next bsi_slots_advance. */
 int bsi_slots_admit(bsi_slots s, const bsi_request* r, int32_t* admitted);
+
+/* Admit requests reqs[0..n-1] in order until one does not fit (first-come,
+ * first-served: a request is never passed by a later one); *n_admitted
+ * receives how many were admitted.  An invalid request fails the call with
+ * the requests before it admitted. */
+int bsi_slots_admit_many(bsi_slots s, int32_t n, const bsi_request* reqs, int32_t* n_admitted);
 
 /* Enqueue n_iter >= 1 HMC iterations for every resident, unfinished request
  * (admitted requests are first initialised: data spectrum, metric, start

@@ -102,6 +102,7 @@ SIGNATURES = {
     "bsi_slots_destroy": (None, [C.c_void_p]),
     "bsi_slots_footprint": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64)]),
     "bsi_slots_admit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int32)]),
+    "bsi_slots_admit_many": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "bsi_slots_advance": (C.c_int, [C.c_void_p, C.c_int32]),
     "bsi_slots_harvest": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64), C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),

@@ -334,6 +334,29 @@ class Slots:
             self._keep.append(stamp)
         return bool(ok.value)
 
+    # numpy view of bsi_request (same field offsets as the C struct)
+    REQUEST_DTYPE = np.dtype({"names": ["id", "n", "stamp", "psf_fwhm", "sigma", "ref_x", "ref_y", "init"],
+                              "formats": [np.uint64, np.int32, np.uint64, np.float32, np.float32,
+                                          np.float32, np.float32, np.uint64],
+                              "offsets": [N.Request.id.offset, N.Request.n.offset, N.Request.stamp.offset,
+                                          N.Request.psf_fwhm.offset, N.Request.sigma.offset,
+                                          N.Request.ref_x.offset, N.Request.ref_y.offset,
+                                          N.Request.init.offset],
+                              "itemsize": C.sizeof(N.Request)})
+
+    def admit_many(self, reqs: np.ndarray, keep=None) -> int:
+        """Admit requests (a REQUEST_DTYPE array) in order until one does not
+        fit; returns how many were admitted.  `keep` holds whatever owns the
+        stamps and start positions until the next advance has run."""
+        reqs = np.ascontiguousarray(reqs, dtype=self.REQUEST_DTYPE)
+        n = C.c_int32(0)
+        self.lib.check(self.lib.lib.bsi_slots_admit_many(self.h, int(reqs.shape[0]),
+                                                         C.c_void_p(reqs.ctypes.data), C.byref(n)),
+                       "bsi_slots_admit_many")
+        if n.value and keep is not None:
+            self._keep.append(keep)
+        return int(n.value)
+
     def advance(self, n_iter: int):
         self.lib.check(self.lib.lib.bsi_slots_advance(self.h, int(n_iter)), "bsi_slots_advance")
         self._keep_prev, self._keep = self._keep, []

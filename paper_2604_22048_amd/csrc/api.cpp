@@ -380,7 +380,10 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
         return launch_hmc_advance(ac, c.count, sc);
       });
     };
-    if (cfg->use_graph && n_launch > 1) {
+    // Batches of one stamp size replay a captured graph; batches of several
+    // sizes launch their forked per-size branches directly (no capture of
+    // the multi-stream fork).
+    if (cfg->use_graph && n_launch > 1 && p.classes.size() == 1) {
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);

@@ -132,8 +132,6 @@ struct bsi_slots_s {
 
 namespace {
 
-int slots_fail(bsi_slots sv, int code, const char* msg) { return fail(sv->h, code, "%s", msg); }
-
 int class_of(const bsi_slots_s* sv, int N) {
   for (size_t i = 0; i < sv->cls.size(); ++i)
     if (sv->cls[i].N == N) return (int)i;
@@ -363,6 +361,20 @@ int bsi_slots_admit(bsi_slots sv, const bsi_request* r, int32_t* admitted) {
   sv->rec_init.insert(sv->rec_init.end(), r->init, r->init + sv->C * 6);
   sv->cls[c].fresh.push_back(slot);
   *admitted = 1;
+  return BSI_OK;
+}
+
+int bsi_slots_admit_many(bsi_slots sv, int32_t n, const bsi_request* reqs, int32_t* n_admitted) {
+  if (!sv) return BSI_EINVAL;
+  if (!n_admitted || n < 0 || (n > 0 && !reqs)) return fail(sv->h, BSI_EINVAL, "bad admit_many arguments");
+  *n_admitted = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int32_t ok = 0;
+    const int rc = bsi_slots_admit(sv, reqs + i, &ok);
+    if (rc) return rc;
+    if (!ok) break;
+    *n_admitted = i + 1;
+  }
   return BSI_OK;
 }
 

@@ -189,6 +189,37 @@ def test_hmc_fixed_step_parity(bsi, cfg_name, C, jitter):
     assert agree >= G * C * 6 - 2
 
 
+def test_hmc_mixed_sizes_parity_and_invariance(bsi):
+    """One batch of five stamp sizes (per-size launches on forked streams):
+    each chain follows the oracle under the same Philox momenta, and each
+    galaxy's chains are bitwise those of the galaxy run alone."""
+    import torch
+    _log("hmc mixed sizes 25/41/53/73/101")
+    sizes = [25, 41, 53, 73, 101]
+    G, C, S = len(sizes), 2, 3
+    t, params, data, off = synth.make_population("uneven", n_gal=G, seed=17, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, C, seed=18)
+    b = _batch(bsi, torch, t.n_pix, t.psf_fwhm, t.sigma)
+    ref = np.stack([t.dx, t.dy], axis=1)
+    seed = 77
+    base = dict(n_chains=C, n_leapfrog=8, n_warmup=0, n_samples=S, adapt=False, step_size=0.003,
+                jitter=0.1, seed=seed)
+    s, stats, st = _run_gpu(bsi, torch, b, data, ref, init, bsi.HmcConfig(**base))
+    agree = 0
+    for i in range(G):
+        gal = synth.oracle_galaxy(t, data, off, i)
+        for c in range(C):
+            r = hmc.run_chain(hmc.galaxy_potential(gal), init[i, c].astype(np.float32), seed, i * C + c,
+                              8, 0, S, 0.003, adapt=False, jitter=0.1)
+            agree += _compare_chain(s[i, c], r["samples"])
+        N = int(t.n_pix[i])
+        b1 = _batch(bsi, torch, [N], t.psf_fwhm[i:i + 1], t.sigma[i:i + 1])
+        alone = _run_gpu(bsi, torch, b1, data[off[i]:off[i] + N * N], ref[i:i + 1], init[i:i + 1],
+                         bsi.HmcConfig(uid_base=i * C, **base))[0]
+        assert np.array_equal(alone[0], s[i]), N
+    assert agree >= G * C * S - 1
+
+
 def test_hmc_dual_averaging_parity(bsi):
     """Trajectories agree until the first accept/reject decision that float32
     and float64 potentials take differently; the step-size recursion is then
