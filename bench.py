@@ -225,8 +225,8 @@ def make_request_pool(api, torch, per_size, seed_offset=0):
     return serve.RequestPool(**P)
 
 
-def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, iters_per_tick=30,
-                budget=4 << 30, extra_rates=(), log=None):
+def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, iters_per_tick=15,
+                budget=4 << 30, extra_rates=(), pace=True, log=None):
     """Poisson request stream at `rate` for `window_s` seconds of arrivals
     (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
     warmup + n_draws iterations of 20 leapfrog steps each), then the capacity:
@@ -238,11 +238,11 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
                        jitter=0.2, seed=gen.chain_seed(cfg.index))
     pool = make_request_pool(api, torch, 512)
     w = np.array(cfg.extra["size_weights"])
-    rng = np.random.default_rng(seed)
 
-    def run(arr, tag, ess):
-        sizes = rng.choice(np.array(SERVING_SIZES), size=arr.shape[0], p=w)
-        srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget)
+    def run(arr, tag, ess, paced):
+        sizes = np.random.default_rng(seed + arr.shape[0]).choice(np.array(SERVING_SIZES),
+                                                                  size=arr.shape[0], p=w)
+        srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget, pace=paced)
         r = serve.serve(srv, pool, arr, sizes, iters_per_tick, ess=ess, progress=log)
         srv.close()
         if log:
@@ -256,27 +256,33 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
                 "mean_ms": round(float(lat.mean()) * 1e3, 2)}
 
     # warm the kernels and the allocator
-    run(np.zeros(64), "warm", False)
+    run(np.zeros(64), "warm", False, False)
     n_req = int(rate * window_s)
     arr = gen.draw_requests(n_req, rate, gen.data_seed(cfg.index))
-    r, sizes = run(arr, f"{rate:.0f}/s", True)
+    r, sizes = run(arr, f"{rate:.0f}/s", True, False)
     em = r.ess_mean[np.isfinite(r.ess_mean)]
+    by_size = lambda rr, sz: {int(N): round(float(np.nanpercentile(rr.latency[sz == N], 50)) * 1e3, 2)
+                              for N in SERVING_SIZES}
     out = {"rate_req_per_s": rate, "window_s": window_s, "n_requests": n_req, "completed": r.n_done,
            "galaxies_per_s": round(r.n_done / r.wall, 1), **lat_stats(r),
            "max_resident": r.max_resident, "ticks": r.ticks, "iters_per_tick": iters_per_tick,
            "warmup": cfg.warmup, "draws": n_draws, "leapfrog": cfg.leapfrog,
            "ess_mean_median": round(float(np.median(em)), 1),
            "frac_ess_ge_300": round(float(np.mean(em >= 300.0)), 4),
-           "p50_ms_by_size": {int(N): round(float(np.nanpercentile(r.latency[sizes == N], 50)) * 1e3, 2)
-                              for N in SERVING_SIZES}}
-    rc, _ = run(np.zeros(cap_requests), "capacity", False)
+           "p50_ms_by_size": by_size(r, sizes)}
+    if pace:
+        rp, sp = run(arr, f"{rate:.0f}/s paced", False, True)
+        out["paced_by_size"] = {"galaxies_per_s": round(rp.n_done / rp.wall, 1), **lat_stats(rp),
+                                "ticks": rp.ticks, "p50_ms_by_size": by_size(rp, sp)}
+    rc, _ = run(np.zeros(cap_requests), "capacity", False, False)
     cap = rc.n_done / rc.wall
     out["capacity_req_per_s"] = round(cap, 1)
     out["capacity_requests"] = cap_requests
     for frac in extra_rates:
         rr = frac * cap
         n2 = int(rr * window_s)
-        r2, _ = run(gen.draw_requests(n2, rr, gen.data_seed(cfg.index) + 1), f"{frac:.1f}x capacity", False)
+        r2, _ = run(gen.draw_requests(n2, rr, gen.data_seed(cfg.index) + 1), f"{frac:.1f}x capacity",
+                    False, False)
         out[f"at_{frac:.1f}x_capacity"] = {"rate_req_per_s": round(rr, 1), "n_requests": n2,
                                            "galaxies_per_s": round(r2.n_done / r2.wall, 1),
                                            **lat_stats(r2)}
@@ -295,6 +301,10 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
                          use_graph=True, seed=gen.chain_seed(cfg.index))
     wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
     api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
+    # the other launch form (direct, sizes concurrent on forked streams), warmup iterations only
+    dcfg = api.HmcConfig(**{**wcfg.__dict__, "use_graph": False})
+    _, t_w_direct = timed(torch, lambda: api.hmc_sample(b, data, ref, init, dcfg, want_samples=False),
+                          stream)
     (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
@@ -304,7 +314,8 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
     counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
     return {"n_gal": n_gal, "size_counts": counts, "t_hmc_s": round(t_hmc, 4),
-            "t_warmup_s": round(t_w, 4), "n_eff_mean": round(n_eff, 1),
+            "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
+            "n_eff_mean": round(n_eff, 1),
             "galaxies_per_s": round(1.0 / tpg, 1),
             "achieved_tflops": round(flop / t_hmc / 1e12, 3),
             "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4),
@@ -486,6 +497,7 @@ def main():
         "accept_rate": round(float(stats[..., 0].mean()), 4),
         "rhat_max": round(float(np.nanmax(rhat)), 4),
         "frac_rhat_lt_1.01": round(float(np.mean(rhat.max(axis=1) < 1.01)), 4),
+        "frac_status_nonzero": round(float((r["status"] != 0).float().mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": recorded_traffic(),

@@ -57,7 +57,10 @@ enum {
   BSI_ENODEV = -5         /* no usable device                                */
 };
 
-/* Per-galaxy status bits (OR-ed over all of a galaxy's chains). */
+/* Per-galaxy status bits (OR-ed over all of a galaxy's chains).  For
+ * bsi_hmc_sample they cover the start positions and the stored iterations;
+ * warmup trajectories (whose step-size probes routinely leave the support)
+ * are not reported. */
 enum {
   BSI_STATUS_OUT_OF_SUPPORT = 1,  /* a parameter set or trajectory left the prior support */
   BSI_STATUS_NONFINITE = 2,       /* a non-finite log-likelihood or energy was met        */
@@ -161,9 +164,10 @@ typedef struct {
   int32_t form;              /* BSI_FORM_BATCHED: all galaxies per launch;
                                 BSI_FORM_PLAIN: one galaxy and one leapfrog step per launch */
   int32_t iters_per_launch;  /* batched form: trajectories per kernel launch (>= 1)        */
-  int32_t use_graph;         /* batched form: replay launches from a captured HIP graph
-                                (batches of one stamp size; a batch of several sizes
-                                launches its per-size branches directly)                   */
+  int32_t use_graph;         /* batched form: 1 = replay each launch round from a captured
+                                HIP graph (the stamp sizes' launches in sequence on one
+                                stream); 0 = direct launches, the sizes concurrently on
+                                forked streams                                             */
   uint64_t seed;             /* Philox key                                                 */
   uint64_t uid_base;         /* chain uid = uid_base + galaxy * n_chains + chain           */
   float* trace;              /* [device] float[n_gal][n_chains][n_warmup + n_samples][4] or
@@ -182,7 +186,7 @@ typedef struct {
  *   init       [device] float[n_gal][n_chains][6] start positions (theta).
  *   samples    [device] float[n_gal][n_chains][n_samples][6] (theta) or NULL.
  *   chain_stats[device] float[n_gal][n_chains][4] = {accept rate over the
- *              stored iterations, final step size, divergent trajectories,
+ *              stored iterations, final step size, divergent stored trajectories,
  *              final potential energy} or NULL.
  *   status     [device] uint32[n_gal] or NULL.
  * Random numbers: Philox4x32-10 keyed by seed, counter (uid, t, tag, block)
@@ -303,6 +307,11 @@ typedef struct {
   bsi_interim interim;
   float pixel_scale;
   int32_t profile;             /* BSI_PROFILE_*                                             */
+  int32_t pace;                /* 0: every size advances n_iter iterations per call;
+                                  1: the slowest size advances n_iter and every other size
+                                  about n_iter * tau_slowest / tau_N, tau the per-iteration
+                                  time of a size's launch measured with events on earlier
+                                  calls, so that the sizes' launches take about equally long */
 } bsi_slots_cfg;
 
 typedef struct {
@@ -348,7 +357,8 @@ int bsi_slots_admit(bsi_slots s, const bsi_request* r, int32_t* admitted);
  * the requests before it admitted. */
 int bsi_slots_admit_many(bsi_slots s, int32_t n, const bsi_request* reqs, int32_t* n_admitted);
 
-/* Enqueue n_iter >= 1 HMC iterations for every resident, unfinished request
+/* Enqueue n_iter >= 1 HMC iterations (scaled per size when cfg.pace is set)
+ * for every resident, unfinished request
  * (admitted requests are first initialised: data spectrum, metric, start
  * potential).  Returns without waiting for the device. */
 int bsi_slots_advance(bsi_slots s, int32_t n_iter);

@@ -61,7 +61,7 @@ class ShearHmcCfg(C.Structure):
 class SlotsCfg(C.Structure):
     _fields_ = [("n_sizes", C.c_int32), ("sizes", C.POINTER(C.c_int32)), ("hbm_budget", C.c_int64),
                 ("max_slots", C.c_int32), ("hmc", HmcCfg), ("interim", Interim),
-                ("pixel_scale", C.c_float), ("profile", C.c_int32)]
+                ("pixel_scale", C.c_float), ("profile", C.c_int32), ("pace", C.c_int32)]
 
 
 class Request(C.Structure):

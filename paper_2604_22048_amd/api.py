@@ -302,13 +302,14 @@ class Slots:
 
     def __init__(self, sizes, cfg: HmcConfig, hbm_budget: int, max_slots: int = 0, interim=None,
                  pixel_scale: float = 0.2, profile: int = N.PROFILE_EXPONENTIAL,
-                 device: int = 0, lib: Library | None = None):
+                 pace: bool = False, device: int = 0, lib: Library | None = None):
         self.lib = lib or get(device)
         self.device = torch.device("cuda", device)
         self.cfg = cfg
         self._sizes = (C.c_int32 * len(sizes))(*[int(x) for x in sizes])
         c = N.SlotsCfg(len(sizes), C.cast(self._sizes, C.POINTER(C.c_int32)), int(hbm_budget),
-                       int(max_slots), cfg.c(), _interim(interim), float(pixel_scale), int(profile))
+                       int(max_slots), cfg.c(), _interim(interim), float(pixel_scale), int(profile),
+                       int(bool(pace)))
         self._stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         self.lib.check(self.lib.lib.bsi_slots_create(self.lib.h, C.byref(c),

@@ -369,25 +369,32 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   } else {
     const int ipl = std::min(cfg->iters_per_launch, std::max(T, 1));
     const int n_launch = (T + ipl - 1) / ipl;
-    auto enqueue = [&](hipStream_t st) -> hipError_t {
-      return fork_join(h, st, (int)p.classes.size(), [&](int i, hipStream_t sc) {
-        const ClassRange& c = p.classes[i];
-        HmcArgs ac = a;
-        ac.N = c.N;
-        ac.gidx = gidx_ptr(h, c);
-        ac.n_gal = c.count;
-        ac.n_steps = ipl * a.L;
-        return launch_hmc_advance(ac, c.count, sc);
-      });
+    auto advance_class = [&](int i, hipStream_t sc) -> hipError_t {
+      const ClassRange& c = p.classes[i];
+      HmcArgs ac = a;
+      ac.N = c.N;
+      ac.gidx = gidx_ptr(h, c);
+      ac.n_gal = c.count;
+      ac.n_steps = ipl * a.L;
+      return launch_hmc_advance(ac, c.count, sc);
     };
-    // Batches of one stamp size replay a captured graph; batches of several
-    // sizes launch their forked per-size branches directly (no capture of
-    // the multi-stream fork).
-    if (cfg->use_graph && n_launch > 1 && p.classes.size() == 1) {
+    // direct launches: the sizes run concurrently on forked streams
+    auto enqueue = [&](hipStream_t st) -> hipError_t {
+      return fork_join(h, st, (int)p.classes.size(), advance_class);
+    };
+    // graph replay: one stream, the sizes' launches in sequence
+    auto enqueue_serial = [&](hipStream_t st) -> hipError_t {
+      for (int i = 0; i < (int)p.classes.size(); ++i) {
+        hipError_t e = advance_class(i, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    if (cfg->use_graph && n_launch > 1) {
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
-      if (e == hipSuccess) e = enqueue(s);
+      if (e == hipSuccess) e = enqueue_serial(s);
       hipError_t e2 = hipStreamEndCapture(s, &graph);
       if (e == hipSuccess) e = e2;
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);

@@ -418,7 +418,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     for (int j = 0; j < 6; ++j) h.th[j] += h.eps_t * h.im[j] * h.p[j];
     uint32_t st = 0;
     h.Uth = potential<PROF, P>(c, lc, pr, h.th, h.g, st);
-    h.status |= st;
+    if (h.t >= a.W) h.status |= st;     // warmup probes are not reported
     if (!in_support(h.th, pr)) h.ok = 0;
     h.l += 1;
     if (h.l < a.L) {
@@ -436,7 +436,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     const bool finite = isfinite(dH);
     const bool accept = h.ok && finite && log((double)cs->u_acc) < -dH;
     const double alpha = (h.ok && finite) ? fmin(1.0, exp(-dH)) : 0.0;
-    if (!finite || fabs(dH) > kDivergence) h.status |= finite ? 4u : 2u;
+    if ((!finite || fabs(dH) > kDivergence) && h.t >= a.W) h.status |= finite ? 4u : 2u;
     const float eps_used = cs->eps;
     if (trace_chain && lane < 4) {
       const float v = lane == 0 ? eps_used : lane == 1 ? (float)dH : lane == 2 ? (float)alpha
@@ -445,7 +445,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     }
     lane0_sync();
     if (lane == 0) {
-      if (!finite || fabs(dH) > kDivergence) cs->n_div += 1;
+      if ((!finite || fabs(dH) > kDivergence) && h.t >= a.W) cs->n_div += 1;
       if (accept) {
 #pragma unroll
         for (int j = 0; j < 6; ++j) {

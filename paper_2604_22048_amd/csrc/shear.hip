@@ -6,9 +6,11 @@
 // Layout: structure of arrays, float[n_gal][K] per field.  Grid: y = chunk of
 // up to 64 points, x = block of galaxies.  A wave keeps one galaxy's samples
 // in registers (K <= 64 * kMaxPerLane) and loops over the chunk's points; lane
-// j accumulates point j of the chunk.  Log-weights are float; max, exp and the
-// sums over samples and galaxies are float64.  Per-block partials are reduced
-// in a fixed order by shear_reduce_kernel (bitwise reproducible).
+// j accumulates point j of the chunk.  Log-weights and the per-lane sums of
+// their exponentials (at most 16 terms in (0, 1]) are float; the wave maximum,
+// the sums across lanes and galaxies, the logarithm and the gradient assembly
+// are float64.  Per-block partials are reduced in a fixed order (bitwise
+// reproducible).
 #include "bsi_kernels.h"
 
 namespace bsi {
@@ -38,68 +40,93 @@ __device__ __forceinline__ double dlog_z_e(int kind, double sig, double emax) {
   return 2.0 / sig - 2.0 * c * ex / (sig * (1.0 - ex));
 }
 
+// Per-point constants, computed once per block (float64, rounded to float).
 struct Point {
-  float g1, g2, mu, sig_s, inv2se2, inv_sig_s;
-  float lnZ, dlnZ, sig_e, ln1mgg, gg;
-  float size_c;    // ln(ln 10) - ln sig_s - ln(2 pi)/2 + ln(span_s)
+  float g1, g2, mu, inv2se2, inv_sig_s;
+  float lnZ, dlnZ, inv_se3;
+  float lw0;       // 2 ln(1 - |g|^2) (+ size normaliser ln(ln 10) - ln sig_s - ln(2 pi)/2 + ln span_s)
+  float c1, c2;    // 4 g / (1 - |g|^2): the Jacobian's |g| derivative
+  float pad;
 };
 
-__device__ __forceinline__ Point make_point(const double* p, const ShearArgs& a) {
+__device__ Point make_point(const double* p, const ShearArgs& a) {
   Point q;
   q.g1 = (float)p[0];
   q.g2 = (float)p[1];
   q.mu = (float)p[2];
-  q.sig_s = (float)p[3];
-  q.sig_e = (float)p[4];
   q.inv2se2 = (float)(1.0 / (2.0 * p[4] * p[4]));
   q.inv_sig_s = (float)(1.0 / p[3]);
+  q.inv_se3 = (float)(1.0 / (p[4] * p[4] * p[4]));
   q.lnZ = (float)log_z_e(a.e_kind, p[4], a.e_max);
   q.dlnZ = (float)dlog_z_e(a.e_kind, p[4], a.e_max);
   const double gg = p[0] * p[0] + p[1] * p[1];
-  q.gg = (float)gg;
-  q.ln1mgg = (float)log(1.0 - gg);
-  q.size_c = (float)(log(kLn10) - log(p[3]) - 0.5 * log(2.0 * kPi) + a.log_span_s);
+  double lw0 = 2.0 * log(1.0 - gg);
+  if (a.size_term) lw0 += log(kLn10) - log(p[3]) - 0.5 * log(2.0 * kPi) + a.log_span_s;
+  q.lw0 = (float)lw0;
+  q.c1 = (float)(4.0 * p[0] / (1.0 - gg));
+  q.c2 = (float)(4.0 * p[1] / (1.0 - gg));
+  q.pad = 0.f;
   return q;
 }
 
-// ln w of one sample at one point, excluding the point-independent part c0
-// (the interim ellipticity and flux terms, added by the caller).
-__device__ __forceinline__ float logw_point(const Point& P, const ShearArgs& a, float e1, float e2,
-                                           float ls, float& E_out, float& B_out, float& br_out,
-                                           float& bi_out) {
-  const float ar = e1 - P.g1, ai = e2 - P.g2;
-  const float br = 1.0f - (P.g1 * e1 + P.g2 * e2);
-  const float bi = P.g2 * e1 - P.g1 * e2;
-  const float B = br * br + bi * bi;
-  const float E = (ar * ar + ai * ai) / B;
-  E_out = E;
-  B_out = B;
-  br_out = br;
-  bi_out = bi;
+// Inverse shear of one sample at one point: eps = (eps' - g) / (1 - conj(g) eps')
+// as numerator a = eps' - g, denominator b = 1 - conj(g) eps', B = |b|^2 and
+// E = |eps|^2 = |a|^2 / B.
+struct Geo {
+  float ar, ai, br, bi, iB, E;
+};
+
+__device__ __forceinline__ Geo geo(const Point& P, float e1, float e2) {
+  Geo q;
+  q.ar = e1 - P.g1;
+  q.ai = e2 - P.g2;
+  q.br = 1.0f - (P.g1 * e1 + P.g2 * e2);
+  q.bi = P.g2 * e1 - P.g1 * e2;
+  const float B = q.br * q.br + q.bi * q.bi;
+  q.iB = __builtin_amdgcn_rcpf(B);
+  q.E = (q.ar * q.ar + q.ai * q.ai) * q.iB;
+  return q;
+}
+
+// ln w of one sample at one point without the point-independent part c0
+// (interim ellipticity and flux terms): true ellipticity density, shear
+// Jacobian 2 ln(1 - |g|^2) - 2 ln B, and the size term.
+__device__ __forceinline__ float logw(const Point& P, const ShearArgs& a, const Geo& q, float ls) {
   float lp;
-  if (a.e_kind == 0) {
-    lp = (E < 1.0f) ? 2.0f * __logf(1.0f - E) - E * P.inv2se2 - P.lnZ : -INFINITY;
-  } else {
-    lp = (E < a.e_max * a.e_max) ? -E * P.inv2se2 - P.lnZ : -INFINITY;
-  }
-  float lw = lp + 2.0f * P.ln1mgg - 2.0f * __logf(B);
+  if (a.e_kind == 0)
+    lp = (q.E < 1.0f) ? 2.0f * __logf(1.0f - q.E) - q.E * P.inv2se2 - P.lnZ : -INFINITY;
+  else
+    lp = (q.E < a.e_max * a.e_max) ? -q.E * P.inv2se2 - P.lnZ : -INFINITY;
+  float lw = lp + P.lw0 + 2.0f * __logf(q.iB);
   if (a.size_term) {
     const float z = (ls * kLn10F - P.mu) * P.inv_sig_s;
-    lw += P.size_c - 0.5f * z * z;
+    lw -= 0.5f * z * z;
   }
   return lw;
 }
 
+// A wave holds one galaxy's K samples in registers (lane l: samples
+// l, l + 64, ...) and evaluates, for each point, the lane's log weights
+// (first pass, kept in registers with their lane maximum m_l), then the
+// lane's sums of e^(lw - m_l) times 1, the two g-derivative terms, z, z^2
+// and E (second pass, float: at most 16 terms, each in (0, 1]).  The lane
+// sums are combined across the wave in float64 after rescaling by
+// e^(m_l - M), M the wave maximum, and the log-sum-exp and the gradient are
+// assembled in float64.
 __global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
   __shared__ double red[4][kPtsPerChunk][6];
+  __shared__ Point pts_s[kPtsPerChunk];
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int chunk0 = blockIdx.y * kPtsPerChunk;
   const int npc = min(kPtsPerChunk, a.n_pts - chunk0);
+  if ((int)threadIdx.x < npc) pts_s[threadIdx.x] = make_point(a.pts + 5 * (int64_t)(chunk0 + threadIdx.x), a);
+  __syncthreads();
   double acc[6] = {0, 0, 0, 0, 0, 0};      // lane j: point chunk0 + j
   const int KL = (a.K + kWave - 1) / kWave;
   const int waves_total = gridDim.x * 4;
   const float lnZ0 = (float)log_z_e(0, a.sigma_e_interim, 1.0);
   const float inv2s0 = (float)(1.0 / (2.0 * a.sigma_e_interim * a.sigma_e_interim));
+  const double logK = log((double)a.K);
   for (int gal = blockIdx.x * 4 + wave; gal < a.n_gal; gal += waves_total) {
     float e1[kMaxPerLane], e2[kMaxPerLane], ls[kMaxPerLane], c0[kMaxPerLane];
     const int64_t base = (int64_t)gal * a.K;
@@ -113,7 +140,7 @@ __global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
         e2[i] = a.e2p[base + k];
         ls[i] = a.l10s[base + k];
         const float Ep = e1[i] * e1[i] + e2[i] * e2[i];
-        // minus the interim ellipticity density (eq. interim-prior, sigma_e = 0.3)
+        // minus the interim ellipticity density (eq. interim-prior)
         float c = -(2.0f * __logf(1.0f - Ep) - Ep * inv2s0 - lnZ0);
         if (a.flux_term) {
           const float lf = a.l10f[base + k];
@@ -125,64 +152,66 @@ __global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
       }
     }
     for (int pj = 0; pj < npc; ++pj) {
-      const Point P = make_point(a.pts + 5 * (int64_t)(chunk0 + pj), a);
+      const Point P = pts_s[pj];
       float lw[kMaxPerLane];
       float m = -INFINITY;
 #pragma unroll
       for (int i = 0; i < kMaxPerLane; ++i) {
         lw[i] = -INFINITY;
         if (i < KL && c0[i] > -INFINITY) {
-          float E, B, br, bi;
-          lw[i] = logw_point(P, a, e1[i], e2[i], ls[i], E, B, br, bi) + c0[i];
+          lw[i] = logw(P, a, geo(P, e1[i], e2[i]), ls[i]) + c0[i];
           m = fmaxf(m, lw[i]);
         }
       }
-      m = wave_max(m);
-      double S = 0.0, Sd[5] = {0, 0, 0, 0, 0};
+      float s0 = 0.f, u0 = 0.f, u1 = 0.f, t1 = 0.f, t2 = 0.f, tE = 0.f;
       if (m > -INFINITY) {
 #pragma unroll
         for (int i = 0; i < kMaxPerLane; ++i) {
           if (i < KL && lw[i] > -INFINITY) {
-            const double ex = exp((double)lw[i] - (double)m);
-            S += ex;
+            const float ex = __expf(lw[i] - m);
+            s0 += ex;
             if (a.want_grad) {
-              float E, B, br, bi;
-              (void)logw_point(P, a, e1[i], e2[i], ls[i], E, B, br, bi);
-              const float ar = e1[i] - P.g1, ai = e2[i] - P.g2;
-              const float dB1 = 2.0f * (-br * e1[i] - bi * e2[i]);
-              const float dB2 = 2.0f * (-br * e2[i] + bi * e1[i]);
-              const float iB = 1.0f / B;
-              const float dE1 = (-2.0f * ar - E * dB1) * iB;
-              const float dE2 = (-2.0f * ai - E * dB2) * iB;
-              const float dlp = (a.e_kind == 0) ? -2.0f / (1.0f - E) - P.inv2se2 : -P.inv2se2;
-              const float omg = 1.0f - P.gg;
-              const float d0 = dlp * dE1 - 4.0f * P.g1 / omg - 2.0f * dB1 * iB;
-              const float d1 = dlp * dE2 - 4.0f * P.g2 / omg - 2.0f * dB2 * iB;
-              float d2 = 0.f, d3 = 0.f;
+              const Geo q = geo(P, e1[i], e2[i]);
+              const float dB1 = 2.0f * (-q.br * e1[i] - q.bi * e2[i]);
+              const float dB2 = 2.0f * (-q.br * e2[i] + q.bi * e1[i]);
+              const float dE1 = (-2.0f * q.ar - q.E * dB1) * q.iB;
+              const float dE2 = (-2.0f * q.ai - q.E * dB2) * q.iB;
+              const float dlp = (a.e_kind == 0) ? -2.0f * __builtin_amdgcn_rcpf(1.0f - q.E) - P.inv2se2
+                                                : -P.inv2se2;
+              u0 += ex * (dlp * dE1 - 2.0f * dB1 * q.iB);
+              u1 += ex * (dlp * dE2 - 2.0f * dB2 * q.iB);
               if (a.size_term) {
                 const float z = (ls[i] * kLn10F - P.mu) * P.inv_sig_s;
-                d2 = z * P.inv_sig_s;
-                d3 = (z * z - 1.0f) * P.inv_sig_s;
+                t1 += ex * z;
+                t2 += ex * z * z;
               }
-              const float d4 = E / (P.sig_e * P.sig_e * P.sig_e) - P.dlnZ;
-              Sd[0] += ex * d0;
-              Sd[1] += ex * d1;
-              Sd[2] += ex * d2;
-              Sd[3] += ex * d3;
-              Sd[4] += ex * d4;
+              tE += ex * q.E;
             }
           }
         }
       }
-      S = wave_sum(S);
-      double ell = (m > -INFINITY) ? (double)m + log(S) - log((double)a.K) : -INFINITY;
-      if (lane == pj) acc[0] += ell;
-      if (a.want_grad) {
-#pragma unroll
-        for (int j = 0; j < 5; ++j) {
-          const double v = wave_sum(Sd[j]) / S;
-          if (lane == pj) acc[1 + j] += v;
+      const float M = wave_max(m);
+      double ell = -INFINITY, g[5] = {0, 0, 0, 0, 0};
+      if (M > -INFINITY) {
+        const double f = (m > -INFINITY) ? (double)__expf(m - M) : 0.0;
+        const double S = wave_total((double)s0 * f);
+        ell = (double)M + log(S) - logK;
+        if (a.want_grad) {
+          const double iS = 1.0 / S;
+          const double inv_ss = (double)P.inv_sig_s;
+          g[0] = wave_total((double)u0 * f) * iS - (double)P.c1;
+          g[1] = wave_total((double)u1 * f) * iS - (double)P.c2;
+          if (a.size_term) {
+            g[2] = inv_ss * wave_total((double)t1 * f) * iS;
+            g[3] = inv_ss * (wave_total((double)t2 * f) * iS - 1.0);
+          }
+          g[4] = (double)P.inv_se3 * wave_total((double)tE * f) * iS - (double)P.dlnZ;
         }
+      }
+      if (lane == pj) {
+        acc[0] += ell;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) acc[1 + j] += g[j];
       }
     }
   }

@@ -94,6 +94,9 @@ struct Slot {
 struct SizeClass {
   int N;
   int64_t stamp_bytes, bin_bytes;
+  hipEvent_t ev_beg = nullptr, ev_end = nullptr;   // this size's last advance launch
+  double tau = -1.0;               // measured milliseconds per iteration (-1: unknown)
+  int last_k = 0;                  // iterations of the last timed launch (0: none pending)
   std::vector<int32_t> fresh;      // slots admitted since the last advance
   std::vector<int32_t> resident;   // running slots
 };
@@ -288,6 +291,10 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   e = hipHostMalloc(reinterpret_cast<void**>(&sv->pinned), (size_t)sv->up_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sv->dev_up), (size_t)sv->up_bytes);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_up, hipEventDisableTiming);
+  for (SizeClass& k : sv->cls) {
+    if (e == hipSuccess) e = hipEventCreate(&k.ev_beg);
+    if (e == hipSuccess) e = hipEventCreate(&k.ev_end);
+  }
   if (e != hipSuccess) {
     (void)hipGetLastError();
     bsi_slots_destroy(sv);
@@ -306,6 +313,10 @@ void bsi_slots_destroy(bsi_slots sv) {
   if (sv->s) (void)hipStreamSynchronize(sv->s);
   else (void)hipDeviceSynchronize();
   if (sv->ev_up) (void)hipEventDestroy(sv->ev_up);
+  for (SizeClass& k : sv->cls) {
+    if (k.ev_beg) (void)hipEventDestroy(k.ev_beg);
+    if (k.ev_end) (void)hipEventDestroy(k.ev_end);
+  }
   if (sv->dev_up) (void)hipFree(sv->dev_up);
   if (sv->pinned) (void)hipHostFree(sv->pinned);
   if (sv->block) (void)hipFree(sv->block);
@@ -423,6 +434,17 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
   std::vector<int> active;
   for (size_t i = 0; i < sv->cls.size(); ++i)
     if (!sv->cls[i].resident.empty()) active.push_back((int)i);
+  // iterations per size: n_iter, or balanced by the measured per-iteration times
+  std::vector<int> iters(sv->cls.size(), n_iter);
+  if (sv->cfg.pace) {
+    double tmax = 0.0;
+    for (int i : active) tmax = std::max(tmax, sv->cls[i].tau);
+    for (int i : active) {
+      const double tau = sv->cls[i].tau;
+      if (tau > 0.0 && tmax > 0.0)
+        iters[i] = (int)std::min<double>(64.0 * n_iter, std::max(1.0, std::round(n_iter * tmax / tau)));
+    }
+  }
   const HmcArgs base = base_args(sv);
   e = fork_join(h, sv->s, (int)active.size(), [&](int j, hipStream_t st) -> hipError_t {
     const int i = active[j];
@@ -447,18 +469,23 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     a.N = k.N;
     a.gidx = res;
     a.n_gal = (int)k.resident.size();
-    a.n_steps = n_iter * sv->L;
-    return launch_hmc_advance(a, a.n_gal, st);
+    a.n_steps = iters[i] * sv->L;
+    if (sv->cfg.pace && (x = hipEventRecord(k.ev_beg, st)) != hipSuccess) return x;
+    x = launch_hmc_advance(a, a.n_gal, st);
+    if (x == hipSuccess && sv->cfg.pace) x = hipEventRecord(k.ev_end, st);
+    return x;
   });
   if (e != hipSuccess) return hip_fail(h, e, "advance launch");
-  // bookkeeping: every resident request got n_iter iterations (or what it had left)
-  for (SizeClass& k : sv->cls) {
+  // bookkeeping: every resident request got its size's iterations (or what it had left)
+  for (size_t i = 0; i < sv->cls.size(); ++i) {
+    SizeClass& k = sv->cls[i];
     k.fresh.clear();
+    if (sv->cfg.pace && !k.resident.empty()) k.last_k = iters[i];
     std::vector<int32_t> keep;
     keep.reserve(k.resident.size());
     for (int32_t slot : k.resident) {
       Slot& s = sv->slots[slot];
-      s.t = std::min(sv->T, s.t + n_iter);
+      s.t = std::min(sv->T, s.t + iters[i]);
       if (s.t >= sv->T) {
         s.done = true;
         sv->finished.push_back(slot);
@@ -484,6 +511,17 @@ int bsi_slots_harvest(bsi_slots sv, int32_t max, uint64_t* ids, float* samples,
   hipError_t e = sv->s ? hipStreamSynchronize(sv->s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(h, e, "server sync");
   sv->up_pending = false;
+  for (SizeClass& k : sv->cls) {
+    if (k.last_k <= 0) continue;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, k.ev_beg, k.ev_end) == hipSuccess && ms > 0.f) {
+      const double t = (double)ms / (double)k.last_k;
+      k.tau = k.tau < 0.0 ? t : 0.5 * (k.tau + t);
+    } else {
+      (void)hipGetLastError();
+    }
+    k.last_k = 0;
+  }
   const int n = (int)std::min<size_t>((size_t)max, sv->finished.size());
   if (n == 0) return BSI_OK;
   std::vector<int32_t> list(sv->finished.begin(), sv->finished.begin() + n);

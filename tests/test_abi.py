@@ -59,7 +59,7 @@ int main(void) {
   F(bsi_shear_hmc_cfg, jitter) F(bsi_shear_hmc_cfg, inv_mass) F(bsi_shear_hmc_cfg, seed)
   F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)
   F(bsi_slots_cfg, hbm_budget) F(bsi_slots_cfg, hmc) F(bsi_slots_cfg, interim)
-  F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile)
+  F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile) F(bsi_slots_cfg, pace)
   F(bsi_request, stamp) F(bsi_request, psf_fwhm) F(bsi_request, ref_y) F(bsi_request, init)
   F(bsi_slots_info, budget) F(bsi_slots_info, arena_largest_free)
   return 0;

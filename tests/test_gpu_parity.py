@@ -190,9 +190,9 @@ def test_hmc_fixed_step_parity(bsi, cfg_name, C, jitter):
 
 
 def test_hmc_mixed_sizes_parity_and_invariance(bsi):
-    """One batch of five stamp sizes (per-size launches on forked streams):
-    each chain follows the oracle under the same Philox momenta, and each
-    galaxy's chains are bitwise those of the galaxy run alone."""
+    """One batch of five stamp sizes: each chain follows the oracle under the
+    same Philox momenta; graph replay and forked direct launches agree
+    bitwise; each galaxy's chains are bitwise those of the galaxy alone."""
     import torch
     _log("hmc mixed sizes 25/41/53/73/101")
     sizes = [25, 41, 53, 73, 101]
@@ -205,6 +205,9 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi):
     base = dict(n_chains=C, n_leapfrog=8, n_warmup=0, n_samples=S, adapt=False, step_size=0.003,
                 jitter=0.1, seed=seed)
     s, stats, st = _run_gpu(bsi, torch, b, data, ref, init, bsi.HmcConfig(**base))
+    # graph replay (sizes in sequence) and direct launches (sizes on forked streams) agree bitwise
+    s_direct = _run_gpu(bsi, torch, b, data, ref, init, bsi.HmcConfig(use_graph=False, **base))[0]
+    assert np.array_equal(s, s_direct)
     agree = 0
     for i in range(G):
         gal = synth.oracle_galaxy(t, data, off, i)
