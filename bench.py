@@ -338,6 +338,7 @@ def main():
                          "uneven / serving: the mixed-size batch or the extended serving study")
     ap.add_argument("--no-legs", action="store_true", help="uniform workload without the shear and "
                     "serving legs (profiling)")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
     args = ap.parse_args()
     if args.copy_probe:
@@ -466,7 +467,8 @@ def main():
         legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
         log(f"[bench] shear-level HMC: {legs['shear_hmc']['t_s']} s")
         del results, r["smp"]
-        legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log)
+        if not args.no_serving:
+            legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log)
     out = {
         "metric": "galaxies/sec at 300 ESS (53x53 stamps), batched vs plain; p50/p99 fit latency",
         "value": round(value, 3),

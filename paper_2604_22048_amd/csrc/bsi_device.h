@@ -34,8 +34,8 @@ struct Geom {
   float inv_nc;
 };
 
-__host__ __device__ inline Geom make_geom(int N) {
-  Geom g;
+__host__ __device__ constexpr Geom make_geom(int N) {
+  Geom g{};
   g.N = N;
   g.h = N / 2;
   g.nc = (N & 1) ? N : N - 1;

@@ -34,7 +34,7 @@ struct GalCtx {
   const float2* dh;
   const float* atab;
   float2* X;       // per-wave tables (see fill_tables); the Fisher metric reuses
-  float2* Ym;      // X and Ym as full x and y tables
+  float4* Ym;      // X and Yf as full x and y tables
   float2* Yf;
   float* red;      // per-wave reduction scratch (2 KiB)
   float norm;      // 1 / (N^2 sigma^2)
@@ -60,6 +60,7 @@ __device__ __forceinline__ void fill_xy_full(const Geom& g, const float* __restr
 
 struct Prior {
   float lf_lo, lf_hi, ls_lo, ls_hi, sd, se;
+  float isd2, ise2;     // 1 / sd^2, 1 / se^2
 };
 
 __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
@@ -71,7 +72,7 @@ __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
 // Outside the support U = +inf and the gradient is evaluated at the nearest
 // admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
 // trajectory can continue (it is rejected anyway).
-template <int PROF, int P>
+template <int PROF, int P, bool CHI2 = true, int NFIX = 0>
 __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& lc, const Prior& pr,
                                             const float* th, float* gU, uint32_t& status) {
   const bool inside = in_support(th, pr);
@@ -90,22 +91,25 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& 
   const float F = bcast(e10, 0), s = bcast(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
   fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
-  const Shape sh = make_shape(s * c.rscale, e1, e2);
-  const KSums S = kspace_sums<PROF, P>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh, c.red);
+  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
+  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh,
+                                                           c.red);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
-  const double isd2 = 1.0 / ((double)pr.sd * pr.sd);
-  const double ise2 = 1.0 / ((double)pr.se * pr.se);
-  const double lp = -0.5 * ((double)th[4] * th[4] + (double)th[5] * th[5]) * isd2 +
-                    (double)(2.0f * __logf(1.0f - E)) - 0.5 * (double)E * ise2;
-  const float cpri = -4.0f / (1.0f - E) - (float)ise2;
+  const float isd2 = pr.isd2, ise2 = pr.ise2;
+  const float cpri = -4.0f * sh.inv1mE - ise2;
   gU[0] = -r.dF * F * kLn10F;
   gU[1] = -r.ds * s * kLn10F;
   gU[2] = -(r.de1 + cpri * e1);
   gU[3] = -(r.de2 + cpri * e2);
-  gU[4] = -(r.ddx - th[4] * (float)isd2);
-  gU[5] = -(r.ddy - th[5] * (float)isd2);
-  double U = -(r.loglik + lp);
-  if (!isfinite(U)) status |= 2u;
+  gU[4] = -(r.ddx - th[4] * isd2);
+  gU[5] = -(r.ddy - th[5] * isd2);
+  double U = 0.0;        // only the gradient is needed inside a trajectory
+  if (CHI2) {
+    const double lp = -0.5 * ((double)th[4] * th[4] + (double)th[5] * th[5]) * (double)pr.isd2 +
+                      (double)(2.0f * __logf(1.0f - E)) - 0.5 * (double)E * (double)pr.ise2;
+    U = -(r.loglik + lp);
+    if (!isfinite(U)) status |= 2u;
+  }
   if (!inside) {
     status |= 1u;
     U = INFINITY;
@@ -130,9 +134,9 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
     E = e1 * e1 + e2 * e2;
   }
   const float F = exp10f(t0), s = exp10f(t1);
-  float2* Y = c.Ym;   // the per-wave region holds 2 ntab + ymax entries
+  float2* Y = c.Yf;   // full x and y tables (ntab entries each)
   fill_xy_full(g, c.atab, c.X, Y, c.refx + th[4], c.refy + th[5]);
-  const Shape sh = make_shape(s * c.rscale, e1, e2);
+  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
   const float cg = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;
   // accumulate sum_c |dM/dp|^2 over every bin, frequency points combined per bin
   float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -216,12 +220,14 @@ struct Lds {
   ChainState* cs;     // this wave's chain record
   float* red;         // this wave's reduction scratch (64 x 8 floats)
   float2* X;
-  float2* Ym;
+  float4* Ym;
   float2* Yf;
 };
 
-__device__ __forceinline__ int wave_table_len(const Geom& g, const SlotPlan& sp) {
-  return 2 * g.ntab + sp.ymax;
+// Per-wave tables, in float2 units: Ym (ymax float4, first so that it is
+// 16-byte aligned), X (ntab), Yf (ntab); the length is even.
+__host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp) {
+  return 2 * sp.ymax + 2 * g.ntab;
 }
 
 // LDS: [data spectrum | atab | column table | C chain records | C reduction
@@ -236,10 +242,10 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave
   l.cs = cs0 + wave;
   float* red0 = reinterpret_cast<float*>(cs0 + C);
   l.red = red0 + 512 * wave;
-  float2* w0 = reinterpret_cast<float2*>(red0 + 512 * C);
-  l.X = w0 + wave_table_len(g, sp) * wave;
-  l.Ym = l.X + g.ntab;
-  l.Yf = l.Ym + sp.ymax;
+  float2* w0 = reinterpret_cast<float2*>(red0 + 512 * C) + wave_table_len(g, sp) * wave;
+  l.Ym = reinterpret_cast<float4*>(w0);
+  l.X = w0 + 2 * sp.ymax;
+  l.Yf = l.X + g.ntab;
   return l;
 }
 
@@ -366,7 +372,7 @@ struct Hot {
 
 __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
-template <int PROF, int P>
+template <int PROF, int P, int NFIX>
 __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
                               const Prior& pr, ChainState* cs, float* samples_chain,
                               float* trace_chain) {
@@ -417,7 +423,11 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 #pragma unroll
     for (int j = 0; j < 6; ++j) h.th[j] += h.eps_t * h.im[j] * h.p[j];
     uint32_t st = 0;
-    h.Uth = potential<PROF, P>(c, lc, pr, h.th, h.g, st);
+    // the potential itself is needed only at the end of the trajectory
+    if (h.l + 1 == a.L)
+      h.Uth = potential<PROF, P, true, NFIX>(c, lc, pr, h.th, h.g, st);
+    else
+      h.Uth = potential<PROF, P, false, NFIX>(c, lc, pr, h.th, h.g, st);
     if (h.t >= a.W) h.status |= st;     // warmup probes are not reported
     if (!in_support(h.th, pr)) h.ok = 0;
     h.l += 1;
@@ -505,14 +515,17 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 #define BSI_HMC_WAVES_PER_EU 2
 #endif
 
-template <int PROF, bool INIT, int P, int MAXT>
+// NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
+template <int PROF, bool INIT, int P, int MAXT, int NFIX>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
-  const Geom g = make_geom(a.N);
-  const SlotPlan sp = make_slot_plan(a.N);
+  const int N = NFIX > 0 ? NFIX : a.N;
+  const Geom g = make_geom(N);
+  const SlotPlan sp = make_slot_plan(N);
   const int wave = threadIdx.x / kWave;
   const Lds l = carve(g, sp, wave, a.C);
   build_col_table(g, sp, l.cols);
-  const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e};
+  const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
+                 1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
   for (int gi = blockIdx.x; gi < a.n_gal; gi += gridDim.x) {
     const int gal = a.gidx[gi];
     __syncthreads();
@@ -578,7 +591,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       wave_lds_sync();
       float* sc = a.samples ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = a.trace ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P>(a, c, lc, pr, l.cs, sc, tc);
+      advance_chain<PROF, P, NFIX>(a, c, lc, pr, l.cs, sc, tc);
       reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
     }
   }
@@ -610,25 +623,44 @@ size_t hmc_lds_bytes(int N, int C) {
   const SlotPlan sp = make_slot_plan(N);
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
          sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C + sizeof(float) * 512 * C +
-         sizeof(float2) * (2 * g.ntab + sp.ymax) * C;
+         sizeof(float2) * wave_table_len(g, sp) * C;
 }
 
-template <int PROF, bool INIT, int P>
+template <int PROF, bool INIT, int P, int NFIX = 0>
 static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   const dim3 blk(kWave * a.C);
   if (a.C <= 4) {
-    auto k = hmc_kernel<PROF, INIT, P, 256>;
+    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   } else {
-    auto k = hmc_kernel<PROF, INIT, P, 1024>;
+    auto k = hmc_kernel<PROF, INIT, P, 1024, 0>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   }
 }
 
+// Trajectory kernels specialised for the stamp sizes of the workloads
+// (compile-time geometry, fully unrolled bin loop); other sizes use the
+// generic kernel of their slot plan.
+template <int PROF, int NFIX>
+static void launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  launch_p<PROF, false, make_slot_plan(NFIX).P, NFIX>(a, grid, lds, s);
+}
+
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (!INIT && a.C <= 4) {
+    switch (a.N) {
+      case 25: launch_fixed<PROF, 25>(a, grid, lds, s); return;
+      case 32: launch_fixed<PROF, 32>(a, grid, lds, s); return;
+      case 41: launch_fixed<PROF, 41>(a, grid, lds, s); return;
+      case 53: launch_fixed<PROF, 53>(a, grid, lds, s); return;
+      case 73: launch_fixed<PROF, 73>(a, grid, lds, s); return;
+      case 101: launch_fixed<PROF, 101>(a, grid, lds, s); return;
+      default: break;
+    }
+  }
   switch (make_slot_plan(a.N).P) {
     case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
     case 2: launch_p<PROF, INIT, 2>(a, grid, lds, s); break;

@@ -48,7 +48,7 @@ struct SlotPlan {
   int nbins;          // nslots + nspec: length of the stored data spectrum
 };
 
-__host__ __device__ inline SlotPlan make_slot_plan(int N) {
+__host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
   const int nc = (N & 1) ? N : N - 1;
   const int rows = (nc - 1) / 2 + 1;
   SlotPlan best{0, 0, 0, 1 << 30, 0, 0, 0};
@@ -103,19 +103,35 @@ struct KResult {
   float dF, ds, de1, de2, ddx, ddy;               // d log L / d params
 };
 
-// Per-evaluation constants of the quadratic form q = ca kx^2 + cb ky^2 + cc kx ky.
+// 1/x to within an ulp: the hardware reciprocal refined by one Newton step.
+__device__ __forceinline__ float rcp_nr(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+
+// Per-evaluation constants of the quadratic form q = ca kx^2 + cb ky^2 + cc kx ky
+// and of the profile exponent t = ta kx^2 + tb ky^2 + tc kx ky + t0 in which
+// the profile factor is evaluated: G = t^(-3/2) with t = 1 + r0^2 q for the
+// exponential, G = 2^t with t = -r^2 q log2(e) / 2 for the Gaussian.
 struct Shape {
   float ca, cb, cc, r2, inv1mE;
+  float ta, tb, tc, t0;
 };
 
+template <int PROF>
 __device__ __forceinline__ Shape make_shape(float rpx, float e1, float e2) {
   Shape s;
   const float E = e1 * e1 + e2 * e2;
-  s.inv1mE = 1.0f / (1.0f - E);
+  s.inv1mE = rcp_nr(1.0f - E);
   s.ca = (1.0f + E + 2.0f * e1) * s.inv1mE;
   s.cb = (1.0f + E - 2.0f * e1) * s.inv1mE;
   s.cc = 4.0f * e2 * s.inv1mE;
   s.r2 = rpx * rpx;
+  const float f = (PROF == kProfExp) ? s.r2 : -0.72134752044448170368f * s.r2;   // -log2(e) / 2
+  s.ta = f * s.ca;
+  s.tb = f * s.cb;
+  s.tc = f * s.cc;
+  s.t0 = (PROF == kProfExp) ? 1.0f : 0.0f;
   return s;
 }
 
@@ -175,7 +191,8 @@ __device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
 
 // Per-wave LDS tables of one evaluation.
 //   X [ntab]  : F a(u) exp(-i k_u dx),   u = -h..h  (k_u dx = 2 pi u dx / N)
-//   Ym[ymax]  : a(v) exp(-i k_v dy) for rows v = 0..ymax-1 (row 0 / sqrt 2, rows > hc zero)
+//   Ym[ymax]  : {a(v) exp(-i k_v dy), k_v, k_v^2} for rows v = 0..ymax-1 (row 0
+//               scaled by 1/sqrt 2, rows > hc zero)
 //   Yf[ntab]  : a(v) exp(-i k_v dy),     v = -h..h (even N only, for the Nyquist bins)
 // with a(u) = PSF(k_u) sinc(u/N) from atab.
 // exp(-2 pi i r) for r in revolutions with the hardware sin/cos (input in
@@ -185,10 +202,11 @@ __device__ __forceinline__ float2 cis_neg_rev(float r) {
 }
 
 __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
-                                            const float* __restrict__ atab, float2* X, float2* Ym,
+                                            const float* __restrict__ atab, float2* X, float4* Ym,
                                             float2* Yf, float F, float dx, float dy) {
   const int lane = lane_id();
-  const float rx = dx / (float)g.N, ry = dy / (float)g.N;   // revolutions per unit frequency
+  const float invN = rcp_nr((float)g.N);
+  const float rx = dx * invN, ry = dy * invN;   // revolutions per unit frequency
   for (int t = lane; t < g.ntab; t += kWave) {
     const float a = F * atab[t];
     const float2 w = cis_neg_rev((float)(t - g.h) * rx);
@@ -196,11 +214,12 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
   }
   const bool even = (g.N & 1) == 0;
   for (int v = lane; v < sp.ymax; v += kWave) {
-    float2 y = make_float2(0.f, 0.f);
+    float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
     if (v <= g.hc) {
       const float a = atab[v + g.h] * (v == 0 ? 0.70710678118654752f : 1.0f);
       const float2 w = cis_neg_rev((float)v * ry);
-      y = make_float2(a * w.x, a * w.y);
+      const float ky = (float)v * g.kstep;
+      y = make_float4(a * w.x, a * w.y, ky, ky * ky);
     }
     Ym[v] = y;
   }
@@ -215,25 +234,63 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
 }
 
 // Accumulate the k-space sums of one wave (red: this wave's 2 KiB reduction
-// scratch in LDS).  dh: the data spectrum (or, with
-// RESID, the spectrum of the pixel residual d - m) in slot order followed by
-// the Nyquist bins.  The X table already contains the flux.  Result is
-// lane-uniform.
-template <int PROF, int P, bool RESID = false>
+// scratch in LDS).  dh: the data spectrum (or, with RESID, the spectrum of the
+// pixel residual d - m) in slot order followed by the Nyquist bins.  The X
+// table already contains the flux.  CHI2 = false skips sum |R|^2 (the
+// gradient alone).  NFIX > 0: the stamp side is the compile-time constant
+// NFIX (fully unrolled super-row loop).  Result is lane-uniform.
+//
+// Per bin, with p = X Y the separable factor and T = G p the model spectrum,
+// R = D - T, and z' = conj(R) p: the sums are sum G z' (flux), sum G a^-1 z'
+// times kx^2, ky^2, kx ky (shape) and sum G Im z' times kx, ky (centroid).
+template <int PROF, int P, bool RESID>
+__device__ __forceinline__ void bin_step(const Shape& sh, float2 D, float4 y, float xr, float xim,
+                                         float TA, float Tc, float kx, float kx2, float& c2,
+                                         float& sF, float& sxx, float& syy, float& wky, float& sdx,
+                                         float& sdy, bool chi2) {
+  const float t = fmaf(Tc, y.z, fmaf(sh.tb, y.w, TA));
+  float G, Gw;
+  if (PROF == kProfExp) {
+    const float rs = __builtin_amdgcn_rsqf(t);
+    const float rs2 = rs * rs;
+    G = rs2 * rs;
+    Gw = G * rs2;
+  } else {
+    G = __builtin_amdgcn_exp2f(t);
+    Gw = G;
+  }
+  const float pr = fmaf(xr, y.x, -xim * y.y);
+  const float pi = fmaf(xr, y.y, xim * y.x);
+  const float Rr = RESID ? D.x : fmaf(-G, pr, D.x);
+  const float Ri = RESID ? D.y : fmaf(-G, pi, D.y);
+  if (chi2) c2 = fmaf(Rr, Rr, fmaf(Ri, Ri, c2));
+  const float zr = fmaf(Rr, pr, Ri * pi);
+  const float zi = fmaf(Rr, pi, -Ri * pr);
+  sF = fmaf(G, zr, sF);
+  const float wq = Gw * zr;
+  sxx = fmaf(kx2, wq, sxx);
+  syy = fmaf(y.w, wq, syy);
+  wky = fmaf(y.z, wq, wky);
+  const float gz = G * zi;
+  sdx = fmaf(kx, gz, sdx);
+  sdy = fmaf(y.z, gz, sdy);
+}
+
+template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0>
 __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P>& lc,
-                             const float2* __restrict__ dh, const float2* X, const float2* Ym,
+                             const float2* __restrict__ dh, const float2* X, const float4* Ym,
                              const float2* Yf, const Shape& sh, float* red) {
   const int lane = lane_id();
-  float xr[P], xim[P], A[P], Cc[P], kx2[P];
-  const float2* yp[P];
+  float xr[P], xim[P], TA[P], Tc[P], kx2[P];
+  const float4* yp[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const float2 x = lc.xi[i] >= 0 ? X[lc.xi[i]] : make_float2(0.f, 0.f);
     xr[i] = x.x;
     xim[i] = x.y;
     kx2[i] = lc.kx[i] * lc.kx[i];
-    A[i] = sh.ca * kx2[i];
-    Cc[i] = sh.cc * lc.kx[i];
+    TA[i] = fmaf(sh.ta, kx2[i], sh.t0);
+    Tc[i] = sh.tc * lc.kx[i];
     yp[i] = Ym + lc.yo[i];
   }
   double chi2 = 0.0;
@@ -242,35 +299,42 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
 #pragma unroll
   for (int i = 0; i < P; ++i) wky[i] = 0.f;
   const float2* dp = dh + lane;
-  for (int sr = 0; sr < sp.nsr; ++sr) {
-    const float v0k = (float)(sr * sp.R) * g.kstep;
-    float c2 = 0.f;
+  if constexpr (NFIX > 0) {
+    constexpr SlotPlan spc = make_slot_plan(NFIX);
+    static_assert(spc.P == P, "slot plan of NFIX must use P iterations");
+    // software pipeline: the LDS reads of the next bin are issued before the
+    // arithmetic of the current one
+    float2 Dn = dp[0];
+    float4 yn = yp[0][0];
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      const float2 D = dp[i * 64];
-      const float2 y = yp[i][sr * sp.R];
-      const float ky = lc.rok[i] + v0k;
-      const float ky2 = ky * ky;
-      const float q = fmaf(Cc[i], ky, fmaf(sh.cb, ky2, A[i]));
-      float G, ia;
-      profile_factor<PROF>(sh, q, G, ia);
-      const float pr = fmaf(xr[i], y.x, -xim[i] * y.y);
-      const float pi = fmaf(xr[i], y.y, xim[i] * y.x);
-      const float Tr = G * pr, Ti = G * pi;
-      const float Rr = RESID ? D.x : D.x - Tr, Ri = RESID ? D.y : D.y - Ti;
-      c2 = fmaf(Rr, Rr, fmaf(Ri, Ri, c2));
-      const float zr = fmaf(Rr, Tr, Ri * Ti);
-      const float zi = fmaf(Rr, Ti, -Ri * Tr);
-      sF += zr;
-      const float wq = zr * ia;
-      sxx = fmaf(kx2[i], wq, sxx);
-      syy = fmaf(ky2, wq, syy);
-      wky[i] = fmaf(ky, wq, wky[i]);
-      sdx = fmaf(lc.kx[i], zi, sdx);
-      sdy = fmaf(ky, zi, sdy);
+    for (int sr = 0; sr < spc.nsr; ++sr) {
+      float c2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < P; ++i) {
+        const float2 D = Dn;
+        const float4 y = yn;
+        const int k = sr * P + i + 1;
+        if (k < spc.nsr * P) {
+          Dn = dp[k * 64];
+          yn = yp[k % P][(k / P) * spc.R];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this bin's arithmetic
+        bin_step<PROF, P, RESID>(sh, D, y, xr[i], xim[i], TA[i], Tc[i], lc.kx[i], kx2[i], c2, sF,
+                                 sxx, syy, wky[i], sdx, sdy, CHI2);
+      }
+      if (CHI2) chi2 += (double)c2;
     }
-    chi2 += (double)c2;
-    dp += P * 64;
+  } else {
+    for (int sr = 0; sr < sp.nsr; ++sr) {
+      float c2 = 0.f;
+      const float4* yr = Ym + sr * sp.R;
+#pragma unroll
+      for (int i = 0; i < P; ++i)
+        bin_step<PROF, P, RESID>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xim[i], TA[i], Tc[i],
+                                 lc.kx[i], kx2[i], c2, sF, sxx, syy, wky[i], sdx, sdy, CHI2);
+      if (CHI2) chi2 += (double)c2;
+      dp += P * 64;
+    }
   }
 #pragma unroll
   for (int i = 0; i < P; ++i) sxy = fmaf(lc.kx[i], wky[i], sxy);
@@ -306,7 +370,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     }
     const float Rr = RESID ? D.x : D.x - Mr, Ri = RESID ? D.y : D.y - Mi;
     const float cf = (float)c;
-    chi2 += (double)(cf * fmaf(Rr, Rr, Ri * Ri));
+    if (CHI2) chi2 += (double)(cf * fmaf(Rr, Rr, Ri * Ri));
     for (int au = 0; au < nu; ++au) {
       const int u = (nu == 2) ? (au == 0 ? -h : h) : ub;
       const float cu = (nu == 2) ? (au == 0 ? 0.5f : -0.5f) : 1.0f;
@@ -336,7 +400,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
 
   KSums s;
-  s.chi2 = wave_total(chi2);
+  s.chi2 = CHI2 ? wave_total(chi2) : 0.0;
   float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
   wave_total7(v, red);
   s.sF = v[0];
@@ -359,8 +423,8 @@ __device__ __forceinline__ KResult kspace_finish(const KSums& S, const Shape& sh
   KResult r;
   r.loglik = -0.5 * (double)norm * S.chi2;
   const float c = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;   // d ln G / dq * a
-  r.dF = norm * S.sF / F;
-  r.ds = norm * (2.0f * c / s_arcsec) * S.sq;
+  r.dF = norm * S.sF * rcp_nr(F);
+  r.ds = norm * (2.0f * c * rcp_nr(s_arcsec)) * S.sq;
   r.de1 = norm * c * sh.inv1mE *
           ((2.0f * e1 + 2.0f) * S.sxx + (2.0f * e1 - 2.0f) * S.syy + 2.0f * e1 * S.sq);
   r.de2 = norm * c * sh.inv1mE * (2.0f * e2 * (S.sxx + S.syy) + 4.0f * S.sxy + 2.0f * e2 * S.sq);

@@ -18,13 +18,13 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   const SlotPlan sp = make_slot_plan(N);
   const int gal = gidx[blockIdx.x];
   float2* dh = reinterpret_cast<float2*>(smem4);
-  float* atab = reinterpret_cast<float*>(dh + sp.nbins);
-  float2* X = reinterpret_cast<float2*>(atab + ((g.ntab + 1) & ~1));
-  float2* Ym = X + g.ntab;
-  float2* Yf = Ym + sp.ymax;
-  float4* cols = reinterpret_cast<float4*>(Yf + g.ntab + 1);
-  cols = reinterpret_cast<float4*>((reinterpret_cast<uintptr_t>(cols) + 15) & ~uintptr_t(15));
-  float* red = reinterpret_cast<float*>(cols + sp.P * 64);
+  float* atab = reinterpret_cast<float*>(dh + ((sp.nbins + 1) & ~1));
+  float4* cols = reinterpret_cast<float4*>(atab + ((g.ntab + 3) & ~3));
+  float4* Ym = cols + sp.P * 64;
+  float2* X = reinterpret_cast<float2*>(Ym + sp.ymax);
+  float2* Yf = X + g.ntab;
+  float* red = reinterpret_cast<float*>(Yf + g.ntab + 1);
+  red = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
   build_col_table(g, sp, cols);
   const float2* src = dh_all + bin_off[gal];
   for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) dh[b] = src[b];
@@ -44,7 +44,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   uint32_t st = 0;
   if (!(E < 1.0f) || !(s > 0.0f) || !(F > 0.0f)) st |= 1u;
   fill_tables(g, sp, atab, X, Ym, Yf, F, dx, dy);
-  const Shape sh = make_shape(s * rscale, e1, e2);
+  const Shape sh = make_shape<PROF>(s * rscale, e1, e2);
   const LaneCols<P> lc = lane_cols<P>(cols);
   const KSums S = kspace_sums<PROF, P, RESID>(g, sp, lc, dh, X, Ym, Yf, sh, red);
   KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, norm);
@@ -66,9 +66,9 @@ __global__ void __launch_bounds__(64) loglik_kernel(
 static size_t loglik_lds_bytes(int N) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan(N);
-  return sizeof(float2) * sp.nbins + sizeof(float) * ((g.ntab + 1) & ~1) +
-         sizeof(float2) * (2 * g.ntab + sp.ymax + 1) + 16 + sizeof(float4) * sp.P * 64 +
-         sizeof(float) * 64 * 8;
+  return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
+         sizeof(float4) * sp.P * 64 + sizeof(float4) * sp.ymax + sizeof(float2) * (2 * g.ntab + 1) +
+         16 + sizeof(float) * 64 * 8;
 }
 
 template <int PROF, bool RESID>
