@@ -50,24 +50,30 @@ def flops_per_eval(N: int) -> float:
     return 43.0 * nbins + 12.0 * (ntab + rows) + 100.0
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {
+    "hmc": ("hmc.hip", "kspace.h", "bsi_device.h", "bsi_kernels.h"),
+    "shear": ("shear.hip", "bsi_device.h", "bsi_kernels.h"),
+}
+
+
+def kernel_source_hash(kernel: str = "hmc") -> str:
+    """Digest of the sources a kernel is compiled from (its profile's key)."""
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2604_22048_amd", "csrc", "*"))):
-        if f.endswith((".hip", ".h", ".cpp")):
-            h.update(os.path.basename(f).encode())
-            h.update(open(f, "rb").read())
+    for f in KERNEL_SOURCES[kernel]:
+        h.update(f.encode())
+        h.update(open(os.path.join(ROOT, "paper_2604_22048_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per trajectory launch from the committed counter summary, or
-    None when the kernel sources have changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "hmc_kernel_uniform53.txt")
+def recorded_traffic(profile="hmc_kernel_uniform53.txt", kernel="hmc"):
+    """HBM bytes per launch from a committed counter summary, or None when the
+    kernel's sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", profile)
     try:
         kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
     except OSError:
         return None
-    if kv.get("source_sha256", "").strip() != kernel_source_hash():
+    if kv.get("source_sha256", "").strip() != kernel_source_hash(kernel):
         return None
     return float(kv["traffic_bytes_per_launch"])
 
@@ -201,9 +207,33 @@ def shear_leg(api, torch, stream, smp, G, K, seed):
             "accept_rate": round(float(sst[:, 0].mean()), 4),
             "eval_pass_us": round(t_pass * 1e6, 2),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(gbs / 8000.0, 4), "traffic": None,
+                         "frac": round(gbs / 8000.0, 4),
+                         "traffic": recorded_traffic("shear_kernel_diff_1e7.txt", "shear"),
                          "kernel": "shear_kernel + shear_reduce_kernel (4 points, with gradient)",
                          "alg_bytes_per_pass": bytes_pass}}
+
+
+def shear_pass_leg(api, torch, stream, reps, G=10_000, K=1000):
+    """One evaluation pass of the shear-level sampler (4 points with gradient)
+    over G x K synthetic interim samples, repeated `reps` times without a
+    graph (the counter runs profile this form)."""
+    dev = torch.device("cuda:0")
+    g = torch.Generator(device=dev)
+    g.manual_seed(gen.data_seed(3))
+    e1p = (0.25 * torch.randn(G, K, generator=g, device=dev)).clamp(-0.9, 0.9)
+    e2p = (0.25 * torch.randn(G, K, generator=g, device=dev)).clamp(-0.9, 0.9)
+    l10s = math.log10(0.6) + 0.13 * torch.randn(G, K, generator=g, device=dev)
+    tp = api.TruePriorCfg(e_kind=1, e_max=0.95, size_term=True)
+    pts = torch.tensor([[0.02, 0.0, math.log(0.6), 0.3, 0.2], [0.0, 0.01, -0.5, 0.3, 0.21],
+                        [0.01, -0.01, -0.55, 0.28, 0.2], [-0.01, 0.0, -0.5, 0.32, 0.19]],
+                       dtype=torch.float64, device=dev)
+    api.shear_posterior(e1p, e2p, l10s, None, pts, tp, want_grad=True)
+    _, t = timed(torch, lambda: [api.shear_posterior(e1p, e2p, l10s, None, pts, tp, want_grad=True)
+                                 for _ in range(reps)], stream)
+    t /= reps
+    by = G * K * 12.0
+    return {"reps": reps, "pass_us": round(t * 1e6, 2), "alg_bytes_per_pass": by,
+            "gb_per_s": round(by / t / 1e9, 1), "frac_hbm_peak": round(by / t / 8e12, 4)}
 
 
 SERVING_SIZES = gen.SIZE_CLASSES
@@ -333,7 +363,7 @@ def main():
     ap.add_argument("--plain-gal", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
-    ap.add_argument("--workload", choices=["uniform", "uneven", "serving"], default="uniform",
+    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass"], default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
     ap.add_argument("--no-legs", action="store_true", help="uniform workload without the shear and "
@@ -359,6 +389,14 @@ def main():
         from paper_2604_22048_amd import api
         torch.cuda.init()
         stream = torch.cuda.current_stream(torch.device("cuda:0"))
+        if args.workload == "shear-pass":
+            res = shear_pass_leg(api, torch, stream, args.steps)
+            out = {"metric": "shear posterior evaluation pass (4 points, with gradient)",
+                   "value": res["gb_per_s"], "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
+                   "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "10,000 galaxies x 1,000 interim samples, 4 points"}, **res}
+            print(json.dumps(out), flush=True)
+            return
         if args.workload == "uneven":
             G = args.n_gal or gen.CONFIGS["uneven"].n_gal
             res = uneven_leg(api, torch, stream, G, log)
