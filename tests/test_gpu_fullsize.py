@@ -1,0 +1,173 @@
+"""Parity at the workloads' full sizes, in the launch configuration the
+benchmark times (batched, graph-replayed, kernels specialised per stamp
+size): sampled outputs against the oracle one by one, and properties that
+hold at any size (batch invariance, additivity over galaxies).
+
+Tolerances as in test_gpu_parity: log L relative 1e-6, gradient 1e-4 of
+|g| + sqrt(F_jj), positions 1e-4 until the first accept decision that the
+float32 and float64 potentials take differently.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import diagnostics, hmc, render, shear            # noqa: E402
+from workloads import gen                                    # noqa: E402
+from tests import synth                                      # noqa: E402
+
+PS = gen.PIXEL_SCALE
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsi(device):
+    from paper_2604_22048_amd import api
+    return api
+
+
+@pytest.fixture(scope="module")
+def uniform(bsi):
+    """The batched uniform workload at full size: 10,000 galaxies, 53 x 53."""
+    import torch
+    _log("full-size uniform inputs (oracle-rendered)")
+    cfg = gen.CONFIGS["uniform"]
+    t, params, data, off = synth.make_population("uniform")
+    init = synth.init_positions(t, params, data, off, cfg.chains, seed=77)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=PS)
+    return dict(t=t, params=params, data=data, off=off, init=init, b=b,
+                dev=torch.tensor(data).cuda(),
+                ref=torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32).cuda())
+
+
+SAMPLED = [0, 17, 1234, 4999, 5000, 7777, 9998, 9999]
+
+
+def test_uniform_full_loglik_sampled(bsi, uniform):
+    import torch
+    u = uniform
+    G = len(u["t"])
+    assert G == 10_000
+    p32 = u["params"].astype(np.float32)
+    ll, gr, st = bsi.loglik_grad(u["b"], u["dev"], torch.tensor(p32).cuda())
+    ll, gr = ll.cpu().numpy(), gr.cpu().numpy()
+    assert np.all(np.isfinite(ll)) and np.all(st.cpu().numpy() == 0)
+    for i in SAMPLED:
+        N = int(u["t"].n_pix[i])
+        d = u["data"][u["off"][i]:u["off"][i] + N * N].reshape(N, N).astype(np.float64)
+        psf = float(np.float32(u["t"].psf_fwhm[i]))
+        p = p32[i].astype(np.float64)
+        rll, rg = render.loglik_grad(d, p, N, PS, psf, 1.0)
+        assert abs(ll[i] - rll) <= 1e-6 * abs(rll), (i, ll[i], rll)
+        _, dT = render.spectrum(p, N, PS, psf, derivs=True)
+        sc = np.array([math.sqrt(np.sum(render.synthesize(dT[j], N) ** 2)) for j in range(6)])
+        assert np.all(np.abs(gr[i] - rg) <= 1e-4 * (np.abs(rg) + sc)), (i, gr[i], rg)
+
+
+def test_uniform_full_hmc_sampled_and_invariant(bsi, uniform):
+    """All 40,000 chains advanced together (Fisher metric, jitter 0.2, one
+    graph-replayed launch per trajectory, L = 20) for three iterations at a
+    fixed step; sampled chains follow the oracle, and sampled galaxies run
+    alone reproduce their slice bitwise."""
+    import torch
+    u = uniform
+    C, L, S = 4, 20, 3
+    base = dict(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False, metric=1,
+                step_size=0.3, jitter=0.2, seed=2024, use_graph=True)
+    cfg = bsi.HmcConfig(**base)
+    init_t = torch.tensor(u["init"], dtype=torch.float32).cuda()
+    smp, stats, status = bsi.hmc_sample(u["b"], u["dev"], u["ref"], init_t, cfg)
+    smp = smp.cpu().numpy()
+    assert np.all(np.isfinite(smp))
+    agree = 0
+    for i in SAMPLED[:4]:
+        gal = synth.oracle_galaxy(u["t"], u["data"], u["off"], i)
+        for c in range(C):
+            th0 = u["init"][i, c].astype(np.float32).astype(np.float64)
+            im = hmc.fisher_inv_mass(gal, th0)
+            r = hmc.run_chain(hmc.galaxy_potential(gal), th0, 2024, i * C + c, L, 0, S, 0.3,
+                              adapt=False, inv_mass=im, jitter=0.2)
+            n_ok = 0
+            for k in range(S):
+                d = np.max(np.abs(smp[i, c, k] - r["samples"][k]))
+                if d > 1e-4:
+                    moved_g = k == 0 or np.any(smp[i, c, k] != smp[i, c, k - 1])
+                    moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+                    assert moved_g != moved_o, (i, c, k, d)
+                    break
+                n_ok += 1
+            agree += n_ok
+    assert agree >= 4 * C * S - 2
+    for i in SAMPLED[4:]:
+        N = int(u["t"].n_pix[i])
+        b1 = bsi.Batch(n=np.array([N]), psf_fwhm=u["b"].psf_fwhm[i:i + 1].clone(),
+                       sigma=u["b"].sigma[i:i + 1].clone(), pixel_scale=PS)
+        one = bsi.HmcConfig(uid_base=i * C, **base)
+        s1, _, _ = bsi.hmc_sample(b1, u["dev"][u["off"][i]:u["off"][i] + N * N].contiguous(),
+                                  u["ref"][i:i + 1].contiguous(), init_t[i:i + 1].contiguous(), one)
+        assert np.array_equal(s1[0].cpu().numpy(), smp[i]), i
+
+
+def test_shear_full_size_additivity_and_sampled(bsi):
+    """10,000 galaxies x 1,000 interim samples at 4 points with gradient: the
+    pass over all galaxies equals the sum of the passes over two halves (ln P
+    and its gradient are sums over galaxies), and single sampled galaxies
+    match the oracle's posterior term."""
+    import torch
+    _log("full-size shear pass")
+    G, K = 10_000, 1000
+    S = synth.interim_population(G, K, seed=91)
+    St = [torch.tensor(a).cuda() for a in S]
+    tpg = bsi.TruePriorCfg(e_kind=1, e_max=0.95, size_term=True)
+    pts = np.array([[0.02, 0.0, math.log(0.6), 0.3, 0.2], [0.0, 0.01, -0.5, 0.3, 0.21],
+                    [0.01, -0.01, -0.55, 0.28, 0.2], [0.03, 0.005, -0.5, 0.31, 0.19]])
+    lp, gr = bsi.shear_posterior(St[0], St[1], St[2], None, pts, tpg, want_grad=True)
+    h = G // 2
+    lp1, gr1 = bsi.shear_posterior(St[0][:h], St[1][:h], St[2][:h], None, pts, tpg, want_grad=True)
+    lp2, gr2 = bsi.shear_posterior(St[0][h:], St[1][h:], St[2][h:], None, pts, tpg, want_grad=True)
+    lp, gr = lp.cpu().numpy(), gr.cpu().numpy()
+    s_lp = (lp1 + lp2).cpu().numpy()
+    s_gr = (gr1 + gr2).cpu().numpy()
+    assert np.all(np.abs(lp - s_lp) <= 1e-10 * np.abs(lp)), (lp, s_lp)
+    assert np.all(np.abs(gr - s_gr) <= 1e-9 * (np.abs(gr) + G)), (gr, s_gr)
+    tpo = shear.TruePrior(e_kind=1, e_max=0.95)
+    ip = shear.Interim()
+    for n in (0, 4321, 9999):
+        one = bsi.shear_posterior(St[0][n:n + 1], St[1][n:n + 1], St[2][n:n + 1], None, pts, tpg)
+        one = one.cpu().numpy()
+        Sd = [a[n:n + 1].astype(np.float64) for a in S]
+        for j in range(4):
+            ref = shear.log_posterior(Sd, complex(pts[j, 0], pts[j, 1]), tuple(pts[j, 2:]), tpo, ip)
+            assert abs(one[j] - ref) <= 1e-5 * (abs(ref) + 1.0), (n, j, one[j], ref)
+
+
+def test_ess_full_size_sampled(bsi):
+    """ESS and R-hat over the uniform workload's full sample array shape
+    (10,000 x 4 chains x 1,000 draws x 6), synthetic AR(1) series drawn with
+    torch's generator; sampled galaxies against the oracle."""
+    import torch
+    _log("full-size ESS")
+    G, C, S, P = 10_000, 4, 1000, 6
+    gen_t = torch.Generator(device="cuda")
+    gen_t.manual_seed(5)
+    rho = torch.linspace(0.0, 0.9, P, device="cuda")
+    eps = torch.randn(G, C, S, P, generator=gen_t, device="cuda")
+    x = torch.empty_like(eps)
+    x[:, :, 0] = eps[:, :, 0]
+    for t in range(1, S):
+        x[:, :, t] = rho * x[:, :, t - 1] + torch.sqrt(1 - rho * rho) * eps[:, :, t]
+    e, r = bsi.ess(x)
+    e, r = e.cpu().numpy(), r.cpu().numpy()
+    for g in (0, 3333, 9999):
+        xs = x[g].double().cpu().numpy()
+        for p in range(P):
+            assert abs(e[g, p] / diagnostics.ess(xs[:, :, p]) - 1) < 1e-5, (g, p)
+            assert abs(r[g, p] / diagnostics.rhat(xs[:, :, p]) - 1) < 1e-6, (g, p)
