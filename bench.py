@@ -266,6 +266,7 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
     hc = api.HmcConfig(n_chains=1, n_leapfrog=cfg.leapfrog, n_warmup=cfg.warmup, n_samples=n_draws,
                        adapt=True, metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8,
                        jitter=0.2, seed=gen.chain_seed(cfg.index))
+    plans = api.autotune(list(SERVING_SIZES), n_chains=1)
     pool = make_request_pool(api, torch, 512)
     w = np.array(cfg.extra["size_weights"])
 
@@ -297,6 +298,7 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
            "galaxies_per_s": round(r.n_done / r.wall, 1), **lat_stats(r),
            "max_resident": r.max_resident, "ticks": r.ticks, "iters_per_tick": iters_per_tick,
            "warmup": cfg.warmup, "draws": n_draws, "leapfrog": cfg.leapfrog,
+           "slot_plans": {N: P for N, (P, _) in plans.items()},
            "ess_mean_median": round(float(np.median(em)), 1),
            "frac_ess_ge_300": round(float(np.mean(em >= 300.0)), 4),
            "p50_ms_by_size": by_size(r, sizes)}
@@ -324,6 +326,7 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
     (25-101), PSF FWHM ~ U(0.6, 0.9), SNR 10-200, 4 chains, 20 leapfrog
     steps, 300 warmup + 1000 draws; the size classes launch concurrently."""
     cfg = gen.CONFIGS["uneven"]
+    plans = api.autotune(list(gen.SIZE_CLASSES), n_chains=cfg.chains)
     t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
     C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
     hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
@@ -343,7 +346,8 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
-    return {"n_gal": n_gal, "size_counts": counts, "t_hmc_s": round(t_hmc, 4),
+    return {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
+            "t_hmc_s": round(t_hmc, 4),
             "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
             "n_eff_mean": round(n_eff, 1),
             "galaxies_per_s": round(1.0 / tpg, 1),
@@ -432,6 +436,8 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
+    plans = api.autotune([cfg.n_pix], n_chains=cfg.chains)
+    log(f"[bench] slot plans {plans}")
     t, b, data, ref, init = make_inputs(api, torch, G, cfg)
     N = cfg.n_pix
     C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
@@ -524,7 +530,8 @@ def main():
                                "SNR 15-100, 4 chains, 20 leapfrog steps, 300 dual-averaging warmup "
                                "+ 1000 draws, shear grid 41x41",
                    "n_gal": G, "stamp": N, "chains": C, "leapfrog": L, "warmup_iters": W,
-                   "samples": S, "metric_kind": "fisher-diagonal", "jitter": 0.2},
+                   "samples": S, "metric_kind": "fisher-diagonal", "jitter": 0.2,
+                   "slot_plan_P": plans[N][0]},
         "plain_value": round(plain_value, 4),
         "batched_over_plain": round(value / plain_value, 1),
         "t_warmup_s": round(t_w, 4),

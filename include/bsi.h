@@ -277,6 +277,36 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
                   const bsi_interim* interim, const bsi_shear_hmc_cfg* cfg, const double* init,
                   double* samples, double* chain_stats, bsi_stream stream);
 
+/* ---- Slot plans and their autotuning ---------------------------------------
+ *
+ * The k-space loop of a stamp side N walks the half-plane bins as super-rows
+ * of R rows spread over P iterations of the 64 lanes (the "slot plan"); P
+ * fixes R and the padding.  By default each N uses the P with the fewest
+ * slots.  A handle can hold another choice per N, set explicitly or measured
+ * by bsi_autotune; every later call on the handle (and every request server
+ * created afterwards) uses it.  Results do not depend on the plan beyond
+ * float32 rounding (the order of the sums changes). */
+
+/* Set (P > 0) or reset to the default (P = 0) the slot plan of stamp side n.
+ * BSI_EINVAL unless 8 <= n <= 128 and P is 0 or one of 1, 2, 3, 4, 5, 6, 8
+ * with at least one row per super-row. */
+int bsi_set_plan(bsi_handle h, int32_t n, int32_t P);
+
+/* The slot plan stamp side n uses on this handle (*P), and its number of
+ * slots per evaluation (*slots, nullable). */
+int bsi_get_plan(bsi_handle h, int32_t n, int32_t* P, int32_t* slots);
+
+/* Measure, for each stamp side sizes[i], the trajectory kernel with each
+ * candidate plan (those within 10 % of the fewest slots, at most three) on a
+ * synthetic batch that fills the device (about 16,384 chains of n_chains per
+ * galaxy, exponential profile, 20 leapfrog steps, best of five launches),
+ * and keep the fastest on the handle; the default plan is kept unless
+ * another is at least 2 % faster.  chosen [host] int32[n_sizes] receives
+ * the plans, ms [host] float[n_sizes] the measured milliseconds per launch
+ * (both nullable).  Allocates and frees its own device buffers; synchronous. */
+int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_chains,
+                 int32_t* chosen, float* ms);
+
 /* ---- Request serving: slot-based continuous batching of phase 1 ----------
  *
  * A server keeps the chains of many independent galaxy-fit requests resident

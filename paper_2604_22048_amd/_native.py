@@ -107,6 +107,10 @@ SIGNATURES = {
     "bsi_slots_harvest": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64), C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "bsi_slots_get_info": (C.c_int, [C.c_void_p, C.POINTER(SlotsInfo)]),
+    "bsi_set_plan": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "bsi_get_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bsi_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                               C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "bsi_ess": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                           C.c_void_p, C.c_void_p, C.c_void_p]),
 }

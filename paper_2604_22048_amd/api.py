@@ -394,6 +394,32 @@ class Slots:
             pass
 
 
+def set_plan(n: int, P: int, lib: Library | None = None):
+    """Slot plan P for stamp side n on the handle (0 = default)."""
+    lib = lib or get()
+    lib.check(lib.lib.bsi_set_plan(lib.h, int(n), int(P)), "bsi_set_plan")
+
+
+def get_plan(n: int, lib: Library | None = None):
+    """(P, slots) of stamp side n on the handle."""
+    lib = lib or get()
+    P, sl = C.c_int32(), C.c_int32()
+    lib.check(lib.lib.bsi_get_plan(lib.h, int(n), C.byref(P), C.byref(sl)), "bsi_get_plan")
+    return P.value, sl.value
+
+
+def autotune(sizes, n_chains: int = 4, lib: Library | None = None):
+    """Measure the candidate slot plans of each size and keep the fastest:
+    {N: (P, ms per 20-step launch or None when there was one candidate)}."""
+    lib = lib or get()
+    n = len(sizes)
+    sz = (C.c_int32 * max(n, 1))(*[int(x) for x in sizes])
+    ch = (C.c_int32 * max(n, 1))()
+    ms = (C.c_float * max(n, 1))()
+    lib.check(lib.lib.bsi_autotune(lib.h, n, sz, int(n_chains), ch, ms), "bsi_autotune")
+    return {int(sizes[i]): (int(ch[i]), float(ms[i]) if ms[i] >= 0 else None) for i in range(n)}
+
+
 def ess(samples: torch.Tensor, lib: Library | None = None):
     """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]."""
     dev = samples.device

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbsi.so")
 SOURCES = ["transform.hip", "likelihood.hip", "hmc.hip", "shear.hip", "diag.hip", "slots.hip", "api.cpp",
-           "slots.cpp"]
+           "slots.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -26,6 +26,7 @@ thread_local std::string g_create_error;
 
 struct ClassRange {
   int N;
+  int P;       // slot plan
   int begin;   // position in the sorted galaxy list
   int count;
 };
@@ -56,15 +57,21 @@ int check_batch(bsi_handle h, const bsi_batch* b) {
   return BSI_OK;
 }
 
-Plan make_plan(const bsi_batch* b) {
+// Slot plan of stamp side N on this handle.
+int plan_of(bsi_handle h, int N) {
+  const int P = (N >= 0 && N <= kMaxN) ? h->plan_P[N] : 0;
+  return P > 0 ? P : make_slot_plan(N).P;
+}
+
+Plan make_plan(bsi_handle h, const bsi_batch* b) {
   Plan p;
   std::map<int, std::vector<int32_t>> by;
   for (int i = 0; i < b->n_gal; ++i) by[b->n[i]].push_back(i);
   p.bin_off.assign(b->n_gal, 0);
   int64_t bins = 0;
   for (auto& kv : by) {
-    ClassRange c{kv.first, (int)p.gidx.size(), (int)kv.second.size()};
-    const SlotPlan sp = make_slot_plan(kv.first);
+    ClassRange c{kv.first, plan_of(h, kv.first), (int)p.gidx.size(), (int)kv.second.size()};
+    const SlotPlan sp = make_slot_plan_p(c.N, c.P);
     for (int32_t i : kv.second) {
       p.gidx.push_back(i);
       p.bin_off[i] = bins;
@@ -105,7 +112,7 @@ int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* 
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_dft_bins(data, model, gidx_ptr(h, c), c.count,
                                    static_cast<const int64_t*>(h->off.p),
-                                   static_cast<const int64_t*>(h->bin_off.p), c.N,
+                                   static_cast<const int64_t*>(h->bin_off.p), c.N, c.P,
                                    static_cast<float2*>(h->dh.p), chi2, b->sigma, s);
     if (e != hipSuccess) return hip_fail(h, e, "dft_bins launch");
   }
@@ -209,7 +216,7 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
   if (!params || !out) return fail(h, BSI_EINVAL, "params/out is NULL");
   hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Plan p = make_plan(batch);
+  const Plan p = make_plan(h, batch);
   if ((rc = upload_plan(h, batch, p, s))) return rc;
   const float rs = profile_rscale(batch->profile, batch->pixel_scale);
   for (const ClassRange& c : p.classes) {
@@ -234,7 +241,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     return fail(h, BSI_EINVAL, "unknown likelihood method %d", method);
   hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const Plan p = make_plan(batch);
+  const Plan p = make_plan(h, batch);
   if ((rc = upload_plan(h, batch, p, s))) return rc;
   const float rs = profile_rscale(batch->profile, batch->pixel_scale);
   const int64_t* off = static_cast<const int64_t*>(h->off.p);
@@ -256,7 +263,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_loglik(static_cast<const float2*>(h->dh.p),
                                  static_cast<const int64_t*>(h->bin_off.p), gidx_ptr(h, c), c.count,
-                                 params, batch->psf_fwhm, batch->sigma, c.N, rs,
+                                 params, batch->psf_fwhm, batch->sigma, c.N, c.P, rs,
                                  1.0f / batch->pixel_scale, batch->profile,
                                  method == BSI_LIK_PIXEL, chi2, loglik, grad, status, s);
     if (e != hipSuccess) return hip_fail(h, e, "loglik launch");
@@ -296,13 +303,13 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     return fail(h, BSI_EINVAL, "no output requested");
   hipSetDevice(h->device);
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->own;
-  const Plan p = make_plan(batch);
+  const Plan p = make_plan(h, batch);
   if ((rc = upload_plan(h, batch, p, s))) return rc;
   if ((rc = data_spectrum(h, batch, p, data, nullptr, nullptr, s))) return rc;
   const int C = cfg->n_chains;
   if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
   for (const ClassRange& c : p.classes) {
-    if (hmc_lds_bytes(c.N, C) > 160 * 1024)
+    if (hmc_lds_bytes(c.N, C, c.P) > 160 * 1024)
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", c.N, C);
   }
 
@@ -344,6 +351,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   for (const ClassRange& c : p.classes) {
     HmcArgs ac = a;
     ac.N = c.N;
+    ac.P = c.P;
     ac.gidx = gidx_ptr(h, c);
     ac.n_gal = c.count;
     ac.n_steps = 0;
@@ -357,6 +365,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       for (int i = 0; i < c.count; ++i) {
         HmcArgs ac = a;
         ac.N = c.N;
+        ac.P = c.P;
         ac.gidx = gidx_ptr(h, c) + i;
         ac.n_gal = 1;
         ac.n_steps = 1;
@@ -373,6 +382,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       const ClassRange& c = p.classes[i];
       HmcArgs ac = a;
       ac.N = c.N;
+      ac.P = c.P;
       ac.gidx = gidx_ptr(h, c);
       ac.n_gal = c.count;
       ac.n_steps = ipl * a.L;

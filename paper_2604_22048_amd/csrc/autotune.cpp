@@ -1,0 +1,219 @@
+// Slot-plan selection per stamp side: explicit (bsi_set_plan) or measured
+// on the device (bsi_autotune).
+#include "bsi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "bsi_kernels.h"
+#include "ctx.h"
+#include "kspace.h"
+
+using namespace bsi;
+using namespace bsi_host;
+
+namespace {
+
+bool supported_p(int P) {
+  for (int k : kPlanP)
+    if (k == P) return true;
+  return false;
+}
+
+// Candidate plans of side N, the default first: the specialised ones if
+// any, else the supported P within 10 % of the fewest slots (at most three,
+// fewest slots first).
+std::vector<int> candidates(int N) {
+  std::vector<int> out{make_slot_plan(N).P};
+  for (const int* p = hmc_fixed_plans(N); *p; ++p)
+    if (*p != out[0]) out.push_back(*p);
+  if (out.size() > 1) return out;
+  const int best = make_slot_plan(N).nslots;
+  std::vector<std::pair<int, int>> c;
+  for (int P : kPlanP)
+    if (plan_valid(N, P) && make_slot_plan_p(N, P).nslots * 10 <= best * 11)
+      c.push_back({make_slot_plan_p(N, P).nslots, P});
+  std::sort(c.begin(), c.end());
+  for (size_t i = 0; i < c.size() && out.size() < 3; ++i)
+    if (c[i].second != out[0]) out.push_back(c[i].second);
+  return out;
+}
+
+struct Scratch {
+  std::vector<void*> bufs;
+  hipError_t err = hipSuccess;
+  template <typename T>
+  T* get(size_t n) {
+    void* p = nullptr;
+    if (err == hipSuccess) err = hipMalloc(&p, std::max<size_t>(n * sizeof(T), 256));
+    if (p) bufs.push_back(p);
+    return static_cast<T*>(p);
+  }
+  ~Scratch() {
+    for (void* p : bufs) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int bsi_set_plan(bsi_handle h, int32_t n, int32_t P) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n < 8 || n > kMaxN) return fail(h, BSI_EINVAL, "stamp side %d outside [8, %d]", n, kMaxN);
+  if (P != 0 && (!supported_p(P) || !plan_valid(n, P)))
+    return fail(h, BSI_EINVAL, "plan P = %d is not available for N = %d", P, n);
+  h->plan_P[n] = P;
+  return BSI_OK;
+}
+
+int bsi_get_plan(bsi_handle h, int32_t n, int32_t* P, int32_t* slots) {
+  if (!h || !P) return BSI_EINVAL;
+  if (n < 8 || n > kMaxN) return fail(h, BSI_EINVAL, "stamp side %d outside [8, %d]", n, kMaxN);
+  *P = h->plan_P[n] > 0 ? h->plan_P[n] : make_slot_plan(n).P;
+  if (slots) *slots = make_slot_plan_p(n, *P).nslots;
+  return BSI_OK;
+}
+
+int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_chains,
+                 int32_t* chosen, float* ms_out) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n_sizes < 0 || (n_sizes > 0 && !sizes)) return fail(h, BSI_EINVAL, "sizes is NULL");
+  if (n_chains < 1 || n_chains > 16) return fail(h, BSI_EINVAL, "n_chains must be 1..16");
+  for (int i = 0; i < n_sizes; ++i)
+    if (sizes[i] < 8 || sizes[i] > kMaxN)
+      return fail(h, BSI_EUNSUPPORTED, "stamp side %d outside [8, %d]", sizes[i], kMaxN);
+  hipSetDevice(h->device);
+  hipStream_t s = h->own;
+  const int C = n_chains;
+  const int G = std::max(64, 16384 / C);
+  const float pixel_scale = 0.2f;
+  const float rs = profile_rscale(kProfExpHost, pixel_scale);
+  for (int i = 0; i < n_sizes; ++i) {
+    const int N = sizes[i];
+    const std::vector<int> cand = candidates(N);
+    int best_P = make_slot_plan(N).P;
+    float best_ms = -1.0f;
+    if (cand.size() > 1) {
+      Scratch sc;
+      const int64_t npx = (int64_t)N * N;
+      int max_bins = 0;
+      for (int P : cand) max_bins = std::max(max_bins, make_slot_plan_p(N, P).nbins);
+      float* data = sc.get<float>((size_t)G * npx);
+      float* psf = sc.get<float>(G);
+      float* sig = sc.get<float>(G);
+      float* ref = sc.get<float>((size_t)G * 2);
+      float* prm = sc.get<float>((size_t)G * 6);
+      float* init = sc.get<float>((size_t)G * C * 6);
+      int32_t* gidx = sc.get<int32_t>(G);
+      int64_t* off = sc.get<int64_t>(G);
+      int64_t* boff = sc.get<int64_t>(G);
+      float2* dh = sc.get<float2>((size_t)G * max_bins);
+      ChainState* st = sc.get<ChainState>((size_t)G * C);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (sc.err == hipSuccess) sc.err = hipEventCreate(&e0);
+      if (sc.err == hipSuccess) sc.err = hipEventCreate(&e1);
+      if (sc.err != hipSuccess) {
+        (void)hipGetLastError();
+        if (e0) (void)hipEventDestroy(e0);
+        return fail(h, BSI_ENOMEM, "autotune buffers for N = %d", N);
+      }
+      // one synthetic galaxy repeated: F = 1000, hlr 0.5", e = (0.1, -0.05), centred
+      std::vector<float> hp((size_t)G * 6), hi((size_t)G * C * 6), hpsf(G, 0.7f), hsig(G, 1.0f),
+          href((size_t)G * 2, 0.0f);
+      std::vector<int32_t> hg(G);
+      std::vector<int64_t> ho(G), hb(G);
+      for (int g = 0; g < G; ++g) {
+        const float p6[6] = {1000.0f, 0.5f, 0.1f, -0.05f, 0.0f, 0.0f};
+        std::copy(p6, p6 + 6, hp.begin() + 6 * g);
+        for (int c = 0; c < C; ++c) {
+          const float t6[6] = {3.0f, std::log10(0.5f), 0.1f, -0.05f, 0.0f, 0.0f};
+          std::copy(t6, t6 + 6, hi.begin() + ((size_t)g * C + c) * 6);
+        }
+        hg[g] = g;
+        ho[g] = g * npx;
+        hb[g] = (int64_t)g * max_bins;
+      }
+      hipError_t e = hipMemcpy(prm, hp.data(), hp.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(init, hi.data(), hi.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(psf, hpsf.data(), G * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(sig, hsig.data(), G * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(ref, href.data(), href.size() * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(gidx, hg.data(), G * 4, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(off, ho.data(), G * 8, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(boff, hb.data(), G * 8, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = launch_render(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale,
+                                            kProfExpHost, data, s);
+      HmcArgs a{};
+      a.dh = dh;
+      a.bin_off = boff;
+      a.gidx = gidx;
+      a.n_gal = G;
+      a.psf = psf;
+      a.sigma = sig;
+      a.ref_xy = ref;
+      a.init = init;
+      a.state = st;
+      a.N = N;
+      a.rscale = rs;
+      a.pscale_inv = 1.0f / pixel_scale;
+      a.prof = kProfExpHost;
+      a.C = C;
+      a.L = 20;
+      a.W = 1 << 20;
+      a.S = 0;
+      a.eps0 = 1e-3f;
+      a.delta = 0.8f;
+      a.mu = std::log(1e-2f);
+      a.lf_lo = -1.0f;
+      a.lf_hi = 9.0f;
+      a.ls_lo = -2.0f;
+      a.ls_hi = 1.0f;
+      a.sigma_d = 0.5f;
+      a.sigma_e = 0.3f;
+      a.t_stop = 1 << 20;
+      for (int P : cand) {
+        if (e != hipSuccess) break;
+        if (hmc_lds_bytes(N, C, P) > 160 * 1024) continue;
+        a.P = P;
+        e = launch_dft_bins(data, nullptr, gidx, G, off, boff, N, P, dh, nullptr, sig, s);
+        if (e == hipSuccess) {
+          a.n_steps = 0;
+          e = launch_hmc_init(a, G, s);
+        }
+        a.n_steps = a.L;
+        if (e == hipSuccess) e = launch_hmc_advance(a, G, s);     // warm
+        float best = -1.0f;
+        for (int r = 0; r < 5 && e == hipSuccess; ++r) {
+          e = hipEventRecord(e0, s);
+          if (e == hipSuccess) e = launch_hmc_advance(a, G, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float t = 0.0f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+          if (e == hipSuccess && (best < 0.0f || t < best)) best = t;
+        }
+        // the default plan (the first candidate) is kept unless another is
+        // at least 2 % faster
+        if (e == hipSuccess && (best_ms < 0.0f || best < 0.98f * best_ms)) {
+          best_ms = best;
+          best_P = P;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (e != hipSuccess) return hip_fail(h, e, "autotune");
+    }
+    h->plan_P[N] = best_P;
+    if (chosen) chosen[i] = best_P;
+    if (ms_out) ms_out[i] = best_ms;
+  }
+  return BSI_OK;
+}
+
+}  // extern "C"

@@ -22,8 +22,9 @@ inline float profile_rscale(int prof, float pixel_scale) {
 // ---- transform.hip ----
 size_t dft_bins_lds_bytes(int N);
 size_t render_lds_bytes(int N);
+// The data spectrum is written in the slot order of plan (N, P).
 hipError_t launch_dft_bins(const float* data, const double* model, const int32_t* gidx, int n,
-                           const int64_t* off, const int64_t* bin_off, int N, float2* out,
+                           const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
                            double* chi2, const float* sigma, hipStream_t s);
 hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
                          const int64_t* off, int N, float rscale, float pscale_inv, int prof,
@@ -34,7 +35,7 @@ hipError_t launch_render_f64(const float* params, const float* psf, const int32_
 
 // ---- likelihood.hip ----
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
-                         const float* params, const float* psf, const float* sigma, int N,
+                         const float* params, const float* psf, const float* sigma, int N, int P,
                          float rscale, float pscale_inv, int prof, int resid_mode,
                          const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
                          hipStream_t s);
@@ -83,6 +84,7 @@ struct HmcArgs {
   float* samples;         // [gal][C][S][6] or NULL
   float* trace;           // [gal][C][W+S][4] or NULL
   int N;
+  int P;                  // slot plan of N (iterations per super-row)
   float rscale, pscale_inv;
   int prof;
   int C, L, W, S, adapt, metric;
@@ -94,7 +96,9 @@ struct HmcArgs {
   int t_stop;             // iteration at which a chain stops (W + S)
 };
 
-size_t hmc_lds_bytes(int N, int C);
+size_t hmc_lds_bytes(int N, int C, int P);
+// Slot plans with a trajectory kernel specialised for stamp side N (0-terminated list of P).
+const int* hmc_fixed_plans(int N);
 hipError_t launch_hmc_init(const HmcArgs& a, int grid, hipStream_t s);
 hipError_t launch_hmc_advance(const HmcArgs& a, int grid, hipStream_t s);
 hipError_t launch_hmc_finalize(const ChainState* st, int n_gal, int C, int S, float* chain_stats,

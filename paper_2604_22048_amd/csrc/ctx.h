@@ -26,6 +26,7 @@ struct bsi_ctx {
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kAuxStreams] = {};
   DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts, shear_state;
+  int plan_P[129] = {};   // slot plan per stamp side (0: the default, fewest slots)
 };
 
 namespace bsi_host {

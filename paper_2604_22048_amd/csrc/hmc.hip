@@ -520,7 +520,7 @@ template <int PROF, bool INIT, int P, int MAXT, int NFIX>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
-  const SlotPlan sp = make_slot_plan(N);
+  const SlotPlan sp = make_slot_plan_p(N, P);
   const int wave = threadIdx.x / kWave;
   const Lds l = carve(g, sp, wave, a.C);
   build_col_table(g, sp, l.cols);
@@ -618,9 +618,9 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 }  // namespace
 
-size_t hmc_lds_bytes(int N, int C) {
+size_t hmc_lds_bytes(int N, int C, int P) {
   const Geom g = make_geom(N);
-  const SlotPlan sp = make_slot_plan(N);
+  const SlotPlan sp = make_slot_plan_p(N, P);
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
          sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C + sizeof(float) * 512 * C +
          sizeof(float2) * wave_table_len(g, sp) * C;
@@ -641,27 +641,39 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 }
 
 // Trajectory kernels specialised for the stamp sizes of the workloads
-// (compile-time geometry, fully unrolled bin loop); other sizes use the
-// generic kernel of their slot plan.
-template <int PROF, int NFIX>
-static void launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  launch_p<PROF, false, make_slot_plan(NFIX).P, NFIX>(a, grid, lds, s);
+// (compile-time geometry, fully unrolled bin loop), one per candidate plan
+// (the plans within 10 % of the fewest slots, at most three); other sizes and
+// plans use the generic kernel of their P.
+#define BSI_FIXED_PLANS(X) \
+  X(25, 2) X(25, 3) X(25, 6) X(32, 1) X(32, 2) X(32, 4) X(41, 2) X(41, 5) \
+  X(53, 6) X(53, 8) X(53, 5) X(73, 6) X(73, 8) X(73, 5) X(101, 5) X(101, 8)
+
+template <int PROF>
+static bool launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+#define BSI_CASE(NN, PP) \
+  if (a.N == NN && a.P == PP) { launch_p<PROF, false, PP, NN>(a, grid, lds, s); return true; }
+  BSI_FIXED_PLANS(BSI_CASE)
+#undef BSI_CASE
+  return false;
+}
+
+const int* hmc_fixed_plans(int N) {
+  static const int none[] = {0};
+  switch (N) {
+    case 25: { static const int p[] = {2, 3, 6, 0}; return p; }
+    case 32: { static const int p[] = {1, 2, 4, 0}; return p; }
+    case 41: { static const int p[] = {2, 5, 0}; return p; }
+    case 53: { static const int p[] = {6, 8, 5, 0}; return p; }
+    case 73: { static const int p[] = {6, 8, 5, 0}; return p; }
+    case 101: { static const int p[] = {5, 8, 0}; return p; }
+    default: return none;
+  }
 }
 
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (!INIT && a.C <= 4) {
-    switch (a.N) {
-      case 25: launch_fixed<PROF, 25>(a, grid, lds, s); return;
-      case 32: launch_fixed<PROF, 32>(a, grid, lds, s); return;
-      case 41: launch_fixed<PROF, 41>(a, grid, lds, s); return;
-      case 53: launch_fixed<PROF, 53>(a, grid, lds, s); return;
-      case 73: launch_fixed<PROF, 73>(a, grid, lds, s); return;
-      case 101: launch_fixed<PROF, 101>(a, grid, lds, s); return;
-      default: break;
-    }
-  }
-  switch (make_slot_plan(a.N).P) {
+  if (!INIT && a.C <= 4 && PROF == kProfExp && launch_fixed<PROF>(a, grid, lds, s)) return;
+  switch (a.P) {
     case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
     case 2: launch_p<PROF, INIT, 2>(a, grid, lds, s); break;
     case 3: launch_p<PROF, INIT, 3>(a, grid, lds, s); break;
@@ -675,7 +687,8 @@ static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 template <bool INIT>
 static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   if (a.n_gal <= 0) return hipSuccess;
-  const size_t lds = hmc_lds_bytes(a.N, a.C);
+  if (!plan_valid(a.N, a.P)) return hipErrorInvalidValue;
+  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
   else

@@ -48,24 +48,37 @@ struct SlotPlan {
   int nbins;          // nslots + nspec: length of the stored data spectrum
 };
 
-__host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
+// The slot plan of stamp side N with P iterations per super-row: R rows
+// per super-row (as many as P * 64 lanes hold, at most all rows), nsr
+// super-rows.  P must give R >= 1 (plan_valid).
+__host__ __device__ constexpr SlotPlan make_slot_plan_p(int N, int P) {
   const int nc = (N & 1) ? N : N - 1;
   const int rows = (nc - 1) / 2 + 1;
+  const int R = (64 * P) / nc;
+  const int Rr = R < rows ? R : rows;
+  const int nsr = Rr > 0 ? (rows + Rr - 1) / Rr : 0;
+  SlotPlan sp{Rr, P, nsr, nsr * P * 64, nsr * Rr, 0, 0};
+  sp.nspec = (N & 1) ? 0 : N + 1;
+  sp.nbins = sp.nslots + sp.nspec;
+  return sp;
+}
+
+__host__ __device__ constexpr bool plan_valid(int N, int P) {
+  return (64 * P) / ((N & 1) ? N : N - 1) >= 1;
+}
+
+// Default plan: the supported P with the fewest slots (ties: smaller P).
+__host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
   SlotPlan best{0, 0, 0, 1 << 30, 0, 0, 0};
   for (int k = 0; k < 7; ++k) {
     const int P = kPlanP[k];
 #ifdef BSI_PLAN_P
     if (P != BSI_PLAN_P) continue;
 #endif
-    const int R = (64 * P) / nc;
-    if (R < 1) continue;
-    const int Rr = R < rows ? R : rows;
-    const int nsr = (rows + Rr - 1) / Rr;
-    const int slots = nsr * P * 64;
-    if (slots < best.nslots) best = SlotPlan{Rr, P, nsr, slots, nsr * Rr, 0, 0};
+    if (!plan_valid(N, P)) continue;
+    const SlotPlan sp = make_slot_plan_p(N, P);
+    if (sp.nslots < best.nslots) best = sp;
   }
-  best.nspec = (N & 1) ? 0 : N + 1;
-  best.nbins = best.nslots + best.nspec;
   return best;
 }
 
@@ -300,8 +313,8 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   for (int i = 0; i < P; ++i) wky[i] = 0.f;
   const float2* dp = dh + lane;
   if constexpr (NFIX > 0) {
-    constexpr SlotPlan spc = make_slot_plan(NFIX);
-    static_assert(spc.P == P, "slot plan of NFIX must use P iterations");
+    constexpr SlotPlan spc = make_slot_plan_p(NFIX, P);
+    static_assert(spc.R >= 1, "P too small for NFIX");
     // software pipeline: the LDS reads of the next bin are issued before the
     // arithmetic of the current one
     float2 Dn = dp[0];

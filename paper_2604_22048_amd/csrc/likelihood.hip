@@ -15,7 +15,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
     double* __restrict__ loglik, float* __restrict__ grad, uint32_t* __restrict__ status) {
   extern __shared__ float4 smem4[];
   const Geom g = make_geom(N);
-  const SlotPlan sp = make_slot_plan(N);
+  const SlotPlan sp = make_slot_plan_p(N, P);
   const int gal = gidx[blockIdx.x];
   float2* dh = reinterpret_cast<float2*>(smem4);
   float* atab = reinterpret_cast<float*>(dh + ((sp.nbins + 1) & ~1));
@@ -63,9 +63,9 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   }
 }
 
-static size_t loglik_lds_bytes(int N) {
+static size_t loglik_lds_bytes(int N, int P) {
   const Geom g = make_geom(N);
-  const SlotPlan sp = make_slot_plan(N);
+  const SlotPlan sp = make_slot_plan_p(N, P);
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
          sizeof(float4) * sp.P * 64 + sizeof(float4) * sp.ymax + sizeof(float2) * (2 * g.ntab + 1) +
          16 + sizeof(float) * 64 * 8;
@@ -94,13 +94,13 @@ static void launch_loglik_p(int P, dim3 grid, size_t lds, hipStream_t s, const f
 }
 
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
-                         const float* params, const float* psf, const float* sigma, int N,
+                         const float* params, const float* psf, const float* sigma, int N, int P,
                          float rscale, float pscale_inv, int prof, int resid_mode,
                          const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  const size_t lds = loglik_lds_bytes(N);
-  const int P = make_slot_plan(N).P;
+  if (!plan_valid(N, P)) return hipErrorInvalidValue;
+  const size_t lds = loglik_lds_bytes(N, P);
   const dim3 grid(n);
   if (prof == kProfExp) {
     if (resid_mode)

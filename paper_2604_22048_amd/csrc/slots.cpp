@@ -93,6 +93,7 @@ struct Slot {
 
 struct SizeClass {
   int N;
+  int P;                           // slot plan (the handle's at creation)
   int64_t stamp_bytes, bin_bytes;
   hipEvent_t ev_beg = nullptr, ev_end = nullptr;   // this size's last advance launch
   double tau = -1.0;               // measured milliseconds per iteration (-1: unknown)
@@ -229,14 +230,15 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
       delete sv;
       return fail(h, BSI_EINVAL, "sizes must be distinct and in 8..%d", kMaxN);
     }
-    if (hmc_lds_bytes(N, sv->C) > 160 * 1024) {
+    SizeClass c;
+    c.N = N;
+    c.P = h->plan_P[N] > 0 ? h->plan_P[N] : make_slot_plan(N).P;
+    if (hmc_lds_bytes(N, sv->C, c.P) > 160 * 1024) {
       delete sv;
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", N, hc.n_chains);
     }
-    SizeClass c;
-    c.N = N;
     c.stamp_bytes = align_up((int64_t)N * N * 4);
-    c.bin_bytes = align_up((int64_t)make_slot_plan(N).nbins * 8);
+    c.bin_bytes = align_up((int64_t)make_slot_plan_p(N, c.P).nbins * 8);
     min_var = std::min(min_var, c.stamp_bytes + c.bin_bytes);
     max_var = std::max(max_var, c.stamp_bytes + c.bin_bytes);
     sv->cls.push_back(c);
@@ -454,11 +456,12 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     hipError_t x = hipSuccess;
     if (!k.fresh.empty()) {
       x = launch_dft_bins(reinterpret_cast<const float*>(sv->arena), nullptr, fresh,
-                          (int)k.fresh.size(), sv->arr.off, sv->arr.bin_off, k.N,
+                          (int)k.fresh.size(), sv->arr.off, sv->arr.bin_off, k.N, k.P,
                           reinterpret_cast<float2*>(sv->arena), nullptr, sv->arr.sigma, st);
       if (x != hipSuccess) return x;
       HmcArgs a = base;
       a.N = k.N;
+      a.P = k.P;
       a.gidx = fresh;
       a.n_gal = (int)k.fresh.size();
       a.n_steps = 0;
@@ -467,6 +470,7 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     }
     HmcArgs a = base;
     a.N = k.N;
+    a.P = k.P;
     a.gidx = res;
     a.n_gal = (int)k.resident.size();
     a.n_steps = iters[i] * sv->L;

@@ -26,8 +26,8 @@ __device__ __forceinline__ void build_twiddles(float2* tw, int N) {
 // writes chi2[g] = sum over pixels of (data - model)^2 (float64 throughout).
 __global__ void __launch_bounds__(256) dft_bins_kernel(
     const float* __restrict__ data, const double* __restrict__ model, const int32_t* __restrict__ gidx,
-    const int64_t* __restrict__ off, const int64_t* __restrict__ bin_off, int N, float2* __restrict__ out,
-    double* __restrict__ chi2) {
+    const int64_t* __restrict__ off, const int64_t* __restrict__ bin_off, int N, int P,
+    float2* __restrict__ out, double* __restrict__ chi2) {
   __shared__ double red[4];
   extern __shared__ float4 smem4[];
   const Geom g = make_geom(N);
@@ -76,7 +76,7 @@ __global__ void __launch_bounds__(256) dft_bins_kernel(
   __syncthreads();
   // pass 2 (along x) at every stored bin: the slot layout of the k-space
   // loop (row 0 scaled by 1/sqrt 2, unused slots zero), then the Nyquist bins
-  const SlotPlan sp = make_slot_plan(N);
+  const SlotPlan sp = make_slot_plan_p(N, P);
   float2* dst = out + bin_off[gal];
   for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) {
     int u, v;
@@ -212,7 +212,7 @@ size_t render_lds_bytes(int N) {
 }
 
 hipError_t launch_dft_bins(const float* data, const double* model, const int32_t* gidx, int n,
-                           const int64_t* off, const int64_t* bin_off, int N, float2* out,
+                           const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
                            double* chi2, const float* sigma, hipStream_t s) {
   (void)sigma;
   if (n <= 0) return hipSuccess;
@@ -220,7 +220,7 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
   (void)hipFuncSetAttribute((const void*)dft_bins_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(dft_bins_kernel, dim3(n), dim3(256), lds, s, data, model, gidx, off, bin_off,
-                     N, out, chi2);
+                     N, P, out, chi2);
   return hipGetLastError();
 }
 

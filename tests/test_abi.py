@@ -105,6 +105,8 @@ def test_no_device_and_null_handle_paths(native):
     assert lib.bsi_shear_hmc(None, 1, 1, None, None, None, None, None, None, None, None, None,
                              None, None) == -1
     assert lib.bsi_slots_create(None, None, None, None) == -1
+    assert lib.bsi_set_plan(None, 53, 6) == -1
+    assert lib.bsi_autotune(None, 0, None, 4, None, None) == -1
     assert lib.bsi_slots_advance(None, 1) == -1
     assert lib.bsi_slots_get_info(None, None) == -1
     lib.bsi_slots_destroy(None)

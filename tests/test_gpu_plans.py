@@ -1,0 +1,105 @@
+"""Slot plans: every plan with a specialised trajectory kernel (and a generic
+one) keeps log L, gradient and chains at oracle parity; the autotuner
+returns valid plans and the library works with them."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import hmc, render                              # noqa: E402
+from workloads import gen                                    # noqa: E402
+from tests import synth                                      # noqa: E402
+
+PS = gen.PIXEL_SCALE
+PLANS = {25: (2, 3, 6), 53: (6, 8, 5, 4), 101: (5, 8)}
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsi(device):
+    from paper_2604_22048_amd import api
+    yield api
+    for n in range(8, 129):
+        api.set_plan(n, 0)
+
+
+def _setup(bsi, torch, N, G, C, seed):
+    t, params, data, off = synth.make_population("uneven", n_gal=G, seed=seed, sizes=[N] * G)
+    init = synth.init_positions(t, params, data, off, C, seed=seed + 1)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=PS)
+    return t, params, data, off, init, b
+
+
+@pytest.mark.parametrize("N", sorted(PLANS))
+def test_every_plan_at_parity(bsi, N):
+    import torch
+    G, C, L, S = 2, 2, 10, 3
+    t, params, data, off, init, b = _setup(bsi, torch, N, G, C, 300 + N)
+    dev = torch.tensor(data).cuda()
+    ref = torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32).cuda()
+    p32 = params.astype(np.float32)
+    for P in PLANS[N]:
+        _log(f"plan N={N} P={P}")
+        bsi.set_plan(N, P)
+        assert bsi.get_plan(N)[0] == P
+        ll, gr, _ = bsi.loglik_grad(b, dev, torch.tensor(p32).cuda())
+        ll, gr = ll.cpu().numpy(), gr.cpu().numpy()
+        cfg = bsi.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False,
+                            step_size=0.003, jitter=0.1, seed=11)
+        smp, _, _ = bsi.hmc_sample(b, dev, ref, torch.tensor(init, dtype=torch.float32).cuda(), cfg)
+        smp = smp.cpu().numpy()
+        for i in range(G):
+            d = data[off[i]:off[i] + N * N].reshape(N, N).astype(np.float64)
+            psf = float(np.float32(t.psf_fwhm[i]))
+            rll, rg = render.loglik_grad(d, p32[i].astype(np.float64), N, PS, psf, float(t.sigma[i]))
+            assert abs(ll[i] - rll) <= 1e-6 * abs(rll), (N, P, i)
+            _, dT = render.spectrum(p32[i].astype(np.float64), N, PS, psf, derivs=True)
+            sc = np.array([math.sqrt(np.sum(render.synthesize(dT[j], N) ** 2)) / t.sigma[i]
+                           for j in range(6)])
+            assert np.all(np.abs(gr[i] - rg) <= 1e-4 * (np.abs(rg) + sc)), (N, P, i)
+            gal = synth.oracle_galaxy(t, data, off, i)
+            r = hmc.run_chain(hmc.galaxy_potential(gal), init[i, 0].astype(np.float32), 11, i * C,
+                              L, 0, S, 0.003, adapt=False, jitter=0.1)
+            k = 0
+            while k < S and np.max(np.abs(smp[i, 0, k] - r["samples"][k])) <= 1e-4:
+                k += 1
+            if k < S:      # only an accept decision taken differently may end the agreement
+                moved_g = k == 0 or np.any(smp[i, 0, k] != smp[i, 0, k - 1])
+                moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+                assert moved_g != moved_o, (N, P, i, k)
+    bsi.set_plan(N, 0)
+
+
+def test_autotune_and_tuned_run(bsi):
+    import torch
+    _log("autotune")
+    res = bsi.autotune([25, 41, 53, 73, 101], n_chains=4)
+    for N, (P, ms) in res.items():
+        assert P in (1, 2, 3, 4, 5, 6, 8)
+        assert bsi.get_plan(N)[0] == P
+        assert ms is None or ms > 0
+    _log(f"tuned plans {res}")
+    # a mixed batch with the tuned plans: graph and forked forms agree, chains finite
+    sizes = [25, 41, 53, 73, 101]
+    t, params, data, off = synth.make_population("uneven", n_gal=5, seed=77, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, 2, seed=78)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=PS)
+    ref = torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32).cuda()
+    base = dict(n_chains=2, n_leapfrog=8, n_warmup=4, n_samples=4, adapt=True, step_size=0.01,
+                seed=3)
+    a = bsi.hmc_sample(b, torch.tensor(data).cuda(), ref, torch.tensor(init, dtype=torch.float32).cuda(),
+                       bsi.HmcConfig(**base))[0].cpu().numpy()
+    d = bsi.hmc_sample(b, torch.tensor(data).cuda(), ref, torch.tensor(init, dtype=torch.float32).cuda(),
+                       bsi.HmcConfig(use_graph=False, **base))[0].cpu().numpy()
+    assert np.array_equal(a, d) and np.all(np.isfinite(a))
+    for N in res:
+        bsi.set_plan(N, 0)

@@ -196,3 +196,40 @@ def test_gradient_central_differences_on_256_parameter_sets():
             worst = max(worst, err)
             assert err <= 1e-5, (i, j, fd, g[j], scale[j])
     assert worst > 0.0
+
+
+def test_every_slot_plan_tiles_the_half_plane():
+    """For every stamp side and every supported plan P, the slots (row 0
+    whole, rows 1..hc) and the Nyquist bins cover the odd core's half plane
+    exactly once; the mirrors complete the DFT grid.  Host restatement of the
+    slot layout (R = floor(64 P / nc) rows per super-row, lane l of iteration
+    i holding slot l + 64 i)."""
+    for N in range(8, 129):
+        nc = N if N % 2 else N - 1
+        hc = (nc - 1) // 2
+        rows = hc + 1
+        for P in (1, 2, 3, 4, 5, 6, 8):
+            R = (64 * P) // nc
+            if R < 1:
+                continue
+            R = min(R, rows)
+            nsr = -(-rows // R)
+            seen = set()
+            for sr in range(nsr):
+                for sl in range(P * 64):
+                    if sl >= R * nc:
+                        continue
+                    ro, col = divmod(sl, nc)
+                    v = sr * R + ro
+                    if v > hc:
+                        continue
+                    u = col - hc
+                    assert (u, v) not in seen
+                    seen.add((u, v))
+            assert len(seen) == nc * rows, (N, P)
+            # row 0 holds each +-u pair and DC; rows 1..hc with their mirrors: the core
+            full = set()
+            for (u, v) in seen:
+                full.add((u, v))
+                full.add((-u, -v))
+            assert len(full) == nc * nc, (N, P)
