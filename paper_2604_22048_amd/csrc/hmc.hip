@@ -58,6 +58,17 @@ __device__ __forceinline__ void fill_xy_full(const Geom& g, const float* __restr
   wave_lds_sync();
 }
 
+// 10^x for arguments bounded by the prior support (|x| < 30): 2^(x log2 10)
+// with the rounding errors of the product and of the constant carried by a
+// first-order correction (relative error a few 1e-7).
+__device__ __forceinline__ float exp10_bounded(float x) {
+  const float c = 3.32192802429199219f;           // log2(10) rounded to float
+  const float c_lo = 7.05953713e-8f;              // log2(10) - c
+  const float y = x * c;
+  const float e = fmaf(x, c, -y) + x * c_lo;
+  return __builtin_amdgcn_exp2f(y) * fmaf(e, 0.693147180559945309f, 1.0f);
+}
+
 struct Prior {
   float lf_lo, lf_hi, ls_lo, ls_hi, sd, se;
   float isd2, ise2;     // 1 / sd^2, 1 / se^2
@@ -87,7 +98,7 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& 
     E = e1 * e1 + e2 * e2;
   }
   // F = 10^t0 and s = 10^t1 in one lane-parallel evaluation
-  const float e10 = exp10f(lane_id() == 0 ? t0 : t1);
+  const float e10 = exp10_bounded(lane_id() == 0 ? t0 : t1);
   const float F = bcast(e10, 0), s = bcast(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
   fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
@@ -225,9 +236,10 @@ struct Lds {
 };
 
 // Per-wave tables, in float2 units: Ym (ymax float4, first so that it is
-// 16-byte aligned), X (ntab), Yf (ntab); the length is even.
+// 16-byte aligned), X (ntab + 1, padded to ntab + 2), Yf (ntab); the length
+// is even.
 __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp) {
-  return 2 * sp.ymax + 2 * g.ntab;
+  return 2 * sp.ymax + 2 * g.ntab + 2;
 }
 
 // LDS: [data spectrum | atab | column table | C chain records | C reduction
@@ -245,7 +257,7 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave
   float2* w0 = reinterpret_cast<float2*>(red0 + 512 * C) + wave_table_len(g, sp) * wave;
   l.Ym = reinterpret_cast<float4*>(w0);
   l.X = w0 + 2 * sp.ymax;
-  l.Yf = l.X + g.ntab;
+  l.Yf = l.X + g.ntab + 2;
   return l;
 }
 
@@ -363,7 +375,8 @@ __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_
 // chain state lives in the wave's LDS record and is read and written (by
 // lane 0) only at trajectory boundaries.
 struct Hot {
-  float th[6], p[6], g[6], im[6];
+  float th[6], p[6], g[6];
+  float eim[6];        // eps_t * inverse mass: the drift coefficients of this trajectory
   double Uth;
   float eps_t;
   int l, ok, t;
@@ -384,10 +397,11 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     h.th[j] = cs->th[j];
     h.p[j] = cs->p[j];
     h.g[j] = cs->g[j];
-    h.im[j] = cs->inv_mass[j];
   }
   h.Uth = cs->Uth;
   h.eps_t = cs->eps_t;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) h.eim[j] = h.eps_t * cs->inv_mass[j];
   h.l = cs->l;
   h.ok = cs->ok;
   h.t = cs->t;
@@ -404,10 +418,12 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
       double ke = 0.0;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
-        h.p[j] = z[j] * __builtin_amdgcn_rsqf(h.im[j]);
-        ke += (double)(h.im[j] * h.p[j] * h.p[j]);
+        const float im = cs->inv_mass[j];
+        h.p[j] = z[j] * __builtin_amdgcn_rsqf(im);
+        ke += (double)(im * h.p[j] * h.p[j]);
         h.th[j] = cs->theta[j];
         h.g[j] = cs->grad[j];
+        h.eim[j] = h.eps_t * im;
       }
       const double H0 = cs->U + 0.5 * ke;
       lane0_sync();
@@ -421,7 +437,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
       for (int j = 0; j < 6; ++j) h.p[j] -= 0.5f * h.eps_t * h.g[j];
     }
 #pragma unroll
-    for (int j = 0; j < 6; ++j) h.th[j] += h.eps_t * h.im[j] * h.p[j];
+    for (int j = 0; j < 6; ++j) h.th[j] += h.eim[j] * h.p[j];
     uint32_t st = 0;
     // the potential itself is needed only at the end of the trajectory
     if (h.l + 1 == a.L)
@@ -441,7 +457,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     for (int j = 0; j < 6; ++j) h.p[j] -= 0.5f * h.eps_t * h.g[j];
     double ke = 0.0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) ke += (double)(h.im[j] * h.p[j] * h.p[j]);
+    for (int j = 0; j < 6; ++j) ke += (double)(cs->inv_mass[j] * h.p[j] * h.p[j]);
     const double dH = h.Uth + 0.5 * ke - cs->H0;
     const bool finite = isfinite(dH);
     const bool accept = h.ok && finite && log((double)cs->u_acc) < -dH;

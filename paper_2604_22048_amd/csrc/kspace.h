@@ -168,15 +168,15 @@ template <int P>
 struct LaneCols {
   float kx[P];       // k_x of the lane's column in iteration i (0 if unused)
   float rok[P];      // row offset * kstep
-  int xi[P];         // index into the X table (u + h), or -1 if the slot is unused
+  int xi[P];         // index into the X table (u + h), or ntab (zero entry) if the slot is unused
   int yo[P];         // row offset within the super-row
 };
 
 // Per-slot column table shared by the workgroup: entry (i, lane) =
-// {k_x, row offset * kstep, X index (-1 if unused), row offset}.
+// {k_x, row offset * kstep, X index (ntab, a zero entry, if unused), row offset}.
 __device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& sp, float4* tab) {
   for (int t = threadIdx.x; t < sp.P * 64; t += blockDim.x) {
-    float4 e = make_float4(0.f, 0.f, __int_as_float(-1), __int_as_float(0));
+    float4 e = make_float4(0.f, 0.f, __int_as_float(g.ntab), __int_as_float(0));
     if (t < sp.R * g.nc) {
       const int ro = t / g.nc;
       const int u = t - ro * g.nc - g.hc;
@@ -203,7 +203,7 @@ __device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
 }
 
 // Per-wave LDS tables of one evaluation.
-//   X [ntab]  : F a(u) exp(-i k_u dx),   u = -h..h  (k_u dx = 2 pi u dx / N)
+//   X [ntab+1]: F a(u) exp(-i k_u dx),   u = -h..h  (k_u dx = 2 pi u dx / N), then 0
 //   Ym[ymax]  : {a(v) exp(-i k_v dy), k_v, k_v^2} for rows v = 0..ymax-1 (row 0
 //               scaled by 1/sqrt 2, rows > hc zero)
 //   Yf[ntab]  : a(v) exp(-i k_v dy),     v = -h..h (even N only, for the Nyquist bins)
@@ -225,6 +225,7 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
     const float2 w = cis_neg_rev((float)(t - g.h) * rx);
     X[t] = make_float2(a * w.x, a * w.y);
   }
+  if (lane == 0) X[g.ntab] = make_float2(0.f, 0.f);
   const bool even = (g.N & 1) == 0;
   for (int v = lane; v < sp.ymax; v += kWave) {
     float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -298,7 +299,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   const float4* yp[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    const float2 x = lc.xi[i] >= 0 ? X[lc.xi[i]] : make_float2(0.f, 0.f);
+    const float2 x = X[lc.xi[i]];
     xr[i] = x.x;
     xim[i] = x.y;
     kx2[i] = lc.kx[i] * lc.kx[i];

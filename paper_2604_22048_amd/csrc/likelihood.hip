@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   float4* cols = reinterpret_cast<float4*>(atab + ((g.ntab + 3) & ~3));
   float4* Ym = cols + sp.P * 64;
   float2* X = reinterpret_cast<float2*>(Ym + sp.ymax);
-  float2* Yf = X + g.ntab;
+  float2* Yf = X + g.ntab + 2;
   float* red = reinterpret_cast<float*>(Yf + g.ntab + 1);
   red = reinterpret_cast<float*>((reinterpret_cast<uintptr_t>(red) + 15) & ~uintptr_t(15));
   build_col_table(g, sp, cols);
@@ -67,7 +67,7 @@ static size_t loglik_lds_bytes(int N, int P) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
-         sizeof(float4) * sp.P * 64 + sizeof(float4) * sp.ymax + sizeof(float2) * (2 * g.ntab + 1) +
+         sizeof(float4) * sp.P * 64 + sizeof(float4) * sp.ymax + sizeof(float2) * (2 * g.ntab + 3) +
          16 + sizeof(float) * 64 * 8;
 }
 
