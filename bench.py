@@ -256,7 +256,7 @@ def make_request_pool(api, torch, per_size, seed_offset=0):
 
 
 def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, iters_per_tick=15,
-                budget=4 << 30, extra_rates=(), pace=True, log=None):
+                budget=4 << 30, extra_rates=(), pace=True, split=4, log=None):
     """Poisson request stream at `rate` for `window_s` seconds of arrivals
     (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
     warmup + n_draws iterations of 20 leapfrog steps each), then the capacity:
@@ -270,9 +270,10 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
     pool = make_request_pool(api, torch, 512)
     w = np.array(cfg.extra["size_weights"])
 
-    def run(arr, tag, ess, paced):
+    def run(arr, tag, ess, paced, wpc=0):
         sizes = np.random.default_rng(seed + arr.shape[0]).choice(np.array(SERVING_SIZES),
                                                                   size=arr.shape[0], p=w)
+        hc.waves_per_chain = wpc
         srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget, pace=paced)
         r = serve.serve(srv, pool, arr, sizes, iters_per_tick, ess=ess, progress=log)
         srv.close()
@@ -306,6 +307,16 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
         rp, sp = run(arr, f"{rate:.0f}/s paced", False, True)
         out["paced_by_size"] = {"galaxies_per_s": round(rp.n_done / rp.wall, 1), **lat_stats(rp),
                                 "ticks": rp.ticks, "p50_ms_by_size": by_size(rp, sp)}
+    if split:
+        # chains split over waves run on the default slot plans
+        for N in SERVING_SIZES:
+            api.set_plan(N, 0)
+        run(np.zeros(64), "warm split", False, False, split)
+        rs, ss = run(arr, f"{rate:.0f}/s {split} waves per chain", False, False, split)
+        for N, (P, _) in plans.items():
+            api.set_plan(N, P)
+        out["split_chains"] = {"waves_per_chain": split, "galaxies_per_s": round(rs.n_done / rs.wall, 1),
+                               **lat_stats(rs), "ticks": rs.ticks, "p50_ms_by_size": by_size(rs, ss)}
     rc, _ = run(np.zeros(cap_requests), "capacity", False, False)
     cap = rc.n_done / rc.wall
     out["capacity_req_per_s"] = round(cap, 1)

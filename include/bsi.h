@@ -174,6 +174,14 @@ typedef struct {
                                 NULL: per iteration {base step size, dH, acceptance
                                 statistic min(1, exp(-dH)) (0 if rejected for support or
                                 non-finiteness), accepted (0 or 1)}                          */
+  int32_t waves_per_chain;   /* 0 or 1: one wave per chain (throughput); 2 or 4: up to that
+                                many waves share each chain's evaluations (latency), for the
+                                workload stamp sizes with their default slot plan and the
+                                exponential profile (fewer where a size has fewer super-rows
+                                or n_chains * waves would exceed 4).  The sums are split
+                                differently, so samples agree with the one-wave form to
+                                float32 rounding, and bitwise between calls with equal
+                                settings                                                     */
 } bsi_hmc_cfg;
 
 /*

@@ -42,7 +42,8 @@ class HmcCfg(C.Structure):
                 ("n_samples", C.c_int32), ("adapt", C.c_int32), ("metric", C.c_int32),
                 ("step_size", C.c_float), ("target_accept", C.c_float), ("jitter", C.c_float),
                 ("form", C.c_int32), ("iters_per_launch", C.c_int32), ("use_graph", C.c_int32),
-                ("seed", C.c_uint64), ("uid_base", C.c_uint64), ("trace", C.c_void_p)]
+                ("seed", C.c_uint64), ("uid_base", C.c_uint64), ("trace", C.c_void_p),
+                ("waves_per_chain", C.c_int32)]
 
 
 class TruePrior(C.Structure):

@@ -154,6 +154,7 @@ class HmcConfig:
     use_graph: bool = True
     seed: int = 0
     uid_base: int = 0
+    waves_per_chain: int = 1
 
     def c(self, trace=None) -> N.HmcCfg:
         return N.HmcCfg(int(self.n_chains), int(self.n_leapfrog), int(self.n_warmup),
@@ -161,7 +162,7 @@ class HmcConfig:
                         float(self.step_size), float(self.target_accept), float(self.jitter),
                         int(self.form), int(self.iters_per_launch), int(bool(self.use_graph)),
                         int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.uid_base) & 0xFFFFFFFFFFFFFFFF,
-                        None if trace is None else trace.data_ptr())
+                        None if trace is None else trace.data_ptr(), int(self.waves_per_chain))
 
 
 def hmc_sample(batch: Batch, data: torch.Tensor, ref_xy: torch.Tensor, init: torch.Tensor,

@@ -294,6 +294,8 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     return fail(h, BSI_EINVAL, "unknown form %d", cfg->form);
   if (cfg->form == BSI_FORM_BATCHED && cfg->iters_per_launch < 1)
     return fail(h, BSI_EINVAL, "iters_per_launch must be >= 1");
+  if (cfg->waves_per_chain < 0 || cfg->waves_per_chain > 4)
+    return fail(h, BSI_EINVAL, "waves_per_chain must be 0..4");
   if (!(ip->log10f_lo < ip->log10f_hi) || !(ip->log10s_lo < ip->log10s_hi) || !(ip->sigma_d > 0) ||
       !(ip->sigma_e > 0))
     return fail(h, BSI_EINVAL, "invalid interim prior");
@@ -309,7 +311,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   const int C = cfg->n_chains;
   if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
   for (const ClassRange& c : p.classes) {
-    if (hmc_lds_bytes(c.N, C, c.P) > 160 * 1024)
+    if (hmc_lds_bytes(c.N, C, c.P, hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain)) > 160 * 1024)
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", c.N, C);
   }
 
@@ -347,6 +349,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   a.sigma_d = ip->sigma_d;
   a.sigma_e = ip->sigma_e;
   a.t_stop = cfg->n_warmup + cfg->n_samples;
+  a.wpc = 1;
 
   for (const ClassRange& c : p.classes) {
     HmcArgs ac = a;
@@ -383,6 +386,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       HmcArgs ac = a;
       ac.N = c.N;
       ac.P = c.P;
+      ac.wpc = hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain);
       ac.gidx = gidx_ptr(h, c);
       ac.n_gal = c.count;
       ac.n_steps = ipl * a.L;

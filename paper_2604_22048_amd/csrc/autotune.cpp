@@ -177,9 +177,10 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
       a.sigma_d = 0.5f;
       a.sigma_e = 0.3f;
       a.t_stop = 1 << 20;
+      a.wpc = 1;
       for (int P : cand) {
         if (e != hipSuccess) break;
-        if (hmc_lds_bytes(N, C, P) > 160 * 1024) continue;
+        if (hmc_lds_bytes(N, C, P, 1) > 160 * 1024) continue;
         a.P = P;
         e = launch_dft_bins(data, nullptr, gidx, G, off, boff, N, P, dh, nullptr, sig, s);
         if (e == hipSuccess) {

@@ -85,6 +85,7 @@ struct HmcArgs {
   float* trace;           // [gal][C][W+S][4] or NULL
   int N;
   int P;                  // slot plan of N (iterations per super-row)
+  int wpc;                // waves per chain of the trajectory kernel (hmc_split_waves)
   float rscale, pscale_inv;
   int prof;
   int C, L, W, S, adapt, metric;
@@ -96,7 +97,12 @@ struct HmcArgs {
   int t_stop;             // iteration at which a chain stops (W + S)
 };
 
-size_t hmc_lds_bytes(int N, int C, int P);
+size_t hmc_lds_bytes(int N, int C, int P, int W);
+// Waves per chain for stamp side N, C chains and plan P when up to max_w are
+// requested: a power of two <= max_w, <= the plan's super-rows, C W <= 4, and
+// 1 unless the profile is exponential and P is N's default plan with a
+// specialised kernel.
+int hmc_split_waves(int N, int C, int P, int prof, int max_w);
 // Slot plans with a trajectory kernel specialised for stamp side N (0-terminated list of P).
 const int* hmc_fixed_plans(int N);
 hipError_t launch_hmc_init(const HmcArgs& a, int grid, hipStream_t s);

@@ -37,6 +37,8 @@ struct GalCtx {
   float4* Ym;      // X and Yf as full x and y tables
   float2* Yf;
   float* red;      // per-wave reduction scratch (2 KiB)
+  int part;        // this wave's index among the W waves of its chain
+  float* xch;      // the chain's partial-sum exchange area (2 x W x 12 floats)
   float norm;      // 1 / (N^2 sigma^2)
   float rscale;
   float refx, refy;
@@ -83,9 +85,10 @@ __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
 // Outside the support U = +inf and the gradient is evaluated at the nearest
 // admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
 // trajectory can continue (it is rejected anyway).
-template <int PROF, int P, bool CHI2 = true, int NFIX = 0>
+template <int PROF, int P, bool CHI2 = true, int NFIX = 0, int W = 1>
 __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& lc, const Prior& pr,
-                                            const float* th, float* gU, uint32_t& status) {
+                                            const float* th, float* gU, uint32_t& status,
+                                            float* xbuf = nullptr) {
   const bool inside = in_support(th, pr);
   float t0 = fminf(fmaxf(th[0], pr.lf_lo), pr.lf_hi);
   float t1 = fminf(fmaxf(th[1], pr.ls_lo), pr.ls_hi);
@@ -103,8 +106,8 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& 
   const float dx = c.refx + th[4], dy = c.refy + th[5];
   fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
   const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
-  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh,
-                                                           c.red);
+  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf,
+                                                              sh, c.red, c.part, xbuf);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
   const float isd2 = pr.isd2, ise2 = pr.ise2;
   const float cpri = -4.0f * sh.inv1mE - ise2;
@@ -233,6 +236,7 @@ struct Lds {
   float2* X;
   float4* Ym;
   float2* Yf;
+  float* xch0;        // exchange areas of split chains (2 x W x 12 floats per chain)
 };
 
 // Per-wave tables, in float2 units: Ym (ymax float4, first so that it is
@@ -242,8 +246,8 @@ __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp)
   return 2 * sp.ymax + 2 * g.ntab + 2;
 }
 
-// LDS: [data spectrum | atab | column table | C chain records | C reduction
-// scratches | C table sets]
+// LDS: [data spectrum | atab | column table | NW chain records | NW reduction
+// scratches | NW table sets | exchange areas] for NW waves per block.
 __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave, int C) {
   extern __shared__ float4 smem4[];
   Lds l;
@@ -254,10 +258,12 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave
   l.cs = cs0 + wave;
   float* red0 = reinterpret_cast<float*>(cs0 + C);
   l.red = red0 + 512 * wave;
-  float2* w0 = reinterpret_cast<float2*>(red0 + 512 * C) + wave_table_len(g, sp) * wave;
+  float2* wt = reinterpret_cast<float2*>(red0 + 512 * C);
+  float2* w0 = wt + wave_table_len(g, sp) * wave;
   l.Ym = reinterpret_cast<float4*>(w0);
   l.X = w0 + 2 * sp.ymax;
   l.Yf = l.X + g.ntab + 2;
+  l.xch0 = reinterpret_cast<float*>(wt + wave_table_len(g, sp) * C);
   return l;
 }
 
@@ -385,12 +391,13 @@ struct Hot {
 
 __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
-template <int PROF, int P, int NFIX>
+template <int PROF, int P, int NFIX, int W>
 __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
                               const Prior& pr, ChainState* cs, float* samples_chain,
                               float* trace_chain) {
   const int lane = lane_id();
   const uint32_t uid = cs->uid;
+  int nev = 0;           // evaluations so far (alternates the exchange buffers)
   Hot h;
 #pragma unroll
   for (int j = 0; j < 6; ++j) {
@@ -440,10 +447,12 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     for (int j = 0; j < 6; ++j) h.th[j] += h.eim[j] * h.p[j];
     uint32_t st = 0;
     // the potential itself is needed only at the end of the trajectory
+    float* xbuf = W > 1 ? c.xch + (nev & 1) * (12 * W) : nullptr;
+    ++nev;
     if (h.l + 1 == a.L)
-      h.Uth = potential<PROF, P, true, NFIX>(c, lc, pr, h.th, h.g, st);
+      h.Uth = potential<PROF, P, true, NFIX, W>(c, lc, pr, h.th, h.g, st, xbuf);
     else
-      h.Uth = potential<PROF, P, false, NFIX>(c, lc, pr, h.th, h.g, st);
+      h.Uth = potential<PROF, P, false, NFIX, W>(c, lc, pr, h.th, h.g, st, xbuf);
     if (h.t >= a.W) h.status |= st;     // warmup probes are not reported
     if (!in_support(h.th, pr)) h.ok = 0;
     h.l += 1;
@@ -532,13 +541,16 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 #endif
 
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
-template <int PROF, bool INIT, int P, int MAXT, int NFIX>
+// W > 1: each chain is evaluated by W waves (split evaluation; advance only).
+template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
+  static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int wave = threadIdx.x / kWave;
-  const Lds l = carve(g, sp, wave, a.C);
+  const int cw = wave / W, part = wave % W;      // chain of the galaxy, part of the chain
+  const Lds l = carve(g, sp, wave, a.C * W);
   build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
                  1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
@@ -547,7 +559,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     __syncthreads();
     stage_galaxy(a, gal, g, sp, l.dh, l.atab);
     __syncthreads();
-    if (wave >= a.C) continue;
+    if (cw >= a.C) continue;
     const LaneCols<P> lc = lane_cols<P>(l.cols);
     const float sig = a.sigma[gal];
     GalCtx c;
@@ -559,11 +571,13 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.Ym = l.Ym;
     c.Yf = l.Yf;
     c.red = l.red;
+    c.part = part;
+    c.xch = l.xch0 + cw * (2 * 12 * W);
     c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
     c.rscale = a.rscale;
     c.refx = a.ref_xy[2 * (int64_t)gal];
     c.refy = a.ref_xy[2 * (int64_t)gal + 1];
-    const int64_t chain = (int64_t)gal * a.C + wave;
+    const int64_t chain = (int64_t)gal * a.C + cw;
     ChainState* st = a.state + chain;
     if (INIT) {
       Regs r;
@@ -599,16 +613,18 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       r.n_acc = 0;
       r.n_div = 0;
       r.uid = (uint32_t)((a.uid_gal ? a.uid_gal[gal] : a.uid_base + (uint64_t)gal * a.C) +
-                         (uint64_t)wave);
+                         (uint64_t)cw);
       store_state(st, r);
     } else {
       uint32_t* csw = reinterpret_cast<uint32_t*>(l.cs);
       csw[lane_id()] = reinterpret_cast<const uint32_t*>(st)[lane_id()];
       wave_lds_sync();
-      float* sc = a.samples ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
-      float* tc = a.trace ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P, NFIX>(a, c, lc, pr, l.cs, sc, tc);
-      reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
+      // the W waves of a split chain hold identical copies of its state; the
+      // first writes the outputs
+      float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
+      float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
+      advance_chain<PROF, P, NFIX, W>(a, c, lc, pr, l.cs, sc, tc);
+      if (part == 0) reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
     }
   }
 }
@@ -634,23 +650,24 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 }  // namespace
 
-size_t hmc_lds_bytes(int N, int C, int P) {
+size_t hmc_lds_bytes(int N, int C, int P, int W) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
+  const int NW = C * W;
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
-         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * C + sizeof(float) * 512 * C +
-         sizeof(float2) * wave_table_len(g, sp) * C;
+         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * NW +
+         sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW;
 }
 
-template <int PROF, bool INIT, int P, int NFIX = 0>
+template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1>
 static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  const dim3 blk(kWave * a.C);
-  if (a.C <= 4) {
-    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX>;
+  const dim3 blk(kWave * a.C * W);
+  if (a.C * W <= 4) {
+    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX, W>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   } else {
-    auto k = hmc_kernel<PROF, INIT, P, 1024, 0>;
+    auto k = hmc_kernel<PROF, INIT, P, 1024, 0, 1>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   }
@@ -658,19 +675,50 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 
 // Trajectory kernels specialised for the stamp sizes of the workloads
 // (compile-time geometry, fully unrolled bin loop), one per candidate plan
-// (the plans within 10 % of the fewest slots, at most three); other sizes and
+// (the plans within 10 % of the fewest slots, at most three), and for the
+// default plan also split over 2 and 4 waves per chain; other sizes and
 // plans use the generic kernel of their P.
 #define BSI_FIXED_PLANS(X) \
   X(25, 2) X(25, 3) X(25, 6) X(32, 1) X(32, 2) X(32, 4) X(41, 2) X(41, 5) \
   X(53, 6) X(53, 8) X(53, 5) X(73, 6) X(73, 8) X(73, 5) X(101, 5) X(101, 8)
 
+template <int PROF, int NFIX, int PP>
+static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (a.wpc == 1) {
+    launch_p<PROF, false, PP, NFIX, 1>(a, grid, lds, s);
+    return true;
+  }
+  if constexpr (make_slot_plan(NFIX).P == PP) {
+    if (a.wpc == 2) {
+      launch_p<PROF, false, PP, NFIX, 2>(a, grid, lds, s);
+      return true;
+    }
+    if (a.wpc == 4) {
+      launch_p<PROF, false, PP, NFIX, 4>(a, grid, lds, s);
+      return true;
+    }
+  }
+  return false;
+}
+
 template <int PROF>
 static bool launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 #define BSI_CASE(NN, PP) \
-  if (a.N == NN && a.P == PP) { launch_p<PROF, false, PP, NN>(a, grid, lds, s); return true; }
+  if (a.N == NN && a.P == PP) return launch_fixed_w<PROF, NN, PP>(a, grid, lds, s);
   BSI_FIXED_PLANS(BSI_CASE)
 #undef BSI_CASE
   return false;
+}
+
+int hmc_split_waves(int N, int C, int P, int prof, int max_w) {
+  if (max_w <= 1 || prof != kProfExp || P != make_slot_plan(N).P) return 1;
+  bool fixed = false;
+  for (const int* p = hmc_fixed_plans(N); *p; ++p) fixed |= (*p == P);
+  if (!fixed) return 1;
+  const int nsr = make_slot_plan_p(N, P).nsr;
+  int W = 1;
+  while (W * 2 <= max_w && W * 2 <= nsr && C * W * 2 <= 4) W *= 2;
+  return W;
 }
 
 const int* hmc_fixed_plans(int N) {
@@ -688,7 +736,8 @@ const int* hmc_fixed_plans(int N) {
 
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  if (!INIT && a.C <= 4 && PROF == kProfExp && launch_fixed<PROF>(a, grid, lds, s)) return;
+  if constexpr (!INIT && PROF == kProfExp)
+    if (a.C * a.wpc <= 4 && launch_fixed<PROF>(a, grid, lds, s)) return;
   switch (a.P) {
     case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
     case 2: launch_p<PROF, INIT, 2>(a, grid, lds, s); break;
@@ -704,7 +753,10 @@ template <bool INIT>
 static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   if (a.n_gal <= 0) return hipSuccess;
   if (!plan_valid(a.N, a.P)) return hipErrorInvalidValue;
-  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P);
+  // split chains only where a specialised kernel exists (hmc_split_waves)
+  if (a.wpc != 1 && (INIT || a.wpc != hmc_split_waves(a.N, a.C, a.P, a.prof, a.wpc)))
+    return hipErrorInvalidValue;
+  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
   else

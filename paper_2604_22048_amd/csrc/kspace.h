@@ -290,10 +290,19 @@ __device__ __forceinline__ void bin_step(const Shape& sh, float2 D, float4 y, fl
   sdy = fmaf(y.z, gz, sdy);
 }
 
-template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0>
+// Split evaluation (W > 1 waves per chain, NFIX kernels only): wave `part`
+// of the chain sums the super-rows part, part + W, ... and the Nyquist bins
+// lane + 64 part, ...; the W partial sums are then exchanged through `xch`
+// (W x 12 floats of LDS per chain, alternating between two buffers across
+// evaluations) and added in the order 0..W-1 by every wave, so that all W
+// waves hold the same totals.  The block must reach this function with all
+// its waves (the exchange uses a workgroup barrier).
+template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1>
 __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P>& lc,
                              const float2* __restrict__ dh, const float2* X, const float4* Ym,
-                             const float2* Yf, const Shape& sh, float* red) {
+                             const float2* Yf, const Shape& sh, float* red, int part = 0,
+                             float* xch = nullptr) {
+  static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
   const int lane = lane_id();
   float xr[P], xim[P], TA[P], Tc[P], kx2[P];
   const float4* yp[P];
@@ -316,27 +325,48 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   if constexpr (NFIX > 0) {
     constexpr SlotPlan spc = make_slot_plan_p(NFIX, P);
     static_assert(spc.R >= 1, "P too small for NFIX");
-    // software pipeline: the LDS reads of the next bin are issued before the
-    // arithmetic of the current one
-    float2 Dn = dp[0];
-    float4 yn = yp[0][0];
+    constexpr int K = (spc.nsr + W - 1) / W;   // super-rows of this wave (at most)
+    // this wave's super-rows are part + k W, k = 0..K-1 (the last may not exist)
+    const float2* dq = dp + part * P * 64;
+    const float4* yq[P];
 #pragma unroll
-    for (int sr = 0; sr < spc.nsr; ++sr) {
-      float c2 = 0.f;
+    for (int i = 0; i < P; ++i) yq[i] = yp[i] + part * spc.R;
+    if constexpr (W == 1) {
+      // software pipeline: the LDS reads of the next bin are issued before the
+      // arithmetic of the current one
+      float2 Dn = dq[0];
+      float4 yn = yq[0][0];
 #pragma unroll
-      for (int i = 0; i < P; ++i) {
-        const float2 D = Dn;
-        const float4 y = yn;
-        const int k = sr * P + i + 1;
-        if (k < spc.nsr * P) {
-          Dn = dp[k * 64];
-          yn = yp[k % P][(k / P) * spc.R];
+      for (int k = 0; k < K; ++k) {
+        float c2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          const float2 D = Dn;
+          const float4 y = yn;
+          const int b = k * P + i + 1;          // next bin
+          if (b < K * P) {
+            Dn = dq[b * 64];
+            yn = yq[b % P][(b / P) * spc.R];
+          }
+          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this bin's arithmetic
+          bin_step<PROF, P, RESID>(sh, D, y, xr[i], xim[i], TA[i], Tc[i], lc.kx[i], kx2[i], c2,
+                                   sF, sxx, syy, wky[i], sdx, sdy, CHI2);
         }
-        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this bin's arithmetic
-        bin_step<PROF, P, RESID>(sh, D, y, xr[i], xim[i], TA[i], Tc[i], lc.kx[i], kx2[i], c2, sF,
-                                 sxx, syy, wky[i], sdx, sdy, CHI2);
+        if (CHI2) chi2 += (double)c2;
       }
-      if (CHI2) chi2 += (double)c2;
+    } else {
+      const int nown = (spc.nsr - part + W - 1) / W;
+      for (int k = 0; k < nown; ++k) {
+        float c2 = 0.f;
+#pragma unroll
+        for (int i = 0; i < P; ++i)
+          bin_step<PROF, P, RESID>(sh, dq[i * 64], yq[i][0], xr[i], xim[i], TA[i], Tc[i], lc.kx[i],
+                                   kx2[i], c2, sF, sxx, syy, wky[i], sdx, sdy, CHI2);
+        if (CHI2) chi2 += (double)c2;
+        dq += W * P * 64;
+#pragma unroll
+        for (int i = 0; i < P; ++i) yq[i] += W * spc.R;
+      }
     }
   } else {
     for (int sr = 0; sr < sp.nsr; ++sr) {
@@ -359,7 +389,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   // (weights 1/2, sign -1 on +N/2) on its Nyquist axis or axes.
   const int h = g.h;
   const float ks = g.kstep;
-  for (int i = lane; i < sp.nspec; i += kWave) {
+  for (int i = lane + kWave * part; i < sp.nspec; i += kWave * W) {
     int ub, vb, c;
     nyq_bin_uv(g.N, i, ub, vb, c);
     const float2 D = dh[sp.nslots + i];
@@ -423,6 +453,31 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   s.sxy = v[3];
   s.sdx = v[4];
   s.sdy = v[5];
+  if constexpr (W > 1) {
+    float* mine = xch + 12 * part;
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) mine[j] = v[j];
+      reinterpret_cast<double*>(mine)[4] = s.chi2;
+    }
+    __syncthreads();
+    double c2 = 0.0;
+    float t[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      const float* o = xch + 12 * w;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) t[j] += o[j];
+      c2 += reinterpret_cast<const double*>(o)[4];
+    }
+    s.chi2 = c2;
+    s.sF = t[0];
+    s.sxx = t[1];
+    s.syy = t[2];
+    s.sxy = t[3];
+    s.sdx = t[4];
+    s.sdy = t[5];
+  }
   // q is linear in (kx^2, ky^2, kx ky), so sum q w = ca Sxx + cb Syy + cc Sxy
   s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
   return s;

@@ -94,6 +94,7 @@ struct Slot {
 struct SizeClass {
   int N;
   int P;                           // slot plan (the handle's at creation)
+  int W;                           // waves per chain of the trajectory kernel
   int64_t stamp_bytes, bin_bytes;
   hipEvent_t ev_beg = nullptr, ev_end = nullptr;   // this size's last advance launch
   double tau = -1.0;               // measured milliseconds per iteration (-1: unknown)
@@ -180,6 +181,7 @@ HmcArgs base_args(const bsi_slots_s* sv) {
   a.sigma_d = ip.sigma_d;
   a.sigma_e = ip.sigma_e;
   a.t_stop = sv->T;
+  a.wpc = 1;
   return a;
 }
 
@@ -205,6 +207,8 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   if (!(hc.jitter >= 0.0f && hc.jitter < 1.0f)) return fail(h, BSI_EINVAL, "jitter must be in [0, 1)");
   if (hc.metric != BSI_METRIC_GIVEN && hc.metric != BSI_METRIC_FISHER)
     return fail(h, BSI_EINVAL, "unknown metric %d", hc.metric);
+  if (hc.waves_per_chain < 0 || hc.waves_per_chain > 4)
+    return fail(h, BSI_EINVAL, "waves_per_chain must be 0..4");
   const bsi_interim& ip = cfg->interim;
   if (!(ip.log10f_lo < ip.log10f_hi) || !(ip.log10s_lo < ip.log10s_hi) || !(ip.sigma_d > 0) ||
       !(ip.sigma_e > 0))
@@ -233,7 +237,8 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
     SizeClass c;
     c.N = N;
     c.P = h->plan_P[N] > 0 ? h->plan_P[N] : make_slot_plan(N).P;
-    if (hmc_lds_bytes(N, sv->C, c.P) > 160 * 1024) {
+    c.W = hmc_split_waves(N, sv->C, c.P, cfg->profile, hc.waves_per_chain);
+    if (hmc_lds_bytes(N, sv->C, c.P, c.W) > 160 * 1024) {
       delete sv;
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", N, hc.n_chains);
     }
@@ -471,6 +476,7 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     HmcArgs a = base;
     a.N = k.N;
     a.P = k.P;
+    a.wpc = k.W;
     a.gidx = res;
     a.n_gal = (int)k.resident.size();
     a.n_steps = iters[i] * sv->L;

@@ -103,3 +103,36 @@ def test_autotune_and_tuned_run(bsi):
     assert np.array_equal(a, d) and np.all(np.isfinite(a))
     for N in res:
         bsi.set_plan(N, 0)
+
+
+@pytest.mark.parametrize("wpc", [2, 4])
+def test_split_chains_at_parity(bsi, wpc):
+    """Several waves per chain (latency form): chains follow the oracle under
+    the same momenta, and two calls give bitwise equal samples."""
+    import torch
+    sizes = [25, 53, 73, 101]
+    G, C, L, S = len(sizes), 1, 10, 3
+    t, params, data, off = synth.make_population("uneven", n_gal=G, seed=500 + wpc, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, C, seed=501)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=PS)
+    dev = torch.tensor(data).cuda()
+    ref = torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32).cuda()
+    cfg = bsi.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False,
+                        step_size=0.003, jitter=0.1, seed=13, waves_per_chain=wpc)
+    it = torch.tensor(init, dtype=torch.float32).cuda()
+    s1 = bsi.hmc_sample(b, dev, ref, it, cfg)[0].cpu().numpy()
+    s2 = bsi.hmc_sample(b, dev, ref, it, cfg)[0].cpu().numpy()
+    assert np.array_equal(s1, s2)
+    for i, N in enumerate(sizes):
+        _log(f"split chains wpc={wpc} N={N}")
+        gal = synth.oracle_galaxy(t, data, off, i)
+        r = hmc.run_chain(hmc.galaxy_potential(gal), init[i, 0].astype(np.float32), 13, i, L, 0, S,
+                          0.003, adapt=False, jitter=0.1)
+        k = 0
+        while k < S and np.max(np.abs(s1[i, 0, k] - r["samples"][k])) <= 1e-4:
+            k += 1
+        if k < S:
+            moved_g = k == 0 or np.any(s1[i, 0, k] != s1[i, 0, k - 1])
+            moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+            assert moved_g != moved_o, (wpc, N, k)

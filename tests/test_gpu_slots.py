@@ -38,16 +38,16 @@ CFG = dict(n_chains=1, n_leapfrog=6, n_warmup=12, n_samples=15, adapt=True, metr
            step_size=0.05, jitter=0.2, seed=9)
 
 
-@pytest.mark.parametrize("pace", [False, True])
-def test_slots_alone_equals_mix_bitwise(bsi, pace):
+@pytest.mark.parametrize("pace,wpc", [(False, 1), (True, 1), (False, 4)])
+def test_slots_alone_equals_mix_bitwise(bsi, pace, wpc):
     import torch
-    _log(f"slots alone vs mix pace={pace}")
+    _log(f"slots alone vs mix pace={pace} waves_per_chain={wpc}")
     rng = np.random.default_rng(70)
     n = 20
     sizes = rng.choice([25, 41, 53], n)
     t, params, data, off, init = _requests(n, sizes, 71)
     dev = torch.tensor(data).cuda()
-    cfg = bsi.HmcConfig(**CFG)
+    cfg = bsi.HmcConfig(waves_per_chain=wpc, **CFG)
     srv = bsi.Slots([25, 41, 53], cfg, hbm_budget=64 << 20, max_slots=6, pace=pace)
     ids = 1000 + np.arange(n)
     queue = list(range(n))
@@ -81,7 +81,7 @@ def test_slots_alone_equals_mix_bitwise(bsi, pace):
                       sigma=torch.tensor([t.sigma[i]], dtype=torch.float32).cuda(), pixel_scale=PS)
         ref = torch.tensor([[params[i, 4], params[i, 5]]], dtype=torch.float32).cuda()
         ini = torch.tensor(init[i][None, None, :], dtype=torch.float32).cuda()
-        c1 = bsi.HmcConfig(uid_base=int(ids[i]), **CFG)
+        c1 = bsi.HmcConfig(uid_base=int(ids[i]), waves_per_chain=wpc, **CFG)
         smp, st, _ = bsi.hmc_sample(b, dev[off[i]:off[i] + N * N].contiguous(), ref, ini, c1)
         assert np.array_equal(smp[0].cpu().numpy(), got[int(ids[i])][0]), i
         assert np.array_equal(st[0].cpu().numpy(), got[int(ids[i])][1]), i
