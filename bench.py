@@ -255,12 +255,14 @@ def make_request_pool(api, torch, per_size, seed_offset=0):
     return serve.RequestPool(**P)
 
 
-def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, iters_per_tick=15,
-                budget=4 << 30, extra_rates=(), pace=True, split=4, log=None):
+def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, iters_per_tick=15,
+                budget=4 << 30, extra_rates=(), pace=True, split=4, ess_target=300.0, ess_every=60,
+                log=None):
     """Poisson request stream at `rate` for `window_s` seconds of arrivals
     (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
-    warmup + n_draws iterations of 20 leapfrog steps each), then the capacity:
-    cap_requests requests all present at the start."""
+    warmup iterations of 20 leapfrog steps, then draws until the request's
+    ESS reaches ess_target at a check every ess_every draws, at most n_draws),
+    then the capacity: cap_requests requests all present at the start."""
     from paper_2604_22048_amd import serve
     cfg = gen.CONFIGS["serving"]
     hc = api.HmcConfig(n_chains=1, n_leapfrog=cfg.leapfrog, n_warmup=cfg.warmup, n_samples=n_draws,
@@ -274,7 +276,8 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
         sizes = np.random.default_rng(seed + arr.shape[0]).choice(np.array(SERVING_SIZES),
                                                                   size=arr.shape[0], p=w)
         hc.waves_per_chain = wpc
-        srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget, pace=paced)
+        srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget, pace=paced, ess_target=ess_target,
+                        ess_every=ess_every)
         r = serve.serve(srv, pool, arr, sizes, iters_per_tick, ess=ess, progress=log)
         srv.close()
         if log:
@@ -298,7 +301,11 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=600, ite
     out = {"rate_req_per_s": rate, "window_s": window_s, "n_requests": n_req, "completed": r.n_done,
            "galaxies_per_s": round(r.n_done / r.wall, 1), **lat_stats(r),
            "max_resident": r.max_resident, "ticks": r.ticks, "iters_per_tick": iters_per_tick,
-           "warmup": cfg.warmup, "draws": n_draws, "leapfrog": cfg.leapfrog,
+           "warmup": cfg.warmup, "ess_target": ess_target, "ess_every": ess_every,
+           "max_draws": n_draws, "leapfrog": cfg.leapfrog,
+           "draws_median": float(np.median(r.n_draws[r.n_draws > 0])),
+           "draws_p99": float(np.percentile(r.n_draws[r.n_draws > 0], 99)),
+           "frac_at_max_draws": round(float(np.mean(r.n_draws[r.n_draws > 0] >= n_draws)), 4),
            "slot_plans": {N: P for N, (P, _) in plans.items()},
            "ess_mean_median": round(float(np.median(em)), 1),
            "frac_ess_ge_300": round(float(np.mean(em >= 300.0)), 4),
@@ -385,6 +392,9 @@ def main():
                     "serving legs (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="--workload serving: this many Poisson requests at 2000/s (overrides "
+                         "--serve-window; only the ESS-targeted run and the capacity are measured)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -422,14 +432,19 @@ def main():
                                           "U(0.6, 0.9)in, SNR 10-200, 4 chains, 20 leapfrog steps, "
                                           "300 warmup + 1000 draws"}, **res}
         else:
-            res = serving_leg(api, torch, 2000.0, args.serve_window, 60000, 5, extra_rates=(0.5, 0.9),
-                              log=log)
+            if args.serve_requests:
+                res = serving_leg(api, torch, 2000.0, args.serve_requests / 2000.0, 60000, 5, pace=False,
+                                  split=0, log=log)
+            else:
+                res = serving_leg(api, torch, 2000.0, args.serve_window, 60000, 5,
+                                  extra_rates=(0.5, 0.9), log=log)
             out = {"metric": "p50/p99 fit latency and galaxies/s, Poisson requests",
                    "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
                    "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                    "config": {"workload": "serving: Poisson arrivals at 2000 req/s, stamp sizes "
                                           "25/41/53/73/101 (weights .3/.3/.2/.15/.05), 1 chain, 20 "
-                                          "leapfrog steps, 300 warmup + 600 draws"}, **res}
+                                          "leapfrog steps, 300 warmup, then draws until 300 ESS "
+                                          "(checked every 60 draws, at most 1500)"}, **res}
         print(json.dumps(out), flush=True)
         return
     cfg = gen.CONFIGS["uniform"]

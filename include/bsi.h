@@ -324,8 +324,9 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
  * spectrum, carved from an arena); each bsi_slots_advance moves every
  * resident request forward by a number of HMC iterations, one launch per
  * stamp size, the sizes running concurrently; a request that has run
- * n_warmup + n_samples iterations is finished and is returned by
- * bsi_slots_harvest, which frees its slot and memory for new admissions.
+ * n_warmup + n_samples iterations (or, with an ESS target, reached it at a
+ * check) is finished and is returned by bsi_slots_harvest, which frees its
+ * slot and memory for new admissions.
  * Chain c of request `id` uses Philox counter uid id * n_chains + c, and the
  * iteration is exactly that of bsi_hmc_sample, so a request's samples do not
  * depend on which other requests share the device: with
@@ -350,6 +351,17 @@ typedef struct {
                                   about n_iter * tau_slowest / tau_N, tau the per-iteration
                                   time of a size's launch measured with events on earlier
                                   calls, so that the sizes' launches take about equally long */
+  float ess_target;            /* 0: every request runs n_warmup + n_samples iterations.
+                                  > 0: requests ask for this many effective samples: after
+                                  n_warmup iterations a request is checked every ess_every
+                                  draws (at ess_every, 2 ess_every, ...) and finishes at the
+                                  first check where its effective sample size (multi-chain,
+                                  mean over the six parameters, as bsi_ess computes it) is at
+                                  least ess_target, else after n_samples draws.  A request's
+                                  chains wait at each check until it has run (the check is
+                                  enqueued by the same bsi_slots_advance), so the draws
+                                  returned, like the samples, depend on the request alone    */
+  int32_t ess_every;           /* draws between checks, >= 4 (used when ess_target > 0)     */
 } bsi_slots_cfg;
 
 typedef struct {
@@ -365,7 +377,8 @@ typedef struct {
 
 typedef struct {
   int32_t resident;            /* requests holding a slot (running or finished)             */
-  int32_t finished;            /* of which finished and not yet harvested                   */
+  int32_t finished;            /* of which finished and not yet harvested (as of the last
+                                  poll when ess_target > 0)                                 */
   int32_t pending;             /* admitted since the last bsi_slots_advance                 */
   int32_t max_slots;
   int64_t budget;              /* bytes held (per-request arrays plus arena)                */
@@ -401,15 +414,26 @@ int bsi_slots_admit_many(bsi_slots s, int32_t n, const bsi_request* reqs, int32_
  * potential).  Returns without waiting for the device. */
 int bsi_slots_advance(bsi_slots s, int32_t n_iter);
 
-/* Wait for the enqueued work, then hand out up to max finished requests in
- * the order they finished and free their slots:
+/* Wait for the enqueued work and collect the requests that have finished;
+ * *n_finished (nullable) receives the number finished and not yet handed out.
+ * With ess_target > 0 this is how the host learns of finished requests (the
+ * checks run on the device); bsi_slots_harvest polls by itself. */
+int bsi_slots_poll(bsi_slots s, int32_t* n_finished);
+
+/* Poll, then hand out up to max finished requests in the order they finished
+ * (requests finishing in the same bsi_slots_advance in admission order) and
+ * free their slots:
  *   ids          [host] uint64[max]
- *   samples      [device] float[max][n_chains][n_samples][6] (theta) or NULL
- *   chain_stats  [device] float[max][n_chains][4] as in bsi_hmc_sample, or NULL
+ *   samples      [device] float[max][n_chains][n_samples][6] (theta) or NULL;
+ *                draws past a request's n_draws are NaN
+ *   chain_stats  [device] float[max][n_chains][4] as in bsi_hmc_sample over the
+ *                request's n_draws draws, or NULL
  *   status       [device] uint32[max] (BSI_STATUS_* bits) or NULL
+ *   n_draws      [device] int32[max] draws per chain returned, or NULL
+ *                (n_samples unless ess_target > 0)
  * *n_out receives the number handed out.  Outputs are complete on return. */
 int bsi_slots_harvest(bsi_slots s, int32_t max, uint64_t* ids, float* samples,
-                      float* chain_stats, uint32_t* status, int32_t* n_out);
+                      float* chain_stats, uint32_t* status, int32_t* n_draws, int32_t* n_out);
 
 /* Occupancy and memory of the server. */
 int bsi_slots_get_info(bsi_slots s, bsi_slots_info* info);

@@ -62,7 +62,8 @@ class ShearHmcCfg(C.Structure):
 class SlotsCfg(C.Structure):
     _fields_ = [("n_sizes", C.c_int32), ("sizes", C.POINTER(C.c_int32)), ("hbm_budget", C.c_int64),
                 ("max_slots", C.c_int32), ("hmc", HmcCfg), ("interim", Interim),
-                ("pixel_scale", C.c_float), ("profile", C.c_int32), ("pace", C.c_int32)]
+                ("pixel_scale", C.c_float), ("profile", C.c_int32), ("pace", C.c_int32),
+                ("ess_target", C.c_float), ("ess_every", C.c_int32)]
 
 
 class Request(C.Structure):
@@ -105,8 +106,9 @@ SIGNATURES = {
     "bsi_slots_admit": (C.c_int, [C.c_void_p, C.POINTER(Request), C.POINTER(C.c_int32)]),
     "bsi_slots_admit_many": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "bsi_slots_advance": (C.c_int, [C.c_void_p, C.c_int32]),
+    "bsi_slots_poll": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),
     "bsi_slots_harvest": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_uint64), C.c_void_p,
-                                    C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
+                                    C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int32)]),
     "bsi_slots_get_info": (C.c_int, [C.c_void_p, C.POINTER(SlotsInfo)]),
     "bsi_set_plan": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "bsi_get_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),

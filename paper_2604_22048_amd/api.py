@@ -299,18 +299,23 @@ def shear_hmc(e1p, e2p, log10s, log10f, true_prior: TruePriorCfg, cfg: ShearHmcC
 class Slots:
     """Request server (bsi_slots_*): admit galaxy-fit requests while their
     device footprint fits, advance all resident chains, harvest finished
-    requests.  Work is ordered on the stream current at creation."""
+    requests.  Work is ordered on the stream current at creation.
+
+    ess_target > 0: each request asks for that many effective samples; it is
+    checked every ess_every draws after warmup and finishes at the first check
+    that reaches the target (or after cfg.n_samples draws)."""
 
     def __init__(self, sizes, cfg: HmcConfig, hbm_budget: int, max_slots: int = 0, interim=None,
                  pixel_scale: float = 0.2, profile: int = N.PROFILE_EXPONENTIAL,
-                 pace: bool = False, device: int = 0, lib: Library | None = None):
+                 pace: bool = False, ess_target: float = 0.0, ess_every: int = 100, device: int = 0,
+                 lib: Library | None = None):
         self.lib = lib or get(device)
         self.device = torch.device("cuda", device)
         self.cfg = cfg
         self._sizes = (C.c_int32 * len(sizes))(*[int(x) for x in sizes])
         c = N.SlotsCfg(len(sizes), C.cast(self._sizes, C.POINTER(C.c_int32)), int(hbm_budget),
                        int(max_slots), cfg.c(), _interim(interim), float(pixel_scale), int(profile),
-                       int(bool(pace)))
+                       int(bool(pace)), float(ess_target), int(ess_every))
         self._stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         self.lib.check(self.lib.lib.bsi_slots_create(self.lib.h, C.byref(c),
@@ -363,20 +368,29 @@ class Slots:
         self.lib.check(self.lib.lib.bsi_slots_advance(self.h, int(n_iter)), "bsi_slots_advance")
         self._keep_prev, self._keep = self._keep, []
 
+    def poll(self) -> int:
+        """Wait for the server's work; number of finished, unharvested requests."""
+        n = C.c_int32(0)
+        self.lib.check(self.lib.lib.bsi_slots_poll(self.h, C.byref(n)), "bsi_slots_poll")
+        return int(n.value)
+
     def harvest(self, max_n: int, want_samples: bool = True):
-        """(ids [n] uint64 numpy, samples [n, C, S, 6], chain_stats [n, C, 4], status [n])."""
+        """(ids [n] uint64 numpy, samples [n, C, S, 6], chain_stats [n, C, 4],
+        status [n], n_draws [n]); draws past a request's n_draws are NaN."""
         Cn, S = self.cfg.n_chains, self.cfg.n_samples
         smp = torch.empty(max_n, Cn, S, 6, dtype=torch.float32, device=self.device) if want_samples else None
         st = torch.empty(max_n, Cn, 4, dtype=torch.float32, device=self.device)
         stat = torch.empty(max_n, dtype=torch.int32, device=self.device)
+        nd = torch.empty(max_n, dtype=torch.int32, device=self.device)
         ids = (C.c_uint64 * max(max_n, 1))()
         n = C.c_int32(0)
         self.lib.check(self.lib.lib.bsi_slots_harvest(self.h, int(max_n), ids, _ptr(smp), _ptr(st),
-                                                      _ptr(stat), C.byref(n)), "bsi_slots_harvest")
+                                                      _ptr(stat), _ptr(nd), C.byref(n)),
+                       "bsi_slots_harvest")
         k = n.value
         self._keep_prev = []
         out_ids = np.array(ids[:k], dtype=np.uint64)
-        return out_ids, (smp[:k] if smp is not None else None), st[:k], stat[:k]
+        return out_ids, (smp[:k] if smp is not None else None), st[:k], stat[:k], nd[:k]
 
     def info(self) -> dict:
         i = N.SlotsInfo()

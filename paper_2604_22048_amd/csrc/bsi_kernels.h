@@ -95,6 +95,7 @@ struct HmcArgs {
   float lf_lo, lf_hi, ls_lo, ls_hi, sigma_d, sigma_e;
   int n_steps;            // leapfrog steps to advance in this launch
   int t_stop;             // iteration at which a chain stops (W + S)
+  const int32_t* t_stop_gal;  // [gal] per-galaxy stop (<= t_stop) or NULL (advance kernel only)
 };
 
 size_t hmc_lds_bytes(int N, int C, int P, int W);
@@ -185,12 +186,25 @@ struct SlotArrays {
   float* ref_xy;      // [slot][2]
   uint64_t* uid;
   float* init;        // [slot][C][6]
+  int32_t* stop;      // [slot] iteration at which the request's chains wait (its next check)
+  int32_t* ndraw;     // [slot] draws returned once finished, 0 while running
+  int32_t* done_q;    // [slot] requests finished at checks since the last poll
+  int32_t* done_n;    // entries of done_q
 };
-hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C,
+// stop0: the first stop of an admitted request (its first check, or W + S).
+hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C, int stop0,
                                 const SlotArrays& sa, float* arena, hipStream_t s);
+// ndraw: per-slot draws returned (NULL: all S); out_ndraw: [n] or NULL.
 hipError_t launch_slots_gather(const int32_t* list, int n, int C, int S, const ChainState* st,
-                               const float* samples, float* out, float* stats, uint32_t* status,
-                               hipStream_t s);
+                               const float* samples, const int32_t* ndraw, float* out, float* stats,
+                               uint32_t* status, int32_t* out_ndraw, hipStream_t s);
+// ESS checks of the listed requests whose chains wait at their stop: finish
+// (ndraw, done queue) when the ESS reaches target or S draws are done, else
+// move the stop `every` draws on.
+hipError_t launch_slots_check(const int32_t* list, int n, int C, int W, int S, int every, float target,
+                              const ChainState* st, const float* samples, const SlotArrays& sa,
+                              hipStream_t s);
+size_t slots_check_lds_bytes(int C, int S);
 
 // ---- diag.hip ----
 hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,

@@ -42,6 +42,7 @@ struct GalCtx {
   float norm;      // 1 / (N^2 sigma^2)
   float rscale;
   float refx, refy;
+  int t_stop;      // iteration at which this galaxy's chains stop in this launch
 };
 
 // Plain separable tables over the full frequency range (Fisher metric only):
@@ -414,7 +415,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
   h.t = cs->t;
   h.status = cs->status;
   for (int step = 0; step < a.n_steps; ++step) {
-    if (h.t >= a.t_stop) break;
+    if (h.t >= c.t_stop) break;
     if (h.l == 0) {
       float z[6], u_acc, u_jit;
       draw_iteration(uid, (uint32_t)h.t, a.k0, a.k1, z, u_acc, u_jit);
@@ -577,6 +578,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.rscale = a.rscale;
     c.refx = a.ref_xy[2 * (int64_t)gal];
     c.refy = a.ref_xy[2 * (int64_t)gal + 1];
+    c.t_stop = a.t_stop_gal ? min(a.t_stop, a.t_stop_gal[gal]) : a.t_stop;
     const int64_t chain = (int64_t)gal * a.C + cw;
     ChainState* st = a.state + chain;
     if (INIT) {

@@ -5,7 +5,10 @@
 // takes its stamp copy and data spectrum (first fit, coalescing free list).
 // Scheduling is host-side and deterministic: a request admitted before
 // advance k runs iterations from advance k on and is finished once
-// n_warmup + n_samples iterations have been enqueued for it.
+// n_warmup + n_samples iterations have been enqueued for it.  With an ESS
+// target the device decides instead: each request's chains stop at its next
+// checkpoint, a check kernel enqueued after every advance finishes it there
+// or moves the checkpoint on, and a poll reads the finished requests back.
 #include "bsi.h"
 
 #include <hip/hip_runtime.h>
@@ -85,6 +88,7 @@ struct Slot {
   bool used = false;
   bool done = false;
   uint64_t id = 0;
+  uint64_t seq = 0;       // admission order
   int cls = -1;
   int t = 0;              // iterations enqueued so far
   int64_t arena_off = 0;  // bytes
@@ -110,6 +114,8 @@ struct bsi_slots_s {
   hipStream_t s = nullptr;
   bsi_slots_cfg cfg{};
   int C = 1, L = 1, T = 0, S = 0;
+  bool ess = false;               // ESS-targeted requests (device-side completion)
+  uint64_t n_admitted = 0;
   std::vector<SizeClass> cls;
   int max_slots = 0;
   int64_t fixed_bytes = 0;
@@ -127,6 +133,7 @@ struct bsi_slots_s {
   int64_t up_bytes = 0;
   hipEvent_t ev_up = nullptr;
   bool up_pending = false;
+  int32_t* rd = nullptr;          // pinned readback of the done queue: count, then entries
   // bookkeeping
   std::vector<Slot> slots;
   std::vector<int32_t> free_ids;
@@ -181,6 +188,7 @@ HmcArgs base_args(const bsi_slots_s* sv) {
   a.sigma_d = ip.sigma_d;
   a.sigma_e = ip.sigma_e;
   a.t_stop = sv->T;
+  a.t_stop_gal = sv->ess ? sv->arr.stop : nullptr;
   a.wpc = 1;
   return a;
 }
@@ -217,6 +225,11 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   if (cfg->profile != BSI_PROFILE_EXPONENTIAL && cfg->profile != BSI_PROFILE_GAUSSIAN)
     return fail(h, BSI_EINVAL, "unknown profile %d", cfg->profile);
   if (cfg->hbm_budget <= 0 || cfg->max_slots < 0) return fail(h, BSI_EINVAL, "invalid budget/max_slots");
+  if (!(cfg->ess_target >= 0.0f) || !std::isfinite(cfg->ess_target))
+    return fail(h, BSI_EINVAL, "ess_target must be finite and >= 0");
+  if (cfg->ess_target > 0.0f && cfg->ess_every < 4) return fail(h, BSI_EINVAL, "ess_every must be >= 4");
+  if (cfg->ess_target > 0.0f && slots_check_lds_bytes(hc.n_chains, hc.n_samples) > 160 * 1024)
+    return fail(h, BSI_EUNSUPPORTED, "n_chains * n_samples too large for the on-device ESS check");
 
   bsi_slots_s* sv = new bsi_slots_s();
   sv->h = h;
@@ -227,6 +240,7 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   sv->L = hc.n_leapfrog;
   sv->S = hc.n_samples;
   sv->T = hc.n_warmup + hc.n_samples;
+  sv->ess = cfg->ess_target > 0.0f;
   int64_t min_var = INT64_MAX, max_var = 0;
   for (int i = 0; i < cfg->n_sizes; ++i) {
     const int N = cfg->sizes[i];
@@ -249,16 +263,18 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
     sv->cls.push_back(c);
   }
   const int64_t C = sv->C;
-  // per slot: off, bin_off, psf, sigma, ref_xy, uid, init, states, samples
+  // per slot: off, bin_off, psf, sigma, ref_xy, uid, init, states, samples,
+  // stop, ndraw, done queue entry
   sv->fixed_bytes = 8 + 8 + 4 + 4 + 8 + 8 + C * 24 + C * (int64_t)sizeof(ChainState) +
-                    C * sv->S * 24;
+                    C * sv->S * 24 + 12;
   const int64_t budget = cfg->hbm_budget;
   int64_t ms = cfg->max_slots > 0 ? cfg->max_slots : budget / (sv->fixed_bytes + min_var);
   ms = std::min<int64_t>(ms, 1 << 22);
   // array section, each array 256-byte aligned
   auto arrays_bytes = [&](int64_t n) {
     return align_up(n * 8) * 3 + align_up(n * 4) * 2 + align_up(n * 8) + align_up(n * C * 24) +
-           align_up(n * C * (int64_t)sizeof(ChainState)) + align_up(n * C * sv->S * 24);
+           align_up(n * C * (int64_t)sizeof(ChainState)) + align_up(n * C * sv->S * 24) +
+           align_up(n * 4) * 3 + align_up(4);
   };
   if (ms < 1 || arrays_bytes(ms) + max_var > budget) {
     delete sv;
@@ -290,12 +306,19 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   sv->arr.init = reinterpret_cast<float*>(take(ms * C * 24));
   sv->state = reinterpret_cast<ChainState*>(take(ms * C * (int64_t)sizeof(ChainState)));
   sv->samples = reinterpret_cast<float*>(take(ms * C * sv->S * 24));
+  sv->arr.stop = reinterpret_cast<int32_t*>(take(ms * 4));
+  sv->arr.ndraw = reinterpret_cast<int32_t*>(take(ms * 4));
+  sv->arr.done_q = reinterpret_cast<int32_t*>(take(ms * 4));
+  sv->arr.done_n = reinterpret_cast<int32_t*>(take(4));
   sv->arena = p;
   sv->alloc.reset(arena_bytes);
   // upload staging: records, start positions, and two slot lists per class
   sv->up_bytes = align_up(ms * (int64_t)sizeof(SlotRecord)) + align_up(ms * C * 24) +
                  align_up(ms * 4) * 2 * (int64_t)sv->cls.size();
   e = hipHostMalloc(reinterpret_cast<void**>(&sv->pinned), (size_t)sv->up_bytes, hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&sv->rd), (size_t)(ms + 1) * 4, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(sv->arr.done_n, 0, 4, sv->s);
   if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&sv->dev_up), (size_t)sv->up_bytes);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&sv->ev_up, hipEventDisableTiming);
   for (SizeClass& k : sv->cls) {
@@ -326,6 +349,7 @@ void bsi_slots_destroy(bsi_slots sv) {
   }
   if (sv->dev_up) (void)hipFree(sv->dev_up);
   if (sv->pinned) (void)hipHostFree(sv->pinned);
+  if (sv->rd) (void)hipHostFree(sv->rd);
   if (sv->block) (void)hipFree(sv->block);
   delete sv;
 }
@@ -361,6 +385,7 @@ int bsi_slots_admit(bsi_slots sv, const bsi_request* r, int32_t* admitted) {
   s = Slot{};
   s.used = true;
   s.id = r->id;
+  s.seq = sv->n_admitted++;
   s.cls = c;
   s.arena_off = off;
   s.arena_len = len;
@@ -434,9 +459,11 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     if (e != hipSuccess) return hip_fail(h, e, "staging upload");
     sv->up_pending = true;
   }
+  const int every = sv->cfg.ess_every;
+  const int stop0 = sv->cfg.hmc.n_warmup + (sv->ess ? std::min(every, sv->S) : sv->S);
   e = launch_slots_scatter(reinterpret_cast<const SlotRecord*>(sv->dev_up + rec_at),
-                           reinterpret_cast<const float*>(sv->dev_up + init_at), n_new, C, sv->arr,
-                           reinterpret_cast<float*>(sv->arena), sv->s);
+                           reinterpret_cast<const float*>(sv->dev_up + init_at), n_new, C, stop0,
+                           sv->arr, reinterpret_cast<float*>(sv->arena), sv->s);
   if (e != hipSuccess) return hip_fail(h, e, "admission scatter");
   std::vector<int> active;
   for (size_t i = 0; i < sv->cls.size(); ++i)
@@ -486,6 +513,22 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     return x;
   });
   if (e != hipSuccess) return hip_fail(h, e, "advance launch");
+  if (sv->ess) {
+    // checks at the requests' stops; finished requests are read back by a poll
+    for (int i : active) {
+      e = launch_slots_check(reinterpret_cast<const int32_t*>(sv->dev_up + res_at[i]),
+                             (int)sv->cls[i].resident.size(), C, sv->cfg.hmc.n_warmup, sv->S, every,
+                             sv->cfg.ess_target, sv->state, sv->samples, sv->arr, sv->s);
+      if (e != hipSuccess) return hip_fail(h, e, "ESS check launch");
+    }
+    for (SizeClass& k : sv->cls) {
+      k.fresh.clear();
+      if (sv->cfg.pace && !k.resident.empty()) k.last_k = iters[&k - sv->cls.data()];
+    }
+    sv->rec.clear();
+    sv->rec_init.clear();
+    return BSI_OK;
+  }
   // bookkeeping: every resident request got its size's iterations (or what it had left)
   for (size_t i = 0; i < sv->cls.size(); ++i) {
     SizeClass& k = sv->cls[i];
@@ -510,17 +553,15 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
   return BSI_OK;
 }
 
-int bsi_slots_harvest(bsi_slots sv, int32_t max, uint64_t* ids, float* samples,
-                      float* chain_stats, uint32_t* status, int32_t* n_out) {
+int bsi_slots_poll(bsi_slots sv, int32_t* n_finished) {
   if (!sv) return BSI_EINVAL;
   bsi_handle h = sv->h;
   h->err.clear();
-  if (!n_out || max < 0 || (max > 0 && !ids)) return fail(h, BSI_EINVAL, "bad harvest arguments");
-  *n_out = 0;
   hipSetDevice(h->device);
   hipError_t e = sv->s ? hipStreamSynchronize(sv->s) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(h, e, "server sync");
   sv->up_pending = false;
+  // pacing: per-iteration time of each size's last launch
   for (SizeClass& k : sv->cls) {
     if (k.last_k <= 0) continue;
     float ms = 0.f;
@@ -532,15 +573,55 @@ int bsi_slots_harvest(bsi_slots sv, int32_t max, uint64_t* ids, float* samples,
     }
     k.last_k = 0;
   }
+  if (sv->ess) {
+    e = hipMemcpy(sv->rd, sv->arr.done_n, 4, hipMemcpyDeviceToHost);
+    const int n = e == hipSuccess ? sv->rd[0] : 0;
+    if (e == hipSuccess && n > 0)
+      e = hipMemcpy(sv->rd + 1, sv->arr.done_q, (size_t)n * 4, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && n > 0) e = hipMemsetAsync(sv->arr.done_n, 0, 4, sv->s);
+    if (e != hipSuccess) return hip_fail(h, e, "finished-request readback");
+    if (n > 0) {
+      // the queue's order comes from atomics: hand out in admission order
+      std::vector<int32_t> got(sv->rd + 1, sv->rd + 1 + n);
+      std::sort(got.begin(), got.end(),
+                [&](int32_t a, int32_t b) { return sv->slots[a].seq < sv->slots[b].seq; });
+      for (int32_t slot : got) {
+        sv->slots[slot].done = true;
+        sv->finished.push_back(slot);
+      }
+      for (SizeClass& k : sv->cls) {
+        std::vector<int32_t> keep;
+        keep.reserve(k.resident.size());
+        for (int32_t slot : k.resident)
+          if (!sv->slots[slot].done) keep.push_back(slot);
+        k.resident.swap(keep);
+      }
+    }
+  }
+  if (n_finished) *n_finished = (int32_t)sv->finished.size();
+  return BSI_OK;
+}
+
+int bsi_slots_harvest(bsi_slots sv, int32_t max, uint64_t* ids, float* samples,
+                      float* chain_stats, uint32_t* status, int32_t* n_draws, int32_t* n_out) {
+  if (!sv) return BSI_EINVAL;
+  bsi_handle h = sv->h;
+  h->err.clear();
+  if (!n_out || max < 0 || (max > 0 && !ids)) return fail(h, BSI_EINVAL, "bad harvest arguments");
+  *n_out = 0;
+  int rc = bsi_slots_poll(sv, nullptr);
+  if (rc) return rc;
+  hipError_t e = hipSuccess;
   const int n = (int)std::min<size_t>((size_t)max, sv->finished.size());
   if (n == 0) return BSI_OK;
   std::vector<int32_t> list(sv->finished.begin(), sv->finished.begin() + n);
-  if (samples || chain_stats || status) {
+  if (samples || chain_stats || status || n_draws) {
     std::memcpy(sv->pinned, list.data(), (size_t)n * 4);
     e = hipMemcpyAsync(sv->dev_up, sv->pinned, (size_t)n * 4, hipMemcpyHostToDevice, sv->s);
     if (e == hipSuccess)
       e = launch_slots_gather(reinterpret_cast<const int32_t*>(sv->dev_up), n, sv->C, sv->S,
-                              sv->state, sv->samples, samples, chain_stats, status, sv->s);
+                              sv->state, sv->samples, sv->ess ? sv->arr.ndraw : nullptr, samples,
+                              chain_stats, status, n_draws, sv->s);
     if (e == hipSuccess) e = sv->s ? hipStreamSynchronize(sv->s) : hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(h, e, "harvest gather");
   }

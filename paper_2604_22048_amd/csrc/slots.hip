@@ -1,7 +1,9 @@
 // Device side of the request server: admission scatters each admitted
-// request's scalars, start positions and stamp into its slot; harvest gathers
-// finished requests' samples and chain statistics into caller buffers.
+// request's scalars, start positions and stamp into its slot; the ESS check
+// decides at each of a request's checkpoints whether it has finished; harvest
+// gathers finished requests' samples and chain statistics into caller buffers.
 #include "bsi_kernels.h"
+#include "ess_device.h"
 
 namespace bsi {
 
@@ -9,7 +11,7 @@ namespace {
 
 __global__ void __launch_bounds__(256)
 slots_scatter_kernel(const SlotRecord* __restrict__ rec, const float* __restrict__ init_src, int C,
-                     SlotArrays sa, float* __restrict__ arena) {
+                     int stop0, SlotArrays sa, float* __restrict__ arena) {
   const SlotRecord r = rec[blockIdx.x];
   if (threadIdx.x == 0) {
     sa.off[r.slot] = r.off;
@@ -19,6 +21,8 @@ slots_scatter_kernel(const SlotRecord* __restrict__ rec, const float* __restrict
     sa.ref_xy[2 * (int64_t)r.slot] = r.refx;
     sa.ref_xy[2 * (int64_t)r.slot + 1] = r.refy;
     sa.uid[r.slot] = r.uid;
+    sa.stop[r.slot] = stop0;
+    sa.ndraw[r.slot] = 0;
   }
   const int nin = C * 6;
   for (int i = threadIdx.x; i < nin; i += blockDim.x)
@@ -31,18 +35,21 @@ slots_scatter_kernel(const SlotRecord* __restrict__ rec, const float* __restrict
 
 __global__ void __launch_bounds__(256)
 slots_gather_kernel(const int32_t* __restrict__ list, int C, int S, const ChainState* __restrict__ st,
-                    const float* __restrict__ samples, float* __restrict__ out,
-                    float* __restrict__ stats, uint32_t* __restrict__ status) {
+                    const float* __restrict__ samples, const int32_t* __restrict__ ndraw,
+                    float* __restrict__ out, float* __restrict__ stats, uint32_t* __restrict__ status,
+                    int32_t* __restrict__ out_ndraw) {
   const int j = blockIdx.x;
   const int slot = list[j];
+  const int nd = ndraw ? ndraw[slot] : S;
   if (out) {
-    const int64_t n = (int64_t)C * S * 6;
-    const float4* __restrict__ src = reinterpret_cast<const float4*>(samples + (int64_t)slot * n);
-    float4* __restrict__ dst = reinterpret_cast<float4*>(out + (int64_t)j * n);
-    for (int64_t i = threadIdx.x; i < n / 4; i += blockDim.x) dst[i] = src[i];
-    for (int64_t i = (n / 4) * 4 + threadIdx.x; i < n; i += blockDim.x)
-      out[(int64_t)j * n + i] = samples[(int64_t)slot * n + i];
+    // draws past nd are NaN (a request finished at a check)
+    const int64_t n = (int64_t)C * S * 6, valid = (int64_t)nd * 6;
+    const float* __restrict__ src = samples + (int64_t)slot * n;
+    float* __restrict__ dst = out + (int64_t)j * n;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x)
+      dst[i] = (i % (S * 6) < valid) ? src[i] : __builtin_nanf("");
   }
+  if (threadIdx.x == 0 && out_ndraw) out_ndraw[j] = nd;
   if (threadIdx.x == 0 && status) {
     uint32_t s = 0;
     for (int c = 0; c < C; ++c) s |= st[(int64_t)slot * C + c].status;
@@ -51,28 +58,82 @@ slots_gather_kernel(const int32_t* __restrict__ list, int C, int S, const ChainS
   if (stats && (int)threadIdx.x < C) {
     const ChainState& x = st[(int64_t)slot * C + threadIdx.x];
     float* o = stats + ((int64_t)j * C + threadIdx.x) * 4;
-    o[0] = S > 0 ? (float)x.n_acc / (float)S : 0.f;
+    o[0] = nd > 0 ? (float)x.n_acc / (float)nd : 0.f;
     o[1] = x.eps;
     o[2] = (float)x.n_div;
     o[3] = (float)x.U;
   }
 }
 
+// One workgroup per listed request.  A request whose chains have reached its
+// stop W + n is checked there: it finishes with n draws when n = S or when
+// the mean over the six parameters of its ESS over draws [0, n) reaches the
+// target; otherwise its stop moves to W + min(n + every, S).  Requests still
+// running towards their stop, and finished ones, are left alone.  The
+// decision depends on the request's own draws only.
+__global__ void __launch_bounds__(256)
+slots_check_kernel(const int32_t* __restrict__ list, int C, int W, int S, int every, float target,
+                   const ChainState* __restrict__ st, const float* __restrict__ samples, SlotArrays sa) {
+  extern __shared__ double sm[];
+  __shared__ EssShared es;
+  __shared__ int s_fin;
+  const int slot = list[blockIdx.x];
+  const int stop = sa.stop[slot];
+  if (st[(int64_t)slot * C].t < stop || sa.ndraw[slot] != 0) return;   // uniform in the block
+  const int n = stop - W;
+  if (threadIdx.x == 0) s_fin = n >= S;
+  __syncthreads();
+  if (!s_fin) {
+    double* xs = sm;
+    double* rho = xs + (size_t)C * n;
+    double sum = 0.0;                  // thread 0
+    for (int par = 0; par < 6; ++par) {
+      float e = 0.f, r = 0.f;
+      ess_one_param(samples + (int64_t)slot * C * S * 6, C, n, S, 6, par, xs, rho, es, e, r);
+      sum += (double)e;
+    }
+    if (threadIdx.x == 0) s_fin = sum / 6.0 >= (double)target;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (s_fin) {
+      sa.ndraw[slot] = n;
+      sa.done_q[atomicAdd(sa.done_n, 1)] = slot;
+    } else {
+      sa.stop[slot] = W + min(n + every, S);
+    }
+  }
+}
+
 }  // namespace
 
-hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C,
+hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C, int stop0,
                                 const SlotArrays& sa, float* arena, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(slots_scatter_kernel, dim3(n), dim3(256), 0, s, rec, init_src, C, sa, arena);
+  hipLaunchKernelGGL(slots_scatter_kernel, dim3(n), dim3(256), 0, s, rec, init_src, C, stop0, sa, arena);
   return hipGetLastError();
 }
 
 hipError_t launch_slots_gather(const int32_t* list, int n, int C, int S, const ChainState* st,
-                               const float* samples, float* out, float* stats, uint32_t* status,
-                               hipStream_t s) {
+                               const float* samples, const int32_t* ndraw, float* out, float* stats,
+                               uint32_t* status, int32_t* out_ndraw, hipStream_t s) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(slots_gather_kernel, dim3(n), dim3(256), 0, s, list, C, S, st, samples, out,
-                     stats, status);
+  hipLaunchKernelGGL(slots_gather_kernel, dim3(n), dim3(256), 0, s, list, C, S, st, samples, ndraw,
+                     out, stats, status, out_ndraw);
+  return hipGetLastError();
+}
+
+size_t slots_check_lds_bytes(int C, int S) { return sizeof(double) * ((size_t)C * S + 256); }
+
+hipError_t launch_slots_check(const int32_t* list, int n, int C, int W, int S, int every, float target,
+                              const ChainState* st, const float* samples, const SlotArrays& sa,
+                              hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const size_t lds = slots_check_lds_bytes(C, S);
+  (void)hipFuncSetAttribute((const void*)slots_check_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL(slots_check_kernel, dim3(n), dim3(256), lds, s, list, C, W, S, every, target, st,
+                     samples, sa);
   return hipGetLastError();
 }
 

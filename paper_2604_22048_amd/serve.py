@@ -58,6 +58,7 @@ class ServeResult:
     ticks: int
     max_resident: int
     ess_mean: np.ndarray | None   # mean over the six properties, per completed request
+    n_draws: np.ndarray           # draws per chain returned, per request (0 if not completed)
 
 
 def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.ndarray,
@@ -78,6 +79,7 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     lat = np.full(n, np.nan)
     fin = np.full(n, np.nan)
     ess_out = np.full(n, np.nan) if ess else None
+    draws = np.zeros(n, dtype=np.int32)
     queue_head = 0
     done = 0
     ticks = 0
@@ -102,8 +104,8 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
         max_res = max(max_res, resident)
         srv.advance(n_iter)
         ticks += 1
-        n_fin = srv.info()["finished"]
-        hid, smp, _, _ = srv.harvest(n_fin, want_samples=ess)
+        n_fin = srv.poll()
+        hid, smp, _, _, nd = srv.harvest(n_fin, want_samples=ess)
         t_done = time.perf_counter() - t0
         if hid.size:
             h = hid.astype(np.int64)
@@ -111,13 +113,20 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
             lat[h] = t_done - arrivals[h]
             done += h.size
             resident -= h.size
+            ndh = nd.cpu().numpy()
+            draws[h] = ndh
             if ess:
-                e, _ = api.ess(smp)
-                ess_out[h] = e.mean(dim=1).cpu().numpy()
+                # requests finished at a check return a prefix of their draws
+                for v in np.unique(ndh):
+                    m = np.nonzero(ndh == v)[0]
+                    sel = smp[torch.from_numpy(m).to(smp.device), :, :int(v)].contiguous()
+                    e, _ = api.ess(sel)
+                    ess_out[h[m]] = e.mean(dim=1).cpu().numpy()
         if progress and t_done > next_report:
             progress(f"[serve] t={t_done:.1f}s done={done}/{n} resident={resident} "
                      f"queued={arrived - queue_head}")
             next_report = t_done + 5.0
     wall = float(np.nanmax(fin) - arrivals[0]) if done else float("nan")
     return ServeResult(latency=lat, finish=fin, wall=wall, n_done=done, ticks=ticks,
-                       max_resident=max_res, ess_mean=None if ess_out is None else ess_out)
+                       max_resident=max_res, ess_mean=None if ess_out is None else ess_out,
+                       n_draws=draws)

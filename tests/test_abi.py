@@ -60,6 +60,7 @@ int main(void) {
   F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)
   F(bsi_slots_cfg, hbm_budget) F(bsi_slots_cfg, hmc) F(bsi_slots_cfg, interim)
   F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile) F(bsi_slots_cfg, pace)
+  F(bsi_slots_cfg, ess_target) F(bsi_slots_cfg, ess_every)
   F(bsi_request, stamp) F(bsi_request, psf_fwhm) F(bsi_request, ref_y) F(bsi_request, init)
   F(bsi_slots_info, budget) F(bsi_slots_info, arena_largest_free)
   return 0;
@@ -109,6 +110,7 @@ def test_no_device_and_null_handle_paths(native):
     assert lib.bsi_autotune(None, 0, None, 4, None, None) == -1
     assert lib.bsi_slots_advance(None, 1) == -1
     assert lib.bsi_slots_get_info(None, None) == -1
+    assert lib.bsi_slots_poll(None, None) == -1
     lib.bsi_slots_destroy(None)
     lib.bsi_destroy(None)
     assert lib.bsi_device_count(None) == -1

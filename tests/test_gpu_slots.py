@@ -11,6 +11,7 @@ import pytest
 
 pytestmark = pytest.mark.gpu
 
+from oracle import diagnostics                               # noqa: E402
 from tests import synth                                      # noqa: E402
 from workloads import gen                                    # noqa: E402
 
@@ -66,7 +67,8 @@ def test_slots_alone_equals_mix_bitwise(bsi, pace, wpc):
         assert inf["resident"] <= 6
         srv.advance(int(rng.integers(2, 9)))
         ticks += 1
-        hid, smp, st, status = srv.harvest(n)
+        hid, smp, st, status, nd = srv.harvest(n)
+        assert np.all(nd.cpu().numpy() == CFG["n_samples"])
         for k, rid in enumerate(hid):
             assert int(rid) not in got
             got[int(rid)] = (smp[k].cpu().numpy(), st[k].cpu().numpy())
@@ -92,7 +94,7 @@ def test_slots_alone_equals_mix_bitwise(bsi, pace, wpc):
     assert srv1.admit(int(ids[i]), dev[off[i]:off[i] + N * N], float(t.psf_fwhm[i]), float(t.sigma[i]),
                       (params[i, 4], params[i, 5]), init[i])
     srv1.advance(CFG["n_warmup"] + CFG["n_samples"])
-    hid, smp, st, _ = srv1.harvest(4)
+    hid, smp, st, _, _ = srv1.harvest(4)
     assert list(hid) == [ids[i]]
     assert np.array_equal(smp[0].cpu().numpy(), got[int(ids[i])][0])
     srv.close()
@@ -121,7 +123,7 @@ def test_slots_admission_by_footprint(bsi):
     inf = srv.info()
     assert inf["resident"] == 3 and inf["pending"] == 3
     srv.advance(CFG["n_warmup"] + CFG["n_samples"])
-    hid, smp, st, status = srv.harvest(2)
+    hid, smp, st, status, _ = srv.harvest(2)
     assert list(hid) == [0, 1]
     assert np.all(np.isfinite(smp.cpu().numpy()))
     assert srv.info()["resident"] == 1
@@ -130,3 +132,72 @@ def test_slots_admission_by_footprint(bsi):
     with pytest.raises(Exception):
         srv.admit(4, dev[:25 * 25], 0.7, 1.0, (0, 0), init[4])     # size not served
     srv.close()
+
+
+def test_slots_ess_target(bsi):
+    """Requests asking for an ESS: each finishes at the first check (every
+    20 draws after warmup) where the mean ESS over the six parameters reaches
+    the target, by the oracle's ESS of the returned draws, or at the draw
+    cap; draws past the stop are NaN; and the request alone in a one-galaxy
+    bsi_hmc_sample with n_samples = n_draws gives the same draws and chain
+    statistics bitwise (the chains wait at each check)."""
+    import torch
+    _log("slots ESS target")
+    cfg_d = dict(CFG, n_chains=2, n_warmup=12, n_samples=120)
+    every, target = 20, 45.0
+    rng = np.random.default_rng(80)
+    n = 14
+    sizes = rng.choice([25, 41, 53], n)
+    t, params, data, off = synth.make_population("uneven", n_gal=n, seed=81, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, 2, seed=82)
+    dev = torch.tensor(data).cuda()
+    cfg = bsi.HmcConfig(**cfg_d)
+    srv = bsi.Slots([25, 41, 53], cfg, hbm_budget=64 << 20, max_slots=5, ess_target=target,
+                    ess_every=every)
+    ids = 500 + np.arange(n)
+    queue = list(range(n))
+    got = {}
+    ticks = 0
+    while len(got) < n:
+        while queue:
+            i = queue[0]
+            N = int(t.n_pix[i])
+            if not srv.admit(int(ids[i]), dev[off[i]:off[i] + N * N], float(t.psf_fwhm[i]),
+                             float(t.sigma[i]), (params[i, 4], params[i, 5]), init[i]):
+                break
+            queue.pop(0)
+        srv.advance(int(rng.integers(3, 11)))
+        ticks += 1
+        srv.poll()
+        hid, smp, st, status, nd = srv.harvest(n)
+        for k, rid in enumerate(hid):
+            assert int(rid) not in got
+            got[int(rid)] = (smp[k].cpu().numpy(), st[k].cpu().numpy(), int(nd[k]))
+        assert ticks < 400
+    inf = srv.info()
+    assert inf["resident"] == 0 and inf["arena_free"] == inf["arena_bytes"]
+    srv.close()
+    early = 0
+    for i in range(n):
+        smp, st, nd = got[int(ids[i])]
+        assert nd % every == 0 and every <= nd <= cfg_d["n_samples"], nd
+        assert np.all(np.isfinite(smp[:, :nd])) and np.all(np.isnan(smp[:, nd:]))
+        x = smp.astype(np.float64)
+        e_at = np.mean(diagnostics.ess_params(x[:, :nd]))
+        if nd < cfg_d["n_samples"]:
+            early += 1
+            assert e_at >= target * (1 - 1e-4), (i, nd, e_at)
+        if nd > every:
+            e_prev = np.mean(diagnostics.ess_params(x[:, :nd - every]))
+            assert e_prev < target * (1 + 1e-4), (i, nd, e_prev)
+        # alone, with the draws the server returned
+        N = int(t.n_pix[i])
+        b = bsi.Batch(n=np.array([N]), psf_fwhm=torch.tensor([t.psf_fwhm[i]], dtype=torch.float32).cuda(),
+                      sigma=torch.tensor([t.sigma[i]], dtype=torch.float32).cuda(), pixel_scale=PS)
+        ref = torch.tensor([[params[i, 4], params[i, 5]]], dtype=torch.float32).cuda()
+        ini = torch.tensor(init[i][None], dtype=torch.float32).cuda()
+        c1 = bsi.HmcConfig(uid_base=int(ids[i]) * 2, **dict(cfg_d, n_samples=nd))
+        s1, st1, _ = bsi.hmc_sample(b, dev[off[i]:off[i] + N * N].contiguous(), ref, ini, c1)
+        assert np.array_equal(s1[0].cpu().numpy(), smp[:, :nd]), i
+        assert np.array_equal(st1[0].cpu().numpy(), st), i
+    assert early >= 1
