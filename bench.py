@@ -213,6 +213,37 @@ def shear_leg(api, torch, stream, smp, G, K, seed):
                          "alg_bytes_per_pass": bytes_pass}}
 
 
+def render_flops(N):
+    """(algorithmic, executed) flops of one stamp's render as two dense DFT
+    products: pass 1 complex (rows v = 0..h) x (u = -h..h) x (x), 8 flops per
+    complex multiply-add; pass 2 real, 4 flops per (y, x, v).  Executed: the
+    MFMA tiles the kernel issues (16 x 16 x 4, 2048 flops each), padding
+    included."""
+    h = N // 2
+    ntab, nrow = 2 * h + 1, h + 1
+    alg = 8 * nrow * ntab * N + 4 * N * N * nrow
+    ldT, nrow4, Np = (ntab + 3) // 4 * 4, (nrow + 3) // 4 * 4, (N + 15) // 16 * 16
+    n1 = ((nrow + 15) // 16) * (Np // 16) * (ldT // 4) * 4
+    n2 = (Np // 16) ** 2 * (nrow4 // 4) * 2
+    return alg, (n1 + n2) * 2048
+
+
+def transform_leg(api, sizes=(25, 41, 53, 73, 101), n_gal=10_000):
+    """Render of n_gal stamps per size with each transform (direct float64
+    sums vs FP32 DFT-as-GEMM on MFMA), best of five, and the choice kept."""
+    res = api.autotune_transform(list(sizes), n_gal=n_gal)
+    out = {}
+    for N, (m, t_d, t_m, f_d, f_m) in res.items():
+        alg, exe = render_flops(N)
+        out[N] = {"direct_ms": round(t_d, 4), "mfma_ms": round(t_m, 4),
+                  "forward_direct_ms": round(f_d, 4), "forward_mfma_ms": round(f_m, 4),
+                  "chosen": "mfma" if m == api.N.TRANSFORM_MFMA else "direct",
+                  "mfma_alg_tflops": round(alg * n_gal / (t_m * 1e-3) / 1e12, 2),
+                  "mfma_exec_tflops": round(exe * n_gal / (t_m * 1e-3) / 1e12, 2),
+                  "mfma_exec_frac_fp32_peak": round(exe * n_gal / (t_m * 1e-3) / 157.3e12, 4)}
+    return {"n_gal": n_gal, "by_size": out}
+
+
 def shear_pass_leg(api, torch, stream, reps, G=10_000, K=1000):
     """One evaluation pass of the shear-level sampler (4 points with gradient)
     over G x K synthetic interim samples, repeated `reps` times without a
@@ -392,6 +423,8 @@ def main():
                     "serving legs (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
+    ap.add_argument("--transform-only", action="store_true",
+                    help="only the render-transform comparison (both transforms, workload sizes)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="--workload serving: this many Poisson requests at 2000/s (overrides "
                          "--serve-window; only the ESS-targeted run and the capacity are measured)")
@@ -409,6 +442,12 @@ def main():
               "part of this build", file=sys.stderr)
         sys.exit(2)
     log = lambda m: print(m, file=sys.stderr, flush=True)
+    if args.transform_only:
+        import torch
+        from paper_2604_22048_amd import api
+        torch.cuda.init()
+        print(json.dumps({"transform": transform_leg(api)}), flush=True)
+        return
     if args.workload != "uniform":
         import torch
         from paper_2604_22048_amd import api
@@ -537,6 +576,8 @@ def main():
         legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
         log(f"[bench] shear-level HMC: {legs['shear_hmc']['t_s']} s")
         del results, r["smp"]
+        legs["transform"] = transform_leg(api)
+        log(f"[bench] render transforms: {legs['transform']}")
         if not args.no_serving:
             legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log)
     out = {

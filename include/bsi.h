@@ -109,7 +109,8 @@ typedef struct {
 
 /*
  * bsi_render_stamps -- noiseless model stamps (Section 3.2: exponential
- * profile convolved with the known PSF, integrated over pixels).
+ * profile convolved with the known PSF, integrated over pixels), through the
+ * handle's transform for each stamp side (bsi_set_transform).
  * The stamp is the truncated Fourier series on the stamp's frequency grid:
  *   m[j,i] = N^-2 sum_{u,v} w_u w_v T(u,v) exp(i(k_u x_i + k_v y_j)),
  *   k_u = 2 pi u / N, u in -floor(N/2)..floor(N/2), w = 1/2 at u = +-N/2 for
@@ -314,6 +315,40 @@ int bsi_get_plan(bsi_handle h, int32_t n, int32_t* P, int32_t* slots);
  * (both nullable).  Allocates and frees its own device buffers; synchronous. */
 int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_chains,
                  int32_t* chosen, float* ms);
+
+/* ---- Render transform per stamp side ------------------------------------
+ *
+ * bsi_render_stamps evaluates the spectrum on the half plane and transforms
+ * it to pixels in one of two ways (results agree to float32 rounding, about
+ * 1e-6 of the peak):
+ *   BSI_TRANSFORM_DIRECT  direct DFT sums in float64 on the vector ALUs,
+ *                         stamp, spectrum row and half-transform in LDS;
+ *   BSI_TRANSFORM_MFMA    two dense DFT products (rows, then columns) on the
+ *                         FP32 matrix cores (v_mfma_f32_16x16x4_f32), sizes
+ *                         padded to tiles of 16, spectrum and half-transform
+ *                         in LDS (the default).
+ * The same choice applies to the forward transform of stamps (data, or data
+ * minus model for BSI_LIK_PIXEL) at the likelihood's half-plane bins, done
+ * per galaxy before sampling: direct FP32 sums, or two FP32 DFT products on
+ * the matrix cores (sides whose LDS need exceeds 160 KiB use the direct
+ * sums).  The k-space likelihood of the sampler needs no per-step transform. */
+enum { BSI_TRANSFORM_DEFAULT = 0, BSI_TRANSFORM_DIRECT = 1, BSI_TRANSFORM_MFMA = 2 };
+
+/* Set the render transform of stamp side n (8..128); DEFAULT resets it. */
+int bsi_set_transform(bsi_handle h, int32_t n, int32_t method);
+
+/* The transform stamp side n uses on this handle. */
+int bsi_get_transform(bsi_handle h, int32_t n, int32_t* method);
+
+/* Time, for a synthetic batch of n_gal galaxies of each side sizes[i]
+ * (exponential profile, best of five), the render and the forward transform
+ * of the stamps at the likelihood's bins with each method, and keep the
+ * method with the smaller sum on the handle (it serves both directions).
+ * chosen [host] int32[n_sizes] and ms [host] float[n_sizes][4] (render
+ * direct, render MFMA, forward direct, forward MFMA; milliseconds per batch)
+ * are nullable.  Allocates and frees its own device buffers; synchronous. */
+int bsi_autotune_transform(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_gal,
+                           int32_t* chosen, float* ms);
 
 /* ---- Request serving: slot-based continuous batching of phase 1 ----------
  *

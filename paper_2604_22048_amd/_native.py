@@ -20,6 +20,9 @@ LIK_KSPACE = 0
 LIK_PIXEL = 1
 METRIC_GIVEN = 0
 METRIC_FISHER = 1
+TRANSFORM_DEFAULT = 0
+TRANSFORM_DIRECT = 1
+TRANSFORM_MFMA = 2
 FORM_BATCHED = 0
 FORM_PLAIN = 1
 E_BA14 = 0
@@ -112,6 +115,10 @@ SIGNATURES = {
     "bsi_slots_get_info": (C.c_int, [C.c_void_p, C.POINTER(SlotsInfo)]),
     "bsi_set_plan": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
     "bsi_get_plan": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "bsi_set_transform": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32]),
+    "bsi_get_transform": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32)]),
+    "bsi_autotune_transform": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "bsi_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "bsi_ess": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,

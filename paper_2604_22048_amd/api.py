@@ -435,6 +435,32 @@ def autotune(sizes, n_chains: int = 4, lib: Library | None = None):
     return {int(sizes[i]): (int(ch[i]), float(ms[i]) if ms[i] >= 0 else None) for i in range(n)}
 
 
+def set_transform(n: int, method: int, lib: Library | None = None):
+    """Render transform for stamp side n (N.TRANSFORM_*; DEFAULT resets)."""
+    lib = lib or get()
+    lib.check(lib.lib.bsi_set_transform(lib.h, int(n), int(method)), "bsi_set_transform")
+
+
+def get_transform(n: int, lib: Library | None = None) -> int:
+    lib = lib or get()
+    m = C.c_int32()
+    lib.check(lib.lib.bsi_get_transform(lib.h, int(n), C.byref(m)), "bsi_get_transform")
+    return int(m.value)
+
+
+def autotune_transform(sizes, n_gal: int = 10000, lib: Library | None = None):
+    """Time both transforms per size (render and forward DFT of n_gal stamps)
+    and keep the faster: {N: (method, ms render direct, render MFMA, forward
+    direct, forward MFMA)}."""
+    lib = lib or get()
+    n = len(sizes)
+    sz = (C.c_int32 * max(n, 1))(*[int(x) for x in sizes])
+    ch = (C.c_int32 * max(n, 1))()
+    ms = (C.c_float * max(4 * n, 4))()
+    lib.check(lib.lib.bsi_autotune_transform(lib.h, n, sz, int(n_gal), ch, ms), "bsi_autotune_transform")
+    return {int(sizes[i]): (int(ch[i]), *[float(ms[4 * i + m]) for m in range(4)]) for i in range(n)}
+
+
 def ess(samples: torch.Tensor, lib: Library | None = None):
     """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]."""
     dev = samples.device

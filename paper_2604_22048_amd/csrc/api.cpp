@@ -110,10 +110,10 @@ int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* 
   int rc;
   if ((rc = ensure(h, h->dh, (size_t)p.total_bins * sizeof(float2)))) return rc;
   for (const ClassRange& c : p.classes) {
-    hipError_t e = launch_dft_bins(data, model, gidx_ptr(h, c), c.count,
-                                   static_cast<const int64_t*>(h->off.p),
-                                   static_cast<const int64_t*>(h->bin_off.p), c.N, c.P,
-                                   static_cast<float2*>(h->dh.p), chi2, b->sigma, s);
+    hipError_t e = launch_stamp_dft(transform_of(h, c.N) == BSI_TRANSFORM_MFMA, data, model,
+                                    gidx_ptr(h, c), c.count, static_cast<const int64_t*>(h->off.p),
+                                    static_cast<const int64_t*>(h->bin_off.p), c.N, c.P,
+                                    static_cast<float2*>(h->dh.p), chi2, s);
     if (e != hipSuccess) return hip_fail(h, e, "dft_bins launch");
   }
   return BSI_OK;
@@ -220,9 +220,13 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
   if ((rc = upload_plan(h, batch, p, s))) return rc;
   const float rs = profile_rscale(batch->profile, batch->pixel_scale);
   for (const ClassRange& c : p.classes) {
-    hipError_t e = launch_render(params, batch->psf_fwhm, gidx_ptr(h, c), c.count,
-                                 static_cast<const int64_t*>(h->off.p), c.N, rs,
-                                 1.0f / batch->pixel_scale, batch->profile, out, s);
+    const int32_t* gi = gidx_ptr(h, c);
+    const int64_t* off = static_cast<const int64_t*>(h->off.p);
+    hipError_t e = transform_of(h, c.N) == BSI_TRANSFORM_MFMA
+        ? launch_render_mfma(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
+                             1.0f / batch->pixel_scale, batch->profile, out, s)
+        : launch_render(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
+                        1.0f / batch->pixel_scale, batch->profile, out, s);
     if (e != hipSuccess) return hip_fail(h, e, "render launch");
   }
   return BSI_OK;

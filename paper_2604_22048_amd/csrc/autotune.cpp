@@ -1,5 +1,6 @@
-// Slot-plan selection per stamp side: explicit (bsi_set_plan) or measured
-// on the device (bsi_autotune).
+// Per-stamp-side choices held by a handle, explicit or measured on the
+// device: the trajectory kernel's slot plan (bsi_set_plan, bsi_autotune) and
+// the render transform (bsi_set_transform, bsi_autotune_transform).
 #include "bsi.h"
 
 #include <hip/hip_runtime.h>
@@ -182,7 +183,8 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
         if (e != hipSuccess) break;
         if (hmc_lds_bytes(N, C, P, 1) > 160 * 1024) continue;
         a.P = P;
-        e = launch_dft_bins(data, nullptr, gidx, G, off, boff, N, P, dh, nullptr, sig, s);
+        e = launch_stamp_dft(transform_of(h, N) == BSI_TRANSFORM_MFMA, data, nullptr, gidx, G, off,
+                             boff, N, P, dh, nullptr, s);
         if (e == hipSuccess) {
           a.n_steps = 0;
           e = launch_hmc_init(a, G, s);
@@ -213,6 +215,112 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
     h->plan_P[N] = best_P;
     if (chosen) chosen[i] = best_P;
     if (ms_out) ms_out[i] = best_ms;
+  }
+  return BSI_OK;
+}
+
+int bsi_set_transform(bsi_handle h, int32_t n, int32_t method) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n < 8 || n > kMaxN) return fail(h, BSI_EINVAL, "stamp side %d outside [8, %d]", n, kMaxN);
+  if (method != BSI_TRANSFORM_DEFAULT && method != BSI_TRANSFORM_DIRECT && method != BSI_TRANSFORM_MFMA)
+    return fail(h, BSI_EINVAL, "unknown transform %d", method);
+  h->transform[n] = method;
+  return BSI_OK;
+}
+
+int bsi_get_transform(bsi_handle h, int32_t n, int32_t* method) {
+  if (!h || !method) return BSI_EINVAL;
+  if (n < 8 || n > kMaxN) return fail(h, BSI_EINVAL, "stamp side %d outside [8, %d]", n, kMaxN);
+  *method = transform_of(h, n);
+  return BSI_OK;
+}
+
+int bsi_autotune_transform(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_gal,
+                           int32_t* chosen, float* ms_out) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n_sizes < 0 || (n_sizes > 0 && !sizes)) return fail(h, BSI_EINVAL, "sizes is NULL");
+  if (n_gal < 1 || n_gal > (1 << 20)) return fail(h, BSI_EINVAL, "n_gal must be 1..2^20");
+  for (int i = 0; i < n_sizes; ++i)
+    if (sizes[i] < 8 || sizes[i] > kMaxN)
+      return fail(h, BSI_EUNSUPPORTED, "stamp side %d outside [8, %d]", sizes[i], kMaxN);
+  hipSetDevice(h->device);
+  hipStream_t s = h->own;
+  const int G = n_gal;
+  const float pixel_scale = 0.2f;
+  const float rs = profile_rscale(kProfExpHost, pixel_scale);
+  for (int i = 0; i < n_sizes; ++i) {
+    const int N = sizes[i];
+    Scratch sc;
+    const int64_t npx = (int64_t)N * N;
+    const int P = make_slot_plan(N).P;
+    const int nb = make_slot_plan_p(N, P).nbins;
+    float* out = sc.get<float>((size_t)G * npx);
+    float* psf = sc.get<float>(G);
+    float* prm = sc.get<float>((size_t)G * 6);
+    int32_t* gidx = sc.get<int32_t>(G);
+    int64_t* off = sc.get<int64_t>(G);
+    int64_t* boff = sc.get<int64_t>(G);
+    float2* dh = sc.get<float2>((size_t)G * nb);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (sc.err == hipSuccess) sc.err = hipEventCreate(&e0);
+    if (sc.err == hipSuccess) sc.err = hipEventCreate(&e1);
+    if (sc.err != hipSuccess) {
+      (void)hipGetLastError();
+      if (e0) (void)hipEventDestroy(e0);
+      return fail(h, BSI_ENOMEM, "transform autotune buffers for N = %d", N);
+    }
+    // galaxies with varied shapes and centroids (F = 1000, hlr 0.3-0.9")
+    std::vector<float> hp((size_t)G * 6), hpsf(G);
+    std::vector<int32_t> hg(G);
+    std::vector<int64_t> ho(G), hb(G);
+    for (int g = 0; g < G; ++g) {
+      const float f = (float)(g % 97) / 97.0f;
+      const float p6[6] = {1000.0f, 0.3f + 0.6f * f, 0.3f * f - 0.15f, 0.1f - 0.2f * f, f - 0.5f,
+                           0.5f - f};
+      std::copy(p6, p6 + 6, hp.begin() + 6 * g);
+      hpsf[g] = 0.6f + 0.3f * f;
+      hg[g] = g;
+      ho[g] = g * npx;
+      hb[g] = (int64_t)g * nb;
+    }
+    hipError_t e = hipMemcpy(prm, hp.data(), hp.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(boff, hb.data(), G * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(psf, hpsf.data(), G * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(gidx, hg.data(), G * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(off, ho.data(), G * 8, hipMemcpyHostToDevice);
+    // 0, 1: render direct / MFMA; 2, 3: forward DFT of the rendered stamps direct / MFMA
+    float best[4] = {-1.0f, -1.0f, -1.0f, -1.0f};
+    for (int m = 0; m < 4 && e == hipSuccess; ++m) {
+      auto run = [&]() {
+        switch (m) {
+          case 0: return launch_render(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale, kProfExpHost,
+                                       out, s);
+          case 1: return launch_render_mfma(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale,
+                                            kProfExpHost, out, s);
+          default: return launch_stamp_dft(m == 3, out, nullptr, gidx, G, off, boff, N, P, dh, nullptr, s);
+        }
+      };
+      e = run();     // warm
+      for (int r = 0; r < 5 && e == hipSuccess; ++r) {
+        e = hipEventRecord(e0, s);
+        if (e == hipSuccess) e = run();
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e == hipSuccess && (best[m] < 0.0f || t < best[m])) best[m] = t;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(h, e, "transform autotune");
+    const int pick = best[1] + best[3] <= best[0] + best[2] ? BSI_TRANSFORM_MFMA : BSI_TRANSFORM_DIRECT;
+    h->transform[N] = pick;
+    if (chosen) chosen[i] = pick;
+    if (ms_out)
+      for (int m = 0; m < 4; ++m) ms_out[4 * i + m] = best[m];
   }
   return BSI_OK;
 }

@@ -22,6 +22,21 @@ inline float profile_rscale(int prof, float pixel_scale) {
 // ---- transform.hip ----
 size_t dft_bins_lds_bytes(int N);
 size_t render_lds_bytes(int N);
+size_t render_mfma_lds_bytes(int N);
+size_t dft_bins_mfma_lds_bytes(int N);
+// The transforms as FP32 DFT products on the matrix cores (dft_mfma.hip)
+hipError_t launch_render_mfma(const float* params, const float* psf, const int32_t* gidx, int n,
+                              const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                              float* out, hipStream_t s);
+hipError_t launch_dft_bins_mfma(const float* data, const double* model, const int32_t* gidx, int n,
+                                const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
+                                double* chi2, hipStream_t s);
+// Forward DFT at the half-plane bins by either transform (mfma: the matrix-
+// core form where its LDS fits, else the direct sums).
+inline hipError_t launch_stamp_dft(bool mfma, const float* data, const double* model,
+                                   const int32_t* gidx, int n, const int64_t* off,
+                                   const int64_t* bin_off, int N, int P, float2* out, double* chi2,
+                                   hipStream_t s);
 // The data spectrum is written in the slot order of plan (N, P).
 hipError_t launch_dft_bins(const float* data, const double* model, const int32_t* gidx, int n,
                            const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
@@ -205,6 +220,15 @@ hipError_t launch_slots_check(const int32_t* list, int n, int C, int W, int S, i
                               const ChainState* st, const float* samples, const SlotArrays& sa,
                               hipStream_t s);
 size_t slots_check_lds_bytes(int C, int S);
+
+inline hipError_t launch_stamp_dft(bool mfma, const float* data, const double* model,
+                                   const int32_t* gidx, int n, const int64_t* off,
+                                   const int64_t* bin_off, int N, int P, float2* out, double* chi2,
+                                   hipStream_t s) {
+  if (mfma && dft_bins_mfma_lds_bytes(N) <= 160 * 1024)
+    return launch_dft_bins_mfma(data, model, gidx, n, off, bin_off, N, P, out, chi2, s);
+  return launch_dft_bins(data, model, gidx, n, off, bin_off, N, P, out, chi2, nullptr, s);
+}
 
 // ---- diag.hip ----
 hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,

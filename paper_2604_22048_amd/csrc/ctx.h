@@ -27,9 +27,17 @@ struct bsi_ctx {
   hipEvent_t ev_join[kAuxStreams] = {};
   DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts, shear_state;
   int plan_P[129] = {};   // slot plan per stamp side (0: the default, fewest slots)
+  int transform[129] = {};   // render transform per stamp side (BSI_TRANSFORM_*, 0: default)
 };
 
 namespace bsi_host {
+
+// Render transform of stamp side N on handle h: the handle's choice, else
+// the default (the FP32 DFT-as-GEMM on the matrix cores, the faster of the
+// two at every workload size when measured).
+inline int transform_of(const bsi_ctx* h, int N) {
+  return h->transform[N] ? h->transform[N] : BSI_TRANSFORM_MFMA;
+}
 
 inline int fail(bsi_handle h, int code, const char* fmt, ...) {
   char buf[512];

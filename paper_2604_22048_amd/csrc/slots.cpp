@@ -99,6 +99,7 @@ struct SizeClass {
   int N;
   int P;                           // slot plan (the handle's at creation)
   int W;                           // waves per chain of the trajectory kernel
+  bool mfma;                       // data transform on the matrix cores (the handle's choice)
   int64_t stamp_bytes, bin_bytes;
   hipEvent_t ev_beg = nullptr, ev_end = nullptr;   // this size's last advance launch
   double tau = -1.0;               // measured milliseconds per iteration (-1: unknown)
@@ -252,6 +253,7 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
     c.N = N;
     c.P = h->plan_P[N] > 0 ? h->plan_P[N] : make_slot_plan(N).P;
     c.W = hmc_split_waves(N, sv->C, c.P, cfg->profile, hc.waves_per_chain);
+    c.mfma = transform_of(h, N) == BSI_TRANSFORM_MFMA;
     if (hmc_lds_bytes(N, sv->C, c.P, c.W) > 160 * 1024) {
       delete sv;
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", N, hc.n_chains);
@@ -487,9 +489,9 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     const int32_t* res = reinterpret_cast<const int32_t*>(sv->dev_up + res_at[i]);
     hipError_t x = hipSuccess;
     if (!k.fresh.empty()) {
-      x = launch_dft_bins(reinterpret_cast<const float*>(sv->arena), nullptr, fresh,
-                          (int)k.fresh.size(), sv->arr.off, sv->arr.bin_off, k.N, k.P,
-                          reinterpret_cast<float2*>(sv->arena), nullptr, sv->arr.sigma, st);
+      x = launch_stamp_dft(k.mfma, reinterpret_cast<const float*>(sv->arena), nullptr, fresh,
+                           (int)k.fresh.size(), sv->arr.off, sv->arr.bin_off, k.N, k.P,
+                           reinterpret_cast<float2*>(sv->arena), nullptr, st);
       if (x != hipSuccess) return x;
       HmcArgs a = base;
       a.N = k.N;

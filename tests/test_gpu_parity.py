@@ -55,16 +55,23 @@ def _random_params(rng, G, sizes):
 
 
 @pytest.mark.parametrize("profile", [render.PROFILE_EXP, render.PROFILE_GAUSS])
-def test_render_parity_ragged(bsi, profile):
+@pytest.mark.parametrize("transform", [1, 2])
+def test_render_parity_ragged(bsi, profile, transform):
+    """Both render transforms (float64 direct sums, FP32 MFMA products)."""
     import torch
-    _log(f"render parity profile={profile}")
+    _log(f"render parity profile={profile} transform={transform}")
     rng = np.random.default_rng(10 + profile)
     sizes = [8, 9, 25, 32, 41, 53, 64, 73, 101, 128, 25, 53]
     G = len(sizes)
     params = _random_params(rng, G, sizes)
     psf = rng.uniform(0.6, 0.9, G)
     b = _batch(bsi, torch, sizes, psf, profile=profile)
+    for N in set(sizes):
+        bsi.set_transform(N, transform)
+        assert bsi.get_transform(N) == transform
     out = bsi.render_stamps(b, torch.tensor(params, dtype=torch.float32).cuda()).cpu().numpy()
+    for N in set(sizes):
+        bsi.set_transform(N, 0)
     for i, N in enumerate(sizes):
         p32 = params[i].astype(np.float32).astype(np.float64)
         ref = render.render_one(p32, N, PS, float(np.float32(psf[i])), profile)
@@ -80,9 +87,12 @@ def _grad_scale(p, N, psf, sigma, profile):
 
 @pytest.mark.parametrize("method", [0, 1])
 @pytest.mark.parametrize("profile", [render.PROFILE_EXP, render.PROFILE_GAUSS])
-def test_loglik_grad_parity(bsi, method, profile):
+@pytest.mark.parametrize("transform", [1, 2])
+def test_loglik_grad_parity(bsi, method, profile, transform):
+    """Both likelihood methods, with the data (or residual) spectrum from
+    either transform (direct sums, MFMA products)."""
     import torch
-    _log(f"loglik parity method={method} profile={profile}")
+    _log(f"loglik parity method={method} profile={profile} transform={transform}")
     rng = np.random.default_rng(20 + method + 2 * profile)
     sizes = [8, 25, 32, 32, 41, 53, 73, 101, 128]
     G = len(sizes)
@@ -100,8 +110,12 @@ def test_loglik_grad_parity(bsi, method, profile):
     params[:, 2:4] += rng.uniform(-0.05, 0.05, (G, 2))
     params[:, 4:6] += rng.uniform(-0.2, 0.2, (G, 2))
     p32 = params.astype(np.float32).astype(np.float64)
+    for N in set(sizes):
+        bsi.set_transform(N, transform)
     ll, gr, st = bsi.loglik_grad(b, torch.tensor(data).cuda(),
                                  torch.tensor(p32, dtype=torch.float32).cuda(), method)
+    for N in set(sizes):
+        bsi.set_transform(N, 0)
     ll, gr, st = ll.cpu().numpy(), gr.cpu().numpy(), st.cpu().numpy()
     assert np.all(st == 0)
     for i, N in enumerate(sizes):
