@@ -99,7 +99,10 @@ def _oracle_worker(args):
     return time.perf_counter() - t0, n_iter * L
 
 
-def cpu_baseline_eval_rate(n_iter=40, L=20):
+CPU_ITERS = 400     # per core: about 10 s of oracle work on the host's cores
+
+
+def cpu_baseline_eval_rate(n_iter=CPU_ITERS, L=20):
     """Oracle gradient evaluations per second on the host, all usable cores."""
     import multiprocessing as mp
     cores = min(len(os.sched_getaffinity(0)), 16)
@@ -624,7 +627,7 @@ def main():
         out["cpu_baseline"] = {"value": round(cpu["rate"] / evals_per_gal, 6), "unit": "galaxies/s",
                                "cores": cpu["cores"], "kind": "oracle",
                                "sample": f"{cpu['evals']} float64 oracle gradient evaluations (53x53, "
-                                         f"one 40-iteration warmup chain per core) in "
+                                         f"one {CPU_ITERS}-iteration warmup chain per core) in "
                                          f"{cpu['wall']:.1f} s; galaxies/s = eval rate / evaluations "
                                          f"per galaxy at 300 ESS with the GPU run's n_eff"}
     print(json.dumps(out), flush=True)

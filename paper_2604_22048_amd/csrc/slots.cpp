@@ -229,7 +229,7 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   if (!(cfg->ess_target >= 0.0f) || !std::isfinite(cfg->ess_target))
     return fail(h, BSI_EINVAL, "ess_target must be finite and >= 0");
   if (cfg->ess_target > 0.0f && cfg->ess_every < 4) return fail(h, BSI_EINVAL, "ess_every must be >= 4");
-  if (cfg->ess_target > 0.0f && slots_check_lds_bytes(hc.n_chains, hc.n_samples) > 160 * 1024)
+  if (cfg->ess_target > 0.0f && slots_check_lds_bytes(hc.n_chains, hc.n_samples) > 150 * 1024)
     return fail(h, BSI_EUNSUPPORTED, "n_chains * n_samples too large for the on-device ESS check");
 
   bsi_slots_s* sv = new bsi_slots_s();
@@ -314,9 +314,10 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   sv->arr.done_n = reinterpret_cast<int32_t*>(take(4));
   sv->arena = p;
   sv->alloc.reset(arena_bytes);
-  // upload staging: records, start positions, and two slot lists per class
+  // upload staging: records, start positions, two slot lists per class, and
+  // the list of all resident slots (ESS checks)
   sv->up_bytes = align_up(ms * (int64_t)sizeof(SlotRecord)) + align_up(ms * C * 24) +
-                 align_up(ms * 4) * 2 * (int64_t)sv->cls.size();
+                 align_up(ms * 4) * (2 * (int64_t)sv->cls.size() + 1);
   e = hipHostMalloc(reinterpret_cast<void**>(&sv->pinned), (size_t)sv->up_bytes, hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&sv->rd), (size_t)(ms + 1) * 4, hipHostMallocDefault);
@@ -449,12 +450,15 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
   const int64_t rec_at = place(sv->rec.data(), (int64_t)n_new * (int64_t)sizeof(SlotRecord));
   const int64_t init_at = place(sv->rec_init.data(), (int64_t)n_new * C * 24);
   std::vector<int64_t> fresh_at(sv->cls.size()), res_at(sv->cls.size());
+  std::vector<int32_t> all_res;
   for (size_t i = 0; i < sv->cls.size(); ++i) {
     SizeClass& k = sv->cls[i];
     k.resident.insert(k.resident.end(), k.fresh.begin(), k.fresh.end());
     fresh_at[i] = place(k.fresh.data(), (int64_t)k.fresh.size() * 4);
     res_at[i] = place(k.resident.data(), (int64_t)k.resident.size() * 4);
+    if (sv->ess) all_res.insert(all_res.end(), k.resident.begin(), k.resident.end());
   }
+  const int64_t all_at = place(all_res.data(), (int64_t)all_res.size() * 4);
   if (pos > 0) {
     e = hipMemcpyAsync(sv->dev_up, hp, (size_t)pos, hipMemcpyHostToDevice, sv->s);
     if (e == hipSuccess) e = hipEventRecord(sv->ev_up, sv->s);
@@ -516,13 +520,12 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
   });
   if (e != hipSuccess) return hip_fail(h, e, "advance launch");
   if (sv->ess) {
-    // checks at the requests' stops; finished requests are read back by a poll
-    for (int i : active) {
-      e = launch_slots_check(reinterpret_cast<const int32_t*>(sv->dev_up + res_at[i]),
-                             (int)sv->cls[i].resident.size(), C, sv->cfg.hmc.n_warmup, sv->S, every,
-                             sv->cfg.ess_target, sv->state, sv->samples, sv->arr, sv->s);
-      if (e != hipSuccess) return hip_fail(h, e, "ESS check launch");
-    }
+    // checks at the requests' stops (one launch over every resident request);
+    // finished requests are read back by a poll
+    e = launch_slots_check(reinterpret_cast<const int32_t*>(sv->dev_up + all_at), (int)all_res.size(), C,
+                           sv->cfg.hmc.n_warmup, sv->S, every, sv->cfg.ess_target, sv->state,
+                           sv->samples, sv->arr, sv->s);
+    if (e != hipSuccess) return hip_fail(h, e, "ESS check launch");
     for (SizeClass& k : sv->cls) {
       k.fresh.clear();
       if (sv->cfg.pace && !k.resident.empty()) k.last_k = iters[&k - sv->cls.data()];

@@ -74,7 +74,7 @@ slots_gather_kernel(const int32_t* __restrict__ list, int C, int S, const ChainS
 __global__ void __launch_bounds__(256)
 slots_check_kernel(const int32_t* __restrict__ list, int C, int W, int S, int every, float target,
                    const ChainState* __restrict__ st, const float* __restrict__ samples, SlotArrays sa) {
-  extern __shared__ double sm[];
+  extern __shared__ double xs[];
   __shared__ EssShared es;
   __shared__ int s_fin;
   const int slot = list[blockIdx.x];
@@ -84,12 +84,10 @@ slots_check_kernel(const int32_t* __restrict__ list, int C, int W, int S, int ev
   if (threadIdx.x == 0) s_fin = n >= S;
   __syncthreads();
   if (!s_fin) {
-    double* xs = sm;
-    double* rho = xs + (size_t)C * n;
     double sum = 0.0;                  // thread 0
     for (int par = 0; par < 6; ++par) {
       float e = 0.f, r = 0.f;
-      ess_one_param(samples + (int64_t)slot * C * S * 6, C, n, S, 6, par, xs, rho, es, e, r);
+      ess_one_param(samples + (int64_t)slot * C * S * 6, C, n, S, 6, par, xs, es, e, r);
       sum += (double)e;
     }
     if (threadIdx.x == 0) s_fin = sum / 6.0 >= (double)target;
@@ -123,7 +121,7 @@ hipError_t launch_slots_gather(const int32_t* list, int n, int C, int S, const C
   return hipGetLastError();
 }
 
-size_t slots_check_lds_bytes(int C, int S) { return sizeof(double) * ((size_t)C * S + 256); }
+size_t slots_check_lds_bytes(int C, int S) { return sizeof(double) * (size_t)C * S; }
 
 hipError_t launch_slots_check(const int32_t* list, int n, int C, int W, int S, int every, float target,
                               const ChainState* st, const float* samples, const SlotArrays& sa,
