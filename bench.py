@@ -426,6 +426,8 @@ def main():
                     "serving legs (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
+    ap.add_argument("--plan", type=int, default=0,
+                    help="uniform workload: this slot plan P for the 53-pixel kernel instead of autotuning")
     ap.add_argument("--transform-only", action="store_true",
                     help="only the render-transform comparison (both transforms, workload sizes)")
     ap.add_argument("--serve-requests", type=int, default=0,
@@ -504,7 +506,11 @@ def main():
     torch.cuda.init()
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
-    plans = api.autotune([cfg.n_pix], n_chains=cfg.chains)
+    if args.plan:
+        api.set_plan(cfg.n_pix, args.plan)          # fixed slot plan (profiling runs)
+        plans = {cfg.n_pix: (args.plan, None)}
+    else:
+        plans = api.autotune([cfg.n_pix], n_chains=cfg.chains)
     log(f"[bench] slot plans {plans}")
     t, b, data, ref, init = make_inputs(api, torch, G, cfg)
     N = cfg.n_pix
