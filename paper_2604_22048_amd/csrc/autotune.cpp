@@ -76,7 +76,7 @@ int bsi_get_plan(bsi_handle h, int32_t n, int32_t* P, int32_t* slots) {
   if (!h || !P) return BSI_EINVAL;
   if (n < 8 || n > kMaxN) return fail(h, BSI_EINVAL, "stamp side %d outside [8, %d]", n, kMaxN);
   *P = h->plan_P[n] > 0 ? h->plan_P[n] : make_slot_plan(n).P;
-  if (slots) *slots = make_slot_plan_p(n, *P).nslots;
+  if (slots) *slots = 2 * make_slot_plan_p(n, *P).nslots;
   return BSI_OK;
 }
 

@@ -301,21 +301,24 @@ __global__ void __launch_bounds__(256) dft_bins_mfma_kernel(
     }
   }
   __syncthreads();
-  // slot order: row 0 scaled by 1/sqrt 2, unused slots zero, then the Nyquist bins
+  // pair-slot order (slot_value_uv's scales, padding zero), then the
+  // Nyquist bins, then zero up to the even length
   const SlotPlan sp = make_slot_plan_p(N, P);
   float2* dst = out + bin_off[gal];
   for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) {
     int u, v;
     float scale = 1.0f;
-    if (b < sp.nslots) {
-      if (!slot_uv(N, sp, b, u, v)) {
+    if (b < 2 * sp.nslots) {
+      if (!slot_value_uv(N, sp, b, u, v, scale)) {
         dst[b] = make_float2(0.f, 0.f);
         continue;
       }
-      if (v == 0) scale = 0.70710678118654752f;
-    } else {
+    } else if (b < 2 * sp.nslots + sp.nspec) {
       int cm;
-      nyq_bin_uv(N, b - sp.nslots, u, v, cm);
+      nyq_bin_uv(N, b - 2 * sp.nslots, u, v, cm);
+    } else {
+      dst[b] = make_float2(0.f, 0.f);
+      continue;
     }
     const float2 z = D[((v < 0) ? h : v) * N + (u + h)];
     dst[b] = make_float2(scale * z.x, scale * z.y);

@@ -676,13 +676,14 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 }
 
 // Trajectory kernels specialised for the stamp sizes of the workloads
-// (compile-time geometry, fully unrolled bin loop), one per candidate plan
-// (the plans within 10 % of the fewest slots, at most three), and for the
-// default plan also split over 2 and 4 waves per chain; other sizes and
-// plans use the generic kernel of their P.
+// (compile-time geometry, fully unrolled pair loop), one per candidate plan
+// (the plans within 10 % of the fewest pair-slots, at most three; for 41 also
+// P = 4 beside the single best), and for the default plan also split over 2
+// and 4 waves per chain; other sizes and plans use the generic kernel of
+// their P.
 #define BSI_FIXED_PLANS(X) \
-  X(25, 2) X(25, 3) X(25, 6) X(32, 1) X(32, 2) X(32, 4) X(41, 2) X(41, 5) \
-  X(53, 6) X(53, 8) X(53, 5) X(73, 6) X(73, 8) X(73, 5) X(101, 5) X(101, 8)
+  X(25, 3) X(32, 1) X(32, 2) X(32, 4) X(41, 1) X(41, 4) \
+  X(53, 3) X(53, 4) X(53, 6) X(73, 3) X(73, 6) X(73, 8) X(101, 4) X(101, 5)
 
 template <int PROF, int NFIX, int PP>
 static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
@@ -726,12 +727,12 @@ int hmc_split_waves(int N, int C, int P, int prof, int max_w) {
 const int* hmc_fixed_plans(int N) {
   static const int none[] = {0};
   switch (N) {
-    case 25: { static const int p[] = {2, 3, 6, 0}; return p; }
+    case 25: { static const int p[] = {3, 0}; return p; }
     case 32: { static const int p[] = {1, 2, 4, 0}; return p; }
-    case 41: { static const int p[] = {2, 5, 0}; return p; }
-    case 53: { static const int p[] = {6, 8, 5, 0}; return p; }
-    case 73: { static const int p[] = {6, 8, 5, 0}; return p; }
-    case 101: { static const int p[] = {5, 8, 0}; return p; }
+    case 41: { static const int p[] = {1, 4, 0}; return p; }
+    case 53: { static const int p[] = {3, 4, 6, 0}; return p; }
+    case 73: { static const int p[] = {3, 6, 8, 0}; return p; }
+    case 101: { static const int p[] = {4, 5, 0}; return p; }
     default: return none;
   }
 }

@@ -40,32 +40,38 @@ enum { kProfExp = 0, kProfGauss = 1 };
 // Supported iterations per super-row (template instances of the bin loop).
 constexpr int kPlanP[] = {1, 2, 3, 4, 5, 6, 8};
 
+// Half-plane bins of the odd core (nc = N, or N - 1 for even N, columns u =
+// -hc..hc, rows v = 0..hc) in pair-slots: pair-slot (j, v) holds the bins
+// (+j, v) and (-j, v) for j = 1..hc, and for j = 0 the bin (0, v) split into
+// two half-weight copies, so each row has npc = hc + 1 pair-slots.  A
+// super-row holds R rows in P * 64 pair-slots: lane l of iteration i takes
+// pair-slot l + 64 i, row offset (l + 64 i) / npc, column (l + 64 i) mod npc.
 struct SlotPlan {
   int R, P, nsr;      // rows per super-row, iterations per super-row, super-rows
-  int nslots;         // nsr * P * 64
+  int nslots;         // pair-slots: nsr * P * 64
   int ymax;           // nsr * R rows covered (>= hc + 1)
-  int nspec;          // special (Nyquist) bins after the slots: N + 1 for even N, else 0
-  int nbins;          // nslots + nspec: length of the stored data spectrum
+  int nspec;          // special (Nyquist) bins after the pair-slots: N + 1 for even N, else 0
+  int nbins;          // stored spectrum length in complex values: 2 nslots + nspec, made even
 };
 
+__host__ __device__ constexpr int pair_cols(int N) { return (((N & 1) ? N : N - 1) - 1) / 2 + 1; }
+
 // The slot plan of stamp side N with P iterations per super-row: R rows
-// per super-row (as many as P * 64 lanes hold, at most all rows), nsr
+// per super-row (as many as P * 64 pair-slots hold, at most all rows), nsr
 // super-rows.  P must give R >= 1 (plan_valid).
 __host__ __device__ constexpr SlotPlan make_slot_plan_p(int N, int P) {
-  const int nc = (N & 1) ? N : N - 1;
-  const int rows = (nc - 1) / 2 + 1;
-  const int R = (64 * P) / nc;
+  const int npc = pair_cols(N);
+  const int rows = npc;
+  const int R = (64 * P) / npc;
   const int Rr = R < rows ? R : rows;
   const int nsr = Rr > 0 ? (rows + Rr - 1) / Rr : 0;
   SlotPlan sp{Rr, P, nsr, nsr * P * 64, nsr * Rr, 0, 0};
   sp.nspec = (N & 1) ? 0 : N + 1;
-  sp.nbins = sp.nslots + sp.nspec;
+  sp.nbins = (2 * sp.nslots + sp.nspec + 1) & ~1;
   return sp;
 }
 
-__host__ __device__ constexpr bool plan_valid(int N, int P) {
-  return (64 * P) / ((N & 1) ? N : N - 1) >= 1;
-}
+__host__ __device__ constexpr bool plan_valid(int N, int P) { return (64 * P) / pair_cols(N) >= 1; }
 
 // Default plan: the supported P with the fewest slots (ties: smaller P).
 __host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
@@ -82,17 +88,24 @@ __host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
   return best;
 }
 
-// Slot -> (u, v) or invalid.  Row 0 data are stored scaled by 1/sqrt(2).
-__host__ __device__ inline bool slot_uv(int N, const SlotPlan& sp, int slot, int& u, int& v) {
-  const int nc = (N & 1) ? N : N - 1;
-  const int hc = (nc - 1) / 2;
+// Stored complex value b < 2 nslots -> its bin (u, v) and the scale of the
+// stored data, or invalid (padding, stored as zero).  Value 2 s holds (+j, v)
+// and 2 s + 1 holds (-j, v) of pair-slot s; the data are scaled by 1/sqrt(2)
+// in row 0 (whose bins all appear with their mirrors) and in column 0 (split
+// into two copies).
+__host__ __device__ inline bool slot_value_uv(int N, const SlotPlan& sp, int b, int& u, int& v,
+                                              float& scale) {
+  const int npc = pair_cols(N);
+  const int slot = b >> 1;
   const int per = sp.P * 64;
   const int sr = slot / per, s = slot - sr * per;
-  if (s >= sp.R * nc) return false;
-  const int ro = s / nc;
+  if (s >= sp.R * npc) return false;
+  const int ro = s / npc;
+  const int j = s - ro * npc;
   v = sr * sp.R + ro;
-  u = s - ro * nc - hc;
-  return v <= hc;
+  u = (b & 1) ? -j : j;
+  scale = (v == 0 ? 0.70710678118654752f : 1.0f) * (j == 0 ? 0.70710678118654752f : 1.0f);
+  return v < npc;
 }
 
 // Special (Nyquist) bin i of an even N -> DFT bin (u_b, v_b), Nyquist bins
@@ -163,24 +176,25 @@ __device__ __forceinline__ void profile_factor(const Shape& sh, float q, float& 
   }
 }
 
-// Geometry of one stamp size: grid sizes, slot plan and this lane's columns.
+// This lane's pair-columns: iteration i holds column j (bins +-j).
 template <int P>
 struct LaneCols {
-  float kx[P];       // k_x of the lane's column in iteration i (0 if unused)
-  float rok[P];      // row offset * kstep
-  int xi[P];         // index into the X table (u + h), or ntab (zero entry) if the slot is unused
+  float kx[P];       // k_x = j kstep of the lane's column in iteration i (0 if unused)
+  float sc[P];       // model scale: 1/sqrt(2) for column 0 (two half-weight copies), 1 else, 0 if unused
+  int xi[P];         // index into the X table (j + h), or ntab (zero entry) if the slot is unused
   int yo[P];         // row offset within the super-row
 };
 
-// Per-slot column table shared by the workgroup: entry (i, lane) =
-// {k_x, row offset * kstep, X index (ntab, a zero entry, if unused), row offset}.
+// Per-pair-slot column table shared by the workgroup: entry (i, lane) =
+// {k_x, model scale, X index (ntab, a zero entry, if unused), row offset}.
 __device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& sp, float4* tab) {
+  const int npc = g.hc + 1;
   for (int t = threadIdx.x; t < sp.P * 64; t += blockDim.x) {
     float4 e = make_float4(0.f, 0.f, __int_as_float(g.ntab), __int_as_float(0));
-    if (t < sp.R * g.nc) {
-      const int ro = t / g.nc;
-      const int u = t - ro * g.nc - g.hc;
-      e = make_float4((float)u * g.kstep, (float)ro * g.kstep, __int_as_float(u + g.h),
+    if (t < sp.R * npc) {
+      const int ro = t / npc;
+      const int j = t - ro * npc;
+      e = make_float4((float)j * g.kstep, j == 0 ? 0.70710678118654752f : 1.0f, __int_as_float(j + g.h),
                       __int_as_float(ro));
     }
     tab[t] = e;
@@ -195,7 +209,7 @@ __device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
   for (int i = 0; i < P; ++i) {
     const float4 e = tab[lane + 64 * i];
     c.kx[i] = e.x;
-    c.rok[i] = e.y;
+    c.sc[i] = e.y;
     c.xi[i] = __float_as_int(e.z);
     c.yo[i] = __float_as_int(e.w);
   }
@@ -249,45 +263,63 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
 
 // Accumulate the k-space sums of one wave (red: this wave's 2 KiB reduction
 // scratch in LDS).  dh: the data spectrum (or, with RESID, the spectrum of the
-// pixel residual d - m) in slot order followed by the Nyquist bins.  The X
-// table already contains the flux.  CHI2 = false skips sum |R|^2 (the
+// pixel residual d - m) in pair-slot order followed by the Nyquist bins.  The
+// X table already contains the flux.  CHI2 = false skips sum |R|^2 (the
 // gradient alone).  NFIX > 0: the stamp side is the compile-time constant
 // NFIX (fully unrolled super-row loop).  Result is lane-uniform.
 //
 // Per bin, with p = X Y the separable factor and T = G p the model spectrum,
 // R = D - T, and z' = conj(R) p: the sums are sum G z' (flux), sum G a^-1 z'
 // times kx^2, ky^2, kx ky (shape) and sum G Im z' times kx, ky (centroid).
-template <int PROF, int P, bool RESID>
-__device__ __forceinline__ void bin_step(const Shape& sh, float2 D, float4 y, float xr, float xim,
-                                         float TA, float Tc, float kx, float kx2, float& c2,
-                                         float& sF, float& sxx, float& syy, float& wky, float& sdx,
-                                         float& sdy, bool chi2) {
-  const float t = fmaf(Tc, y.z, fmaf(sh.tb, y.w, TA));
-  float G, Gw;
+//
+// One pair-slot holds the bins (+kx, ky) and (-kx, ky).  They share ky, the
+// row factor Y, kx^2 and |X|, and X(-kx) = conj X(kx) (the PSF-sinc factor is
+// even in kx), so the two profile arguments are t = base +- tc kx ky and the
+// two separable factors X Y and conj(X) Y share their four products.  The
+// kx-odd sums (kx ky and kx terms) take the difference of the pair's terms,
+// the even ones their sum; the kx and kx^2 factors are applied per column
+// after the loop.
+template <int PROF, bool RESID>
+__device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, float xr, float xi,
+                                          float TA, float Tc, float& c2, float& sF, float& swq,
+                                          float& syy, float& wky, float& sdx, float& sdy, bool chi2) {
+  const float base = fmaf(sh.tb, y.w, TA);
+  const float c = Tc * y.z;
+  const float tp = base + c, tm = base - c;
+  float Gp, Gm, Gwp, Gwm;
   if (PROF == kProfExp) {
-    const float rs = __builtin_amdgcn_rsqf(t);
-    const float rs2 = rs * rs;
-    G = rs2 * rs;
-    Gw = G * rs2;
+    const float rp = __builtin_amdgcn_rsqf(tp), rm = __builtin_amdgcn_rsqf(tm);
+    const float rp2 = rp * rp, rm2 = rm * rm;
+    Gp = rp2 * rp;
+    Gm = rm2 * rm;
+    Gwp = Gp * rp2;
+    Gwm = Gm * rm2;
   } else {
-    G = __builtin_amdgcn_exp2f(t);
-    Gw = G;
+    Gp = __builtin_amdgcn_exp2f(tp);
+    Gm = __builtin_amdgcn_exp2f(tm);
+    Gwp = Gp;
+    Gwm = Gm;
   }
-  const float pr = fmaf(xr, y.x, -xim * y.y);
-  const float pi = fmaf(xr, y.y, xim * y.x);
-  const float Rr = RESID ? D.x : fmaf(-G, pr, D.x);
-  const float Ri = RESID ? D.y : fmaf(-G, pi, D.y);
-  if (chi2) c2 = fmaf(Rr, Rr, fmaf(Ri, Ri, c2));
-  const float zr = fmaf(Rr, pr, Ri * pi);
-  const float zi = fmaf(Rr, pi, -Ri * pr);
-  sF = fmaf(G, zr, sF);
-  const float wq = Gw * zr;
-  sxx = fmaf(kx2, wq, sxx);
-  syy = fmaf(y.w, wq, syy);
-  wky = fmaf(y.z, wq, wky);
-  const float gz = G * zi;
-  sdx = fmaf(kx, gz, sdx);
-  sdy = fmaf(y.z, gz, sdy);
+  const float a = xi * y.y, b = xi * y.x;
+  const float ppr = fmaf(xr, y.x, -a), pmr = fmaf(xr, y.x, a);     // X Y, conj(X) Y
+  const float ppi = fmaf(xr, y.y, b), pmi = fmaf(xr, y.y, -b);
+  const float Rpr = RESID ? D.x : fmaf(-Gp, ppr, D.x);
+  const float Rpi = RESID ? D.y : fmaf(-Gp, ppi, D.y);
+  const float Rmr = RESID ? D.z : fmaf(-Gm, pmr, D.z);
+  const float Rmi = RESID ? D.w : fmaf(-Gm, pmi, D.w);
+  if (chi2) c2 = fmaf(Rpr, Rpr, fmaf(Rpi, Rpi, fmaf(Rmr, Rmr, fmaf(Rmi, Rmi, c2))));
+  const float zrp = fmaf(Rpr, ppr, Rpi * ppi), zip = fmaf(Rpr, ppi, -Rpi * ppr);
+  const float zrm = fmaf(Rmr, pmr, Rmi * pmi), zim = fmaf(Rmr, pmi, -Rmi * pmr);
+  sF = fmaf(Gp, zrp, sF);
+  sF = fmaf(Gm, zrm, sF);
+  const float wqp = Gwp * zrp;
+  const float ws = fmaf(Gwm, zrm, wqp), wd = fmaf(-Gwm, zrm, wqp);
+  swq += ws;
+  syy = fmaf(y.w, ws, syy);
+  wky = fmaf(y.z, wd, wky);
+  const float gzp = Gp * zip;
+  sdx = fmaf(-Gm, zim, sdx + gzp);
+  sdy = fmaf(y.z, fmaf(Gm, zim, gzp), sdy);
 }
 
 // Split evaluation (W > 1 waves per chain, NFIX kernels only): wave `part`
@@ -304,53 +336,56 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
                              float* xch = nullptr) {
   static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
   const int lane = lane_id();
-  float xr[P], xim[P], TA[P], Tc[P], kx2[P];
+  float xr[P], xi[P], TA[P], Tc[P];
   const float4* yp[P];
 #pragma unroll
   for (int i = 0; i < P; ++i) {
     const float2 x = X[lc.xi[i]];
-    xr[i] = x.x;
-    xim[i] = x.y;
-    kx2[i] = lc.kx[i] * lc.kx[i];
-    TA[i] = fmaf(sh.ta, kx2[i], sh.t0);
+    xr[i] = x.x * lc.sc[i];
+    xi[i] = x.y * lc.sc[i];
+    TA[i] = fmaf(sh.ta, lc.kx[i] * lc.kx[i], sh.t0);
     Tc[i] = sh.tc * lc.kx[i];
     yp[i] = Ym + lc.yo[i];
   }
   double chi2 = 0.0;
-  float sF = 0.f, sxx = 0.f, syy = 0.f, sxy = 0.f, sdx = 0.f, sdy = 0.f;
-  float wky[P];                       // per column: sum of k_y w (times k_x at the end)
+  float sF = 0.f, syy = 0.f, sdy = 0.f;
+  float swq[P], wky[P], sdc[P];       // per column: times kx^2, kx, kx after the loop
 #pragma unroll
-  for (int i = 0; i < P; ++i) wky[i] = 0.f;
-  const float2* dp = dh + lane;
+  for (int i = 0; i < P; ++i) {
+    swq[i] = 0.f;
+    wky[i] = 0.f;
+    sdc[i] = 0.f;
+  }
+  const float4* dp = reinterpret_cast<const float4*>(dh) + lane;
   if constexpr (NFIX > 0) {
     constexpr SlotPlan spc = make_slot_plan_p(NFIX, P);
     static_assert(spc.R >= 1, "P too small for NFIX");
     constexpr int K = (spc.nsr + W - 1) / W;   // super-rows of this wave (at most)
     // this wave's super-rows are part + k W, k = 0..K-1 (the last may not exist)
-    const float2* dq = dp + part * P * 64;
+    const float4* dq = dp + part * P * 64;
     const float4* yq[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) yq[i] = yp[i] + part * spc.R;
     if constexpr (W == 1) {
-      // software pipeline: the LDS reads of the next bin are issued before the
+      // software pipeline: the LDS reads of the next pair are issued before the
       // arithmetic of the current one
-      float2 Dn = dq[0];
+      float4 Dn = dq[0];
       float4 yn = yq[0][0];
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         float c2 = 0.f;
 #pragma unroll
         for (int i = 0; i < P; ++i) {
-          const float2 D = Dn;
+          const float4 D = Dn;
           const float4 y = yn;
-          const int b = k * P + i + 1;          // next bin
+          const int b = k * P + i + 1;          // next pair-slot
           if (b < K * P) {
             Dn = dq[b * 64];
             yn = yq[b % P][(b / P) * spc.R];
           }
-          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this bin's arithmetic
-          bin_step<PROF, P, RESID>(sh, D, y, xr[i], xim[i], TA[i], Tc[i], lc.kx[i], kx2[i], c2,
-                                   sF, sxx, syy, wky[i], sdx, sdy, CHI2);
+          __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
+          pair_step<PROF, RESID>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
+                                 sdc[i], sdy, CHI2);
         }
         if (CHI2) chi2 += (double)c2;
       }
@@ -360,8 +395,8 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         float c2 = 0.f;
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          bin_step<PROF, P, RESID>(sh, dq[i * 64], yq[i][0], xr[i], xim[i], TA[i], Tc[i], lc.kx[i],
-                                   kx2[i], c2, sF, sxx, syy, wky[i], sdx, sdy, CHI2);
+          pair_step<PROF, RESID>(sh, dq[i * 64], yq[i][0], xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i],
+                                 syy, wky[i], sdc[i], sdy, CHI2);
         if (CHI2) chi2 += (double)c2;
         dq += W * P * 64;
 #pragma unroll
@@ -374,14 +409,19 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
       const float4* yr = Ym + sr * sp.R;
 #pragma unroll
       for (int i = 0; i < P; ++i)
-        bin_step<PROF, P, RESID>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xim[i], TA[i], Tc[i],
-                                 lc.kx[i], kx2[i], c2, sF, sxx, syy, wky[i], sdx, sdy, CHI2);
+        pair_step<PROF, RESID>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xi[i], TA[i], Tc[i], c2, sF,
+                               swq[i], syy, wky[i], sdc[i], sdy, CHI2);
       if (CHI2) chi2 += (double)c2;
       dp += P * 64;
     }
   }
+  float sxx = 0.f, sxy = 0.f, sdx = 0.f;
 #pragma unroll
-  for (int i = 0; i < P; ++i) sxy = fmaf(lc.kx[i], wky[i], sxy);
+  for (int i = 0; i < P; ++i) {
+    sxx = fmaf(lc.kx[i] * lc.kx[i], swq[i], sxx);
+    sxy = fmaf(lc.kx[i], wky[i], sxy);
+    sdx = fmaf(lc.kx[i], sdc[i], sdx);
+  }
   chi2 *= 2.0;
   sF *= 2.f; sxx *= 2.f; syy *= 2.f; sxy *= 2.f; sdx *= 2.f; sdy *= 2.f;
 
@@ -392,7 +432,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   for (int i = lane + kWave * part; i < sp.nspec; i += kWave * W) {
     int ub, vb, c;
     nyq_bin_uv(g.N, i, ub, vb, c);
-    const float2 D = dh[sp.nslots + i];
+    const float2 D = dh[2 * sp.nslots + i];
     const int nu = (ub == -h) ? 2 : 1;
     const int nv = (vb == -h) ? 2 : 1;
     float Mr = 0.f, Mi = 0.f;

@@ -74,22 +74,25 @@ __global__ void __launch_bounds__(256) dft_bins_kernel(
     Q[r * N + i] = make_float2(ar, ai);
   }
   __syncthreads();
-  // pass 2 (along x) at every stored bin: the slot layout of the k-space
-  // loop (row 0 scaled by 1/sqrt 2, unused slots zero), then the Nyquist bins
+  // pass 2 (along x) at every stored value: the pair-slot layout of the
+  // k-space loop (slot_value_uv's scales, padding zero), then the Nyquist
+  // bins, then zero up to the even length
   const SlotPlan sp = make_slot_plan_p(N, P);
   float2* dst = out + bin_off[gal];
   for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) {
     int u, v;
     float scale = 1.0f;
-    if (b < sp.nslots) {
-      if (!slot_uv(N, sp, b, u, v)) {
+    if (b < 2 * sp.nslots) {
+      if (!slot_value_uv(N, sp, b, u, v, scale)) {
         dst[b] = make_float2(0.f, 0.f);
         continue;
       }
-      if (v == 0) scale = 0.70710678118654752f;
-    } else {
+    } else if (b < 2 * sp.nslots + sp.nspec) {
       int c;
-      nyq_bin_uv(N, b - sp.nslots, u, v, c);
+      nyq_bin_uv(N, b - 2 * sp.nslots, u, v, c);
+    } else {
+      dst[b] = make_float2(0.f, 0.f);
+      continue;
     }
     const int r = (v < 0) ? g.h : v;
     const float2* q = Q + r * N;

@@ -14,7 +14,7 @@ from workloads import gen                                    # noqa: E402
 from tests import synth                                      # noqa: E402
 
 PS = gen.PIXEL_SCALE
-PLANS = {25: (2, 3, 6), 53: (6, 8, 5, 4), 101: (5, 8)}
+PLANS = {25: (3, 1), 53: (3, 4, 6, 2), 101: (4, 5)}
 
 
 def _log(msg):
