@@ -181,6 +181,71 @@ __device__ __forceinline__ void wave_total7(float* v, float* scratch) {
   wave_lds_sync();
 }
 
+// ---- Two chains per wave: lanes 0..31 serve one chain, 32..63 the other --
+
+// Lane index within the lanes serving this lane's chain (H chains per wave).
+template <int H>
+__device__ __forceinline__ int chain_lane() {
+  return H == 1 ? lane_id() : (lane_id() & 31);
+}
+
+// Value of lane k of this lane's chain (lane k of the wave for H = 1, lane k
+// of the lane's half for H = 2).
+template <int H>
+__device__ __forceinline__ float hbcast(float x, int k) {
+  if constexpr (H == 1) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+  } else {
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32 + k));
+    return (lane_id() & 32) ? b : a;
+  }
+}
+template <int H>
+__device__ __forceinline__ uint32_t hbcast(uint32_t x, int k) {
+  if constexpr (H == 1) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, k);
+  } else {
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)x, k);
+    const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)x, 32 + k);
+    return (lane_id() & 32) ? b : a;
+  }
+}
+
+// Sum over each 32-lane half by a butterfly: every lane of a half ends with
+// the same bits (each stage adds the same two operands on both partners).
+__device__ __forceinline__ double half_total(double x) {
+#pragma unroll
+  for (int o = 16; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+// Seven sums over each 32-lane half through the wave's 2 KiB LDS scratch:
+// each lane writes its eight partials, lane l of a half adds value (l % 32) / 4
+// of lanes 8 (l % 4) .. 8 (l % 4) + 7 of its half, and a two-step DPP prefix
+// sum inside each group of four lanes finishes the sum on lane 4 v + 3.
+__device__ __forceinline__ void half_total7(float* v, float* scratch) {
+  const int lane = lane_id();
+  float4* s4 = reinterpret_cast<float4*>(scratch);
+  s4[2 * lane] = make_float4(v[0], v[1], v[2], v[3]);
+  s4[2 * lane + 1] = make_float4(v[4], v[5], v[6], 0.f);
+  wave_lds_sync();
+  const int half = lane & 32, r = lane & 31;
+  const int val = r >> 2, grp = r & 3;
+  float acc = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += scratch[(half + 8 * grp + k) * 8 + val];
+  acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
+  acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 4 * j + 3));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 32 + 4 * j + 3));
+    v[j] = half ? b : a;
+  }
+  wave_lds_sync();
+}
+
 __device__ __forceinline__ float wave_max(float x) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) x = fmaxf(x, __shfl_xor(x, o, kWave));

@@ -86,8 +86,8 @@ __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
 // Outside the support U = +inf and the gradient is evaluated at the nearest
 // admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
 // trajectory can continue (it is rejected anyway).
-template <int PROF, int P, bool CHI2 = true, int NFIX = 0, int W = 1>
-__device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& lc, const Prior& pr,
+template <int PROF, int P, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1>
+__device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * H>& lc, const Prior& pr,
                                             const float* th, float* gU, uint32_t& status,
                                             float* xbuf = nullptr) {
   const bool inside = in_support(th, pr);
@@ -102,13 +102,13 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P>& 
     E = e1 * e1 + e2 * e2;
   }
   // F = 10^t0 and s = 10^t1 in one lane-parallel evaluation
-  const float e10 = exp10_bounded(lane_id() == 0 ? t0 : t1);
-  const float F = bcast(e10, 0), s = bcast(e10, 1);
+  const float e10 = exp10_bounded(chain_lane<H>() == 0 ? t0 : t1);
+  const float F = hbcast<H>(e10, 0), s = hbcast<H>(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
-  fill_tables(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
+  fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
   const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
-  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf,
-                                                              sh, c.red, c.part, xbuf);
+  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf,
+                                                                 sh, c.red, c.part, xbuf);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
   const float isd2 = pr.isd2, ise2 = pr.ise2;
   const float cpri = -4.0f * sh.inv1mE - ise2;
@@ -249,18 +249,20 @@ __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp)
 
 // LDS: [data spectrum | atab | column table | NW chain records | NW reduction
 // scratches | NW table sets | exchange areas] for NW waves per block.
-__device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int wave, int C) {
+// idx: this lane's chain record and table set (its wave, or its chain with
+// two chains per wave); wave: its reduction scratch.
+__device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx, int wave, int C) {
   extern __shared__ float4 smem4[];
   Lds l;
   l.dh = reinterpret_cast<float2*>(smem4);
   l.atab = reinterpret_cast<float*>(l.dh + ((sp.nbins + 1) & ~1));
   l.cols = reinterpret_cast<float4*>(l.atab + ((g.ntab + 3) & ~3));
   ChainState* cs0 = reinterpret_cast<ChainState*>(l.cols + sp.P * 64);
-  l.cs = cs0 + wave;
+  l.cs = cs0 + idx;
   float* red0 = reinterpret_cast<float*>(cs0 + C);
   l.red = red0 + 512 * wave;
   float2* wt = reinterpret_cast<float2*>(red0 + 512 * C);
-  float2* w0 = wt + wave_table_len(g, sp) * wave;
+  float2* w0 = wt + wave_table_len(g, sp) * idx;
   l.Ym = reinterpret_cast<float4*>(w0);
   l.X = w0 + 2 * sp.ymax;
   l.Yf = l.X + g.ntab + 2;
@@ -354,9 +356,10 @@ __device__ __forceinline__ void store_state(ChainState* st, const Regs& r) {
 // Random numbers of iteration t: 6 normals (Box-Muller on lanes 0 and 1,
 // float hardware log/sqrt/sin/cos: relative error ~1e-7), the Metropolis
 // uniform and the step-jitter uniform.
+template <int H = 1>
 __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_t k0, uint32_t k1,
                                                float* z, float& u_acc, float& u_jit) {
-  const int lane = lane_id();
+  const int lane = chain_lane<H>();
   uint32_t tag = kTagMomentum, blk = 0;
   if (lane == 1) blk = 1;
   if (lane == 2) tag = kTagAccept;
@@ -368,14 +371,14 @@ __device__ __forceinline__ void draw_iteration(uint32_t uid, uint32_t t, uint32_
   const float a1 = u01(w.y), a2 = u01(w.w);       // angles in revolutions
   const float za = r1 * __builtin_amdgcn_cosf(a1), zb = r1 * __builtin_amdgcn_sinf(a1);
   const float zc = r2 * __builtin_amdgcn_cosf(a2), zd = r2 * __builtin_amdgcn_sinf(a2);
-  z[0] = bcast(za, 0);
-  z[1] = bcast(zb, 0);
-  z[2] = bcast(zc, 0);
-  z[3] = bcast(zd, 0);
-  z[4] = bcast(za, 1);
-  z[5] = bcast(zb, 1);
-  u_acc = u01(bcast(w.x, 2));
-  u_jit = u01(bcast(w.x, 3));
+  z[0] = hbcast<H>(za, 0);
+  z[1] = hbcast<H>(zb, 0);
+  z[2] = hbcast<H>(zc, 0);
+  z[3] = hbcast<H>(zd, 0);
+  z[4] = hbcast<H>(za, 1);
+  z[5] = hbcast<H>(zb, 1);
+  u_acc = u01(hbcast<H>(w.x, 2));
+  u_jit = u01(hbcast<H>(w.x, 3));
 }
 
 // Values the leapfrog touches every step stay in registers; the rest of the
@@ -392,11 +395,13 @@ struct Hot {
 
 __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
-template <int PROF, int P, int NFIX, int W>
-__device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
+// H = 2: two chains per wave, each 32-lane half running its own chain (its
+// own record cs, tables and outputs); lane below is the lane within the half.
+template <int PROF, int P, int NFIX, int W, int H = 1>
+__device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P * H>& lc,
                               const Prior& pr, ChainState* cs, float* samples_chain,
                               float* trace_chain) {
-  const int lane = lane_id();
+  const int lane = chain_lane<H>();
   const uint32_t uid = cs->uid;
   int nev = 0;           // evaluations so far (alternates the exchange buffers)
   Hot h;
@@ -418,7 +423,7 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     if (h.t >= c.t_stop) break;
     if (h.l == 0) {
       float z[6], u_acc, u_jit;
-      draw_iteration(uid, (uint32_t)h.t, a.k0, a.k1, z, u_acc, u_jit);
+      draw_iteration<H>(uid, (uint32_t)h.t, a.k0, a.k1, z, u_acc, u_jit);
       const float eps = cs->eps;
       h.eps_t = eps;
       if (a.jitter > 0.0f)
@@ -451,9 +456,9 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     float* xbuf = W > 1 ? c.xch + (nev & 1) * (12 * W) : nullptr;
     ++nev;
     if (h.l + 1 == a.L)
-      h.Uth = potential<PROF, P, true, NFIX, W>(c, lc, pr, h.th, h.g, st, xbuf);
+      h.Uth = potential<PROF, P, true, NFIX, W, H>(c, lc, pr, h.th, h.g, st, xbuf);
     else
-      h.Uth = potential<PROF, P, false, NFIX, W>(c, lc, pr, h.th, h.g, st, xbuf);
+      h.Uth = potential<PROF, P, false, NFIX, W, H>(c, lc, pr, h.th, h.g, st, xbuf);
     if (h.t >= a.W) h.status |= st;     // warmup probes are not reported
     if (!in_support(h.th, pr)) h.ok = 0;
     h.l += 1;
@@ -543,15 +548,19 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
 // W > 1: each chain is evaluated by W waves (split evaluation; advance only).
-template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1>
+// H = 2: two chains per wave (lanes 0..31 and 32..63; advance only, C even).
+template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
+  static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int wave = threadIdx.x / kWave;
-  const int cw = wave / W, part = wave % W;      // chain of the galaxy, part of the chain
-  const Lds l = carve(g, sp, wave, a.C * W);
+  // chain of the galaxy, part of the chain
+  const int cw = (H == 1) ? wave / W : 2 * wave + ((threadIdx.x >> 5) & 1);
+  const int part = (H == 1) ? wave % W : 0;
+  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W);
   build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
                  1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
@@ -561,7 +570,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     stage_galaxy(a, gal, g, sp, l.dh, l.atab);
     __syncthreads();
     if (cw >= a.C) continue;
-    const LaneCols<P> lc = lane_cols<P>(l.cols);
+    const LaneCols<P * H> lc = lane_cols<P * H, H>(l.cols);
     const float sig = a.sigma[gal];
     GalCtx c;
     c.g = g;
@@ -581,7 +590,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.t_stop = a.t_stop_gal ? min(a.t_stop, a.t_stop_gal[gal]) : a.t_stop;
     const int64_t chain = (int64_t)gal * a.C + cw;
     ChainState* st = a.state + chain;
-    if (INIT) {
+    if constexpr (INIT) {
       Regs r;
       const float* ini = a.init + chain * 6;
 #pragma unroll
@@ -618,15 +627,23 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
                          (uint64_t)cw);
       store_state(st, r);
     } else {
+      // the 64-word record of this lane's chain, copied by the chain's lanes
       uint32_t* csw = reinterpret_cast<uint32_t*>(l.cs);
-      csw[lane_id()] = reinterpret_cast<const uint32_t*>(st)[lane_id()];
+      const uint32_t* src = reinterpret_cast<const uint32_t*>(st);
+      const int cl = chain_lane<H>();
+#pragma unroll
+      for (int k = 0; k < H; ++k) csw[cl + 32 * k] = src[cl + 32 * k];
       wave_lds_sync();
       // the W waves of a split chain hold identical copies of its state; the
       // first writes the outputs
       float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P, NFIX, W>(a, c, lc, pr, l.cs, sc, tc);
-      if (part == 0) reinterpret_cast<uint32_t*>(st)[lane_id()] = csw[lane_id()];
+      advance_chain<PROF, P, NFIX, W, H>(a, c, lc, pr, l.cs, sc, tc);
+      if (part == 0) {
+        uint32_t* dst = reinterpret_cast<uint32_t*>(st);
+#pragma unroll
+        for (int k = 0; k < H; ++k) dst[cl + 32 * k] = csw[cl + 32 * k];
+      }
     }
   }
 }
@@ -661,11 +678,11 @@ size_t hmc_lds_bytes(int N, int C, int P, int W) {
          sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW;
 }
 
-template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1>
+template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1, int H = 1>
 static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  const dim3 blk(kWave * a.C * W);
+  const dim3 blk(kWave * a.C * W / H);
   if (a.C * W <= 4) {
-    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX, W>;
+    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX, W, H>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   } else {
@@ -685,9 +702,21 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   X(25, 3) X(32, 1) X(32, 2) X(32, 4) X(41, 1) X(41, 4) \
   X(53, 3) X(53, 4) X(53, 6) X(73, 3) X(73, 6) X(73, 8) X(101, 4) X(101, 5)
 
+// Plans whose two-chains-per-wave kernel fits the 256 registers without
+// spilling (twice the lane's pair-columns of the one-chain kernel).
+constexpr bool paired_chains_plan(int N, int P) {
+  return (N == 25 && P == 3) || (N == 41 && P == 1) || (N == 53 && P == 3) || (N == 73 && P == 3);
+}
+
 template <int PROF, int NFIX, int PP>
 static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   if (a.wpc == 1) {
+    if constexpr (paired_chains_plan(NFIX, PP)) {
+      if (hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) == 2) {
+        launch_p<PROF, false, PP, NFIX, 1, 2>(a, grid, lds, s);
+        return true;
+      }
+    }
     launch_p<PROF, false, PP, NFIX, 1>(a, grid, lds, s);
     return true;
   }
@@ -722,6 +751,16 @@ int hmc_split_waves(int N, int C, int P, int prof, int max_w) {
   int W = 1;
   while (W * 2 <= max_w && W * 2 <= nsr && C * W * 2 <= 4) W *= 2;
   return W;
+}
+
+int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc) {
+#ifdef BSI_ONE_CHAIN_PER_WAVE
+  (void)N; (void)C; (void)P; (void)prof; (void)wpc;
+  return 1;
+#else
+  if (wpc != 1 || (C & 1) || C > 4 || prof != kProfExp) return 1;
+  return paired_chains_plan(N, P) ? 2 : 1;
+#endif
 }
 
 const int* hmc_fixed_plans(int N) {

@@ -201,13 +201,15 @@ __device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& s
   }
 }
 
-template <int P>
-__device__ __forceinline__ LaneCols<P> lane_cols(const float4* tab) {
-  LaneCols<P> c;
-  const int lane = lane_id();
+// PI pair-iterations per super-row for this lane: with H chains per wave the
+// 64 / H lanes of a chain take pair-slots l, l + 64 / H, ... (PI = H P).
+template <int PI, int H = 1>
+__device__ __forceinline__ LaneCols<PI> lane_cols(const float4* tab) {
+  LaneCols<PI> c;
+  const int lane = chain_lane<H>();
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    const float4 e = tab[lane + 64 * i];
+  for (int i = 0; i < PI; ++i) {
+    const float4 e = tab[lane + (64 / H) * i];
     c.kx[i] = e.x;
     c.sc[i] = e.y;
     c.xi[i] = __float_as_int(e.z);
@@ -228,20 +230,23 @@ __device__ __forceinline__ float2 cis_neg_rev(float r) {
   return make_float2(__builtin_amdgcn_cosf(r), -__builtin_amdgcn_sinf(r));
 }
 
+// H chains per wave: the 64 / H lanes of each chain fill that chain's tables.
+template <int H = 1>
 __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
                                             const float* __restrict__ atab, float2* X, float4* Ym,
                                             float2* Yf, float F, float dx, float dy) {
-  const int lane = lane_id();
+  constexpr int LS = kWave / H;
+  const int lane = chain_lane<H>();
   const float invN = rcp_nr((float)g.N);
   const float rx = dx * invN, ry = dy * invN;   // revolutions per unit frequency
-  for (int t = lane; t < g.ntab; t += kWave) {
+  for (int t = lane; t < g.ntab; t += LS) {
     const float a = F * atab[t];
     const float2 w = cis_neg_rev((float)(t - g.h) * rx);
     X[t] = make_float2(a * w.x, a * w.y);
   }
   if (lane == 0) X[g.ntab] = make_float2(0.f, 0.f);
   const bool even = (g.N & 1) == 0;
-  for (int v = lane; v < sp.ymax; v += kWave) {
+  for (int v = lane; v < sp.ymax; v += LS) {
     float4 y = make_float4(0.f, 0.f, 0.f, 0.f);
     if (v <= g.hc) {
       const float a = atab[v + g.h] * (v == 0 ? 0.70710678118654752f : 1.0f);
@@ -252,7 +257,7 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
     Ym[v] = y;
   }
   if (even) {
-    for (int t = lane; t < g.ntab; t += kWave) {
+    for (int t = lane; t < g.ntab; t += LS) {
       const float a = atab[t];
       const float2 w = cis_neg_rev((float)(t - g.h) * ry);
       Yf[t] = make_float2(a * w.x, a * w.y);
@@ -329,17 +334,25 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
 // evaluations) and added in the order 0..W-1 by every wave, so that all W
 // waves hold the same totals.  The block must reach this function with all
 // its waves (the exchange uses a workgroup barrier).
-template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1>
-__device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P>& lc,
+//
+// Two chains per wave (H = 2, NFIX kernels only): each 32-lane half runs the
+// loop for its own chain (its own X, Ym, Yf tables and shape constants) over
+// pair-slots l, l + 32, ..., i.e. 2 P pair-iterations per super-row, and the
+// sums are reduced per half.
+template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1>
+__device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P * H>& lc,
                              const float2* __restrict__ dh, const float2* X, const float4* Ym,
                              const float2* Yf, const Shape& sh, float* red, int part = 0,
                              float* xch = nullptr) {
   static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
-  const int lane = lane_id();
-  float xr[P], xi[P], TA[P], Tc[P];
-  const float4* yp[P];
+  static_assert(H == 1 || (NFIX > 0 && W == 1), "two chains per wave need a specialised kernel");
+  constexpr int PI = P * H;           // pair-iterations per super-row of this lane
+  constexpr int LS = kWave / H;       // lanes per chain
+  const int lane = chain_lane<H>();
+  float xr[PI], xi[PI], TA[PI], Tc[PI];
+  const float4* yp[PI];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
+  for (int i = 0; i < PI; ++i) {
     const float2 x = X[lc.xi[i]];
     xr[i] = x.x * lc.sc[i];
     xi[i] = x.y * lc.sc[i];
@@ -349,9 +362,9 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
   double chi2 = 0.0;
   float sF = 0.f, syy = 0.f, sdy = 0.f;
-  float swq[P], wky[P], sdc[P];       // per column: times kx^2, kx, kx after the loop
+  float swq[PI], wky[PI], sdc[PI];    // per column: times kx^2, kx, kx after the loop
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
+  for (int i = 0; i < PI; ++i) {
     swq[i] = 0.f;
     wky[i] = 0.f;
     sdc[i] = 0.f;
@@ -363,9 +376,9 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     constexpr int K = (spc.nsr + W - 1) / W;   // super-rows of this wave (at most)
     // this wave's super-rows are part + k W, k = 0..K-1 (the last may not exist)
     const float4* dq = dp + part * P * 64;
-    const float4* yq[P];
+    const float4* yq[PI];
 #pragma unroll
-    for (int i = 0; i < P; ++i) yq[i] = yp[i] + part * spc.R;
+    for (int i = 0; i < PI; ++i) yq[i] = yp[i] + part * spc.R;
     if constexpr (W == 1) {
       // software pipeline: the LDS reads of the next pair are issued before the
       // arithmetic of the current one
@@ -375,13 +388,13 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
       for (int k = 0; k < K; ++k) {
         float c2 = 0.f;
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
+        for (int i = 0; i < PI; ++i) {
           const float4 D = Dn;
           const float4 y = yn;
-          const int b = k * P + i + 1;          // next pair-slot
-          if (b < K * P) {
-            Dn = dq[b * 64];
-            yn = yq[b % P][(b / P) * spc.R];
+          const int b = k * PI + i + 1;         // next pair-slot of this lane
+          if (b < K * PI) {
+            Dn = dq[b * LS];
+            yn = yq[b % PI][(b / PI) * spc.R];
           }
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
           pair_step<PROF, RESID>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
@@ -417,7 +430,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
   float sxx = 0.f, sxy = 0.f, sdx = 0.f;
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
+  for (int i = 0; i < PI; ++i) {
     sxx = fmaf(lc.kx[i] * lc.kx[i], swq[i], sxx);
     sxy = fmaf(lc.kx[i], wky[i], sxy);
     sdx = fmaf(lc.kx[i], sdc[i], sdx);
@@ -429,7 +442,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   // (weights 1/2, sign -1 on +N/2) on its Nyquist axis or axes.
   const int h = g.h;
   const float ks = g.kstep;
-  for (int i = lane + kWave * part; i < sp.nspec; i += kWave * W) {
+  for (int i = lane + LS * part; i < sp.nspec; i += LS * W) {
     int ub, vb, c;
     nyq_bin_uv(g.N, i, ub, vb, c);
     const float2 D = dh[2 * sp.nslots + i];
@@ -484,9 +497,14 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
 
   KSums s;
-  s.chi2 = CHI2 ? wave_total(chi2) : 0.0;
   float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
-  wave_total7(v, red);
+  if constexpr (H == 1) {
+    s.chi2 = CHI2 ? wave_total(chi2) : 0.0;
+    wave_total7(v, red);
+  } else {
+    s.chi2 = CHI2 ? half_total(chi2) : 0.0;
+    half_total7(v, red);
+  }
   s.sF = v[0];
   s.sxx = v[1];
   s.syy = v[2];
