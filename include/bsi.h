@@ -288,13 +288,18 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
 
 /* ---- Slot plans and their autotuning ---------------------------------------
  *
- * The k-space loop of a stamp side N walks the half-plane bins as super-rows
- * of R rows spread over P iterations of the 64 lanes (the "slot plan"); P
- * fixes R and the padding.  By default each N uses the P with the fewest
- * slots.  A handle can hold another choice per N, set explicitly or measured
- * by bsi_autotune; every later call on the handle (and every request server
+ * The k-space loop of a stamp side N walks the half-plane bins in pair-slots
+ * (the bins (+kx, ky) and (-kx, ky) of one row per slot), as super-rows of R
+ * rows spread over P iterations of the 64 lanes (the "slot plan"); P fixes R
+ * and the padding.  By default each N uses the P with the fewest pair-slots.
+ * A handle can hold another choice per N, set explicitly or measured by
+ * bsi_autotune; every later call on the handle (and every request server
  * created afterwards) uses it.  Results do not depend on the plan beyond
- * float32 rounding (the order of the sums changes). */
+ * float32 rounding (the order of the sums changes).  The trajectory kernel
+ * runs two chains per wave (32 lanes each) for an even number of chains up
+ * to 4 on the plans 25: P 3, 41: P 1, 53: P 3, 73: P 3 (exponential profile,
+ * one wave per chain requested), one chain per wave otherwise; the choice
+ * depends only on the size, plan and configuration, never on the batch. */
 
 /* Set (P > 0) or reset to the default (P = 0) the slot plan of stamp side n.
  * BSI_EINVAL unless 8 <= n <= 128 and P is 0 or one of 1, 2, 3, 4, 5, 6, 8
@@ -302,11 +307,12 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
 int bsi_set_plan(bsi_handle h, int32_t n, int32_t P);
 
 /* The slot plan stamp side n uses on this handle (*P), and its number of
- * slots per evaluation (*slots, nullable). */
+ * bin slots per evaluation (*slots, nullable: two per pair-slot, padding
+ * included). */
 int bsi_get_plan(bsi_handle h, int32_t n, int32_t* P, int32_t* slots);
 
 /* Measure, for each stamp side sizes[i], the trajectory kernel with each
- * candidate plan (those within 10 % of the fewest slots, at most three) on a
+ * candidate plan (those within 10 % of the fewest pair-slots, at most three) on a
  * synthetic batch that fills the device (about 16,384 chains of n_chains per
  * galaxy, exponential profile, 20 leapfrog steps, best of five launches),
  * and keep the fastest on the handle; the default plan is kept unless
