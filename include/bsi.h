@@ -297,7 +297,7 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
  * created afterwards) uses it.  Results do not depend on the plan beyond
  * float32 rounding (the order of the sums changes).  The trajectory kernel
  * runs two chains per wave (32 lanes each) for an even number of chains up
- * to 4 on the plans 25: P 3, 41: P 1, 53: P 3, 73: P 3 (exponential profile,
+ * to 4 on the plans 25: P 3, 41: P 1, 53: P 3 (exponential profile,
  * one wave per chain requested), one chain per wave otherwise; the choice
  * depends only on the size, plan and configuration, never on the batch. */
 

@@ -121,8 +121,8 @@ size_t hmc_lds_bytes(int N, int C, int P, int W);
 int hmc_split_waves(int N, int C, int P, int prof, int max_w);
 // Chains per wave of the trajectory kernel: 2 (two 32-lane halves) for an
 // even number of chains (at most 4), one wave per chain (wpc = 1), the
-// exponential profile and a plan whose specialised two-chain kernel fits the
-// registers (25: P 3, 41: P 1, 53: P 3, 73: P 3); else 1.
+// exponential profile and a plan whose specialised two-chain kernel is the
+// faster one (25: P 3, 41: P 1, 53: P 3); else 1.
 int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc);
 // Slot plans with a trajectory kernel specialised for stamp side N (0-terminated list of P).
 const int* hmc_fixed_plans(int N);

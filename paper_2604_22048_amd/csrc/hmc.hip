@@ -702,10 +702,11 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   X(25, 3) X(32, 1) X(32, 2) X(32, 4) X(41, 1) X(41, 4) \
   X(53, 3) X(53, 4) X(53, 6) X(73, 3) X(73, 6) X(73, 8) X(101, 4) X(101, 5)
 
-// Plans whose two-chains-per-wave kernel fits the 256 registers without
-// spilling (twice the lane's pair-columns of the one-chain kernel).
+// Plans whose two-chains-per-wave kernel is faster than the one-chain kernel
+// (measured per size and plan; at 73 and 101 the two-chain kernels either
+// spill or run slower, and the larger P spill everywhere).
 constexpr bool paired_chains_plan(int N, int P) {
-  return (N == 25 && P == 3) || (N == 41 && P == 1) || (N == 53 && P == 3) || (N == 73 && P == 3);
+  return (N == 25 && P == 3) || (N == 41 && P == 1) || (N == 53 && P == 3);
 }
 
 template <int PROF, int NFIX, int PP>
