@@ -113,7 +113,8 @@ struct HmcArgs {
   const int32_t* t_stop_gal;  // [gal] per-galaxy stop (<= t_stop) or NULL (advance kernel only)
 };
 
-size_t hmc_lds_bytes(int N, int C, int P, int W);
+// LDS bytes of the trajectory kernel: C chains, W waves per chain, H chains per wave.
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1);
 // Waves per chain for stamp side N, C chains and plan P when up to max_w are
 // requested: a power of two <= max_w, <= the plan's super-rows, C W <= 4, and
 // 1 unless the profile is exponential and P is N's default plan with a

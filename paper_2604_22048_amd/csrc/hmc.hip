@@ -247,11 +247,13 @@ __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp)
   return 2 * sp.ymax + 2 * g.ntab + 2;
 }
 
-// LDS: [data spectrum | atab | column table | NW chain records | NW reduction
-// scratches | NW table sets | exchange areas] for NW waves per block.
+// LDS: [data spectrum | atab | column table | NW chain records | NWV reduction
+// scratches | NW table sets | exchange areas] for NW chain records (one per
+// wave, or per chain with two chains per wave) and NWV waves per block.
 // idx: this lane's chain record and table set (its wave, or its chain with
 // two chains per wave); wave: its reduction scratch.
-__device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx, int wave, int C) {
+__device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx, int wave, int C,
+                                     int NWV) {
   extern __shared__ float4 smem4[];
   Lds l;
   l.dh = reinterpret_cast<float2*>(smem4);
@@ -261,7 +263,7 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx,
   l.cs = cs0 + idx;
   float* red0 = reinterpret_cast<float*>(cs0 + C);
   l.red = red0 + 512 * wave;
-  float2* wt = reinterpret_cast<float2*>(red0 + 512 * C);
+  float2* wt = reinterpret_cast<float2*>(red0 + 512 * NWV);
   float2* w0 = wt + wave_table_len(g, sp) * idx;
   l.Ym = reinterpret_cast<float4*>(w0);
   l.X = w0 + 2 * sp.ymax;
@@ -560,7 +562,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
   // chain of the galaxy, part of the chain
   const int cw = (H == 1) ? wave / W : 2 * wave + ((threadIdx.x >> 5) & 1);
   const int part = (H == 1) ? wave % W : 0;
-  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W);
+  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H);
   build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
                  1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
@@ -669,12 +671,12 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 }  // namespace
 
-size_t hmc_lds_bytes(int N, int C, int P, int W) {
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int NW = C * W;
   return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
-         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * NW +
+         sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * (NW / H) +
          sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW;
 }
 
@@ -799,7 +801,10 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   // split chains only where a specialised kernel exists (hmc_split_waves)
   if (a.wpc != 1 && (INIT || a.wpc != hmc_split_waves(a.N, a.C, a.P, a.prof, a.wpc)))
     return hipErrorInvalidValue;
-  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc);
+  // two chains per wave exactly where launch_fixed_w launches them
+  const int H = (!INIT && a.prof == kProfExp && a.C * a.wpc <= 4)
+                    ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
+  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
   else

@@ -289,8 +289,7 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
                                           float TA, float Tc, float& c2, float& sF, float& swq,
                                           float& syy, float& wky, float& sdx, float& sdy, bool chi2) {
   const float base = fmaf(sh.tb, y.w, TA);
-  const float c = Tc * y.z;
-  const float tp = base + c, tm = base - c;
+  const float tp = fmaf(Tc, y.z, base), tm = fmaf(-Tc, y.z, base);
   float Gp, Gm, Gwp, Gwm;
   if (PROF == kProfExp) {
     const float rp = __builtin_amdgcn_rsqf(tp), rm = __builtin_amdgcn_rsqf(tm);
