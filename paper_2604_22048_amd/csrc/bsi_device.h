@@ -222,8 +222,9 @@ __device__ __forceinline__ double half_total(double x) {
 
 // Seven sums over each 32-lane half through the wave's 2 KiB LDS scratch:
 // each lane writes its eight partials, lane l of a half adds value (l % 32) / 4
-// of lanes 8 (l % 4) .. 8 (l % 4) + 7 of its half, and a two-step DPP prefix
-// sum inside each group of four lanes finishes the sum on lane 4 v + 3.
+// of lanes 8 (l % 4) .. 8 (l % 4) + 7 of its half, a two-step DPP prefix sum
+// inside each group of four lanes finishes the sum on lane 4 v + 3, and the
+// sums go back through LDS to every lane of their half.
 __device__ __forceinline__ void half_total7(float* v, float* scratch) {
   const int lane = lane_id();
   float4* s4 = reinterpret_cast<float4*>(scratch);
@@ -237,12 +238,12 @@ __device__ __forceinline__ void half_total7(float* v, float* scratch) {
   for (int k = 0; k < 8; ++k) acc += scratch[(half + 8 * grp + k) * 8 + val];
   acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
   acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
+  wave_lds_sync();
+  if (grp == 3) scratch[(half >> 2) + val] = acc;
+  wave_lds_sync();
+  const float* res = scratch + (half >> 2);
 #pragma unroll
-  for (int j = 0; j < 7; ++j) {
-    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 4 * j + 3));
-    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), 32 + 4 * j + 3));
-    v[j] = half ? b : a;
-  }
+  for (int j = 0; j < 7; ++j) v[j] = res[j];
   wave_lds_sync();
 }
 

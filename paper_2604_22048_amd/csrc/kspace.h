@@ -119,9 +119,11 @@ __host__ __device__ inline void nyq_bin_uv(int N, int i, int& u, int& v, int& c)
   u = -h; v = i - (h + 1); c = 2;                               // v = 1..h-1
 }
 
+// Half of the full-grid sums (the stored half plane counts once; the factor
+// 2 is applied by kspace_finish).
 struct KSums {
-  double chi2;                                    // sum over the full grid of |D - M|^2
-  float sF, sxx, syy, sxy, sq, sdx, sdy;          // weighted Re/Im sums
+  double chi2;                                    // half the full-grid sum of |D - M|^2
+  float sF, sxx, syy, sxy, sq, sdx, sdy;          // weighted Re/Im sums (halved likewise)
 };
 
 struct KResult {
@@ -180,13 +182,14 @@ __device__ __forceinline__ void profile_factor(const Shape& sh, float q, float& 
 template <int P>
 struct LaneCols {
   float kx[P];       // k_x = j kstep of the lane's column in iteration i (0 if unused)
-  float sc[P];       // model scale: 1/sqrt(2) for column 0 (two half-weight copies), 1 else, 0 if unused
-  int xi[P];         // index into the X table (j + h), or ntab (zero entry) if the slot is unused
+  float kx2[P];      // k_x^2
+  int xi[P];         // index into the X table: j + h; ntab + 1 (X(0) / sqrt 2, the two
+                     // half-weight copies of column 0) for j = 0; ntab (zero entry) if unused
   int yo[P];         // row offset within the super-row
 };
 
 // Per-pair-slot column table shared by the workgroup: entry (i, lane) =
-// {k_x, model scale, X index (ntab, a zero entry, if unused), row offset}.
+// {k_x, k_x^2, X index, row offset}.
 __device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& sp, float4* tab) {
   const int npc = g.hc + 1;
   for (int t = threadIdx.x; t < sp.P * 64; t += blockDim.x) {
@@ -194,8 +197,8 @@ __device__ __forceinline__ void build_col_table(const Geom& g, const SlotPlan& s
     if (t < sp.R * npc) {
       const int ro = t / npc;
       const int j = t - ro * npc;
-      e = make_float4((float)j * g.kstep, j == 0 ? 0.70710678118654752f : 1.0f, __int_as_float(j + g.h),
-                      __int_as_float(ro));
+      const float kx = (float)j * g.kstep;
+      e = make_float4(kx, kx * kx, __int_as_float(j == 0 ? g.ntab + 1 : j + g.h), __int_as_float(ro));
     }
     tab[t] = e;
   }
@@ -211,7 +214,7 @@ __device__ __forceinline__ LaneCols<PI> lane_cols(const float4* tab) {
   for (int i = 0; i < PI; ++i) {
     const float4 e = tab[lane + (64 / H) * i];
     c.kx[i] = e.x;
-    c.sc[i] = e.y;
+    c.kx2[i] = e.y;
     c.xi[i] = __float_as_int(e.z);
     c.yo[i] = __float_as_int(e.w);
   }
@@ -243,6 +246,8 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
     const float a = F * atab[t];
     const float2 w = cis_neg_rev((float)(t - g.h) * rx);
     X[t] = make_float2(a * w.x, a * w.y);
+    // column 0 of the pair loop: two half-weight copies of X(0)
+    if (t == g.h) X[g.ntab + 1] = make_float2(0.70710678118654752f * a * w.x, 0.70710678118654752f * a * w.y);
   }
   if (lane == 0) X[g.ntab] = make_float2(0.f, 0.f);
   const bool even = (g.N & 1) == 0;
@@ -353,9 +358,9 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
 #pragma unroll
   for (int i = 0; i < PI; ++i) {
     const float2 x = X[lc.xi[i]];
-    xr[i] = x.x * lc.sc[i];
-    xi[i] = x.y * lc.sc[i];
-    TA[i] = fmaf(sh.ta, lc.kx[i] * lc.kx[i], sh.t0);
+    xr[i] = x.x;
+    xi[i] = x.y;
+    TA[i] = fmaf(sh.ta, lc.kx2[i], sh.t0);
     Tc[i] = sh.tc * lc.kx[i];
     yp[i] = Ym + lc.yo[i];
   }
@@ -430,12 +435,10 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   float sxx = 0.f, sxy = 0.f, sdx = 0.f;
 #pragma unroll
   for (int i = 0; i < PI; ++i) {
-    sxx = fmaf(lc.kx[i] * lc.kx[i], swq[i], sxx);
+    sxx = fmaf(lc.kx2[i], swq[i], sxx);
     sxy = fmaf(lc.kx[i], wky[i], sxy);
     sdx = fmaf(lc.kx[i], sdc[i], sdx);
   }
-  chi2 *= 2.0;
-  sF *= 2.f; sxx *= 2.f; syy *= 2.f; sxy *= 2.f; sdx *= 2.f; sdy *= 2.f;
 
   // Nyquist bins of an even N: each combines the frequency points +-N/2
   // (weights 1/2, sign -1 on +N/2) on its Nyquist axis or axes.
@@ -465,7 +468,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
       }
     }
     const float Rr = RESID ? D.x : D.x - Mr, Ri = RESID ? D.y : D.y - Mi;
-    const float cf = (float)c;
+    const float cf = 0.5f * (float)c;         // the sums are kept halved
     if (CHI2) chi2 += (double)(cf * fmaf(Rr, Rr, Ri * Ri));
     for (int au = 0; au < nu; ++au) {
       const int u = (nu == 2) ? (au == 0 ? -h : h) : ub;
@@ -547,15 +550,16 @@ template <int PROF>
 __device__ __forceinline__ KResult kspace_finish(const KSums& S, const Shape& sh, float F,
                                                  float s_arcsec, float e1, float e2, float norm) {
   KResult r;
-  r.loglik = -0.5 * (double)norm * S.chi2;
+  r.loglik = -(double)norm * S.chi2;            // -1/2 norm (2 S.chi2)
   const float c = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;   // d ln G / dq * a
-  r.dF = norm * S.sF * rcp_nr(F);
-  r.ds = norm * (2.0f * c * rcp_nr(s_arcsec)) * S.sq;
-  r.de1 = norm * c * sh.inv1mE *
+  const float n2 = 2.0f * norm;                  // the halved sums doubled
+  r.dF = n2 * S.sF * rcp_nr(F);
+  r.ds = n2 * (2.0f * c * rcp_nr(s_arcsec)) * S.sq;
+  r.de1 = n2 * c * sh.inv1mE *
           ((2.0f * e1 + 2.0f) * S.sxx + (2.0f * e1 - 2.0f) * S.syy + 2.0f * e1 * S.sq);
-  r.de2 = norm * c * sh.inv1mE * (2.0f * e2 * (S.sxx + S.syy) + 4.0f * S.sxy + 2.0f * e2 * S.sq);
-  r.ddx = norm * S.sdx;
-  r.ddy = norm * S.sdy;
+  r.de2 = n2 * c * sh.inv1mE * (2.0f * e2 * (S.sxx + S.syy) + 4.0f * S.sxy + 2.0f * e2 * S.sq);
+  r.ddx = n2 * S.sdx;
+  r.ddy = n2 * S.sdy;
   return r;
 }
 
