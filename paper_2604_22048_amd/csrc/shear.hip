@@ -91,18 +91,43 @@ __device__ __forceinline__ Geo geo(const Point& P, float e1, float e2) {
 // ln w of one sample at one point without the point-independent part c0
 // (interim ellipticity and flux terms): true ellipticity density, shear
 // Jacobian 2 ln(1 - |g|^2) - 2 ln B, and the size term.
+template <int EK, bool SZ>
 __device__ __forceinline__ float logw(const Point& P, const ShearArgs& a, const Geo& q, float ls) {
   float lp;
-  if (a.e_kind == 0)
+  if (EK == 0)
     lp = (q.E < 1.0f) ? 2.0f * __logf(1.0f - q.E) - q.E * P.inv2se2 - P.lnZ : -INFINITY;
   else
     lp = (q.E < a.e_max * a.e_max) ? -q.E * P.inv2se2 - P.lnZ : -INFINITY;
   float lw = lp + P.lw0 + 2.0f * __logf(q.iB);
-  if (a.size_term) {
+  if (SZ) {
     const float z = (ls * kLn10F - P.mu) * P.inv_sig_s;
     lw -= 0.5f * z * z;
   }
   return lw;
+}
+
+// Float64 totals over the wave of six per-lane float values, in one
+// transposed reduction through the wave's LDS scratch (64 x 8 floats): lane
+// l adds value l / 8 of lanes 8 (l % 8) .. 8 (l % 8) + 7 in float64, a
+// three-step DPP prefix sum inside each group of eight lanes finishes it on
+// lane 8 j + 7, and the six totals are read back as wave-uniform values.
+// Fixed order: the totals are bitwise reproducible.
+__device__ __forceinline__ void wave_total6_f64(const float* v, float* scratch, double* T) {
+  const int lane = lane_id();
+  float4* s4 = reinterpret_cast<float4*>(scratch);
+  s4[2 * lane] = make_float4(v[0], v[1], v[2], v[3]);
+  s4[2 * lane + 1] = make_float4(v[4], v[5], 0.f, 0.f);
+  wave_lds_sync();
+  const int val = lane >> 3, grp = lane & 7;
+  double acc = 0.0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc += (double)scratch[(8 * grp + k) * 8 + val];
+  acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
+  acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
+  acc = dpp_shift_add<0x114, 0xf>(acc);   // row_shr:4
+#pragma unroll
+  for (int j = 0; j < 6; ++j) T[j] = bcast(acc, 8 * j + 7);
+  wave_lds_sync();
 }
 
 // A wave holds one galaxy's K samples in registers (lane l: samples
@@ -113,9 +138,17 @@ __device__ __forceinline__ float logw(const Point& P, const ShearArgs& a, const 
 // sums are combined across the wave in float64 after rescaling by
 // e^(m_l - M), M the wave maximum, and the log-sum-exp and the gradient are
 // assembled in float64.
-__global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
+// Minimum resident waves per SIMD requested from the register allocator.
+#ifndef BSI_SHEAR_WAVES_PER_EU
+#define BSI_SHEAR_WAVES_PER_EU 2
+#endif
+
+// Template flags: GRAD = a.want_grad, SZ = a.size_term, EK = a.e_kind.
+template <bool GRAD, bool SZ, int EK>
+__global__ void __launch_bounds__(256, BSI_SHEAR_WAVES_PER_EU) shear_kernel(ShearArgs a) {
   __shared__ double red[4][kPtsPerChunk][6];
   __shared__ Point pts_s[kPtsPerChunk];
+  __shared__ __align__(16) float wred[4][64 * 8];     // per-wave transposed-reduction scratch
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int chunk0 = blockIdx.y * kPtsPerChunk;
   const int npc = min(kPtsPerChunk, a.n_pts - chunk0);
@@ -153,59 +186,65 @@ __global__ void __launch_bounds__(256) shear_kernel(ShearArgs a) {
     }
     for (int pj = 0; pj < npc; ++pj) {
       const Point P = pts_s[pj];
+      // pass 1: log weights (padding and out-of-support samples -inf), lane maximum
       float lw[kMaxPerLane];
       float m = -INFINITY;
 #pragma unroll
       for (int i = 0; i < kMaxPerLane; ++i) {
-        lw[i] = -INFINITY;
-        if (i < KL && c0[i] > -INFINITY) {
-          lw[i] = logw(P, a, geo(P, e1[i], e2[i]), ls[i]) + c0[i];
-          m = fmaxf(m, lw[i]);
-        }
+        lw[i] = (i < KL) ? logw<EK, SZ>(P, a, geo(P, e1[i], e2[i]), ls[i]) + c0[i] : -INFINITY;
+        m = fmaxf(m, lw[i]);
       }
-      float s0 = 0.f, u0 = 0.f, u1 = 0.f, t1 = 0.f, t2 = 0.f, tE = 0.f;
-      if (m > -INFINITY) {
+      // pass 2: the lane's sums of e^(lw - m) times 1 and the derivative terms;
+      // every term is finite (E is clamped below 1 in the ellipticity-density
+      // derivative) and carries the factor e^(lw - m), zero for -inf weights
+      const float ms = (m > -INFINITY) ? m : 0.0f;
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // s0, u0, u1, t1, t2, tE
 #pragma unroll
-        for (int i = 0; i < kMaxPerLane; ++i) {
-          if (i < KL && lw[i] > -INFINITY) {
-            const float ex = __expf(lw[i] - m);
-            s0 += ex;
-            if (a.want_grad) {
-              const Geo q = geo(P, e1[i], e2[i]);
-              const float dB1 = 2.0f * (-q.br * e1[i] - q.bi * e2[i]);
-              const float dB2 = 2.0f * (-q.br * e2[i] + q.bi * e1[i]);
-              const float dE1 = (-2.0f * q.ar - q.E * dB1) * q.iB;
-              const float dE2 = (-2.0f * q.ai - q.E * dB2) * q.iB;
-              const float dlp = (a.e_kind == 0) ? -2.0f * __builtin_amdgcn_rcpf(1.0f - q.E) - P.inv2se2
-                                                : -P.inv2se2;
-              u0 += ex * (dlp * dE1 - 2.0f * dB1 * q.iB);
-              u1 += ex * (dlp * dE2 - 2.0f * dB2 * q.iB);
-              if (a.size_term) {
-                const float z = (ls[i] * kLn10F - P.mu) * P.inv_sig_s;
-                t1 += ex * z;
-                t2 += ex * z * z;
-              }
-              tE += ex * q.E;
-            }
+      for (int i = 0; i < kMaxPerLane; ++i) {
+        if (i >= KL) continue;
+        const float ex = __expf(lw[i] - ms);
+        v[0] += ex;
+        if (GRAD) {
+          const Geo q = geo(P, e1[i], e2[i]);
+          const float dB1 = 2.0f * (-q.br * e1[i] - q.bi * e2[i]);
+          const float dB2 = 2.0f * (-q.br * e2[i] + q.bi * e1[i]);
+          const float dE1 = (-2.0f * q.ar - q.E * dB1) * q.iB;
+          const float dE2 = (-2.0f * q.ai - q.E * dB2) * q.iB;
+          const float dlp = (EK == 0)
+                                ? -2.0f * __builtin_amdgcn_rcpf(1.0f - fminf(q.E, 0.999999f)) - P.inv2se2
+                                : -P.inv2se2;
+          v[1] = fmaf(ex, dlp * dE1 - 2.0f * dB1 * q.iB, v[1]);
+          v[2] = fmaf(ex, dlp * dE2 - 2.0f * dB2 * q.iB, v[2]);
+          if (SZ) {
+            const float z = (ls[i] * kLn10F - P.mu) * P.inv_sig_s;
+            v[3] = fmaf(ex, z, v[3]);
+            v[4] = fmaf(ex * z, z, v[4]);
           }
+          v[5] = fmaf(ex, q.E, v[5]);
         }
       }
+      // the wave maximum M, the lanes' sums rescaled by e^(m - M), and their
+      // float64 totals over the wave in one transposed reduction
       const float M = wave_max(m);
       double ell = -INFINITY, g[5] = {0, 0, 0, 0, 0};
       if (M > -INFINITY) {
-        const double f = (m > -INFINITY) ? (double)__expf(m - M) : 0.0;
-        const double S = wave_total((double)s0 * f);
+        const float f = (m > -INFINITY) ? __expf(m - M) : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) v[j] *= f;
+        double T[6];
+        wave_total6_f64(v, wred[wave], T);
+        const double S = T[0];
         ell = (double)M + log(S) - logK;
-        if (a.want_grad) {
+        if (GRAD) {
           const double iS = 1.0 / S;
           const double inv_ss = (double)P.inv_sig_s;
-          g[0] = wave_total((double)u0 * f) * iS - (double)P.c1;
-          g[1] = wave_total((double)u1 * f) * iS - (double)P.c2;
-          if (a.size_term) {
-            g[2] = inv_ss * wave_total((double)t1 * f) * iS;
-            g[3] = inv_ss * (wave_total((double)t2 * f) * iS - 1.0);
+          g[0] = T[1] * iS - (double)P.c1;
+          g[1] = T[2] * iS - (double)P.c2;
+          if (SZ) {
+            g[2] = inv_ss * T[3] * iS;
+            g[3] = inv_ss * (T[4] * iS - 1.0);
           }
-          g[4] = (double)P.inv_se3 * wave_total((double)tE * f) * iS - (double)P.dlnZ;
+          g[4] = (double)P.inv_se3 * T[5] * iS - (double)P.dlnZ;
         }
       }
       if (lane == pj) {
@@ -442,7 +481,18 @@ __global__ void shear_hmc_stats_kernel(const ShearChain* __restrict__ st, int C,
 hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s) {
   if (a.n_pts <= 0) return hipSuccess;
   const int chunks = (a.n_pts + kPtsPerChunk - 1) / kPtsPerChunk;
-  hipLaunchKernelGGL(shear_kernel, dim3(n_blocks, chunks), dim3(256), 0, s, a);
+  const dim3 grid(n_blocks, chunks), blk(256);
+  const int key = (a.want_grad ? 4 : 0) | (a.size_term ? 2 : 0) | (a.e_kind == 0 ? 0 : 1);
+  switch (key) {
+    case 0: hipLaunchKernelGGL((shear_kernel<false, false, 0>), grid, blk, 0, s, a); break;
+    case 1: hipLaunchKernelGGL((shear_kernel<false, false, 1>), grid, blk, 0, s, a); break;
+    case 2: hipLaunchKernelGGL((shear_kernel<false, true, 0>), grid, blk, 0, s, a); break;
+    case 3: hipLaunchKernelGGL((shear_kernel<false, true, 1>), grid, blk, 0, s, a); break;
+    case 4: hipLaunchKernelGGL((shear_kernel<true, false, 0>), grid, blk, 0, s, a); break;
+    case 5: hipLaunchKernelGGL((shear_kernel<true, false, 1>), grid, blk, 0, s, a); break;
+    case 6: hipLaunchKernelGGL((shear_kernel<true, true, 0>), grid, blk, 0, s, a); break;
+    default: hipLaunchKernelGGL((shear_kernel<true, true, 1>), grid, blk, 0, s, a); break;
+  }
   return hipGetLastError();
 }
 

@@ -237,14 +237,16 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi):
     assert agree >= G * C * S - 1
 
 
-def test_hmc_dual_averaging_parity(bsi):
+@pytest.mark.parametrize("workload", ["tiny", "uniform"])
+def test_hmc_dual_averaging_parity(bsi, workload):
     """Trajectories agree until the first accept/reject decision that float32
     and float64 potentials take differently; the step-size recursion is then
-    checked exactly by replaying the GPU's own acceptance statistics."""
+    checked exactly by replaying the GPU's own acceptance statistics.  The
+    53-pixel case runs the two-chains-per-wave kernel (trace included)."""
     import torch
-    _log("hmc dual averaging parity")
+    _log(f"hmc dual averaging parity {workload}")
     G, C, W, S = 3, 2, 30, 4
-    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, "tiny", G, C, seed=11)
+    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, workload, G, C, seed=11)
     seed = 77
     # Fisher-diagonal metric: a well-conditioned trajectory (with the identity
     # metric the log-flux direction puts eps * omega near the leapfrog
