@@ -47,7 +47,7 @@ class Galaxy:
     psf_fwhm: float
     sigma: float
     ref_xy: tuple = (0.0, 0.0)
-    profile: int = render.PROFILE_EXP
+    profile: object = render.PROFILE_EXP   # PROFILE_EXP, PROFILE_GAUSS or a render.Spergel
 
 
 def clamp_theta(theta, ip=prior.PAPER_INTERIM):

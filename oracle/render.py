@@ -25,6 +25,15 @@ frequency, which makes m exactly real).  The spectrum is
 
 G(q) = (1 + r0^2 q)^(-3/2) for the exponential profile (its 2-D Fourier
 transform) and G(q) = exp(-sigma_g^2 q / 2) for the Gaussian test profile.
+
+Appendix B of the paper also fits Spergel profiles of fixed index nu (the
+model-bias study).  A Spergel profile (Spergel 2010) has the surface
+brightness I(r) = F / (2 pi r0^2) (r/r0)^nu K_nu(r/r0) / (2^nu Gamma(nu + 1))
+(K_nu the modified Bessel function of the second kind) and the unit-flux
+Fourier transform (1 + k^2 r0^2)^(-(1 + nu)), so G(q) = (1 + r0^2 q)^(-(1+nu));
+nu = 1/2 is the exponential profile.  Its half-light radius is eta_nu r0,
+eta_nu the root of x^(nu+1) K_(nu+1)(x) = 2^(nu-1) Gamma(nu + 1) (the
+enclosed flux 1 - x^(nu+1) K_(nu+1)(x) / (2^nu Gamma(nu + 1)) equal to 1/2).
 """
 from __future__ import annotations
 
@@ -47,6 +56,37 @@ HLR_TO_SIGMA_GAUSS = 1.0 / np.sqrt(2.0 * np.log(2.0))
 
 PROFILE_EXP = 0
 PROFILE_GAUSS = 1
+PROFILE_SPERGEL = 2
+
+
+def spergel_hlr_factor(nu: float) -> float:
+    """eta_nu = half-light radius / r0 of the Spergel profile of index nu:
+    the root of x^(nu+1) K_(nu+1)(x) = 2^(nu-1) Gamma(nu+1), by bisection."""
+    from scipy.special import gamma, kv
+    target = 2.0 ** (nu - 1.0) * gamma(nu + 1.0)
+    f = lambda x: x ** (nu + 1.0) * kv(nu + 1.0, x) - target     # decreasing in x
+    lo, hi = 1e-8, 1.0
+    while f(hi) > 0.0:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) > 0.0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+class Spergel:
+    """Spergel profile of fixed index nu (pass as ``profile``)."""
+
+    def __init__(self, nu: float):
+        self.nu = float(nu)
+        self.eta = spergel_hlr_factor(self.nu)
+
+
+def _kind(profile) -> int:
+    return PROFILE_SPERGEL if isinstance(profile, Spergel) else int(profile)
 
 
 def freq_points(N: int):
@@ -67,7 +107,10 @@ def pixel_centres(N: int) -> np.ndarray:
 def scales(s_arcsec, psf_fwhm_arcsec, pixel_scale, profile=PROFILE_EXP):
     """Profile scale (pixels) and PSF sigma (pixels)."""
     s_pix = np.asarray(s_arcsec, dtype=np.float64) / pixel_scale
-    if profile == PROFILE_EXP:
+    kind = _kind(profile)
+    if kind == PROFILE_SPERGEL:
+        r = s_pix / profile.eta        # Spergel scale radius r0
+    elif kind == PROFILE_EXP:
         r = s_pix / ETA_EXP            # exponential scale radius r0
     else:
         r = s_pix * HLR_TO_SIGMA_GAUSS  # Gaussian sigma
@@ -104,7 +147,11 @@ def spectrum(params, N, pixel_scale, psf_fwhm, profile=PROFILE_EXP, derivs=False
     r, sp = scales(s, psf_fwhm, pixel_scale, profile)
     E = e1 * e1 + e2 * e2
     q = quad_form(KX, KY, e1, e2)
-    if profile == PROFILE_EXP:
+    kind = _kind(profile)
+    if kind == PROFILE_SPERGEL:
+        a = 1.0 + r * r * q
+        G = a ** -(1.0 + profile.nu)
+    elif kind == PROFILE_EXP:
         a = 1.0 + r * r * q
         G = a ** -1.5
     else:
@@ -119,7 +166,10 @@ def spectrum(params, N, pixel_scale, psf_fwhm, profile=PROFILE_EXP, derivs=False
     P = KX * KY
     dq_de1 = (2.0 * e1 * K + 2.0 * D + 2.0 * e1 * q) / (1.0 - E)
     dq_de2 = (2.0 * e2 * K + 4.0 * P + 2.0 * e2 * q) / (1.0 - E)
-    if profile == PROFILE_EXP:
+    if kind == PROFILE_SPERGEL:
+        dlnG_dq = -(1.0 + profile.nu) * r * r / a
+        dlnG_ds = -2.0 * (1.0 + profile.nu) * r * r * q / (s * a)
+    elif kind == PROFILE_EXP:
         dlnG_dq = -1.5 * r * r / a
         dlnG_ds = -3.0 * r * r * q / (s * a)
     else:

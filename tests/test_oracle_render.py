@@ -239,3 +239,75 @@ def test_every_slot_plan_tiles_the_half_plane():
                 full.add((u, v))
                 full.add((-u, -v))
             assert len(full) == nc * nc, (N, P)
+
+# ---- Spergel profiles (the paper's Appendix B model-bias fits) -------------
+
+def _spergel_intensity(r, nu, r0=1.0):
+    """Unit-flux Spergel surface brightness (Spergel 2010), written out."""
+    x = r / r0
+    return x ** nu * special.kv(nu, x) / (2 ** nu * special.gamma(nu + 1) * 2 * math.pi * r0 * r0)
+
+
+@pytest.mark.parametrize("nu", [-0.6, 0.0, 0.5, 1.5, 3.0])
+def test_spergel_hlr_factor_by_quadrature(nu):
+    # the enclosed flux at eta_nu r0, integrated from the intensity itself, is 1/2
+    eta = render.spergel_hlr_factor(nu)
+    f = lambda r: 2 * math.pi * r * _spergel_intensity(r, nu)
+    inner, _ = integrate.quad(f, 0.0, eta, limit=400, epsabs=1e-14, epsrel=1e-12)
+    total, _ = integrate.quad(f, 0.0, np.inf, limit=400, epsabs=1e-14, epsrel=1e-12)
+    assert abs(total - 1.0) < 1e-9
+    assert abs(inner - 0.5) < 1e-9, (nu, inner)
+
+
+@pytest.mark.parametrize("nu", [-0.6, 0.0, 1.5, 3.0])
+def test_spergel_ft_against_hankel_quadrature(nu):
+    # the oracle's G at e = 0 (pixel sinc divided out) against the Hankel
+    # transform 2 pi int r J0(k r) I(r) dr of the intensity
+    r0 = 1.9
+    prof = render.Spergel(nu)
+    N = 64
+    s = r0 * prof.eta * PS
+    T = render.spectrum([1.0, s, 0, 0, 0, 0], N, PS, 1e-9, prof)
+    u, _ = render.freq_points(N)
+    kk = 2 * np.pi * u / N
+    iv = int(np.argmin(np.abs(kk)))
+    for kt in (0.0, 0.4, 1.2):
+        iu = int(np.argmin(np.abs(kk - kt)))
+        kx = kk[iu]
+        f = lambda r: 2 * math.pi * r * special.j0(kx * r) * _spergel_intensity(r, nu, r0)
+        hank, _ = integrate.quad(f, 0.0, 120 * r0, limit=2000, epsabs=1e-13, epsrel=1e-11)
+        val = T[iv, iu].real / np.sinc(u[iu] / N)
+        assert abs(val - hank) < 2e-9, (nu, kx, val, hank)
+
+
+def test_spergel_half_is_the_exponential():
+    p = [150.0, 0.45, 0.3, -0.2, 0.4, -0.7]
+    for N in (25, 32):
+        a = render.render_one(p, N, PS, 0.7)
+        b = render.render_one(p, N, PS, 0.7, render.Spergel(0.5))
+        assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+        _, da = render.spectrum(p, N, PS, 0.7, derivs=True)
+        _, db = render.spectrum(p, N, PS, 0.7, render.Spergel(0.5), derivs=True)
+        assert np.max(np.abs(da - db)) < 1e-11 * np.max(np.abs(da))
+
+
+@pytest.mark.parametrize("nu", [-0.6, 1.5])
+def test_spergel_flux_and_gradient(nu):
+    prof = render.Spergel(nu)
+    N = 32
+    p = np.array([180.0, 0.5, 0.2, -0.25, 0.3, -0.2])
+    m = render.render_one(p, N, PS, 0.7, prof)
+    assert abs(m.sum() - p[0]) < 1e-11 * p[0]
+    rng = np.random.default_rng(31)
+    d = render.render_one(p * [1.1, 0.95, 1, 1, 1, 1] + [0, 0, 0.05, 0.02, 0.1, -0.1],
+                          N, PS, 0.7, prof) + rng.normal(0, 1, (N, N))
+    ll, g = render.loglik_grad(d, p, N, PS, 0.7, 1.0, prof)
+    _, dT = render.spectrum(p, N, PS, 0.7, prof, derivs=True)
+    scale = [math.sqrt(np.sum(render.synthesize(dT[j], N) ** 2)) for j in range(6)]
+    f = lambda q: render.loglik(d, q, N, PS, 0.7, 1.0, prof)
+    for j in range(6):
+        h = 1e-4 * max(1.0, abs(p[j]))
+        e = np.zeros(6)
+        e[j] = h
+        fd = (8 * (f(p + e) - f(p - e)) - (f(p + 2 * e) - f(p - 2 * e))) / (12 * h)
+        assert abs(fd - g[j]) <= 1e-6 * (abs(g[j]) + scale[j]), (nu, j, fd, g[j])
