@@ -409,6 +409,34 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
             "status_nonzero": int((status != 0).sum())}
 
 
+def spergel_leg(api, torch, stream, n_gal, nu, log=None):
+    """Model-bias fit (Appendix B): the uniform workload's exponential galaxies
+    (53-pixel stamps) fitted with a Spergel profile of fixed index nu, same
+    sampler settings as the headline line."""
+    cfg = gen.CONFIGS["uniform"]
+    t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
+    bs = api.Batch(n=b.n, psf_fwhm=b.psf_fwhm, sigma=b.sigma, pixel_scale=b.pixel_scale,
+                   profile=api.N.PROFILE_SPERGEL, spergel_nu=nu)
+    C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
+    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
+                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
+                         use_graph=True, seed=gen.chain_seed(cfg.index))
+    wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
+    api.hmc_sample(bs, data, ref, init, wcfg, want_samples=False)      # warm
+    (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(bs, data, ref, init, hcfg), stream)
+    (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
+    _, t_w = timed(torch, lambda: api.hmc_sample(bs, data, ref, init, wcfg, want_samples=False), stream)
+    n_eff = float(e.mean(dim=1).mean())
+    t_s = t_hmc - t_w
+    tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
+    flop = flops_per_eval(cfg.n_pix) * n_gal * C * L * (W + S)
+    return {"n_gal": n_gal, "spergel_nu": nu, "t_hmc_s": round(t_hmc, 4), "t_warmup_s": round(t_w, 4),
+            "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 1),
+            "achieved_tflops": round(flop / t_hmc / 1e12, 3),
+            "accept_rate": round(float(st[..., 0].mean()), 4),
+            "status_nonzero": int((status != 0).sum())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -419,13 +447,16 @@ def main():
     ap.add_argument("--plain-gal", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
-    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass"], default="uniform",
+    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "spergel"],
+                    default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
     ap.add_argument("--no-legs", action="store_true", help="uniform workload without the shear and "
                     "serving legs (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
+    ap.add_argument("--spergel-nu", type=float, default=-0.6,
+                    help="--workload spergel: the fixed Spergel index of the fit")
     ap.add_argument("--plan", type=int, default=0,
                     help="uniform workload: this slot plan P for the 53-pixel kernel instead of autotuning")
     ap.add_argument("--transform-only", action="store_true",
@@ -466,7 +497,16 @@ def main():
                    "config": {"workload": "10,000 galaxies x 1,000 interim samples, 4 points"}, **res}
             print(json.dumps(out), flush=True)
             return
-        if args.workload == "uneven":
+        if args.workload == "spergel":
+            G = args.n_gal or gen.CONFIGS["uniform"].n_gal
+            res = spergel_leg(api, torch, stream, G, args.spergel_nu, log)
+            out = {"metric": "galaxies/sec at 300 ESS (Spergel-profile fit of exponential galaxies)",
+                   "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": f"model-bias fit: 53-pixel exponential galaxies, Spergel "
+                                          f"nu = {args.spergel_nu}, 4 chains, 20 leapfrog steps, "
+                                          "300 warmup + 1000 draws"}, **res}
+        elif args.workload == "uneven":
             G = args.n_gal or gen.CONFIGS["uneven"].n_gal
             res = uneven_leg(api, torch, stream, G, log)
             out = {"metric": "galaxies/sec at 300 ESS (uneven stamps 25-101 px)",

@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define BSI_VERSION 1
+#define BSI_VERSION 2
 
 enum {
   BSI_OK = 0,
@@ -67,7 +67,17 @@ enum {
   BSI_STATUS_DIVERGENT = 4        /* |dH| > 1000 in some trajectory                       */
 };
 
-enum { BSI_PROFILE_EXPONENTIAL = 0, BSI_PROFILE_GAUSSIAN = 1 };
+/* Galaxy light profiles.  EXPONENTIAL is the model of Section 3.2 (its
+ * Fourier transform (1 + r0^2 k^2)^(-3/2)); SPERGEL is the Spergel (2010)
+ * profile of fixed index nu used for the model-bias fits of Appendix B, with
+ * Fourier transform (1 + r0^2 k^2)^(-(1+nu)) (nu = 1/2 is the exponential,
+ * nu near -0.6 close to de Vaucouleurs); GAUSSIAN is a test profile.  The size
+ * parameter is always the half-light radius. */
+enum { BSI_PROFILE_EXPONENTIAL = 0, BSI_PROFILE_GAUSSIAN = 1, BSI_PROFILE_SPERGEL = 2 };
+
+/* Spergel indices accepted (BSI_EINVAL outside). */
+#define BSI_SPERGEL_NU_MIN (-0.85f)
+#define BSI_SPERGEL_NU_MAX 4.0f
 
 /* Log-likelihood evaluation method for bsi_loglik_grad. */
 enum {
@@ -105,6 +115,8 @@ typedef struct {
   const float* sigma;        /* [device] pixel noise sigma per galaxy (b = sigma^2), > 0 */
   float pixel_scale;         /* arcsec per pixel, > 0                                   */
   int32_t profile;           /* BSI_PROFILE_*                                           */
+  float spergel_nu;          /* Spergel index for BSI_PROFILE_SPERGEL, in
+                                [BSI_SPERGEL_NU_MIN, BSI_SPERGEL_NU_MAX]; else ignored   */
 } bsi_batch;
 
 /*
@@ -178,7 +190,7 @@ typedef struct {
   int32_t waves_per_chain;   /* 0 or 1: one wave per chain (throughput); 2 or 4: up to that
                                 many waves share each chain's evaluations (latency), for the
                                 workload stamp sizes with their default slot plan and the
-                                exponential profile (fewer where a size has fewer super-rows
+                                exponential or Spergel profile (fewer where a size has fewer super-rows
                                 or n_chains * waves would exceed 4).  The sums are split
                                 differently, so samples agree with the one-wave form to
                                 float32 rounding, and bitwise between calls with equal
@@ -297,7 +309,7 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
  * created afterwards) uses it.  Results do not depend on the plan beyond
  * float32 rounding (the order of the sums changes).  The trajectory kernel
  * runs two chains per wave (32 lanes each) for an even number of chains up
- * to 4 on the plans 25: P 3, 41: P 1, 53: P 3 (exponential profile,
+ * to 4 on the plans 25: P 3, 41: P 1, 53: P 3 (exponential or Spergel profile,
  * one wave per chain requested), one chain per wave otherwise; the choice
  * depends only on the size, plan and configuration, never on the batch. */
 
@@ -387,6 +399,7 @@ typedef struct {
   bsi_interim interim;
   float pixel_scale;
   int32_t profile;             /* BSI_PROFILE_*                                             */
+  float spergel_nu;            /* Spergel index (BSI_PROFILE_SPERGEL only)                  */
   int32_t pace;                /* 0: every size advances n_iter iterations per call;
                                   1: the slowest size advances n_iter and every other size
                                   about n_iter * tau_slowest / tau_N, tau the per-iteration

@@ -16,6 +16,9 @@ STATUS_DIVERGENT = 4
 
 PROFILE_EXPONENTIAL = 0
 PROFILE_GAUSSIAN = 1
+PROFILE_SPERGEL = 2
+SPERGEL_NU_MIN = -0.85
+SPERGEL_NU_MAX = 4.0
 LIK_KSPACE = 0
 LIK_PIXEL = 1
 METRIC_GIVEN = 0
@@ -32,7 +35,7 @@ E_TRUNC_GAUSS = 1
 class Batch(C.Structure):
     _fields_ = [("n_gal", C.c_int32), ("n", C.POINTER(C.c_int32)), ("off", C.POINTER(C.c_int64)),
                 ("psf_fwhm", C.c_void_p), ("sigma", C.c_void_p), ("pixel_scale", C.c_float),
-                ("profile", C.c_int32)]
+                ("profile", C.c_int32), ("spergel_nu", C.c_float)]
 
 
 class Interim(C.Structure):
@@ -65,7 +68,8 @@ class ShearHmcCfg(C.Structure):
 class SlotsCfg(C.Structure):
     _fields_ = [("n_sizes", C.c_int32), ("sizes", C.POINTER(C.c_int32)), ("hbm_budget", C.c_int64),
                 ("max_slots", C.c_int32), ("hmc", HmcCfg), ("interim", Interim),
-                ("pixel_scale", C.c_float), ("profile", C.c_int32), ("pace", C.c_int32),
+                ("pixel_scale", C.c_float), ("profile", C.c_int32),
+                ("spergel_nu", C.c_float), ("pace", C.c_int32),
                 ("ess_target", C.c_float), ("ess_every", C.c_int32)]
 
 

@@ -75,6 +75,7 @@ class Batch:
     pixel_scale: float = 0.2
     profile: int = N.PROFILE_EXPONENTIAL
     off: np.ndarray = field(default=None)   # int64 [G]; default: packed in order
+    spergel_nu: float = 0.5       # Spergel index (profile PROFILE_SPERGEL only)
 
     def __post_init__(self):
         self.n = np.ascontiguousarray(self.n, dtype=np.int32)
@@ -102,6 +103,7 @@ class Batch:
         b.sigma = self.sigma.data_ptr()
         b.pixel_scale = float(self.pixel_scale)
         b.profile = int(self.profile)
+        b.spergel_nu = float(self.spergel_nu)
         return b
 
 
@@ -308,14 +310,14 @@ class Slots:
     def __init__(self, sizes, cfg: HmcConfig, hbm_budget: int, max_slots: int = 0, interim=None,
                  pixel_scale: float = 0.2, profile: int = N.PROFILE_EXPONENTIAL,
                  pace: bool = False, ess_target: float = 0.0, ess_every: int = 100, device: int = 0,
-                 lib: Library | None = None):
+                 lib: Library | None = None, spergel_nu: float = 0.5):
         self.lib = lib or get(device)
         self.device = torch.device("cuda", device)
         self.cfg = cfg
         self._sizes = (C.c_int32 * len(sizes))(*[int(x) for x in sizes])
         c = N.SlotsCfg(len(sizes), C.cast(self._sizes, C.POINTER(C.c_int32)), int(hbm_budget),
                        int(max_slots), cfg.c(), _interim(interim), float(pixel_scale), int(profile),
-                       int(bool(pace)), float(ess_target), int(ess_every))
+                       float(spergel_nu), int(bool(pace)), float(ess_target), int(ess_every))
         self._stream = torch.cuda.current_stream(self.device)
         h = C.c_void_p()
         self.lib.check(self.lib.lib.bsi_slots_create(self.lib.h, C.byref(c),

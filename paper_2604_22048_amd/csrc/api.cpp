@@ -47,8 +47,13 @@ int check_batch(bsi_handle h, const bsi_batch* b) {
   if (!b->psf_fwhm || !b->sigma) return fail(h, BSI_EINVAL, "batch psf_fwhm/sigma are NULL");
   if (!(b->pixel_scale > 0.0f) || !std::isfinite(b->pixel_scale))
     return fail(h, BSI_EINVAL, "pixel_scale must be positive");
-  if (b->profile != BSI_PROFILE_EXPONENTIAL && b->profile != BSI_PROFILE_GAUSSIAN)
+  if (b->profile != BSI_PROFILE_EXPONENTIAL && b->profile != BSI_PROFILE_GAUSSIAN &&
+      b->profile != BSI_PROFILE_SPERGEL)
     return fail(h, BSI_EINVAL, "unknown profile %d", b->profile);
+  if (b->profile == BSI_PROFILE_SPERGEL &&
+      !(b->spergel_nu >= BSI_SPERGEL_NU_MIN && b->spergel_nu <= BSI_SPERGEL_NU_MAX))
+    return fail(h, BSI_EINVAL, "Spergel index %g outside [%g, %g]", (double)b->spergel_nu,
+                (double)BSI_SPERGEL_NU_MIN, (double)BSI_SPERGEL_NU_MAX);
   for (int i = 0; i < b->n_gal; ++i) {
     if (b->n[i] < 8 || b->n[i] > kMaxN)
       return fail(h, BSI_EUNSUPPORTED, "stamp side %d of galaxy %d outside [8, %d]", b->n[i], i, kMaxN);
@@ -218,15 +223,15 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Plan p = make_plan(h, batch);
   if ((rc = upload_plan(h, batch, p, s))) return rc;
-  const float rs = profile_rscale(batch->profile, batch->pixel_scale);
+  const float rs = profile_rscale(batch->profile, batch->pixel_scale, batch->spergel_nu);
   for (const ClassRange& c : p.classes) {
     const int32_t* gi = gidx_ptr(h, c);
     const int64_t* off = static_cast<const int64_t*>(h->off.p);
     hipError_t e = transform_of(h, c.N) == BSI_TRANSFORM_MFMA
         ? launch_render_mfma(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
-                             1.0f / batch->pixel_scale, batch->profile, out, s)
+                             1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s)
         : launch_render(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
-                        1.0f / batch->pixel_scale, batch->profile, out, s);
+                        1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s);
     if (e != hipSuccess) return hip_fail(h, e, "render launch");
   }
   return BSI_OK;
@@ -247,7 +252,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Plan p = make_plan(h, batch);
   if ((rc = upload_plan(h, batch, p, s))) return rc;
-  const float rs = profile_rscale(batch->profile, batch->pixel_scale);
+  const float rs = profile_rscale(batch->profile, batch->pixel_scale, batch->spergel_nu);
   const int64_t* off = static_cast<const int64_t*>(h->off.p);
   double* chi2 = nullptr;
   const double* model = nullptr;
@@ -256,7 +261,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     if ((rc = ensure(h, h->chi2, (size_t)batch->n_gal * sizeof(double)))) return rc;
     for (const ClassRange& c : p.classes) {
       hipError_t e = launch_render_f64(params, batch->psf_fwhm, gidx_ptr(h, c), c.count, off, c.N,
-                                       rs, 1.0f / batch->pixel_scale, batch->profile,
+                                       rs, 1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu,
                                        static_cast<double*>(h->model.p), s);
       if (e != hipSuccess) return hip_fail(h, e, "render launch");
     }
@@ -268,7 +273,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     hipError_t e = launch_loglik(static_cast<const float2*>(h->dh.p),
                                  static_cast<const int64_t*>(h->bin_off.p), gidx_ptr(h, c), c.count,
                                  params, batch->psf_fwhm, batch->sigma, c.N, c.P, rs,
-                                 1.0f / batch->pixel_scale, batch->profile,
+                                 1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu,
                                  method == BSI_LIK_PIXEL, chi2, loglik, grad, status, s);
     if (e != hipSuccess) return hip_fail(h, e, "loglik launch");
   }
@@ -330,9 +335,10 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   a.state = static_cast<ChainState*>(h->state.p);
   a.samples = samples;
   a.trace = cfg->trace;
-  a.rscale = profile_rscale(batch->profile, batch->pixel_scale);
+  a.rscale = profile_rscale(batch->profile, batch->pixel_scale, batch->spergel_nu);
   a.pscale_inv = 1.0f / batch->pixel_scale;
   a.prof = batch->profile;
+  a.nu = batch->spergel_nu;
   a.C = C;
   a.L = cfg->n_leapfrog;
   a.W = cfg->n_warmup;

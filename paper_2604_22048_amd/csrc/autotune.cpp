@@ -149,7 +149,7 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
       if (e == hipSuccess) e = hipMemcpy(off, ho.data(), G * 8, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = hipMemcpy(boff, hb.data(), G * 8, hipMemcpyHostToDevice);
       if (e == hipSuccess) e = launch_render(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale,
-                                            kProfExpHost, data, s);
+                                            kProfExpHost, 0.5f, data, s);
       HmcArgs a{};
       a.dh = dh;
       a.bin_off = boff;
@@ -296,9 +296,9 @@ int bsi_autotune_transform(bsi_handle h, int32_t n_sizes, const int32_t* sizes, 
       auto run = [&]() {
         switch (m) {
           case 0: return launch_render(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale, kProfExpHost,
-                                       out, s);
+                                       0.5f, out, s);
           case 1: return launch_render_mfma(prm, psf, gidx, G, off, N, rs, 1.0f / pixel_scale,
-                                            kProfExpHost, out, s);
+                                            kProfExpHost, 0.5f, out, s);
           default: return launch_stamp_dft(m == 3, out, nullptr, gidx, G, off, boff, N, P, dh, nullptr, s);
         }
       };

@@ -8,14 +8,19 @@
 
 namespace bsi {
 
-enum { kProfExpHost = 0, kProfGaussHost = 1 };
+enum { kProfExpHost = 0, kProfGaussHost = 1, kProfSpergelHost = 2 };
 
 // Half-light radius of exp(-r) in scale radii: root of (1 + x) exp(-x) = 1/2.
 double exponential_hlr_factor();
+// Half-light radius of the Spergel profile of index nu in scale radii r0: the
+// root of x^(nu+1) K_(nu+1)(x) = 2^(nu-1) Gamma(nu+1) (enclosed flux 1/2).
+double spergel_hlr_factor(double nu);
 
 // Scale from half-light radius [arcsec] to the profile radius in pixels.
-inline float profile_rscale(int prof, float pixel_scale) {
-  if (prof == 0) return (float)(1.0 / (exponential_hlr_factor() * (double)pixel_scale));
+inline float profile_rscale(int prof, float pixel_scale, float nu = 0.5f) {
+  if (prof == kProfExpHost) return (float)(1.0 / (exponential_hlr_factor() * (double)pixel_scale));
+  if (prof == kProfSpergelHost)
+    return (float)(1.0 / (spergel_hlr_factor((double)nu) * (double)pixel_scale));
   return (float)(1.0 / (1.1774100225154747 * (double)pixel_scale));   // sqrt(2 ln 2)
 }
 
@@ -26,7 +31,7 @@ size_t render_mfma_lds_bytes(int N);
 size_t dft_bins_mfma_lds_bytes(int N);
 // The transforms as FP32 DFT products on the matrix cores (dft_mfma.hip)
 hipError_t launch_render_mfma(const float* params, const float* psf, const int32_t* gidx, int n,
-                              const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                              const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                               float* out, hipStream_t s);
 hipError_t launch_dft_bins_mfma(const float* data, const double* model, const int32_t* gidx, int n,
                                 const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
@@ -42,16 +47,16 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
                            const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
                            double* chi2, const float* sigma, hipStream_t s);
 hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
-                         const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                         const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                          float* out, hipStream_t s);
 hipError_t launch_render_f64(const float* params, const float* psf, const int32_t* gidx, int n,
-                             const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                             const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                              double* out, hipStream_t s);
 
 // ---- likelihood.hip ----
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
                          const float* params, const float* psf, const float* sigma, int N, int P,
-                         float rscale, float pscale_inv, int prof, int resid_mode,
+                         float rscale, float pscale_inv, int prof, float nu, int resid_mode,
                          const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
                          hipStream_t s);
 
@@ -103,6 +108,7 @@ struct HmcArgs {
   int wpc;                // waves per chain of the trajectory kernel (hmc_split_waves)
   float rscale, pscale_inv;
   int prof;
+  float nu;               // Spergel index (prof == kProfSpergelHost)
   int C, L, W, S, adapt, metric;
   float eps0, delta, jitter, mu;
   uint32_t k0, k1;
@@ -117,12 +123,12 @@ struct HmcArgs {
 size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1);
 // Waves per chain for stamp side N, C chains and plan P when up to max_w are
 // requested: a power of two <= max_w, <= the plan's super-rows, C W <= 4, and
-// 1 unless the profile is exponential and P is N's default plan with a
+// 1 unless the profile is exponential or Spergel and P is N's default plan with a
 // specialised kernel.
 int hmc_split_waves(int N, int C, int P, int prof, int max_w);
 // Chains per wave of the trajectory kernel: 2 (two 32-lane halves) for an
 // even number of chains (at most 4), one wave per chain (wpc = 1), the
-// exponential profile and a plan whose specialised two-chain kernel is the
+// exponential or Spergel profile and a plan whose specialised two-chain kernel is the
 // faster one (25: P 3, 41: P 1, 53: P 3); else 1.
 int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc);
 // Slot plans with a trajectory kernel specialised for stamp side N (0-terminated list of P).

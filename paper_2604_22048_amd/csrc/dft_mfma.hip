@@ -60,7 +60,7 @@ __host__ __device__ inline size_t render_mfma_lds(int N) {
 
 __global__ void __launch_bounds__(256) render_mfma_kernel(
     const float* __restrict__ params, const float* __restrict__ psf_fwhm, const int32_t* __restrict__ gidx,
-    const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof,
+    const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof, float nu,
     float* __restrict__ out) {
   extern __shared__ float2 smr[];
   const RenderDims d = render_dims(N);
@@ -117,6 +117,8 @@ __global__ void __launch_bounds__(256) render_mfma_kernel(
         if (prof == kProfExp) {
           const float rs = rsqrtf(fmaf(r2, q, 1.0f));
           G = rs * rs * rs;
+        } else if (prof == kProfSpergel) {
+          G = exp2f(-(1.0f + nu) * log2f(fmaf(r2, q, 1.0f)));
         } else {
           G = expf(-0.5f * r2 * q);
         }
@@ -344,7 +346,7 @@ hipError_t launch_dft_bins_mfma(const float* data, const double* model, const in
 }
 
 hipError_t launch_render_mfma(const float* params, const float* psf, const int32_t* gidx, int n,
-                              const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                              const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                               float* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = render_mfma_lds(N);
@@ -352,7 +354,7 @@ hipError_t launch_render_mfma(const float* params, const float* psf, const int32
   (void)hipFuncSetAttribute((const void*)render_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   hipLaunchKernelGGL(render_mfma_kernel, dim3(n), dim3(256), lds, s, params, psf, gidx, off, N, rscale,
-                     pscale_inv, prof, out);
+                     pscale_inv, prof, nu, out);
   return hipGetLastError();
 }
 

@@ -41,6 +41,7 @@ struct GalCtx {
   float* xch;      // the chain's partial-sum exchange area (2 x W x 12 floats)
   float norm;      // 1 / (N^2 sigma^2)
   float rscale;
+  float nu;        // Spergel index (Spergel profile only)
   float refx, refy;
   int t_stop;      // iteration at which this galaxy's chains stop in this launch
 };
@@ -106,7 +107,7 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * 
   const float F = hbcast<H>(e10, 0), s = hbcast<H>(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
   fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
-  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
+  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2, c.nu);
   const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf,
                                                                  sh, c.red, c.part, xbuf);
   const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
@@ -151,8 +152,8 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
   const float F = exp10f(t0), s = exp10f(t1);
   float2* Y = c.Yf;   // full x and y tables (ntab entries each)
   fill_xy_full(g, c.atab, c.X, Y, c.refx + th[4], c.refy + th[5]);
-  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2);
-  const float cg = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;
+  const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2, c.nu);
+  const float cg = sh.cg;
   // accumulate sum_c |dM/dp|^2 over every bin, frequency points combined per bin
   float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const bool even = (g.N & 1) == 0;
@@ -587,6 +588,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.xch = l.xch0 + cw * (2 * 12 * W);
     c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
     c.rscale = a.rscale;
+    c.nu = a.nu;
     c.refx = a.ref_xy[2 * (int64_t)gal];
     c.refy = a.ref_xy[2 * (int64_t)gal + 1];
     c.t_stop = a.t_stop_gal ? min(a.t_stop, a.t_stop_gal[gal]) : a.t_stop;
@@ -746,7 +748,7 @@ static bool launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) 
 }
 
 int hmc_split_waves(int N, int C, int P, int prof, int max_w) {
-  if (max_w <= 1 || prof != kProfExp || P != make_slot_plan(N).P) return 1;
+  if (max_w <= 1 || prof == kProfGauss || P != make_slot_plan(N).P) return 1;
   bool fixed = false;
   for (const int* p = hmc_fixed_plans(N); *p; ++p) fixed |= (*p == P);
   if (!fixed) return 1;
@@ -761,7 +763,7 @@ int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc) {
   (void)N; (void)C; (void)P; (void)prof; (void)wpc;
   return 1;
 #else
-  if (wpc != 1 || (C & 1) || C > 4 || prof != kProfExp) return 1;
+  if (wpc != 1 || (C & 1) || C > 4 || prof == kProfGauss) return 1;
   return paired_chains_plan(N, P) ? 2 : 1;
 #endif
 }
@@ -781,7 +783,7 @@ const int* hmc_fixed_plans(int N) {
 
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
-  if constexpr (!INIT && PROF == kProfExp)
+  if constexpr (!INIT && PROF != kProfGauss)
     if (a.C * a.wpc <= 4 && launch_fixed<PROF>(a, grid, lds, s)) return;
   switch (a.P) {
     case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
@@ -802,11 +804,13 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   if (a.wpc != 1 && (INIT || a.wpc != hmc_split_waves(a.N, a.C, a.P, a.prof, a.wpc)))
     return hipErrorInvalidValue;
   // two chains per wave exactly where launch_fixed_w launches them
-  const int H = (!INIT && a.prof == kProfExp && a.C * a.wpc <= 4)
+  const int H = (!INIT && a.prof != kProfGauss && a.C * a.wpc <= 4)
                     ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
   const size_t lds = hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
+  else if (a.prof == kProfSpergel)
+    launch_prof<kProfSpergel, INIT>(a, grid, lds, s);
   else
     launch_prof<kProfGauss, INIT>(a, grid, lds, s);
   return hipGetLastError();

@@ -35,7 +35,7 @@
 
 namespace bsi {
 
-enum { kProfExp = 0, kProfGauss = 1 };
+enum { kProfExp = 0, kProfGauss = 1, kProfSpergel = 2 };
 
 // Supported iterations per super-row (template instances of the bin loop).
 constexpr int kPlanP[] = {1, 2, 3, 4, 5, 6, 8};
@@ -140,14 +140,18 @@ __device__ __forceinline__ float rcp_nr(float x) {
 // Per-evaluation constants of the quadratic form q = ca kx^2 + cb ky^2 + cc kx ky
 // and of the profile exponent t = ta kx^2 + tb ky^2 + tc kx ky + t0 in which
 // the profile factor is evaluated: G = t^(-3/2) with t = 1 + r0^2 q for the
-// exponential, G = 2^t with t = -r^2 q log2(e) / 2 for the Gaussian.
+// exponential, G = t^(-(1+nu)) with the same t for the Spergel profile of
+// index nu, G = 2^t with t = -r^2 q log2(e) / 2 for the Gaussian.  cg is
+// (d ln G / dq) times a = 1 + r0^2 q (times 1 for the Gaussian), gw the
+// Spergel exponent -(2 + nu) of G / t.
 struct Shape {
   float ca, cb, cc, r2, inv1mE;
   float ta, tb, tc, t0;
+  float cg, gw;
 };
 
 template <int PROF>
-__device__ __forceinline__ Shape make_shape(float rpx, float e1, float e2) {
+__device__ __forceinline__ Shape make_shape(float rpx, float e1, float e2, float nu = 0.5f) {
   Shape s;
   const float E = e1 * e1 + e2 * e2;
   s.inv1mE = rcp_nr(1.0f - E);
@@ -155,16 +159,25 @@ __device__ __forceinline__ Shape make_shape(float rpx, float e1, float e2) {
   s.cb = (1.0f + E - 2.0f * e1) * s.inv1mE;
   s.cc = 4.0f * e2 * s.inv1mE;
   s.r2 = rpx * rpx;
-  const float f = (PROF == kProfExp) ? s.r2 : -0.72134752044448170368f * s.r2;   // -log2(e) / 2
+  const float f = (PROF != kProfGauss) ? s.r2 : -0.72134752044448170368f * s.r2;   // -log2(e) / 2
   s.ta = f * s.ca;
   s.tb = f * s.cb;
   s.tc = f * s.cc;
-  s.t0 = (PROF == kProfExp) ? 1.0f : 0.0f;
+  s.t0 = (PROF != kProfGauss) ? 1.0f : 0.0f;
+  s.cg = (PROF == kProfExp) ? -1.5f * s.r2 : (PROF == kProfGauss) ? -0.5f * s.r2 : -(1.0f + nu) * s.r2;
+  s.gw = -(2.0f + nu);
   return s;
 }
 
+// Spergel factors from a = 1 + r0^2 q >= 1: G / a = a^gw = 2^(gw log2 a)
+// and G = a (G / a).
+__device__ __forceinline__ void spergel_factor(float gw, float a, float& G, float& Gw) {
+  Gw = __builtin_amdgcn_exp2f(gw * __builtin_amdgcn_logf(a));
+  G = Gw * a;
+}
+
 // Profile factor G(q) and the factor ia multiplying z in the shape sums
-// (1/(1 + r0^2 q) for the exponential, 1 for the Gaussian).
+// (1/(1 + r0^2 q) for the exponential and Spergel profiles, 1 for the Gaussian).
 template <int PROF>
 __device__ __forceinline__ void profile_factor(const Shape& sh, float q, float& G, float& ia) {
   if (PROF == kProfExp) {
@@ -172,6 +185,11 @@ __device__ __forceinline__ void profile_factor(const Shape& sh, float q, float& 
     const float rs = __builtin_amdgcn_rsqf(a);
     ia = rs * rs;
     G = ia * rs;
+  } else if (PROF == kProfSpergel) {
+    const float a = fmaf(sh.r2, q, 1.0f);
+    float Gw;
+    spergel_factor(sh.gw, a, G, Gw);
+    ia = rcp_nr(a);
   } else {
     G = __expf(-0.5f * sh.r2 * q);
     ia = 1.0f;
@@ -303,6 +321,9 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
     Gm = rm2 * rm;
     Gwp = Gp * rp2;
     Gwm = Gm * rm2;
+  } else if (PROF == kProfSpergel) {
+    spergel_factor(sh.gw, tp, Gp, Gwp);
+    spergel_factor(sh.gw, tm, Gm, Gwm);
   } else {
     Gp = __builtin_amdgcn_exp2f(tp);
     Gm = __builtin_amdgcn_exp2f(tm);
@@ -551,7 +572,7 @@ __device__ __forceinline__ KResult kspace_finish(const KSums& S, const Shape& sh
                                                  float s_arcsec, float e1, float e2, float norm) {
   KResult r;
   r.loglik = -(double)norm * S.chi2;            // -1/2 norm (2 S.chi2)
-  const float c = (PROF == kProfExp) ? -1.5f * sh.r2 : -0.5f * sh.r2;   // d ln G / dq * a
+  const float c = sh.cg;                          // d ln G / dq * a
   const float n2 = 2.0f * norm;                  // the halved sums doubled
   r.dF = n2 * S.sF * rcp_nr(F);
   r.ds = n2 * (2.0f * c * rcp_nr(s_arcsec)) * S.sq;

@@ -2,6 +2,8 @@
 // galaxy.  The DFT of the data (or, for the pixel method, of the pixel
 // residual) at the half-plane bins is staged in LDS and contracted with the
 // analytic spectrum by kspace_sums (the same routine the sampler uses).
+#include <type_traits>
+
 #include "bsi_kernels.h"
 #include "kspace.h"
 
@@ -11,7 +13,7 @@ template <int PROF, bool RESID, int P>
 __global__ void __launch_bounds__(64) loglik_kernel(
     const float2* __restrict__ dh_all, const int64_t* __restrict__ bin_off, const int32_t* __restrict__ gidx,
     const float* __restrict__ params, const float* __restrict__ psf, const float* __restrict__ sigma,
-    int N, float rscale, float pscale_inv, const double* __restrict__ chi2_pix,
+    int N, float rscale, float pscale_inv, float nu, const double* __restrict__ chi2_pix,
     double* __restrict__ loglik, float* __restrict__ grad, uint32_t* __restrict__ status) {
   extern __shared__ float4 smem4[];
   const Geom g = make_geom(N);
@@ -44,7 +46,7 @@ __global__ void __launch_bounds__(64) loglik_kernel(
   uint32_t st = 0;
   if (!(E < 1.0f) || !(s > 0.0f) || !(F > 0.0f)) st |= 1u;
   fill_tables(g, sp, atab, X, Ym, Yf, F, dx, dy);
-  const Shape sh = make_shape<PROF>(s * rscale, e1, e2);
+  const Shape sh = make_shape<PROF>(s * rscale, e1, e2, nu);
   const LaneCols<P> lc = lane_cols<P>(cols);
   const KSums S = kspace_sums<PROF, P, RESID>(g, sp, lc, dh, X, Ym, Yf, sh, red);
   KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, norm);
@@ -75,12 +77,12 @@ template <int PROF, bool RESID>
 static void launch_loglik_p(int P, dim3 grid, size_t lds, hipStream_t s, const float2* dh,
                             const int64_t* bin_off, const int32_t* gidx, const float* params,
                             const float* psf, const float* sigma, int N, float rscale,
-                            float pscale_inv, const double* chi2_pix, double* loglik, float* grad,
-                            uint32_t* status) {
+                            float pscale_inv, float nu, const double* chi2_pix, double* loglik,
+                            float* grad, uint32_t* status) {
   auto go = [&](auto kern) {
     (void)hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(kern, grid, dim3(64), lds, s, dh, bin_off, gidx, params, psf, sigma, N,
-                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
+                       rscale, pscale_inv, nu, chi2_pix, loglik, grad, status);
   };
   switch (P) {
     case 1: go(loglik_kernel<PROF, RESID, 1>); break;
@@ -95,28 +97,28 @@ static void launch_loglik_p(int P, dim3 grid, size_t lds, hipStream_t s, const f
 
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
                          const float* params, const float* psf, const float* sigma, int N, int P,
-                         float rscale, float pscale_inv, int prof, int resid_mode,
+                         float rscale, float pscale_inv, int prof, float nu, int resid_mode,
                          const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
                          hipStream_t s) {
   if (n <= 0) return hipSuccess;
   if (!plan_valid(N, P)) return hipErrorInvalidValue;
   const size_t lds = loglik_lds_bytes(N, P);
   const dim3 grid(n);
-  if (prof == kProfExp) {
+  auto run = [&](auto prof_tag) {
+    constexpr int PR = decltype(prof_tag)::value;
     if (resid_mode)
-      launch_loglik_p<kProfExp, true>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
-                                      rscale, pscale_inv, chi2_pix, loglik, grad, status);
+      launch_loglik_p<PR, true>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N, rscale,
+                                pscale_inv, nu, chi2_pix, loglik, grad, status);
     else
-      launch_loglik_p<kProfExp, false>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
-                                       rscale, pscale_inv, chi2_pix, loglik, grad, status);
-  } else {
-    if (resid_mode)
-      launch_loglik_p<kProfGauss, true>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N,
-                                        rscale, pscale_inv, chi2_pix, loglik, grad, status);
-    else
-      launch_loglik_p<kProfGauss, false>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma,
-                                         N, rscale, pscale_inv, chi2_pix, loglik, grad, status);
-  }
+      launch_loglik_p<PR, false>(P, grid, lds, s, dh, bin_off, gidx, params, psf, sigma, N, rscale,
+                                 pscale_inv, nu, chi2_pix, loglik, grad, status);
+  };
+  if (prof == kProfExp)
+    run(std::integral_constant<int, kProfExp>());
+  else if (prof == kProfSpergel)
+    run(std::integral_constant<int, kProfSpergel>());
+  else
+    run(std::integral_constant<int, kProfGauss>());
   return hipGetLastError();
 }
 

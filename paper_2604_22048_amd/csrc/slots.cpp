@@ -166,9 +166,10 @@ HmcArgs base_args(const bsi_slots_s* sv) {
   a.state = sv->state;
   a.samples = sv->samples;
   a.trace = nullptr;
-  a.rscale = profile_rscale(sv->cfg.profile, sv->cfg.pixel_scale);
+  a.rscale = profile_rscale(sv->cfg.profile, sv->cfg.pixel_scale, sv->cfg.spergel_nu);
   a.pscale_inv = 1.0f / sv->cfg.pixel_scale;
   a.prof = sv->cfg.profile;
+  a.nu = sv->cfg.spergel_nu;
   a.C = sv->C;
   a.L = sv->L;
   a.W = c.n_warmup;
@@ -223,8 +224,13 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
       !(ip.sigma_e > 0))
     return fail(h, BSI_EINVAL, "invalid interim prior");
   if (!(cfg->pixel_scale > 0.0f)) return fail(h, BSI_EINVAL, "pixel_scale must be positive");
-  if (cfg->profile != BSI_PROFILE_EXPONENTIAL && cfg->profile != BSI_PROFILE_GAUSSIAN)
+  if (cfg->profile != BSI_PROFILE_EXPONENTIAL && cfg->profile != BSI_PROFILE_GAUSSIAN &&
+      cfg->profile != BSI_PROFILE_SPERGEL)
     return fail(h, BSI_EINVAL, "unknown profile %d", cfg->profile);
+  if (cfg->profile == BSI_PROFILE_SPERGEL &&
+      !(cfg->spergel_nu >= BSI_SPERGEL_NU_MIN && cfg->spergel_nu <= BSI_SPERGEL_NU_MAX))
+    return fail(h, BSI_EINVAL, "Spergel index %g outside [%g, %g]", (double)cfg->spergel_nu,
+                (double)BSI_SPERGEL_NU_MIN, (double)BSI_SPERGEL_NU_MAX);
   if (cfg->hbm_budget <= 0 || cfg->max_slots < 0) return fail(h, BSI_EINVAL, "invalid budget/max_slots");
   if (!(cfg->ess_target >= 0.0f) || !std::isfinite(cfg->ess_target))
     return fail(h, BSI_EINVAL, "ess_target must be finite and >= 0");

@@ -7,6 +7,8 @@
 // half-transform resident in LDS; twiddles come from a 2N-entry table of
 // exp(-i pi m / N) built in double precision, indexed by the exactly reduced
 // phase u (2 i - N + 1) mod 2N, since pixel centres sit at i - (N-1)/2.
+#include <cmath>
+
 #include "bsi_kernels.h"
 #include "kspace.h"
 
@@ -119,7 +121,7 @@ size_t dft_bins_lds_bytes(int N) {
 // Analytic spectrum at frequency point (u, v) for render, in float64.
 __device__ __forceinline__ double2 spectrum_point(int u, int v, int N, double F, double rpx,
                                                   double e1, double e2, double dx, double dy,
-                                                  double sp, int prof) {
+                                                  double sp, int prof, double nu) {
   const double ks = 2.0 * 3.14159265358979323846 / (double)N;
   const double kx = u * ks, ky = v * ks;
   const double E = e1 * e1 + e2 * e2;
@@ -129,6 +131,8 @@ __device__ __forceinline__ double2 spectrum_point(int u, int v, int N, double F,
   if (prof == kProfExp) {
     const double a = 1.0 + rpx * rpx * q;
     G = 1.0 / (a * sqrt(a));
+  } else if (prof == kProfSpergel) {
+    G = pow(1.0 + rpx * rpx * q, -(1.0 + nu));
   } else {
     G = exp(-0.5 * rpx * rpx * q);
   }
@@ -156,7 +160,7 @@ __device__ __forceinline__ void build_twiddles_f64(double2* tw, int N) {
 template <typename OutT>
 __global__ void __launch_bounds__(256) render_kernel(
     const float* __restrict__ params, const float* __restrict__ psf_fwhm, const int32_t* __restrict__ gidx,
-    const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof,
+    const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof, float nu,
     OutT* __restrict__ out) {
   extern __shared__ double2 smemd[];
   const int gal = gidx[blockIdx.x];
@@ -177,7 +181,7 @@ __global__ void __launch_bounds__(256) render_kernel(
       const int u = c - h;
       double w = (even && (u == h || u == -h)) ? 0.5 : 1.0;      // Nyquist point weight
       w *= (v == 0 || (even && v == h)) ? 1.0 : 2.0;             // Hermitian mirror in v
-      const double2 z = spectrum_point(u, v, N, F, rpx, e1, e2, dx, dy, sp, prof);
+      const double2 z = spectrum_point(u, v, N, F, rpx, e1, e2, dx, dy, sp, prof, (double)nu);
       T[c] = make_double2(w * z.x, w * z.y);
     }
     __syncthreads();
@@ -229,27 +233,27 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
 
 template <typename OutT>
 static hipError_t render_impl(const float* params, const float* psf, const int32_t* gidx, int n,
-                              const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                              const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                               OutT* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = render_lds_bytes(N);
   (void)hipFuncSetAttribute((const void*)render_kernel<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(render_kernel<OutT>, dim3(n), dim3(256), lds, s, params, psf, gidx, off, N,
-                     rscale, pscale_inv, prof, out);
+                     rscale, pscale_inv, prof, nu, out);
   return hipGetLastError();
 }
 
 hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
-                         const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                         const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                          float* out, hipStream_t s) {
-  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, out, s);
+  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, out, s);
 }
 
 hipError_t launch_render_f64(const float* params, const float* psf, const int32_t* gidx, int n,
-                             const int64_t* off, int N, float rscale, float pscale_inv, int prof,
+                             const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
                              double* out, hipStream_t s) {
-  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, out, s);
+  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, out, s);
 }
 
 double exponential_hlr_factor() {
@@ -259,6 +263,19 @@ double exponential_hlr_factor() {
     x -= f / (-x * exp(-x));
   }
   return x;
+}
+
+double spergel_hlr_factor(double nu) {
+  // x^(nu+1) K_(nu+1)(x) falls from 2^nu Gamma(nu+1) at 0 to 0; bisect for half of that
+  const double target = std::tgamma(nu + 1.0) * std::pow(2.0, nu - 1.0);
+  auto f = [&](double x) { return std::pow(x, nu + 1.0) * std::cyl_bessel_k(nu + 1.0, x) - target; };
+  double lo = 1e-6, hi = 1.0;
+  while (f(hi) > 0.0) hi *= 2.0;
+  for (int i = 0; i < 80; ++i) {
+    const double mid = 0.5 * (lo + hi);
+    (f(mid) > 0.0 ? lo : hi) = mid;
+  }
+  return 0.5 * (lo + hi);
 }
 
 }  // namespace bsi

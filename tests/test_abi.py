@@ -52,14 +52,14 @@ int main(void) {
   printf("bsi_slots_cfg %zu\n", sizeof(bsi_slots_cfg));
   printf("bsi_request %zu\n", sizeof(bsi_request));
   printf("bsi_slots_info %zu\n", sizeof(bsi_slots_info));
-  F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile)
+  F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile) F(bsi_batch, spergel_nu)
   F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
   F(bsi_hmc_cfg, trace) F(bsi_hmc_cfg, waves_per_chain)
   F(bsi_true_prior, mu_ln_f) F(bsi_true_prior, sigma_ln_f)
   F(bsi_shear_hmc_cfg, jitter) F(bsi_shear_hmc_cfg, inv_mass) F(bsi_shear_hmc_cfg, seed)
   F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)
   F(bsi_slots_cfg, hbm_budget) F(bsi_slots_cfg, hmc) F(bsi_slots_cfg, interim)
-  F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile) F(bsi_slots_cfg, pace)
+  F(bsi_slots_cfg, pixel_scale) F(bsi_slots_cfg, profile) F(bsi_slots_cfg, spergel_nu) F(bsi_slots_cfg, pace)
   F(bsi_slots_cfg, ess_target) F(bsi_slots_cfg, ess_every)
   F(bsi_request, stamp) F(bsi_request, psf_fwhm) F(bsi_request, ref_y) F(bsi_request, init)
   F(bsi_slots_info, budget) F(bsi_slots_info, arena_largest_free)
@@ -94,7 +94,7 @@ def test_no_device_and_null_handle_paths(native):
     lib = native.load()
     n = C.c_int32(-1)
     assert lib.bsi_device_count(C.byref(n)) == 0 and n.value >= 0
-    assert lib.bsi_version() == 1
+    assert lib.bsi_version() == 2
     if n.value == 0:
         h = C.c_void_p()
         assert lib.bsi_create(C.byref(h), 0) == -5
