@@ -20,6 +20,8 @@ diagnostics multi-chain ESS (Geyer initial monotone sequence), R-hat, and the
 shear       shear response (eq. shear-transform), its Jacobian
             (eq. true-prior-jacobian-shear), true priors, importance weights
             and the Monte-Carlo shear likelihood (eq. likelihood-shear).
+bias        multiplicative and additive shear bias by shape-noise cancellation
+            with bootstrap errors (Section 3.5, Table 2).
 
 Every function here is pinned by a ``-m "not gpu"`` test against something
 other than itself (closed forms, quadrature, brute force, invariants, known
