@@ -124,13 +124,14 @@ def lens(e1, e2, g):
     return ep.real, ep.imag
 
 
-def make_inputs(api, torch, n_gal, cfg, seed_offset=0, sizes=None, chains=None):
+def make_inputs(api, torch, n_gal, cfg, seed_offset=0, sizes=None, chains=None, g=None):
     """Seeded synthetic galaxies of workload cfg rendered on the device, with
-    pixel noise, reference centroids and chain starts (eq. initialize)."""
+    pixel noise, reference centroids and chain starts (eq. initialize); g
+    overrides the applied shear (same galaxies and noise)."""
     dev = torch.device("cuda:0")
     t = gen.draw_truth(cfg, n_gal=n_gal, seed=gen.data_seed(cfg.index) + seed_offset,
                        size_override=sizes)
-    e1p, e2p = lens(t.e1, t.e2, cfg.g_true)
+    e1p, e2p = lens(t.e1, t.e2, cfg.g_true if g is None else g)
     params = np.stack([t.flux, t.hlr, e1p, e2p, t.dx, t.dy], axis=1).astype(np.float32)
     b = api.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32, device=dev),
                   sigma=torch.tensor(t.sigma, dtype=torch.float32, device=dev), pixel_scale=PS)
@@ -437,6 +438,63 @@ def spergel_leg(api, torch, stream, n_gal, nu, log=None):
             "status_nonzero": int((status != 0).sum())}
 
 
+def bias_leg(api, torch, stream, n_gal, n_boot, log):
+    """Multiplicative and additive shear bias by shape-noise cancellation with
+    bootstrap errors (Section 3.5; Table 2's all-fixed setting): the uniform
+    workload's galaxies and noise sheared by +g and by -g, every property
+    sampled (4 chains, 20 leapfrog steps, 300 warmup + 1000 draws), the shear
+    phase with the population parameters at their true values on a 33 x 33 grid
+    of g around each dataset's shear (K = 1000: every 4th draw), n_boot
+    resamples of the galaxies."""
+    import math
+    cfg = gen.CONFIGS["uniform"]
+    dev = torch.device("cuda:0")
+    C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
+    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
+                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
+                         use_graph=True, seed=gen.chain_seed(cfg.index))
+    g_abs = cfg.g_true[0]
+    mu_f, sd_f = gen.flux_lognormal(*cfg.snr, cfg.sigma)
+    tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True, flux_term=True, mu_ln_f=mu_f,
+                          sigma_ln_f=sd_f)
+    alpha = (math.log(0.6), 0.3, 0.2)
+    n1, half = 33, 0.03
+    g1 = np.linspace(g_abs - half, g_abs + half, n1)
+    g2 = np.linspace(-half, half, n1)
+    G1, G2 = np.meshgrid(g1, g2)
+    gpp = np.stack([G1.ravel(), G2.ravel()], axis=1)
+    gpm = gpp * [-1.0, 1.0]
+    K = 1000
+    ells, t_hmc, t_ell, acc = [], [], [], []
+    for sgn, gp in ((1.0, gpp), (-1.0, gpm)):
+        t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg, g=(sgn * g_abs, 0.0))
+        (smp, st, status), th = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
+        thn = smp[:, :, 3::4, :].reshape(n_gal, K, 6)
+        pts = np.array([[a, bb, *alpha] for a, bb in gp])
+        ell, tl = timed(torch, lambda: api.shear_galaxy_loglik(thn[..., 2], thn[..., 3], thn[..., 1],
+                                                               thn[..., 0], pts, tp), stream)
+        ells.append(ell)
+        t_hmc.append(th)
+        t_ell.append(tl)
+        acc.append(float(st[..., 0].mean()))
+        log(f"[bench] bias: dataset g1 = {sgn * g_abs:+.2f}: hmc {th:.3f} s, shear table {tl:.3f} s")
+    counts = torch.tensor(gen.bootstrap_counts(n_boot, n_gal, gen.chain_seed(cfg.index) + 5), device=dev)
+    gps = torch.tensor(np.stack([gpp, gpm]), device=dev)
+    api.shear_bias(ells[0], ells[1], gps, g_abs, counts)          # warm
+    res, t_boot = timed(torch, lambda: api.shear_bias(ells[0], ells[1], gps, g_abs, counts), stream)
+    st = res["stats"].cpu().numpy()
+    P = n1 * n1
+    boot_flop = 2.0 * (n_boot + 1) * 2 * P * n_gal
+    total = sum(t_hmc) + sum(t_ell) + t_boot
+    return {"n_gal": n_gal, "n_boot": n_boot, "grid": f"{n1}x{n1}", "K": K,
+            "m": float(st[0]), "c": float(st[1]), "m_err_3sigma": 3 * float(st[2]),
+            "c_err_3sigma": 3 * float(st[3]),
+            "t_hmc_s": [round(x, 4) for x in t_hmc], "t_shear_table_s": [round(x, 4) for x in t_ell],
+            "t_bootstrap_s": round(t_boot, 5), "bootstrap_tflops": round(boot_flop / t_boot / 1e12, 3),
+            "accept_rate": [round(a, 4) for a in acc], "t_total_s": round(total, 3),
+            "galaxy_pairs_per_s": round(n_gal / total, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,7 +505,7 @@ def main():
     ap.add_argument("--plain-gal", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
-    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "spergel"],
+    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "spergel", "bias"],
                     default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
@@ -455,6 +513,7 @@ def main():
                     "serving legs (profiling)")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving leg (profiling)")
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
+    ap.add_argument("--n-boot", type=int, default=500, help="--workload bias: bootstrap resamples")
     ap.add_argument("--spergel-nu", type=float, default=-0.6,
                     help="--workload spergel: the fixed Spergel index of the fit")
     ap.add_argument("--plan", type=int, default=0,
@@ -497,7 +556,16 @@ def main():
                    "config": {"workload": "10,000 galaxies x 1,000 interim samples, 4 points"}, **res}
             print(json.dumps(out), flush=True)
             return
-        if args.workload == "spergel":
+        if args.workload == "bias":
+            G = args.n_gal or gen.CONFIGS["uniform"].n_gal
+            res = bias_leg(api, torch, stream, G, args.n_boot, log)
+            out = {"metric": "m/c bias study by shape-noise cancellation (galaxy pairs/s, end to end)",
+                   "value": res["galaxy_pairs_per_s"], "unit": "galaxy pairs/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
+                   "config": {"workload": f"{G} 53-pixel galaxies sheared by +-(0.02, 0), same noise; "
+                                          "4 chains x (300 + 1000), K = 1000, 33 x 33 grid, "
+                                          f"{args.n_boot} bootstrap resamples"}, **res}
+        elif args.workload == "spergel":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
             res = spergel_leg(api, torch, stream, G, args.spergel_nu, log)
             out = {"metric": "galaxies/sec at 300 ESS (Spergel-profile fit of exponential galaxies)",

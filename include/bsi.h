@@ -256,6 +256,56 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
                         const double* pts, int32_t pts_on_device, double* logpost, double* grad,
                         bsi_stream stream);
 
+/*
+ * bsi_shear_galaxy_loglik -- the per-galaxy terms of bsi_shear_posterior's
+ * sum (eq. likelihood-shear) at n_pts points:
+ *   ell[p][n] = ln sum_k w_nk(point p) - ln K,
+ * -inf where no sample of galaxy n lies in the true prior's support at point
+ * p.  The points are not checked against the hyper-prior support (every
+ * point is evaluated).
+ *   e1p .. log10f, tp, interim, pts, pts_on_device   as for bsi_shear_posterior.
+ *   ell   [device] double[n_pts][n_gal].
+ */
+int bsi_shear_galaxy_loglik(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                            const float* e2p, const float* log10s, const float* log10f,
+                            const bsi_true_prior* tp, const bsi_interim* interim, int32_t n_pts,
+                            const double* pts, int32_t pts_on_device, double* ell,
+                            bsi_stream stream);
+
+/*
+ * bsi_shear_bias -- multiplicative and additive shear bias by shape-noise
+ * cancellation with bootstrap errors (Section 3.5; Table 2).  Two datasets
+ * hold the same galaxies and noise, sheared by +g and -g with g = (g_abs, 0).
+ * With the population parameters fixed, the shear posterior of a galaxy
+ * resample that draws galaxy n c_n times is ln P(g_p) = sum_n c_n ell_n(g_p)
+ * (+ const), and the estimator is its mean over the dataset's grid points:
+ *   g_hat = sum_p g_p e^(ln P(g_p) - max) / sum_p e^(ln P(g_p) - max).
+ * Row r = 0 uses every galaxy once; rows r = 1..n_boot use counts[r - 1].
+ *   m_r = (g_hat+_1 - g_hat-_1) / (2 g_abs) - 1,   c_r = (g_hat+_2 + g_hat-_2) / 2.
+ * The sums over galaxies are one float64 product on the matrix cores (the
+ * order of the additions differs from a sequential sum).
+ *   ell_plus, ell_minus  [device] double[n_pts][n_gal]: bsi_shear_galaxy_loglik
+ *                        of each dataset at its grid points.
+ *   gpts    [device] double[2][n_pts][2]: the grid points' (g1, g2), those of
+ *           the +g dataset, then those of the -g dataset.
+ *   counts  [device] int32[n_boot][n_gal]: times galaxy n is drawn in each
+ *           resample (rows of the classic bootstrap sum to n_gal; not
+ *           checked); may be NULL when n_boot = 0.
+ *   gmean   [device] double[2][n_boot + 1][2]: g_hat of the +g rows, then of
+ *           the -g rows, or NULL.
+ *   mc      [device] double[n_boot + 1][2]: (m_r, c_r), or NULL.
+ *   stats   [device] double[4] = {m_0, c_0, sd(m_1..m_B), sd(c_1..c_B)}
+ *           (population standard deviations; 0 when n_boot = 0).
+ * ell = -inf is carried as -1e300, so a galaxy not drawn adds exactly 0; a
+ * row whose every grid point is -inf has no meaningful mean.
+ * Limits: 1 <= n_pts <= 8192, n_boot >= 0, g_abs > 0.  Uses handle
+ * workspace (n_boot + 1) x 2 n_pts doubles per galaxy split.
+ */
+int bsi_shear_bias(bsi_handle h, int32_t n_gal, int32_t n_pts, const double* ell_plus,
+                   const double* ell_minus, const double* gpts, double g_abs, int32_t n_boot,
+                   const int32_t* counts, double* gmean, double* mc, double* stats,
+                   bsi_stream stream);
+
 /* Shear-level sampler settings (the per-galaxy sampler's scheme on the five
  * population parameters). */
 typedef struct {

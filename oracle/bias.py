@@ -91,13 +91,14 @@ def mc_from_means(gplus, gminus, g_abs):
     return m, c
 
 
-def mc_bootstrap(ell_plus, ell_minus, gpts, counts, g_abs):
-    """m, c from all galaxies and their bootstrap standard deviations."""
+def mc_bootstrap(ell_plus, ell_minus, gpts_plus, gpts_minus, counts, g_abs):
+    """m, c from all galaxies and their bootstrap standard deviations; each
+    dataset's table and posterior mean are on its own grid."""
     G = ell_plus.shape[1]
     ones = np.ones((1, G))
-    m0, c0 = mc_from_means(grid_mean(resampled_logpost(ell_plus, ones), gpts)[0],
-                           grid_mean(resampled_logpost(ell_minus, ones), gpts)[0], g_abs)
-    mb, cb = mc_from_means(grid_mean(resampled_logpost(ell_plus, counts), gpts),
-                           grid_mean(resampled_logpost(ell_minus, counts), gpts), g_abs)
+    m0, c0 = mc_from_means(grid_mean(resampled_logpost(ell_plus, ones), gpts_plus)[0],
+                           grid_mean(resampled_logpost(ell_minus, ones), gpts_minus)[0], g_abs)
+    mb, cb = mc_from_means(grid_mean(resampled_logpost(ell_plus, counts), gpts_plus),
+                           grid_mean(resampled_logpost(ell_minus, counts), gpts_minus), g_abs)
     return {"m": float(m0), "c": float(c0), "m_err": float(np.std(mb)), "c_err": float(np.std(cb)),
             "m_boot": mb, "c_boot": cb}

@@ -103,6 +103,13 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
                                       C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bsi_shear_galaxy_loglik": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                          C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
+                                          C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_int32,
+                                          C.c_void_p, C.c_void_p]),
+    "bsi_shear_bias": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                 C.c_void_p]),
     "bsi_shear_hmc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.c_void_p, C.POINTER(TruePrior), C.POINTER(Interim),
                                 C.POINTER(ShearHmcCfg), C.c_void_p, C.c_void_p, C.c_void_p,

@@ -243,6 +243,50 @@ def shear_posterior(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, int
     return (lp, gr) if want_grad else lp
 
 
+def shear_galaxy_loglik(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, interim=None,
+                        lib: Library | None = None):
+    """Per-galaxy log-marginals ell[p, n] at points (g1, g2, mu_ln_s, sigma_ln_s,
+    sigma_e) (bsi_shear_galaxy_loglik); samples are [G, K] tensors."""
+    dev = e1p.device
+    lib = lib or get(dev.index or 0)
+    G, K = e1p.shape
+    e1p, e2p = e1p.contiguous().float(), e2p.contiguous().float()
+    log10s = log10s.contiguous().float() if log10s is not None else None
+    log10f = log10f.contiguous().float() if log10f is not None else None
+    pts_t = torch.as_tensor(pts, dtype=torch.float64).reshape(-1, 5).to(dev).contiguous()
+    P = pts_t.shape[0]
+    ell = torch.empty(P, G, dtype=torch.float64, device=dev)
+    tp = true_prior.c()
+    ip = _interim(interim)
+    lib.check(lib.lib.bsi_shear_galaxy_loglik(lib.h, G, K, _ptr(e1p), _ptr(e2p), _ptr(log10s),
+                                              _ptr(log10f), C.byref(tp), C.byref(ip), P, _ptr(pts_t), 1,
+                                              _ptr(ell), _stream(dev)), "bsi_shear_galaxy_loglik")
+    return ell
+
+
+def shear_bias(ell_plus, ell_minus, gpts, g_abs: float, counts=None, lib: Library | None = None):
+    """m and c by shape-noise cancellation with bootstrap errors (bsi_shear_bias).
+    ell_*: [P, G] float64 device tensors; gpts: [2, P, 2] (the +g dataset's grid, then the
+    -g dataset's) or [P, 2] (one grid for both); counts: [B, G] int32 or None.
+    Returns dict(stats=[m, c, sd(m), sd(c)], mc=[B+1, 2] (m_r, c_r), gmean=[2, B+1, 2]) as tensors."""
+    dev = ell_plus.device
+    lib = lib or get(dev.index or 0)
+    P, G = ell_plus.shape
+    ep = ell_plus.contiguous().double()
+    em = ell_minus.contiguous().double()
+    gp = torch.as_tensor(gpts, dtype=torch.float64).to(dev).reshape(-1, P, 2)
+    gp = (gp.expand(2, P, 2) if gp.shape[0] == 1 else gp).contiguous()
+    B = 0 if counts is None else int(counts.shape[0])
+    cnt = None if counts is None else torch.as_tensor(counts, dtype=torch.int32).to(dev).contiguous()
+    gmean = torch.empty(2, B + 1, 2, dtype=torch.float64, device=dev)
+    mc = torch.empty(B + 1, 2, dtype=torch.float64, device=dev)
+    stats = torch.empty(4, dtype=torch.float64, device=dev)
+    lib.check(lib.lib.bsi_shear_bias(lib.h, G, P, _ptr(ep), _ptr(em), _ptr(gp), float(g_abs), B,
+                                     _ptr(cnt), _ptr(gmean), _ptr(mc), _ptr(stats), _stream(dev)),
+              "bsi_shear_bias")
+    return {"stats": stats, "mc": mc, "gmean": gmean}
+
+
 @dataclass
 class ShearHmcConfig:
     n_chains: int = 4

@@ -15,7 +15,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbsi.so")
-SOURCES = ["transform.hip", "dft_mfma.hip", "likelihood.hip", "hmc.hip", "shear.hip", "diag.hip", "slots.hip", "api.cpp",
+SOURCES = ["transform.hip", "dft_mfma.hip", "likelihood.hip", "hmc.hip", "shear.hip", "bootstrap.hip",
+           "diag.hip", "slots.hip", "api.cpp",
            "slots.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -496,6 +496,7 @@ ShearArgs shear_args(int32_t n_gal, int32_t K, const float* e1p, const float* e2
   a.pts = dpts;
   a.partial = partial;
   a.want_grad = want_grad;
+  a.per_gal = nullptr;
   return a;
 }
 
@@ -534,6 +535,67 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
   if (e != hipSuccess) return hip_fail(h, e, "shear launch");
   e = launch_shear_reduce(a.partial, n_blocks, n_pts, dpts, logpost, grad, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
+  return BSI_OK;
+}
+
+int bsi_shear_galaxy_loglik(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                            const float* e2p, const float* log10s, const float* log10f,
+                            const bsi_true_prior* tp, const bsi_interim* ip, int32_t n_pts,
+                            const double* pts, int32_t pts_on_device, double* ell,
+                            bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_shear_inputs(h, n_gal, K, e1p, e2p, log10s, log10f, tp, ip);
+  if (rc) return rc;
+  if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
+  if (n_pts == 0 || n_gal == 0) return BSI_OK;
+  if (!pts || !ell) return fail(h, BSI_EINVAL, "pts/ell is NULL");
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const double* dpts = pts;
+  if (!pts_on_device) {
+    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
+    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "points upload");
+    dpts = static_cast<const double*>(h->pts.p);
+  }
+  const int n_blocks = shear_blocks(n_gal, n_pts);
+  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
+  ShearArgs a = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, n_pts, dpts,
+                           static_cast<double*>(h->partial.p), 0);
+  a.per_gal = ell;
+  hipError_t e = launch_shear(a, n_blocks, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear launch");
+  return BSI_OK;
+}
+
+int bsi_shear_bias(bsi_handle h, int32_t n_gal, int32_t n_pts, const double* ell_plus,
+                   const double* ell_minus, const double* gpts, double g_abs, int32_t n_boot,
+                   const int32_t* counts, double* gmean, double* mc, double* stats,
+                   bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (n_gal < 1) return fail(h, BSI_EINVAL, "n_gal must be >= 1");
+  if (n_pts < 1 || n_pts > 8192) return fail(h, BSI_EINVAL, "n_pts must be 1..8192");
+  if (n_boot < 0) return fail(h, BSI_EINVAL, "n_boot < 0");
+  if (!(g_abs > 0.0) || !std::isfinite(g_abs)) return fail(h, BSI_EINVAL, "g_abs must be positive");
+  if (!ell_plus || !ell_minus || !gpts || !stats) return fail(h, BSI_EINVAL, "ell/gpts/stats is NULL");
+  if (n_boot > 0 && !counts) return fail(h, BSI_EINVAL, "counts is NULL");
+  hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const BiasPlan b = bias_plan(n_gal, n_pts, n_boot);
+  int rc;
+  if ((rc = ensure(h, h->bias_part, b.partial_doubles * sizeof(double)))) return rc;
+  double* mcp = mc;
+  if (!mcp) {
+    if ((rc = ensure(h, h->bias_mc, (size_t)b.R * 2 * sizeof(double)))) return rc;
+    mcp = static_cast<double*>(h->bias_mc.p);
+  }
+  hipError_t e = launch_bias(b, counts, ell_plus, ell_minus, n_gal, n_pts, gpts, g_abs,
+                             static_cast<double*>(h->bias_part.p), gmean, mcp, stats, s);
+  if (e != hipSuccess) return hip_fail(h, e, "bias launch");
   return BSI_OK;
 }
 

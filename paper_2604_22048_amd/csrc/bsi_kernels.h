@@ -152,8 +152,22 @@ struct ShearArgs {
   const double* pts;               // device [n_pts][5]
   double* partial;                 // device [n_blocks][n_pts][6]
   int want_grad;
+  double* per_gal;                 // device [n_pts][n_gal] per-galaxy log-marginals, or NULL
 };
 hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s);
+
+// ---- bootstrap.hip ----
+// Shape of the m/c bootstrap product: R = n_boot + 1 rows, the galaxies
+// split into n_split ranges of k_per_split for the partial products.
+struct BiasPlan {
+  int R, n_split, k_per_split;
+  size_t partial_doubles;   // n_split x R x 2 P
+};
+BiasPlan bias_plan(int G, int P, int n_boot);
+size_t bias_mean_lds_bytes(int P);
+hipError_t launch_bias(const BiasPlan& b, const int32_t* counts, const double* ep, const double* em,
+                       int G, int P, const double* gpts, double g_abs, double* partial, double* gmean,
+                       double* mc, double* stats, hipStream_t s);
 hipError_t launch_shear_reduce(const double* partial, int n_blocks, int n_pts, const double* pts,
                                double* logpost, double* grad, hipStream_t s);
 

@@ -248,6 +248,7 @@ __global__ void __launch_bounds__(256, BSI_SHEAR_WAVES_PER_EU) shear_kernel(Shea
         }
       }
       if (lane == pj) {
+        if (a.per_gal) a.per_gal[(int64_t)(chunk0 + pj) * a.n_gal + gal] = ell;
         acc[0] += ell;
 #pragma unroll
         for (int j = 0; j < 5; ++j) acc[1 + j] += g[j];

@@ -1,0 +1,162 @@
+"""GPU parity of the m/c bias path (Section 3.5: shape-noise cancellation
+with bootstrap errors) against the FP64 oracle.
+
+Tolerances:
+  ell_n          |ell_gpu - ell_oracle| <= 1e-6 (|ell| + 1) (float32 weights,
+                 float64 log-sum-exp: the shear posterior's per-galaxy bar)
+  bootstrap      float64 throughout, only the order of the sums differs:
+                 g_hat within 1e-10, m within 1e-8 (the difference of the two
+                 datasets' means divided by 2 |g| = 0.04), c within 1e-10
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import bias, shear            # noqa: E402
+from workloads import gen                 # noqa: E402
+
+G_ABS = 0.02
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsi(device):
+    from paper_2604_22048_amd import api
+    return api
+
+
+def _grid(n1, n2, span1, span2, alpha):
+    g1 = np.linspace(span1[0], span1[1], n1)
+    g2 = np.linspace(span2[0], span2[1], n2)
+    G1, G2 = np.meshgrid(g1, g2)
+    gpts = np.stack([G1.ravel(), G2.ravel()], axis=1)
+    pts = np.array([[a, b, *alpha] for a, b in gpts])
+    return gpts, pts
+
+
+def _pairs(rng, G, K, sig=0.2, emax=0.7, noise=0.05):
+    """Interim-like samples of G galaxies sheared by +g and -g: the same
+    intrinsic ellipticities and the same per-sample scatter."""
+    e = rng.normal(0, sig, 4 * G) + 1j * rng.normal(0, sig, 4 * G)
+    e = e[np.abs(e) < emax][:G]
+    scat = rng.normal(0, noise, (G, K)) + 1j * rng.normal(0, noise, (G, K))
+    ls = rng.normal(math.log10(0.6), 0.05, (G, K))
+    out = []
+    for g in (complex(G_ABS, 0.0), complex(-G_ABS, 0.0)):
+        ep = shear.shear_forward(e, g)[:, None] + scat
+        r = np.abs(ep)
+        ep = np.where(r < 0.95, ep, ep * 0.9 / r)
+        out.append([a.astype(np.float32) for a in (ep.real, ep.imag, ls, ls)])
+    return out
+
+
+def test_galaxy_loglik_parity(bsi):
+    import torch
+    _log("per-galaxy shear log-marginals")
+    rng = np.random.default_rng(50)
+    G, K = 37, 130                      # ragged in waves, galaxies and samples
+    Sp, _ = _pairs(rng, G, K)
+    alpha = (math.log(0.6), 0.3, 0.2)
+    gpts, pts = _grid(9, 8, (-0.3, 0.3), (-0.25, 0.35), alpha)   # 72 points: two chunks
+    pts = np.vstack([pts, [[0.9, 0.0, *alpha]]])                  # a point some galaxies cannot reach
+    tpo = shear.TruePrior(e_kind=1, e_max=0.7)
+    tpg = bsi.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True, flux_term=False)
+    St = [torch.tensor(a).cuda() for a in Sp]
+    ell = bsi.shear_galaxy_loglik(St[0], St[1], St[2], None, pts, tpg).cpu().numpy()
+    ref = bias.galaxy_loglikes([a.astype(np.float64) for a in Sp], pts, tpo, shear.Interim())
+    fin = np.isfinite(ref)
+    assert np.array_equal(fin, np.isfinite(ell))
+    assert np.all(ell[~fin] == -np.inf)
+    assert (~fin).any() and fin.any()
+    assert np.all(np.abs(ell[fin] - ref[fin]) <= 1e-6 * (np.abs(ref[fin]) + 1.0))
+
+
+def _gaussian_tables(rng, G, gpts, s=0.3):
+    a = rng.normal(0.02, 0.2, G) + 1j * rng.normal(0.0, 0.2, G)
+    out = []
+    for sgn in (1.0, -1.0):
+        c = sgn * a.real + 1j * a.imag
+        out.append(-((gpts[:, :1] - c.real[None, :]) ** 2 + (gpts[:, 1:] - c.imag[None, :]) ** 2)
+                   / (2 * s * s))
+    return out
+
+
+@pytest.mark.parametrize("G,B,n1", [(300, 100, 9), (1, 3, 5), (129, 0, 11)])
+def test_bias_parity_on_oracle_tables(bsi, G, B, n1):
+    """Oracle tables with -inf entries, ragged in every tile dimension and in the
+    galaxy splits; the degenerate single galaxy and the no-resample case."""
+    import torch
+    _log(f"bias bootstrap parity G={G} B={B} grid={n1}x{n1}")
+    rng = np.random.default_rng(60 + G)
+    gpts, _ = _grid(n1, n1, (-0.06, 0.06), (-0.06, 0.06), (0, 0, 0))
+    ep, em = _gaussian_tables(rng, G, gpts)
+    # a few galaxies with no support at the grid's first column of points
+    bad = rng.choice(G, size=min(3, G), replace=False)
+    edge = np.where(gpts[:, 0] == gpts[:, 0].min())[0]
+    for n in bad:
+        ep[edge, n] = -np.inf
+        em[edge, n] = -np.inf
+    counts = gen.bootstrap_counts(B, G, 61) if B else None
+    res = bsi.shear_bias(torch.tensor(ep).cuda(), torch.tensor(em).cuda(), torch.tensor(gpts).cuda(),
+                         G_ABS, None if counts is None else torch.tensor(counts).cuda())
+    mc = res["mc"].cpu().numpy()
+    gm = res["gmean"].cpu().numpy()
+    st = res["stats"].cpu().numpy()
+    cnt = np.zeros((0, G)) if counts is None else counts.astype(np.float64)
+    allc = np.vstack([np.ones((1, G)), cnt])
+    gp = bias.grid_mean(bias.resampled_logpost(ep, allc), gpts)
+    gq = bias.grid_mean(bias.resampled_logpost(em, allc), gpts)
+    m, c = bias.mc_from_means(gp, gq, G_ABS)
+    assert np.max(np.abs(gm[0] - gp)) < 1e-10 and np.max(np.abs(gm[1] - gq)) < 1e-10
+    assert np.max(np.abs(mc[:, 0] - m)) < 1e-8 and np.max(np.abs(mc[:, 1] - c)) < 1e-10
+    ref = bias.mc_bootstrap(ep, em, gpts, gpts, cnt, G_ABS) if B else None
+    assert abs(st[0] - m[0]) < 1e-8 and abs(st[1] - c[0]) < 1e-10
+    if B:
+        assert abs(st[2] - ref["m_err"]) < 1e-8 and abs(st[3] - ref["c_err"]) < 1e-10
+    else:
+        assert st[2] == 0.0 and st[3] == 0.0
+
+
+def test_bias_full_size_sampled_rows(bsi):
+    """10,000 galaxies x 33 x 33 grid x 500 resamples (the bias study's launch):
+    sampled rows against the oracle; every row against the closed form (Gaussian
+    per-galaxy log-likelihoods: each resample's mean is its count-weighted mean
+    of the centres)."""
+    import torch
+    _log("bias bootstrap full size")
+    G, B, n1 = 10000, 500, 33
+    rng = np.random.default_rng(70)
+    gpp, _ = _grid(n1, n1, (-0.02, 0.06), (-0.04, 0.04), (0, 0, 0))
+    gpm = gpp * [-1.0, 1.0]                     # the -g dataset's grid: g1 mirrored
+    a = rng.normal(0.02, 0.2, G) + 1j * rng.normal(0.0, 0.2, G)
+    s = 0.5
+    ep = -((gpp[:, :1] - a.real[None, :]) ** 2 + (gpp[:, 1:] - a.imag[None, :]) ** 2) / (2 * s * s)
+    em = -((gpm[:, :1] + a.real[None, :]) ** 2 + (gpm[:, 1:] - a.imag[None, :]) ** 2) / (2 * s * s)
+    counts = gen.bootstrap_counts(B, G, 71)
+    res = bsi.shear_bias(torch.tensor(ep).cuda(), torch.tensor(em).cuda(),
+                         torch.tensor(np.stack([gpp, gpm])).cuda(), G_ABS, torch.tensor(counts).cuda())
+    gm = res["gmean"].cpu().numpy()
+    mc = res["mc"].cpu().numpy()
+    allc = np.vstack([np.ones((1, G)), counts.astype(np.float64)])
+    for r in (0, 1, 250, 500):
+        gp = bias.grid_mean(bias.resampled_logpost(ep, allc[r:r + 1]), gpp)[0]
+        gq = bias.grid_mean(bias.resampled_logpost(em, allc[r:r + 1]), gpm)[0]
+        assert np.max(np.abs(gm[0, r] - gp)) < 1e-10 and np.max(np.abs(gm[1, r] - gq)) < 1e-10, r
+        m, c = bias.mc_from_means(gp, gq, G_ABS)
+        assert abs(mc[r, 0] - m) < 1e-8 and abs(mc[r, 1] - c) < 1e-10, r
+    # closed form: the posterior is Gaussian with sd s / sqrt(G) = 0.005, so the
+    # grid (spacing 0.0025, reaching 6 sd past a mean within 0.006 of its centre)
+    # resolves it; the mean of resample r is sum_n c_rn a_n / G (g1 negated for
+    # the -g dataset), and m_r follows in closed form
+    want = allc @ np.stack([a.real, a.imag], axis=1) / G
+    assert np.max(np.abs(gm[0] - want)) < 1e-9
+    assert np.max(np.abs(gm[1] - want * [-1.0, 1.0])) < 1e-9
+    assert np.max(np.abs(mc[:, 0] - (want[:, 0] / G_ABS - 1.0))) < 1e-7

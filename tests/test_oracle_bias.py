@@ -67,7 +67,7 @@ def test_bootstrap_equals_resampled_datasets_brute_force():
     ell_m = bias.galaxy_loglikes(Sm, pts, tp, ip)
     rng = np.random.default_rng(4)
     idx = rng.integers(0, n, (5, n))
-    res = bias.mc_bootstrap(ell_p, ell_m, gpts, bias.resample_counts(idx, n), g1)
+    res = bias.mc_bootstrap(ell_p, ell_m, gpts, gpts, bias.resample_counts(idx, n), g1)
     for b in range(idx.shape[0]):
         means = []
         for S in (Sp, Sm):

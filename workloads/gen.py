@@ -193,3 +193,20 @@ def draw_requests(n_req: int, rate: float, seed: int):
     """Poisson arrival times (seconds) of n_req requests."""
     rng = np.random.default_rng(seed)
     return np.cumsum(rng.exponential(1.0 / rate, n_req))
+
+
+def bootstrap_indices(n_boot: int, n_gal: int, seed: int):
+    """Galaxy indices of n_boot bootstrap resamples, each n_gal draws with
+    replacement: int64 [n_boot, n_gal]."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, n_gal, (n_boot, n_gal))
+
+
+def bootstrap_counts(n_boot: int, n_gal: int, seed: int):
+    """Times each galaxy is drawn in each resample of bootstrap_indices:
+    int32 [n_boot, n_gal]."""
+    idx = bootstrap_indices(n_boot, n_gal, seed)
+    out = np.zeros((n_boot, n_gal), np.int32)
+    for b in range(n_boot):
+        out[b] = np.bincount(idx[b], minlength=n_gal)
+    return out
