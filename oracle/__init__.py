@@ -10,7 +10,9 @@ be checked against the paper by eye.
 Modules
 -------
 render      k-space stamp definition, pixel log-likelihood (eq. likelihood-pixels)
-            and its gradient by forward-mode differentiation of the stamp.
+            and its gradient by forward-mode differentiation of the stamp;
+            Appendix C's correlated-noise and multi-exposure likelihood with
+            the covariance formed explicitly.
 prior       interim prior of eq. interim-prior in sampling coordinates.
 philox      Philox4x32-10 counter-based generator, uniforms, Box-Muller normals.
 hmc         potential energy, leapfrog, Metropolis test, dual averaging,

@@ -50,6 +50,28 @@ class Galaxy:
     profile: object = render.PROFILE_EXP   # PROFILE_EXP, PROFILE_GAUSS or a render.Spergel
 
 
+@dataclass
+class Exposures:
+    """One galaxy seen in several exposures (Appendix C): stamps of one side N,
+    each with its PSF, noise sigma and (optionally) stationary noise power."""
+    datas: list               # (N, N) stamps
+    N: int
+    pixel_scale: float
+    psf_fwhm: list
+    sigma: list
+    noise_ps: list | None = None      # (N, N) DFT-mode noise powers in FFT order, or None (white)
+    ref_xy: tuple = (0.0, 0.0)
+    profile: object = render.PROFILE_EXP
+
+
+def _loglik_grad(gal, prm):
+    if isinstance(gal, Exposures):
+        return render.loglik_grad_exposures(gal.datas, prm, gal.N, gal.pixel_scale, gal.psf_fwhm,
+                                            gal.sigma, gal.noise_ps, gal.profile)
+    return render.loglik_grad(gal.data, prm, gal.N, gal.pixel_scale, gal.psf_fwhm, gal.sigma,
+                              gal.profile)
+
+
 def clamp_theta(theta, ip=prior.PAPER_INTERIM):
     """Position used to evaluate the likelihood when theta is outside the support."""
     t = np.array(theta, dtype=np.float64)
@@ -73,8 +95,7 @@ def potential(gal: Galaxy, theta, ip=prior.PAPER_INTERIM):
     inside = prior.in_support(theta, ip)
     tc = clamp_theta(theta, ip)
     prm = theta_to_params(tc, gal.ref_xy)
-    ll, g_p = render.loglik_grad(gal.data, prm, gal.N, gal.pixel_scale, gal.psf_fwhm,
-                                 gal.sigma, gal.profile)
+    ll, g_p = _loglik_grad(gal, prm)
     g_theta = g_p.copy()
     g_theta[0] *= prm[0] * LN10
     g_theta[1] *= prm[1] * LN10
@@ -247,10 +268,14 @@ def fisher_inv_mass(gal: Galaxy, theta, ip=prior.PAPER_INTERIM):
     synthesised from the spectrum derivative (forward mode)."""
     tc = clamp_theta(theta, ip)
     prm = theta_to_params(tc, gal.ref_xy)
-    _, dT = render.spectrum(prm, gal.N, gal.pixel_scale, gal.psf_fwhm, gal.profile, derivs=True)
     jac = np.array([prm[0] * LN10, prm[1] * LN10, 1.0, 1.0, 1.0, 1.0])
-    fi = np.array([np.sum(render.synthesize(dT[j], gal.N) ** 2) for j in range(6)])
-    fi = fi * jac * jac / (gal.sigma * gal.sigma)
+    if isinstance(gal, Exposures):
+        fi = render.fisher_diag_exposures(prm, gal.N, gal.pixel_scale, gal.psf_fwhm, gal.sigma,
+                                          gal.noise_ps, gal.profile) * jac * jac
+    else:
+        _, dT = render.spectrum(prm, gal.N, gal.pixel_scale, gal.psf_fwhm, gal.profile, derivs=True)
+        fi = np.array([np.sum(render.synthesize(dT[j], gal.N) ** 2) for j in range(6)])
+        fi = fi * jac * jac / (gal.sigma * gal.sigma)
     e1, e2 = tc[2], tc[3]
     E = e1 * e1 + e2 * e2
     se, sd = ip["sigma_e"], ip["sigma_d"]

@@ -257,3 +257,64 @@ def loglik_grad_batch(data, params, N, pixel_scale, psf_fwhm, sigma, profile=PRO
     for n in range(G):
         ll[n], gr[n] = loglik_grad(data[n], params[n], N, pixel_scale, psf[n], sig[n], profile)
     return ll, gr
+
+
+# ---- Appendix C: correlated noise and several exposures ----------------------
+#
+# Stationary noise on the stamp (periodic, as the stamp's own DFT grid assumes)
+# has a circulant covariance Sigma[x, x'] = sigma^2 c(x - x' mod N); its
+# eigenvalues are sigma^2 lambda_k with lambda_k = sum_x c(x) exp(-i k.x), the
+# noise power of DFT mode k.  ``noise_ps`` holds lambda on the N x N DFT grid
+# in FFT order (row v, column u, indices 0..N-1, numpy.fft layout); all ones
+# is white noise.  The likelihood of eq. covar-pixel-likelihood is evaluated
+# here by forming Sigma explicitly and solving with it.
+
+def covariance_matrix(noise_ps, sigma):
+    """Sigma (N^2 x N^2, pixels row-major) of stationary noise with the DFT-mode
+    powers noise_ps (N x N, FFT order) times sigma^2."""
+    ps = np.asarray(noise_ps, dtype=np.float64)
+    N = ps.shape[0]
+    c = np.real(np.fft.ifft2(ps))                     # c(dy, dx), lags mod N
+    iy, ix = np.divmod(np.arange(N * N), N)
+    dy = (iy[:, None] - iy[None, :]) % N
+    dx = (ix[:, None] - ix[None, :]) % N
+    return sigma * sigma * c[dy, dx]
+
+
+def loglik_grad_cov(data, params, N, pixel_scale, psf_fwhm, sigma, noise_ps, profile=PROFILE_EXP):
+    """eq. covar-pixel-likelihood (C = 0) and its gradient by forward mode:
+    d log L / dp = (dm/dp)^T Sigma^-1 (d - m)."""
+    T, dT = spectrum(params, N, pixel_scale, psf_fwhm, profile, derivs=True)
+    r = (np.asarray(data, dtype=np.float64) - synthesize(T, N)).ravel()
+    S = covariance_matrix(noise_ps, sigma)
+    y = np.linalg.solve(S, r)
+    ll = -0.5 * float(r @ y)
+    g = np.array([synthesize(dT[j], N).ravel() @ y for j in range(6)])
+    return ll, g
+
+
+def loglik_grad_exposures(datas, params, N, pixel_scale, psfs, sigmas, noise_pss=None,
+                          profile=PROFILE_EXP):
+    """Several independent exposures of one galaxy (Appendix C): the same
+    parameters, each exposure its own PSF, noise level and noise power; log L
+    and its gradient are sums over the exposures."""
+    ll, g = 0.0, np.zeros(6)
+    for j in range(len(datas)):
+        ps = np.ones((N, N)) if noise_pss is None else noise_pss[j]
+        lj, gj = loglik_grad_cov(datas[j], params, N, pixel_scale, psfs[j], sigmas[j], ps, profile)
+        ll += lj
+        g += gj
+    return ll, g
+
+
+def fisher_diag_exposures(params, N, pixel_scale, psfs, sigmas, noise_pss=None, profile=PROFILE_EXP):
+    """Diagonal of sum_j (dm_j/dp)^T Sigma_j^-1 (dm_j/dp) (physical parameters)."""
+    f = np.zeros(6)
+    for j in range(len(psfs)):
+        ps = np.ones((N, N)) if noise_pss is None else noise_pss[j]
+        _, dT = spectrum(params, N, pixel_scale, psfs[j], profile, derivs=True)
+        S = covariance_matrix(ps, sigmas[j])
+        for i in range(6):
+            dm = synthesize(dT[i], N).ravel()
+            f[i] += dm @ np.linalg.solve(S, dm)
+    return f
