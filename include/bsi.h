@@ -117,7 +117,25 @@ typedef struct {
   int32_t profile;           /* BSI_PROFILE_*                                           */
   float spergel_nu;          /* Spergel index for BSI_PROFILE_SPERGEL, in
                                 [BSI_SPERGEL_NU_MIN, BSI_SPERGEL_NU_MAX]; else ignored   */
+  int32_t n_exp;             /* exposures per galaxy (Appendix C), 0..BSI_MAX_EXPOSURES;
+                                0 and 1: one.  With E > 1 exposures, stamp i E + j is
+                                exposure j of galaxy i: n, off, psf_fwhm and sigma hold
+                                n_gal E entries (per stamp) and the exposures of a galaxy
+                                share N; params, ref_xy, init, outputs stay per galaxy.
+                                log L and its gradient are sums over the exposures        */
+  const float* noise_ps;     /* [device] stationary correlated noise (Appendix C), or NULL
+                                for white noise: per stamp, float[N][N] at element off[s]
+                                (the stamps' packing), lambda(v, u) for the DFT mode
+                                (u, v) in FFT order (index (v mod N) N + (u mod N)), the
+                                noise covariance being sigma^2 times the circulant matrix
+                                with these eigenvalues (lambda = sum_x c(x) e^{-i k.x} of
+                                the covariance function c, c(0) = 1 for unit variance);
+                                every lambda > 0 and lambda(-k) = lambda(k).  All ones is
+                                white noise                                               */
 } bsi_batch;
+
+/* Largest n_exp of a batch. */
+#define BSI_MAX_EXPOSURES 16
 
 /*
  * bsi_render_stamps -- noiseless model stamps (Section 3.2: exponential
@@ -130,7 +148,8 @@ typedef struct {
  *   T = F G(q) exp(-sigma_psf^2 |k|^2 / 2) sinc(u/N) sinc(v/N) exp(-i k.d),
  * with G the Fourier transform of the sheared, unit-flux profile.
  *   params [device] float[n_gal][6] physical parameters.
- *   out    [device] packed stamps, element off[i] .. off[i] + N_i^2 - 1.
+ *   out    [device] packed stamps, element off[s] .. off[s] + N_s^2 - 1 for
+ *          every stamp s (with n_exp > 1 each exposure with its own PSF).
  */
 int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params, float* out,
                       bsi_stream stream);
@@ -146,6 +165,10 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
  *   status  [device] uint32[n_gal] or NULL (bit OUT_OF_SUPPORT when
  *           |e| >= 1 or s <= 0 or F <= 0; NONFINITE when log L is not finite).
  *   method  BSI_LIK_KSPACE or BSI_LIK_PIXEL (same value up to rounding).
+ * With n_exp > 1 or noise_ps (Appendix C, eq. covar-pixel-likelihood):
+ *   log L = -1/2 sum_j (d_j - m_j)^T Sigma_j^-1 (d_j - m_j),
+ * evaluated on the DFT grid, where Sigma_j^-1 is diagonal with entries
+ * 1 / (sigma_j^2 lambda_j(k)); BSI_LIK_KSPACE only (BSI_EUNSUPPORTED else).
  */
 int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, const float* params,
                     double* loglik, float* grad, uint32_t* status, int32_t method,
@@ -213,6 +236,10 @@ typedef struct {
  * Random numbers: Philox4x32-10 keyed by seed, counter (uid, t, tag, block)
  * with t the iteration index; so the output of a chain does not depend on
  * which other galaxies share the call.
+ * With n_exp > 1 or noise_ps the potential uses the likelihood of
+ * bsi_loglik_grad's Appendix C form (and the Fisher metric its weighted
+ * curvature); those batches run on the general kernels with one wave per
+ * chain (waves_per_chain ignored) and need n_chains <= 4.
  */
 int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, const float* ref_xy,
                    const float* inv_mass, const float* init, const bsi_interim* interim,

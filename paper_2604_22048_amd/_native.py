@@ -19,6 +19,7 @@ PROFILE_GAUSSIAN = 1
 PROFILE_SPERGEL = 2
 SPERGEL_NU_MIN = -0.85
 SPERGEL_NU_MAX = 4.0
+MAX_EXPOSURES = 16
 LIK_KSPACE = 0
 LIK_PIXEL = 1
 METRIC_GIVEN = 0
@@ -35,7 +36,8 @@ E_TRUNC_GAUSS = 1
 class Batch(C.Structure):
     _fields_ = [("n_gal", C.c_int32), ("n", C.POINTER(C.c_int32)), ("off", C.POINTER(C.c_int64)),
                 ("psf_fwhm", C.c_void_p), ("sigma", C.c_void_p), ("pixel_scale", C.c_float),
-                ("profile", C.c_int32), ("spergel_nu", C.c_float)]
+                ("profile", C.c_int32), ("spergel_nu", C.c_float), ("n_exp", C.c_int32),
+                ("noise_ps", C.c_void_p)]
 
 
 class Interim(C.Structure):

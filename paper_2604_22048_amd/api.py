@@ -76,6 +76,8 @@ class Batch:
     profile: int = N.PROFILE_EXPONENTIAL
     off: np.ndarray = field(default=None)   # int64 [G]; default: packed in order
     spergel_nu: float = 0.5       # Spergel index (profile PROFILE_SPERGEL only)
+    n_exp: int = 1                # exposures per galaxy; n, psf_fwhm, sigma, off are per stamp
+    noise_ps: torch.Tensor = None # float32 packed like the stamps: DFT-mode noise powers, or None
 
     def __post_init__(self):
         self.n = np.ascontiguousarray(self.n, dtype=np.int32)
@@ -85,10 +87,12 @@ class Batch:
         self.off = np.ascontiguousarray(self.off, dtype=np.int64)
         self.psf_fwhm = self.psf_fwhm.contiguous().float()
         self.sigma = self.sigma.contiguous().float()
+        if self.noise_ps is not None:
+            self.noise_ps = self.noise_ps.contiguous().float()
 
     @property
     def n_gal(self):
-        return int(self.n.shape[0])
+        return int(self.n.shape[0]) // max(1, int(self.n_exp))
 
     @property
     def n_pixels(self):
@@ -104,6 +108,8 @@ class Batch:
         b.pixel_scale = float(self.pixel_scale)
         b.profile = int(self.profile)
         b.spergel_nu = float(self.spergel_nu)
+        b.n_exp = int(self.n_exp)
+        b.noise_ps = None if self.noise_ps is None else self.noise_ps.data_ptr()
         return b
 
 

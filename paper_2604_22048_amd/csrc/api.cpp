@@ -24,20 +24,28 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// A batch holds n_gal galaxies of E exposures each: stamp i E + j is exposure
+// j of galaxy i (E = 1: one stamp per galaxy, stamp = galaxy).
 struct ClassRange {
   int N;
   int P;       // slot plan
-  int begin;   // position in the sorted galaxy list
-  int count;
+  int begin;   // position in the sorted stamp list
+  int count;   // stamps
+  int gbegin;  // position in the sorted galaxy list
+  int gcount;  // galaxies
 };
 
 struct Plan {
-  std::vector<int32_t> gidx;      // galaxies grouped by stamp side
-  std::vector<int64_t> bin_off;   // per galaxy, offset into the bin buffer (complex units)
+  int E = 1;                      // exposures per galaxy
+  std::vector<int32_t> gidx;      // stamps grouped by stamp side (a galaxy's exposures in order)
+  std::vector<int32_t> ggidx;     // galaxies grouped by stamp side
+  std::vector<int64_t> bin_off;   // per stamp, offset into the bin buffer (complex units)
   std::vector<ClassRange> classes;
   int64_t total_bins = 0;
   int64_t max_pixel = 0;          // one past the largest pixel index
 };
+
+inline int exposures(const bsi_batch* b) { return b->n_exp > 1 ? b->n_exp : 1; }
 
 int check_batch(bsi_handle h, const bsi_batch* b) {
   if (!b) return fail(h, BSI_EINVAL, "batch is NULL");
@@ -54,10 +62,16 @@ int check_batch(bsi_handle h, const bsi_batch* b) {
       !(b->spergel_nu >= BSI_SPERGEL_NU_MIN && b->spergel_nu <= BSI_SPERGEL_NU_MAX))
     return fail(h, BSI_EINVAL, "Spergel index %g outside [%g, %g]", (double)b->spergel_nu,
                 (double)BSI_SPERGEL_NU_MIN, (double)BSI_SPERGEL_NU_MAX);
-  for (int i = 0; i < b->n_gal; ++i) {
+  if (b->n_exp < 0 || b->n_exp > BSI_MAX_EXPOSURES)
+    return fail(h, BSI_EINVAL, "n_exp %d outside [0, %d]", b->n_exp, BSI_MAX_EXPOSURES);
+  const int E = exposures(b);
+  for (int64_t i = 0; i < (int64_t)b->n_gal * E; ++i) {
     if (b->n[i] < 8 || b->n[i] > kMaxN)
-      return fail(h, BSI_EUNSUPPORTED, "stamp side %d of galaxy %d outside [8, %d]", b->n[i], i, kMaxN);
-    if (b->off[i] < 0) return fail(h, BSI_EINVAL, "negative offset for galaxy %d", i);
+      return fail(h, BSI_EUNSUPPORTED, "stamp side %d of stamp %lld outside [8, %d]", b->n[i],
+                  (long long)i, kMaxN);
+    if (b->n[i] != b->n[i - i % E])
+      return fail(h, BSI_EINVAL, "exposures of galaxy %lld differ in stamp side", (long long)(i / E));
+    if (b->off[i] < 0) return fail(h, BSI_EINVAL, "negative offset for stamp %lld", (long long)i);
   }
   return BSI_OK;
 }
@@ -70,18 +84,25 @@ int plan_of(bsi_handle h, int N) {
 
 Plan make_plan(bsi_handle h, const bsi_batch* b) {
   Plan p;
+  p.E = exposures(b);
+  const int E = p.E;
   std::map<int, std::vector<int32_t>> by;
-  for (int i = 0; i < b->n_gal; ++i) by[b->n[i]].push_back(i);
-  p.bin_off.assign(b->n_gal, 0);
+  for (int i = 0; i < b->n_gal; ++i) by[b->n[(int64_t)i * E]].push_back(i);
+  p.bin_off.assign((size_t)b->n_gal * E, 0);
   int64_t bins = 0;
   for (auto& kv : by) {
-    ClassRange c{kv.first, plan_of(h, kv.first), (int)p.gidx.size(), (int)kv.second.size()};
+    ClassRange c{kv.first, plan_of(h, kv.first), (int)p.gidx.size(), (int)kv.second.size() * E,
+                 (int)p.ggidx.size(), (int)kv.second.size()};
     const SlotPlan sp = make_slot_plan_p(c.N, c.P);
     for (int32_t i : kv.second) {
-      p.gidx.push_back(i);
-      p.bin_off[i] = bins;
-      bins += sp.nbins;
-      p.max_pixel = std::max<int64_t>(p.max_pixel, b->off[i] + (int64_t)kv.first * kv.first);
+      p.ggidx.push_back(i);
+      for (int j = 0; j < E; ++j) {
+        const int32_t st = i * E + j;
+        p.gidx.push_back(st);
+        p.bin_off[st] = bins;
+        bins += sp.nbins;
+        p.max_pixel = std::max<int64_t>(p.max_pixel, b->off[st] + (int64_t)kv.first * kv.first);
+      }
     }
     p.classes.push_back(c);
   }
@@ -92,23 +113,48 @@ Plan make_plan(bsi_handle h, const bsi_batch* b) {
 // Upload the plan's index arrays into the handle workspace.
 int upload_plan(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s) {
   int rc;
-  const size_t n = (size_t)b->n_gal;
+  const size_t n = (size_t)b->n_gal * p.E;     // stamps
   if ((rc = ensure(h, h->gidx, n * sizeof(int32_t)))) return rc;
   if ((rc = ensure(h, h->off, n * sizeof(int64_t)))) return rc;
   if ((rc = ensure(h, h->bin_off, n * sizeof(int64_t)))) return rc;
+  if (p.E > 1 && (rc = ensure(h, h->ggidx, (size_t)b->n_gal * sizeof(int32_t)))) return rc;
   hipError_t e;
   if ((e = hipMemcpyAsync(h->gidx.p, p.gidx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s)) ||
       (e = hipMemcpyAsync(h->off.p, b->off, n * sizeof(int64_t), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(h->bin_off.p, p.bin_off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s)))
+      (e = hipMemcpyAsync(h->bin_off.p, p.bin_off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s)) ||
+      (p.E > 1 && (e = hipMemcpyAsync(h->ggidx.p, p.ggidx.data(), (size_t)b->n_gal * sizeof(int32_t),
+                                       hipMemcpyHostToDevice, s))))
     return hip_fail(h, e, "plan upload");
   // pageable sources: make sure the copies are done before the vectors die
   if ((e = hipStreamSynchronize(s))) return hip_fail(h, e, "plan upload sync");
   return BSI_OK;
 }
 
+// The class's stamps, and its galaxies (the same list when E = 1).
 const int32_t* gidx_ptr(bsi_handle h, const ClassRange& c) {
   return static_cast<const int32_t*>(h->gidx.p) + c.begin;
 }
+
+const int32_t* ggidx_ptr(bsi_handle h, const Plan& p, const ClassRange& c) {
+  return static_cast<const int32_t*>(p.E > 1 ? h->ggidx.p : h->gidx.p) + c.gbegin;
+}
+
+// Per-bin noise weights (sqrt w beside the spectrum, which is whitened) for
+// batches with several exposures or correlated noise.
+int noise_weights(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s) {
+  int rc;
+  if ((rc = ensure(h, h->sqw, (size_t)p.total_bins * sizeof(float)))) return rc;
+  for (const ClassRange& c : p.classes) {
+    hipError_t e = launch_whiten(b->noise_ps, gidx_ptr(h, c), c.count,
+                                 static_cast<const int64_t*>(h->off.p),
+                                 static_cast<const int64_t*>(h->bin_off.p), c.N, c.P,
+                                 static_cast<float2*>(h->dh.p), static_cast<float*>(h->sqw.p), s);
+    if (e != hipSuccess) return hip_fail(h, e, "noise weights launch");
+  }
+  return BSI_OK;
+}
+
+inline bool weighted(const bsi_batch* b) { return b->n_exp > 1 || b->noise_ps != nullptr; }
 
 int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* data,
                   const double* model, double* chi2, hipStream_t s) {
@@ -229,9 +275,10 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
     const int64_t* off = static_cast<const int64_t*>(h->off.p);
     hipError_t e = transform_of(h, c.N) == BSI_TRANSFORM_MFMA
         ? launch_render_mfma(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
-                             1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s)
+                             1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s,
+                             p.E)
         : launch_render(params, batch->psf_fwhm, gi, c.count, off, c.N, rs,
-                        1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s);
+                        1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s, p.E);
     if (e != hipSuccess) return hip_fail(h, e, "render launch");
   }
   return BSI_OK;
@@ -248,6 +295,8 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
   if (!data || !params) return fail(h, BSI_EINVAL, "data/params is NULL");
   if (method != BSI_LIK_KSPACE && method != BSI_LIK_PIXEL)
     return fail(h, BSI_EINVAL, "unknown likelihood method %d", method);
+  if (method == BSI_LIK_PIXEL && weighted(batch))
+    return fail(h, BSI_EUNSUPPORTED, "several exposures / noise_ps need the k-space method");
   hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Plan p = make_plan(h, batch);
@@ -269,12 +318,15 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     chi2 = static_cast<double*>(h->chi2.p);
   }
   if ((rc = data_spectrum(h, batch, p, data, model, chi2, s))) return rc;
+  const bool mx = weighted(batch);
+  if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_loglik(static_cast<const float2*>(h->dh.p),
-                                 static_cast<const int64_t*>(h->bin_off.p), gidx_ptr(h, c), c.count,
-                                 params, batch->psf_fwhm, batch->sigma, c.N, c.P, rs,
+                                 static_cast<const int64_t*>(h->bin_off.p), ggidx_ptr(h, p, c),
+                                 c.gcount, params, batch->psf_fwhm, batch->sigma, c.N, c.P, rs,
                                  1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu,
-                                 method == BSI_LIK_PIXEL, chi2, loglik, grad, status, s);
+                                 method == BSI_LIK_PIXEL, chi2, loglik, grad, status, s, p.E,
+                                 mx ? static_cast<const float*>(h->sqw.p) : nullptr);
     if (e != hipSuccess) return hip_fail(h, e, "loglik launch");
   }
   return BSI_OK;
@@ -318,10 +370,16 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   if ((rc = upload_plan(h, batch, p, s))) return rc;
   if ((rc = data_spectrum(h, batch, p, data, nullptr, nullptr, s))) return rc;
   const int C = cfg->n_chains;
+  const bool mx = weighted(batch);
+  if (mx && C > 4) return fail(h, BSI_EUNSUPPORTED, "several exposures / noise_ps: n_chains <= 4");
+  if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
   if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
   for (const ClassRange& c : p.classes) {
-    if (hmc_lds_bytes(c.N, C, c.P, hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain)) > 160 * 1024)
-      return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains exceeds LDS", c.N, C);
+    const size_t lds = mx ? hmc_lds_bytes(c.N, C, c.P, 1, 1, p.E, true)
+                          : hmc_lds_bytes(c.N, C, c.P,
+                                          hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain));
+    if (lds > 160 * 1024)
+      return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains (and %d exposures) exceeds LDS", c.N, C, p.E);
   }
 
   HmcArgs a{};
@@ -360,26 +418,31 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   a.sigma_e = ip->sigma_e;
   a.t_stop = cfg->n_warmup + cfg->n_samples;
   a.wpc = 1;
+  a.mx = mx ? 1 : 0;
+  a.n_exp = p.E;
+  a.sqw = mx ? static_cast<const float*>(h->sqw.p) : nullptr;
+  a.noise_ps = batch->noise_ps;
+  a.off = static_cast<const int64_t*>(h->off.p);
 
   for (const ClassRange& c : p.classes) {
     HmcArgs ac = a;
     ac.N = c.N;
     ac.P = c.P;
-    ac.gidx = gidx_ptr(h, c);
-    ac.n_gal = c.count;
+    ac.gidx = ggidx_ptr(h, p, c);
+    ac.n_gal = c.gcount;
     ac.n_steps = 0;
-    hipError_t e = launch_hmc_init(ac, c.count, s);
+    hipError_t e = launch_hmc_init(ac, c.gcount, s);
     if (e != hipSuccess) return hip_fail(h, e, "hmc init launch");
   }
   const int T = a.t_stop;
   if (cfg->form == BSI_FORM_PLAIN) {
     // one galaxy, one leapfrog step per launch
     for (const ClassRange& c : p.classes) {
-      for (int i = 0; i < c.count; ++i) {
+      for (int i = 0; i < c.gcount; ++i) {
         HmcArgs ac = a;
         ac.N = c.N;
         ac.P = c.P;
-        ac.gidx = gidx_ptr(h, c) + i;
+        ac.gidx = ggidx_ptr(h, p, c) + i;
         ac.n_gal = 1;
         ac.n_steps = 1;
         for (int64_t k = 0; k < (int64_t)T * a.L; ++k) {
@@ -396,11 +459,11 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       HmcArgs ac = a;
       ac.N = c.N;
       ac.P = c.P;
-      ac.wpc = hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain);
-      ac.gidx = gidx_ptr(h, c);
-      ac.n_gal = c.count;
+      ac.wpc = mx ? 1 : hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain);
+      ac.gidx = ggidx_ptr(h, p, c);
+      ac.n_gal = c.gcount;
       ac.n_steps = ipl * a.L;
-      return launch_hmc_advance(ac, c.count, sc);
+      return launch_hmc_advance(ac, c.gcount, sc);
     };
     // direct launches: the sizes run concurrently on forked streams
     auto enqueue = [&](hipStream_t st) -> hipError_t {

@@ -32,7 +32,7 @@ size_t dft_bins_mfma_lds_bytes(int N);
 // The transforms as FP32 DFT products on the matrix cores (dft_mfma.hip)
 hipError_t launch_render_mfma(const float* params, const float* psf, const int32_t* gidx, int n,
                               const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                              float* out, hipStream_t s);
+                              float* out, hipStream_t s, int n_exp = 1);
 hipError_t launch_dft_bins_mfma(const float* data, const double* model, const int32_t* gidx, int n,
                                 const int64_t* off, const int64_t* bin_off, int N, int P, float2* out,
                                 double* chi2, hipStream_t s);
@@ -48,17 +48,21 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
                            double* chi2, const float* sigma, hipStream_t s);
 hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
                          const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                         float* out, hipStream_t s);
+                         float* out, hipStream_t s, int n_exp = 1);
 hipError_t launch_render_f64(const float* params, const float* psf, const int32_t* gidx, int n,
                              const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                             double* out, hipStream_t s);
+                             double* out, hipStream_t s, int n_exp = 1);
+
+// Whitened spectrum and per-bin sqrt-weights for stationary correlated noise.
+hipError_t launch_whiten(const float* noise_ps, const int32_t* gidx, int n, const int64_t* off,
+                         const int64_t* bin_off, int N, int P, float2* dh, float* sqw, hipStream_t s);
 
 // ---- likelihood.hip ----
 hipError_t launch_loglik(const float2* dh, const int64_t* bin_off, const int32_t* gidx, int n,
                          const float* params, const float* psf, const float* sigma, int N, int P,
                          float rscale, float pscale_inv, int prof, float nu, int resid_mode,
                          const double* chi2_pix, double* loglik, float* grad, uint32_t* status,
-                         hipStream_t s);
+                         hipStream_t s, int n_exp = 1, const float* sqw = nullptr);
 
 // ---- hmc.hip ----
 // Per-chain device state: 64 words, loaded and stored one word per lane.
@@ -117,10 +121,19 @@ struct HmcArgs {
   int n_steps;            // leapfrog steps to advance in this launch
   int t_stop;             // iteration at which a chain stops (W + S)
   const int32_t* t_stop_gal;  // [gal] per-galaxy stop (<= t_stop) or NULL (advance kernel only)
+  // several exposures / correlated noise (general kernels, mx = 1): galaxy
+  // gal's exposures are the stamps gal * n_exp + j (psf, sigma and bin_off
+  // are indexed by stamp), sqw holds sqrt w per bin beside dh, noise_ps the
+  // DFT-mode noise powers at off[stamp] (NULL: white; Fisher metric only)
+  int mx, n_exp;
+  const float* sqw;
+  const float* noise_ps;
+  const int64_t* off;
 };
 
-// LDS bytes of the trajectory kernel: C chains, W waves per chain, H chains per wave.
-size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1);
+// LDS bytes of the trajectory kernel: C chains, W waves per chain, H chains per
+// wave; E exposures and sqrt-weights (mx) for the general kernels' MX form.
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1, int E = 1, bool mx = false);
 // Waves per chain for stamp side N, C chains and plan P when up to max_w are
 // requested: a power of two <= max_w, <= the plan's super-rows, C W <= 4, and
 // 1 unless the profile is exponential or Spergel and P is N's default plan with a

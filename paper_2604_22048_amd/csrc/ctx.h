@@ -25,7 +25,8 @@ struct bsi_ctx {
   hipStream_t aux[kAuxStreams] = {};   // per-class branches of a forked launch
   hipEvent_t ev_fork = nullptr;
   hipEvent_t ev_join[kAuxStreams] = {};
-  DevBuf gidx, off, bin_off, dh, chi2, model, state, partial, pts, shear_state, bias_part, bias_mc;
+  DevBuf gidx, ggidx, off, bin_off, dh, sqw, chi2, model, state, partial, pts, shear_state, bias_part,
+      bias_mc;
   int plan_P[129] = {};   // slot plan per stamp side (0: the default, fewest slots)
   int transform[129] = {};   // render transform per stamp side (BSI_TRANSFORM_*, 0: default)
 };

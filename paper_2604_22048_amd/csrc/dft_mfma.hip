@@ -61,7 +61,7 @@ __host__ __device__ inline size_t render_mfma_lds(int N) {
 __global__ void __launch_bounds__(256) render_mfma_kernel(
     const float* __restrict__ params, const float* __restrict__ psf_fwhm, const int32_t* __restrict__ gidx,
     const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof, float nu,
-    float* __restrict__ out) {
+    int n_exp, float* __restrict__ out) {
   extern __shared__ float2 smr[];
   const RenderDims d = render_dims(N);
   const int h = d.h, ntab = d.ntab, nrow = d.nrow, ldT = d.ldT, nrow4 = d.nrow4, Np = d.Np;
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(256) render_mfma_kernel(
   float2* T = Y + nrow;             // spectrum [nrow][ldT]
   float2* B = T + nrow * ldT;       // half-transform [nrow4][Np]
   const int gal = gidx[blockIdx.x];
-  const float* p = params + 6 * (int64_t)gal;
+  const float* p = params + 6 * (int64_t)(gal / n_exp);     // stamps gal n_exp + j share a galaxy
   const double F = p[0], rpx = (double)p[1] * (double)rscale;
   const float e1 = p[2], e2 = p[3];
   const double dx = p[4], dy = p[5];
@@ -347,14 +347,14 @@ hipError_t launch_dft_bins_mfma(const float* data, const double* model, const in
 
 hipError_t launch_render_mfma(const float* params, const float* psf, const int32_t* gidx, int n,
                               const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                              float* out, hipStream_t s) {
+                              float* out, hipStream_t s, int n_exp) {
   if (n <= 0) return hipSuccess;
   const size_t lds = render_mfma_lds(N);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   (void)hipFuncSetAttribute((const void*)render_mfma_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
   hipLaunchKernelGGL(render_mfma_kernel, dim3(n), dim3(256), lds, s, params, psf, gidx, off, N, rscale,
-                     pscale_inv, prof, nu, out);
+                     pscale_inv, prof, nu, n_exp, out);
   return hipGetLastError();
 }
 

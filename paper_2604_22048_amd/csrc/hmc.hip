@@ -43,6 +43,16 @@ struct GalCtx {
   float rscale;
   float nu;        // Spergel index (Spergel profile only)
   float refx, refy;
+  // several exposures / correlated noise (MX kernels): exposure j's spectrum
+  // at dh + j dstride, its sqrt-weights at sqw + j wstride, its PSF-sinc
+  // table at atab + j astride, its noise sigma sig[j] and DFT-mode noise
+  // powers nps + off[s0 + j] (NULL: white)
+  int E, dstride, wstride, astride;
+  const float* sqw;
+  const float* sig;
+  const float* nps;
+  const int64_t* off;
+  int64_t s0;
   int t_stop;      // iteration at which this galaxy's chains stop in this launch
 };
 
@@ -87,7 +97,17 @@ __device__ __forceinline__ bool in_support(const float* th, const Prior& pr) {
 // Outside the support U = +inf and the gradient is evaluated at the nearest
 // admissible position (bounds clamped, |e|^2 <= 1 - 1e-6) so that a
 // trajectory can continue (it is rejected anyway).
-template <int PROF, int P, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1>
+__device__ __forceinline__ void add_result(KResult& r, const KResult& q) {
+  r.loglik += q.loglik;
+  r.dF += q.dF;
+  r.ds += q.ds;
+  r.de1 += q.de1;
+  r.de2 += q.de2;
+  r.ddx += q.ddx;
+  r.ddy += q.ddy;
+}
+
+template <int PROF, int P, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1, bool MX = false>
 __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * H>& lc, const Prior& pr,
                                             const float* th, float* gU, uint32_t& status,
                                             float* xbuf = nullptr) {
@@ -106,11 +126,26 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * 
   const float e10 = exp10_bounded(chain_lane<H>() == 0 ? t0 : t1);
   const float F = hbcast<H>(e10, 0), s = hbcast<H>(e10, 1);
   const float dx = c.refx + th[4], dy = c.refy + th[5];
-  fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
   const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2, c.nu);
-  const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf,
-                                                                 sh, c.red, c.part, xbuf);
-  const KResult r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
+  KResult r;
+  if constexpr (MX) {
+    // log L and its gradient summed over the exposures (Appendix C)
+    r = KResult{0.0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const float n2 = (float)c.g.N * (float)c.g.N;
+    for (int j = 0; j < c.E; ++j) {
+      fill_tables<H>(c.g, c.sp, c.atab + j * c.astride, c.X, c.Ym, c.Yf, F, dx, dy);
+      const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H, true>(
+          c.g, c.sp, lc, c.dh + j * c.dstride, c.X, c.Ym, c.Yf, sh, c.red, c.part, xbuf,
+          c.sqw + j * c.wstride);
+      const float sj = c.sig[j];
+      add_result(r, kspace_finish<PROF>(S, sh, F, s, e1, e2, 1.0f / (n2 * sj * sj)));
+    }
+  } else {
+    fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
+    const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym,
+                                                                   c.Yf, sh, c.red, c.part, xbuf);
+    r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
+  }
   const float isd2 = pr.isd2, ise2 = pr.ise2;
   const float cpri = -4.0f * sh.inv1mE - ise2;
   gU[0] = -r.dF * F * kLn10F;
@@ -135,7 +170,7 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * 
 
 // Diagonal Fisher information of the likelihood plus the prior curvature, at
 // theta, in sampling coordinates; returns the inverse as the metric.
-template <int PROF>
+template <int PROF, bool MX = false>
 __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* th, float* im) {
   const Geom& g = c.g;
   const int lane = lane_id();
@@ -151,9 +186,14 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
   }
   const float F = exp10f(t0), s = exp10f(t1);
   float2* Y = c.Yf;   // full x and y tables (ntab entries each)
-  fill_xy_full(g, c.atab, c.X, Y, c.refx + th[4], c.refy + th[5]);
   const Shape sh = make_shape<PROF>(s * c.rscale, e1, e2, c.nu);
   const float cg = sh.cg;
+  float fi[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  const int n_exp = MX ? c.E : 1;
+  for (int x = 0; x < n_exp; ++x) {
+  fill_xy_full(g, MX ? c.atab + x * c.astride : c.atab, c.X, Y, c.refx + th[4], c.refy + th[5]);
+  // noise weights 1 / lambda of the exposure's DFT modes (correlated noise), else 1
+  const float* nps = (MX && c.nps) ? c.nps + c.off[c.s0 + x] : nullptr;
   // accumulate sum_c |dM/dp|^2 over every bin, frequency points combined per bin
   float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const bool even = (g.N & 1) == 0;
@@ -165,6 +205,7 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
     } else {
       spec_bin_uv(g.N, b - g.nmain, ub, vb, cmul);
     }
+    const float wgt = nps ? 1.0f / nps[((vb + g.N) % g.N) * g.N + (ub + g.N) % g.N] : 1.0f;
     const int nu = (even && ub == -g.h) ? 2 : 1;
     const int nv = (even && vb == -g.h) ? 2 : 1;
     float dr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, di[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
@@ -197,11 +238,12 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
       }
     }
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc[j] += (float)cmul * (dr[j] * dr[j] + di[j] * di[j]);
+    for (int j = 0; j < 6; ++j) acc[j] += (float)cmul * wgt * (dr[j] * dr[j] + di[j] * di[j]);
   }
-  float fi[6];
+  const float nx = MX ? 1.0f / ((float)g.N * (float)g.N * c.sig[x] * c.sig[x]) : c.norm;
 #pragma unroll
-  for (int j = 0; j < 6; ++j) fi[j] = wave_total(acc[j]) * c.norm;
+  for (int j = 0; j < 6; ++j) fi[j] += wave_total(acc[j]) * nx;
+  }
   fi[0] *= F * F * kLn10F * kLn10F;
   fi[1] *= s * s * kLn10F * kLn10F;
   const float ise2 = 1.0f / (pr.se * pr.se), omE = 1.0f - E;
@@ -213,24 +255,44 @@ __device__ void fisher_inv_mass(const GalCtx& c, const Prior& pr, const float* t
   for (int j = 0; j < 6; ++j) im[j] = 1.0f / fi[j];
 }
 
-// Stage one galaxy's data spectrum and PSF-sinc table in LDS.
+// LDS strides of one exposure (MX kernels): spectrum (float2), sqrt-weights
+// and PSF-sinc table (floats), each a multiple of 16 bytes.
+__host__ __device__ inline int dh_stride(const SlotPlan& sp) { return (sp.nbins + 1) & ~1; }
+__host__ __device__ inline int sw_stride(const SlotPlan& sp) { return (dh_stride(sp) + 3) & ~3; }
+__host__ __device__ inline int atab_stride(const Geom& g) { return (g.ntab + 3) & ~3; }
+
+// Stage one galaxy's data spectrum and PSF-sinc table in LDS; MX: those of
+// each of its E exposures (stamps gal E + j), and the sqrt-weights.
+template <bool MX = false>
 __device__ void stage_galaxy(const HmcArgs& a, int gal, const Geom& g, const SlotPlan& sp,
-                             float2* dh, float* atab) {
-  const float4* src = reinterpret_cast<const float4*>(a.dh + a.bin_off[gal]);
-  float4* d4 = reinterpret_cast<float4*>(dh);
-  for (int b = threadIdx.x; b < sp.nbins / 2; b += blockDim.x) d4[b] = src[b];
-  if ((sp.nbins & 1) && threadIdx.x == 0) dh[sp.nbins - 1] = a.dh[a.bin_off[gal] + sp.nbins - 1];
-  const float spsf = a.psf[gal] * 0.42466090014400953f * a.pscale_inv;
-  for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
-    const int u = t - g.h;
-    const double k = 2.0 * 3.14159265358979323846 * u / g.N;
-    const double sn = (u == 0) ? 1.0 : sinpi((double)u / g.N) / (3.14159265358979323846 * u / g.N);
-    atab[t] = (float)(exp(-0.5 * (double)spsf * spsf * k * k) * sn);
+                             float2* dh, float* sqw, float* atab) {
+  const int E = MX ? a.n_exp : 1;
+  for (int x = 0; x < E; ++x) {
+    const int64_t st = MX ? (int64_t)gal * E + x : gal;
+    const int64_t bo = a.bin_off[st];
+    float2* dx = dh + x * dh_stride(sp);
+    const float4* src = reinterpret_cast<const float4*>(a.dh + bo);
+    float4* d4 = reinterpret_cast<float4*>(dx);
+    for (int b = threadIdx.x; b < sp.nbins / 2; b += blockDim.x) d4[b] = src[b];
+    if ((sp.nbins & 1) && threadIdx.x == 0) dx[sp.nbins - 1] = a.dh[bo + sp.nbins - 1];
+    if constexpr (MX) {
+      float* wx = sqw + x * sw_stride(sp);
+      for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) wx[b] = a.sqw[bo + b];
+    }
+    float* ax = atab + x * atab_stride(g);
+    const float spsf = a.psf[st] * 0.42466090014400953f * a.pscale_inv;
+    for (int t = threadIdx.x; t < g.ntab; t += blockDim.x) {
+      const int u = t - g.h;
+      const double k = 2.0 * 3.14159265358979323846 * u / g.N;
+      const double sn = (u == 0) ? 1.0 : sinpi((double)u / g.N) / (3.14159265358979323846 * u / g.N);
+      ax[t] = (float)(exp(-0.5 * (double)spsf * spsf * k * k) * sn);
+    }
   }
 }
 
 struct Lds {
   float2* dh;
+  float* sqw;         // sqrt-weights (MX kernels)
   float* atab;
   float4* cols;       // per-slot column table (shared)
   ChainState* cs;     // this wave's chain record
@@ -248,18 +310,20 @@ __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp)
   return 2 * sp.ymax + 2 * g.ntab + 2;
 }
 
-// LDS: [data spectrum | atab | column table | NW chain records | NWV reduction
-// scratches | NW table sets | exchange areas] for NW chain records (one per
-// wave, or per chain with two chains per wave) and NWV waves per block.
+// LDS: [data spectrum | sqrt-weights | atab | column table | NW chain
+// records | NWV reduction scratches | NW table sets | exchange areas] for NW
+// chain records (one per wave, or per chain with two chains per wave) and NWV
+// waves per block; E exposures of the first three (sqrt-weights only for MX).
 // idx: this lane's chain record and table set (its wave, or its chain with
 // two chains per wave); wave: its reduction scratch.
 __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx, int wave, int C,
-                                     int NWV) {
+                                     int NWV, int E = 1, bool mx = false) {
   extern __shared__ float4 smem4[];
   Lds l;
   l.dh = reinterpret_cast<float2*>(smem4);
-  l.atab = reinterpret_cast<float*>(l.dh + ((sp.nbins + 1) & ~1));
-  l.cols = reinterpret_cast<float4*>(l.atab + ((g.ntab + 3) & ~3));
+  l.sqw = reinterpret_cast<float*>(l.dh + E * dh_stride(sp));
+  l.atab = l.sqw + (mx ? E * sw_stride(sp) : 0);
+  l.cols = reinterpret_cast<float4*>(l.atab + E * atab_stride(g));
   ChainState* cs0 = reinterpret_cast<ChainState*>(l.cols + sp.P * 64);
   l.cs = cs0 + idx;
   float* red0 = reinterpret_cast<float*>(cs0 + C);
@@ -400,7 +464,7 @@ __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
 // H = 2: two chains per wave, each 32-lane half running its own chain (its
 // own record cs, tables and outputs); lane below is the lane within the half.
-template <int PROF, int P, int NFIX, int W, int H = 1>
+template <int PROF, int P, int NFIX, int W, int H = 1, bool MX = false>
 __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P * H>& lc,
                               const Prior& pr, ChainState* cs, float* samples_chain,
                               float* trace_chain) {
@@ -459,9 +523,9 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
     float* xbuf = W > 1 ? c.xch + (nev & 1) * (12 * W) : nullptr;
     ++nev;
     if (h.l + 1 == a.L)
-      h.Uth = potential<PROF, P, true, NFIX, W, H>(c, lc, pr, h.th, h.g, st, xbuf);
+      h.Uth = potential<PROF, P, true, NFIX, W, H, MX>(c, lc, pr, h.th, h.g, st, xbuf);
     else
-      h.Uth = potential<PROF, P, false, NFIX, W, H>(c, lc, pr, h.th, h.g, st, xbuf);
+      h.Uth = potential<PROF, P, false, NFIX, W, H, MX>(c, lc, pr, h.th, h.g, st, xbuf);
     if (h.t >= a.W) h.status |= st;     // warmup probes are not reported
     if (!in_support(h.th, pr)) h.ok = 0;
     h.l += 1;
@@ -552,9 +616,12 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
 // W > 1: each chain is evaluated by W waves (split evaluation; advance only).
 // H = 2: two chains per wave (lanes 0..31 and 32..63; advance only, C even).
-template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1>
+// MX: several exposures per galaxy and/or per-bin noise weights (general
+// kernels, one wave per chain).
+template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
+  static_assert(!MX || (NFIX == 0 && W == 1 && H == 1), "exposures and noise weights: general kernels");
   static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
@@ -563,18 +630,20 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
   // chain of the galaxy, part of the chain
   const int cw = (H == 1) ? wave / W : 2 * wave + ((threadIdx.x >> 5) & 1);
   const int part = (H == 1) ? wave % W : 0;
-  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H);
+  const int E = MX ? a.n_exp : 1;
+  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H, E, MX);
   build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
                  1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
   for (int gi = blockIdx.x; gi < a.n_gal; gi += gridDim.x) {
     const int gal = a.gidx[gi];
     __syncthreads();
-    stage_galaxy(a, gal, g, sp, l.dh, l.atab);
+    stage_galaxy<MX>(a, gal, g, sp, l.dh, l.sqw, l.atab);
     __syncthreads();
     if (cw >= a.C) continue;
     const LaneCols<P * H> lc = lane_cols<P * H, H>(l.cols);
-    const float sig = a.sigma[gal];
+    const int64_t s0 = (int64_t)gal * E;     // the galaxy's first stamp
+    const float sig = a.sigma[s0];
     GalCtx c;
     c.g = g;
     c.sp = sp;
@@ -592,6 +661,17 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.refx = a.ref_xy[2 * (int64_t)gal];
     c.refy = a.ref_xy[2 * (int64_t)gal + 1];
     c.t_stop = a.t_stop_gal ? min(a.t_stop, a.t_stop_gal[gal]) : a.t_stop;
+    if constexpr (MX) {
+      c.E = E;
+      c.dstride = dh_stride(sp);
+      c.wstride = sw_stride(sp);
+      c.astride = atab_stride(g);
+      c.sqw = l.sqw;
+      c.sig = a.sigma + s0;
+      c.nps = a.noise_ps;
+      c.off = a.off;
+      c.s0 = s0;
+    }
     const int64_t chain = (int64_t)gal * a.C + cw;
     ChainState* st = a.state + chain;
     if constexpr (INIT) {
@@ -600,13 +680,13 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
 #pragma unroll
       for (int j = 0; j < 6; ++j) r.theta[j] = ini[j];
       if (a.metric == 1) {
-        fisher_inv_mass<PROF>(c, pr, r.theta, r.im);
+        fisher_inv_mass<PROF, MX>(c, pr, r.theta, r.im);
       } else {
 #pragma unroll
         for (int j = 0; j < 6; ++j) r.im[j] = a.inv_mass ? a.inv_mass[(int64_t)gal * 6 + j] : 1.0f;
       }
       uint32_t stt = 0;
-      r.U = potential<PROF, P>(c, lc, pr, r.theta, r.grad, stt);
+      r.U = potential<PROF, P, true, 0, 1, 1, MX>(c, lc, pr, r.theta, r.grad, stt);
       r.status = stt;
 #pragma unroll
       for (int j = 0; j < 6; ++j) {
@@ -642,7 +722,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       // first writes the outputs
       float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P, NFIX, W, H>(a, c, lc, pr, l.cs, sc, tc);
+      advance_chain<PROF, P, NFIX, W, H, MX>(a, c, lc, pr, l.cs, sc, tc);
       if (part == 0) {
         uint32_t* dst = reinterpret_cast<uint32_t*>(st);
 #pragma unroll
@@ -673,19 +753,24 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 }  // namespace
 
-size_t hmc_lds_bytes(int N, int C, int P, int W, int H) {
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H, int E, bool mx) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int NW = C * W;
-  return sizeof(float2) * ((sp.nbins + 1) & ~1) + sizeof(float) * ((g.ntab + 3) & ~3) +
+  return sizeof(float2) * E * dh_stride(sp) + sizeof(float) * (mx ? E * sw_stride(sp) : 0) +
+         sizeof(float) * E * atab_stride(g) +
          sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * (NW / H) +
          sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW;
 }
 
-template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1, int H = 1>
+template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1, int H = 1, bool MX = false>
 static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   const dim3 blk(kWave * a.C * W / H);
-  if (a.C * W <= 4) {
+  if constexpr (MX) {
+    auto k = hmc_kernel<PROF, INIT, P, 256, 0, 1, 1, true>;   // C <= 4 (checked by the caller)
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
+  } else if (a.C * W <= 4) {
     auto k = hmc_kernel<PROF, INIT, P, 256, NFIX, W, H>;
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
@@ -783,6 +868,18 @@ const int* hmc_fixed_plans(int N) {
 
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (a.mx) {
+    switch (a.P) {
+      case 1: launch_p<PROF, INIT, 1, 0, 1, 1, true>(a, grid, lds, s); break;
+      case 2: launch_p<PROF, INIT, 2, 0, 1, 1, true>(a, grid, lds, s); break;
+      case 3: launch_p<PROF, INIT, 3, 0, 1, 1, true>(a, grid, lds, s); break;
+      case 4: launch_p<PROF, INIT, 4, 0, 1, 1, true>(a, grid, lds, s); break;
+      case 5: launch_p<PROF, INIT, 5, 0, 1, 1, true>(a, grid, lds, s); break;
+      case 6: launch_p<PROF, INIT, 6, 0, 1, 1, true>(a, grid, lds, s); break;
+      default: launch_p<PROF, INIT, 8, 0, 1, 1, true>(a, grid, lds, s); break;
+    }
+    return;
+  }
   if constexpr (!INIT && PROF != kProfGauss)
     if (a.C * a.wpc <= 4 && launch_fixed<PROF>(a, grid, lds, s)) return;
   switch (a.P) {
@@ -803,10 +900,13 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   // split chains only where a specialised kernel exists (hmc_split_waves)
   if (a.wpc != 1 && (INIT || a.wpc != hmc_split_waves(a.N, a.C, a.P, a.prof, a.wpc)))
     return hipErrorInvalidValue;
+  // exposures / noise weights: general kernels, one wave per chain, C <= 4
+  if (a.mx && (a.wpc != 1 || a.C > 4 || a.n_exp < 1 || !a.sqw)) return hipErrorInvalidValue;
   // two chains per wave exactly where launch_fixed_w launches them
-  const int H = (!INIT && a.prof != kProfGauss && a.C * a.wpc <= 4)
+  const int H = (!INIT && !a.mx && a.prof != kProfGauss && a.C * a.wpc <= 4)
                     ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
-  const size_t lds = hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H);
+  const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, 1, a.n_exp, true)
+                          : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
   else if (a.prof == kProfSpergel)

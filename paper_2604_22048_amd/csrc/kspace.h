@@ -307,10 +307,17 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
 // kx-odd sums (kx ky and kx terms) take the difference of the pair's terms,
 // the even ones their sum; the kx and kx^2 factors are applied per column
 // after the loop.
-template <int PROF, bool RESID>
+//
+// Stationary correlated noise (CORR): each bin carries the weight w = 1 /
+// lambda (lambda the noise power of its DFT mode relative to sigma^2).  The
+// data spectrum is stored whitened (D sqrt w) and sw = (sqrt w(+kx), sqrt
+// w(-kx)) scales the model of each bin, so every sum above becomes its
+// w-weighted form (Appendix C, eq. covar-pixel-likelihood).
+template <int PROF, bool RESID, bool CORR = false>
 __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, float xr, float xi,
                                           float TA, float Tc, float& c2, float& sF, float& swq,
-                                          float& syy, float& wky, float& sdx, float& sdy, bool chi2) {
+                                          float& syy, float& wky, float& sdx, float& sdy, bool chi2,
+                                          float2 sw = float2{1.f, 1.f}) {
   const float base = fmaf(sh.tb, y.w, TA);
   const float tp = fmaf(Tc, y.z, base), tm = fmaf(-Tc, y.z, base);
   float Gp, Gm, Gwp, Gwm;
@@ -329,6 +336,12 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
     Gm = __builtin_amdgcn_exp2f(tm);
     Gwp = Gp;
     Gwm = Gm;
+  }
+  if constexpr (CORR) {
+    Gp *= sw.x;
+    Gwp *= sw.x;
+    Gm *= sw.y;
+    Gwm *= sw.y;
   }
   const float a = xi * y.y, b = xi * y.x;
   const float ppr = fmaf(xr, y.x, -a), pmr = fmaf(xr, y.x, a);     // X Y, conj(X) Y
@@ -364,12 +377,17 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
 // loop for its own chain (its own X, Ym, Yf tables and shape constants) over
 // pair-slots l, l + 32, ..., i.e. 2 P pair-iterations per super-row, and the
 // sums are reduced per half.
-template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1>
+//
+// CORR (general kernels only): sqw holds sqrt w per bin in the data
+// spectrum's order (pair-slot order, then the Nyquist bins).
+template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1,
+          bool CORR = false>
 __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P * H>& lc,
                              const float2* __restrict__ dh, const float2* X, const float4* Ym,
                              const float2* Yf, const Shape& sh, float* red, int part = 0,
-                             float* xch = nullptr) {
+                             float* xch = nullptr, const float* __restrict__ sqw = nullptr) {
   static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
+  static_assert(!CORR || NFIX == 0, "noise weights: general kernels only");
   static_assert(H == 1 || (NFIX > 0 && W == 1), "two chains per wave need a specialised kernel");
   constexpr int PI = P * H;           // pair-iterations per super-row of this lane
   constexpr int LS = kWave / H;       // lanes per chain
@@ -442,15 +460,18 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
       }
     }
   } else {
+    const float2* wp = CORR ? reinterpret_cast<const float2*>(sqw) + lane : nullptr;
     for (int sr = 0; sr < sp.nsr; ++sr) {
       float c2 = 0.f;
       const float4* yr = Ym + sr * sp.R;
 #pragma unroll
       for (int i = 0; i < P; ++i)
-        pair_step<PROF, RESID>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xi[i], TA[i], Tc[i], c2, sF,
-                               swq[i], syy, wky[i], sdc[i], sdy, CHI2);
+        pair_step<PROF, RESID, CORR>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xi[i], TA[i], Tc[i], c2,
+                                     sF, swq[i], syy, wky[i], sdc[i], sdy, CHI2,
+                                     CORR ? wp[i * 64] : float2{1.f, 1.f});
       if (CHI2) chi2 += (double)c2;
       dp += P * 64;
+      if constexpr (CORR) wp += P * 64;
     }
   }
   float sxx = 0.f, sxy = 0.f, sdx = 0.f;
@@ -469,6 +490,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     int ub, vb, c;
     nyq_bin_uv(g.N, i, ub, vb, c);
     const float2 D = dh[2 * sp.nslots + i];
+    const float sw = CORR ? sqw[2 * sp.nslots + i] : 1.0f;
     const int nu = (ub == -h) ? 2 : 1;
     const int nv = (vb == -h) ? 2 : 1;
     float Mr = 0.f, Mi = 0.f;
@@ -483,7 +505,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         const float q = fmaf(sh.ca, kx * kx, fmaf(sh.cb, ky * ky, sh.cc * kx * ky));
         float G, ia;
         profile_factor<PROF>(sh, q, G, ia);
-        const float amp = G * cu * cv;
+        const float amp = sw * G * cu * cv;
         Mr += amp * fmaf(xu.x, yv.x, -xu.y * yv.y);
         Mi += amp * fmaf(xu.x, yv.y, xu.y * yv.x);
       }
@@ -503,8 +525,8 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         const float q = fmaf(sh.ca, kx2b, fmaf(sh.cb, ky2b, sh.cc * kxy));
         float G, ia;
         profile_factor<PROF>(sh, q, G, ia);
-        const float Tr = G * fmaf(xu.x, yv.x, -xu.y * yv.y);
-        const float Ti = G * fmaf(xu.x, yv.y, xu.y * yv.x);
+        const float Tr = sw * G * fmaf(xu.x, yv.x, -xu.y * yv.y);
+        const float Ti = sw * G * fmaf(xu.x, yv.y, xu.y * yv.x);
         const float w = cf * cu * cv;
         const float zr = w * fmaf(Rr, Tr, Ri * Ti);
         const float zi = w * fmaf(Rr, Ti, -Ri * Tr);

@@ -161,7 +161,7 @@ template <typename OutT>
 __global__ void __launch_bounds__(256) render_kernel(
     const float* __restrict__ params, const float* __restrict__ psf_fwhm, const int32_t* __restrict__ gidx,
     const int64_t* __restrict__ off, int N, float rscale, float pscale_inv, int prof, float nu,
-    OutT* __restrict__ out) {
+    int n_exp, OutT* __restrict__ out) {
   extern __shared__ double2 smemd[];
   const int gal = gidx[blockIdx.x];
   const int h = N / 2, ntab = 2 * h + 1, nrow = h + 1;
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(256) render_kernel(
   double2* tw = smemd;              // [2N]
   double2* B = tw + 2 * N;          // [nrow][N]
   double2* T = B + nrow * N;        // [ntab], one row at a time
-  const float* p = params + 6 * (int64_t)gal;
+  const float* p = params + 6 * (int64_t)(gal / n_exp);     // stamps gal n_exp + j share a galaxy
   const double F = p[0], s = p[1], e1 = p[2], e2 = p[3], dx = p[4], dy = p[5];
   const double rpx = s * (double)rscale;
   const double sp = (double)psf_fwhm[gal] * 0.42466090014400953 * (double)pscale_inv;
@@ -234,26 +234,70 @@ hipError_t launch_dft_bins(const float* data, const double* model, const int32_t
 template <typename OutT>
 static hipError_t render_impl(const float* params, const float* psf, const int32_t* gidx, int n,
                               const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                              OutT* out, hipStream_t s) {
+                              int n_exp, OutT* out, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const size_t lds = render_lds_bytes(N);
   (void)hipFuncSetAttribute((const void*)render_kernel<OutT>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds);
   hipLaunchKernelGGL(render_kernel<OutT>, dim3(n), dim3(256), lds, s, params, psf, gidx, off, N,
-                     rscale, pscale_inv, prof, nu, out);
+                     rscale, pscale_inv, prof, nu, n_exp, out);
   return hipGetLastError();
 }
 
 hipError_t launch_render(const float* params, const float* psf, const int32_t* gidx, int n,
                          const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                         float* out, hipStream_t s) {
-  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, out, s);
+                         float* out, hipStream_t s, int n_exp) {
+  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, n_exp, out, s);
 }
 
 hipError_t launch_render_f64(const float* params, const float* psf, const int32_t* gidx, int n,
                              const int64_t* off, int N, float rscale, float pscale_inv, int prof, float nu,
-                             double* out, hipStream_t s) {
-  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, out, s);
+                             double* out, hipStream_t s, int n_exp) {
+  return render_impl(params, psf, gidx, n, off, N, rscale, pscale_inv, prof, nu, n_exp, out, s);
+}
+
+// Noise weights of stationary correlated noise (Appendix C): every bin of
+// stamp gidx[block] (pair-slot order, then the Nyquist bins) is multiplied by
+// sqrt w = lambda^-1/2, lambda the noise power of its DFT mode (u, v) read
+// from noise_ps at off[stamp] in FFT order; sqw receives sqrt w per bin (0 in
+// padding bins).  noise_ps NULL: w = 1 (the spectrum is unchanged).
+__global__ void __launch_bounds__(256) whiten_bins_kernel(
+    const float* __restrict__ noise_ps, const int32_t* __restrict__ gidx, const int64_t* __restrict__ off,
+    const int64_t* __restrict__ bin_off, int N, int P, float2* __restrict__ dh, float* __restrict__ sqw) {
+  const int st = gidx[blockIdx.x];
+  const SlotPlan sp = make_slot_plan_p(N, P);
+  float2* d = dh + bin_off[st];
+  float* w = sqw + bin_off[st];
+  const float* ps = noise_ps ? noise_ps + off[st] : nullptr;
+  for (int b = threadIdx.x; b < sp.nbins; b += blockDim.x) {
+    int u = 0, v = 0;
+    bool used = true;
+    if (b < 2 * sp.nslots) {
+      float sc;
+      used = slot_value_uv(N, sp, b, u, v, sc);
+    } else if (b < 2 * sp.nslots + sp.nspec) {
+      int cm;
+      nyq_bin_uv(N, b - 2 * sp.nslots, u, v, cm);
+    } else {
+      used = false;
+    }
+    float r = 0.0f;
+    if (used) {
+      const double lam = ps ? (double)ps[((v + N) % N) * N + (u + N) % N] : 1.0;
+      r = (float)(1.0 / sqrt(lam));
+    }
+    w[b] = r;
+    const float2 z = d[b];
+    d[b] = make_float2(z.x * r, z.y * r);
+  }
+}
+
+hipError_t launch_whiten(const float* noise_ps, const int32_t* gidx, int n, const int64_t* off,
+                         const int64_t* bin_off, int N, int P, float2* dh, float* sqw, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(whiten_bins_kernel, dim3(n), dim3(256), 0, s, noise_ps, gidx, off, bin_off, N, P,
+                     dh, sqw);
+  return hipGetLastError();
 }
 
 double exponential_hlr_factor() {

@@ -73,3 +73,54 @@ def interim_population(G, K, seed, g=(0.02, 0.0), sig_e=0.2, e_max=0.7, mu_ln_s=
     l10s = (ln_s[:, None] + rng.normal(0, noise_ln_s, (G, K))) / math.log(10.0)
     l10f = rng.normal(3.0, 0.1, (G, K))
     return [a.astype(np.float32) for a in (smp.real, smp.imag, l10s, l10f)]
+
+
+def noise_kernel_ps(rng, N):
+    """DFT-mode noise powers |DFT kappa|^2 (FFT order) of a random positive 3 x 3
+    correlation kernel kappa wrapped on the N grid, normalised to unit pixel
+    variance; and kappa itself."""
+    kap = np.zeros((N, N))
+    w = rng.uniform(0.0, 0.1, (3, 3))
+    w[1, 1] = 1.0                          # |DFT kappa| >= 1 - 0.8: well conditioned
+    for a in range(3):
+        for b in range(3):
+            kap[(a - 1) % N, (b - 1) % N] = w[a, b]
+    kap /= math.sqrt(np.sum(kap * kap))
+    return np.abs(np.fft.fft2(kap)) ** 2, kap
+
+
+def correlated_noise(rng, kap, sigma):
+    """sigma times the circular convolution of white noise with kappa."""
+    N = kap.shape[0]
+    wn = rng.normal(0, 1, (N, N))
+    return sigma * np.real(np.fft.ifft2(np.fft.fft2(wn) * np.fft.fft2(kap)))
+
+
+def exposure_population(rng, sizes, E, correlated=True):
+    """Galaxies (params [G, 6]) seen in E exposures each: per stamp (galaxy-major)
+    side, PSF FWHM, sigma, noise powers (or None) and the data stamps."""
+    G = len(sizes)
+    p = np.empty((G, 6))
+    p[:, 0] = rng.uniform(200, 2000, G)
+    p[:, 1] = rng.uniform(0.3, 0.9, G)
+    e = rng.uniform(0, 0.6, G)
+    a = rng.uniform(0, np.pi, G)
+    p[:, 2] = e * np.cos(2 * a)
+    p[:, 3] = e * np.sin(2 * a)
+    p[:, 4] = rng.uniform(-1.0, 1.0, G)
+    p[:, 5] = rng.uniform(-1.0, 1.0, G)
+    n = np.repeat(np.asarray(sizes), E)
+    psf = rng.uniform(0.6, 0.9, G * E)
+    sig = rng.uniform(0.7, 1.5, G * E)
+    ps, stamps = [], []
+    for s in range(G * E):
+        N = int(n[s])
+        m = render.render_one(p[s // E], N, gen.PIXEL_SCALE, float(np.float32(psf[s])))
+        if correlated:
+            q, kap = noise_kernel_ps(rng, N)
+            ps.append(q)
+            stamps.append(m + correlated_noise(rng, kap, sig[s]))
+        else:
+            ps.append(None)
+            stamps.append(m + rng.normal(0, sig[s], (N, N)))
+    return p, n, psf, sig, ps, stamps
