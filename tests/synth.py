@@ -75,25 +75,8 @@ def interim_population(G, K, seed, g=(0.02, 0.0), sig_e=0.2, e_max=0.7, mu_ln_s=
     return [a.astype(np.float32) for a in (smp.real, smp.imag, l10s, l10f)]
 
 
-def noise_kernel_ps(rng, N):
-    """DFT-mode noise powers |DFT kappa|^2 (FFT order) of a random positive 3 x 3
-    correlation kernel kappa wrapped on the N grid, normalised to unit pixel
-    variance; and kappa itself."""
-    kap = np.zeros((N, N))
-    w = rng.uniform(0.0, 0.1, (3, 3))
-    w[1, 1] = 1.0                          # |DFT kappa| >= 1 - 0.8: well conditioned
-    for a in range(3):
-        for b in range(3):
-            kap[(a - 1) % N, (b - 1) % N] = w[a, b]
-    kap /= math.sqrt(np.sum(kap * kap))
-    return np.abs(np.fft.fft2(kap)) ** 2, kap
-
-
-def correlated_noise(rng, kap, sigma):
-    """sigma times the circular convolution of white noise with kappa."""
-    N = kap.shape[0]
-    wn = rng.normal(0, 1, (N, N))
-    return sigma * np.real(np.fft.ifft2(np.fft.fft2(wn) * np.fft.fft2(kap)))
+noise_kernel_ps = gen.noise_kernel_ps
+correlated_noise = gen.correlated_noise
 
 
 def exposure_population(rng, sizes, E, correlated=True):

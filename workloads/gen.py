@@ -210,3 +210,26 @@ def bootstrap_counts(n_boot: int, n_gal: int, seed: int):
     for b in range(n_boot):
         out[b] = np.bincount(idx[b], minlength=n_gal)
     return out
+
+
+def noise_kernel_ps(rng, N):
+    """DFT-mode noise powers |DFT kappa|^2 (FFT order) of a random positive 3 x 3
+    correlation kernel kappa wrapped on the N grid (centre 1, the others in
+    [0, 0.1], normalised to unit pixel variance); and kappa itself."""
+    kap = np.zeros((N, N))
+    w = rng.uniform(0.0, 0.1, (3, 3))
+    w[1, 1] = 1.0
+    for a in range(3):
+        for b in range(3):
+            kap[(a - 1) % N, (b - 1) % N] = w[a, b]
+    kap /= math.sqrt(np.sum(kap * kap))
+    return np.abs(np.fft.fft2(kap)) ** 2, kap
+
+
+def correlated_noise(rng, kap, sigma, n=None):
+    """sigma times the circular convolution of white noise with kappa: one
+    N x N field, or n of them ([n, N, N])."""
+    N = kap.shape[0]
+    shape = (N, N) if n is None else (n, N, N)
+    wn = rng.standard_normal(shape)
+    return sigma * np.real(np.fft.ifft2(np.fft.fft2(wn) * np.fft.fft2(kap)))
