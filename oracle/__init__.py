@@ -17,6 +17,9 @@ prior       interim prior of eq. interim-prior in sampling coordinates.
 philox      Philox4x32-10 counter-based generator, uniforms, Box-Muller normals.
 hmc         potential energy, leapfrog, Metropolis test, dual averaging,
             chain initialisation (eq. initialize).
+nuts        the No-U-Turn transition (multinomial trajectory sampling, momentum-sum
+            U-turn criterion, maximum tree depth) and a NUTS chain with
+            dual-averaging warmup (Section 3.3).
 diagnostics multi-chain ESS (Geyer initial monotone sequence), R-hat, and the
             time-per-galaxy extrapolation of Section 4.1.
 shear       shear response (eq. shear-transform), its Jacobian

@@ -85,3 +85,26 @@ def accept_uniform(seed: int, chain_uid: int, t: int) -> float:
 def jitter_uniform(seed: int, chain_uid: int, t: int) -> float:
     w = philox4x32_10((chain_uid, t, TAG_JITTER, 0), seed_key(seed))
     return uniform_from_word(w[0])
+
+
+# ---- NUTS stream (tag 4) ------------------------------------------------------
+# counter (chain_uid, t, 4, block): block d < 64, word 0 -> direction of doubling
+# d (uniform < 1/2: backward), word 1 -> the uniform of the merge after doubling
+# d; block 64 + n // 4, word n % 4 -> the uniform of the n-th leaf of the
+# iteration (counted over the whole trajectory) in its subtree's sampling.
+TAG_NUTS = 4
+
+
+def nuts_direction(seed: int, chain_uid: int, t: int, d: int) -> int:
+    w = philox4x32_10((chain_uid, t, TAG_NUTS, d), seed_key(seed))
+    return -1 if uniform_from_word(w[0]) < 0.5 else 1
+
+
+def nuts_merge_uniform(seed: int, chain_uid: int, t: int, d: int) -> float:
+    w = philox4x32_10((chain_uid, t, TAG_NUTS, d), seed_key(seed))
+    return uniform_from_word(w[1])
+
+
+def nuts_leaf_uniform(seed: int, chain_uid: int, t: int, n: int) -> float:
+    w = philox4x32_10((chain_uid, t, TAG_NUTS, 64 + n // 4), seed_key(seed))
+    return uniform_from_word(w[n % 4])
