@@ -183,6 +183,10 @@ typedef struct {
 } bsi_interim;
 
 enum { BSI_METRIC_GIVEN = 0, BSI_METRIC_FISHER = 1 };
+/* Transition of bsi_hmc_sample: fixed-length HMC (n_leapfrog steps, step
+ * jitter) or the No-U-Turn sampler of Section 3.3 (the paper's sampler). */
+enum { BSI_SAMPLER_HMC = 0, BSI_SAMPLER_NUTS = 1 };
+#define BSI_NUTS_MAX_DEPTH 10
 enum { BSI_FORM_BATCHED = 0, BSI_FORM_PLAIN = 1 };
 
 /* Hamiltonian sampler settings.  One iteration = one trajectory of
@@ -218,6 +222,18 @@ typedef struct {
                                 differently, so samples agree with the one-wave form to
                                 float32 rounding, and bitwise between calls with equal
                                 settings                                                     */
+  int32_t sampler;           /* BSI_SAMPLER_HMC (0) or BSI_SAMPLER_NUTS.  NUTS: each
+                                iteration doubles its trajectory up to max_tree_depth times
+                                (multinomial sampling of the points, momentum-sum U-turn
+                                criterion at every node of the trajectory's binary tree,
+                                divergence at H - H0 > 1000); n_leapfrog, jitter and
+                                waves_per_chain are ignored; iters_per_launch counts
+                                transitions; each chain is one wave of the general kernels,
+                                so chains of different trajectory lengths do not wait for
+                                each other (a galaxy's workgroup ends with its slowest
+                                chain); trace rows hold {step size, leapfrog steps,
+                                acceptance statistic, doublings}                              */
+  int32_t max_tree_depth;    /* NUTS: 1..BSI_NUTS_MAX_DEPTH (the paper uses 5)              */
 } bsi_hmc_cfg;
 
 /*

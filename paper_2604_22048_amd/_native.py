@@ -24,6 +24,9 @@ LIK_KSPACE = 0
 LIK_PIXEL = 1
 METRIC_GIVEN = 0
 METRIC_FISHER = 1
+SAMPLER_HMC = 0
+SAMPLER_NUTS = 1
+NUTS_MAX_DEPTH = 10
 TRANSFORM_DEFAULT = 0
 TRANSFORM_DIRECT = 1
 TRANSFORM_MFMA = 2
@@ -51,7 +54,7 @@ class HmcCfg(C.Structure):
                 ("step_size", C.c_float), ("target_accept", C.c_float), ("jitter", C.c_float),
                 ("form", C.c_int32), ("iters_per_launch", C.c_int32), ("use_graph", C.c_int32),
                 ("seed", C.c_uint64), ("uid_base", C.c_uint64), ("trace", C.c_void_p),
-                ("waves_per_chain", C.c_int32)]
+                ("waves_per_chain", C.c_int32), ("sampler", C.c_int32), ("max_tree_depth", C.c_int32)]
 
 
 class TruePrior(C.Structure):

@@ -163,6 +163,8 @@ class HmcConfig:
     seed: int = 0
     uid_base: int = 0
     waves_per_chain: int = 1
+    sampler: int = N.SAMPLER_HMC      # or N.SAMPLER_NUTS (Section 3.3's sampler)
+    max_tree_depth: int = 5           # NUTS doublings per transition (the paper's 5)
 
     def c(self, trace=None) -> N.HmcCfg:
         return N.HmcCfg(int(self.n_chains), int(self.n_leapfrog), int(self.n_warmup),
@@ -170,7 +172,8 @@ class HmcConfig:
                         float(self.step_size), float(self.target_accept), float(self.jitter),
                         int(self.form), int(self.iters_per_launch), int(bool(self.use_graph)),
                         int(self.seed) & 0xFFFFFFFFFFFFFFFF, int(self.uid_base) & 0xFFFFFFFFFFFFFFFF,
-                        None if trace is None else trace.data_ptr(), int(self.waves_per_chain))
+                        None if trace is None else trace.data_ptr(), int(self.waves_per_chain),
+                        int(self.sampler), int(self.max_tree_depth))
 
 
 def hmc_sample(batch: Batch, data: torch.Tensor, ref_xy: torch.Tensor, init: torch.Tensor,

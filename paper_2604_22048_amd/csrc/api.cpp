@@ -357,6 +357,11 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     return fail(h, BSI_EINVAL, "iters_per_launch must be >= 1");
   if (cfg->waves_per_chain < 0 || cfg->waves_per_chain > 4)
     return fail(h, BSI_EINVAL, "waves_per_chain must be 0..4");
+  if (cfg->sampler != BSI_SAMPLER_HMC && cfg->sampler != BSI_SAMPLER_NUTS)
+    return fail(h, BSI_EINVAL, "unknown sampler %d", cfg->sampler);
+  const bool nuts = cfg->sampler == BSI_SAMPLER_NUTS;
+  if (nuts && (cfg->max_tree_depth < 1 || cfg->max_tree_depth > BSI_NUTS_MAX_DEPTH))
+    return fail(h, BSI_EINVAL, "max_tree_depth must be 1..%d", BSI_NUTS_MAX_DEPTH);
   if (!(ip->log10f_lo < ip->log10f_hi) || !(ip->log10s_lo < ip->log10s_hi) || !(ip->sigma_d > 0) ||
       !(ip->sigma_e > 0))
     return fail(h, BSI_EINVAL, "invalid interim prior");
@@ -375,7 +380,8 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
   if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
   for (const ClassRange& c : p.classes) {
-    const size_t lds = mx ? hmc_lds_bytes(c.N, C, c.P, 1, 1, p.E, true)
+    const size_t lds = mx ? hmc_lds_bytes(c.N, C, c.P, 1, 1, p.E, true, nuts)
+                     : nuts ? hmc_lds_bytes(c.N, C, c.P, 1, 1, 1, false, true)
                           : hmc_lds_bytes(c.N, C, c.P,
                                           hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain));
     if (lds > 160 * 1024)
@@ -423,6 +429,8 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   a.sqw = mx ? static_cast<const float*>(h->sqw.p) : nullptr;
   a.noise_ps = batch->noise_ps;
   a.off = static_cast<const int64_t*>(h->off.p);
+  a.nuts = nuts ? 1 : 0;
+  a.max_depth = cfg->max_tree_depth;
 
   for (const ClassRange& c : p.classes) {
     HmcArgs ac = a;
@@ -445,7 +453,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
         ac.gidx = ggidx_ptr(h, p, c) + i;
         ac.n_gal = 1;
         ac.n_steps = 1;
-        for (int64_t k = 0; k < (int64_t)T * a.L; ++k) {
+        for (int64_t k = 0; k < (int64_t)T * (nuts ? 1 : a.L); ++k) {
           hipError_t e = launch_hmc_advance(ac, 1, s);
           if (e != hipSuccess) return hip_fail(h, e, "hmc advance launch");
         }
@@ -459,10 +467,10 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       HmcArgs ac = a;
       ac.N = c.N;
       ac.P = c.P;
-      ac.wpc = mx ? 1 : hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain);
+      ac.wpc = (mx || nuts) ? 1 : hmc_split_waves(c.N, C, c.P, batch->profile, cfg->waves_per_chain);
       ac.gidx = ggidx_ptr(h, p, c);
       ac.n_gal = c.gcount;
-      ac.n_steps = ipl * a.L;
+      ac.n_steps = nuts ? ipl : ipl * a.L;
       return launch_hmc_advance(ac, c.gcount, sc);
     };
     // direct launches: the sizes run concurrently on forked streams

@@ -129,11 +129,17 @@ struct HmcArgs {
   const float* sqw;
   const float* noise_ps;
   const int64_t* off;
+  // NUTS (general kernels, one wave per chain): n_steps counts transitions
+  int nuts, max_depth;
 };
+
+// Deepest NUTS tree (doublings per transition).
+constexpr int kNutsMaxDepth = 10;
 
 // LDS bytes of the trajectory kernel: C chains, W waves per chain, H chains per
 // wave; E exposures and sqrt-weights (mx) for the general kernels' MX form.
-size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1, int E = 1, bool mx = false);
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1, int E = 1, bool mx = false,
+                     bool nuts = false);
 // Waves per chain for stamp side N, C chains and plan P when up to max_w are
 // requested: a power of two <= max_w, <= the plan's super-rows, C W <= 4, and
 // 1 unless the profile is exponential or Spergel and P is N's default plan with a

@@ -290,8 +290,11 @@ __device__ void stage_galaxy(const HmcArgs& a, int gal, const Geom& g, const Slo
   }
 }
 
+struct NutsTree;
+
 struct Lds {
   float2* dh;
+  NutsTree* nuts;     // per-wave NUTS scratch (NUTS launches)
   float* sqw;         // sqrt-weights (MX kernels)
   float* atab;
   float4* cols;       // per-slot column table (shared)
@@ -334,6 +337,7 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx,
   l.X = w0 + 2 * sp.ymax;
   l.Yf = l.X + g.ntab + 2;
   l.xch0 = reinterpret_cast<float*>(wt + wave_table_len(g, sp) * C);
+  l.nuts = reinterpret_cast<NutsTree*>(l.xch0 + 2 * 12 * C);
   return l;
 }
 
@@ -607,6 +611,277 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
   lane0_sync();
 }
 
+// ---- No-U-Turn transitions (Section 3.3's sampler) -------------------------
+//
+// One transition per call, run by the chain's wave to the end: draw p0, then
+// double the trajectory up to max_depth times in Philox-chosen directions;
+// within a new subtree each point replaces the subtree's candidate with
+// probability w / (sum of the subtree's weights so far), w = exp(H0 - H); the
+// subtree is abandoned (and the transition ends) at a divergence (H - H0 >
+// 1000 or not finite) or when any complete aligned block of 2^k of its points
+// (k >= 1) makes a U-turn; otherwise its candidate replaces the proposal with
+// probability min(1, W_sub / W_old) and the transition ends if the whole
+// trajectory makes a U-turn.  A span makes a U-turn when rho = the sum of its
+// momenta has (M^-1 p_end) . rho <= 0 at either end.  The open block of each
+// level k keeps its first momentum and the running momentum sum at its start
+// (checkpoints), so each check costs one difference and two dot products.
+// Philox NUTS stream: counter (uid, t, tag 4, d) words 0, 1 = direction and
+// merge uniform of doubling d; (uid, t, 4, 64 + n / 4) word n % 4 = the
+// uniform of the transition's n-th point.
+constexpr uint32_t kTagNuts = 4;
+
+struct NutsTree {                  // per-wave LDS scratch, written by lane 0
+  float eth[2][6], ep[2][6], eg[2][6];   // trajectory ends: 0 backward, 1 forward
+  double eU[2];
+  float pth[6], pg[6];             // proposal
+  double pU;
+  float sth[6], sg[6];             // candidate of the subtree being built
+  double sU;
+  float rho[6];                    // momentum sum of the trajectory
+  float ckp[kNutsMaxDepth][6];     // first momentum of the open block of level k + 1
+  float ckr[kNutsMaxDepth][6];     // subtree momentum sum at that block's start
+};
+
+__device__ __forceinline__ double log_add_exp(double a, double b) {
+  if (a == -INFINITY) return b;
+  if (b == -INFINITY) return a;
+  const double m = fmax(a, b);
+  return m + log(exp(a - m) + exp(b - m));
+}
+
+__device__ __forceinline__ bool u_turn(const float* pa, const float* pb, const float* rho,
+                                       const float* im) {
+  float da = 0.f, db = 0.f;
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    da = fmaf(im[j] * pa[j], rho[j], da);
+    db = fmaf(im[j] * pb[j], rho[j], db);
+  }
+  return da <= 0.f || db <= 0.f;
+}
+
+// Advance the chain by up to a.n_steps NUTS transitions (iterations).
+template <int PROF, int P, bool MX>
+__device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
+                                   const Prior& pr, ChainState* cs, NutsTree* tr,
+                                   float* samples_chain, float* trace_chain) {
+  const int lane = lane_id();
+  const uint32_t uid = cs->uid;
+  float im[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) im[j] = cs->inv_mass[j];
+  int t = cs->t;
+  uint32_t status = cs->status;
+  for (int it = 0; it < a.n_steps && t < c.t_stop; ++it, ++t) {
+    const float eps = cs->eps;
+    float z[6], u_acc, u_jit;
+    draw_iteration<1>(uid, (uint32_t)t, a.k0, a.k1, z, u_acc, u_jit);
+    float p0[6];
+    double ke0 = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      p0[j] = z[j] * __builtin_amdgcn_rsqf(im[j]);
+      ke0 += (double)(im[j] * p0[j] * p0[j]);
+    }
+    const double H0 = cs->U + 0.5 * ke0;
+    lane0_sync();
+    if (lane == 0) {
+      for (int e = 0; e < 2; ++e) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          tr->eth[e][j] = cs->theta[j];
+          tr->ep[e][j] = p0[j];
+          tr->eg[e][j] = cs->grad[j];
+        }
+        tr->eU[e] = cs->U;
+      }
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        tr->pth[j] = cs->theta[j];
+        tr->pg[j] = cs->grad[j];
+        tr->rho[j] = p0[j];
+      }
+      tr->pU = cs->U;
+    }
+    lane0_sync();
+    double log_w = 0.0, sum_alpha = 0.0;
+    int n_lf = 0, n_leaf = 0, depth = 0;
+    bool diverged = false, turned = false, moved = false;
+    for (int d = 0; d < a.max_depth; ++d) {
+      const uint4 wd = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, (uint32_t)d), a.k0, a.k1);
+      const int side = (u01(wd.x) < 0.5f) ? 0 : 1;
+      const float ve = side ? eps : -eps;
+      const float u_merge = u01(wd.y);
+      float th[6], p[6], g[6], srho[6];
+      double U = tr->eU[side];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        th[j] = tr->eth[side][j];
+        p[j] = tr->ep[side][j];
+        g[j] = tr->eg[side][j];
+        srho[j] = 0.f;
+      }
+      double sub_logw = -INFINITY;
+      bool sub_turn = false;
+      const int n_sub = 1 << d;
+      for (int jl = 0; jl < n_sub; ++jl) {
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          p[j] -= 0.5f * ve * g[j];
+          th[j] += ve * im[j] * p[j];
+        }
+        uint32_t st = 0;
+        U = potential<PROF, P, true, 0, 1, 1, MX>(c, lc, pr, th, g, st);
+        if (t >= a.W) status |= st;     // warmup probes are not reported
+        double ke = 0.0;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          p[j] -= 0.5f * ve * g[j];
+          ke += (double)(im[j] * p[j] * p[j]);
+        }
+        const double dH = U + 0.5 * ke - H0;
+        ++n_lf;
+        const bool fin = isfinite(dH);
+        sum_alpha += fin ? fmin(1.0, exp(-dH)) : 0.0;
+        if (!(fin && dH <= kDivergence)) {
+          diverged = true;
+          if (t >= a.W) status |= fin ? 4u : 2u;
+          break;
+        }
+        const double lw = -dH;
+        const double nl = log_add_exp(sub_logw, lw);
+        const uint4 wl = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, 64u + (uint32_t)(n_leaf >> 2)),
+                                       a.k0, a.k1);
+        const uint32_t wsel = (n_leaf & 3) == 0 ? wl.x : (n_leaf & 3) == 1 ? wl.y : (n_leaf & 3) == 2 ? wl.z : wl.w;
+        const bool take = log((double)u01(wsel)) < lw - nl;
+        sub_logw = nl;
+        ++n_leaf;
+        // checkpoints of the blocks opening at this point, then the momentum sum
+        lane0_sync();
+        if (lane == 0) {
+          if (take) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+              tr->sth[j] = th[j];
+              tr->sg[j] = g[j];
+            }
+            tr->sU = U;
+          }
+          for (int k = 1; k <= d; ++k) {
+            if ((jl & ((1 << k) - 1)) == 0) {
+#pragma unroll
+              for (int j = 0; j < 6; ++j) {
+                tr->ckp[k - 1][j] = p[j];
+                tr->ckr[k - 1][j] = srho[j];
+              }
+            }
+          }
+        }
+        lane0_sync();
+#pragma unroll
+        for (int j = 0; j < 6; ++j) srho[j] += p[j];
+        // every complete aligned block ending here
+        for (int k = 1; k <= d && !sub_turn; ++k) {
+          if (((jl + 1) & ((1 << k) - 1)) == 0) {
+            float rb[6], pf[6];
+#pragma unroll
+            for (int j = 0; j < 6; ++j) {
+              rb[j] = srho[j] - tr->ckr[k - 1][j];
+              pf[j] = tr->ckp[k - 1][j];
+            }
+            sub_turn = u_turn(pf, p, rb, im);
+          }
+        }
+        if (sub_turn) break;
+      }
+      if (diverged || sub_turn) {
+        turned = sub_turn;
+        break;
+      }
+      const bool merge = log((double)u_merge) < sub_logw - log_w;
+      log_w = log_add_exp(log_w, sub_logw);
+      lane0_sync();
+      if (lane == 0) {
+        if (merge) {
+#pragma unroll
+          for (int j = 0; j < 6; ++j) {
+            tr->pth[j] = tr->sth[j];
+            tr->pg[j] = tr->sg[j];
+          }
+          tr->pU = tr->sU;
+        }
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          tr->rho[j] += srho[j];
+          tr->eth[side][j] = th[j];
+          tr->ep[side][j] = p[j];
+          tr->eg[side][j] = g[j];
+        }
+        tr->eU[side] = U;
+      }
+      lane0_sync();
+      moved |= merge;
+      depth = d + 1;
+      float pl[6], pr6[6], rh[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        pl[j] = tr->ep[0][j];
+        pr6[j] = tr->ep[1][j];
+        rh[j] = tr->rho[j];
+      }
+      if (u_turn(pl, pr6, rh, im)) {
+        turned = true;
+        break;
+      }
+    }
+    (void)turned;
+    const double alpha = sum_alpha / (double)max(n_lf, 1);
+    if (trace_chain && lane < 4) {
+      const float v = lane == 0 ? eps : lane == 1 ? (float)n_lf : lane == 2 ? (float)alpha : (float)depth;
+      trace_chain[(int64_t)t * 4 + lane] = v;
+    }
+    lane0_sync();
+    if (lane == 0) {
+      if (diverged && t >= a.W) cs->n_div += 1;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        cs->theta[j] = tr->pth[j];
+        cs->grad[j] = tr->pg[j];
+      }
+      cs->U = tr->pU;
+      if (t < a.W) {
+        if (a.adapt) {
+          const double m = (double)(t + 1);
+          const double eta = 1.0 / (m + kDaT0);
+          const double hbar = (1.0 - eta) * cs->hbar + eta * ((double)a.delta - alpha);
+          const double le = (double)a.mu - sqrt(m) / kDaGamma * hbar;
+          const double x = (double)exp2f(-(float)kDaKappa * log2f((float)m));   // m^-kappa
+          const double lbar = x * le + (1.0 - x) * cs->log_eps_bar;
+          cs->hbar = hbar;
+          cs->log_eps_bar = lbar;
+          cs->eps = (t == a.W - 1) ? (float)exp(lbar) : (float)exp(le);
+        }
+      } else {
+        cs->n_acc += moved ? 1 : 0;
+        cs->sum_alpha += (float)alpha;
+      }
+    }
+    lane0_sync();
+    if (t >= a.W && samples_chain && lane < 6) {
+      float v = cs->theta[0];
+#pragma unroll
+      for (int j = 1; j < 6; ++j) v = (lane == j) ? cs->theta[j] : v;
+      samples_chain[(int64_t)(t - a.W) * 6 + lane] = v;
+    }
+  }
+  lane0_sync();
+  if (lane == 0) {
+    cs->t = t;
+    cs->status = status;
+  }
+  lane0_sync();
+}
+
 // Minimum resident waves per SIMD requested from the register allocator for
 // the trajectory kernel (occupancy against instruction-level parallelism).
 #ifndef BSI_HMC_WAVES_PER_EU
@@ -618,9 +893,13 @@ __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<
 // H = 2: two chains per wave (lanes 0..31 and 32..63; advance only, C even).
 // MX: several exposures per galaxy and/or per-bin noise weights (general
 // kernels, one wave per chain).
-template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false>
+// NUTS: No-U-Turn transitions instead of fixed-length trajectories (general
+// kernels, one wave per chain, advance only).
+template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false,
+          bool NUTS = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
+  static_assert(!NUTS || (!INIT && NFIX == 0 && W == 1 && H == 1), "NUTS: general advance kernels");
   static_assert(!MX || (NFIX == 0 && W == 1 && H == 1), "exposures and noise weights: general kernels");
   static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
@@ -722,7 +1001,10 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       // first writes the outputs
       float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      advance_chain<PROF, P, NFIX, W, H, MX>(a, c, lc, pr, l.cs, sc, tc);
+      if constexpr (NUTS)
+        advance_chain_nuts<PROF, P, MX>(a, c, lc, pr, l.cs, l.nuts + wave, sc, tc);
+      else
+        advance_chain<PROF, P, NFIX, W, H, MX>(a, c, lc, pr, l.cs, sc, tc);
       if (part == 0) {
         uint32_t* dst = reinterpret_cast<uint32_t*>(st);
 #pragma unroll
@@ -753,19 +1035,34 @@ __global__ void hmc_finalize_kernel(const ChainState* __restrict__ st, int n_gal
 
 }  // namespace
 
-size_t hmc_lds_bytes(int N, int C, int P, int W, int H, int E, bool mx) {
+size_t hmc_lds_bytes(int N, int C, int P, int W, int H, int E, bool mx, bool nuts) {
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int NW = C * W;
   return sizeof(float2) * E * dh_stride(sp) + sizeof(float) * (mx ? E * sw_stride(sp) : 0) +
          sizeof(float) * E * atab_stride(g) +
          sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * (NW / H) +
-         sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW;
+         sizeof(float2) * wave_table_len(g, sp) * NW + sizeof(float) * 2 * 12 * NW +
+         (nuts ? sizeof(NutsTree) * NW : 0);
 }
 
 template <int PROF, bool INIT, int P, int NFIX = 0, int W = 1, int H = 1, bool MX = false>
 static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   const dim3 blk(kWave * a.C * W / H);
+  if constexpr (!INIT && NFIX == 0 && W == 1 && H == 1) {
+    if (a.nuts) {
+      if (MX || a.C <= 4) {
+        auto k = hmc_kernel<PROF, false, P, 256, 0, 1, 1, MX, true>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
+      } else {
+        auto k = hmc_kernel<PROF, false, P, 1024, 0, 1, 1, false, true>;
+        (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
+      }
+      return;
+    }
+  }
   if constexpr (MX) {
     auto k = hmc_kernel<PROF, INIT, P, 256, 0, 1, 1, true>;   // C <= 4 (checked by the caller)
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -868,6 +1165,18 @@ const int* hmc_fixed_plans(int N) {
 
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  if (a.nuts && !a.mx) {
+    switch (a.P) {
+      case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
+      case 2: launch_p<PROF, INIT, 2>(a, grid, lds, s); break;
+      case 3: launch_p<PROF, INIT, 3>(a, grid, lds, s); break;
+      case 4: launch_p<PROF, INIT, 4>(a, grid, lds, s); break;
+      case 5: launch_p<PROF, INIT, 5>(a, grid, lds, s); break;
+      case 6: launch_p<PROF, INIT, 6>(a, grid, lds, s); break;
+      default: launch_p<PROF, INIT, 8>(a, grid, lds, s); break;
+    }
+    return;
+  }
   if (a.mx) {
     switch (a.P) {
       case 1: launch_p<PROF, INIT, 1, 0, 1, 1, true>(a, grid, lds, s); break;
@@ -902,11 +1211,14 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
     return hipErrorInvalidValue;
   // exposures / noise weights: general kernels, one wave per chain, C <= 4
   if (a.mx && (a.wpc != 1 || a.C > 4 || a.n_exp < 1 || !a.sqw)) return hipErrorInvalidValue;
+  // NUTS: general kernels, one wave per chain
+  if (a.nuts && (a.wpc != 1 || a.max_depth < 1 || a.max_depth > kNutsMaxDepth))
+    return hipErrorInvalidValue;
   // two chains per wave exactly where launch_fixed_w launches them
-  const int H = (!INIT && !a.mx && a.prof != kProfGauss && a.C * a.wpc <= 4)
+  const int H = (!INIT && !a.mx && !a.nuts && a.prof != kProfGauss && a.C * a.wpc <= 4)
                     ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
-  const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, 1, a.n_exp, true)
-                          : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H);
+  const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, 1, a.n_exp, true, a.nuts)
+                          : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H, 1, false, a.nuts);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);
   else if (a.prof == kProfSpergel)

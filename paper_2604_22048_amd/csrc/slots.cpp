@@ -224,6 +224,8 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
       !(ip.sigma_e > 0))
     return fail(h, BSI_EINVAL, "invalid interim prior");
   if (!(cfg->pixel_scale > 0.0f)) return fail(h, BSI_EINVAL, "pixel_scale must be positive");
+  if (cfg->hmc.sampler != BSI_SAMPLER_HMC)
+    return fail(h, BSI_EUNSUPPORTED, "the request server runs fixed-length HMC only");
   if (cfg->profile != BSI_PROFILE_EXPONENTIAL && cfg->profile != BSI_PROFILE_GAUSSIAN &&
       cfg->profile != BSI_PROFILE_SPERGEL)
     return fail(h, BSI_EINVAL, "unknown profile %d", cfg->profile);

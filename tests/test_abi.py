@@ -54,7 +54,7 @@ int main(void) {
   printf("bsi_slots_info %zu\n", sizeof(bsi_slots_info));
   F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile) F(bsi_batch, spergel_nu)
   F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
-  F(bsi_hmc_cfg, trace) F(bsi_hmc_cfg, waves_per_chain)
+  F(bsi_hmc_cfg, trace) F(bsi_hmc_cfg, waves_per_chain) F(bsi_hmc_cfg, sampler) F(bsi_hmc_cfg, max_tree_depth)
   F(bsi_true_prior, mu_ln_f) F(bsi_true_prior, sigma_ln_f)
   F(bsi_shear_hmc_cfg, jitter) F(bsi_shear_hmc_cfg, inv_mass) F(bsi_shear_hmc_cfg, seed)
   F(bsi_shear_hmc_cfg, use_graph) F(bsi_shear_hmc_cfg, trace)

@@ -1,0 +1,106 @@
+"""GPU parity of the No-U-Turn transitions (Section 3.3's sampler) against the
+oracle's NUTS under the same Philox streams.
+
+Bar: positions within 2e-4 (the Fisher-metric HMC bar) and identical
+leapfrog counts per transition until the first decision (a U-turn, a
+multinomial or merge draw, a divergence) that the float32 and float64
+trajectories take differently; after it chains legitimately differ."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import hmc, nuts               # noqa: E402
+from tests import synth                    # noqa: E402
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bsi(device):
+    from paper_2604_22048_amd import api
+    return api
+
+
+def _setup(bsi, torch, cfg_name, G, C, seed, sizes=None):
+    t, params, data, off = synth.make_population(cfg_name, n_gal=G, seed=seed, sizes=sizes)
+    init = synth.init_positions(t, params, data, off, C, seed=seed + 1)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=0.2)
+    ref = np.stack([t.dx, t.dy], axis=1)
+    return t, data, off, init, b, ref
+
+
+def _run(bsi, torch, b, data, ref, init, cfg, G, C):
+    T = cfg.n_warmup + cfg.n_samples
+    trace = torch.zeros(G, C, T, 4, dtype=torch.float32).cuda()
+    s, stats, st = bsi.hmc_sample(b, torch.tensor(data).cuda(),
+                                  torch.tensor(ref, dtype=torch.float32).cuda(),
+                                  torch.tensor(init, dtype=torch.float32).cuda(), cfg, trace=trace)
+    torch.cuda.synchronize()
+    return s.cpu().numpy(), stats.cpu().numpy(), st.cpu().numpy(), trace.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg_name,sizes", [("uniform", None), ("uneven", [25, 41, 73])])
+def test_nuts_parity(bsi, cfg_name, sizes):
+    import torch
+    _log(f"nuts parity {cfg_name}")
+    G, C, S, D = 3, 2, 5, 5
+    t, data, off, init, b, ref = _setup(bsi, torch, cfg_name, G, C, 11, sizes)
+    seed = 321
+    cfg = bsi.HmcConfig(n_chains=C, n_warmup=0, n_samples=S, adapt=False, step_size=0.25,
+                        metric=bsi.N.METRIC_FISHER, seed=seed, iters_per_launch=2,
+                        sampler=bsi.N.SAMPLER_NUTS, max_tree_depth=D)
+    s, stats, st, tr = _run(bsi, torch, b, data, ref, init, cfg, G, C)
+    agree = total = 0
+    depths = []
+    for i in range(G):
+        gal = synth.oracle_galaxy(t, data, off, i)
+        for c in range(C):
+            th0 = init[i, c].astype(np.float32).astype(np.float64)
+            im = hmc.fisher_inv_mass(gal, th0)
+            r = nuts.run_chain_nuts(hmc.galaxy_potential(gal), th0, seed, i * C + c, 0, S, 0.25,
+                                    max_depth=D, adapt=False, inv_mass=im)
+            for k in range(S):
+                total += 1
+                if (np.max(np.abs(s[i, c, k] - r["samples"][k])) > 2e-4
+                        or int(tr[i, c, k, 1]) != int(r["n_leapfrog"][k])):
+                    break
+                agree += 1
+                depths.append(int(tr[i, c, k, 3]))
+    assert agree >= total - 3, (agree, total)
+    assert max(depths) >= 2             # the trees do double and turn
+
+
+def test_nuts_adaptation_and_invariance(bsi):
+    """Dual averaging replayed on the sampler's own statistics; a galaxy alone
+    equals the galaxy in a mixed-size batch bitwise."""
+    import torch
+    _log("nuts adaptation and batch invariance")
+    G, C, W, S = 3, 2, 40, 10
+    t, data, off, init, b, ref = _setup(bsi, torch, "uneven", G, C, 21, [25, 53, 41])
+    cfg = bsi.HmcConfig(n_chains=C, n_warmup=W, n_samples=S, adapt=True, step_size=0.3,
+                        metric=bsi.N.METRIC_FISHER, seed=9, iters_per_launch=3,
+                        sampler=bsi.N.SAMPLER_NUTS, max_tree_depth=5)
+    s, stats, st, tr = _run(bsi, torch, b, data, ref, init, cfg, G, C)
+    for i in range(G):
+        for c in range(C):
+            da = hmc.DualAveraging(0.3)
+            for k in range(W):
+                assert abs(tr[i, c, k, 0] - hmc.f32(math.exp(da.log_eps) if k else 0.3)) <= \
+                    2e-6 * tr[i, c, k, 0], (i, c, k)
+                da.update(float(tr[i, c, k, 2]))
+            assert abs(stats[i, c, 1] - hmc.f32(da.final())) <= 1e-5 * stats[i, c, 1]
+            assert np.all(tr[i, c, :, 1] >= 1) and np.all(tr[i, c, :, 3] <= 5)
+    N1 = int(t.n_pix[1])
+    b1 = bsi.Batch(n=t.n_pix[1:2], psf_fwhm=torch.tensor(t.psf_fwhm[1:2], dtype=torch.float32).cuda(),
+                   sigma=torch.tensor(t.sigma[1:2], dtype=torch.float32).cuda(), pixel_scale=0.2)
+    cfg1 = bsi.HmcConfig(**{**cfg.__dict__, "uid_base": C})
+    s1, _, _, _ = _run(bsi, torch, b1, data[off[1]:off[1] + N1 * N1], ref[1:2], init[1:2], cfg1, 1, C)
+    assert np.array_equal(s1[0], s[1])
