@@ -495,6 +495,49 @@ def bias_leg(api, torch, stream, n_gal, n_boot, log):
             "galaxy_pairs_per_s": round(n_gal / total, 1)}
 
 
+def nuts_leg(api, torch, stream, n_gal, depth, ipl, log):
+    """The paper's sampler (Section 3.3: NUTS, maximum tree depth 5) on the
+    uniform workload with the headline's warmup and draws, beside fixed-length
+    HMC on the same galaxies: galaxies/s at 300 ESS, leapfrog steps per
+    transition (from the per-iteration trace) and the kernels' algorithmic rate."""
+    cfg = gen.CONFIGS["uniform"]
+    t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
+    C, W, S = cfg.chains, cfg.warmup, cfg.samples
+    dev = torch.device("cuda:0")
+    ipl = ipl if ipl > 0 else W + S
+    ncfg = api.HmcConfig(n_chains=C, n_warmup=W, n_samples=S, adapt=True,
+                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8,
+                         iters_per_launch=ipl, use_graph=True, seed=gen.chain_seed(cfg.index),
+                         sampler=api.N.SAMPLER_NUTS, max_tree_depth=depth)
+    wcfg = api.HmcConfig(**{**ncfg.__dict__, "n_samples": 0})
+    trace = torch.zeros(n_gal, C, W + S, 4, dtype=torch.float32, device=dev)
+    api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
+    (smp, st, status), t_all = timed(torch, lambda: api.hmc_sample(b, data, ref, init, ncfg, trace=trace),
+                                     stream)
+    (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
+    _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
+    n_eff = float(e.mean(dim=1).mean())
+    t_s = t_all - t_w
+    tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
+    nlf = trace[..., 1]
+    steps = float(nlf.sum())
+    steps_w = float(nlf[:, :, :W].sum())
+    depth_hist = torch.bincount(trace[..., 3].reshape(-1).long(), minlength=depth + 1).cpu().tolist()
+    flop = flops_per_eval(cfg.n_pix) * steps
+    log(f"[bench] nuts: depth {depth}, {ipl} per launch: {t_all:.3f} s, {steps / (n_gal * C * (W + S)):.2f} "
+        f"leapfrog steps per transition, n_eff {n_eff:.0f}")
+    return {"n_gal": n_gal, "max_tree_depth": depth, "iters_per_launch": ipl,
+            "t_sampler_s": round(t_all, 4), "t_warmup_s": round(t_w, 4), "n_eff_mean": round(n_eff, 1),
+            "galaxies_per_s": round(1.0 / tpg, 1),
+            "leapfrog_per_transition": round(steps / (n_gal * C * (W + S)), 3),
+            "leapfrog_per_transition_sampling": round((steps - steps_w) / (n_gal * C * S), 3),
+            "depth_histogram": depth_hist,
+            "ess_per_gradient_eval": round(n_eff / ((steps - steps_w) / n_gal), 4),
+            "achieved_tflops": round(flop / t_all / 1e12, 3),
+            "accept_stat_mean": round(float(trace[:, :, W:, 2].mean()), 4),
+            "status_nonzero": int((status != 0).sum())}
+
+
 def exposures_leg(api, torch, stream, n_gal, E, log):
     """Appendix C likelihood: the uniform workload's galaxies (53-pixel stamps)
     each seen in E exposures with their own PSF FWHM ~ U(0.6", 0.9"), noise
@@ -562,7 +605,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
     ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "spergel", "bias",
-                                           "exposures"],
+                                           "exposures", "nuts"],
                     default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
@@ -572,6 +615,9 @@ def main():
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
     ap.add_argument("--n-boot", type=int, default=500, help="--workload bias: bootstrap resamples")
     ap.add_argument("--n-exp", type=int, default=4, help="--workload exposures: exposures per galaxy")
+    ap.add_argument("--depth", type=int, default=5, help="--workload nuts: maximum tree depth")
+    ap.add_argument("--ipl", type=int, default=0,
+                    help="--workload nuts: transitions per launch (0: all in one launch)")
     ap.add_argument("--spergel-nu", type=float, default=-0.6,
                     help="--workload spergel: the fixed Spergel index of the fit")
     ap.add_argument("--plan", type=int, default=0,
@@ -614,7 +660,16 @@ def main():
                    "config": {"workload": "10,000 galaxies x 1,000 interim samples, 4 points"}, **res}
             print(json.dumps(out), flush=True)
             return
-        if args.workload == "exposures":
+        if args.workload == "nuts":
+            G = args.n_gal or gen.CONFIGS["uniform"].n_gal
+            res = nuts_leg(api, torch, stream, G, args.depth, args.ipl, log)
+            out = {"metric": "galaxies/sec at 300 ESS (NUTS, Section 3.3's sampler)",
+                   "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": f"batched uniform: {G} galaxies, 53x53, 4 chains, NUTS max "
+                                          f"tree depth {args.depth}, 300 warmup + 1000 draws, "
+                                          f"{args.ipl} transitions per launch"}, **res}
+        elif args.workload == "exposures":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
             res = exposures_leg(api, torch, stream, G, args.n_exp, log)
             out = {"metric": "galaxies/sec at 300 ESS (several exposures, correlated noise)",

@@ -642,11 +642,20 @@ struct NutsTree {                  // per-wave LDS scratch, written by lane 0
   float ckr[kNutsMaxDepth][6];     // subtree momentum sum at that block's start
 };
 
-__device__ __forceinline__ double log_add_exp(double a, double b) {
+// log(e^a + e^b) in float for the trajectory weights (hardware exp2/log2).
+__device__ __forceinline__ float log_add_expf(float a, float b) {
   if (a == -INFINITY) return b;
   if (b == -INFINITY) return a;
-  const double m = fmax(a, b);
-  return m + log(exp(a - m) + exp(b - m));
+  const float m = fmaxf(a, b);
+  return m + __logf(1.0f + __expf(-fabsf(a - b)));
+}
+
+// Component `lane` of a 6-vector held by every lane (lanes 0..5).
+__device__ __forceinline__ float pick6(const float* v, int i) {
+  float r = v[0];
+#pragma unroll
+  for (int j = 1; j < 6; ++j) r = (i == j) ? v[j] : r;
+  return r;
 }
 
 __device__ __forceinline__ bool u_turn(const float* pa, const float* pb, const float* rho,
@@ -661,7 +670,7 @@ __device__ __forceinline__ bool u_turn(const float* pa, const float* pb, const f
 }
 
 // Advance the chain by up to a.n_steps NUTS transitions (iterations).
-template <int PROF, int P, bool MX>
+template <int PROF, int P, int NFIX, bool MX>
 __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const LaneCols<P>& lc,
                                    const Prior& pr, ChainState* cs, NutsTree* tr,
                                    float* samples_chain, float* trace_chain) {
@@ -704,8 +713,9 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
       tr->pU = cs->U;
     }
     lane0_sync();
-    double log_w = 0.0, sum_alpha = 0.0;
+    float log_w = 0.0f, sum_alpha = 0.0f;
     int n_lf = 0, n_leaf = 0, depth = 0;
+    uint4 wl = make_uint4(0u, 0u, 0u, 0u);   // leaf uniforms, four per Philox block
     bool diverged = false, turned = false, moved = false;
     for (int d = 0; d < a.max_depth; ++d) {
       const uint4 wd = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, (uint32_t)d), a.k0, a.k1);
@@ -721,7 +731,7 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
         g[j] = tr->eg[side][j];
         srho[j] = 0.f;
       }
-      double sub_logw = -INFINITY;
+      float sub_logw = -INFINITY;
       bool sub_turn = false;
       const int n_sub = 1 << d;
       for (int jl = 0; jl < n_sub; ++jl) {
@@ -731,7 +741,7 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
           th[j] += ve * im[j] * p[j];
         }
         uint32_t st = 0;
-        U = potential<PROF, P, true, 0, 1, 1, MX>(c, lc, pr, th, g, st);
+        U = potential<PROF, P, true, NFIX, 1, 1, MX>(c, lc, pr, th, g, st);
         if (t >= a.W) status |= st;     // warmup probes are not reported
         double ke = 0.0;
 #pragma unroll
@@ -739,42 +749,36 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
           p[j] -= 0.5f * ve * g[j];
           ke += (double)(im[j] * p[j] * p[j]);
         }
-        const double dH = U + 0.5 * ke - H0;
+        const double dH = U + 0.5 * ke - H0;     // float64: U and H0 are O(N^2)
         ++n_lf;
         const bool fin = isfinite(dH);
-        sum_alpha += fin ? fmin(1.0, exp(-dH)) : 0.0;
+        const float lw = -(float)dH;               // the weights' arithmetic in float
+        sum_alpha += fin ? fminf(1.0f, __expf(lw)) : 0.0f;
         if (!(fin && dH <= kDivergence)) {
           diverged = true;
           if (t >= a.W) status |= fin ? 4u : 2u;
           break;
         }
-        const double lw = -dH;
-        const double nl = log_add_exp(sub_logw, lw);
-        const uint4 wl = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, 64u + (uint32_t)(n_leaf >> 2)),
-                                       a.k0, a.k1);
+        const float nl = log_add_expf(sub_logw, lw);
+        if ((n_leaf & 3) == 0)
+          wl = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, 64u + (uint32_t)(n_leaf >> 2)), a.k0,
+                             a.k1);
         const uint32_t wsel = (n_leaf & 3) == 0 ? wl.x : (n_leaf & 3) == 1 ? wl.y : (n_leaf & 3) == 2 ? wl.z : wl.w;
-        const bool take = log((double)u01(wsel)) < lw - nl;
+        const bool take = __logf(u01(wsel)) < lw - nl;
         sub_logw = nl;
         ++n_leaf;
-        // checkpoints of the blocks opening at this point, then the momentum sum
-        lane0_sync();
-        if (lane == 0) {
-          if (take) {
-#pragma unroll
-            for (int j = 0; j < 6; ++j) {
-              tr->sth[j] = th[j];
-              tr->sg[j] = g[j];
-            }
-            tr->sU = U;
-          }
-          for (int k = 1; k <= d; ++k) {
-            if ((jl & ((1 << k) - 1)) == 0) {
-#pragma unroll
-              for (int j = 0; j < 6; ++j) {
-                tr->ckp[k - 1][j] = p[j];
-                tr->ckr[k - 1][j] = srho[j];
-              }
-            }
+        // the subtree candidate and the checkpoints of the blocks opening at this
+        // point, one component per lane (lanes 0..11)
+        if (take) {
+          if (lane < 12) (&tr->sth[0])[lane] = lane < 6 ? pick6(th, lane) : pick6(g, lane - 6);
+          if (lane == 0) tr->sU = U;
+        }
+        for (int k = 1; k <= d; ++k) {
+          if ((jl & ((1 << k) - 1)) == 0 && lane < 12) {
+            if (lane < 6)
+              tr->ckp[k - 1][lane] = pick6(p, lane);
+            else
+              tr->ckr[k - 1][lane - 6] = pick6(srho, lane - 6);
           }
         }
         lane0_sync();
@@ -798,8 +802,8 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
         turned = sub_turn;
         break;
       }
-      const bool merge = log((double)u_merge) < sub_logw - log_w;
-      log_w = log_add_exp(log_w, sub_logw);
+      const bool merge = __logf(u_merge) < sub_logw - log_w;
+      log_w = log_add_expf(log_w, sub_logw);
       lane0_sync();
       if (lane == 0) {
         if (merge) {
@@ -835,7 +839,7 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
       }
     }
     (void)turned;
-    const double alpha = sum_alpha / (double)max(n_lf, 1);
+    const double alpha = (double)(sum_alpha / (float)max(n_lf, 1));
     if (trace_chain && lane < 4) {
       const float v = lane == 0 ? eps : lane == 1 ? (float)n_lf : lane == 2 ? (float)alpha : (float)depth;
       trace_chain[(int64_t)t * 4 + lane] = v;
@@ -899,7 +903,7 @@ template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, 
           bool NUTS = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
-  static_assert(!NUTS || (!INIT && NFIX == 0 && W == 1 && H == 1), "NUTS: general advance kernels");
+  static_assert(!NUTS || (!INIT && W == 1 && H == 1), "NUTS: advance kernels, one wave per chain");
   static_assert(!MX || (NFIX == 0 && W == 1 && H == 1), "exposures and noise weights: general kernels");
   static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
@@ -1002,7 +1006,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
       if constexpr (NUTS)
-        advance_chain_nuts<PROF, P, MX>(a, c, lc, pr, l.cs, l.nuts + wave, sc, tc);
+        advance_chain_nuts<PROF, P, NFIX, MX>(a, c, lc, pr, l.cs, l.nuts + wave, sc, tc);
       else
         advance_chain<PROF, P, NFIX, W, H, MX>(a, c, lc, pr, l.cs, sc, tc);
       if (part == 0) {
@@ -1163,8 +1167,25 @@ const int* hmc_fixed_plans(int N) {
   }
 }
 
+// NUTS on the kernels specialised per stamp size (one wave per chain).
+template <int PROF>
+static bool launch_fixed_nuts(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+#define BSI_CASE(NN, PP)                                                                        \
+  if (a.N == NN && a.P == PP) {                                                                 \
+    auto k = hmc_kernel<PROF, false, PP, 256, NN, 1, 1, false, true>;                           \
+    (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kWave * a.C), lds, s, a);                            \
+    return true;                                                                                \
+  }
+  BSI_FIXED_PLANS(BSI_CASE)
+#undef BSI_CASE
+  return false;
+}
+
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+  if constexpr (!INIT && PROF != kProfGauss)
+    if (a.nuts && !a.mx && a.C <= 4 && launch_fixed_nuts<PROF>(a, grid, lds, s)) return;
   if (a.nuts && !a.mx) {
     switch (a.P) {
       case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;
