@@ -668,7 +668,7 @@ def main():
                    "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                    "config": {"workload": f"batched uniform: {G} galaxies, 53x53, 4 chains, NUTS max "
                                           f"tree depth {args.depth}, 300 warmup + 1000 draws, "
-                                          f"{args.ipl} transitions per launch"}, **res}
+                                          f"{res['iters_per_launch']} transitions per launch"}, **res}
         elif args.workload == "exposures":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
             res = exposures_leg(api, torch, stream, G, args.n_exp, log)
