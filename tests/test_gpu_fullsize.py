@@ -171,3 +171,119 @@ def test_ess_full_size_sampled(bsi):
         for p in range(P):
             assert abs(e[g, p] / diagnostics.ess(xs[:, :, p]) - 1) < 1e-5, (g, p)
             assert abs(r[g, p] / diagnostics.rhat(xs[:, :, p]) - 1) < 1e-6, (g, p)
+
+
+def test_uniform_full_nuts_sampled_and_invariant(bsi, uniform):
+    """NUTS (depth 5) on all 40,000 chains in the benchmark's launch form (a
+    call's transitions in one launch, kernels specialised per size): sampled
+    chains follow the oracle's NUTS under the same Philox streams, and sampled
+    galaxies run alone reproduce their slice bitwise."""
+    import torch
+    from oracle import nuts
+    u = uniform
+    C, S, D = 4, 3, 5
+    base = dict(n_chains=C, n_warmup=0, n_samples=S, adapt=False, metric=1, step_size=0.3,
+                seed=77, use_graph=True, iters_per_launch=S, sampler=bsi.N.SAMPLER_NUTS,
+                max_tree_depth=D)
+    cfg = bsi.HmcConfig(**base)
+    init_t = torch.tensor(u["init"], dtype=torch.float32).cuda()
+    smp, stats, status = bsi.hmc_sample(u["b"], u["dev"], u["ref"], init_t, cfg)
+    smp = smp.cpu().numpy()
+    assert np.all(np.isfinite(smp))
+    agree = total = 0
+    for i in SAMPLED[:4]:
+        gal = synth.oracle_galaxy(u["t"], u["data"], u["off"], i)
+        for c in range(C):
+            th0 = u["init"][i, c].astype(np.float32).astype(np.float64)
+            im = hmc.fisher_inv_mass(gal, th0)
+            r = nuts.run_chain_nuts(hmc.galaxy_potential(gal), th0, 77, i * C + c, 0, S, 0.3,
+                                    max_depth=D, adapt=False, inv_mass=im)
+            for k in range(S):
+                total += 1
+                if np.max(np.abs(smp[i, c, k] - r["samples"][k])) > 2e-4:
+                    break
+                agree += 1
+    assert agree >= total - 2, (agree, total)
+    for i in SAMPLED[4:6]:
+        N = int(u["t"].n_pix[i])
+        b1 = bsi.Batch(n=np.array([N]), psf_fwhm=u["b"].psf_fwhm[i:i + 1].clone(),
+                       sigma=u["b"].sigma[i:i + 1].clone(), pixel_scale=PS)
+        one = bsi.HmcConfig(uid_base=i * C, **base)
+        s1, _, _ = bsi.hmc_sample(b1, u["dev"][u["off"][i]:u["off"][i] + N * N].contiguous(),
+                                  u["ref"][i:i + 1].contiguous(), init_t[i:i + 1].contiguous(), one)
+        assert np.array_equal(s1[0].cpu().numpy(), smp[i]), i
+
+
+def test_uniform_full_spergel_hmc_sampled(bsi, uniform):
+    """The model-bias fit at full size: the 10,000 exponential galaxies fitted
+    with a Spergel profile (nu = -0.6) by the specialised two-chain kernels;
+    sampled chains follow the oracle."""
+    import torch
+    u = uniform
+    C, L, S, nu = 4, 20, 3, -0.6
+    bs = bsi.Batch(n=u["b"].n, psf_fwhm=u["b"].psf_fwhm, sigma=u["b"].sigma, pixel_scale=PS,
+                   profile=bsi.N.PROFILE_SPERGEL, spergel_nu=nu)
+    cfg = bsi.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False, metric=1,
+                        step_size=0.3, jitter=0.2, seed=31, use_graph=True)
+    init_t = torch.tensor(u["init"], dtype=torch.float32).cuda()
+    smp, stats, status = bsi.hmc_sample(bs, u["dev"], u["ref"], init_t, cfg)
+    smp = smp.cpu().numpy()
+    assert np.all(np.isfinite(smp))
+    prof = render.Spergel(nu)
+    agree = 0
+    for i in SAMPLED[:3]:
+        gal = synth.oracle_galaxy(u["t"], u["data"], u["off"], i, prof)
+        for c in range(C):
+            th0 = u["init"][i, c].astype(np.float32).astype(np.float64)
+            im = hmc.fisher_inv_mass(gal, th0)
+            r = hmc.run_chain(hmc.galaxy_potential(gal), th0, 31, i * C + c, L, 0, S, 0.3,
+                              adapt=False, inv_mass=im, jitter=0.2)
+            for k in range(S):
+                d = np.max(np.abs(smp[i, c, k] - r["samples"][k]))
+                if d > 2e-4:
+                    moved_g = k == 0 or np.any(smp[i, c, k] != smp[i, c, k - 1])
+                    moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+                    assert moved_g != moved_o, (i, c, k, d)
+                    break
+                agree += 1
+    assert agree >= 3 * C * S - 2
+
+
+def test_exposures_full_loglik_sampled(bsi, uniform):
+    """10,000 galaxies x 2 exposures (Appendix C) in one call: exposure 0 the
+    workload's stamp with white noise, exposure 1 the same stamp plus
+    correlated noise, its own PSF and noise power; sampled galaxies' log L
+    and gradient against the oracle's explicit-covariance likelihood."""
+    import torch
+    u = uniform
+    t = u["t"]
+    G, E, N = len(t), 2, 53
+    rng = np.random.default_rng(5)
+    ps1, kap = synth.noise_kernel_ps(rng, N)
+    st0 = u["data"].reshape(G, N * N)
+    st1 = st0 + synth.correlated_noise(rng, kap, 0.7, n=G).reshape(G, N * N).astype(np.float32)
+    data = np.stack([st0, st1], axis=1).reshape(-1).astype(np.float32)
+    psf = np.stack([t.psf_fwhm, t.psf_fwhm * 1.15], axis=1).reshape(-1).astype(np.float32)
+    sig = np.stack([t.sigma, np.hypot(t.sigma, 0.7)], axis=1).reshape(-1).astype(np.float32)
+    nps = np.stack([np.ones((G, N * N)), np.broadcast_to(ps1.ravel(), (G, N * N))], axis=1)
+    nps = nps.reshape(-1).astype(np.float32)
+    b = bsi.Batch(n=np.full(G * E, N), psf_fwhm=torch.tensor(psf).cuda(), sigma=torch.tensor(sig).cuda(),
+                  pixel_scale=PS, n_exp=E, noise_ps=torch.tensor(nps).cuda())
+    p32 = u["params"].astype(np.float32)
+    ll, gr, st = bsi.loglik_grad(b, torch.tensor(data).cuda(), torch.tensor(p32).cuda())
+    ll, gr = ll.cpu().numpy(), gr.cpu().numpy()
+    assert ll.shape == (G,) and np.all(np.isfinite(ll)) and np.all(st.cpu().numpy() == 0)
+    for i in SAMPLED[:3]:
+        ds = [data[(i * E + j) * N * N:(i * E + j + 1) * N * N].reshape(N, N).astype(np.float64)
+              for j in range(E)]
+        f32 = [float(psf[i * E + j]) for j in range(E)]
+        s32 = [float(sig[i * E + j]) for j in range(E)]
+        pss = [np.ones((N, N)), ps1.astype(np.float32).astype(np.float64)]
+        p = p32[i].astype(np.float64)
+        rll, rg = render.loglik_grad_exposures(ds, p, N, PS, f32, s32, pss)
+        assert abs(ll[i] - rll) <= 1e-6 * abs(rll), (i, ll[i], rll)
+        sc = np.zeros(6)
+        for j in range(E):
+            _, dT = render.spectrum(p, N, PS, f32[j], derivs=True)
+            sc += np.array([np.sum(render.synthesize(dT[k], N) ** 2) for k in range(6)]) / s32[j] ** 2
+        assert np.all(np.abs(gr[i] - rg) <= 1e-4 * (np.abs(rg) + np.sqrt(sc))), (i, gr[i], rg)
