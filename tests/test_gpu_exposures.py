@@ -133,3 +133,46 @@ def test_hmc_exposures_parity(bsi, metric):
             U, _ = hmc.potential(gal, s[i, c, -1].astype(np.float64))
             assert abs(stats[i, c, 3] - U) <= 1e-6 * abs(U), (stats[i, c, 3], U)
     assert agree >= G * C * S - 2
+
+
+def test_nuts_exposures_parity(bsi):
+    """NUTS on galaxies seen in two exposures with correlated noise (the
+    general kernels' weighted form): chains follow the oracle's NUTS."""
+    import torch
+    from oracle import nuts
+    _log("exposures nuts parity")
+    rng = np.random.default_rng(95)
+    sizes, E, C, S = [25, 25], 2, 2, 4
+    p, n, psf, sig, ps, stamps = synth.exposure_population(rng, sizes, E, True)
+    G = len(sizes)
+    b, data = _upload(bsi, torch, n, psf, sig, ps, stamps, E)
+    ref = p[:, 4:6].copy()
+    init = np.empty((G, C, 6))
+    for i in range(G):
+        for c in range(C):
+            init[i, c] = [math.log10(p[i, 0]) + 0.01 * (c + 1), math.log10(p[i, 1]) - 0.01 * c,
+                          p[i, 2] + 0.02 * c, p[i, 3] - 0.01, 0.05 * c, -0.05]
+    cfg = bsi.HmcConfig(n_chains=C, n_warmup=0, n_samples=S, adapt=False, step_size=0.3, seed=17,
+                        metric=1, iters_per_launch=S, sampler=bsi.N.SAMPLER_NUTS, max_tree_depth=4)
+    s, stats, st = bsi.hmc_sample(b, data, torch.tensor(ref, dtype=torch.float32).cuda(),
+                                  torch.tensor(init, dtype=torch.float32).cuda(), cfg)
+    s = s.cpu().numpy()
+    agree = total = 0
+    for i in range(G):
+        sl = slice(i * E, (i + 1) * E)
+        gal = hmc.Exposures(datas=[m.astype(np.float32).astype(np.float64) for m in stamps[sl]],
+                            N=int(n[i * E]), pixel_scale=PS,
+                            psf_fwhm=[float(np.float32(x)) for x in psf[sl]],
+                            sigma=[float(np.float32(x)) for x in sig[sl]],
+                            noise_ps=[x.astype(np.float32).astype(np.float64) for x in ps[sl]],
+                            ref_xy=(float(np.float32(ref[i, 0])), float(np.float32(ref[i, 1]))))
+        for c in range(C):
+            th0 = init[i, c].astype(np.float32).astype(np.float64)
+            r = nuts.run_chain_nuts(hmc.galaxy_potential(gal), th0, 17, i * C + c, 0, S, 0.3,
+                                    max_depth=4, adapt=False, inv_mass=hmc.fisher_inv_mass(gal, th0))
+            for k in range(S):
+                total += 1
+                if np.max(np.abs(s[i, c, k] - r["samples"][k])) > 2e-4:
+                    break
+                agree += 1
+    assert agree >= total - 2, (agree, total)

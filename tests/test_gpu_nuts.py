@@ -104,3 +104,7 @@ def test_nuts_adaptation_and_invariance(bsi):
     cfg1 = bsi.HmcConfig(**{**cfg.__dict__, "uid_base": C})
     s1, _, _, _ = _run(bsi, torch, b1, data[off[1]:off[1] + N1 * N1], ref[1:2], init[1:2], cfg1, 1, C)
     assert np.array_equal(s1[0], s[1])
+    # the plain form (one galaxy, one transition per launch) and direct launches agree bitwise
+    for form in ({"form": bsi.N.FORM_PLAIN}, {"use_graph": False, "iters_per_launch": 7}):
+        sp, _, _, _ = _run(bsi, torch, b, data, ref, init, bsi.HmcConfig(**{**cfg.__dict__, **form}), G, C)
+        assert np.array_equal(sp, s), form
