@@ -7,7 +7,11 @@
  * (eq. interim-post with the pixel likelihood eq. likelihood-pixels and the
  * interim prior eq. interim-prior); phase 2 evaluates the Monte-Carlo shear
  * likelihood eq. likelihood-shear from the fixed interim samples, with the
- * shear Jacobian of eq. true-prior-jacobian-shear.
+ * shear Jacobian of eq. true-prior-jacobian-shear.  Beyond that path: the
+ * multiplicative and additive bias by shape-noise cancellation with
+ * bootstrap errors (Section 3.5), Spergel profiles (Appendix B), correlated
+ * noise and several exposures per galaxy (Appendix C), and the No-U-Turn
+ * sampler of Section 3.3 beside fixed-length HMC.
  *
  * Conventions for every call
  *   - Return value: BSI_OK (0) or a negative BSI_E* code.  Arguments are
@@ -26,8 +30,9 @@
  *     default stream).  A handle must be used from one host thread at a
  *     time.
  *   - Stamps: square N x N single-precision images stored row-major
- *     ([y][x]), packed back to back in one buffer; galaxy i starts at
- *     element off[i].  Pixel centres are at x_i = i - (N-1)/2 (same in y).
+ *     ([y][x]), packed back to back in one buffer; stamp i starts at
+ *     element off[i] (one stamp per galaxy unless bsi_batch.n_exp > 1).
+ *     Pixel centres are at x_i = i - (N-1)/2 (same in y).
  *   - Physical parameters (params): float[6] per galaxy =
  *     {flux F, half-light radius s [arcsec] of the circular pre-shear
  *      profile, e1, e2 (reduced-shear convention, eq. ellip-phi-transform),
@@ -138,8 +143,9 @@ typedef struct {
 #define BSI_MAX_EXPOSURES 16
 
 /*
- * bsi_render_stamps -- noiseless model stamps (Section 3.2: exponential
- * profile convolved with the known PSF, integrated over pixels), through the
+ * bsi_render_stamps -- noiseless model stamps (Section 3.2: the batch's
+ * profile -- exponential, Spergel or Gaussian -- sheared, convolved with the
+ * known Gaussian PSF and integrated over pixels), through the
  * handle's transform for each stamp side (bsi_set_transform).
  * The stamp is the truncated Fourier series on the stamp's frequency grid:
  *   m[j,i] = N^-2 sum_{u,v} w_u w_v T(u,v) exp(i(k_u x_i + k_v y_j)),
