@@ -886,6 +886,253 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
   lane0_sync();
 }
 
+// Two chains per wave (H = 2): the same transitions, each 32-lane half running
+// its own chain's tree as a step machine.  Every pass of the loop evaluates the
+// potential once for both halves (the evaluation is a whole-wave function);
+// before it each half starts a transition or a doubling as its own state
+// requires and takes the first half of a leapfrog step, after it the half does
+// its point's bookkeeping and ends its subtree or transition when due.  A half
+// whose transitions are done evaluates at its last position and discards the
+// result until the other half is done too.  The trees and the random streams
+// are those of advance_chain_nuts, so both forms give the same chains.
+template <int PROF, int P, int NFIX>
+__device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const LaneCols<2 * P>& lc,
+                                    const Prior& pr, ChainState* cs, NutsTree* tr,
+                                    float* samples_chain, float* trace_chain) {
+  constexpr int H = 2;
+  const int hl = chain_lane<H>();
+  const uint32_t uid = cs->uid;
+  float im[6], th[6], p[6], g[6], srho[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    im[j] = cs->inv_mass[j];
+    th[j] = cs->theta[j];
+    p[j] = 0.f;
+    g[j] = cs->grad[j];
+    srho[j] = 0.f;
+  }
+  int t = cs->t;
+  uint32_t status = cs->status;
+  int it = 0, phase = 0, d = 0, jl = 0, side = 0, depth = 0, n_lf = 0, n_leaf = 0;
+  bool active = (a.n_steps > 0 && t < c.t_stop);
+  bool diverged = false, moved = false;
+  double H0 = 0.0, U = 0.0;
+  float eps = 0.f, ve = 0.f, u_merge = 0.f, log_w = 0.f, sub_logw = 0.f, sum_alpha = 0.f;
+  uint4 wl = make_uint4(0u, 0u, 0u, 0u);
+  // evaluations needed at most: every transition builds fewer than 2^max_depth points
+  const int cap = a.n_steps * (1 << a.max_depth) + 2;
+  for (int pass = 0; pass < cap; ++pass) {
+    if (__ballot(active) == 0) break;
+    if (active && phase == 0) {            // start a transition
+      eps = cs->eps;
+      float z[6], u_acc, u_jit;
+      draw_iteration<H>(uid, (uint32_t)t, a.k0, a.k1, z, u_acc, u_jit);
+      double ke0 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        p[j] = z[j] * __builtin_amdgcn_rsqf(im[j]);
+        ke0 += (double)(im[j] * p[j] * p[j]);
+      }
+      H0 = cs->U + 0.5 * ke0;
+      wave_lds_sync();
+      if (hl < 12) {
+        const float v = hl < 6 ? pick6(p, hl) : cs->theta[hl - 6];
+        if (hl < 6) {
+          tr->ep[0][hl] = v;
+          tr->ep[1][hl] = v;
+          tr->rho[hl] = v;
+        } else {
+          tr->eth[0][hl - 6] = v;
+          tr->eth[1][hl - 6] = v;
+          tr->pth[hl - 6] = v;
+        }
+      } else if (hl < 18) {
+        const float v = cs->grad[hl - 12];
+        tr->eg[0][hl - 12] = v;
+        tr->eg[1][hl - 12] = v;
+        tr->pg[hl - 12] = v;
+      } else if (hl == 18) {
+        tr->eU[0] = cs->U;
+        tr->eU[1] = cs->U;
+        tr->pU = cs->U;
+      }
+      wave_lds_sync();
+      log_w = 0.f;
+      sum_alpha = 0.f;
+      n_lf = n_leaf = depth = 0;
+      d = 0;
+      diverged = moved = false;
+      phase = 1;
+    }
+    if (active && phase == 1) {            // start doubling d
+      const uint4 wd = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, (uint32_t)d), a.k0, a.k1);
+      side = (u01(wd.x) < 0.5f) ? 0 : 1;
+      ve = side ? eps : -eps;
+      u_merge = u01(wd.y);
+      U = tr->eU[side];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        th[j] = tr->eth[side][j];
+        p[j] = tr->ep[side][j];
+        g[j] = tr->eg[side][j];
+        srho[j] = 0.f;
+      }
+      sub_logw = -INFINITY;
+      jl = 0;
+      phase = 2;
+    }
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        p[j] -= 0.5f * ve * g[j];
+        th[j] += ve * im[j] * p[j];
+      }
+    }
+    uint32_t st = 0;
+    const double Un = potential<PROF, P, true, NFIX, 1, H>(c, lc, pr, th, g, st);
+    if (!active) continue;
+    U = Un;
+    if (t >= a.W) status |= st;
+    double ke = 0.0;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+      p[j] -= 0.5f * ve * g[j];
+      ke += (double)(im[j] * p[j] * p[j]);
+    }
+    const double dH = U + 0.5 * ke - H0;
+    ++n_lf;
+    const bool fin = isfinite(dH);
+    const float lw = -(float)dH;
+    sum_alpha += fin ? fminf(1.0f, __expf(lw)) : 0.0f;
+    bool end_sub = false, end_tr = false;
+    if (!(fin && dH <= kDivergence)) {
+      diverged = true;
+      if (t >= a.W) status |= fin ? 4u : 2u;
+      end_tr = true;
+    } else {
+      const float nl = log_add_expf(sub_logw, lw);
+      if ((n_leaf & 3) == 0)
+        wl = philox4x32_10(make_uint4(uid, (uint32_t)t, kTagNuts, 64u + (uint32_t)(n_leaf >> 2)), a.k0,
+                           a.k1);
+      const uint32_t wsel = (n_leaf & 3) == 0 ? wl.x : (n_leaf & 3) == 1 ? wl.y : (n_leaf & 3) == 2 ? wl.z : wl.w;
+      const bool take = __logf(u01(wsel)) < lw - nl;
+      sub_logw = nl;
+      ++n_leaf;
+      if (take) {
+        if (hl < 12) (&tr->sth[0])[hl] = hl < 6 ? pick6(th, hl) : pick6(g, hl - 6);
+        if (hl == 0) tr->sU = U;
+      }
+      for (int k = 1; k <= d; ++k) {
+        if ((jl & ((1 << k) - 1)) == 0 && hl < 12) {
+          if (hl < 6)
+            tr->ckp[k - 1][hl] = pick6(p, hl);
+          else
+            tr->ckr[k - 1][hl - 6] = pick6(srho, hl - 6);
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int j = 0; j < 6; ++j) srho[j] += p[j];
+      bool sub_turn = false;
+      for (int k = 1; k <= d && !sub_turn; ++k) {
+        if (((jl + 1) & ((1 << k) - 1)) == 0) {
+          float rb[6], pf[6];
+#pragma unroll
+          for (int j = 0; j < 6; ++j) {
+            rb[j] = srho[j] - tr->ckr[k - 1][j];
+            pf[j] = tr->ckp[k - 1][j];
+          }
+          sub_turn = u_turn(pf, p, rb, im);
+        }
+      }
+      ++jl;
+      if (sub_turn) end_tr = true;
+      else if (jl == (1 << d)) end_sub = true;
+    }
+    if (end_sub) {                          // merge the finished subtree
+      const bool merge = __logf(u_merge) < sub_logw - log_w;
+      log_w = log_add_expf(log_w, sub_logw);
+      wave_lds_sync();
+      if (hl < 12) {
+        if (merge) (&tr->pth[0])[hl] = (&tr->sth[0])[hl];   // pth, pg and sth, sg are adjacent
+        if (hl < 6) {
+          tr->rho[hl] += pick6(srho, hl);
+          tr->ep[side][hl] = pick6(p, hl);
+        } else {
+          tr->eth[side][hl - 6] = pick6(th, hl - 6);
+        }
+      } else if (hl < 18) {
+        tr->eg[side][hl - 12] = pick6(g, hl - 12);
+      } else if (hl == 18) {
+        if (merge) tr->pU = tr->sU;
+        tr->eU[side] = U;
+      }
+      wave_lds_sync();
+      moved |= merge;
+      depth = d + 1;
+      float pl[6], pr6[6], rh[6];
+#pragma unroll
+      for (int j = 0; j < 6; ++j) {
+        pl[j] = tr->ep[0][j];
+        pr6[j] = tr->ep[1][j];
+        rh[j] = tr->rho[j];
+      }
+      if (u_turn(pl, pr6, rh, im) || d + 1 == a.max_depth) {
+        end_tr = true;
+      } else {
+        d += 1;
+        phase = 1;
+      }
+    }
+    if (end_tr) {                           // the transition's outputs
+      const double alpha = (double)(sum_alpha / (float)max(n_lf, 1));
+      if (trace_chain && hl < 4) {
+        const float v = hl == 0 ? eps : hl == 1 ? (float)n_lf : hl == 2 ? (float)alpha : (float)depth;
+        trace_chain[(int64_t)t * 4 + hl] = v;
+      }
+      wave_lds_sync();
+      if (hl == 0) {
+        if (diverged && t >= a.W) cs->n_div += 1;
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+          cs->theta[j] = tr->pth[j];
+          cs->grad[j] = tr->pg[j];
+        }
+        cs->U = tr->pU;
+        if (t < a.W) {
+          if (a.adapt) {
+            const double m = (double)(t + 1);
+            const double eta = 1.0 / (m + kDaT0);
+            const double hbar = (1.0 - eta) * cs->hbar + eta * ((double)a.delta - alpha);
+            const double le = (double)a.mu - sqrt(m) / kDaGamma * hbar;
+            const double x = (double)exp2f(-(float)kDaKappa * log2f((float)m));   // m^-kappa
+            const double lbar = x * le + (1.0 - x) * cs->log_eps_bar;
+            cs->hbar = hbar;
+            cs->log_eps_bar = lbar;
+            cs->eps = (t == a.W - 1) ? (float)exp(lbar) : (float)exp(le);
+          }
+        } else {
+          cs->n_acc += moved ? 1 : 0;
+          cs->sum_alpha += (float)alpha;
+        }
+      }
+      wave_lds_sync();
+      if (t >= a.W && samples_chain && hl < 6)
+        samples_chain[(int64_t)(t - a.W) * 6 + hl] = cs->theta[hl];
+      t += 1;
+      it += 1;
+      phase = 0;
+      active = (it < a.n_steps && t < c.t_stop);
+    }
+  }
+  wave_lds_sync();
+  if (hl == 0) {
+    cs->t = t;
+    cs->status = status;
+  }
+  wave_lds_sync();
+}
+
 // Minimum resident waves per SIMD requested from the register allocator for
 // the trajectory kernel (occupancy against instruction-level parallelism).
 #ifndef BSI_HMC_WAVES_PER_EU
@@ -903,7 +1150,7 @@ template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, 
           bool NUTS = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
-  static_assert(!NUTS || (!INIT && W == 1 && H == 1), "NUTS: advance kernels, one wave per chain");
+  static_assert(!NUTS || (!INIT && W == 1 && (H == 1 || NFIX > 0)), "NUTS: advance kernels, W = 1");
   static_assert(!MX || (NFIX == 0 && W == 1 && H == 1), "exposures and noise weights: general kernels");
   static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
@@ -1005,7 +1252,9 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       // first writes the outputs
       float* sc = (a.samples && part == 0) ? a.samples + chain * (int64_t)a.S * 6 : nullptr;
       float* tc = (a.trace && part == 0) ? a.trace + chain * (int64_t)a.t_stop * 4 : nullptr;
-      if constexpr (NUTS)
+      if constexpr (NUTS && H == 2)
+        advance_chain_nuts2<PROF, P, NFIX>(a, c, lc, pr, l.cs, l.nuts + cw, sc, tc);
+      else if constexpr (NUTS)
         advance_chain_nuts<PROF, P, NFIX, MX>(a, c, lc, pr, l.cs, l.nuts + wave, sc, tc);
       else
         advance_chain<PROF, P, NFIX, W, H, MX>(a, c, lc, pr, l.cs, sc, tc);
@@ -1172,6 +1421,14 @@ template <int PROF>
 static bool launch_fixed_nuts(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 #define BSI_CASE(NN, PP)                                                                        \
   if (a.N == NN && a.P == PP) {                                                                 \
+    if constexpr (paired_chains_plan(NN, PP)) {                                                 \
+      if (hmc_chains_per_wave(a.N, a.C, a.P, a.prof, 1) == 2) {                                 \
+        auto k2 = hmc_kernel<PROF, false, PP, 256, NN, 1, 2, false, true>;                      \
+        (void)hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(k2, dim3(grid), dim3(kWave * a.C / 2), lds, s, a);                   \
+        return true;                                                                            \
+      }                                                                                         \
+    }                                                                                           \
     auto k = hmc_kernel<PROF, false, PP, 256, NN, 1, 1, false, true>;                           \
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
     hipLaunchKernelGGL(k, dim3(grid), dim3(kWave * a.C), lds, s, a);                            \
@@ -1236,7 +1493,8 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   if (a.nuts && (a.wpc != 1 || a.max_depth < 1 || a.max_depth > kNutsMaxDepth))
     return hipErrorInvalidValue;
   // two chains per wave exactly where launch_fixed_w launches them
-  const int H = (!INIT && !a.mx && !a.nuts && a.prof != kProfGauss && a.C * a.wpc <= 4)
+  // (NUTS too: launch_fixed_nuts takes the two-chain kernel by the same rule)
+  const int H = (!INIT && !a.mx && a.prof != kProfGauss && a.C * a.wpc <= 4)
                     ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
   const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, 1, a.n_exp, true, a.nuts)
                           : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H, 1, false, a.nuts);
