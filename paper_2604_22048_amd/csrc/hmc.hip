@@ -650,12 +650,13 @@ __device__ __forceinline__ float log_add_expf(float a, float b) {
   return m + __logf(1.0f + __expf(-fabsf(a - b)));
 }
 
-// Component `lane` of a 6-vector held by every lane (lanes 0..5).
-__device__ __forceinline__ float pick6(const float* v, int i) {
-  float r = v[0];
-#pragma unroll
-  for (int j = 1; j < 6; ++j) r = (i == j) ? v[j] : r;
-  return r;
+// A 6-vector held in registers (the same in every lane of the chain) stored
+// by one lane as three 8-byte writes (the LDS records' vectors are 8-aligned).
+__device__ __forceinline__ void store6(float* dst, const float* v) {
+  float2* d = reinterpret_cast<float2*>(dst);
+  d[0] = make_float2(v[0], v[1]);
+  d[1] = make_float2(v[2], v[3]);
+  d[2] = make_float2(v[4], v[5]);
 }
 
 __device__ __forceinline__ bool u_turn(const float* pa, const float* pb, const float* rho,
@@ -769,16 +770,17 @@ __device__ void advance_chain_nuts(const HmcArgs& a, const GalCtx& c, const Lane
         ++n_leaf;
         // the subtree candidate and the checkpoints of the blocks opening at this
         // point, one component per lane (lanes 0..11)
-        if (take) {
-          if (lane < 12) (&tr->sth[0])[lane] = lane < 6 ? pick6(th, lane) : pick6(g, lane - 6);
-          if (lane == 0) tr->sU = U;
-        }
-        for (int k = 1; k <= d; ++k) {
-          if ((jl & ((1 << k) - 1)) == 0 && lane < 12) {
-            if (lane < 6)
-              tr->ckp[k - 1][lane] = pick6(p, lane);
-            else
-              tr->ckr[k - 1][lane - 6] = pick6(srho, lane - 6);
+        if (lane == 0) {
+          if (take) {
+            store6(tr->sth, th);
+            store6(tr->sg, g);
+            tr->sU = U;
+          }
+          for (int k = 1; k <= d; ++k) {
+            if ((jl & ((1 << k) - 1)) == 0) {
+              store6(tr->ckp[k - 1], p);
+              store6(tr->ckr[k - 1], srho);
+            }
           }
         }
         lane0_sync();
@@ -935,18 +937,17 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
       }
       H0 = cs->U + 0.5 * ke0;
       wave_lds_sync();
-      if (hl < 12) {
-        const float v = hl < 6 ? pick6(p, hl) : cs->theta[hl - 6];
-        if (hl < 6) {
-          tr->ep[0][hl] = v;
-          tr->ep[1][hl] = v;
-          tr->rho[hl] = v;
-        } else {
-          tr->eth[0][hl - 6] = v;
-          tr->eth[1][hl - 6] = v;
-          tr->pth[hl - 6] = v;
-        }
-      } else if (hl < 18) {
+      if (hl == 0) {
+        store6(tr->ep[0], p);
+        store6(tr->ep[1], p);
+        store6(tr->rho, p);
+      }
+      if (hl >= 6 && hl < 12) {
+        const float v = cs->theta[hl - 6];
+        tr->eth[0][hl - 6] = v;
+        tr->eth[1][hl - 6] = v;
+        tr->pth[hl - 6] = v;
+      } else if (hl >= 12 && hl < 18) {
         const float v = cs->grad[hl - 12];
         tr->eg[0][hl - 12] = v;
         tr->eg[1][hl - 12] = v;
@@ -1018,16 +1019,17 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
       const bool take = __logf(u01(wsel)) < lw - nl;
       sub_logw = nl;
       ++n_leaf;
-      if (take) {
-        if (hl < 12) (&tr->sth[0])[hl] = hl < 6 ? pick6(th, hl) : pick6(g, hl - 6);
-        if (hl == 0) tr->sU = U;
-      }
-      for (int k = 1; k <= d; ++k) {
-        if ((jl & ((1 << k) - 1)) == 0 && hl < 12) {
-          if (hl < 6)
-            tr->ckp[k - 1][hl] = pick6(p, hl);
-          else
-            tr->ckr[k - 1][hl - 6] = pick6(srho, hl - 6);
+      if (hl == 0) {
+        if (take) {
+          store6(tr->sth, th);
+          store6(tr->sg, g);
+          tr->sU = U;
+        }
+        for (int k = 1; k <= d; ++k) {
+          if ((jl & ((1 << k) - 1)) == 0) {
+            store6(tr->ckp[k - 1], p);
+            store6(tr->ckr[k - 1], srho);
+          }
         }
       }
       wave_lds_sync();
@@ -1053,17 +1055,15 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
       const bool merge = __logf(u_merge) < sub_logw - log_w;
       log_w = log_add_expf(log_w, sub_logw);
       wave_lds_sync();
-      if (hl < 12) {
-        if (merge) (&tr->pth[0])[hl] = (&tr->sth[0])[hl];   // pth, pg and sth, sg are adjacent
-        if (hl < 6) {
-          tr->rho[hl] += pick6(srho, hl);
-          tr->ep[side][hl] = pick6(p, hl);
-        } else {
-          tr->eth[side][hl - 6] = pick6(th, hl - 6);
-        }
-      } else if (hl < 18) {
-        tr->eg[side][hl - 12] = pick6(g, hl - 12);
-      } else if (hl == 18) {
+      if (merge && hl < 12) (&tr->pth[0])[hl] = (&tr->sth[0])[hl];   // pth, pg and sth, sg are adjacent
+      if (hl == 0) {
+        float r6[6];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) r6[j] = tr->rho[j] + srho[j];
+        store6(tr->rho, r6);
+        store6(tr->ep[side], p);
+        store6(tr->eth[side], th);
+        store6(tr->eg[side], g);
         if (merge) tr->pU = tr->sU;
         tr->eU[side] = U;
       }
