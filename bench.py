@@ -543,7 +543,7 @@ def exposures_leg(api, torch, stream, n_gal, E, log):
     each seen in E exposures with their own PSF FWHM ~ U(0.6", 0.9"), noise
     sigma ~ U(0.8, 1.2) and stationary correlated noise (exposure j: a 3 x 3
     correlation kernel shared by all galaxies), sampled with the headline
-    settings on the general kernels."""
+    settings on the 53-pixel kernels (default plan, two chains per wave)."""
     cfg = gen.CONFIGS["uniform"]
     dev = torch.device("cuda:0")
     N = cfg.n_pix

@@ -38,6 +38,7 @@ enclosed flux 1 - x^(nu+1) K_(nu+1)(x) / (2^nu Gamma(nu + 1)) equal to 1/2).
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 # Half-light radius of exp(-r/r0) in units of r0: the root of
 # (1 + eta) exp(-eta) = 1/2 (enclosed-flux fraction of an exponential disk).
@@ -281,13 +282,35 @@ def covariance_matrix(noise_ps, sigma):
     return sigma * sigma * c[dy, dx]
 
 
+_COV_FACTORS: dict = {}
+
+
+def _cov_factor(noise_ps, sigma):
+    """Cholesky factor of covariance_matrix(noise_ps, sigma) (symmetric
+    positive definite), kept for the last few (noise_ps, sigma) pairs so that
+    a chain's evaluations factor each exposure's N^2 x N^2 matrix once."""
+    ps = np.ascontiguousarray(noise_ps, dtype=np.float64)
+    key = (ps.shape, ps.tobytes(), float(sigma))
+    f = _COV_FACTORS.get(key)
+    if f is None:
+        if len(_COV_FACTORS) >= 4:
+            _COV_FACTORS.pop(next(iter(_COV_FACTORS)))
+        f = scipy.linalg.cho_factor(covariance_matrix(ps, sigma), lower=True)
+        _COV_FACTORS[key] = f
+    return f
+
+
+def cov_solve(noise_ps, sigma, r):
+    """Sigma^-1 r with the explicit covariance (a Cholesky solve)."""
+    return scipy.linalg.cho_solve(_cov_factor(noise_ps, sigma), r)
+
+
 def loglik_grad_cov(data, params, N, pixel_scale, psf_fwhm, sigma, noise_ps, profile=PROFILE_EXP):
     """eq. covar-pixel-likelihood (C = 0) and its gradient by forward mode:
     d log L / dp = (dm/dp)^T Sigma^-1 (d - m)."""
     T, dT = spectrum(params, N, pixel_scale, psf_fwhm, profile, derivs=True)
     r = (np.asarray(data, dtype=np.float64) - synthesize(T, N)).ravel()
-    S = covariance_matrix(noise_ps, sigma)
-    y = np.linalg.solve(S, r)
+    y = cov_solve(noise_ps, sigma, r)
     ll = -0.5 * float(r @ y)
     g = np.array([synthesize(dT[j], N).ravel() @ y for j in range(6)])
     return ll, g
@@ -313,8 +336,7 @@ def fisher_diag_exposures(params, N, pixel_scale, psfs, sigmas, noise_pss=None, 
     for j in range(len(psfs)):
         ps = np.ones((N, N)) if noise_pss is None else noise_pss[j]
         _, dT = spectrum(params, N, pixel_scale, psfs[j], profile, derivs=True)
-        S = covariance_matrix(ps, sigmas[j])
         for i in range(6):
             dm = synthesize(dT[i], N).ravel()
-            f[i] += dm @ np.linalg.solve(S, dm)
+            f[i] += dm @ cov_solve(ps, sigmas[j], dm)
     return f

@@ -137,7 +137,7 @@ struct HmcArgs {
 constexpr int kNutsMaxDepth = 10;
 
 // LDS bytes of the trajectory kernel: C chains, W waves per chain, H chains per
-// wave; E exposures and sqrt-weights (mx) for the general kernels' MX form.
+// wave; E exposures and sqrt-weights (mx) for the kernels' MX form.
 size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1, int E = 1, bool mx = false,
                      bool nuts = false);
 // Waves per chain for stamp side N, C chains and plan P when up to max_w are
@@ -150,6 +150,10 @@ int hmc_split_waves(int N, int C, int P, int prof, int max_w);
 // exponential or Spergel profile and a plan whose specialised two-chain kernel is the
 // faster one (25: P 3, 41: P 1, 53: P 3); else 1.
 int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc);
+// Whether the advance kernel with exposures / noise weights (mx) runs on the
+// kernels specialised for stamp side N: one wave per chain, the exponential or
+// Spergel profile and P N's default plan with a specialised kernel.
+bool hmc_mx_fixed(int N, int P, int prof, int wpc);
 // Slot plans with a trajectory kernel specialised for stamp side N (0-terminated list of P).
 const int* hmc_fixed_plans(int N);
 hipError_t launch_hmc_init(const HmcArgs& a, int grid, hipStream_t s);

@@ -1142,8 +1142,9 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
 // W > 1: each chain is evaluated by W waves (split evaluation; advance only).
 // H = 2: two chains per wave (lanes 0..31 and 32..63; advance only, C even).
-// MX: several exposures per galaxy and/or per-bin noise weights (general
-// kernels, one wave per chain).
+// MX: several exposures per galaxy and/or per-bin noise weights (advance
+// kernels of either form with one wave per chain or two chains per wave; the
+// chain start runs on the general kernels).
 // NUTS: No-U-Turn transitions instead of fixed-length trajectories (general
 // kernels, one wave per chain, advance only).
 template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false,
@@ -1151,7 +1152,7 @@ template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, 
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
   static_assert(!NUTS || (!INIT && W == 1 && (H == 1 || NFIX > 0)), "NUTS: advance kernels, W = 1");
-  static_assert(!MX || (NFIX == 0 && W == 1 && H == 1), "exposures and noise weights: general kernels");
+  static_assert(!MX || (W == 1 && (NFIX == 0 || !INIT)), "exposures and noise weights: no split evaluation");
   static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
@@ -1317,7 +1318,7 @@ static void launch_p(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
     }
   }
   if constexpr (MX) {
-    auto k = hmc_kernel<PROF, INIT, P, 256, 0, 1, 1, true>;   // C <= 4 (checked by the caller)
+    auto k = hmc_kernel<PROF, INIT, P, 256, NFIX, 1, H, true>;   // C <= 4 (checked by the caller)
     (void)hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k, dim3(grid), blk, lds, s, a);
   } else if (a.C * W <= 4) {
@@ -1373,6 +1374,38 @@ static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s
   return false;
 }
 
+// Chains per wave of an advance launch.  With noise weights (mx) two chains
+// per wave only for a single exposure on the specialised kernels: with
+// several, the two-chain kernels keep too much live across the exposure loop
+// (they spill) and one chain per wave is the faster form.
+static int launch_chains_per_wave(const HmcArgs& a, bool init) {
+  if (init || a.prof == kProfGauss || a.C * a.wpc > 4) return 1;
+  if (a.mx && (a.nuts || a.n_exp != 1 || !hmc_mx_fixed(a.N, a.P, a.prof, a.wpc))) return 1;
+  return hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc);
+}
+
+// Several exposures / noise weights on the specialised kernels of the
+// default plan of each size.
+template <int PROF>
+static bool launch_fixed_mx(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
+#define BSI_CASE(NN, PP)                                                         \
+  if (a.N == NN && a.P == PP) {                                                  \
+    if constexpr (make_slot_plan(NN).P == PP) {                                  \
+      if constexpr (paired_chains_plan(NN, PP)) {                                \
+        if (launch_chains_per_wave(a, false) == 2) {                             \
+          launch_p<PROF, false, PP, NN, 1, 2, true>(a, grid, lds, s);            \
+          return true;                                                           \
+        }                                                                        \
+      }                                                                          \
+      launch_p<PROF, false, PP, NN, 1, 1, true>(a, grid, lds, s);                \
+      return true;                                                               \
+    }                                                                            \
+  }
+  BSI_FIXED_PLANS(BSI_CASE)
+#undef BSI_CASE
+  return false;
+}
+
 template <int PROF>
 static bool launch_fixed(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 #define BSI_CASE(NN, PP) \
@@ -1401,6 +1434,13 @@ int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc) {
   if (wpc != 1 || (C & 1) || C > 4 || prof == kProfGauss) return 1;
   return paired_chains_plan(N, P) ? 2 : 1;
 #endif
+}
+
+bool hmc_mx_fixed(int N, int P, int prof, int wpc) {
+  if (wpc != 1 || prof == kProfGauss || P != make_slot_plan(N).P) return false;
+  for (const int* p = hmc_fixed_plans(N); *p; ++p)
+    if (*p == P) return true;
+  return false;
 }
 
 const int* hmc_fixed_plans(int N) {
@@ -1456,6 +1496,9 @@ static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
     return;
   }
   if (a.mx) {
+    if constexpr (!INIT && PROF != kProfGauss)
+      if (!a.nuts && hmc_mx_fixed(a.N, a.P, a.prof, a.wpc) && launch_fixed_mx<PROF>(a, grid, lds, s))
+        return;
     switch (a.P) {
       case 1: launch_p<PROF, INIT, 1, 0, 1, 1, true>(a, grid, lds, s); break;
       case 2: launch_p<PROF, INIT, 2, 0, 1, 1, true>(a, grid, lds, s); break;
@@ -1492,11 +1535,10 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   // NUTS: general kernels, one wave per chain
   if (a.nuts && (a.wpc != 1 || a.max_depth < 1 || a.max_depth > kNutsMaxDepth))
     return hipErrorInvalidValue;
-  // two chains per wave exactly where launch_fixed_w launches them
-  // (NUTS too: launch_fixed_nuts takes the two-chain kernel by the same rule)
-  const int H = (!INIT && !a.mx && a.prof != kProfGauss && a.C * a.wpc <= 4)
-                    ? hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) : 1;
-  const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, 1, a.n_exp, true, a.nuts)
+  // two chains per wave exactly where launch_fixed_w, launch_fixed_nuts and
+  // launch_fixed_mx launch them
+  const int H = launch_chains_per_wave(a, INIT);
+  const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, H, a.n_exp, true, a.nuts)
                           : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H, 1, false, a.nuts);
   if (a.prof == kProfExp)
     launch_prof<kProfExp, INIT>(a, grid, lds, s);

@@ -378,8 +378,9 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
 // pair-slots l, l + 32, ..., i.e. 2 P pair-iterations per super-row, and the
 // sums are reduced per half.
 //
-// CORR (general kernels only): sqw holds sqrt w per bin in the data
-// spectrum's order (pair-slot order, then the Nyquist bins).
+// CORR (one wave per chain or two chains per wave; not with a split
+// evaluation): sqw holds sqrt w per bin in the data spectrum's order
+// (pair-slot order, then the Nyquist bins).
 template <int PROF, int P, bool RESID = false, bool CHI2 = true, int NFIX = 0, int W = 1, int H = 1,
           bool CORR = false>
 __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P * H>& lc,
@@ -387,7 +388,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
                              const float2* Yf, const Shape& sh, float* red, int part = 0,
                              float* xch = nullptr, const float* __restrict__ sqw = nullptr) {
   static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
-  static_assert(!CORR || NFIX == 0, "noise weights: general kernels only");
+  static_assert(!CORR || W == 1, "noise weights: not with a split evaluation");
   static_assert(H == 1 || (NFIX > 0 && W == 1), "two chains per wave need a specialised kernel");
   constexpr int PI = P * H;           // pair-iterations per super-row of this lane
   constexpr int LS = kWave / H;       // lanes per chain
@@ -419,6 +420,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     constexpr int K = (spc.nsr + W - 1) / W;   // super-rows of this wave (at most)
     // this wave's super-rows are part + k W, k = 0..K-1 (the last may not exist)
     const float4* dq = dp + part * P * 64;
+    const float2* wq = CORR ? reinterpret_cast<const float2*>(sqw) + lane : nullptr;
     const float4* yq[PI];
 #pragma unroll
     for (int i = 0; i < PI; ++i) yq[i] = yp[i] + part * spc.R;
@@ -427,6 +429,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
       // arithmetic of the current one
       float4 Dn = dq[0];
       float4 yn = yq[0][0];
+      float2 wn = CORR ? wq[0] : float2{1.f, 1.f};
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         float c2 = 0.f;
@@ -434,14 +437,16 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         for (int i = 0; i < PI; ++i) {
           const float4 D = Dn;
           const float4 y = yn;
+          const float2 w = wn;
           const int b = k * PI + i + 1;         // next pair-slot of this lane
           if (b < K * PI) {
             Dn = dq[b * LS];
             yn = yq[b % PI][(b / PI) * spc.R];
+            if constexpr (CORR) wn = wq[b * LS];
           }
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
-          pair_step<PROF, RESID>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
-                                 sdc[i], sdy, CHI2);
+          pair_step<PROF, RESID, CORR>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy,
+                                       wky[i], sdc[i], sdy, CHI2, w);
         }
         if (CHI2) chi2 += (double)c2;
       }

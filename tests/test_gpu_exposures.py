@@ -91,14 +91,22 @@ def _compare_chain(gpu, ora, tol=1e-4):
     return n_ok
 
 
+# (sizes, chains, exposures): the size-specialised kernels with two chains per
+# wave (one exposure with correlated noise, 25 and 41 with C = 2) and one chain
+# per wave (several exposures: 25 with C = 2; odd C: 32 and 41 with C = 3),
+# and the general kernels (30 has no specialised kernel)
+KERNEL_FORMS = [([25, 41], 2, 1), ([25, 25], 2, 2), ([32, 41], 3, 2), ([30, 30], 2, 2)]
+
+
+@pytest.mark.parametrize("sizes,C,E", KERNEL_FORMS)
 @pytest.mark.parametrize("metric", [0, 1])
-def test_hmc_exposures_parity(bsi, metric):
-    """Two exposures with correlated noise per galaxy: chains follow the
-    oracle's under the same Philox momenta (given metric and Fisher metric)."""
+def test_hmc_exposures_parity(bsi, metric, sizes, C, E):
+    """Exposures with correlated noise per galaxy: chains follow the oracle's
+    under the same Philox momenta (given metric and Fisher metric)."""
     import torch
-    _log(f"exposures hmc parity metric={metric}")
-    rng = np.random.default_rng(90 + metric)
-    sizes, E, C, S = [25, 25], 2, 2, 4
+    _log(f"exposures hmc parity metric={metric} sizes={sizes} C={C} E={E}")
+    rng = np.random.default_rng(90 + metric + sizes[-1] + 7 * E)
+    S = 4
     p, n, psf, sig, ps, stamps = synth.exposure_population(rng, sizes, E, True)
     G = len(sizes)
     b, data = _upload(bsi, torch, n, psf, sig, ps, stamps, E)

@@ -249,15 +249,12 @@ def test_uniform_full_spergel_hmc_sampled(bsi, uniform):
     assert agree >= 3 * C * S - 2
 
 
-def test_exposures_full_loglik_sampled(bsi, uniform):
-    """10,000 galaxies x 2 exposures (Appendix C) in one call: exposure 0 the
-    workload's stamp with white noise, exposure 1 the same stamp plus
-    correlated noise, its own PSF and noise power; sampled galaxies' log L
-    and gradient against the oracle's explicit-covariance likelihood."""
-    import torch
-    u = uniform
+def _two_exposures(bsi, torch, u, E=2):
+    """The uniform workload's galaxies seen twice: exposure 0 the workload's
+    stamp with white noise, exposure 1 the same stamp plus correlated noise,
+    its own PSF (15 % wider) and noise power.  E = 1: exposure 1 alone."""
     t = u["t"]
-    G, E, N = len(t), 2, 53
+    G, N = len(t), 53
     rng = np.random.default_rng(5)
     ps1, kap = synth.noise_kernel_ps(rng, N)
     st0 = u["data"].reshape(G, N * N)
@@ -267,8 +264,23 @@ def test_exposures_full_loglik_sampled(bsi, uniform):
     sig = np.stack([t.sigma, np.hypot(t.sigma, 0.7)], axis=1).reshape(-1).astype(np.float32)
     nps = np.stack([np.ones((G, N * N)), np.broadcast_to(ps1.ravel(), (G, N * N))], axis=1)
     nps = nps.reshape(-1).astype(np.float32)
+    if E == 1:
+        data, psf, sig = (x.reshape(G, 2, -1)[:, 1].reshape(-1) for x in (data, psf, sig))
+        nps = nps.reshape(G, 2, -1)[:, 1].reshape(-1)
     b = bsi.Batch(n=np.full(G * E, N), psf_fwhm=torch.tensor(psf).cuda(), sigma=torch.tensor(sig).cuda(),
                   pixel_scale=PS, n_exp=E, noise_ps=torch.tensor(nps).cuda())
+    return b, data, psf, sig, ps1
+
+
+def test_exposures_full_loglik_sampled(bsi, uniform):
+    """10,000 galaxies x 2 exposures (Appendix C) in one call: exposure 0 the
+    workload's stamp with white noise, exposure 1 the same stamp plus
+    correlated noise, its own PSF and noise power; sampled galaxies' log L
+    and gradient against the oracle's explicit-covariance likelihood."""
+    import torch
+    u = uniform
+    G, E, N = len(u["t"]), 2, 53
+    b, data, psf, sig, ps1 = _two_exposures(bsi, torch, u)
     p32 = u["params"].astype(np.float32)
     ll, gr, st = bsi.loglik_grad(b, torch.tensor(data).cuda(), torch.tensor(p32).cuda())
     ll, gr = ll.cpu().numpy(), gr.cpu().numpy()
@@ -287,3 +299,46 @@ def test_exposures_full_loglik_sampled(bsi, uniform):
             _, dT = render.spectrum(p, N, PS, f32[j], derivs=True)
             sc += np.array([np.sum(render.synthesize(dT[k], N) ** 2) for k in range(6)]) / s32[j] ** 2
         assert np.all(np.abs(gr[i] - rg) <= 1e-4 * (np.abs(rg) + np.sqrt(sc))), (i, gr[i], rg)
+
+
+@pytest.mark.parametrize("E", [1, 2])
+def test_exposures_full_hmc_sampled(bsi, uniform, E):
+    """The 10,000 galaxies seen in E exposures (E = 1: the correlated-noise
+    exposure alone) sampled in the benchmark's launch configuration (4 chains,
+    the 53-pixel kernels: two chains per wave for E = 1, one for E = 2;
+    graph-replayed): every chain of sampled galaxies follows the oracle's."""
+    import torch
+    u = uniform
+    G, N = len(u["t"]), 53
+    C, L, S = 4, 20, 3
+    b, data, psf, sig, ps1 = _two_exposures(bsi, torch, u, E)
+    cfg = bsi.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False, metric=1,
+                        step_size=0.3, jitter=0.2, seed=41, use_graph=True)
+    init_t = torch.tensor(u["init"], dtype=torch.float32).cuda()
+    smp, stats, status = bsi.hmc_sample(b, torch.tensor(data).cuda(), u["ref"], init_t, cfg)
+    smp = smp.cpu().numpy()
+    assert smp.shape == (G, C, S, 6) and np.all(np.isfinite(smp))
+    ref = u["ref"].cpu().numpy()
+    agree = 0
+    pairs = [(i, c) for i in SAMPLED[:3] for c in range(C)]
+    for i, c in pairs:
+        sl = slice(i * E, (i + 1) * E)
+        gal = hmc.Exposures(
+            datas=[data[(i * E + j) * N * N:(i * E + j + 1) * N * N].reshape(N, N).astype(np.float64)
+                   for j in range(E)],
+            N=N, pixel_scale=PS, psf_fwhm=[float(x) for x in psf[sl]], sigma=[float(x) for x in sig[sl]],
+            noise_ps=[np.ones((N, N)), ps1.astype(np.float32).astype(np.float64)][2 - E:],
+            ref_xy=(float(ref[i, 0]), float(ref[i, 1])))
+        th0 = u["init"][i, c].astype(np.float32).astype(np.float64)
+        im = hmc.fisher_inv_mass(gal, th0)
+        r = hmc.run_chain(hmc.galaxy_potential(gal), th0, 41, i * C + c, L, 0, S, 0.3,
+                          adapt=False, inv_mass=im, jitter=0.2)
+        for k in range(S):
+            d = np.max(np.abs(smp[i, c, k] - r["samples"][k]))
+            if d > 2e-4:
+                moved_g = k == 0 or np.any(smp[i, c, k] != smp[i, c, k - 1])
+                moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+                assert moved_g != moved_o, (i, c, k, d)
+                break
+            agree += 1
+    assert agree >= len(pairs) * S - 2
