@@ -438,21 +438,28 @@ def spergel_leg(api, torch, stream, n_gal, nu, log=None):
             "status_nonzero": int((status != 0).sum())}
 
 
-def bias_leg(api, torch, stream, n_gal, n_boot, log):
+def bias_leg(api, torch, stream, n_gal, n_boot, log, sampler="hmc", depth=5):
     """Multiplicative and additive shear bias by shape-noise cancellation with
     bootstrap errors (Section 3.5; Table 2's all-fixed setting): the uniform
     workload's galaxies and noise sheared by +g and by -g, every property
-    sampled (4 chains, 20 leapfrog steps, 300 warmup + 1000 draws), the shear
-    phase with the population parameters at their true values on a 33 x 33 grid
-    of g around each dataset's shear (K = 1000: every 4th draw), n_boot
-    resamples of the galaxies."""
+    sampled (4 chains, 300 warmup + 1000 draws; fixed-length HMC with 20
+    leapfrog steps, or NUTS of the given maximum tree depth with all
+    transitions in one launch), the shear phase with the population parameters
+    at their true values on a 33 x 33 grid of g around each dataset's shear
+    (K = 1000: every 4th draw), n_boot resamples of the galaxies."""
     import math
     cfg = gen.CONFIGS["uniform"]
     dev = torch.device("cuda:0")
     C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
-    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
-                         metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
-                         use_graph=True, seed=gen.chain_seed(cfg.index))
+    if sampler == "nuts":
+        hcfg = api.HmcConfig(n_chains=C, n_warmup=W, n_samples=S, adapt=True,
+                             metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8,
+                             iters_per_launch=W + S, use_graph=True, seed=gen.chain_seed(cfg.index),
+                             sampler=api.N.SAMPLER_NUTS, max_tree_depth=depth)
+    else:
+        hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
+                             metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
+                             use_graph=True, seed=gen.chain_seed(cfg.index))
     g_abs = cfg.g_true[0]
     mu_f, sd_f = gen.flux_lognormal(*cfg.snr, cfg.sigma)
     tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True, flux_term=True, mu_ln_f=mu_f,
@@ -486,7 +493,7 @@ def bias_leg(api, torch, stream, n_gal, n_boot, log):
     P = n1 * n1
     boot_flop = 2.0 * (n_boot + 1) * 2 * P * n_gal
     total = sum(t_hmc) + sum(t_ell) + t_boot
-    return {"n_gal": n_gal, "n_boot": n_boot, "grid": f"{n1}x{n1}", "K": K,
+    return {"n_gal": n_gal, "n_boot": n_boot, "grid": f"{n1}x{n1}", "K": K, "sampler": sampler,
             "m": float(st[0]), "c": float(st[1]), "m_err_3sigma": 3 * float(st[2]),
             "c_err_3sigma": 3 * float(st[3]),
             "t_hmc_s": [round(x, 4) for x in t_hmc], "t_shear_table_s": [round(x, 4) for x in t_ell],
@@ -615,7 +622,9 @@ def main():
     ap.add_argument("--serve-window", type=float, default=8.0, help="seconds of request arrivals")
     ap.add_argument("--n-boot", type=int, default=500, help="--workload bias: bootstrap resamples")
     ap.add_argument("--n-exp", type=int, default=4, help="--workload exposures: exposures per galaxy")
-    ap.add_argument("--depth", type=int, default=5, help="--workload nuts: maximum tree depth")
+    ap.add_argument("--depth", type=int, default=5, help="--workload nuts / bias: maximum tree depth")
+    ap.add_argument("--sampler", choices=["hmc", "nuts"], default="hmc",
+                    help="--workload bias: per-galaxy sampler")
     ap.add_argument("--ipl", type=int, default=0,
                     help="--workload nuts: transitions per launch (0: all in one launch)")
     ap.add_argument("--spergel-nu", type=float, default=-0.6,
@@ -680,13 +689,13 @@ def main():
                                           "leapfrog steps, 300 warmup + 1000 draws"}, **res}
         elif args.workload == "bias":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
-            res = bias_leg(api, torch, stream, G, args.n_boot, log)
+            res = bias_leg(api, torch, stream, G, args.n_boot, log, args.sampler, args.depth)
             out = {"metric": "m/c bias study by shape-noise cancellation (galaxy pairs/s, end to end)",
                    "value": res["galaxy_pairs_per_s"], "unit": "galaxy pairs/s", "n_gpus": 1,
                    "higher_is_better": True, "dtype": "f32+f64", "data": "synthetic",
                    "config": {"workload": f"{G} 53-pixel galaxies sheared by +-(0.02, 0), same noise; "
-                                          "4 chains x (300 + 1000), K = 1000, 33 x 33 grid, "
-                                          f"{args.n_boot} bootstrap resamples"}, **res}
+                                          f"{args.sampler.upper()}, 4 chains x (300 + 1000), K = 1000, "
+                                          f"33 x 33 grid, {args.n_boot} bootstrap resamples"}, **res}
         elif args.workload == "spergel":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
             res = spergel_leg(api, torch, stream, G, args.spergel_nu, log)
