@@ -234,7 +234,9 @@ typedef struct {
                                 criterion at every node of the trajectory's binary tree,
                                 divergence at H - H0 > 1000); n_leapfrog, jitter and
                                 waves_per_chain are ignored; iters_per_launch counts
-                                transitions; each chain is one wave of the general kernels,
+                                transitions; each chain runs on its own wave (with an even
+                                n_chains on the 25-, 41- and 53-pixel kernels of the default
+                                plans: its own half-wave, stepping its tree independently),
                                 so chains of different trajectory lengths do not wait for
                                 each other (a galaxy's workgroup ends with its slowest
                                 chain); trace rows hold {step size, leapfrog steps,
@@ -260,8 +262,9 @@ typedef struct {
  * which other galaxies share the call.
  * With n_exp > 1 or noise_ps the potential uses the likelihood of
  * bsi_loglik_grad's Appendix C form (and the Fisher metric its weighted
- * curvature); those batches run on the general kernels with one wave per
- * chain (waves_per_chain ignored) and need n_chains <= 4.
+ * curvature); those batches ignore waves_per_chain (one wave per chain, or two
+ * chains per wave for a single exposure on the kernels specialised per stamp
+ * size) and need n_chains <= 4.
  */
 int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, const float* ref_xy,
                    const float* inv_mass, const float* init, const bsi_interim* interim,

@@ -121,7 +121,7 @@ struct HmcArgs {
   int n_steps;            // leapfrog steps to advance in this launch
   int t_stop;             // iteration at which a chain stops (W + S)
   const int32_t* t_stop_gal;  // [gal] per-galaxy stop (<= t_stop) or NULL (advance kernel only)
-  // several exposures / correlated noise (general kernels, mx = 1): galaxy
+  // several exposures / correlated noise (mx = 1): galaxy
   // gal's exposures are the stamps gal * n_exp + j (psf, sigma and bin_off
   // are indexed by stamp), sqw holds sqrt w per bin beside dh, noise_ps the
   // DFT-mode noise powers at off[stamp] (NULL: white; Fisher metric only)
@@ -129,7 +129,7 @@ struct HmcArgs {
   const float* sqw;
   const float* noise_ps;
   const int64_t* off;
-  // NUTS (general kernels, one wave per chain): n_steps counts transitions
+  // NUTS (one wave or half-wave per chain): n_steps counts transitions
   int nuts, max_depth;
 };
 

@@ -1145,8 +1145,9 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 // MX: several exposures per galaxy and/or per-bin noise weights (advance
 // kernels of either form with one wave per chain or two chains per wave; the
 // chain start runs on the general kernels).
-// NUTS: No-U-Turn transitions instead of fixed-length trajectories (general
-// kernels, one wave per chain, advance only).
+// NUTS: No-U-Turn transitions instead of fixed-length trajectories (advance
+// only; one wave per chain, or two chains per wave on the specialised kernels
+// of the paired plans; with MX the general kernels).
 template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false,
           bool NUTS = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
@@ -1530,9 +1531,9 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   // split chains only where a specialised kernel exists (hmc_split_waves)
   if (a.wpc != 1 && (INIT || a.wpc != hmc_split_waves(a.N, a.C, a.P, a.prof, a.wpc)))
     return hipErrorInvalidValue;
-  // exposures / noise weights: general kernels, one wave per chain, C <= 4
+  // exposures / noise weights: no split evaluation, C <= 4
   if (a.mx && (a.wpc != 1 || a.C > 4 || a.n_exp < 1 || !a.sqw)) return hipErrorInvalidValue;
-  // NUTS: general kernels, one wave per chain
+  // NUTS: no split evaluation
   if (a.nuts && (a.wpc != 1 || a.max_depth < 1 || a.max_depth > kNutsMaxDepth))
     return hipErrorInvalidValue;
   // two chains per wave exactly where launch_fixed_w, launch_fixed_nuts and
