@@ -545,12 +545,13 @@ def nuts_leg(api, torch, stream, n_gal, depth, ipl, log):
             "status_nonzero": int((status != 0).sum())}
 
 
-def exposures_leg(api, torch, stream, n_gal, E, log):
+def exposures_leg(api, torch, stream, n_gal, E, log, sampler="hmc", depth=5):
     """Appendix C likelihood: the uniform workload's galaxies (53-pixel stamps)
     each seen in E exposures with their own PSF FWHM ~ U(0.6", 0.9"), noise
     sigma ~ U(0.8, 1.2) and stationary correlated noise (exposure j: a 3 x 3
     correlation kernel shared by all galaxies), sampled with the headline
-    settings on the 53-pixel kernels (default plan, two chains per wave)."""
+    settings on the 53-pixel kernels of the default plan (fixed-length HMC; or
+    NUTS of the given maximum tree depth, all transitions in one launch)."""
     cfg = gen.CONFIGS["uniform"]
     dev = torch.device("cuda:0")
     N = cfg.n_pix
@@ -583,6 +584,9 @@ def exposures_leg(api, torch, stream, n_gal, E, log):
     hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=Sd, adapt=True,
                          metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
                          use_graph=True, seed=gen.chain_seed(cfg.index))
+    if sampler == "nuts":
+        hcfg = api.HmcConfig(**{**hcfg.__dict__, "sampler": api.N.SAMPLER_NUTS, "max_tree_depth": depth,
+                                "iters_per_launch": W + Sd})
     wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
     api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
     (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
@@ -591,12 +595,12 @@ def exposures_leg(api, torch, stream, n_gal, E, log):
     n_eff = float(e.mean(dim=1).mean())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
-    flop = flops_per_eval(N) * E * n_gal * C * L * (W + Sd)
-    log(f"[bench] exposures: E = {E}, hmc {t_hmc:.3f} s, warmup {t_w:.3f} s, n_eff {n_eff:.0f}")
-    return {"n_gal": n_gal, "n_exp": E, "t_hmc_s": round(t_hmc, 4), "t_warmup_s": round(t_w, 4),
-            "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 1),
-            "achieved_tflops": round(flop / t_hmc / 1e12, 3),
-            "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4),
+    flop = flops_per_eval(N) * E * n_gal * C * L * (W + Sd) if sampler == "hmc" else None
+    log(f"[bench] exposures: E = {E}, {sampler} {t_hmc:.3f} s, warmup {t_w:.3f} s, n_eff {n_eff:.0f}")
+    return {"n_gal": n_gal, "n_exp": E, "sampler": sampler, "t_hmc_s": round(t_hmc, 4),
+            "t_warmup_s": round(t_w, 4), "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 1),
+            "achieved_tflops": round(flop / t_hmc / 1e12, 3) if flop else None,
+            "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4) if flop else None,
             "accept_rate": round(float(st[..., 0].mean()), 4),
             "status_nonzero": int((status != 0).sum())}
 
@@ -624,7 +628,7 @@ def main():
     ap.add_argument("--n-exp", type=int, default=4, help="--workload exposures: exposures per galaxy")
     ap.add_argument("--depth", type=int, default=5, help="--workload nuts / bias: maximum tree depth")
     ap.add_argument("--sampler", choices=["hmc", "nuts"], default="hmc",
-                    help="--workload bias: per-galaxy sampler")
+                    help="--workload bias / exposures: per-galaxy sampler")
     ap.add_argument("--ipl", type=int, default=0,
                     help="--workload nuts: transitions per launch (0: all in one launch)")
     ap.add_argument("--spergel-nu", type=float, default=-0.6,
@@ -680,13 +684,15 @@ def main():
                                           f"{res['iters_per_launch']} transitions per launch"}, **res}
         elif args.workload == "exposures":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
-            res = exposures_leg(api, torch, stream, G, args.n_exp, log)
+            res = exposures_leg(api, torch, stream, G, args.n_exp, log, args.sampler, args.depth)
             out = {"metric": "galaxies/sec at 300 ESS (several exposures, correlated noise)",
                    "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
                    "higher_is_better": True, "dtype": "f32", "data": "synthetic",
                    "config": {"workload": f"{G} galaxies x {args.n_exp} exposures of 53 x 53, PSF FWHM "
-                                          "U(0.6, 0.9)in, stationary correlated noise, 4 chains, 20 "
-                                          "leapfrog steps, 300 warmup + 1000 draws"}, **res}
+                                          "U(0.6, 0.9)in, stationary correlated noise, 4 chains, "
+                                          + ("20 leapfrog steps" if args.sampler == "hmc" else
+                                             f"NUTS max tree depth {args.depth}")
+                                          + ", 300 warmup + 1000 draws"}, **res}
         elif args.workload == "bias":
             G = args.n_gal or gen.CONFIGS["uniform"].n_gal
             res = bias_leg(api, torch, stream, G, args.n_boot, log, args.sampler, args.depth)

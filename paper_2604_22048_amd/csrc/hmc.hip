@@ -1147,7 +1147,7 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 // chain start runs on the general kernels).
 // NUTS: No-U-Turn transitions instead of fixed-length trajectories (advance
 // only; one wave per chain, or two chains per wave on the specialised kernels
-// of the paired plans; with MX the general kernels).
+// of the paired plans without MX).
 template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false,
           bool NUTS = false>
 __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
@@ -1457,11 +1457,22 @@ const int* hmc_fixed_plans(int N) {
   }
 }
 
-// NUTS on the kernels specialised per stamp size (one wave per chain).
+// NUTS on the kernels specialised per stamp size (one wave per chain, or two
+// on the paired plans; with exposures / noise weights one wave per chain on
+// the default plans).
 template <int PROF>
 static bool launch_fixed_nuts(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
 #define BSI_CASE(NN, PP)                                                                        \
   if (a.N == NN && a.P == PP) {                                                                 \
+    if (a.mx) {                                                                                 \
+      if constexpr (make_slot_plan(NN).P == PP) {                                               \
+        auto km = hmc_kernel<PROF, false, PP, 256, NN, 1, 1, true, true>;                       \
+        (void)hipFuncSetAttribute((const void*)km, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
+        hipLaunchKernelGGL(km, dim3(grid), dim3(kWave * a.C), lds, s, a);                       \
+        return true;                                                                            \
+      }                                                                                         \
+      return false;                                                                             \
+    }                                                                                           \
     if constexpr (paired_chains_plan(NN, PP)) {                                                 \
       if (hmc_chains_per_wave(a.N, a.C, a.P, a.prof, 1) == 2) {                                 \
         auto k2 = hmc_kernel<PROF, false, PP, 256, NN, 1, 2, false, true>;                      \
@@ -1483,7 +1494,9 @@ static bool launch_fixed_nuts(const HmcArgs& a, int grid, size_t lds, hipStream_
 template <int PROF, bool INIT>
 static void launch_prof(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   if constexpr (!INIT && PROF != kProfGauss)
-    if (a.nuts && !a.mx && a.C <= 4 && launch_fixed_nuts<PROF>(a, grid, lds, s)) return;
+    if (a.nuts && a.C <= 4 && (!a.mx || hmc_mx_fixed(a.N, a.P, a.prof, a.wpc)) &&
+        launch_fixed_nuts<PROF>(a, grid, lds, s))
+      return;
   if (a.nuts && !a.mx) {
     switch (a.P) {
       case 1: launch_p<PROF, INIT, 1>(a, grid, lds, s); break;

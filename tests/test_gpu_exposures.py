@@ -143,14 +143,16 @@ def test_hmc_exposures_parity(bsi, metric, sizes, C, E):
     assert agree >= G * C * S - 2
 
 
-def test_nuts_exposures_parity(bsi):
+@pytest.mark.parametrize("sizes", [[25, 25], [30, 30]])
+def test_nuts_exposures_parity(bsi, sizes):
     """NUTS on galaxies seen in two exposures with correlated noise (the
-    general kernels' weighted form): chains follow the oracle's NUTS."""
+    weighted form of the 25-pixel specialised kernel and of the general
+    kernels): chains follow the oracle's NUTS."""
     import torch
     from oracle import nuts
-    _log("exposures nuts parity")
-    rng = np.random.default_rng(95)
-    sizes, E, C, S = [25, 25], 2, 2, 4
+    _log(f"exposures nuts parity sizes={sizes}")
+    rng = np.random.default_rng(95 + sizes[0])
+    E, C, S = 2, 2, 4
     p, n, psf, sig, ps, stamps = synth.exposure_population(rng, sizes, E, True)
     G = len(sizes)
     b, data = _upload(bsi, torch, n, psf, sig, ps, stamps, E)
