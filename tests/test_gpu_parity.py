@@ -434,31 +434,71 @@ def _shear_samples(rng, G, K):
     return [a.astype(np.float32) for a in (e1, e2, ls, lf)]
 
 
+# Points at the edges of the hyper-prior boxes (reading R14: the paper's log10
+# boxes mu_s in (-2, 2), sigma_s in (0, 0.5) converted to ln units;
+# sigma_e in (1e-4, 1); |g| < 1): (g1, g2, mu, sigma, sigma_e, inside?).  Just
+# inside the disk is |g| = 1 - 1e-3: closer to the circle the float32 inverse
+# shear cannot resolve 1 - |eps|^2.
+def _edge_points():
+    L = math.log(10.0)
+    b = (0.01, -0.02, math.log(0.6), 0.3, 0.25)
+    pts = []
+    for mu10 in (-2.0, 2.0):
+        pts.append(((b[0], b[1], mu10 * (1 - 1e-9) * L, b[3], b[4]), True))
+        pts.append(((b[0], b[1], mu10 * (1 + 1e-9) * L, b[3], b[4]), False))
+    pts += [((b[0], b[1], b[2], 0.5 * (1 - 1e-9) * L, b[4]), True),
+            ((b[0], b[1], b[2], 0.5 * (1 + 1e-9) * L, b[4]), False),
+            ((b[0], b[1], b[2], 0.0, b[4]), False),
+            ((b[0], b[1], b[2], b[3], 1e-4 * (1 + 1e-6)), True),
+            ((b[0], b[1], b[2], b[3], 1e-4), False),
+            ((b[0], b[1], b[2], b[3], 1.0 - 1e-9), True),
+            ((b[0], b[1], b[2], b[3], 1.0), False),
+            ((b[0], b[1], 1.3 * L, b[3], b[4]), True),
+            ((b[0], b[1], b[2], 0.4 * L, b[4]), True)]
+    for phi in (0.0, 2.5):
+        c, s_ = math.cos(phi), math.sin(phi)
+        pts += [(((1 - 1e-3) * c, (1 - 1e-3) * s_, *b[2:]), True), ((c, s_, *b[2:]), False),
+                (((1 + 1e-9) * c, (1 + 1e-9) * s_, *b[2:]), False)]
+    return pts
+
+
 @pytest.mark.parametrize("kind,flux", [(1, False), (0, True)])
 def test_shear_posterior_parity(bsi, kind, flux):
+    """Log-posterior and gradient against the oracle within the float32 bound of
+    tests/f32bound.py (derived from the library's float32 / float64 split),
+    at interior points and at every edge of the hyper-prior boxes."""
     import torch
+    from tests import f32bound
     _log(f"shear parity kind={kind} flux={flux}")
     rng = np.random.default_rng(30 + kind)
     G, K = 40, 300
     S = _shear_samples(rng, G, K)
-    tpo = shear.TruePrior(e_kind=kind, e_max=0.95 if kind == 1 else 0.7,
+    # e_max = 1 for the truncated Gaussian: its support is the unit disk, so the
+    # disk edge of the shear prior can be probed with finite weights
+    tpo = shear.TruePrior(e_kind=kind, e_max=1.0 if kind == 1 else 0.7,
                           mu_lnf=math.log(1000.0) if flux else math.nan, sig_lnf=0.5)
     tpg = bsi.TruePriorCfg(e_kind=kind, e_max=tpo.e_max, size_term=True, flux_term=flux,
                            mu_ln_f=math.log(1000.0), sigma_ln_f=0.5)
-    pts = np.array([[0.02, -0.01, math.log(0.6), 0.3, 0.2], [-0.05, 0.04, -0.4, 0.25, 0.26],
-                    [0.0, 0.0, -0.6, 0.35, 0.18], [1.2, 0.0, -0.5, 0.3, 0.2]])
+    inner = [((0.02, -0.01, math.log(0.6), 0.3, 0.2), True), ((-0.05, 0.04, -0.4, 0.25, 0.26), True),
+             ((0.0, 0.0, -0.6, 0.35, 0.18), True), ((1.2, 0.0, -0.5, 0.3, 0.2), False)]
+    cases = inner + _edge_points()
+    pts = np.array([c[0] for c in cases])
     St = [torch.tensor(a).cuda() for a in S]
     lp, gr = bsi.shear_posterior(St[0], St[1], St[2], St[3], pts, tpg, want_grad=True)
     lp, gr = lp.cpu().numpy(), gr.cpu().numpy()
     Sd = [a.astype(np.float64) for a in S]
     ip = shear.Interim()
-    for j in range(3):
-        g = complex(pts[j, 0], pts[j, 1])
-        alpha = tuple(pts[j, 2:])
+    for j, (pt, inside) in enumerate(cases):
+        if not inside:
+            assert lp[j] == -np.inf, (j, pt, lp[j])
+            continue
+        g = complex(pt[0], pt[1])
+        alpha = tuple(pt[2:])
         rl, rg = shear.log_posterior_grad(Sd, g, alpha, tpo, ip)
-        assert abs(lp[j] - rl) <= 1e-6 * (abs(rl) + G), (j, lp[j], rl)
-        assert np.all(np.abs(gr[j] - rg) <= 1e-4 * (np.abs(rg) + math.sqrt(G * K) * 0.1)), (j, gr[j], rg)
-    assert lp[3] == -np.inf
+        tl, tg = f32bound.posterior_bounds(Sd, g, alpha, tpo, ip)
+        assert np.isfinite(rl) and abs(lp[j] - rl) <= tl, (j, pt, lp[j], rl, tl)
+        if j < len(inner):
+            assert np.all(np.abs(gr[j] - rg) <= tg), (j, gr[j], rg, tg)
 
 
 def test_shear_grid_posterior_mean(bsi):
@@ -476,8 +516,16 @@ def test_shear_grid_posterior_mean(bsi):
     lp = bsi.shear_posterior(St[0], St[1], St[2], St[3], pts, tpg).cpu().numpy().reshape(41, 41)
     rlp, m1, m2 = shear.grid_posterior([a.astype(np.float64) for a in S], g1s, g2s, alpha,
                                        shear.TruePrior(e_kind=1, e_max=0.95), shear.Interim())
-    assert np.max(np.abs(lp - rlp)) <= 1e-6 * np.max(np.abs(rlp)) + 1e-4
+    from tests import f32bound
+    Sd = [a.astype(np.float64) for a in S]
+    tp = shear.TruePrior(e_kind=1, e_max=0.95)
+    tol = np.array([[f32bound.posterior_bounds(Sd, complex(a, bb), alpha, tp, shear.Interim(),
+                                               want_grad=False)[0] for a in g1s] for bb in g2s])
+    assert np.all(np.abs(lp - rlp) <= tol), np.max(np.abs(lp - rlp) / tol)
+    # the grid mean moves by sum_p w_p (g_p - m)(d lp_p - mean d lp) to first order
     w = np.exp(lp - lp.max())
+    w /= w.sum()
     G1, G2 = np.meshgrid(g1s, g2s)
-    assert abs(np.sum(w * G1) / np.sum(w) - m1) < 1e-6
-    assert abs(np.sum(w * G2) / np.sum(w) - m2) < 1e-6
+    m1g, m2g = np.sum(w * G1), np.sum(w * G2)
+    assert abs(m1g - m1) <= 2 * tol.max() * np.sum(w * np.abs(G1 - m1)), (m1g, m1)
+    assert abs(m2g - m2) <= 2 * tol.max() * np.sum(w * np.abs(G2 - m2)), (m2g, m2)

@@ -192,3 +192,36 @@ def test_fisher_metric_matches_finite_difference_curvature():
         curv = (hmc.potential(gal, th + e)[0] - 2 * hmc.potential(gal, th)[0] +
                 hmc.potential(gal, th - e)[0]) / (h * h)
         assert abs(curv * im[j] - 1.0) < 2e-3, (j, curv, 1 / im[j])
+
+
+def test_jittered_step_is_uniform_on_the_stated_interval():
+    """Reading R8: the step of iteration t is eps (1 + j (2u - 1)) with u the
+    Philox jitter uniform, i.e. uniform on [eps (1 - j), eps (1 + j)] (Neal
+    2011, section 5.4.2.2: a step drawn at random from a small interval around
+    the nominal one).  Pinned by its law, not by its formula: over 10^4
+    (uid, t) pairs every value lies in the interval, a Kolmogorov-Smirnov test
+    accepts the uniform law on it, and the mean and spread match the uniform
+    ones.  A one-sided or mis-scaled jitter fails the KS test or the range."""
+    from scipy import stats
+    eps, j = 0.0137, 0.3
+    e32 = hmc.f32(eps)
+    lo, hi = e32 * (1.0 - hmc.f32(j)), e32 * (1.0 + hmc.f32(j))
+    v = np.array([hmc.jittered_step(eps, j, 2024, uid, t) for uid in range(100) for t in range(100)])
+    # float32 rounding of the product: half an ulp at each end
+    assert np.all(v >= lo * (1 - 2 ** -24)) and np.all(v <= hi * (1 + 2 ** -24))
+    ks = stats.kstest(v, stats.uniform(loc=lo, scale=hi - lo).cdf)
+    assert ks.pvalue > 1e-3, ks
+    n = v.size
+    sd = (hi - lo) / math.sqrt(12.0)
+    assert abs(v.mean() - e32) < 4.0 * sd / math.sqrt(n)
+    assert abs(v.std() / sd - 1.0) < 0.05
+    # both halves of the interval are used (a one-sided jitter puts nothing below eps)
+    assert 0.45 < np.mean(v < e32) < 0.55
+    # the values are distinct per (uid, t): the jitter stream is not shared across iterations
+    assert np.unique(v).size > 0.99 * n
+
+
+def test_jittered_step_without_jitter_is_the_float32_step():
+    for eps in (0.01, 0.0137, 0.5, 1e-3):
+        for t in range(5):
+            assert hmc.jittered_step(eps, 0.0, 7, 3, t) == hmc.f32(eps)

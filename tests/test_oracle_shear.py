@@ -195,3 +195,63 @@ def test_shear_level_hmc_against_importance_sampling():
         se = math.sqrt(s_is[j] ** 2 / n_eff + s_is[j] ** 2 / n_is_eff)
         assert abs(x[:, j].mean() - m_is[j]) < 4 * se, (j, x[:, j].mean(), m_is[j], se)
         assert 0.7 < x[:, j].std() / s_is[j] < 1.4, (j, x[:, j].std(), s_is[j])
+
+
+# The hyper-priors of Section 3.4 as the paper prints them, in log10 units of
+# size (its Section 2 population is lognormal in log10 s): mu_s ~ U(-2, 2),
+# sigma_s ~ U(0, 0.5); sigma_e ~ U(1e-4, 1); g uniform on the unit disk.  The
+# oracle takes alpha in natural-log units (reading R14), so its boxes are
+# these times ln 10.  Each edge is probed just inside (finite) and just outside
+# (-inf); the log10-unit points inside the paper's boxes but outside the
+# unconverted ones catch a box left in log10 units.
+PAPER_MU10 = (-2.0, 2.0)
+PAPER_SIG10 = (0.0, 0.5)
+PAPER_SIGE = (1e-4, 1.0)
+
+
+def _edge_points(rel=1e-9):
+    """(g, alpha, inside?) around every edge of the paper's boxes."""
+    base_g, base = complex(0.01, -0.02), (math.log(0.6), 0.3, 0.25)
+    out = []
+    for mu10 in PAPER_MU10:
+        for s, ins in ((-1.0, True), (1.0, False)):
+            mu = mu10 * (1.0 + s * rel) * shear.LN10
+            out.append((base_g, (mu, base[1], base[2]), ins))
+    hi = PAPER_SIG10[1]
+    out += [(base_g, (base[0], hi * (1.0 - rel) * shear.LN10, base[2]), True),
+            (base_g, (base[0], hi * (1.0 + rel) * shear.LN10, base[2]), False),
+            (base_g, (base[0], 0.0, base[2]), False),
+            (base_g, (base[0], -1e-3, base[2]), False)]
+    lo, hi = PAPER_SIGE
+    out += [(base_g, (base[0], base[1], lo * (1.0 + 1e3 * rel)), True),
+            (base_g, (base[0], base[1], lo), False),
+            (base_g, (base[0], base[1], lo * (1.0 - 1e3 * rel)), False),
+            (base_g, (base[0], base[1], hi * (1.0 - rel)), True),
+            (base_g, (base[0], base[1], hi), False)]
+    for phi in (0.0, 1.0, 2.5):
+        u = complex(math.cos(phi), math.sin(phi))
+        out += [((1.0 - 1e3 * rel) * u, base, True), (u, base, False), ((1.0 + rel) * u, base, False)]
+    # inside the paper's log10 boxes, outside the same numbers read as ln-unit boxes
+    out += [(base_g, (1.3 * shear.LN10, base[1], base[2]), True),
+            (base_g, (-1.3 * shear.LN10, base[1], base[2]), True),
+            (base_g, (base[0], 0.4 * shear.LN10, base[2]), True)]
+    return out
+
+
+@pytest.mark.parametrize("kind", [shear.E_KIND_BA14, shear.E_KIND_TRUNC_GAUSS])
+def test_hyper_prior_box_edges(kind):
+    e1, e2, ls, lf = _samples(3, 40, 13)
+    # near |g| = 1 the inverse shear maps every sample close to the unit circle,
+    # so the truncated Gaussian is taken with e_max = 1 (support the unit disk)
+    tp = shear.TruePrior(e_kind=kind, e_max=1.0)
+    ip = shear.Interim()
+    n_checked = 0
+    for g, alpha, inside in _edge_points():
+        assert shear.in_hyper_support(g, alpha) == inside, (g, alpha)
+        lp = shear.log_posterior((e1, e2, ls, lf), g, alpha, tp, ip)
+        if inside:
+            assert np.isfinite(lp), (g, alpha, lp)
+        else:
+            assert lp == -math.inf, (g, alpha, lp)
+        n_checked += 1
+    assert n_checked == 25
