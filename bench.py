@@ -34,20 +34,39 @@ TARGET_ESS = 300.0
 PS = gen.PIXEL_SCALE
 
 
-def flops_per_eval(N: int) -> float:
-    """Algorithmic float32 operations of one gradient evaluation (k-space form).
+FP32_PEAK_TFLOPS = 157.3      # MI355X published FP32 peak (vector, packed / matrix)
+VALU_ISSUE_TFLOPS = 78.6      # one wave64 FMA per CU per cycle (non-packed issue): 256 x 64 x 2 x 2.4 GHz
+CLOCK_HZ = 2.4e9
+N_CU = 256
 
-    Per half-plane DFT bin ((N^2 + 1) / 2 for odd N, N^2 / 2 + 2 for even N):
-    43 (an FMA counts 2): spectrum 15 (k_y, q, 1 + r0^2 q, rsqrt, G, X Y, G X Y),
-    residual and |R|^2 6, conj(R) T 6, and the six weighted sums 16 (F, k_x^2,
-    k_y^2, k_x k_y, k_x, k_y).  Per frequency point 12 for the separable
-    PSF-sinc-phase tables, and 100 for the per-evaluation shape constants,
-    reductions and the gradient assembly.  Slots that only pad the lane
-    layout are not counted."""
-    nbins = (N * N + 1) // 2 if N % 2 else N * N // 2 + 2
-    ntab = 2 * (N // 2) + 1
-    rows = (N if N % 2 else N - 1) // 2 + 1
-    return 43.0 * nbins + 12.0 * (ntab + rows) + 100.0
+
+def half_plane_bins(N: int) -> int:
+    """Distinct bins of the Hermitian half plane (the even-N Nyquist bins combined)."""
+    return (N * N + 1) // 2 if N % 2 else N * N // 2 + 2
+
+
+def flops_per_eval(N: int, L: int = 20, chi2_every_step: bool = False, weighted: bool = False) -> float:
+    """Algorithmic float32 operations of one gradient evaluation in the k-space
+    form, counted from the trajectory kernel's pair loop as it executes (an FMA
+    counts 2; a reciprocal square root, logarithm or exponential 1).
+
+    One pair of bins (+kx, ky), (-kx, ky) costs 66 operations for the gradient:
+    the two profile arguments 6, the profile powers G and G/(1 + r0^2 q) 8 (two
+    rsqrt and three products each; the Spergel form's log2/exp2 pair costs the
+    same), the separable factors X Y and conj(X) Y 10, the residuals 8,
+    conj(R) X Y 12, and the flux, shape and centroid accumulations 22.  Sum
+    |R|^2 adds 8 per pair; fixed-length HMC forms it on the last leapfrog step
+    of a trajectory only (1 in L evaluations), NUTS on every step.  Stationary
+    noise weights scale the two bins' G factors: 4 more per pair.  Per bin
+    that is 33 (+4 for Sum |R|^2, +2 for the weights), counted over the
+    distinct half-plane bins (the lane layout's duplicated column-0 and
+    padding slots are not counted).  Per evaluation also: the separable
+    PSF-sinc-phase tables (6 per x frequency, 8 per row), the per-column
+    constants and post-loop products (9 per column), and 150 for the shape
+    constants, reductions, gradient assembly, prior and leapfrog update."""
+    h = N // 2
+    per_bin = 33.0 + (4.0 if chi2_every_step else 4.0 / L) + (2.0 if weighted else 0.0)
+    return per_bin * half_plane_bins(N) + 6.0 * (2 * h + 1) + 8.0 * (h + 1) + 9.0 * (h + 1) + 150.0
 
 
 KERNEL_SOURCES = {
@@ -65,17 +84,31 @@ def kernel_source_hash(kernel: str = "hmc") -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(profile="hmc_kernel_uniform53.txt", kernel="hmc"):
-    """HBM bytes per launch from a committed counter summary, or None when the
-    kernel's sources have changed since the counters were taken."""
+def recorded_counter(profile="hmc_kernel_uniform53.txt", kernel="hmc", key="traffic_bytes_per_launch"):
+    """A per-launch figure from a committed counter summary (key: value lines),
+    or None when the kernel's sources have changed since the counters were
+    taken or the summary lacks the key."""
     path = os.path.join(ROOT, "profiles", profile)
     try:
         kv = dict(line.split(": ", 1) for line in open(path).read().splitlines() if ": " in line)
     except OSError:
         return None
-    if kv.get("source_sha256", "").strip() != kernel_source_hash(kernel):
+    if kv.get("source_sha256", "").strip() != kernel_source_hash(kernel) or key not in kv:
         return None
-    return float(kv["traffic_bytes_per_launch"])
+    return float(kv[key])
+
+
+def recorded_traffic(profile="hmc_kernel_uniform53.txt", kernel="hmc"):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
+    return recorded_counter(profile, kernel, "traffic_bytes_per_launch")
+
+
+def valu_issue_frac(launch_s, profile="hmc_kernel_uniform53.txt", kernel="hmc"):
+    """Wave64 VALU instructions issued per CU per cycle (the non-packed issue
+    ceiling is 1): the counter summary's SQ_INSTS_VALU per launch over the
+    live launch duration at 2.4 GHz, or None."""
+    n = recorded_counter(profile, kernel, "valu_insts_per_launch")
+    return None if n is None else round(n / N_CU / (launch_s * CLOCK_HZ), 4)
 
 
 # ---------------------------------------------------------------- CPU baseline
@@ -99,13 +132,18 @@ def _oracle_worker(args):
     return time.perf_counter() - t0, n_iter * L
 
 
-CPU_ITERS = 400     # per core: about 10 s of oracle work on the host's cores
+CPU_ITERS = 600     # per worker: about 15 s of oracle work
+# Worker processes for the oracle baseline: one per usable core, at most the
+# host-CPU share that comes with one GPU on the measurement machines (16
+# cores); the affinity mask there can list the whole host.
+CPU_WORKER_CAP = 16
 
 
 def cpu_baseline_eval_rate(n_iter=CPU_ITERS, L=20):
-    """Oracle gradient evaluations per second on the host, all usable cores."""
+    """Oracle gradient evaluations per second on the host: one single-threaded
+    worker per usable core (capped at CPU_WORKER_CAP)."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), 16)
+    cores = min(len(os.sched_getaffinity(0)), CPU_WORKER_CAP)
     ctx = mp.get_context("fork")
     t0 = time.perf_counter()
     with ctx.Pool(cores) as pool:
@@ -405,7 +443,7 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
             "n_eff_mean": round(n_eff, 1),
             "galaxies_per_s": round(1.0 / tpg, 1),
             "achieved_tflops": round(flop / t_hmc / 1e12, 3),
-            "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4),
+            "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
             "accept_rate": round(float(st[..., 0].mean()), 4),
             "status_nonzero": int((status != 0).sum())}
 
@@ -434,6 +472,7 @@ def spergel_leg(api, torch, stream, n_gal, nu, log=None):
     return {"n_gal": n_gal, "spergel_nu": nu, "t_hmc_s": round(t_hmc, 4), "t_warmup_s": round(t_w, 4),
             "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 1),
             "achieved_tflops": round(flop / t_hmc / 1e12, 3),
+            "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
             "accept_rate": round(float(st[..., 0].mean()), 4),
             "status_nonzero": int((status != 0).sum())}
 
@@ -530,7 +569,7 @@ def nuts_leg(api, torch, stream, n_gal, depth, ipl, log):
     steps = float(nlf.sum())
     steps_w = float(nlf[:, :, :W].sum())
     depth_hist = torch.bincount(trace[..., 3].reshape(-1).long(), minlength=depth + 1).cpu().tolist()
-    flop = flops_per_eval(cfg.n_pix) * steps
+    flop = flops_per_eval(cfg.n_pix, chi2_every_step=True) * steps
     log(f"[bench] nuts: depth {depth}, {ipl} per launch: {t_all:.3f} s, {steps / (n_gal * C * (W + S)):.2f} "
         f"leapfrog steps per transition, n_eff {n_eff:.0f}")
     return {"n_gal": n_gal, "max_tree_depth": depth, "iters_per_launch": ipl,
@@ -541,6 +580,7 @@ def nuts_leg(api, torch, stream, n_gal, depth, ipl, log):
             "depth_histogram": depth_hist,
             "ess_per_gradient_eval": round(n_eff / ((steps - steps_w) / n_gal), 4),
             "achieved_tflops": round(flop / t_all / 1e12, 3),
+            "frac_fp32_peak": round(flop / t_all / 1e12 / FP32_PEAK_TFLOPS, 4),
             "accept_stat_mean": round(float(trace[:, :, W:, 2].mean()), 4),
             "status_nonzero": int((status != 0).sum())}
 
@@ -595,12 +635,12 @@ def exposures_leg(api, torch, stream, n_gal, E, log, sampler="hmc", depth=5):
     n_eff = float(e.mean(dim=1).mean())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
-    flop = flops_per_eval(N) * E * n_gal * C * L * (W + Sd) if sampler == "hmc" else None
+    flop = flops_per_eval(N, L, weighted=True) * E * n_gal * C * L * (W + Sd) if sampler == "hmc" else None
     log(f"[bench] exposures: E = {E}, {sampler} {t_hmc:.3f} s, warmup {t_w:.3f} s, n_eff {n_eff:.0f}")
     return {"n_gal": n_gal, "n_exp": E, "sampler": sampler, "t_hmc_s": round(t_hmc, 4),
             "t_warmup_s": round(t_w, 4), "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 1),
             "achieved_tflops": round(flop / t_hmc / 1e12, 3) if flop else None,
-            "frac_alu_peak": round(flop / t_hmc / 1e12 / 78.6, 4) if flop else None,
+            "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4) if flop else None,
             "accept_rate": round(float(st[..., 0].mean()), 4),
             "status_nonzero": int((status != 0).sum())}
 
@@ -742,7 +782,8 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         rate, cores, evals, wall = cpu_baseline_eval_rate()
-        cpu = dict(rate=rate, cores=cores, evals=evals, wall=wall)
+        cpu = dict(rate=rate, cores=cores, evals=evals, wall=wall,
+                   visible=len(os.sched_getaffinity(0)))
         print(f"[bench] oracle: {evals} gradient evaluations on {cores} cores in {wall:.1f} s",
               file=sys.stderr, flush=True)
 
@@ -773,13 +814,14 @@ def main():
     def step():
         (smp, stats, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg),
                                             stream)
-        (ess, rh), t_ess = timed(torch, lambda: api.ess(smp), stream)
+        (ess, rh, rhs), t_ess = timed(torch, lambda: api.ess(smp, split=True), stream)
         # interim samples for the shear phase: every 4th draw of the 4 chains
         def shear_step():
             th = smp[:, :, 3::4, :].reshape(G, K, 6)
             return api.shear_posterior(th[..., 2], th[..., 3], th[..., 1], th[..., 0], pts, tp)
         lp, t_shear = timed(torch, shear_step, stream)
-        return dict(smp=smp, stats=stats, status=status, ess=ess, rhat=rh, lp=lp, t_hmc=t_hmc,
+        return dict(smp=smp, stats=stats, status=status, ess=ess, rhat=rh, rhat_split=rhs, lp=lp,
+                    t_hmc=t_hmc,
                     t_ess=t_ess, t_shear=t_shear)
 
     for i in range(args.warmup):
@@ -806,6 +848,8 @@ def main():
     value = 1.0 / tpg
     stats = r["stats"].cpu().numpy()
     rhat = r["rhat"].cpu().numpy()
+    rhat_split = r["rhat_split"].cpu().numpy()
+    flagged = (r["status"] != 0).cpu().numpy()
 
     # plain form: one galaxy and one leapfrog step per launch, on a subset
     Gp = args.plain_gal
@@ -822,9 +866,9 @@ def main():
     # roofline of the trajectory kernel: one launch = one iteration of every chain
     n_launch = W + S
     t_launch = t_hmc / n_launch
-    alg = flops_per_eval(N) * G * C * L
+    alg = flops_per_eval(N, L) * G * C * L
     achieved = alg / t_launch / 1e12
-    peak = 78.6
+    peak = FP32_PEAK_TFLOPS
     legs = {}
     if not args.no_legs:
         legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
@@ -865,18 +909,27 @@ def main():
         "accept_rate": round(float(stats[..., 0].mean()), 4),
         "rhat_max": round(float(np.nanmax(rhat)), 4),
         "frac_rhat_lt_1.01": round(float(np.mean(rhat.max(axis=1) < 1.01)), 4),
+        "rhat_split_max": round(float(np.nanmax(rhat_split)), 4),
+        "frac_rhat_split_lt_1.01": round(float(np.mean(rhat_split.max(axis=1) < 1.01)), 4),
+        "n_eff_mean_unflagged": round(float(n_eff[~flagged].mean()), 1),
         "frac_status_nonzero": round(float((r["status"] != 0).float().mean()), 4),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": recorded_traffic(),
                      "kernel": "hmc_kernel (advance)", "launch_ms": round(t_launch * 1e3, 4),
-                     "alg_flop_per_launch": alg},
+                     "alg_flop_per_eval": flops_per_eval(N, L), "evals_per_launch": G * C * L,
+                     "alg_flop_per_launch": alg,
+                     "valu_issue_frac": valu_issue_frac(t_launch),
+                     "frac_of_nonpacked_issue_ceiling": round(achieved / VALU_ISSUE_TFLOPS, 4)},
         **legs,
     }
     if cpu:
         evals_per_gal = C * L * (W + S * TARGET_ESS / n_eff_mean)
         out["cpu_baseline"] = {"value": round(cpu["rate"] / evals_per_gal, 6), "unit": "galaxies/s",
                                "cores": cpu["cores"], "kind": "oracle",
+                               "cores_visible": cpu["visible"],
+                               "cores_note": f"one worker per usable core, capped at {CPU_WORKER_CAP} "
+                                             "(the host-CPU share of one GPU on the measurement box)",
                                "sample": f"{cpu['evals']} float64 oracle gradient evaluations (53x53, "
                                          f"one {CPU_ITERS}-iteration warmup chain per core) in "
                                          f"{cpu['wall']:.1f} s; galaxies/s = eval rate / evaluations "

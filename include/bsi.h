@@ -25,7 +25,7 @@
  *   - Pointers marked [device] are caller-owned device memory on the
  *     handle's device; [host] pointers are read during the call only.  The
  *     library never frees caller memory.  It allocates only handle-owned
- *     workspace, which grows on demand and is released by bsi_destroy().
+ *     workspace (see "Workspace, streams and graph capture" below).
  *   - Calls are stream-ordered on `stream` (a hipStream_t; NULL means the
  *     default stream).  A handle must be used from one host thread at a
  *     time.
@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define BSI_VERSION 2
+#define BSI_VERSION 3
 
 enum {
   BSI_OK = 0,
@@ -110,6 +110,65 @@ void bsi_destroy(bsi_handle h);
 /* Message of the last failing call on h (empty string if none; never NULL).
  * With h == NULL returns the last error of bsi_create on this thread. */
 const char* bsi_last_error(bsi_handle h);
+
+/*
+ * Workspace, streams and graph capture.
+ *   - Each call sizes the handle's workspace for its arguments before it
+ *     enqueues anything.  Growing allocates new device buffers; the buffers
+ *     they replace stay allocated (work enqueued earlier may still read
+ *     them) until bsi_reserve or bsi_destroy.  No call synchronises the
+ *     device.
+ *   - Host inputs the device needs (a batch's stamp plan from n and off, and
+ *     host-side shear points) are packed into a pinned, device-mapped
+ *     staging buffer of the handle and copied by a kernel; a call first waits
+ *     on the host until the previous call's copy out of that buffer has run.
+ *   - Calls on different streams: a call waits (on the device) for the
+ *     handle's previous call when that was made on another stream, because
+ *     they share the workspace.
+ *   - Graph capture (the two phases of Section 3.3 run as fixed launch
+ *     sequences, so a caller can capture them): a call whose stream is being
+ *     captured (relaxed or thread-local mode) records kernel nodes only,
+ *     never allocates, and fails with BSI_EINVAL before enqueueing anything
+ *     when the workspace is smaller than it needs, so call bsi_reserve first.
+ *     The graph reads the handle's workspace and staging buffer at every
+ *     replay: until it is destroyed, use the handle for no other call
+ *     (one handle per live graph), and replay it after bsi_reserve only if
+ *     that reserve came first.  bsi_hmc_sample under capture ignores
+ *     use_graph and records its trajectory launches (the stamp sizes in
+ *     sequence) into the caller's graph.
+ *   - bsi_autotune, bsi_autotune_transform and the slot server allocate
+ *     their own buffers and are not for capture.
+ */
+
+/* Workspace limits of bsi_reserve (every field >= 0). */
+typedef struct {
+  int64_t max_stamps;     /* stamps (galaxies x exposures) of the largest batch of
+                             bsi_render_stamps, bsi_loglik_grad and bsi_hmc_sample, packed
+                             (their offsets span at most max_stamps max_n^2 elements)      */
+  int32_t max_n;          /* largest stamp side of those batches, 8..128 (any slot plan)  */
+  int32_t max_chains;     /* largest n_chains of bsi_hmc_sample, 0..16                    */
+  int32_t weighted;       /* nonzero: batches with n_exp > 1 or noise_ps                  */
+  int32_t pixel_method;   /* nonzero: bsi_loglik_grad with BSI_LIK_PIXEL                  */
+  int64_t max_shear_gal;  /* galaxies of bsi_shear_posterior, _galaxy_loglik, _hmc, _bias */
+  int32_t max_points;     /* points of bsi_shear_posterior / bsi_shear_galaxy_loglik (host
+                             or device points), chains of bsi_shear_hmc, grid points of
+                             bsi_shear_bias                                               */
+  int32_t bias;           /* nonzero: bsi_shear_bias with max_points grid points          */
+  int32_t max_boot;       /* bootstrap resamples of bsi_shear_bias                        */
+} bsi_reserve_cfg;
+
+/*
+ * bsi_reserve -- size the handle's workspace for every call within the
+ * limits, so that such calls neither allocate nor fail under graph capture
+ * (Section 3.3's two phases: the per-galaxy sampler and the shear
+ * posterior).  Synchronises the device, frees the buffers earlier growth
+ * replaced, and grows (never shrinks) each buffer.  Graphs captured before
+ * the call may read freed buffers: capture after reserving.
+ * Returns BSI_EINVAL (negative limits, max_chains > 16, bias without
+ * 1..8192 points), BSI_EUNSUPPORTED (max_n outside 8..128 with
+ * max_stamps > 0), BSI_ENOMEM, or BSI_EHIP.
+ */
+int bsi_reserve(bsi_handle h, const bsi_reserve_cfg* cfg);
 
 /* A ragged batch of square stamps. */
 typedef struct {
@@ -597,14 +656,20 @@ int bsi_slots_get_info(bsi_slots s, bsi_slots_info* info);
 /*
  * bsi_ess -- diagnostics of Section 4.1 for stored samples:
  * multi-chain effective sample size per parameter (autocorrelation with
- * Geyer's initial monotone sequence, no rank normalisation) and the classic
- * potential scale reduction R-hat.
- *   samples  [device] float[n_gal][n_chains][n_samples][n_par].
- *   ess      [device] float[n_gal][n_par] or NULL.
- *   rhat     [device] float[n_gal][n_par] or NULL.
+ * Geyer's initial monotone sequence, no rank normalisation), the classic
+ * potential scale reduction R-hat of the R-hat < 1.01 convergence test, and
+ * its split form (each chain cut into its first and last floor(n_samples/2)
+ * draws, the middle draw of an odd count dropped; the classic statistic over
+ * the 2 n_chains halves), which also flags chains that drift.
+ *   samples    [device] float[n_gal][n_chains][n_samples][n_par].
+ *   ess        [device] float[n_gal][n_par] or NULL.
+ *   rhat       [device] float[n_gal][n_par] or NULL.
+ *   rhat_split [device] float[n_gal][n_par] or NULL.
+ * At least one output must be non-NULL; n_samples >= 4, n_chains <= 16 and
+ * n_chains * n_samples * 8 bytes within the LDS stage (else BSI_EUNSUPPORTED).
  */
 int bsi_ess(bsi_handle h, int32_t n_gal, int32_t n_chains, int32_t n_samples, int32_t n_par,
-            const float* samples, float* ess, float* rhat, bsi_stream stream);
+            const float* samples, float* ess, float* rhat, float* rhat_split, bsi_stream stream);
 
 #ifdef __cplusplus
 }

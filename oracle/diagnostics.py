@@ -7,7 +7,11 @@ Test infrastructure only (see ``oracle/__init__``).
   initial monotone sequence (Gelman et al., Bayesian Data Analysis 3rd ed.,
   Section 11.5), without rank normalisation.
 * R-hat: the classic (non-split) potential scale reduction of Gelman & Rubin
-  (1992), as used for the convergence test of Section 4.1.
+  (1992), as used for the convergence test of Section 4.1, and the split
+  form (Gelman et al., BDA3 Section 11.4): every chain cut into its first and
+  last floor(n/2) draws (the middle draw of an odd n dropped), then the
+  classic statistic over the 2M half-chains, which also flags a chain whose
+  level drifts during the run.
 * Time per galaxy to a target number of effective samples: the extrapolation
   formula of Section 4.1, T_warmup / G + T_sampling / (G * n_eff) * target.
 """
@@ -67,6 +71,14 @@ def rhat(chains) -> float:
     B_over_n = np.var(x.mean(axis=1), ddof=1)
     var_plus = (n - 1.0) / n * W + B_over_n
     return float(np.sqrt(var_plus / W))
+
+
+def split_rhat(chains) -> float:
+    x = np.asarray(chains, dtype=np.float64)
+    M, n = x.shape
+    h = n // 2
+    halves = np.concatenate([x[:, :h], x[:, n - h:]], axis=0)      # (2M, h)
+    return rhat(halves)
 
 
 def time_per_galaxy(t_warmup, t_sampling, n_gal, n_eff_mean, target=300.0):

@@ -84,6 +84,12 @@ class Request(C.Structure):
                 ("init", C.POINTER(C.c_float))]
 
 
+class ReserveCfg(C.Structure):
+    _fields_ = [("max_stamps", C.c_int64), ("max_n", C.c_int32), ("max_chains", C.c_int32),
+                ("weighted", C.c_int32), ("pixel_method", C.c_int32), ("max_shear_gal", C.c_int64),
+                ("max_points", C.c_int32), ("bias", C.c_int32), ("max_boot", C.c_int32)]
+
+
 class SlotsInfo(C.Structure):
     _fields_ = [("resident", C.c_int32), ("finished", C.c_int32), ("pending", C.c_int32),
                 ("max_slots", C.c_int32), ("budget", C.c_int64), ("slot_fixed_bytes", C.c_int64),
@@ -98,6 +104,7 @@ SIGNATURES = {
     "bsi_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32]),
     "bsi_destroy": (None, [C.c_void_p]),
     "bsi_last_error": (C.c_char_p, [C.c_void_p]),
+    "bsi_reserve": (C.c_int, [C.c_void_p, C.POINTER(ReserveCfg)]),
     "bsi_render_stamps": (C.c_int, [C.c_void_p, C.POINTER(Batch), C.c_void_p, C.c_void_p, C.c_void_p]),
     "bsi_loglik_grad": (C.c_int, [C.c_void_p, C.POINTER(Batch), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p]),
@@ -138,7 +145,7 @@ SIGNATURES = {
     "bsi_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32,
                                C.POINTER(C.c_int32), C.POINTER(C.c_float)]),
     "bsi_ess": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
-                          C.c_void_p, C.c_void_p, C.c_void_p]),
+                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _lib = None

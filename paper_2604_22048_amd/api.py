@@ -516,14 +516,28 @@ def autotune_transform(sizes, n_gal: int = 10000, lib: Library | None = None):
     return {int(sizes[i]): (int(ch[i]), *[float(ms[4 * i + m]) for m in range(4)]) for i in range(n)}
 
 
-def ess(samples: torch.Tensor, lib: Library | None = None):
-    """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]."""
+def reserve(max_stamps: int = 0, max_n: int = 8, max_chains: int = 0, weighted: bool = False,
+            pixel_method: bool = False, max_shear_gal: int = 0, max_points: int = 0, bias: bool = False,
+            max_boot: int = 0, lib: Library | None = None):
+    """bsi_reserve: size the handle's workspace so that calls within the
+    limits neither allocate nor fail under graph capture."""
+    lib = lib or get()
+    cfg = N.ReserveCfg(int(max_stamps), int(max_n), int(max_chains), int(bool(weighted)),
+                       int(bool(pixel_method)), int(max_shear_gal), int(max_points), int(bool(bias)),
+                       int(max_boot))
+    lib.check(lib.lib.bsi_reserve(lib.h, C.byref(cfg)), "bsi_reserve")
+
+
+def ess(samples: torch.Tensor, lib: Library | None = None, split: bool = False):
+    """(ESS [G, P], R-hat [G, P]) of samples [G, C, S, P]; with split=True
+    also the split R-hat [G, P] as a third element."""
     dev = samples.device
     lib = lib or get(dev.index or 0)
     samples = samples.contiguous().float()
     G, Cn, S, P = samples.shape
     e = torch.empty(G, P, dtype=torch.float32, device=dev)
     r = torch.empty(G, P, dtype=torch.float32, device=dev)
-    lib.check(lib.lib.bsi_ess(lib.h, G, Cn, S, P, _ptr(samples), _ptr(e), _ptr(r), _stream(dev)),
-              "bsi_ess")
-    return e, r
+    rs = torch.empty(G, P, dtype=torch.float32, device=dev) if split else None
+    lib.check(lib.lib.bsi_ess(lib.h, G, Cn, S, P, _ptr(samples), _ptr(e), _ptr(r), _ptr(rs),
+                              _stream(dev)), "bsi_ess")
+    return (e, r, rs) if split else (e, r)

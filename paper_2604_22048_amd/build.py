@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libbsi.so")
 SOURCES = ["transform.hip", "dft_mfma.hip", "likelihood.hip", "hmc.hip", "shear.hip", "bootstrap.hip",
-           "diag.hip", "slots.hip", "api.cpp",
+           "diag.hip", "slots.hip", "stage.hip", "api.cpp",
            "slots.cpp", "autotune.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,6 +26,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"), "-I", CSRC,
     "-Wno-unused-command-line-argument",
+    # lifetime mistakes (a returned temporary, a dangling reference) stop the build
+    "-Werror=return-stack-address", "-Werror=dangling",
 ]
 
 

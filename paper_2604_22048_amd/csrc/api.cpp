@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -110,24 +111,26 @@ Plan make_plan(bsi_handle h, const bsi_batch* b) {
   return p;
 }
 
-// Upload the plan's index arrays into the handle workspace.
-int upload_plan(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s) {
-  int rc;
+// Workspace of a batch's plan: stamp and galaxy index lists, pixel and bin
+// offsets (device), and their staging.
+struct PlanBytes {
+  size_t gidx, off, bin_off, ggidx;
+  size_t stage() const { return bsi_host::stage_size({gidx, off, bin_off, ggidx}); }
+};
+
+PlanBytes plan_bytes(const bsi_batch* b, const Plan& p) {
   const size_t n = (size_t)b->n_gal * p.E;     // stamps
-  if ((rc = ensure(h, h->gidx, n * sizeof(int32_t)))) return rc;
-  if ((rc = ensure(h, h->off, n * sizeof(int64_t)))) return rc;
-  if ((rc = ensure(h, h->bin_off, n * sizeof(int64_t)))) return rc;
-  if (p.E > 1 && (rc = ensure(h, h->ggidx, (size_t)b->n_gal * sizeof(int32_t)))) return rc;
-  hipError_t e;
-  if ((e = hipMemcpyAsync(h->gidx.p, p.gidx.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(h->off.p, b->off, n * sizeof(int64_t), hipMemcpyHostToDevice, s)) ||
-      (e = hipMemcpyAsync(h->bin_off.p, p.bin_off.data(), n * sizeof(int64_t), hipMemcpyHostToDevice, s)) ||
-      (p.E > 1 && (e = hipMemcpyAsync(h->ggidx.p, p.ggidx.data(), (size_t)b->n_gal * sizeof(int32_t),
-                                       hipMemcpyHostToDevice, s))))
-    return hip_fail(h, e, "plan upload");
-  // pageable sources: make sure the copies are done before the vectors die
-  if ((e = hipStreamSynchronize(s))) return hip_fail(h, e, "plan upload sync");
-  return BSI_OK;
+  return {n * sizeof(int32_t), n * sizeof(int64_t), n * sizeof(int64_t),
+          p.E > 1 ? (size_t)b->n_gal * sizeof(int32_t) : 0};
+}
+
+// Upload the plan's index arrays into the handle workspace (sized by prepare).
+int upload_plan(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s, bool cap) {
+  const PlanBytes pb = plan_bytes(b, p);
+  return stage_upload(h, s, cap, {{h->gidx.p, p.gidx.data(), pb.gidx},
+                                   {h->off.p, b->off, pb.off},
+                                   {h->bin_off.p, p.bin_off.data(), pb.bin_off},
+                                   {h->ggidx.p, p.ggidx.data(), pb.ggidx}});
 }
 
 // The class's stamps, and its galaxies (the same list when E = 1).
@@ -142,8 +145,6 @@ const int32_t* ggidx_ptr(bsi_handle h, const Plan& p, const ClassRange& c) {
 // Per-bin noise weights (sqrt w beside the spectrum, which is whitened) for
 // batches with several exposures or correlated noise.
 int noise_weights(bsi_handle h, const bsi_batch* b, const Plan& p, hipStream_t s) {
-  int rc;
-  if ((rc = ensure(h, h->sqw, (size_t)p.total_bins * sizeof(float)))) return rc;
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_whiten(b->noise_ps, gidx_ptr(h, c), c.count,
                                  static_cast<const int64_t*>(h->off.p),
@@ -158,8 +159,6 @@ inline bool weighted(const bsi_batch* b) { return b->n_exp > 1 || b->noise_ps !=
 
 int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* data,
                   const double* model, double* chi2, hipStream_t s) {
-  int rc;
-  if ((rc = ensure(h, h->dh, (size_t)p.total_bins * sizeof(float2)))) return rc;
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_stamp_dft(transform_of(h, c.N) == BSI_TRANSFORM_MFMA, data, model,
                                     gidx_ptr(h, c), c.count, static_cast<const int64_t*>(h->off.p),
@@ -168,6 +167,34 @@ int data_spectrum(bsi_handle h, const bsi_batch* b, const Plan& p, const float* 
     if (e != hipSuccess) return hip_fail(h, e, "dft_bins launch");
   }
   return BSI_OK;
+}
+
+// Every workspace buffer of a handle (an array: an initializer_list returned
+// from a function would refer to a temporary that dies with the return).
+std::array<DevBuf*, 14> all_buffers(bsi_handle h) {
+  return {&h->gidx, &h->ggidx, &h->off, &h->bin_off, &h->dh, &h->sqw, &h->chi2, &h->model, &h->state,
+          &h->partial, &h->pts, &h->shear_state, &h->bias_part, &h->bias_mc};
+}
+
+// Free replaced buffers and finished graphs; the caller has synchronised the
+// device, so nothing enqueued by the library can still use them.
+void release_retired(bsi_handle h) {
+  for (void* p : h->retired) (void)hipFree(p);
+  h->retired.clear();
+  for (void* p : h->retired_host) (void)hipHostFree(p);
+  h->retired_host.clear();
+  bsi_host::reap_graphs(h);
+  h->stage_pending = false;
+}
+
+// Largest stored spectrum (complex values) of one stamp of side <= max_n
+// under any slot plan a handle can choose.
+size_t max_bins_per_stamp(int max_n) {
+  size_t m = 0;
+  for (int N = 8; N <= max_n; ++N)
+    for (int P : kPlanP)
+      if (plan_valid(N, P)) m = std::max<size_t>(m, (size_t)make_slot_plan_p(N, P).nbins);
+  return m;
 }
 
 }  // namespace
@@ -222,7 +249,9 @@ int bsi_create(bsi_handle* out, int32_t device) {
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
   bool ok = hipStreamCreate(&h->own) == hipSuccess &&
-            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess;
+            hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming) == hipSuccess &&
+            hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; ok && i < kAuxStreams; ++i)
     ok = hipStreamCreate(&h->aux[i]) == hipSuccess &&
          hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming) == hipSuccess;
@@ -240,9 +269,12 @@ void bsi_destroy(bsi_handle h) {
   if (!h) return;
   (void)hipSetDevice(h->device);
   (void)hipDeviceSynchronize();
-  for (DevBuf* b : {&h->gidx, &h->off, &h->bin_off, &h->dh, &h->chi2, &h->model, &h->state,
-                    &h->partial, &h->pts, &h->shear_state})
+  release_retired(h);
+  for (DevBuf* b : all_buffers(h))
     if (b->p) (void)hipFree(b->p);
+  if (h->stage) (void)hipHostFree(h->stage);
+  if (h->ev_done) (void)hipEventDestroy(h->ev_done);
+  if (h->ev_stage) (void)hipEventDestroy(h->ev_stage);
   if (h->own) (void)hipStreamDestroy(h->own);
   for (int i = 0; i < kAuxStreams; ++i) {
     if (h->aux[i]) (void)hipStreamDestroy(h->aux[i]);
@@ -265,10 +297,15 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
   if (rc) return rc;
   if (batch->n_gal == 0) return BSI_OK;
   if (!params || !out) return fail(h, BSI_EINVAL, "params/out is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool cap = capturing(s);
   const Plan p = make_plan(h, batch);
-  if ((rc = upload_plan(h, batch, p, s))) return rc;
+  const PlanBytes pb = plan_bytes(batch, p);
+  if ((rc = prepare(h, s, cap, {{&h->gidx, pb.gidx}, {&h->off, pb.off}, {&h->bin_off, pb.bin_off},
+                                {&h->ggidx, pb.ggidx}}, pb.stage())))
+    return rc;
+  if ((rc = upload_plan(h, batch, p, s, cap))) return rc;
   const float rs = profile_rscale(batch->profile, batch->pixel_scale, batch->spergel_nu);
   for (const ClassRange& c : p.classes) {
     const int32_t* gi = gidx_ptr(h, c);
@@ -281,7 +318,7 @@ int bsi_render_stamps(bsi_handle h, const bsi_batch* batch, const float* params,
                         1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu, out, s, p.E);
     if (e != hipSuccess) return hip_fail(h, e, "render launch");
   }
-  return BSI_OK;
+  return finish(h, s, cap);
 }
 
 int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, const float* params,
@@ -297,17 +334,27 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     return fail(h, BSI_EINVAL, "unknown likelihood method %d", method);
   if (method == BSI_LIK_PIXEL && weighted(batch))
     return fail(h, BSI_EUNSUPPORTED, "several exposures / noise_ps need the k-space method");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool cap = capturing(s);
   const Plan p = make_plan(h, batch);
-  if ((rc = upload_plan(h, batch, p, s))) return rc;
+  const PlanBytes pb = plan_bytes(batch, p);
+  const bool pixel = method == BSI_LIK_PIXEL;
+  const bool mx = weighted(batch);
+  if ((rc = prepare(h, s, cap,
+                    {{&h->gidx, pb.gidx}, {&h->off, pb.off}, {&h->bin_off, pb.bin_off},
+                     {&h->ggidx, pb.ggidx}, {&h->dh, (size_t)p.total_bins * sizeof(float2)},
+                     {&h->sqw, mx ? (size_t)p.total_bins * sizeof(float) : 0},
+                     {&h->model, pixel ? (size_t)p.max_pixel * sizeof(double) : 0},
+                     {&h->chi2, pixel ? (size_t)batch->n_gal * sizeof(double) : 0}},
+                    pb.stage())))
+    return rc;
+  if ((rc = upload_plan(h, batch, p, s, cap))) return rc;
   const float rs = profile_rscale(batch->profile, batch->pixel_scale, batch->spergel_nu);
   const int64_t* off = static_cast<const int64_t*>(h->off.p);
   double* chi2 = nullptr;
   const double* model = nullptr;
-  if (method == BSI_LIK_PIXEL) {
-    if ((rc = ensure(h, h->model, (size_t)p.max_pixel * sizeof(double)))) return rc;
-    if ((rc = ensure(h, h->chi2, (size_t)batch->n_gal * sizeof(double)))) return rc;
+  if (pixel) {
     for (const ClassRange& c : p.classes) {
       hipError_t e = launch_render_f64(params, batch->psf_fwhm, gidx_ptr(h, c), c.count, off, c.N,
                                        rs, 1.0f / batch->pixel_scale, batch->profile, batch->spergel_nu,
@@ -318,7 +365,6 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
     chi2 = static_cast<double*>(h->chi2.p);
   }
   if ((rc = data_spectrum(h, batch, p, data, model, chi2, s))) return rc;
-  const bool mx = weighted(batch);
   if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
   for (const ClassRange& c : p.classes) {
     hipError_t e = launch_loglik(static_cast<const float2*>(h->dh.p),
@@ -329,7 +375,7 @@ int bsi_loglik_grad(bsi_handle h, const bsi_batch* batch, const float* data, con
                                  mx ? static_cast<const float*>(h->sqw.p) : nullptr);
     if (e != hipSuccess) return hip_fail(h, e, "loglik launch");
   }
-  return BSI_OK;
+  return finish(h, s, cap);
 }
 
 int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, const float* ref_xy,
@@ -369,16 +415,14 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   if (!data || !ref_xy || !init) return fail(h, BSI_EINVAL, "data/ref_xy/init is NULL");
   if (cfg->n_samples > 0 && !samples && !chain_stats && !status)
     return fail(h, BSI_EINVAL, "no output requested");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->own;
+  const bool cap = capturing(s);
   const Plan p = make_plan(h, batch);
-  if ((rc = upload_plan(h, batch, p, s))) return rc;
-  if ((rc = data_spectrum(h, batch, p, data, nullptr, nullptr, s))) return rc;
   const int C = cfg->n_chains;
   const bool mx = weighted(batch);
+  // every check before anything is enqueued
   if (mx && C > 4) return fail(h, BSI_EUNSUPPORTED, "several exposures / noise_ps: n_chains <= 4");
-  if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
-  if ((rc = ensure(h, h->state, (size_t)batch->n_gal * C * sizeof(ChainState)))) return rc;
   for (const ClassRange& c : p.classes) {
     const size_t lds = mx ? hmc_lds_bytes(c.N, C, c.P, 1, 1, p.E, true, nuts)
                      : nuts ? hmc_lds_bytes(c.N, C, c.P, 1, 1, 1, false, true)
@@ -387,6 +431,17 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     if (lds > 160 * 1024)
       return fail(h, BSI_EUNSUPPORTED, "N = %d with %d chains (and %d exposures) exceeds LDS", c.N, C, p.E);
   }
+  const PlanBytes pb = plan_bytes(batch, p);
+  if ((rc = prepare(h, s, cap,
+                    {{&h->gidx, pb.gidx}, {&h->off, pb.off}, {&h->bin_off, pb.bin_off},
+                     {&h->ggidx, pb.ggidx}, {&h->dh, (size_t)p.total_bins * sizeof(float2)},
+                     {&h->sqw, mx ? (size_t)p.total_bins * sizeof(float) : 0},
+                     {&h->state, (size_t)batch->n_gal * C * sizeof(ChainState)}},
+                    pb.stage())))
+    return rc;
+  if ((rc = upload_plan(h, batch, p, s, cap))) return rc;
+  if ((rc = data_spectrum(h, batch, p, data, nullptr, nullptr, s))) return rc;
+  if (mx && (rc = noise_weights(h, batch, p, s))) return rc;
 
   HmcArgs a{};
   a.dh = static_cast<const float2*>(h->dh.p);
@@ -485,7 +540,14 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       }
       return hipSuccess;
     };
-    if (cfg->use_graph && n_launch > 1) {
+    if (cap) {
+      // the caller's graph replays this call: its launches go in as they are,
+      // the sizes in sequence on the capturing stream
+      for (int k = 0; k < n_launch; ++k) {
+        hipError_t e = enqueue_serial(s);
+        if (e != hipSuccess) return hip_fail(h, e, "hmc advance launch");
+      }
+    } else if (cfg->use_graph && n_launch > 1) {
       hipGraph_t graph = nullptr;
       hipGraphExec_t exec = nullptr;
       hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
@@ -494,9 +556,15 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
       if (e == hipSuccess) e = e2;
       if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       for (int k = 0; e == hipSuccess && k < n_launch; ++k) e = hipGraphLaunch(exec, s);
-      if (exec) (void)hipGraphExecDestroy(exec);
-      if (graph) (void)hipGraphDestroy(graph);
-      if (e != hipSuccess) return hip_fail(h, e, "hmc graph");
+      if (e != hipSuccess) {
+        // nothing of the graph may still run unless a launch succeeded: wait, then destroy
+        (void)hipStreamSynchronize(s);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(h, e, "hmc graph");
+      }
+      // the replays are in flight: the graph is destroyed once they have run
+      if ((rc = keep_graph(h, exec, graph, s))) return rc;
     } else {
       for (int k = 0; k < n_launch; ++k) {
         hipError_t e = enqueue(s);
@@ -507,6 +575,7 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
   hipError_t e = launch_hmc_finalize(static_cast<const ChainState*>(h->state.p), batch->n_gal, C,
                                      cfg->n_samples, chain_stats, status, s);
   if (e != hipSuccess) return hip_fail(h, e, "hmc finalize launch");
+  if ((rc = finish(h, s, cap))) return rc;
   if (!stream) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "hmc sync");
@@ -587,26 +656,27 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
   if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
   if (n_pts == 0) return BSI_OK;
   if (!pts || !logpost) return fail(h, BSI_EINVAL, "pts/logpost is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool cap = capturing(s);
+  const int n_blocks = shear_blocks(n_gal, n_pts);
+  const size_t pts_bytes = pts_on_device ? 0 : (size_t)n_pts * 5 * sizeof(double);
+  if ((rc = prepare(h, s, cap, {{&h->pts, pts_bytes},
+                                {&h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)}},
+                    stage_size({pts_bytes}))))
+    return rc;
   const double* dpts = pts;
   if (!pts_on_device) {
-    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
-    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "points upload");
+    if ((rc = stage_upload(h, s, cap, {{h->pts.p, pts, pts_bytes}}))) return rc;
     dpts = static_cast<const double*>(h->pts.p);
   }
-  const int n_blocks = shear_blocks(n_gal, n_pts);
-  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
   const ShearArgs a = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, n_pts, dpts,
                                  static_cast<double*>(h->partial.p), grad != nullptr);
   hipError_t e = launch_shear(a, n_blocks, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear launch");
   e = launch_shear_reduce(a.partial, n_blocks, n_pts, dpts, logpost, grad, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
-  return BSI_OK;
+  return finish(h, s, cap);
 }
 
 int bsi_shear_galaxy_loglik(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
@@ -621,25 +691,26 @@ int bsi_shear_galaxy_loglik(bsi_handle h, int32_t n_gal, int32_t K, const float*
   if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
   if (n_pts == 0 || n_gal == 0) return BSI_OK;
   if (!pts || !ell) return fail(h, BSI_EINVAL, "pts/ell is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool cap = capturing(s);
+  const int n_blocks = shear_blocks(n_gal, n_pts);
+  const size_t pts_bytes = pts_on_device ? 0 : (size_t)n_pts * 5 * sizeof(double);
+  if ((rc = prepare(h, s, cap, {{&h->pts, pts_bytes},
+                                {&h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)}},
+                    stage_size({pts_bytes}))))
+    return rc;
   const double* dpts = pts;
   if (!pts_on_device) {
-    if ((rc = ensure(h, h->pts, (size_t)n_pts * 5 * sizeof(double)))) return rc;
-    hipError_t e = hipMemcpyAsync(h->pts.p, pts, (size_t)n_pts * 5 * sizeof(double),
-                                  hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(h, e, "points upload");
+    if ((rc = stage_upload(h, s, cap, {{h->pts.p, pts, pts_bytes}}))) return rc;
     dpts = static_cast<const double*>(h->pts.p);
   }
-  const int n_blocks = shear_blocks(n_gal, n_pts);
-  if ((rc = ensure(h, h->partial, (size_t)n_blocks * n_pts * 6 * sizeof(double)))) return rc;
   ShearArgs a = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, n_pts, dpts,
                            static_cast<double*>(h->partial.p), 0);
   a.per_gal = ell;
   hipError_t e = launch_shear(a, n_blocks, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear launch");
-  return BSI_OK;
+  return finish(h, s, cap);
 }
 
 int bsi_shear_bias(bsi_handle h, int32_t n_gal, int32_t n_pts, const double* ell_plus,
@@ -654,20 +725,19 @@ int bsi_shear_bias(bsi_handle h, int32_t n_gal, int32_t n_pts, const double* ell
   if (!(g_abs > 0.0) || !std::isfinite(g_abs)) return fail(h, BSI_EINVAL, "g_abs must be positive");
   if (!ell_plus || !ell_minus || !gpts || !stats) return fail(h, BSI_EINVAL, "ell/gpts/stats is NULL");
   if (n_boot > 0 && !counts) return fail(h, BSI_EINVAL, "counts is NULL");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool cap = capturing(s);
   const BiasPlan b = bias_plan(n_gal, n_pts, n_boot);
   int rc;
-  if ((rc = ensure(h, h->bias_part, b.partial_doubles * sizeof(double)))) return rc;
-  double* mcp = mc;
-  if (!mcp) {
-    if ((rc = ensure(h, h->bias_mc, (size_t)b.R * 2 * sizeof(double)))) return rc;
-    mcp = static_cast<double*>(h->bias_mc.p);
-  }
+  if ((rc = prepare(h, s, cap, {{&h->bias_part, b.partial_doubles * sizeof(double)},
+                                {&h->bias_mc, mc ? 0 : (size_t)b.R * 2 * sizeof(double)}})))
+    return rc;
+  double* mcp = mc ? mc : static_cast<double*>(h->bias_mc.p);
   hipError_t e = launch_bias(b, counts, ell_plus, ell_minus, n_gal, n_pts, gpts, g_abs,
                              static_cast<double*>(h->bias_part.p), gmean, mcp, stats, s);
   if (e != hipSuccess) return hip_fail(h, e, "bias launch");
-  return BSI_OK;
+  return finish(h, s, cap);
 }
 
 int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
@@ -691,16 +761,18 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
   for (int j = 0; j < 5; ++j)
     if (!(cfg->inv_mass[j] > 0.0) || !std::isfinite(cfg->inv_mass[j]))
       return fail(h, BSI_EINVAL, "inv_mass entries must be positive");
-  hipSetDevice(h->device);
+  (void)hipSetDevice(h->device);
   hipStream_t s = stream ? static_cast<hipStream_t>(stream) : h->own;
+  const bool cap = capturing(s);
   const int n_blocks = shear_blocks(n_gal, C);
-  if ((rc = ensure(h, h->pts, (size_t)C * 5 * sizeof(double)))) return rc;
-  if ((rc = ensure(h, h->partial, (size_t)n_blocks * C * 6 * sizeof(double)))) return rc;
-  if ((rc = ensure(h, h->shear_state, (size_t)C * sizeof(ShearChain)))) return rc;
-  hipError_t e = hipMemcpyAsync(h->pts.p, init, (size_t)C * 5 * sizeof(double),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(h, e, "start points upload");
+  const size_t pts_bytes = (size_t)C * 5 * sizeof(double);
+  if ((rc = prepare(h, s, cap, {{&h->pts, pts_bytes},
+                                {&h->partial, (size_t)n_blocks * C * 6 * sizeof(double)},
+                                {&h->shear_state, (size_t)C * sizeof(ShearChain)}},
+                    stage_size({pts_bytes}))))
+    return rc;
+  if ((rc = stage_upload(h, s, cap, {{h->pts.p, init, pts_bytes}}))) return rc;
+  hipError_t e;
 
   double* dpts = static_cast<double*>(h->pts.p);
   const ShearArgs sa = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, C, dpts,
@@ -740,7 +812,7 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
     return hipSuccess;
   };
   const int T = a.t_stop;
-  if (cfg->use_graph && T > 1) {
+  if (!cap && cfg->use_graph && T > 1) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     e = hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed);
@@ -749,9 +821,13 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     for (int k = 0; e == hipSuccess && k < T; ++k) e = hipGraphLaunch(exec, s);
-    if (exec) (void)hipGraphExecDestroy(exec);
-    if (graph) (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return hip_fail(h, e, "shear hmc graph");
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      return hip_fail(h, e, "shear hmc graph");
+    }
+    if ((rc = keep_graph(h, exec, graph, s))) return rc;
   } else {
     for (int k = 0; k < T; ++k) {
       e = trajectory(s);
@@ -760,6 +836,7 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
   }
   e = launch_shear_hmc_stats(a.state, C, a.S, chain_stats, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear hmc stats");
+  if ((rc = finish(h, s, cap))) return rc;
   if (!stream) {
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(h, e, "shear hmc sync");
@@ -767,8 +844,59 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
   return BSI_OK;
 }
 
+int bsi_reserve(bsi_handle h, const bsi_reserve_cfg* r) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  if (!r) return fail(h, BSI_EINVAL, "cfg is NULL");
+  if (r->max_stamps < 0 || r->max_shear_gal < 0 || r->max_points < 0 || r->max_chains < 0 ||
+      r->max_boot < 0)
+    return fail(h, BSI_EINVAL, "negative limit");
+  if (r->max_stamps > 0 && (r->max_n < 8 || r->max_n > kMaxN))
+    return fail(h, BSI_EUNSUPPORTED, "max_n %d outside [8, %d]", r->max_n, kMaxN);
+  if (r->max_chains > 16) return fail(h, BSI_EINVAL, "max_chains must be 0..16");
+  if (r->bias && (r->max_points < 1 || r->max_points > 8192))
+    return fail(h, BSI_EINVAL, "bias workspace needs max_points in 1..8192");
+  (void)hipSetDevice(h->device);
+  hipError_t e = hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(h, e, "reserve: device synchronisation");
+  release_retired(h);
+  const size_t S = (size_t)r->max_stamps;
+  const size_t bins = S ? max_bins_per_stamp(r->max_n) : 0;
+  const size_t N2 = (size_t)r->max_n * r->max_n;
+  // shear partial sums: the largest blocks x points over every point count
+  size_t partial = 0;
+  const int64_t sg = std::max<int64_t>(r->max_shear_gal, 1);
+  const int sgi = (int)std::min<int64_t>(sg, 1 << 30);
+  for (int np = 1; np <= r->max_points; ++np)
+    partial = std::max(partial, (size_t)shear_blocks(sgi, np) * np * 6 * sizeof(double));
+  size_t bias_part = 0, bias_mc = 0;
+  if (r->bias) {
+    bias_part = std::max(bias_plan(std::max(sgi, 1), r->max_points, r->max_boot).partial_doubles,
+                         bias_plan(1 << 30, r->max_points, r->max_boot).partial_doubles) * sizeof(double);
+    bias_mc = (size_t)(r->max_boot + 1) * 2 * sizeof(double);
+  }
+  const size_t stage = std::max(bsi_host::stage_size({S * 4, S * 8, S * 8, r->weighted ? S * 4 : 0}),
+                                bsi_host::stage_size({(size_t)r->max_points * 5 * sizeof(double)}));
+  struct { DevBuf* b; size_t n; } want[] = {
+      {&h->gidx, S * 4}, {&h->ggidx, r->weighted ? S * 4 : 0}, {&h->off, S * 8}, {&h->bin_off, S * 8},
+      {&h->dh, S * bins * sizeof(float2)}, {&h->sqw, r->weighted ? S * bins * sizeof(float) : 0},
+      {&h->state, S * (size_t)r->max_chains * sizeof(ChainState)},
+      {&h->model, r->pixel_method ? S * N2 * sizeof(double) : 0},
+      {&h->chi2, r->pixel_method ? S * sizeof(double) : 0},
+      {&h->pts, (size_t)r->max_points * 5 * sizeof(double)}, {&h->partial, partial},
+      {&h->shear_state, (size_t)r->max_points * sizeof(ShearChain)},
+      {&h->bias_part, bias_part}, {&h->bias_mc, bias_mc}};
+  int rc;
+  for (auto& w : want)
+    if ((rc = bsi_host::grow(h, *w.b, w.n))) return rc;
+  if ((rc = bsi_host::grow_stage(h, stage))) return rc;
+  release_retired(h);   // the buffers just replaced were idle
+  h->pending = false;
+  return BSI_OK;
+}
+
 int bsi_ess(bsi_handle h, int32_t n_gal, int32_t n_chains, int32_t n_samples, int32_t n_par,
-            const float* samples, float* ess, float* rhat, bsi_stream stream) {
+            const float* samples, float* ess, float* rhat, float* rhat_split, bsi_stream stream) {
   if (!h) return BSI_EINVAL;
   h->err.clear();
   if (n_gal < 0 || n_chains < 1 || n_chains > 16 || n_samples < 4 || n_par < 1)
@@ -776,12 +904,12 @@ int bsi_ess(bsi_handle h, int32_t n_gal, int32_t n_chains, int32_t n_samples, in
   if ((size_t)n_chains * n_samples * sizeof(double) + 256 * sizeof(double) > 150 * 1024)
     return fail(h, BSI_EUNSUPPORTED, "n_chains * n_samples too large for LDS");
   if (n_gal == 0) return BSI_OK;
-  if (!samples || (!ess && !rhat)) return fail(h, BSI_EINVAL, "NULL samples or outputs");
-  hipSetDevice(h->device);
-  hipError_t e = launch_ess(n_gal, n_chains, n_samples, n_par, samples, ess, rhat,
+  if (!samples || (!ess && !rhat && !rhat_split)) return fail(h, BSI_EINVAL, "NULL samples or outputs");
+  (void)hipSetDevice(h->device);
+  hipError_t e = launch_ess(n_gal, n_chains, n_samples, n_par, samples, ess, rhat, rhat_split,
                             static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return hip_fail(h, e, "ess launch");
-  return BSI_OK;
+  return BSI_OK;   // uses no handle workspace
 }
 
 }  // extern "C"

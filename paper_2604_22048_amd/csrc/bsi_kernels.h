@@ -281,6 +281,6 @@ inline hipError_t launch_stamp_dft(bool mfma, const float* data, const double* m
 
 // ---- diag.hip ----
 hipError_t launch_ess(int n_gal, int C, int S, int P, const float* samples, float* ess,
-                      float* rhat, hipStream_t s);
+                      float* rhat, float* rsplit, hipStream_t s);
 
 }  // namespace bsi

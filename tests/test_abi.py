@@ -52,6 +52,7 @@ int main(void) {
   printf("bsi_slots_cfg %zu\n", sizeof(bsi_slots_cfg));
   printf("bsi_request %zu\n", sizeof(bsi_request));
   printf("bsi_slots_info %zu\n", sizeof(bsi_slots_info));
+  printf("bsi_reserve_cfg %zu\n", sizeof(bsi_reserve_cfg));
   F(bsi_batch, psf_fwhm) F(bsi_batch, pixel_scale) F(bsi_batch, profile) F(bsi_batch, spergel_nu)
   F(bsi_hmc_cfg, step_size) F(bsi_hmc_cfg, form) F(bsi_hmc_cfg, seed) F(bsi_hmc_cfg, uid_base)
   F(bsi_hmc_cfg, trace) F(bsi_hmc_cfg, waves_per_chain) F(bsi_hmc_cfg, sampler) F(bsi_hmc_cfg, max_tree_depth)
@@ -63,6 +64,8 @@ int main(void) {
   F(bsi_slots_cfg, ess_target) F(bsi_slots_cfg, ess_every)
   F(bsi_request, stamp) F(bsi_request, psf_fwhm) F(bsi_request, ref_y) F(bsi_request, init)
   F(bsi_slots_info, budget) F(bsi_slots_info, arena_largest_free)
+  F(bsi_reserve_cfg, max_n) F(bsi_reserve_cfg, max_shear_gal) F(bsi_reserve_cfg, max_points)
+  F(bsi_reserve_cfg, max_boot)
   return 0;
 }
 """
@@ -72,6 +75,9 @@ int main(void) {
         open(c, "w").write(prog)
         subprocess.check_call(["gcc", "-I", os.path.dirname(HEADER), c, "-o", exe])
         out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([exe], text=True).splitlines())
+    assert int(out["bsi_reserve_cfg"]) == C.sizeof(native.ReserveCfg)
+    for m in ("max_n", "max_shear_gal", "max_points", "max_boot"):
+        assert int(out[f"bsi_reserve_cfg.{m}"]) == getattr(native.ReserveCfg, m).offset, m
     assert int(out["bsi_batch"]) == C.sizeof(native.Batch)
     assert int(out["bsi_interim"]) == C.sizeof(native.Interim)
     assert int(out["bsi_hmc_cfg"]) == C.sizeof(native.HmcCfg)
@@ -86,7 +92,7 @@ int main(void) {
             cls = {"bsi_batch": native.Batch, "bsi_hmc_cfg": native.HmcCfg,
                    "bsi_true_prior": native.TruePrior, "bsi_shear_hmc_cfg": native.ShearHmcCfg,
                    "bsi_slots_cfg": native.SlotsCfg, "bsi_request": native.Request,
-                   "bsi_slots_info": native.SlotsInfo}[t]
+                   "bsi_slots_info": native.SlotsInfo, "bsi_reserve_cfg": native.ReserveCfg}[t]
             assert getattr(cls, m).offset == int(val), key
 
 
@@ -94,7 +100,7 @@ def test_no_device_and_null_handle_paths(native):
     lib = native.load()
     n = C.c_int32(-1)
     assert lib.bsi_device_count(C.byref(n)) == 0 and n.value >= 0
-    assert lib.bsi_version() == 2
+    assert lib.bsi_version() == 3
     if n.value == 0:
         h = C.c_void_p()
         assert lib.bsi_create(C.byref(h), 0) == -5
@@ -102,7 +108,9 @@ def test_no_device_and_null_handle_paths(native):
     b = native.Batch()
     assert lib.bsi_render_stamps(None, C.byref(b), None, None, None) == -1
     assert lib.bsi_loglik_grad(None, C.byref(b), None, None, None, None, None, 0, None) == -1
-    assert lib.bsi_ess(None, 1, 1, 10, 1, None, None, None, None) == -1
+    assert lib.bsi_ess(None, 1, 1, 10, 1, None, None, None, None, None) == -1
+    r = native.ReserveCfg(max_stamps=10, max_n=53, max_chains=4)
+    assert lib.bsi_reserve(None, C.byref(r)) == -1
     assert lib.bsi_shear_hmc(None, 1, 1, None, None, None, None, None, None, None, None, None,
                              None, None) == -1
     assert lib.bsi_slots_create(None, None, None, None) == -1

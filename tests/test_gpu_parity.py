@@ -413,14 +413,19 @@ def test_ess_rhat_parity(bsi):
                 v[0] = e[0]
                 for k in range(1, S):
                     v[k] = rho * v[k - 1] + e[k]
-                x[g, c, :, p] = v + 0.1 * c * (g == 2)
-    e, r = bsi.ess(torch.tensor(x).cuda())
-    e, r = e.cpu().numpy(), r.cpu().numpy()
-    for g in range(G):
-        for p in range(P):
-            xe = x[g, :, :, p].astype(np.float64)
-            assert abs(e[g, p] / diagnostics.ess(xe) - 1) < 1e-5, (g, p, e[g, p], diagnostics.ess(xe))
-            assert abs(r[g, p] / diagnostics.rhat(xe) - 1) < 1e-6
+                x[g, c, :, p] = v + 0.1 * c * (g == 2) + 0.8 * np.arange(S) / S * (g == 1)
+    # galaxy 2's chains sit at different levels, galaxy 1's all drift alike (seen by the
+    # split form only); S odd drops a middle draw in the split form
+    for S_ in (S, S - 1):
+        xs = np.ascontiguousarray(x[:, :, :S_])
+        e, r, rs = bsi.ess(torch.tensor(xs).cuda(), split=True)
+        e, r, rs = e.cpu().numpy(), r.cpu().numpy(), rs.cpu().numpy()
+        for g in range(G):
+            for p in range(P):
+                xe = xs[g, :, :, p].astype(np.float64)
+                assert abs(e[g, p] / diagnostics.ess(xe) - 1) < 1e-5, (g, p, e[g, p], diagnostics.ess(xe))
+                assert abs(r[g, p] / diagnostics.rhat(xe) - 1) < 1e-6
+                assert abs(rs[g, p] / diagnostics.split_rhat(xe) - 1) < 1e-6, (g, p, rs[g, p])
 
 
 def _shear_samples(rng, G, K):

@@ -225,3 +225,43 @@ def test_jittered_step_without_jitter_is_the_float32_step():
     for eps in (0.01, 0.0137, 0.5, 1e-3):
         for t in range(5):
             assert hmc.jittered_step(eps, 0.0, 7, 3, t) == hmc.f32(eps)
+
+
+@pytest.mark.parametrize("n", [40, 41])
+def test_split_rhat_closed_form(n):
+    """Split R-hat on draws built from an alternating pattern: each half-chain
+    of length m = floor(n/2) is a level a_h plus (+1, -1, +1, ...), so every
+    half-chain has the same sample variance v (m / (m - 1) for even m) and
+    mean a_h + pattern mean; the statistic is then sqrt(((m - 1)/m v +
+    var(means)) / v) exactly.  The levels rise within each chain (first half
+    a, second half a + d), which the classic statistic over whole chains
+    cannot see when every chain drifts alike."""
+    M, d = 3, 1.0
+    m = n // 2
+    pat = np.array([(-1.0) ** k for k in range(m)])
+    v = np.var(pat, ddof=1)                     # exact for the pattern
+    if m % 2 == 0:
+        assert abs(v - m / (m - 1.0)) < 1e-15
+    base = np.array([0.1, -0.2, 0.3])
+    x = np.empty((M, n))
+    for c in range(M):
+        x[c, :m] = base[c] + pat
+        x[c, n - m:] = base[c] + d + pat
+        if n % 2:
+            x[c, m] = 1e6                       # the middle draw of an odd n is dropped
+    levels = np.concatenate([base, base + d])
+    pat_mean = pat.mean()
+    want = math.sqrt(((m - 1.0) / m * v + np.var(levels + pat_mean, ddof=1)) / v)
+    assert abs(diagnostics.split_rhat(x) - want) < 1e-12
+    assert want > 1.05
+    # the same drift in every chain leaves the classic statistic near 1 (n even)
+    if n % 2 == 0:
+        assert diagnostics.rhat(x) < diagnostics.split_rhat(x)
+
+
+def test_split_rhat_on_iid_draws():
+    rng = np.random.default_rng(4)
+    x = rng.normal(size=(4, 4000))
+    assert abs(diagnostics.split_rhat(x) - 1.0) < 0.01
+    x[:, 2000:] += 1.0                           # every chain shifts half way through
+    assert diagnostics.rhat(x) < 1.05 and diagnostics.split_rhat(x) > 1.1
