@@ -367,6 +367,32 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
                         const double* pts, int32_t pts_on_device, double* logpost, double* grad,
                         bsi_stream stream);
 
+/* Capacity of the device scratch of bsi_shear_posterior_noalloc (per device). */
+#define BSI_NOALLOC_SCRATCH_BYTES (16 << 20)
+
+/*
+ * bsi_shear_posterior_noalloc -- bsi_shear_posterior for callers that cannot
+ * allocate device memory (code under graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and results (bitwise),
+ * with the per-block partial sums of the evaluation pass kept in a fixed
+ * device array of BSI_NOALLOC_SCRATCH_BYTES that the library holds on every
+ * device it runs on until the process ends, instead of handle workspace.
+ * The call allocates nothing and uses no handle workspace.
+ *   pts      [device] double[n_pts][5] (host points would need staging memory).
+ *   other arguments as for bsi_shear_posterior.
+ * The pass needs blocks x n_pts x 48 bytes of scratch, blocks =
+ * min(ceil(n_gal / 4), max(64, 4096 / ceil(n_pts / 64))); every n_pts <= 5461
+ * fits, larger counts fail with BSI_EINVAL when they exceed it.  All calls on
+ * one device share its scratch, and the array keeps the last call's contents
+ * (every entry a call reads, it has written first): calls that overlap on one
+ * device -- on different streams or handles, or different host threads --
+ * race.
+ */
+int bsi_shear_posterior_noalloc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                                const float* e2p, const float* log10s, const float* log10f,
+                                const bsi_true_prior* tp, const bsi_interim* interim, int32_t n_pts,
+                                const double* pts, double* logpost, double* grad, bsi_stream stream);
+
 /*
  * bsi_shear_galaxy_loglik -- the per-galaxy terms of bsi_shear_posterior's
  * sum (eq. likelihood-shear) at n_pts points:

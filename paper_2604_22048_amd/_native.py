@@ -20,6 +20,7 @@ PROFILE_SPERGEL = 2
 SPERGEL_NU_MIN = -0.85
 SPERGEL_NU_MAX = 4.0
 MAX_EXPOSURES = 16
+NOALLOC_SCRATCH_BYTES = 16 << 20
 LIK_KSPACE = 0
 LIK_PIXEL = 1
 METRIC_GIVEN = 0
@@ -115,6 +116,10 @@ SIGNATURES = {
                                       C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
                                       C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_int32,
                                       C.c_void_p, C.c_void_p, C.c_void_p]),
+    "bsi_shear_posterior_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
+                                              C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_void_p,
+                                              C.c_void_p, C.c_void_p]),
     "bsi_shear_galaxy_loglik": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                                           C.c_void_p, C.c_void_p, C.POINTER(TruePrior),
                                           C.POINTER(Interim), C.c_int32, C.c_void_p, C.c_int32,

@@ -252,6 +252,31 @@ def shear_posterior(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, int
     return (lp, gr) if want_grad else lp
 
 
+def shear_posterior_noalloc(e1p, e2p, log10s, log10f, pts: torch.Tensor, true_prior: TruePriorCfg,
+                            interim=None, want_grad: bool = False, lib: Library | None = None):
+    """bsi_shear_posterior_noalloc: as shear_posterior with device points, the
+    pass's partial sums in the library's fixed device scratch (no allocation
+    by the library; the outputs are allocated here by torch)."""
+    dev = e1p.device
+    lib = lib or get(dev.index or 0)
+    G, K = e1p.shape
+    e1p, e2p = e1p.contiguous().float(), e2p.contiguous().float()
+    log10s = log10s.contiguous().float() if log10s is not None else None
+    log10f = log10f.contiguous().float() if log10f is not None else None
+    assert isinstance(pts, torch.Tensor) and pts.is_cuda, "points must be a device tensor"
+    pts = pts.contiguous().double()
+    P = pts.shape[0]
+    lp = torch.empty(P, dtype=torch.float64, device=dev)
+    gr = torch.empty(P, 5, dtype=torch.float64, device=dev) if want_grad else None
+    tp = true_prior.c()
+    ip = _interim(interim)
+    lib.check(lib.lib.bsi_shear_posterior_noalloc(lib.h, G, K, _ptr(e1p), _ptr(e2p), _ptr(log10s),
+                                                  _ptr(log10f), C.byref(tp), C.byref(ip), P, _ptr(pts),
+                                                  _ptr(lp), _ptr(gr), _stream(dev)),
+              "bsi_shear_posterior_noalloc")
+    return (lp, gr) if want_grad else lp
+
+
 def shear_galaxy_loglik(e1p, e2p, log10s, log10f, pts, true_prior: TruePriorCfg, interim=None,
                         lib: Library | None = None):
     """Per-galaxy log-marginals ell[p, n] at points (g1, g2, mu_ln_s, sigma_ln_s,

@@ -245,9 +245,18 @@ int bsi_create(bsi_handle* out, int32_t device) {
     g_create_error = "hipSetDevice failed";
     return BSI_EHIP;
   }
+  // the allocation-free entry point's scratch: this device's address of the
+  // library's device array, looked up once per device with the device current
+  void* scratch = nullptr;
+  if (device >= kMaxDevices || noalloc_scratch(device, &scratch) != hipSuccess) {
+    (void)hipGetLastError();
+    g_create_error = "device scratch lookup failed";
+    return BSI_EHIP;
+  }
   bsi_ctx* h = new bsi_ctx();
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
+  h->scratch = scratch;
   bool ok = hipStreamCreate(&h->own) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming) == hipSuccess &&
@@ -677,6 +686,34 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
   e = launch_shear_reduce(a.partial, n_blocks, n_pts, dpts, logpost, grad, s);
   if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
   return finish(h, s, cap);
+}
+
+int bsi_shear_posterior_noalloc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
+                                const float* e2p, const float* log10s, const float* log10f,
+                                const bsi_true_prior* tp, const bsi_interim* ip, int32_t n_pts,
+                                const double* pts, double* logpost, double* grad, bsi_stream stream) {
+  if (!h) return BSI_EINVAL;
+  h->err.clear();
+  int rc = check_shear_inputs(h, n_gal, K, e1p, e2p, log10s, log10f, tp, ip);
+  if (rc) return rc;
+  if (n_pts < 0) return fail(h, BSI_EINVAL, "n_pts < 0");
+  if (n_pts == 0) return BSI_OK;
+  if (!pts || !logpost) return fail(h, BSI_EINVAL, "pts/logpost is NULL");
+  const int n_blocks = shear_blocks(n_gal, n_pts);
+  const size_t need = (size_t)n_blocks * n_pts * 6 * sizeof(double);
+  if (need > (size_t)BSI_NOALLOC_SCRATCH_BYTES)
+    return fail(h, BSI_EINVAL, "%d galaxies at %d points need %zu bytes of scratch, more than %d",
+                n_gal, n_pts, need, BSI_NOALLOC_SCRATCH_BYTES);
+  if (!h->scratch) return fail(h, BSI_EHIP, "device scratch unavailable");
+  (void)hipSetDevice(h->device);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ShearArgs a = shear_args(n_gal, K, e1p, e2p, log10s, log10f, tp, ip, n_pts, pts,
+                                 static_cast<double*>(h->scratch), grad != nullptr);
+  hipError_t e = launch_shear(a, n_blocks, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear launch");
+  e = launch_shear_reduce(a.partial, n_blocks, n_pts, pts, logpost, grad, s);
+  if (e != hipSuccess) return hip_fail(h, e, "shear reduce launch");
+  return BSI_OK;
 }
 
 int bsi_shear_galaxy_loglik(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,

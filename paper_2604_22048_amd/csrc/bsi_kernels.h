@@ -226,6 +226,10 @@ struct ShearHmcArgs {
   float* trace;        // [C][W+S][4] or NULL
 };
 hipError_t launch_shear_hmc_update(const ShearHmcArgs& a, int init, hipStream_t s);
+// Device address of the allocation-free pass's scratch array on `device`
+// (which must be current); looked up once per device.
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch(int device, void** ptr);
 hipError_t launch_shear_hmc_stats(const ShearChain* st, int C, int S, double* stats, hipStream_t s);
 
 // ---- slots.hip ----

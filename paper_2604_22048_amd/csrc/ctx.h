@@ -68,6 +68,7 @@ struct bsi_ctx {
   std::vector<void*> retired;         // replaced device buffers
   std::vector<void*> retired_host;    // replaced staging buffers
   std::vector<PendingGraph> graphs;   // graphs whose replays may still run
+  void* scratch = nullptr;   // this device's allocation-free scratch (device address)
 };
 
 namespace bsi_host {

@@ -11,7 +11,10 @@
 // the sums across lanes and galaxies, the logarithm and the gradient assembly
 // are float64.  Per-block partials are reduced in a fixed order (bitwise
 // reproducible).
+#include "bsi.h"
 #include "bsi_kernels.h"
+
+#include <mutex>
 
 namespace bsi {
 
@@ -503,6 +506,33 @@ hipError_t launch_shear_reduce(const double* partial, int n_blocks, int n_pts, c
   hipLaunchKernelGGL(shear_reduce_kernel, dim3(n_pts), dim3(kRedThreads), 0, s, partial, n_blocks,
                      n_pts, pts, logpost, grad);
   return hipGetLastError();
+}
+
+// ---- allocation-free evaluation pass ---------------------------------------
+// Scratch of bsi_shear_posterior_noalloc: the per-block partial sums of one
+// pass (blocks x points x 6 doubles), in a file-scope device array that every
+// device holds, at its own address, while the library is loaded.  Host code
+// never uses the array's name as an address: noalloc_scratch reads each
+// device's address once, with that device current, through
+// hipGetSymbolAddress, and the entry point passes that pointer to the kernels
+// as the ordinary entry point passes its workspace.  shear_kernel writes every
+// (block, point) entry before shear_reduce_kernel reads it, so nothing needs
+// clearing between calls.
+static __device__ __align__(256) unsigned char scratch[BSI_NOALLOC_SCRATCH_BYTES];
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t noalloc_scratch(int device, void** ptr) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = p;
+  }
+  *ptr = g_scratch_ptr[device];
+  return hipSuccess;
 }
 
 hipError_t launch_shear_hmc_update(const ShearHmcArgs& a, int init, hipStream_t s) {
