@@ -380,9 +380,10 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
  * The call allocates nothing and uses no handle workspace.
  *   pts      [device] double[n_pts][5] (host points would need staging memory).
  *   other arguments as for bsi_shear_posterior.
- * The pass needs blocks x n_pts x 48 bytes of scratch, blocks =
- * min(ceil(n_gal / 4), max(64, 4096 / ceil(n_pts / 64))); every n_pts <= 5461
- * fits, larger counts fail with BSI_EINVAL when they exceed it.  All calls on
+ * The pass needs blocks x n_pts x 48 bytes of scratch for its partial sums,
+ * blocks = min(ceil(n_gal / 4), max(16, 512 / ceil(n_pts / 64))); every
+ * n_pts <= 21845 fits, larger counts fail with BSI_EINVAL when they exceed
+ * it.  All calls on
  * one device share its scratch, and the array keeps the last call's contents
  * (every entry a call reads, it has written first): calls that overlap on one
  * device -- on different streams or handles, or different host threads --

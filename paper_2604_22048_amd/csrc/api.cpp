@@ -615,10 +615,13 @@ int check_shear_inputs(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
 }
 
 // Blocks of one evaluation pass over n_gal galaxies at n_pts points (four
-// galaxies per block and pass, at most 4096 blocks over all point chunks).
+// waves per block, one galaxy per wave at a time): about one round of
+// resident workgroups over all point chunks (two per compute unit on 256
+// units), so that each wave runs through several galaxies and prefetches the
+// next one's samples while it evaluates the current one.
 int shear_blocks(int n_gal, int n_pts) {
   const int chunks = (n_pts + 63) / 64;
-  return std::max(1, std::min((n_gal + 3) / 4, std::max(64, 4096 / chunks)));
+  return std::max(1, std::min((n_gal + 3) / 4, std::max(16, 512 / chunks)));
 }
 
 ShearArgs shear_args(int32_t n_gal, int32_t K, const float* e1p, const float* e2p,
@@ -646,6 +649,14 @@ ShearArgs shear_args(int32_t n_gal, int32_t K, const float* e1p, const float* e2
   a.partial = partial;
   a.want_grad = want_grad;
   a.per_gal = nullptr;
+  // the interim ellipticity density (eq. interim-prior, the unit-disk form) in
+  // log2 units: E' coefficient log2(e) / (2 sigma0^2) and log2 of its normaliser
+  // Z0 = pi (2 s^2 - 8 s^4 + 16 s^6 (1 - exp(-1 / (2 s^2))))
+  const double s0 = ip->sigma_e, s2 = s0 * s0;
+  const double z0 = M_PI * (2.0 * s2 - 8.0 * s2 * s2 + 16.0 * s2 * s2 * s2 * (1.0 - std::exp(-1.0 / (2.0 * s2))));
+  a.b0 = (float)(1.0 / (2.0 * s2) / M_LN2);
+  a.lz0 = (float)std::log2(z0);
+  a.logK = std::log((double)K);
   return a;
 }
 

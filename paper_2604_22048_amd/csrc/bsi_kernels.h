@@ -176,7 +176,11 @@ struct ShearArgs {
   double* partial;                 // device [n_blocks][n_pts][6]
   int want_grad;
   double* per_gal;                 // device [n_pts][n_gal] per-galaxy log-marginals, or NULL
+  float b0, lz0;                   // interim ellipticity density in log2 units: E' coefficient,
+                                   // log2 of its normaliser
+  double logK;                     // ln K
 };
+
 hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s);
 
 // ---- bootstrap.hip ----

@@ -35,91 +35,93 @@ __device__ __forceinline__ double log_z_e(int kind, double sig, double emax) {
 __device__ __forceinline__ double dlog_z_e(int kind, double sig, double emax) {
   if (kind == 0) {
     const double c = 1.0 / (2.0 * sig * sig), ex = exp(-c);
-    const double f = 2 * sig * sig - 8 * pow(sig, 4) + 16 * pow(sig, 6) * (1.0 - ex);
-    const double fp = 4 * sig - 32 * pow(sig, 3) + 96 * pow(sig, 5) * (1.0 - ex) - 16 * pow(sig, 3) * ex;
+    const double s2 = sig * sig, s3 = s2 * sig, s4 = s2 * s2, s5 = s4 * sig, s6 = s4 * s2;
+    const double f = 2 * s2 - 8 * s4 + 16 * s6 * (1.0 - ex);
+    const double fp = 4 * sig - 32 * s3 + 96 * s5 * (1.0 - ex) - 16 * s3 * ex;
     return fp / f;
   }
   const double c = emax * emax / (2.0 * sig * sig), ex = exp(-c);
   return 2.0 / sig - 2.0 * c * ex / (sig * (1.0 - ex));
 }
 
-// Per-point constants, computed once per block (float64, rounded to float).
+// Per-point constants, computed once per block.  The log weights are carried
+// in log2 units (lw2 = ln w / ln 2) so that their exponentials are bare
+// exp2; the point-independent part of ln w is folded into each sample's c0,
+// the sample-independent part (k0) is added after the log-sum-exp.
 struct Point {
-  float g1, g2, mu, inv2se2, inv_sig_s;
-  float lnZ, dlnZ, inv_se3;
-  float lw0;       // 2 ln(1 - |g|^2) (+ size normaliser ln(ln 10) - ln sig_s - ln(2 pi)/2 + ln span_s)
-  float c1, c2;    // 4 g / (1 - |g|^2): the Jacobian's |g| derivative
-  float pad;
+  float g1, g2, gg;       // shear and |g|^2
+  float a1;               // E coefficient of lw2: log2(e) / (2 sigma_e^2)
+  float dlp;              // natural-unit E coefficient -1 / (2 sigma_e^2) (gradient)
+  float w0;               // 2 - dlp: w = c - dlp = dlp E + w0
+  float kz, kz0;          // zq = kz log10 s + kz0 = sqrt(log2(e) / 2) z, z = (ln s - mu) / sigma
+  float du;               // -4 log2(1 - |g|): bound of -2 log2 B on the unit disk
+  double g1d, g2d;        // shear in float64 (gradient assembly)
+  double k0;              // 2 ln(1 - |g|^2) - ln Z (+ size normaliser): natural units
+  double c1, c2;          // 4 g / (1 - |g|^2): the Jacobian's |g| derivative
+  double inv_sig_s, inv_se3, dlnZ;
 };
+
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr double kLn2 = 0.69314718055994530942;
+// zq^2 = log2(e) z^2 / 2, so z = zq / kZq and z^2 = zq^2 / kZq^2
+constexpr double kZq = 0.84932180028801904272;   // sqrt(log2(e) / 2)
 
 __device__ Point make_point(const double* p, const ShearArgs& a) {
   Point q;
   q.g1 = (float)p[0];
   q.g2 = (float)p[1];
-  q.mu = (float)p[2];
-  q.inv2se2 = (float)(1.0 / (2.0 * p[4] * p[4]));
-  q.inv_sig_s = (float)(1.0 / p[3]);
-  q.inv_se3 = (float)(1.0 / (p[4] * p[4] * p[4]));
-  q.lnZ = (float)log_z_e(a.e_kind, p[4], a.e_max);
-  q.dlnZ = (float)dlog_z_e(a.e_kind, p[4], a.e_max);
   const double gg = p[0] * p[0] + p[1] * p[1];
-  double lw0 = 2.0 * log(1.0 - gg);
-  if (a.size_term) lw0 += log(kLn10) - log(p[3]) - 0.5 * log(2.0 * kPi) + a.log_span_s;
-  q.lw0 = (float)lw0;
-  q.c1 = (float)(4.0 * p[0] / (1.0 - gg));
-  q.c2 = (float)(4.0 * p[1] / (1.0 - gg));
-  q.pad = 0.f;
+  q.gg = (float)gg;
+  const double i2s = 1.0 / (2.0 * p[4] * p[4]);
+  q.a1 = (float)(kLog2e * i2s);
+  q.dlp = (float)(-i2s);
+  q.w0 = (float)(2.0 + i2s);
+  q.kz = (float)(kZq * kLn10 / p[3]);
+  q.kz0 = (float)(-kZq * p[2] / p[3]);
+  // rounded up, so that the weight bound stays a bound
+  q.du = (float)(-4.0 * log2(1.0 - sqrt(gg)) * (1.0 + 1e-6) + 1e-6);
+  q.g1d = p[0];
+  q.g2d = p[1];
+  double k0 = 2.0 * log(1.0 - gg) - log_z_e(a.e_kind, p[4], a.e_max);
+  if (a.size_term) k0 += log(kLn10) - log(p[3]) - 0.5 * log(2.0 * kPi) + a.log_span_s;
+  q.k0 = k0;
+  q.c1 = 4.0 * p[0] / (1.0 - gg);
+  q.c2 = 4.0 * p[1] / (1.0 - gg);
+  q.inv_sig_s = 1.0 / p[3];
+  q.inv_se3 = 1.0 / (p[4] * p[4] * p[4]);
+  q.dlnZ = dlog_z_e(a.e_kind, p[4], a.e_max);
   return q;
 }
 
-// Inverse shear of one sample at one point: eps = (eps' - g) / (1 - conj(g) eps')
-// as numerator a = eps' - g, denominator b = 1 - conj(g) eps', B = |b|^2 and
-// E = |eps|^2 = |a|^2 / B.
-struct Geo {
-  float ar, ai, br, bi, iB, E;
-};
-
-__device__ __forceinline__ Geo geo(const Point& P, float e1, float e2) {
-  Geo q;
-  q.ar = e1 - P.g1;
-  q.ai = e2 - P.g2;
-  q.br = 1.0f - (P.g1 * e1 + P.g2 * e2);
-  q.bi = P.g2 * e1 - P.g1 * e2;
-  const float B = q.br * q.br + q.bi * q.bi;
-  q.iB = __builtin_amdgcn_rcpf(B);
-  q.E = (q.ar * q.ar + q.ai * q.ai) * q.iB;
-  return q;
+// Wave maximum with DPP row shifts and row broadcasts (lanes without a
+// source keep their own value); the total is read from lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_max_step(float x) {
+  const int v = __float_as_int(x);
+  return fmaxf(x, __int_as_float(__builtin_amdgcn_update_dpp(v, v, CTRL, ROW_MASK, 0xf, false)));
 }
 
-// ln w of one sample at one point without the point-independent part c0
-// (interim ellipticity and flux terms): true ellipticity density, shear
-// Jacobian 2 ln(1 - |g|^2) - 2 ln B, and the size term.
-template <int EK, bool SZ>
-__device__ __forceinline__ float logw(const Point& P, const ShearArgs& a, const Geo& q, float ls) {
-  float lp;
-  if (EK == 0)
-    lp = (q.E < 1.0f) ? 2.0f * __logf(1.0f - q.E) - q.E * P.inv2se2 - P.lnZ : -INFINITY;
-  else
-    lp = (q.E < a.e_max * a.e_max) ? -q.E * P.inv2se2 - P.lnZ : -INFINITY;
-  float lw = lp + P.lw0 + 2.0f * __logf(q.iB);
-  if (SZ) {
-    const float z = (ls * kLn10F - P.mu) * P.inv_sig_s;
-    lw -= 0.5f * z * z;
-  }
-  return lw;
+__device__ __forceinline__ float wave_max_dpp(float x) {
+  x = dpp_max_step<0x111, 0xf>(x);   // row_shr:1
+  x = dpp_max_step<0x112, 0xf>(x);   // row_shr:2
+  x = dpp_max_step<0x114, 0xf>(x);   // row_shr:4
+  x = dpp_max_step<0x118, 0xf>(x);   // row_shr:8
+  x = dpp_max_step<0x142, 0xa>(x);   // row_bcast:15 into rows 1 and 3
+  x = dpp_max_step<0x143, 0xc>(x);   // row_bcast:31 into rows 2 and 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
-// Float64 totals over the wave of six per-lane float values, in one
+// Float64 totals over the wave of seven per-lane float values, in one
 // transposed reduction through the wave's LDS scratch (64 x 8 floats): lane
-// l adds value l / 8 of lanes 8 (l % 8) .. 8 (l % 8) + 7 in float64, a
-// three-step DPP prefix sum inside each group of eight lanes finishes it on
-// lane 8 j + 7, and the six totals are read back as wave-uniform values.
-// Fixed order: the totals are bitwise reproducible.
-__device__ __forceinline__ void wave_total6_f64(const float* v, float* scratch, double* T) {
+// l adds value l / 8 of lanes 8 (l % 8) .. 8 (l % 8) + 7 in float64, and a
+// three-step DPP prefix sum inside each group of eight lanes finishes total j
+// on lane 8 j + 7 (returned there; value 7 is zero).  Fixed order: the totals
+// are bitwise reproducible.
+__device__ __forceinline__ double wave_group8_f64(const float* v, float* scratch) {
   const int lane = lane_id();
   float4* s4 = reinterpret_cast<float4*>(scratch);
   s4[2 * lane] = make_float4(v[0], v[1], v[2], v[3]);
-  s4[2 * lane + 1] = make_float4(v[4], v[5], 0.f, 0.f);
+  s4[2 * lane + 1] = make_float4(v[4], v[5], v[6], 0.f);
   wave_lds_sync();
   const int val = lane >> 3, grp = lane & 7;
   double acc = 0.0;
@@ -128,136 +130,255 @@ __device__ __forceinline__ void wave_total6_f64(const float* v, float* scratch, 
   acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
   acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
   acc = dpp_shift_add<0x114, 0xf>(acc);   // row_shr:4
-#pragma unroll
-  for (int j = 0; j < 6; ++j) T[j] = bcast(acc, 8 * j + 7);
   wave_lds_sync();
+  return acc;
 }
 
-// A wave holds one galaxy's K samples in registers (lane l: samples
-// l, l + 64, ...) and evaluates, for each point, the lane's log weights
-// (first pass, kept in registers with their lane maximum m_l), then the
-// lane's sums of e^(lw - m_l) times 1, the two g-derivative terms, z, z^2
-// and E (second pass, float: at most 16 terms, each in (0, 1]).  The lane
-// sums are combined across the wave in float64 after rescaling by
-// e^(m_l - M), M the wave maximum, and the log-sum-exp and the gradient are
-// assembled in float64.
-// Minimum resident waves per SIMD requested from the register allocator.
-#ifndef BSI_SHEAR_WAVES_PER_EU
-#define BSI_SHEAR_WAVES_PER_EU 2
-#endif
+// One sample's log weight at a point, in log2 units, and the quantities the
+// gradient needs: B = |1 - conj(g) e'|^2 = 1 - 2 Re(conj(g) e') + |g|^2 |e'|^2,
+// E = |e' - g|^2 / B with |e' - g|^2 = |e'|^2 - 2 Re(conj(g) e') + |g|^2,
+// lw2 = c0 - a1 E - 2 log2 B - zq^2 (+ 2 log2(1 - E) for the unit-disk density),
+// -inf outside the density's support.
+template <bool SZ, int EK>
+__device__ __forceinline__ float sample_lw(const Point& P, float emax2, float e1, float e2, float ep2,
+                                           float ls, float c0, float& E, float& iB, float& zq) {
+  const float dot = fmaf(P.g2, e2, P.g1 * e1);
+  const float B = fmaf(P.gg, ep2, fmaf(-2.0f, dot, 1.0f));
+  iB = __builtin_amdgcn_rcpf(B);
+  E = fmaf(-2.0f, dot, ep2 + P.gg) * iB;
+  float l = fmaf(-E, P.a1, c0);
+  l = fmaf(-2.0f, __builtin_amdgcn_logf(B), l);
+  if (EK == 0) {
+    l = fmaf(2.0f, __builtin_amdgcn_logf(1.0f - E), l);
+    l = (E < 1.0f) ? l : -INFINITY;
+  } else {
+    l = (E < emax2) ? l : -INFINITY;
+  }
+  if (SZ) {
+    zq = fmaf(ls, P.kz, P.kz0);
+    l = fmaf(-zq, zq, l);
+  }
+  return l;
+}
 
-// Template flags: GRAD = a.want_grad, SZ = a.size_term, EK = a.e_kind.
-template <bool GRAD, bool SZ, int EK>
-__global__ void __launch_bounds__(256, BSI_SHEAR_WAVES_PER_EU) shear_kernel(ShearArgs a) {
-  __shared__ double red[4][kPtsPerChunk][6];
+// The lane's sums over its samples at one point, each weight taken as
+// x = 2^(lw2 - U) for a wave-uniform reference U: x and, with the gradient,
+// x/B (dlp - c |e'|^2), x/B (c - dlp) e1', x/B (c - dlp) e2', x zq, x zq^2,
+// x E, where c = dlp E + 2 and dlp = d ln p_e / dE (natural units): the
+// g-derivative of ln w is 2/B [g (dlp - c |e'|^2) + (c - dlp) e'] - 4 g /
+// (1 - |g|^2), so g enters only after the sums.
+template <bool GRAD, bool SZ, int EK, int NS>
+__device__ __forceinline__ void lane_sums(const Point& P, float emax2, const float* e1, const float* e2,
+                                          const float* ls, const float* c0, float U, float* v) {
+#pragma unroll
+  for (int j = 0; j < 7; ++j) v[j] = 0.f;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    float E, iB, zq = 0.f;
+    const float ep2 = fmaf(e1[i], e1[i], e2[i] * e2[i]);
+    const float l = sample_lw<SZ, EK>(P, emax2, e1[i], e2[i], ep2, ls[i], c0[i], E, iB, zq);
+    const float x = __builtin_amdgcn_exp2f(l - U);
+    v[0] += x;
+    if (GRAD) {
+      float c, w, dl;
+      if (EK == 0) {
+        dl = fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f - fminf(E, 0.999999f)), P.dlp);
+        c = fmaf(dl, E, 2.0f);
+        w = c - dl;
+      } else {
+        dl = P.dlp;
+        c = fmaf(dl, E, 2.0f);
+        w = fmaf(dl, E, P.w0);
+      }
+      const float u = fmaf(-c, ep2, dl);
+      const float q = x * iB;
+      v[1] = fmaf(q, u, v[1]);
+      const float r = q * w;
+      v[2] = fmaf(r, e1[i], v[2]);
+      v[3] = fmaf(r, e2[i], v[3]);
+      if (SZ) {
+        const float xz = x * zq;
+        v[4] += xz;
+        v[5] = fmaf(xz, zq, v[5]);
+      }
+      v[6] = fmaf(x, E, v[6]);
+    }
+    // groups of four samples: the scheduler interleaves within a group only,
+    // which bounds the live temporaries (and so the registers per wave)
+    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// The wave maximum of the log weights at one point.
+template <bool SZ, int EK, int NS>
+__device__ __forceinline__ float wave_lw_max(const Point& P, float emax2, const float* e1, const float* e2,
+                                             const float* ls, const float* c0) {
+  float m = -INFINITY;
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    float E, iB, zq;
+    const float ep2 = fmaf(e1[i], e1[i], e2[i] * e2[i]);
+    m = fmaxf(m, sample_lw<SZ, EK>(P, emax2, e1[i], e2[i], ep2, ls[i], c0[i], E, iB, zq));
+  }
+  return wave_max_dpp(m);
+}
+
+// Wait counters (gfx9 encoding): all vector memory operations done; all LDS
+// operations done.
+constexpr int kWaitVmcnt0 = 0x0F70;
+constexpr int kWaitLgkmcnt0 = 0xC07F;
+// A point whose total weight against the bound falls below this is evaluated
+// again against its exact maximum (weights below 2^-126 of the bound would
+// have underflowed).
+constexpr double kLooseTotal = 0x1p-60;
+
+// A wave holds one galaxy's K samples in registers (lane l: samples l,
+// l + 64, ...; NS slots per lane, padding slots with weight zero) with the
+// point-independent part of each log weight (c0: minus the interim
+// ellipticity density, plus the flux term) in log2 units; the next galaxy's
+// samples stream into LDS meanwhile.  Per point one pass over the samples
+// forms the lane's sums with weights 2^(lw2 - U) against the wave-uniform
+// bound U = max c0 - 4 log2(1 - |g|) >= lw2 (the other terms are <= 0, and
+// B >= (1 - |g|)^2 on the unit disk), so nothing is stored per sample and no
+// lane needs rescaling; the sums are totalled over the wave in float64 into
+// the wave's LDS record of the point.  A point whose total weight comes out
+// below 2^-60 (extreme population parameters: tiny sigma_e or sigma_s) is
+// evaluated again against the exact wave maximum of its log weights, so no
+// weight that matters underflows.  When every point of the chunk is done,
+// lane j finishes point j from its record -- the float64 logarithm of the
+// log-sum-exp and the gradient assembly -- so those run once per point, in
+// parallel across the lanes.
+template <bool GRAD, bool SZ, int EK, int NS>
+__global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
+  // per wave: the next galaxy's e1', e2', log10 s, loaded straight into LDS
+  // while the current galaxy is evaluated (sample k at index k)
+  __shared__ float pre[4][3][NS * 64];
   __shared__ Point pts_s[kPtsPerChunk];
-  __shared__ __align__(16) float wred[4][64 * 8];     // per-wave transposed-reduction scratch
+  __shared__ __align__(16) float wred[4][64 * 8];       // per-wave transposed-reduction scratch
+  // per-wave point records (7 totals, reference U) while the galaxies run; the
+  // block's per-point sums (acc of each wave) at the end
+  __shared__ double fin[4][kPtsPerChunk][8];
+  double (*red)[kPtsPerChunk][6] = reinterpret_cast<double (*)[kPtsPerChunk][6]>(&fin[0][0][0]);
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int chunk0 = blockIdx.y * kPtsPerChunk;
   const int npc = min(kPtsPerChunk, a.n_pts - chunk0);
+  const int waves_total = gridDim.x * 4;
+  // LDS DMA of galaxy g's samples into this wave's buffer (lanes past K load
+  // the galaxy's first sample, masked when read)
+  auto prefetch = [&](int g) {
+    const int64_t base = (int64_t)g * a.K;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
+      const int k = lane + i * kWave;
+      const int64_t o = base + (k < a.K ? k : 0);
+      __builtin_amdgcn_global_load_lds(a.e1p + o, &pre[wave][0][i * kWave], 4, 0, 0);
+      __builtin_amdgcn_global_load_lds(a.e2p + o, &pre[wave][1][i * kWave], 4, 0, 0);
+      if (SZ) __builtin_amdgcn_global_load_lds(a.l10s + o, &pre[wave][2][i * kWave], 4, 0, 0);
+    }
+  };
+  int gal = blockIdx.x * 4 + wave;
+  if (gal < a.n_gal) prefetch(gal);
+  // the points' constants, while the first galaxy's samples are in flight
   if ((int)threadIdx.x < npc) pts_s[threadIdx.x] = make_point(a.pts + 5 * (int64_t)(chunk0 + threadIdx.x), a);
   __syncthreads();
   double acc[6] = {0, 0, 0, 0, 0, 0};      // lane j: point chunk0 + j
-  const int KL = (a.K + kWave - 1) / kWave;
-  const int waves_total = gridDim.x * 4;
-  const float lnZ0 = (float)log_z_e(0, a.sigma_e_interim, 1.0);
-  const float inv2s0 = (float)(1.0 / (2.0 * a.sigma_e_interim * a.sigma_e_interim));
-  const double logK = log((double)a.K);
-  for (int gal = blockIdx.x * 4 + wave; gal < a.n_gal; gal += waves_total) {
-    float e1[kMaxPerLane], e2[kMaxPerLane], ls[kMaxPerLane], c0[kMaxPerLane];
-    const int64_t base = (int64_t)gal * a.K;
+  // minus the interim ellipticity density (eq. interim-prior) in log2 units:
+  // -2 log2(1 - E') + E' b0 + lz0, b0 = log2(e) / (2 sigma0^2), lz0 = log2 Z0
+  const float b0 = a.b0, lz0 = a.lz0;
+  const double logK = a.logK;
+  const float emax2 = a.e_max * a.e_max;
+  double* rec = &fin[wave][0][0];
+  for (; gal < a.n_gal; gal += waves_total) {
+    float e1[NS], e2[NS], ls[NS], c0[NS];
+    // this galaxy's samples have landed: move them to registers, then start
+    // the next galaxy's transfer into the freed buffer
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    wave_lds_sync();
 #pragma unroll
-    for (int i = 0; i < kMaxPerLane; ++i) {
+    for (int i = 0; i < NS; ++i) {
+      e1[i] = pre[wave][0][i * kWave + lane];
+      e2[i] = pre[wave][1][i * kWave + lane];
+      ls[i] = SZ ? pre[wave][2][i * kWave + lane] : 0.f;
+    }
+    __builtin_amdgcn_s_waitcnt(kWaitLgkmcnt0);
+    wave_lds_sync();
+    if (gal + waves_total < a.n_gal) prefetch(gal + waves_total);
+    float cmax = -INFINITY;
+#pragma unroll
+    for (int i = 0; i < NS; ++i) {
       const int k = lane + i * kWave;
-      e1[i] = e2[i] = ls[i] = 0.f;
       c0[i] = -INFINITY;
-      if (i < KL && k < a.K) {
-        e1[i] = a.e1p[base + k];
-        e2[i] = a.e2p[base + k];
-        ls[i] = a.l10s[base + k];
-        const float Ep = e1[i] * e1[i] + e2[i] * e2[i];
-        // minus the interim ellipticity density (eq. interim-prior)
-        float c = -(2.0f * __logf(1.0f - Ep) - Ep * inv2s0 - lnZ0);
+      if (k >= a.K) {
+        e1[i] = e2[i] = ls[i] = 0.f;
+      } else {
+        const float Ep = fmaf(e1[i], e1[i], e2[i] * e2[i]);
+        float c = fmaf(-2.0f, __builtin_amdgcn_logf(1.0f - Ep), fmaf(Ep, b0, lz0));
         if (a.flux_term) {
-          const float lf = a.l10f[base + k];
+          const float lf = a.l10f[(int64_t)gal * a.K + k];
           const double z = ((double)lf * kLn10 - a.mu_lnf) / a.sig_lnf;
-          c += (float)(log(kLn10) - log(a.sig_lnf) - 0.5 * log(2.0 * kPi) - 0.5 * z * z +
-                       a.log_span_f);
+          c += (float)(kLog2e * (log(kLn10) - log(a.sig_lnf) - 0.5 * log(2.0 * kPi) - 0.5 * z * z +
+                                 a.log_span_f));
         }
         c0[i] = c;
+        cmax = fmaxf(cmax, c);
       }
     }
+    const float cwave = wave_max_dpp(cmax);
     for (int pj = 0; pj < npc; ++pj) {
-      const Point P = pts_s[pj];
-      // pass 1: log weights (padding and out-of-support samples -inf), lane maximum
-      float lw[kMaxPerLane];
-      float m = -INFINITY;
-#pragma unroll
-      for (int i = 0; i < kMaxPerLane; ++i) {
-        lw[i] = (i < KL) ? logw<EK, SZ>(P, a, geo(P, e1[i], e2[i]), ls[i]) + c0[i] : -INFINITY;
-        m = fmaxf(m, lw[i]);
+      const Point& P = pts_s[pj];
+      const float U = (cwave > -INFINITY) ? cwave + P.du : 0.0f;
+      float v[7];
+      lane_sums<GRAD, SZ, EK, NS>(P, emax2, e1, e2, ls, c0, U, v);
+      // float64 totals over the wave (lane 8 j + 7 holds total j) into the
+      // point's record; U in slot 7
+      const double t = wave_group8_f64(v, wred[wave]);
+      if ((lane & 7) == 7) rec[pj * 8 + (lane >> 3)] = (lane == 63) ? (double)U : t;
+    }
+    wave_lds_sync();
+    // points whose total weight against the bound is tiny (or zero): again
+    // against the exact maximum of their log weights
+    {
+      const bool loose = lane < npc && rec[lane * 8] < kLooseTotal;
+      uint64_t todo = __builtin_amdgcn_ballot_w64(loose);
+      while (todo) {
+        const int pj = __builtin_ctzll(todo);
+        todo &= todo - 1;
+        const Point& P = pts_s[pj];
+        const float M = wave_lw_max<SZ, EK, NS>(P, emax2, e1, e2, ls, c0);
+        float v[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (M > -INFINITY) lane_sums<GRAD, SZ, EK, NS>(P, emax2, e1, e2, ls, c0, M, v);
+        const double t = wave_group8_f64(v, wred[wave]);
+        if ((lane & 7) == 7) rec[pj * 8 + (lane >> 3)] = (lane == 63) ? (double)M : t;
       }
-      // pass 2: the lane's sums of e^(lw - m) times 1 and the derivative terms;
-      // every term is finite (E is clamped below 1 in the ellipticity-density
-      // derivative) and carries the factor e^(lw - m), zero for -inf weights
-      const float ms = (m > -INFINITY) ? m : 0.0f;
-      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // s0, u0, u1, t1, t2, tE
-#pragma unroll
-      for (int i = 0; i < kMaxPerLane; ++i) {
-        if (i >= KL) continue;
-        const float ex = __expf(lw[i] - ms);
-        v[0] += ex;
-        if (GRAD) {
-          const Geo q = geo(P, e1[i], e2[i]);
-          const float dB1 = 2.0f * (-q.br * e1[i] - q.bi * e2[i]);
-          const float dB2 = 2.0f * (-q.br * e2[i] + q.bi * e1[i]);
-          const float dE1 = (-2.0f * q.ar - q.E * dB1) * q.iB;
-          const float dE2 = (-2.0f * q.ai - q.E * dB2) * q.iB;
-          const float dlp = (EK == 0)
-                                ? -2.0f * __builtin_amdgcn_rcpf(1.0f - fminf(q.E, 0.999999f)) - P.inv2se2
-                                : -P.inv2se2;
-          v[1] = fmaf(ex, dlp * dE1 - 2.0f * dB1 * q.iB, v[1]);
-          v[2] = fmaf(ex, dlp * dE2 - 2.0f * dB2 * q.iB, v[2]);
-          if (SZ) {
-            const float z = (ls[i] * kLn10F - P.mu) * P.inv_sig_s;
-            v[3] = fmaf(ex, z, v[3]);
-            v[4] = fmaf(ex * z, z, v[4]);
-          }
-          v[5] = fmaf(ex, q.E, v[5]);
-        }
-      }
-      // the wave maximum M, the lanes' sums rescaled by e^(m - M), and their
-      // float64 totals over the wave in one transposed reduction
-      const float M = wave_max(m);
+      wave_lds_sync();
+    }
+    // lane j finishes point j: log-sum-exp and gradient in float64
+    if (lane < npc) {
+      const Point& P = pts_s[lane];
+      const double* T = rec + lane * 8;
+      const double S = T[0];
       double ell = -INFINITY, g[5] = {0, 0, 0, 0, 0};
-      if (M > -INFINITY) {
-        const float f = (m > -INFINITY) ? __expf(m - M) : 0.0f;
-#pragma unroll
-        for (int j = 0; j < 6; ++j) v[j] *= f;
-        double T[6];
-        wave_total6_f64(v, wred[wave], T);
-        const double S = T[0];
-        ell = (double)M + log(S) - logK;
+      if (S > 0.0) {
+        ell = T[7] * kLn2 + log(S) + P.k0 - logK;
         if (GRAD) {
           const double iS = 1.0 / S;
-          const double inv_ss = (double)P.inv_sig_s;
-          g[0] = T[1] * iS - (double)P.c1;
-          g[1] = T[2] * iS - (double)P.c2;
+          g[0] = 2.0 * (P.g1d * T[1] + T[2]) * iS - P.c1;
+          g[1] = 2.0 * (P.g2d * T[1] + T[3]) * iS - P.c2;
           if (SZ) {
-            g[2] = inv_ss * T[3] * iS;
-            g[3] = inv_ss * (T[4] * iS - 1.0);
+            g[2] = P.inv_sig_s * T[4] * iS * (1.0 / kZq);
+            g[3] = P.inv_sig_s * (T[5] * iS * (1.0 / (kZq * kZq)) - 1.0);
           }
-          g[4] = (double)P.inv_se3 * T[5] * iS - (double)P.dlnZ;
+          g[4] = P.inv_se3 * T[6] * iS - P.dlnZ;
         }
       }
-      if (lane == pj) {
-        if (a.per_gal) a.per_gal[(int64_t)(chunk0 + pj) * a.n_gal + gal] = ell;
-        acc[0] += ell;
+      if (a.per_gal) a.per_gal[(int64_t)(chunk0 + lane) * a.n_gal + gal] = ell;
+      acc[0] += ell;
 #pragma unroll
-        for (int j = 0; j < 5; ++j) acc[1 + j] += g[j];
-      }
+      for (int j = 0; j < 5; ++j) acc[1 + j] += g[j];
     }
+    wave_lds_sync();
   }
+  __syncthreads();    // every wave is done with its records
 #pragma unroll
   for (int j = 0; j < 6; ++j) red[wave][lane][j] = acc[j];
   __syncthreads();
@@ -368,12 +489,11 @@ __device__ void shear_begin_iteration(const ShearHmcArgs& a, ShearChain& c, uint
   }
 }
 
-__global__ void __launch_bounds__(kRedThreads) shear_hmc_update_kernel(ShearHmcArgs a, int init) {
-  __shared__ double red[kRedThreads][6];
-  const int chain = blockIdx.x;
-  double v[6];
-  reduce_point(a.partial, a.n_blocks, a.C, chain, red, v);
-  if (threadIdx.x != 0) return;
+// One chain's move after an evaluation pass (v: the pass's totals at the
+// chain's current point): the leapfrog, the Metropolis test at a trajectory's
+// end, dual averaging, the next trajectory's start; pt then holds the chain's
+// next evaluation point.
+__device__ void shear_hmc_move(const ShearHmcArgs& a, int init, int chain, const double* v) {
   ShearChain c = a.state[chain];
   double* pt = a.pts + 5 * (int64_t)chain;
   const uint32_t uid = (uint32_t)(a.uid_base + (uint64_t)chain);
@@ -469,6 +589,15 @@ __global__ void __launch_bounds__(kRedThreads) shear_hmc_update_kernel(ShearHmcA
   a.state[chain] = c;
 }
 
+__global__ void __launch_bounds__(kRedThreads) shear_hmc_update_kernel(ShearHmcArgs a, int init) {
+  __shared__ double red[kRedThreads][6];
+  const int chain = blockIdx.x;
+  double v[6];
+  reduce_point(a.partial, a.n_blocks, a.C, chain, red, v);
+  if (threadIdx.x != 0) return;
+  shear_hmc_move(a, init, chain, v);
+}
+
 __global__ void shear_hmc_stats_kernel(const ShearChain* __restrict__ st, int C, int S,
                                        double* __restrict__ stats) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -486,16 +615,23 @@ hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s) {
   if (a.n_pts <= 0) return hipSuccess;
   const int chunks = (a.n_pts + kPtsPerChunk - 1) / kPtsPerChunk;
   const dim3 grid(n_blocks, chunks), blk(256);
+  const int KL = (a.K + kWave - 1) / kWave;
+  const int ns = KL <= 4 ? 0 : KL <= 8 ? 1 : 2;    // 4, 8 or 16 sample slots per lane
   const int key = (a.want_grad ? 4 : 0) | (a.size_term ? 2 : 0) | (a.e_kind == 0 ? 0 : 1);
-  switch (key) {
-    case 0: hipLaunchKernelGGL((shear_kernel<false, false, 0>), grid, blk, 0, s, a); break;
-    case 1: hipLaunchKernelGGL((shear_kernel<false, false, 1>), grid, blk, 0, s, a); break;
-    case 2: hipLaunchKernelGGL((shear_kernel<false, true, 0>), grid, blk, 0, s, a); break;
-    case 3: hipLaunchKernelGGL((shear_kernel<false, true, 1>), grid, blk, 0, s, a); break;
-    case 4: hipLaunchKernelGGL((shear_kernel<true, false, 0>), grid, blk, 0, s, a); break;
-    case 5: hipLaunchKernelGGL((shear_kernel<true, false, 1>), grid, blk, 0, s, a); break;
-    case 6: hipLaunchKernelGGL((shear_kernel<true, true, 0>), grid, blk, 0, s, a); break;
-    default: hipLaunchKernelGGL((shear_kernel<true, true, 1>), grid, blk, 0, s, a); break;
+  switch (key * 3 + ns) {
+#define BSI_SHEAR_CASE(G, S, E)                                                                     \
+    case ((G) * 4 + (S) * 2 + (E)) * 3 + 0:                                                         \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 4>), grid, blk, 0, s, a); break;                    \
+    case ((G) * 4 + (S) * 2 + (E)) * 3 + 1:                                                         \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 8>), grid, blk, 0, s, a); break;                    \
+    case ((G) * 4 + (S) * 2 + (E)) * 3 + 2:                                                         \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 16>), grid, blk, 0, s, a); break;
+    BSI_SHEAR_CASE(false, false, 0) BSI_SHEAR_CASE(false, false, 1)
+    BSI_SHEAR_CASE(false, true, 0) BSI_SHEAR_CASE(false, true, 1)
+    BSI_SHEAR_CASE(true, false, 0) BSI_SHEAR_CASE(true, false, 1)
+    BSI_SHEAR_CASE(true, true, 0) BSI_SHEAR_CASE(true, true, 1)
+#undef BSI_SHEAR_CASE
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

@@ -67,7 +67,7 @@ def test_noalloc_matches_shear_posterior(mods):
 def test_noalloc_rejects_a_pass_beyond_the_scratch(mods):
     api, torch = mods
     _log("noalloc scratch limit")
-    G, K, P = 256, 8, 6000            # 64 blocks x 6000 points x 48 B > 16 MiB
+    G, K, P = 256, 8, 24000           # 16 blocks x 24000 points x 48 B > 16 MiB
     lib = api.get(0)
     e = torch.zeros(G, K, device="cuda")
     pts = torch.tensor(_points(np.random.default_rng(3), P), dtype=torch.float64, device="cuda")
