@@ -214,9 +214,14 @@ def shear_leg(api, torch, stream, smp, G, K, seed):
     interim samples of the uniform step (every 4th draw of the 4 chains: K =
     1000 per galaxy, 10^7 in all): 4 chains, 10 leapfrog steps, 500 warmup +
     3000 draws, and the HBM roofline of one evaluation pass."""
-    dev = torch.device("cuda:0")
     th = smp[:, :, 3::4, :].reshape(G, K, 6)
     e1p, e2p, l10s = th[..., 2].contiguous(), th[..., 3].contiguous(), th[..., 1].contiguous()
+    return shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed)
+
+
+def shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed):
+    """The shear-level HMC leg on interim samples (e1', e2', log10 s) [G, K]."""
+    dev = torch.device("cuda:0")
     tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True)
     dcfg = gen.CONFIGS["diff"].extra
     Cs = 4
@@ -655,8 +660,8 @@ def main():
     ap.add_argument("--plain-gal", type=int, default=4)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
-    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "spergel", "bias",
-                                           "exposures", "nuts"],
+    ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "shear-hmc",
+                                           "spergel", "bias", "exposures", "nuts"],
                     default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
@@ -705,6 +710,17 @@ def main():
         from paper_2604_22048_amd import api
         torch.cuda.init()
         stream = torch.cuda.current_stream(torch.device("cuda:0"))
+        if args.workload == "shear-hmc":
+            G, K = args.n_gal or 10_000, 1000
+            S = [torch.tensor(a, device="cuda:0") for a in gen.draw_interim_samples(G, K, gen.data_seed(3))]
+            shear_hmc_run(api, torch, stream, *S, G, K, gen.chain_seed(3))          # warm
+            res = shear_hmc_run(api, torch, stream, *S, G, K, gen.chain_seed(3))
+            out = {"metric": "shear-level HMC (500 warmup + 3000 draws, L = 10, 4 chains)",
+                   "value": res["t_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
+                   "dtype": "f32+f64", "data": "synthetic",
+                   "config": {"workload": f"{G} galaxies x {K} stand-in interim samples"}, **res}
+            print(json.dumps(out), flush=True)
+            return
         if args.workload == "shear-pass":
             res = shear_pass_leg(api, torch, stream, args.steps)
             out = {"metric": "shear posterior evaluation pass (4 points, with gradient)",

@@ -189,6 +189,25 @@ def draw_noise(truth: Truth, seed: int, dtype=np.float32):
     return noise.astype(dtype), off
 
 
+def draw_interim_samples(n_gal: int, K: int, seed: int, g=(0.02, 0.0), noise_e=0.05, noise_ln_s=0.05):
+    """Stand-in interim samples for the shear phase: per galaxy an intrinsic
+    ellipticity of the population (truncated Gaussian), sheared by g with the
+    reduced-shear map, and a lognormal size; its K samples scatter around them
+    (e' kept inside |e'| < 0.95).  Returns float32 (e1', e2', log10 s), each
+    [n_gal, K]."""
+    rng = np.random.default_rng(seed)
+    e1, e2 = _truncated_ellipticity(rng, n_gal)
+    e = e1 + 1j * e2
+    gg = complex(*g)
+    ep = (e + gg) / (1.0 + np.conj(gg) * e)
+    ln_s = rng.normal(np.log(0.6), 0.3, n_gal)
+    smp = ep[:, None] + rng.normal(0, noise_e, (n_gal, K)) + 1j * rng.normal(0, noise_e, (n_gal, K))
+    r = np.abs(smp)
+    smp = np.where(r < 0.95, smp, smp * 0.9 / np.maximum(r, 1e-12))
+    l10s = (ln_s[:, None] + rng.normal(0, noise_ln_s, (n_gal, K))) / np.log(10.0)
+    return [a.astype(np.float32) for a in (smp.real, smp.imag, l10s)]
+
+
 def draw_requests(n_req: int, rate: float, seed: int):
     """Poisson arrival times (seconds) of n_req requests."""
     rng = np.random.default_rng(seed)
