@@ -417,10 +417,11 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
     return out
 
 
-def uneven_leg(api, torch, stream, n_gal, log=None):
+def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
     """Batched uneven workload: n_gal galaxies, stamp side from the size rule
     (25-101), PSF FWHM ~ U(0.6, 0.9), SNR 10-200, 4 chains, 20 leapfrog
-    steps, 300 warmup + 1000 draws; the size classes launch concurrently."""
+    steps, 300 warmup + 1000 draws; the size classes launch concurrently.
+    per_size_runs: also time each size class alone (uneven_per_size)."""
     cfg = gen.CONFIGS["uneven"]
     plans = api.autotune(list(gen.SIZE_CLASSES), n_chains=cfg.chains)
     t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
@@ -438,10 +439,14 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
+    acc = st[..., 0].mean()
+    n_flag = int((status != 0).sum())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
+    del smp, st, e, rh, data
+    per_size = uneven_per_size(api, torch, stream, cfg, counts, hcfg) if per_size_runs else None
     return {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
             "t_hmc_s": round(t_hmc, 4),
             "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
@@ -449,8 +454,37 @@ def uneven_leg(api, torch, stream, n_gal, log=None):
             "galaxies_per_s": round(1.0 / tpg, 1),
             "achieved_tflops": round(flop / t_hmc / 1e12, 3),
             "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
-            "accept_rate": round(float(st[..., 0].mean()), 4),
-            "status_nonzero": int((status != 0).sum())}
+            "accept_rate": round(float(acc), 4),
+            "status_nonzero": n_flag,
+            "per_size": per_size}
+
+
+def uneven_per_size(api, torch, stream, cfg, counts, hcfg, n1=20, n2=60):
+    """Trajectory-kernel time per launch of each size class of the uneven
+    batch, alone on the device: a batch of that many galaxies of that size
+    (drawn from the uneven population with the stamp side forced), timed as
+    the difference of two warmup-only calls of n2 and n1 iterations (one
+    launch per iteration, replayed from a graph), so that the chain start and
+    data transform cancel.  Fractions use the algorithmic flop count per
+    evaluation of that size."""
+    out = {}
+    for N, k in sorted(counts.items()):
+        t, b, data, ref, init = make_inputs(api, torch, k, cfg, seed_offset=1000 + N,
+                                            sizes=np.full(k, N, dtype=np.int32))
+        ts = []
+        for n in (n1, n2):
+            c = api.HmcConfig(**{**hcfg.__dict__, "n_warmup": n, "n_samples": 0})
+            api.hmc_sample(b, data, ref, init, c, want_samples=False)          # warm
+            _, dt = timed(torch, lambda: api.hmc_sample(b, data, ref, init, c, want_samples=False),
+                          stream)
+            ts.append(dt)
+        t_launch = (ts[1] - ts[0]) / (n2 - n1)
+        tf = flops_per_eval(N, hcfg.n_leapfrog) * k * hcfg.n_chains * hcfg.n_leapfrog / t_launch / 1e12
+        out[N] = {"n_gal": k, "launch_ms": round(t_launch * 1e3, 4), "achieved_tflops": round(tf, 3),
+                  "frac_fp32_peak": round(tf / FP32_PEAK_TFLOPS, 4),
+                  "frac_of_nonpacked_issue_ceiling": round(tf / VALU_ISSUE_TFLOPS, 4)}
+        del t, b, data, ref, init
+    return out
 
 
 def spergel_leg(api, torch, stream, n_gal, nu, log=None):
@@ -471,6 +505,8 @@ def spergel_leg(api, torch, stream, n_gal, nu, log=None):
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(bs, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
+    acc = st[..., 0].mean()
+    n_flag = int((status != 0).sum())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     flop = flops_per_eval(cfg.n_pix) * n_gal * C * L * (W + S)
@@ -638,6 +674,8 @@ def exposures_leg(api, torch, stream, n_gal, E, log, sampler="hmc", depth=5):
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
+    acc = st[..., 0].mean()
+    n_flag = int((status != 0).sum())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     flop = flops_per_eval(N, L, weighted=True) * E * n_gal * C * L * (W + Sd) if sampler == "hmc" else None
@@ -890,6 +928,9 @@ def main():
         legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
         log(f"[bench] shear-level HMC: {legs['shear_hmc']['t_s']} s")
         del results, r["smp"]
+        legs["uneven"] = uneven_leg(api, torch, stream, gen.CONFIGS["uneven"].n_gal, log)
+        log(f"[bench] uneven: {legs['uneven']['galaxies_per_s']} galaxies/s, per size "
+            f"{ {N: v['frac_fp32_peak'] for N, v in legs['uneven']['per_size'].items()} }")
         legs["transform"] = transform_leg(api)
         log(f"[bench] render transforms: {legs['transform']}")
         if not args.no_serving:

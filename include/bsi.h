@@ -496,9 +496,11 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
  * bsi_autotune; every later call on the handle (and every request server
  * created afterwards) uses it.  Results do not depend on the plan beyond
  * float32 rounding (the order of the sums changes).  The trajectory kernel
- * runs two chains per wave (32 lanes each) for an even number of chains up
- * to 4 on the plans 25: P 3, 41: P 1, 53: P 3 (exponential or Spergel profile,
- * one wave per chain requested), one chain per wave otherwise; the choice
+ * runs several chains per wave on the plans 25: P 3, 41: P 1, 53: P 3
+ * (exponential or Spergel profile, one wave per chain requested, an even
+ * number of chains up to 4): four (16 lanes each) for fixed-length
+ * trajectories of exactly four chains at 25 and 41 (one exposure, white
+ * noise), else two (32 lanes each); one chain per wave otherwise.  The choice
  * depends only on the size, plan and configuration, never on the batch. */
 
 /* Set (P > 0) or reset to the default (P = 0) the slot plan of stamp side n.

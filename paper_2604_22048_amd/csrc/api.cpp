@@ -541,7 +541,10 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     auto enqueue = [&](hipStream_t st) -> hipError_t {
       return fork_join(h, st, (int)p.classes.size(), advance_class);
     };
-    // graph replay: one stream, the sizes' launches in sequence
+    // any capture (the library's own graph or the caller's): one stream, the
+    // sizes' launches in sequence.  Capturing the fork/join has ended in a
+    // host segmentation fault inside the call (cause not identified), so it
+    // is never captured.
     auto enqueue_serial = [&](hipStream_t st) -> hipError_t {
       for (int i = 0; i < (int)p.classes.size(); ++i) {
         hipError_t e = advance_class(i, st);

@@ -181,67 +181,73 @@ __device__ __forceinline__ void wave_total7(float* v, float* scratch) {
   wave_lds_sync();
 }
 
-// ---- Two chains per wave: lanes 0..31 serve one chain, 32..63 the other --
+// ---- Several chains per wave: H = 2 (lanes 0..31 and 32..63) or H = 4 -----
+// (lanes 16 c .. 16 c + 15 serve chain c of the wave)
 
 // Lane index within the lanes serving this lane's chain (H chains per wave).
 template <int H>
 __device__ __forceinline__ int chain_lane() {
-  return H == 1 ? lane_id() : (lane_id() & 31);
+  static_assert(H == 1 || H == 2 || H == 4, "1, 2 or 4 chains per wave");
+  return lane_id() & (kWave / H - 1);
 }
 
-// Value of lane k of this lane's chain (lane k of the wave for H = 1, lane k
-// of the lane's half for H = 2).
-template <int H>
-__device__ __forceinline__ float hbcast(float x, int k) {
-  if constexpr (H == 1) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
-  } else {
-    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
-    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32 + k));
-    return (lane_id() & 32) ? b : a;
-  }
-}
+// Value of lane k of this lane's chain (lane k of the wave for H = 1; for
+// H = 2 two lane reads and a select; for H = 4 one ds_bpermute, which uses
+// no LDS storage).
 template <int H>
 __device__ __forceinline__ uint32_t hbcast(uint32_t x, int k) {
   if constexpr (H == 1) {
     return (uint32_t)__builtin_amdgcn_readlane((int)x, k);
-  } else {
+  } else if constexpr (H == 2) {
     const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)x, k);
     const uint32_t b = (uint32_t)__builtin_amdgcn_readlane((int)x, 32 + k);
     return (lane_id() & 32) ? b : a;
+  } else {
+    const int src = (lane_id() & ~(kWave / H - 1)) + k;
+    return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)x);
   }
 }
+template <int H>
+__device__ __forceinline__ float hbcast(float x, int k) {
+  return __uint_as_float(hbcast<H>(__float_as_uint(x), k));
+}
 
-// Sum over each 32-lane half by a butterfly: every lane of a half ends with
-// the same bits (each stage adds the same two operands on both partners).
-__device__ __forceinline__ double half_total(double x) {
+// Sum over the 64 / H lanes of each chain by a butterfly: every lane of a
+// chain ends with the same bits (each stage adds the same two operands on
+// both partners).
+template <int H>
+__device__ __forceinline__ double group_total(double x) {
 #pragma unroll
-  for (int o = 16; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
+  for (int o = kWave / H / 2; o >= 1; o >>= 1) x += __shfl_xor(x, o, kWave);
   return x;
 }
 
-// Seven sums over each 32-lane half through the wave's 2 KiB LDS scratch:
-// each lane writes its eight partials, lane l of a half adds value (l % 32) / 4
-// of lanes 8 (l % 4) .. 8 (l % 4) + 7 of its half, a two-step DPP prefix sum
-// inside each group of four lanes finishes the sum on lane 4 v + 3, and the
-// sums go back through LDS to every lane of their half.
-__device__ __forceinline__ void half_total7(float* v, float* scratch) {
+// Seven sums over the LS = 64 / H lanes of each chain (H = 2 or 4) through
+// the wave's 2 KiB LDS scratch: each lane writes its eight partials; with
+// LV = LS / 8 lanes per value, lane r of a chain adds value r / LV of lanes
+// 8 (r % LV) .. 8 (r % LV) + 7 of its chain, a DPP prefix sum inside each
+// group of LV lanes finishes the sum on its last lane, and the sums go back
+// through LDS to every lane of their chain.
+template <int H>
+__device__ __forceinline__ void group_total7(float* v, float* scratch) {
+  static_assert(H == 2 || H == 4, "several chains per wave");
+  constexpr int LS = kWave / H, LV = LS / 8;
   const int lane = lane_id();
   float4* s4 = reinterpret_cast<float4*>(scratch);
   s4[2 * lane] = make_float4(v[0], v[1], v[2], v[3]);
   s4[2 * lane + 1] = make_float4(v[4], v[5], v[6], 0.f);
   wave_lds_sync();
-  const int half = lane & 32, r = lane & 31;
-  const int val = r >> 2, grp = r & 3;
+  const int base = lane & ~(LS - 1), r = lane & (LS - 1);
+  const int val = r / LV, grp = r % LV;
   float acc = 0.f;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) acc += scratch[(half + 8 * grp + k) * 8 + val];
-  acc = dpp_shift_add<0x111, 0xf>(acc);   // row_shr:1
-  acc = dpp_shift_add<0x112, 0xf>(acc);   // row_shr:2
+  for (int k = 0; k < 8; ++k) acc += scratch[(base + 8 * grp + k) * 8 + val];
+  acc = dpp_shift_add<0x111, 0xf>(acc);                        // row_shr:1
+  if constexpr (LV == 4) acc = dpp_shift_add<0x112, 0xf>(acc);  // row_shr:2
   wave_lds_sync();
-  if (grp == 3) scratch[(half >> 2) + val] = acc;
+  if (grp == LV - 1) scratch[base / LV + val] = acc;
   wave_lds_sync();
-  const float* res = scratch + (half >> 2);
+  const float* res = scratch + base / LV;
 #pragma unroll
   for (int j = 0; j < 7; ++j) v[j] = res[j];
   wave_lds_sync();

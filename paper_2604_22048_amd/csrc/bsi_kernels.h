@@ -145,11 +145,6 @@ size_t hmc_lds_bytes(int N, int C, int P, int W, int H = 1, int E = 1, bool mx =
 // 1 unless the profile is exponential or Spergel and P is N's default plan with a
 // specialised kernel.
 int hmc_split_waves(int N, int C, int P, int prof, int max_w);
-// Chains per wave of the trajectory kernel: 2 (two 32-lane halves) for an
-// even number of chains (at most 4), one wave per chain (wpc = 1), the
-// exponential or Spergel profile and a plan whose specialised two-chain kernel is the
-// faster one (25: P 3, 41: P 1, 53: P 3); else 1.
-int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc);
 // Whether the advance kernel with exposures / noise weights (mx) runs on the
 // kernels specialised for stamp side N: one wave per chain, the exponential or
 // Spergel profile and P N's default plan with a specialised kernel.

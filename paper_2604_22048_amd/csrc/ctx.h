@@ -275,7 +275,10 @@ inline int stage_upload(bsi_handle h, hipStream_t s, bool cap, std::initializer_
 // Enqueue fn(i, stream) for i = 0..n-1 with item 0 on s and the others on
 // the handle's auxiliary streams, forked from and joined back into s by
 // events, so that the launches of different size classes can run
-// concurrently.  Used for launches outside graph capture only.
+// concurrently.  Used outside stream capture only: a capture of the fork
+// (with the executable kept alive until its replays had run) still ended in
+// a host segmentation fault inside the call, so every capture records the
+// launches in sequence on one stream instead.
 template <typename F>
 hipError_t fork_join(bsi_handle h, hipStream_t s, int n, F&& fn) {
   if (n <= 1) return n == 1 ? fn(0, s) : hipSuccess;

@@ -37,6 +37,7 @@ struct GalCtx {
   float4* Ym;      // X and Yf as full x and y tables
   float2* Yf;
   float* red;      // per-wave reduction scratch (2 KiB)
+  const float4* cols;   // the workgroup's pair-slot column table
   int part;        // this wave's index among the W waves of its chain
   float* xch;      // the chain's partial-sum exchange area (2 x W x 12 floats)
   float norm;      // 1 / (N^2 sigma^2)
@@ -142,8 +143,18 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * 
     }
   } else {
     fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
-    const KSums S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym,
-                                                                   c.Yf, sh, c.red, c.part, xbuf);
+    KSums S;
+    if constexpr (H == 4) {
+      // four chains per wave: the lane's 4 P columns are read again from the
+      // column table at each evaluation rather than held in registers for the
+      // whole trajectory
+      const LaneCols<P * H> lr = lane_cols<P * H, H>(c.cols);
+      S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lr, c.dh, c.X, c.Ym, c.Yf, sh,
+                                                        c.red, c.part, xbuf);
+    } else {
+      S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh,
+                                                        c.red, c.part, xbuf);
+    }
     r = kspace_finish<PROF>(S, sh, F, s, e1, e2, c.norm);
   }
   const float isd2 = pr.isd2, ise2 = pr.ise2;
@@ -466,8 +477,9 @@ struct Hot {
 
 __device__ __forceinline__ void lane0_sync() { wave_lds_sync(); }
 
-// H = 2: two chains per wave, each 32-lane half running its own chain (its
-// own record cs, tables and outputs); lane below is the lane within the half.
+// H = 2 or 4: several chains per wave, each group of 64 / H lanes running its
+// own chain (its own record cs, tables and outputs); lane below is the lane
+// within the group.
 template <int PROF, int P, int NFIX, int W, int H = 1, bool MX = false>
 __device__ void advance_chain(const HmcArgs& a, const GalCtx& c, const LaneCols<P * H>& lc,
                               const Prior& pr, ChainState* cs, float* samples_chain,
@@ -1141,7 +1153,8 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
 // W > 1: each chain is evaluated by W waves (split evaluation; advance only).
-// H = 2: two chains per wave (lanes 0..31 and 32..63; advance only, C even).
+// H = 2 or 4: two chains per wave (lanes 0..31 and 32..63) or four (16 lanes
+// each); advance only, C a multiple of H.
 // MX: several exposures per galaxy and/or per-bin noise weights (advance
 // kernels of either form with one wave per chain or two chains per wave; the
 // chain start runs on the general kernels).
@@ -1154,13 +1167,14 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
   static_assert(!NUTS || (!INIT && W == 1 && (H == 1 || NFIX > 0)), "NUTS: advance kernels, W = 1");
   static_assert(!MX || (W == 1 && (NFIX == 0 || !INIT)), "exposures and noise weights: no split evaluation");
-  static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "two chains per wave: advance kernels only");
+  static_assert(H == 1 || (!INIT && W == 1 && NFIX > 0), "several chains per wave: advance kernels only");
+  static_assert(H <= 2 || (!MX && !NUTS), "four chains per wave: fixed-length trajectories, one exposure");
   const int N = NFIX > 0 ? NFIX : a.N;
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int wave = threadIdx.x / kWave;
   // chain of the galaxy, part of the chain
-  const int cw = (H == 1) ? wave / W : 2 * wave + ((threadIdx.x >> 5) & 1);
+  const int cw = (H == 1) ? wave / W : H * wave + (int)((threadIdx.x % kWave) / (kWave / H));
   const int part = (H == 1) ? wave % W : 0;
   const int E = MX ? a.n_exp : 1;
   const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H, E, MX);
@@ -1185,6 +1199,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
     c.Ym = l.Ym;
     c.Yf = l.Yf;
     c.red = l.red;
+    c.cols = l.cols;
     c.part = part;
     c.xch = l.xch0 + cw * (2 * 12 * W);
     c.norm = 1.0f / ((float)g.N * (float)g.N * sig * sig);
@@ -1248,7 +1263,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       const uint32_t* src = reinterpret_cast<const uint32_t*>(st);
       const int cl = chain_lane<H>();
 #pragma unroll
-      for (int k = 0; k < H; ++k) csw[cl + 32 * k] = src[cl + 32 * k];
+      for (int k = 0; k < H; ++k) csw[cl + (kWave / H) * k] = src[cl + (kWave / H) * k];
       wave_lds_sync();
       // the W waves of a split chain hold identical copies of its state; the
       // first writes the outputs
@@ -1263,7 +1278,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
       if (part == 0) {
         uint32_t* dst = reinterpret_cast<uint32_t*>(st);
 #pragma unroll
-        for (int k = 0; k < H; ++k) dst[cl + 32 * k] = csw[cl + 32 * k];
+        for (int k = 0; k < H; ++k) dst[cl + (kWave / H) * k] = csw[cl + (kWave / H) * k];
       }
     }
   }
@@ -1350,11 +1365,39 @@ constexpr bool paired_chains_plan(int N, int P) {
   return (N == 25 && P == 3) || (N == 41 && P == 1) || (N == 53 && P == 3);
 }
 
+// Plans with a four-chains-per-wave kernel (16 lanes per chain; fixed-length
+// trajectories of four chains, one exposure): the small stamps, whose work
+// outside the pair loop (tables, reductions, leapfrog update, random numbers)
+// is per wave and so shared by four chains instead of two.
+constexpr bool quad_chains_plan(int N, int P) { return (N == 25 && P == 3) || (N == 41 && P == 1); }
+
+// Chains per wave of an advance launch, the one rule that launch_fixed_w,
+// launch_fixed_nuts, launch_fixed_mx and the LDS size follow.  Several chains
+// per wave only on the specialised kernels of the paired plans, one wave per
+// galaxy at most (C <= 4) and no split evaluation; four for fixed-length
+// trajectories of exactly four chains on the quad plans.  With noise weights
+// two only for a single exposure on the default plan: with several, the
+// two-chain kernels keep too much live across the exposure loop (they spill).
+static int launch_chains_per_wave(const HmcArgs& a, bool init) {
+  if (init || a.prof == kProfGauss || a.wpc != 1 || a.C > 4 || (a.C & 1)) return 1;
+  if (!paired_chains_plan(a.N, a.P)) return 1;
+  if (a.mx && (a.nuts || a.n_exp != 1 || !hmc_mx_fixed(a.N, a.P, a.prof, a.wpc))) return 1;
+  if (!a.mx && !a.nuts && a.C == 4 && quad_chains_plan(a.N, a.P)) return 4;
+  return 2;
+}
+
 template <int PROF, int NFIX, int PP>
 static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s) {
   if (a.wpc == 1) {
     if constexpr (paired_chains_plan(NFIX, PP)) {
-      if (hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc) == 2) {
+      const int H = launch_chains_per_wave(a, false);
+      if constexpr (quad_chains_plan(NFIX, PP)) {
+        if (H == 4) {
+          launch_p<PROF, false, PP, NFIX, 1, 4>(a, grid, lds, s);
+          return true;
+        }
+      }
+      if (H == 2) {
         launch_p<PROF, false, PP, NFIX, 1, 2>(a, grid, lds, s);
         return true;
       }
@@ -1373,16 +1416,6 @@ static bool launch_fixed_w(const HmcArgs& a, int grid, size_t lds, hipStream_t s
     }
   }
   return false;
-}
-
-// Chains per wave of an advance launch.  With noise weights (mx) two chains
-// per wave only for a single exposure on the specialised kernels: with
-// several, the two-chain kernels keep too much live across the exposure loop
-// (they spill) and one chain per wave is the faster form.
-static int launch_chains_per_wave(const HmcArgs& a, bool init) {
-  if (init || a.prof == kProfGauss || a.C * a.wpc > 4) return 1;
-  if (a.mx && (a.nuts || a.n_exp != 1 || !hmc_mx_fixed(a.N, a.P, a.prof, a.wpc))) return 1;
-  return hmc_chains_per_wave(a.N, a.C, a.P, a.prof, a.wpc);
 }
 
 // Several exposures / noise weights on the specialised kernels of the
@@ -1427,16 +1460,6 @@ int hmc_split_waves(int N, int C, int P, int prof, int max_w) {
   return W;
 }
 
-int hmc_chains_per_wave(int N, int C, int P, int prof, int wpc) {
-#ifdef BSI_ONE_CHAIN_PER_WAVE
-  (void)N; (void)C; (void)P; (void)prof; (void)wpc;
-  return 1;
-#else
-  if (wpc != 1 || (C & 1) || C > 4 || prof == kProfGauss) return 1;
-  return paired_chains_plan(N, P) ? 2 : 1;
-#endif
-}
-
 bool hmc_mx_fixed(int N, int P, int prof, int wpc) {
   if (wpc != 1 || prof == kProfGauss || P != make_slot_plan(N).P) return false;
   for (const int* p = hmc_fixed_plans(N); *p; ++p)
@@ -1474,7 +1497,7 @@ static bool launch_fixed_nuts(const HmcArgs& a, int grid, size_t lds, hipStream_
       return false;                                                                             \
     }                                                                                           \
     if constexpr (paired_chains_plan(NN, PP)) {                                                 \
-      if (hmc_chains_per_wave(a.N, a.C, a.P, a.prof, 1) == 2) {                                 \
+      if (launch_chains_per_wave(a, false) == 2) {                                              \
         auto k2 = hmc_kernel<PROF, false, PP, 256, NN, 1, 2, false, true>;                      \
         (void)hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
         hipLaunchKernelGGL(k2, dim3(grid), dim3(kWave * a.C / 2), lds, s, a);                   \
@@ -1549,8 +1572,8 @@ static hipError_t launch_impl(const HmcArgs& a, int grid, hipStream_t s) {
   // NUTS: no split evaluation
   if (a.nuts && (a.wpc != 1 || a.max_depth < 1 || a.max_depth > kNutsMaxDepth))
     return hipErrorInvalidValue;
-  // two chains per wave exactly where launch_fixed_w, launch_fixed_nuts and
-  // launch_fixed_mx launch them
+  // several chains per wave exactly where launch_fixed_w, launch_fixed_nuts
+  // and launch_fixed_mx launch them
   const int H = launch_chains_per_wave(a, INIT);
   const size_t lds = a.mx ? hmc_lds_bytes(a.N, a.C, a.P, 1, H, a.n_exp, true, a.nuts)
                           : hmc_lds_bytes(a.N, a.C, a.P, INIT ? 1 : a.wpc, H, 1, false, a.nuts);

@@ -78,9 +78,6 @@ __host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
   SlotPlan best{0, 0, 0, 1 << 30, 0, 0, 0};
   for (int k = 0; k < 7; ++k) {
     const int P = kPlanP[k];
-#ifdef BSI_PLAN_P
-    if (P != BSI_PLAN_P) continue;
-#endif
     if (!plan_valid(N, P)) continue;
     const SlotPlan sp = make_slot_plan_p(N, P);
     if (sp.nslots < best.nslots) best = sp;
@@ -373,10 +370,10 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
 // waves hold the same totals.  The block must reach this function with all
 // its waves (the exchange uses a workgroup barrier).
 //
-// Two chains per wave (H = 2, NFIX kernels only): each 32-lane half runs the
-// loop for its own chain (its own X, Ym, Yf tables and shape constants) over
-// pair-slots l, l + 32, ..., i.e. 2 P pair-iterations per super-row, and the
-// sums are reduced per half.
+// Several chains per wave (H = 2 or 4, NFIX kernels only): the 64 / H lanes
+// of each chain run the loop for their own chain (its own X, Ym, Yf tables
+// and shape constants) over pair-slots l, l + 64 / H, ..., i.e. H P
+// pair-iterations per super-row, and the sums are reduced per chain.
 //
 // CORR (one wave per chain or two chains per wave; not with a split
 // evaluation): sqw holds sqrt w per bin in the data spectrum's order
@@ -389,7 +386,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
                              float* xch = nullptr, const float* __restrict__ sqw = nullptr) {
   static_assert(W == 1 || NFIX > 0, "split evaluation needs a specialised kernel");
   static_assert(!CORR || W == 1, "noise weights: not with a split evaluation");
-  static_assert(H == 1 || (NFIX > 0 && W == 1), "two chains per wave need a specialised kernel");
+  static_assert(H == 1 || (NFIX > 0 && W == 1), "several chains per wave need a specialised kernel");
   constexpr int PI = P * H;           // pair-iterations per super-row of this lane
   constexpr int LS = kWave / H;       // lanes per chain
   const int lane = chain_lane<H>();
@@ -552,8 +549,8 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     s.chi2 = CHI2 ? wave_total(chi2) : 0.0;
     wave_total7(v, red);
   } else {
-    s.chi2 = CHI2 ? half_total(chi2) : 0.0;
-    half_total7(v, red);
+    s.chi2 = CHI2 ? group_total<H>(chi2) : 0.0;
+    group_total7<H>(v, red);
   }
   s.sF = v[0];
   s.sxx = v[1];

@@ -172,8 +172,8 @@ def test_loglik_edge_cases(bsi):
             bsi.loglik_grad(bad, torch.zeros(625).cuda(), torch.ones(1, 6).cuda())
 
 
-def _hmc_setup(bsi, torch, cfg_name, n_gal, C, seed=3):
-    t, params, data, off = synth.make_population(cfg_name, n_gal=n_gal, seed=seed)
+def _hmc_setup(bsi, torch, cfg_name, n_gal, C, seed=3, sizes=None):
+    t, params, data, off = synth.make_population(cfg_name, n_gal=n_gal, seed=seed, sizes=sizes)
     init = synth.init_positions(t, params, data, off, C, seed=seed + 1)
     b = _batch(bsi, torch, t.n_pix, t.psf_fwhm, t.sigma)
     ref = np.stack([t.dx, t.dy], axis=1)
@@ -257,14 +257,18 @@ def test_hmc_spergel_fit_parity(bsi, nu):
     assert agree >= G * C * S - 2
 
 
-def test_hmc_mixed_sizes_parity_and_invariance(bsi):
-    """One batch of five stamp sizes: each chain follows the oracle under the
-    same Philox momenta; graph replay and forked direct launches agree
-    bitwise; each galaxy's chains are bitwise those of the galaxy alone."""
+@pytest.mark.parametrize("C,sizes", [(2, [25, 41, 53, 73, 101]), (4, [25, 41, 53, 73, 101, 41])])
+def test_hmc_mixed_sizes_parity_and_invariance(bsi, C, sizes):
+    """One batch of several stamp sizes: each chain follows the oracle under
+    the same Philox momenta; graph replay (sizes in sequence) and direct
+    launches (sizes on forked streams) agree bitwise; each galaxy's chains are bitwise
+    those of the galaxy alone.  With two chains the 25-, 41- and 53-pixel
+    galaxies run two chains per wave; with four, the 25- and 41-pixel ones
+    run four per wave (16 lanes each), the 53-pixel one two, and the others
+    one wave per chain."""
     import torch
-    _log("hmc mixed sizes 25/41/53/73/101")
-    sizes = [25, 41, 53, 73, 101]
-    G, C, S = len(sizes), 2, 3
+    _log(f"hmc mixed sizes {sizes} C={C}")
+    G, S = len(sizes), 3
     t, params, data, off = synth.make_population("uneven", n_gal=G, seed=17, sizes=sizes)
     init = synth.init_positions(t, params, data, off, C, seed=18)
     b = _batch(bsi, torch, t.n_pix, t.psf_fwhm, t.sigma)
@@ -273,7 +277,7 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi):
     base = dict(n_chains=C, n_leapfrog=8, n_warmup=0, n_samples=S, adapt=False, step_size=0.003,
                 jitter=0.1, seed=seed)
     s, stats, st = _run_gpu(bsi, torch, b, data, ref, init, bsi.HmcConfig(**base))
-    # graph replay (sizes in sequence) and direct launches (sizes on forked streams) agree bitwise
+    # graph replay and direct launches agree bitwise
     s_direct = _run_gpu(bsi, torch, b, data, ref, init, bsi.HmcConfig(use_graph=False, **base))[0]
     assert np.array_equal(s, s_direct)
     agree = 0
@@ -291,16 +295,18 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi):
     assert agree >= G * C * S - 1
 
 
-@pytest.mark.parametrize("workload", ["tiny", "uniform"])
-def test_hmc_dual_averaging_parity(bsi, workload):
+@pytest.mark.parametrize("workload,C,sizes", [("tiny", 2, None), ("uniform", 2, None),
+                                               ("uneven", 4, [41, 25, 41])])
+def test_hmc_dual_averaging_parity(bsi, workload, C, sizes):
     """Trajectories agree until the first accept/reject decision that float32
     and float64 potentials take differently; the step-size recursion is then
     checked exactly by replaying the GPU's own acceptance statistics.  The
-    53-pixel case runs the two-chains-per-wave kernel (trace included)."""
+    53-pixel case runs the two-chains-per-wave kernel, the 25- and 41-pixel
+    case with four chains the four-chains-per-wave kernel (trace included)."""
     import torch
-    _log(f"hmc dual averaging parity {workload}")
-    G, C, W, S = 3, 2, 30, 4
-    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, workload, G, C, seed=11)
+    _log(f"hmc dual averaging parity {workload} C={C} sizes={sizes}")
+    G, W, S = 3, 30, 4
+    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, workload, G, C, seed=11, sizes=sizes)
     seed = 77
     # Fisher-diagonal metric: a well-conditioned trajectory (with the identity
     # metric the log-flux direction puts eps * omega near the leapfrog
@@ -376,11 +382,16 @@ def test_hmc_fisher_metric_parity(bsi):
     assert agree >= G * 4 - 1
 
 
-def test_hmc_forms_and_batch_invariance_bitwise(bsi):
+@pytest.mark.parametrize("workload,C,sizes", [("tiny", 2, None), ("uneven", 4, [41, 25, 41, 25])])
+def test_hmc_forms_and_batch_invariance_bitwise(bsi, workload, C, sizes):
+    """Plain form (one galaxy and one leapfrog step per launch), one and three
+    iterations per launch, graph and direct launches give the same chains
+    bitwise, and a galaxy alone equals its slice of the batch (with four
+    chains at 25 and 41 pixels: the four-chains-per-wave kernel)."""
     import torch
-    _log("hmc plain/batched/graph/batch-invariance")
-    G, C = 4, 2
-    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, "tiny", G, C, seed=21)
+    _log(f"hmc plain/batched/graph/batch-invariance {workload} C={C}")
+    G = 4
+    t, params, data, off, init, b, ref = _hmc_setup(bsi, torch, workload, G, C, seed=21, sizes=sizes)
     base = dict(n_chains=C, n_leapfrog=5, n_warmup=4, n_samples=5, adapt=True, step_size=0.005,
                 jitter=0.1, seed=5)
     outs = []

@@ -136,3 +136,65 @@ def test_split_chains_at_parity(bsi, wpc):
             moved_g = k == 0 or np.any(s1[i, 0, k] != s1[i, 0, k - 1])
             moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
             assert moved_g != moved_o, (wpc, N, k)
+
+
+def _restated_layout(N, P):
+    """Host restatement of the pair-slot layout: npc = hc + 1 pair-columns per
+    row (rows 0..hc), R = floor(64 P / npc) rows per super-row, lane l of
+    iteration i holding pair-slot l + 64 i, pair-slot (j, v) holding the bins
+    (+j, v) and (-j, v), column 0 as two half-weight copies.  Returns (number
+    of super-rows, {bin: total squared weight}) or None for an invalid plan."""
+    nc = N if N % 2 else N - 1
+    hc = (nc - 1) // 2
+    rows = npc = hc + 1
+    R = (64 * P) // npc
+    if R < 1:
+        return None
+    R = min(R, rows)
+    nsr = -(-rows // R)
+    weight = {}
+    for sr in range(nsr):
+        for sl in range(min(P * 64, R * npc)):
+            ro, j = divmod(sl, npc)
+            v = sr * R + ro
+            if v > hc:
+                continue
+            for half in (0, 1):
+                u = -j if half else j
+                w = (0.5 if v == 0 else 1.0) * (0.5 if j == 0 else 1.0)
+                weight[(u, v)] = weight.get((u, v), 0.0) + w
+    return nsr, weight
+
+
+def test_library_plans_tile_the_half_plane(bsi):
+    """For every stamp side 8..128 and every plan P the library accepts
+    (bsi_set_plan / bsi_get_plan), its slot count is that of the pair-slot
+    layout (two stored values per pair-slot, padding included); that layout
+    covers the odd core's half plane with total weight 1 per bin (row 0) or
+    1 with its mirror (rows 1..hc), and the mirrors complete the DFT grid.
+    The plans the library rejects are exactly those with no row per super-row,
+    and its default plan has the fewest slots (ties: the smaller P)."""
+    import torch  # noqa: F401  (device fixture)
+    for N in range(8, 129):
+        nc = N if N % 2 else N - 1
+        rows = (nc - 1) // 2 + 1
+        best = None
+        for P in (1, 2, 3, 4, 5, 6, 8):
+            lay = _restated_layout(N, P)
+            if lay is None:
+                with pytest.raises(bsi.BsiError):
+                    bsi.set_plan(N, P)
+                continue
+            bsi.set_plan(N, P)
+            got_P, slots = bsi.get_plan(N)
+            nsr, weight = lay
+            assert got_P == P and slots == 2 * nsr * P * 64, (N, P, got_P, slots)
+            assert len(weight) == nc * rows, (N, P)
+            for (u, v), w in weight.items():
+                assert w == (0.5 if v == 0 else 1.0), (N, P, u, v, w)
+            full = {(u, v) for (u, v) in weight} | {(-u, -v) for (u, v) in weight}
+            assert len(full) == nc * nc, (N, P)
+            if best is None or slots < best[1]:
+                best = (P, slots)
+        bsi.set_plan(N, 0)
+        assert bsi.get_plan(N) == best, (N, bsi.get_plan(N), best)

@@ -198,48 +198,6 @@ def test_gradient_central_differences_on_256_parameter_sets():
     assert worst > 0.0
 
 
-def test_every_slot_plan_tiles_the_half_plane():
-    """For every stamp side and every supported plan P, the pair-slots (row 0
-    whole, rows 1..hc; pair-slot (j, v) holding the bins (+j, v) and (-j, v),
-    column 0 as two half-weight copies) cover the odd core's half plane with
-    total weight 1 per bin; the mirrors complete the DFT grid.  Host
-    restatement of the layout (npc = hc + 1 pair-columns per row, R =
-    floor(64 P / npc) rows per super-row, lane l of iteration i holding
-    pair-slot l + 64 i, stored value 2 s + h the bin (+-j, v) of pair-slot s)."""
-    for N in range(8, 129):
-        nc = N if N % 2 else N - 1
-        hc = (nc - 1) // 2
-        rows = npc = hc + 1
-        for P in (1, 2, 3, 4, 5, 6, 8):
-            R = (64 * P) // npc
-            if R < 1:
-                continue
-            R = min(R, rows)
-            nsr = -(-rows // R)
-            weight = {}
-            for sr in range(nsr):
-                for sl in range(P * 64):
-                    if sl >= R * npc:
-                        continue
-                    ro, j = divmod(sl, npc)
-                    v = sr * R + ro
-                    if v > hc:
-                        continue
-                    for half in (0, 1):
-                        u = -j if half else j
-                        w = (0.5 if v == 0 else 1.0) * (0.5 if j == 0 else 1.0)
-                        weight[(u, v)] = weight.get((u, v), 0.0) + w
-            # each stored value's squared scale is w; with the factor 2 of the
-            # half plane, row 0 totals 1 per bin, rows 1..hc count 2 (with mirror)
-            assert len(weight) == nc * rows, (N, P)
-            for (u, v), w in weight.items():
-                assert w == (0.5 if v == 0 else 1.0), (N, P, u, v, w)
-            full = set()
-            for (u, v) in weight:
-                full.add((u, v))
-                full.add((-u, -v))
-            assert len(full) == nc * nc, (N, P)
-
 # ---- Spergel profiles (the paper's Appendix B model-bias fits) -------------
 
 def _spergel_intensity(r, nu, r0=1.0):
