@@ -51,7 +51,7 @@
 extern "C" {
 #endif
 
-#define BSI_VERSION 3
+#define BSI_VERSION 4
 
 enum {
   BSI_OK = 0,
@@ -100,8 +100,25 @@ int bsi_version(void);
 int bsi_device_count(int32_t* n);
 
 /* Create a handle bound to `device` (HIP ordinal).  Fails with BSI_ENODEV
- * when no device exists, BSI_EUNSUPPORTED when it is not gfx950. */
-int bsi_create(bsi_handle* out, int32_t device);
+ * when no device exists, BSI_EUNSUPPORTED when it is not gfx950.
+ *
+ * tune_cache [host, nullable or empty: none]: path of a tuning cache, a text
+ * file holding the slot plans and render transforms chosen per stamp side.
+ * If the file exists and was written by this library version for this device
+ * (architecture and compute-unit count), the handle starts with its choices;
+ * a file of another version or device is ignored, a missing file is an empty
+ * cache, and a file that does not parse fails the call with BSI_EINVAL
+ * (message from bsi_last_error(NULL)).  bsi_autotune and
+ * bsi_autotune_transform then rewrite the file with the handle's choices at
+ * that moment (explicit bsi_set_plan / bsi_set_transform choices included),
+ * by writing a private file and renaming it over the cache; a failed write
+ * makes those calls return BSI_EINVAL (the handle keeps its new choices).
+ * Format, one item per line: "bsi-tune-cache 1", "library <version>",
+ * "device <arch> <compute units>", then "plan <N> <P>" and
+ * "transform <N> <method>" lines.  (A runtime facility: the paper's
+ * method does not depend on these settings, only the speed of the kernels
+ * that evaluate it.) */
+int bsi_create(bsi_handle* out, int32_t device, const char* tune_cache);
 
 /* Release a handle and its workspace; NULL is ignored.  Waits for the
  * handle's outstanding work. */

@@ -102,7 +102,7 @@ class SlotsInfo(C.Structure):
 SIGNATURES = {
     "bsi_version": (C.c_int, []),
     "bsi_device_count": (C.c_int, [C.POINTER(C.c_int32)]),
-    "bsi_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32]),
+    "bsi_create": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.c_char_p]),
     "bsi_destroy": (None, [C.c_void_p]),
     "bsi_last_error": (C.c_char_p, [C.c_void_p]),
     "bsi_reserve": (C.c_int, [C.c_void_p, C.POINTER(ReserveCfg)]),

@@ -4,6 +4,7 @@ the HIP library; this module only checks shapes and passes pointers."""
 from __future__ import annotations
 
 import ctypes as C
+import os
 import math
 from dataclasses import dataclass, field
 
@@ -29,13 +30,15 @@ def _stream(device):
 
 
 class Library:
-    """One handle on one device.  Use ``get()`` for the process-wide default."""
+    """One handle on one device.  Use ``get()`` for the process-wide default.
+    tune_cache: path of the handle's tuning cache (bsi_create), or None."""
 
-    def __init__(self, device: int = 0):
+    def __init__(self, device: int = 0, tune_cache: str | None = None):
         self.lib = N.load()
         self.device = device
         h = C.c_void_p()
-        rc = self.lib.bsi_create(C.byref(h), device)
+        path = None if tune_cache is None else os.fsencode(tune_cache)
+        rc = self.lib.bsi_create(C.byref(h), device, path)
         if rc != N.BSI_OK:
             raise BsiError(f"bsi_create: {N.ERRORS.get(rc, rc)}: {self.lib.bsi_last_error(None).decode()}")
         self.h = h

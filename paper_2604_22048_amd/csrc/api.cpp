@@ -216,7 +216,7 @@ int bsi_device_count(int32_t* n) {
   return BSI_OK;
 }
 
-int bsi_create(bsi_handle* out, int32_t device) {
+int bsi_create(bsi_handle* out, int32_t device, const char* tune_cache) {
   if (!out) {
     g_create_error = "out is NULL";
     return BSI_EINVAL;
@@ -257,6 +257,16 @@ int bsi_create(bsi_handle* out, int32_t device) {
   h->device = device;
   h->num_cu = prop.multiProcessorCount;
   h->scratch = scratch;
+  h->arch = std::string(prop.gcnArchName).substr(0, std::string(prop.gcnArchName).find(':'));
+  if (tune_cache && *tune_cache) {
+    h->tune_cache = tune_cache;
+    std::string err;
+    if (load_tune_cache(h, err) != BSI_OK) {
+      delete h;
+      g_create_error = err;
+      return BSI_EINVAL;
+    }
+  }
   bool ok = hipStreamCreate(&h->own) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming) == hipSuccess &&

@@ -5,8 +5,15 @@
 
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <cerrno>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "bsi_kernels.h"
@@ -59,6 +66,115 @@ struct Scratch {
 };
 
 }  // namespace
+
+// Tuning cache file: a text file of lines
+//   bsi-tune-cache 1
+//   library <BSI_VERSION>
+//   device <architecture name> <compute units>
+//   plan <N> <P>              one per stamp side with a chosen slot plan
+//   transform <N> <method>    one per stamp side with a chosen transform
+// The choices were measured on one device with one library build: a file of
+// another library version or device is ignored, and a missing file is an
+// empty cache.  Anything else that does not parse is an error.
+namespace bsi_host {
+
+int load_tune_cache(bsi_ctx* h, std::string& err) {
+  FILE* fp = std::fopen(h->tune_cache.c_str(), "r");
+  if (!fp) {
+    if (errno == ENOENT) return BSI_OK;
+    err = "tune cache " + h->tune_cache + ": cannot read (" + std::strerror(errno) + ")";
+    return BSI_EINVAL;
+  }
+  std::string text;
+  char buf[4096];
+  for (size_t k; (k = std::fread(buf, 1, sizeof(buf), fp)) > 0;) text.append(buf, k);
+  const bool read_ok = !std::ferror(fp);
+  std::fclose(fp);
+  if (!read_ok) {
+    err = "tune cache " + h->tune_cache + ": read error";
+    return BSI_EINVAL;
+  }
+  std::istringstream f(text);
+  int plan[kMaxN + 1] = {}, tr[kMaxN + 1] = {};
+  bool matches = true, seen_lib = false, seen_dev = false;
+  std::string line;
+  int no = 0;
+  auto bad = [&](const char* why) {
+    err = "tune cache " + h->tune_cache + ", line " + std::to_string(no) + ": " + why;
+    return BSI_EINVAL;
+  };
+  while (std::getline(f, line)) {
+    ++no;
+    std::istringstream in(line);
+    std::string key;
+    if (!(in >> key)) continue;   // blank line
+    std::string extra;
+    if (no == 1) {
+      int fmt = 0;
+      if (key != "bsi-tune-cache" || !(in >> fmt) || fmt != 1 || (in >> extra))
+        return bad("not a tuning cache of format 1");
+      continue;
+    }
+    if (key == "library") {
+      int v = 0;
+      if (!(in >> v) || (in >> extra)) return bad("expected 'library <version>'");
+      matches &= (v == BSI_VERSION);
+      seen_lib = true;
+    } else if (key == "device") {
+      std::string arch;
+      int cus = 0;
+      if (!(in >> arch >> cus) || (in >> extra)) return bad("expected 'device <arch> <compute units>'");
+      matches &= (arch == h->arch && cus == h->num_cu);
+      seen_dev = true;
+    } else if (key == "plan" || key == "transform") {
+      int n = 0, v = 0;
+      if (!(in >> n >> v) || (in >> extra)) return bad("expected '<key> <stamp side> <value>'");
+      if (n < 8 || n > kMaxN) return bad("stamp side outside [8, 128]");
+      if (key == "plan") {
+        if (!supported_p(v) || !plan_valid(n, v)) return bad("slot plan not available for this side");
+        plan[n] = v;
+      } else {
+        if (v != BSI_TRANSFORM_DIRECT && v != BSI_TRANSFORM_MFMA) return bad("unknown transform");
+        tr[n] = v;
+      }
+    } else {
+      return bad("unknown key");
+    }
+  }
+  if (no == 0) return BSI_OK;        // empty file: empty cache
+  if (!seen_lib || !seen_dev) {
+    err = "tune cache " + h->tune_cache + ": no 'library' or 'device' line";
+    return BSI_EINVAL;
+  }
+  if (!matches) return BSI_OK;       // measured by another build or on another device
+  for (int n = 8; n <= kMaxN; ++n) {
+    if (plan[n]) h->plan_P[n] = plan[n];
+    if (tr[n]) h->transform[n] = tr[n];
+  }
+  return BSI_OK;
+}
+
+int save_tune_cache(bsi_handle h) {
+  if (h->tune_cache.empty()) return BSI_OK;
+  // written whole to a private file, then renamed over the cache
+  const std::string tmp = h->tune_cache + ".tmp." + std::to_string((long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return fail(h, BSI_EINVAL, "tune cache %s: cannot write (%s)", tmp.c_str(), std::strerror(errno));
+  std::fprintf(f, "bsi-tune-cache 1\nlibrary %d\ndevice %s %d\n", BSI_VERSION, h->arch.c_str(), h->num_cu);
+  for (int n = 8; n <= kMaxN; ++n)
+    if (h->plan_P[n] > 0) std::fprintf(f, "plan %d %d\n", n, h->plan_P[n]);
+  for (int n = 8; n <= kMaxN; ++n)
+    if (h->transform[n] != 0) std::fprintf(f, "transform %d %d\n", n, h->transform[n]);
+  const bool ok = !std::ferror(f);
+  if (std::fclose(f) != 0 || !ok || std::rename(tmp.c_str(), h->tune_cache.c_str()) != 0) {
+    const int e = errno;
+    std::remove(tmp.c_str());
+    return fail(h, BSI_EINVAL, "tune cache %s: write failed (%s)", h->tune_cache.c_str(), std::strerror(e));
+  }
+  return BSI_OK;
+}
+
+}  // namespace bsi_host
 
 extern "C" {
 
@@ -216,7 +332,7 @@ int bsi_autotune(bsi_handle h, int32_t n_sizes, const int32_t* sizes, int32_t n_
     if (chosen) chosen[i] = best_P;
     if (ms_out) ms_out[i] = best_ms;
   }
-  return BSI_OK;
+  return save_tune_cache(h);
 }
 
 int bsi_set_transform(bsi_handle h, int32_t n, int32_t method) {
@@ -322,7 +438,7 @@ int bsi_autotune_transform(bsi_handle h, int32_t n_sizes, const int32_t* sizes, 
     if (ms_out)
       for (int m = 0; m < 4; ++m) ms_out[4 * i + m] = best[m];
   }
-  return BSI_OK;
+  return save_tune_cache(h);
 }
 
 }  // extern "C"

@@ -69,6 +69,8 @@ struct bsi_ctx {
   std::vector<void*> retired_host;    // replaced staging buffers
   std::vector<PendingGraph> graphs;   // graphs whose replays may still run
   void* scratch = nullptr;   // this device's allocation-free scratch (device address)
+  std::string arch;          // device architecture name (tuning cache key)
+  std::string tune_cache;    // tuning cache path (empty: none)
 };
 
 namespace bsi_host {
@@ -234,6 +236,13 @@ inline size_t stage_size(std::initializer_list<size_t> sizes) {
   for (size_t b : sizes) t += (b + 15) & ~size_t(15);
   return t;
 }
+
+// Tuning cache (autotune.cpp): apply the choices stored at h->tune_cache if
+// the file exists and was written by this library version for this device
+// (BSI_EINVAL with a message in err for a malformed file); write the
+// handle's current choices there.
+int load_tune_cache(bsi_ctx* h, std::string& err);
+int save_tune_cache(bsi_handle h);
 
 }  // namespace bsi_host
 

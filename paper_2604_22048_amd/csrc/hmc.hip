@@ -1368,7 +1368,10 @@ constexpr bool paired_chains_plan(int N, int P) {
 // Plans with a four-chains-per-wave kernel (16 lanes per chain; fixed-length
 // trajectories of four chains, one exposure): the small stamps, whose work
 // outside the pair loop (tables, reductions, leapfrog update, random numbers)
-// is per wave and so shared by four chains instead of two.
+// is per wave and so shared by four chains instead of two.  Not at 53: a
+// wave then holds a whole galaxy, so each wave needs its own 12 KiB data
+// spectrum in LDS (LDS would limit a CU to about 6 waves instead of 8), and
+// the 4 P = 12 columns over 4 super-rows spill inside the step loop.
 constexpr bool quad_chains_plan(int N, int P) { return (N == 25 && P == 3) || (N == 41 && P == 1); }
 
 // Chains per wave of an advance launch, the one rule that launch_fixed_w,

@@ -100,11 +100,13 @@ def test_no_device_and_null_handle_paths(native):
     lib = native.load()
     n = C.c_int32(-1)
     assert lib.bsi_device_count(C.byref(n)) == 0 and n.value >= 0
-    assert lib.bsi_version() == 3
+    assert lib.bsi_version() == 4
+    assert lib.bsi_create(None, 0, None) == -1
     if n.value == 0:
         h = C.c_void_p()
-        assert lib.bsi_create(C.byref(h), 0) == -5
+        assert lib.bsi_create(C.byref(h), 0, None) == -5
         assert b"device" in lib.bsi_last_error(None)
+        assert lib.bsi_create(C.byref(h), 0, b"/nonexistent/cache") == -5   # device checked first
     b = native.Batch()
     assert lib.bsi_render_stamps(None, C.byref(b), None, None, None) == -1
     assert lib.bsi_loglik_grad(None, C.byref(b), None, None, None, None, None, 0, None) == -1

@@ -143,16 +143,17 @@ def test_hmc_exposures_parity(bsi, metric, sizes, C, E):
     assert agree >= G * C * S - 2
 
 
-@pytest.mark.parametrize("sizes", [[25, 25], [30, 30]])
-def test_nuts_exposures_parity(bsi, sizes):
+@pytest.mark.parametrize("sizes,C", [([25, 25], 2), ([30, 30], 2), ([53, 53], 4)])
+def test_nuts_exposures_parity(bsi, sizes, C):
     """NUTS on galaxies seen in two exposures with correlated noise (the
-    weighted form of the 25-pixel specialised kernel and of the general
+    weighted form of the 25- and 53-pixel specialised kernels, the latter
+    with four chains as in the exposures benchmark, and of the general
     kernels): chains follow the oracle's NUTS."""
     import torch
     from oracle import nuts
-    _log(f"exposures nuts parity sizes={sizes}")
+    _log(f"exposures nuts parity sizes={sizes} C={C}")
     rng = np.random.default_rng(95 + sizes[0])
-    E, C, S = 2, 2, 4
+    E, S = 2, 4
     p, n, psf, sig, ps, stamps = synth.exposure_population(rng, sizes, E, True)
     G = len(sizes)
     b, data = _upload(bsi, torch, n, psf, sig, ps, stamps, E)

@@ -198,3 +198,54 @@ def test_library_plans_tile_the_half_plane(bsi):
                 best = (P, slots)
         bsi.set_plan(N, 0)
         assert bsi.get_plan(N) == best, (N, bsi.get_plan(N), best)
+
+
+def test_tune_cache_round_trip(bsi, tmp_path):
+    """bsi_create's tuning cache: bsi_autotune writes the handle's choices;
+    a new handle on the same cache starts with them; a cache written for
+    another device is ignored; a cache that does not parse fails creation."""
+    _log("tune cache")
+    path = tmp_path / "tune.txt"
+    lib = bsi.Library(0, tune_cache=str(path))
+    assert not path.exists()
+    bsi.set_transform(53, bsi.N.TRANSFORM_DIRECT, lib=lib)
+    bsi.autotune([25, 53], n_chains=4, lib=lib)
+    lines = path.read_text().splitlines()
+    assert lines[0] == "bsi-tune-cache 1" and lines[1] == "library 4"
+    dev = lines[2].split()
+    assert dev[0] == "device" and dev[1].startswith("gfx950") and int(dev[2]) > 0
+    chosen = {N: bsi.get_plan(N, lib=lib)[0] for N in (25, 53)}
+    assert {f"plan {N} {P}" for N, P in chosen.items()} <= set(lines[3:])
+    assert "transform 53 1" in lines[3:]
+    lib.close()
+
+    lib2 = bsi.Library(0, tune_cache=str(path))
+    assert {N: bsi.get_plan(N, lib=lib2)[0] for N in (25, 53)} == chosen
+    assert bsi.get_transform(53, lib=lib2) == bsi.N.TRANSFORM_DIRECT
+    lib2.close()
+
+    # a cache for this device with a plan the defaults would not pick
+    mine = tmp_path / "mine.txt"
+    mine.write_text("\n".join(lines[:3] + ["plan 53 6", "transform 41 1"]) + "\n")
+    lib3 = bsi.Library(0, tune_cache=str(mine))
+    assert bsi.get_plan(53, lib=lib3)[0] == 6 and bsi.get_transform(41, lib=lib3) == 1
+    assert bsi.get_plan(25, lib=lib3)[0] == 3
+    lib3.close()
+
+    # another device's (or library version's) cache is ignored
+    for hdr in (lines[:2] + [f"device {dev[1]} {int(dev[2]) + 1}"],
+                ["bsi-tune-cache 1", "library 3", lines[2]]):
+        other = tmp_path / "other.txt"
+        other.write_text("\n".join(hdr + ["plan 53 6"]) + "\n")
+        lib4 = bsi.Library(0, tune_cache=str(other))
+        assert bsi.get_plan(53, lib=lib4)[0] == 3
+        lib4.close()
+
+    # malformed caches fail bsi_create with BSI_EINVAL
+    for body in ("not a cache\n", "bsi-tune-cache 1\nplan 53 7\n", "bsi-tune-cache 1\nplan 300 3\n",
+                 "bsi-tune-cache 1\ncolour blue\n", "bsi-tune-cache 1\ntransform 53 9\n",
+                 "bsi-tune-cache 1\nplan 53 6\n"):
+        bad = tmp_path / "bad.txt"
+        bad.write_text(body)
+        with pytest.raises(bsi.BsiError, match="BSI_EINVAL.*tune cache"):
+            bsi.Library(0, tune_cache=str(bad))
