@@ -423,8 +423,11 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
     steps, 300 warmup + 1000 draws; the size classes launch concurrently.
     per_size_runs: also time each size class alone (uneven_per_size)."""
     cfg = gen.CONFIGS["uneven"]
+    say = log or (lambda m: None)
     plans = api.autotune(list(gen.SIZE_CLASSES), n_chains=cfg.chains)
+    say(f"[uneven] plans {plans}")
     t, b, data, ref, init = make_inputs(api, torch, n_gal, cfg)
+    say(f"[uneven] {n_gal} galaxies rendered")
     C, L, W, S = cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
     hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
                          metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
@@ -435,7 +438,9 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
     dcfg = api.HmcConfig(**{**wcfg.__dict__, "use_graph": False})
     _, t_w_direct = timed(torch, lambda: api.hmc_sample(b, data, ref, init, dcfg, want_samples=False),
                           stream)
+    say(f"[uneven] warmup-only direct call {t_w_direct:.3f} s")
     (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
+    say(f"[uneven] sampler call {t_hmc:.3f} s")
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
@@ -446,7 +451,7 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
     counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
     del smp, st, e, rh, data
-    per_size = uneven_per_size(api, torch, stream, cfg, counts, hcfg) if per_size_runs else None
+    per_size = uneven_per_size(api, torch, stream, cfg, counts, hcfg, log=say) if per_size_runs else None
     return {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
             "t_hmc_s": round(t_hmc, 4),
             "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
@@ -459,7 +464,7 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
             "per_size": per_size}
 
 
-def uneven_per_size(api, torch, stream, cfg, counts, hcfg, n1=20, n2=60):
+def uneven_per_size(api, torch, stream, cfg, counts, hcfg, n1=20, n2=60, log=None):
     """Trajectory-kernel time per launch of each size class of the uneven
     batch, alone on the device: a batch of that many galaxies of that size
     (drawn from the uneven population with the stamp side forced), timed as
@@ -480,6 +485,8 @@ def uneven_per_size(api, torch, stream, cfg, counts, hcfg, n1=20, n2=60):
             ts.append(dt)
         t_launch = (ts[1] - ts[0]) / (n2 - n1)
         tf = flops_per_eval(N, hcfg.n_leapfrog) * k * hcfg.n_chains * hcfg.n_leapfrog / t_launch / 1e12
+        if log:
+            log(f"[uneven] {N} px alone: {t_launch * 1e3:.4f} ms per launch")
         out[N] = {"n_gal": k, "launch_ms": round(t_launch * 1e3, 4), "achieved_tflops": round(tf, 3),
                   "frac_fp32_peak": round(tf / FP32_PEAK_TFLOPS, 4),
                   "frac_of_nonpacked_issue_ceiling": round(tf / VALU_ISSUE_TFLOPS, 4)}
@@ -670,7 +677,9 @@ def exposures_leg(api, torch, stream, n_gal, E, log, sampler="hmc", depth=5):
                                 "iters_per_launch": W + Sd})
     wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
     api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
+    say(f"[uneven] warmup-only direct call {t_w_direct:.3f} s")
     (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
+    say(f"[uneven] sampler call {t_hmc:.3f} s")
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())

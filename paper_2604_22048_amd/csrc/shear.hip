@@ -21,6 +21,8 @@ namespace bsi {
 namespace {
 
 constexpr int kMaxPerLane = 16;    // K <= 1024
+constexpr int kSampleGroup = 16;   // samples per scheduling group of the weight sums
+constexpr int kPairPoints = 2;     // points evaluated together in the main pass
 constexpr int kPtsPerChunk = 64;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -161,64 +163,96 @@ __device__ __forceinline__ float sample_lw(const Point& P, float emax2, float e1
   return l;
 }
 
-// The lane's sums over its samples at one point, each weight taken as
-// x = 2^(lw2 - U) for a wave-uniform reference U: x and, with the gradient,
+// One sample's weight against a reference U, x = 2^(lw2 - U), formed as
+// 2^(c0 - U - a1 E - zq^2) / B^2 (times (1 - E)^2 for the unit-disk density):
+// the same value as exp2 of sample_lw's sum, with the logarithms of B and
+// 1 - E replaced by products (one transcendental instead of three), and 0
+// outside the density's support.  ep2 = |e'|^2 of the sample.
+template <bool SZ, int EK>
+__device__ __forceinline__ float sample_x(const Point& P, float emax2, float e1, float e2, float ep2,
+                                          float ls, float c0U, float& E, float& iB, float& zq) {
+  const float dot = fmaf(P.g2, e2, P.g1 * e1);
+  const float B = fmaf(P.gg, ep2, fmaf(-2.0f, dot, 1.0f));
+  iB = __builtin_amdgcn_rcpf(B);
+  E = fmaf(-2.0f, dot, ep2 + P.gg) * iB;
+  float l = fmaf(-E, P.a1, c0U);
+  if (SZ) {
+    zq = fmaf(ls, P.kz, P.kz0);
+    l = fmaf(-zq, zq, l);
+  }
+  float x = __builtin_amdgcn_exp2f(l) * (iB * iB);
+  if (EK == 0) {
+    const float om = 1.0f - E;
+    x = (E < 1.0f) ? x * (om * om) : 0.0f;
+  } else {
+    x = (E < emax2) ? x : 0.0f;
+  }
+  return x;
+}
+
+// The lane's sums over its samples at NP points at once (independent work
+// for the scheduler to interleave), each weight taken as x = 2^(lw2 - U) for
+// a wave-uniform reference U of its point: x and, with the gradient,
 // x/B (dlp - c |e'|^2), x/B (c - dlp) e1', x/B (c - dlp) e2', x zq, x zq^2,
 // x E, where c = dlp E + 2 and dlp = d ln p_e / dE (natural units): the
 // g-derivative of ln w is 2/B [g (dlp - c |e'|^2) + (c - dlp) e'] - 4 g /
 // (1 - |g|^2), so g enters only after the sums.
-template <bool GRAD, bool SZ, int EK, int NS>
-__device__ __forceinline__ void lane_sums(const Point& P, float emax2, const float* e1, const float* e2,
-                                          const float* ls, const float* c0, float U, float* v) {
+template <bool GRAD, bool SZ, int EK, int NS, int NP = 1>
+__device__ __forceinline__ void lane_sums(const Point* const* Ps, float emax2, const float* e1,
+                                          const float* e2, const float* ep2, const float* ls,
+                                          const float* c0, const float* U, float (*v)[7]) {
 #pragma unroll
-  for (int j = 0; j < 7; ++j) v[j] = 0.f;
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int j = 0; j < 7; ++j) v[p][j] = 0.f;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
-    float E, iB, zq = 0.f;
-    const float ep2 = fmaf(e1[i], e1[i], e2[i] * e2[i]);
-    const float l = sample_lw<SZ, EK>(P, emax2, e1[i], e2[i], ep2, ls[i], c0[i], E, iB, zq);
-    const float x = __builtin_amdgcn_exp2f(l - U);
-    v[0] += x;
-    if (GRAD) {
-      float c, w, dl;
-      if (EK == 0) {
-        dl = fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f - fminf(E, 0.999999f)), P.dlp);
-        c = fmaf(dl, E, 2.0f);
-        w = c - dl;
-      } else {
-        dl = P.dlp;
-        c = fmaf(dl, E, 2.0f);
-        w = fmaf(dl, E, P.w0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const Point& P = *Ps[p];
+      float E, iB, zq = 0.f;
+      const float x = sample_x<SZ, EK>(P, emax2, e1[i], e2[i], ep2[i], ls[i], c0[i] - U[p], E, iB, zq);
+      v[p][0] += x;
+      if (GRAD) {
+        float c, w, dl;
+        if (EK == 0) {
+          dl = fmaf(-2.0f, __builtin_amdgcn_rcpf(1.0f - fminf(E, 0.999999f)), P.dlp);
+          c = fmaf(dl, E, 2.0f);
+          w = c - dl;
+        } else {
+          dl = P.dlp;
+          c = fmaf(dl, E, 2.0f);
+          w = fmaf(dl, E, P.w0);
+        }
+        const float u = fmaf(-c, ep2[i], dl);
+        const float q = x * iB;
+        v[p][1] = fmaf(q, u, v[p][1]);
+        const float r = q * w;
+        v[p][2] = fmaf(r, e1[i], v[p][2]);
+        v[p][3] = fmaf(r, e2[i], v[p][3]);
+        if (SZ) {
+          const float xz = x * zq;
+          v[p][4] += xz;
+          v[p][5] = fmaf(xz, zq, v[p][5]);
+        }
+        v[p][6] = fmaf(x, E, v[p][6]);
       }
-      const float u = fmaf(-c, ep2, dl);
-      const float q = x * iB;
-      v[1] = fmaf(q, u, v[1]);
-      const float r = q * w;
-      v[2] = fmaf(r, e1[i], v[2]);
-      v[3] = fmaf(r, e2[i], v[3]);
-      if (SZ) {
-        const float xz = x * zq;
-        v[4] += xz;
-        v[5] = fmaf(xz, zq, v[5]);
-      }
-      v[6] = fmaf(x, E, v[6]);
     }
-    // groups of four samples: the scheduler interleaves within a group only,
-    // which bounds the live temporaries (and so the registers per wave)
-    if ((i & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    // groups of kSampleGroup samples: the scheduler interleaves within a
+    // group only, which bounds the live temporaries (and so the registers)
+    if ((i % kSampleGroup) == kSampleGroup - 1) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
 // The wave maximum of the log weights at one point.
 template <bool SZ, int EK, int NS>
 __device__ __forceinline__ float wave_lw_max(const Point& P, float emax2, const float* e1, const float* e2,
-                                             const float* ls, const float* c0) {
+                                             const float* ep2, const float* ls, const float* c0) {
   float m = -INFINITY;
 #pragma unroll
   for (int i = 0; i < NS; ++i) {
     float E, iB, zq;
-    const float ep2 = fmaf(e1[i], e1[i], e2[i] * e2[i]);
-    m = fmaxf(m, sample_lw<SZ, EK>(P, emax2, e1[i], e2[i], ep2, ls[i], c0[i], E, iB, zq));
+    m = fmaxf(m, sample_lw<SZ, EK>(P, emax2, e1[i], e2[i], ep2[i], ls[i], c0[i], E, iB, zq));
   }
   return wave_max_dpp(m);
 }
@@ -289,7 +323,7 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
   const float emax2 = a.e_max * a.e_max;
   double* rec = &fin[wave][0][0];
   for (; gal < a.n_gal; gal += waves_total) {
-    float e1[NS], e2[NS], ls[NS], c0[NS];
+    float e1[NS], e2[NS], ep2[NS], ls[NS], c0[NS];
     // this galaxy's samples have landed: move them to registers, then start
     // the next galaxy's transfer into the freed buffer
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
@@ -310,8 +344,10 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
       c0[i] = -INFINITY;
       if (k >= a.K) {
         e1[i] = e2[i] = ls[i] = 0.f;
-      } else {
-        const float Ep = fmaf(e1[i], e1[i], e2[i] * e2[i]);
+      }
+      ep2[i] = fmaf(e1[i], e1[i], e2[i] * e2[i]);
+      if (k < a.K) {
+        const float Ep = ep2[i];
         float c = fmaf(-2.0f, __builtin_amdgcn_logf(1.0f - Ep), fmaf(Ep, b0, lz0));
         if (a.flux_term) {
           const float lf = a.l10f[(int64_t)gal * a.K + k];
@@ -324,15 +360,31 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
       }
     }
     const float cwave = wave_max_dpp(cmax);
-    for (int pj = 0; pj < npc; ++pj) {
-      const Point& P = pts_s[pj];
-      const float U = (cwave > -INFINITY) ? cwave + P.du : 0.0f;
-      float v[7];
-      lane_sums<GRAD, SZ, EK, NS>(P, emax2, e1, e2, ls, c0, U, v);
-      // float64 totals over the wave (lane 8 j + 7 holds total j) into the
-      // point's record; U in slot 7
-      const double t = wave_group8_f64(v, wred[wave]);
-      if ((lane & 7) == 7) rec[pj * 8 + (lane >> 3)] = (lane == 63) ? (double)U : t;
+    // kPairPoints points per pass over the samples, then the remaining ones
+    // singly; each point's sums are totalled over the wave in float64 (lane
+    // 8 j + 7 holds total j) into the point's record, with U in slot 7
+    int pj = 0;
+    for (; pj + kPairPoints <= npc; pj += kPairPoints) {
+      const Point* Ps[kPairPoints];
+      float U[kPairPoints], v[kPairPoints][7];
+#pragma unroll
+      for (int p = 0; p < kPairPoints; ++p) {
+        Ps[p] = &pts_s[pj + p];
+        U[p] = (cwave > -INFINITY) ? cwave + Ps[p]->du : 0.0f;
+      }
+      lane_sums<GRAD, SZ, EK, NS, kPairPoints>(Ps, emax2, e1, e2, ep2, ls, c0, U, v);
+#pragma unroll
+      for (int p = 0; p < kPairPoints; ++p) {
+        const double t = wave_group8_f64(v[p], wred[wave]);
+        if ((lane & 7) == 7) rec[(pj + p) * 8 + (lane >> 3)] = (lane == 63) ? (double)U[p] : t;
+      }
+    }
+    for (; pj < npc; ++pj) {
+      const Point* Ps[1] = {&pts_s[pj]};
+      float U[1] = {(cwave > -INFINITY) ? cwave + Ps[0]->du : 0.0f}, v[1][7];
+      lane_sums<GRAD, SZ, EK, NS>(Ps, emax2, e1, e2, ep2, ls, c0, U, v);
+      const double t = wave_group8_f64(v[0], wred[wave]);
+      if ((lane & 7) == 7) rec[pj * 8 + (lane >> 3)] = (lane == 63) ? (double)U[0] : t;
     }
     wave_lds_sync();
     // points whose total weight against the bound is tiny (or zero): again
@@ -343,11 +395,11 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
       while (todo) {
         const int pj = __builtin_ctzll(todo);
         todo &= todo - 1;
-        const Point& P = pts_s[pj];
-        const float M = wave_lw_max<SZ, EK, NS>(P, emax2, e1, e2, ls, c0);
-        float v[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        if (M > -INFINITY) lane_sums<GRAD, SZ, EK, NS>(P, emax2, e1, e2, ls, c0, M, v);
-        const double t = wave_group8_f64(v, wred[wave]);
+        const Point* Ps[1] = {&pts_s[pj]};
+        const float M = wave_lw_max<SZ, EK, NS>(*Ps[0], emax2, e1, e2, ep2, ls, c0);
+        float v[1][7] = {{0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}};
+        if (M > -INFINITY) lane_sums<GRAD, SZ, EK, NS>(Ps, emax2, e1, e2, ep2, ls, c0, &M, v);
+        const double t = wave_group8_f64(v[0], wred[wave]);
         if ((lane & 7) == 7) rec[pj * 8 + (lane >> 3)] = (lane == 63) ? (double)M : t;
       }
       wave_lds_sync();
