@@ -512,8 +512,6 @@ def spergel_leg(api, torch, stream, n_gal, nu, log=None):
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(bs, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
-    acc = st[..., 0].mean()
-    n_flag = int((status != 0).sum())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     flop = flops_per_eval(cfg.n_pix) * n_gal * C * L * (W + S)
@@ -677,14 +675,10 @@ def exposures_leg(api, torch, stream, n_gal, E, log, sampler="hmc", depth=5):
                                 "iters_per_launch": W + Sd})
     wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
     api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
-    say(f"[uneven] warmup-only direct call {t_w_direct:.3f} s")
     (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
-    say(f"[uneven] sampler call {t_hmc:.3f} s")
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
     _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
     n_eff = float(e.mean(dim=1).mean())
-    acc = st[..., 0].mean()
-    n_flag = int((status != 0).sum())
     t_s = t_hmc - t_w
     tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
     flop = flops_per_eval(N, L, weighted=True) * E * n_gal * C * L * (W + Sd) if sampler == "hmc" else None
