@@ -1,12 +1,14 @@
 """Float32 error bounds for the shear-phase parity tests.
 
-The library evaluates each log importance weight ln w_nk (eq.
-true-prior-jacobian-shear over the interim prior) in float32 and everything
-after it (the log-sum-exp over k, the sum over galaxies, the gradient
-assembly) in float64, except the per-lane partial sums of at most 16 terms
-e^(ln w - m) in float32 (reading R17).  These bounds are derived from that
-split with the float32 unit roundoff u = 2^-24, using the oracle's float64
-functions only; nothing here depends on the library.
+The library evaluates each importance weight w_nk (eq.
+true-prior-jacobian-shear over the interim prior) in float32, as
+x = 2^(lw2 - U) with lw2 = ln w / ln 2 and U a wave-uniform bound >= lw2
+(the Jacobian's 1/B^2 applied as a product rather than through a
+logarithm), and everything after it (the log-sum-exp over k, the sum over
+galaxies, the gradient assembly) in float64, except the per-lane partial
+sums of at most 16 terms x in float32 (reading R17).  These bounds are
+derived from that split with the float32 unit roundoff u = 2^-24, using the
+oracle's float64 functions only; nothing here depends on the library.
 
 Per sample, a float32 evaluation of ln w = sum_i t_i (the ellipticity
 density, the shear Jacobian, minus the interim density, the size and flux
