@@ -723,6 +723,8 @@ def main():
                     help="uniform workload: this slot plan P for the 53-pixel kernel instead of autotuning")
     ap.add_argument("--transform-only", action="store_true",
                     help="only the render-transform comparison (both transforms, workload sizes)")
+    ap.add_argument("--shear-k", type=int, default=1000,
+                    help="--workload shear-pass: interim samples per galaxy (above 1024: chunked)")
     ap.add_argument("--serve-requests", type=int, default=0,
                     help="--workload serving: this many Poisson requests at 2000/s (overrides "
                          "--serve-window; only the ESS-targeted run and the capacity are measured)")
@@ -763,11 +765,13 @@ def main():
             print(json.dumps(out), flush=True)
             return
         if args.workload == "shear-pass":
-            res = shear_pass_leg(api, torch, stream, args.steps)
+            G = args.n_gal or 10_000
+            K = args.shear_k
+            res = shear_pass_leg(api, torch, stream, args.steps, G=G, K=K)
             out = {"metric": "shear posterior evaluation pass (4 points, with gradient)",
                    "value": res["gb_per_s"], "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
                    "dtype": "f32", "data": "synthetic",
-                   "config": {"workload": "10,000 galaxies x 1,000 interim samples, 4 points"}, **res}
+                   "config": {"workload": f"{G:,} galaxies x {K:,} interim samples, 4 points"}, **res}
             print(json.dumps(out), flush=True)
             return
         if args.workload == "nuts":

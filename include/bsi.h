@@ -372,6 +372,9 @@ typedef struct {
  * The log-sum-exp over k and the sum over galaxies are carried in float64.
  *   e1p, e2p, log10s, log10f  [device] float[n_gal][K] interim samples
  *              (structure of arrays; log10f may be NULL when flux_term = 0).
+ *              Any K >= 1: up to 1024 samples per galaxy are held at once;
+ *              larger K is taken in chunks of 512 whose float64 sums are
+ *              combined exactly (a rescaling to the larger reference).
  *   pts      [host or device, see pts_on_device] double[n_pts][5].
  *   logpost  [device] double[n_pts].
  *   grad     [device] double[n_pts][5] gradient of ln P, or NULL.

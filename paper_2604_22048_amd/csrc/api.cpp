@@ -613,7 +613,7 @@ int check_shear_inputs(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
                        const float* log10s, const float* log10f, const bsi_true_prior* tp,
                        const bsi_interim* ip) {
   if (n_gal < 1) return fail(h, BSI_EINVAL, "n_gal must be >= 1");
-  if (K < 1 || K > 1024) return fail(h, BSI_EUNSUPPORTED, "K must be in 1..1024");
+  if (K < 1) return fail(h, BSI_EINVAL, "K must be >= 1");
   if (!tp || !ip) return fail(h, BSI_EINVAL, "true prior / interim is NULL");
   if (tp->e_kind != BSI_E_BA14 && tp->e_kind != BSI_E_TRUNC_GAUSS)
     return fail(h, BSI_EINVAL, "unknown e_kind");

@@ -5,8 +5,8 @@
 //   ln |d eps / d eps'| = 2 ln(1 - |g|^2) - 2 ln |1 - conj(g) eps'|^2.
 // Layout: structure of arrays, float[n_gal][K] per field.  Grid: y = chunk of
 // up to 64 points, x = block of galaxies.  A wave keeps one galaxy's samples
-// in registers (K <= 64 * kMaxPerLane) and loops over the chunk's points; lane
-// j accumulates point j of the chunk.  Log-weights and the per-lane sums of
+// in registers (K <= 64 * kMaxPerLane; larger K in chunks of 512 samples) and
+// loops over the chunk's points; lane j accumulates point j of the chunk.  Log-weights and the per-lane sums of
 // their exponentials (at most 16 terms in (0, 1]) are float; the wave maximum,
 // the sums across lanes and galaxies, the logarithm and the gradient assembly
 // are float64.  Per-block partials are reduced in a fixed order (bitwise
@@ -20,7 +20,7 @@ namespace bsi {
 
 namespace {
 
-constexpr int kMaxPerLane = 16;    // K <= 1024
+constexpr int kMaxPerLane = 16;    // samples per lane held at once (K <= 1024 in one chunk)
 constexpr int kSampleGroup = 16;   // samples per scheduling group of the weight sums
 constexpr int kPairPoints = 2;     // points evaluated together in the main pass
 constexpr int kPtsPerChunk = 64;
@@ -282,36 +282,45 @@ constexpr double kLooseTotal = 0x1p-60;
 // lane j finishes point j from its record -- the float64 logarithm of the
 // log-sum-exp and the gradient assembly -- so those run once per point, in
 // parallel across the lanes.
-template <bool GRAD, bool SZ, int EK, int NS>
+//
+// MULTI (K > 64 NS): a galaxy's samples are taken in chunks of 64 NS; each
+// chunk's totals (against the chunk's own bound, with the same fallback) are
+// added in float64 into a running record per point, rescaled to the larger
+// of the two references, and the finish runs after the galaxy's last chunk.
+template <bool GRAD, bool SZ, int EK, int NS, bool MULTI = false>
 __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
-  // per wave: the next galaxy's e1', e2', log10 s, loaded straight into LDS
-  // while the current galaxy is evaluated (sample k at index k)
-  __shared__ float pre[4][3][NS * 64];
+  constexpr int CH = NS * kWave;   // samples per chunk
+  // per wave: the next chunk's e1', e2', log10 s, loaded straight into LDS
+  // while the current one is evaluated (sample k of the chunk at index k)
+  __shared__ float pre[4][3][CH];
   __shared__ Point pts_s[kPtsPerChunk];
   __shared__ __align__(16) float wred[4][64 * 8];       // per-wave transposed-reduction scratch
-  // per-wave point records (7 totals, reference U) while the galaxies run; the
+  // per-wave point records (7 totals, reference U) of the current chunk; the
   // block's per-point sums (acc of each wave) at the end
   __shared__ double fin[4][kPtsPerChunk][8];
+  // per-wave running records of the galaxy over its chunks (MULTI only)
+  __shared__ double run_s[MULTI ? 4 : 1][MULTI ? kPtsPerChunk : 1][8];
   double (*red)[kPtsPerChunk][6] = reinterpret_cast<double (*)[kPtsPerChunk][6]>(&fin[0][0][0]);
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int chunk0 = blockIdx.y * kPtsPerChunk;
   const int npc = min(kPtsPerChunk, a.n_pts - chunk0);
   const int waves_total = gridDim.x * 4;
-  // LDS DMA of galaxy g's samples into this wave's buffer (lanes past K load
-  // the galaxy's first sample, masked when read)
-  auto prefetch = [&](int g) {
-    const int64_t base = (int64_t)g * a.K;
+  const int nch = MULTI ? (a.K + CH - 1) / CH : 1;   // sample chunks per galaxy
+  // LDS DMA of chunk c of galaxy g into this wave's buffer (lanes past K load
+  // the chunk's first sample, masked when read)
+  auto prefetch = [&](int g, int c) {
+    const int64_t base = (int64_t)g * a.K + (int64_t)c * CH;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
       const int k = lane + i * kWave;
-      const int64_t o = base + (k < a.K ? k : 0);
+      const int64_t o = base + (c * CH + k < a.K ? k : 0);
       __builtin_amdgcn_global_load_lds(a.e1p + o, &pre[wave][0][i * kWave], 4, 0, 0);
       __builtin_amdgcn_global_load_lds(a.e2p + o, &pre[wave][1][i * kWave], 4, 0, 0);
       if (SZ) __builtin_amdgcn_global_load_lds(a.l10s + o, &pre[wave][2][i * kWave], 4, 0, 0);
     }
   };
-  int gal = blockIdx.x * 4 + wave;
-  if (gal < a.n_gal) prefetch(gal);
+  int gal = blockIdx.x * 4 + wave, ch = 0;
+  if (gal < a.n_gal) prefetch(gal, 0);
   // the points' constants, while the first galaxy's samples are in flight
   if ((int)threadIdx.x < npc) pts_s[threadIdx.x] = make_point(a.pts + 5 * (int64_t)(chunk0 + threadIdx.x), a);
   __syncthreads();
@@ -322,10 +331,11 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
   const double logK = a.logK;
   const float emax2 = a.e_max * a.e_max;
   double* rec = &fin[wave][0][0];
-  for (; gal < a.n_gal; gal += waves_total) {
+  double* run = &run_s[MULTI ? wave : 0][0][0];
+  while (gal < a.n_gal) {
     float e1[NS], e2[NS], ep2[NS], ls[NS], c0[NS];
-    // this galaxy's samples have landed: move them to registers, then start
-    // the next galaxy's transfer into the freed buffer
+    // this chunk's samples have landed: move them to registers, then start
+    // the next chunk's transfer (of this galaxy or the next) into the freed buffer
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     wave_lds_sync();
 #pragma unroll
@@ -336,11 +346,16 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
     }
     __builtin_amdgcn_s_waitcnt(kWaitLgkmcnt0);
     wave_lds_sync();
-    if (gal + waves_total < a.n_gal) prefetch(gal + waves_total);
+    int next_gal = gal, next_ch = ch + 1;
+    if (next_ch == nch) {
+      next_gal = gal + waves_total;
+      next_ch = 0;
+    }
+    if (next_gal < a.n_gal) prefetch(next_gal, next_ch);
     float cmax = -INFINITY;
 #pragma unroll
     for (int i = 0; i < NS; ++i) {
-      const int k = lane + i * kWave;
+      const int k = ch * CH + lane + i * kWave;   // the sample's index in the galaxy
       c0[i] = -INFINITY;
       if (k >= a.K) {
         e1[i] = e2[i] = ls[i] = 0.f;
@@ -404,10 +419,34 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
       }
       wave_lds_sync();
     }
+    if constexpr (MULTI) {
+      // lane j adds the chunk's record of point j into the galaxy's running
+      // record, both scaled to the larger reference (float64)
+      if (lane < npc) {
+        double* Rr = run + lane * 8;
+        const double* T = rec + lane * 8;
+        if (ch == 0 || !(Rr[0] > 0.0)) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Rr[j] = T[j];
+        } else if (T[0] > 0.0) {
+          const double Un = fmax(Rr[7], T[7]);
+          const double fo = exp2(Rr[7] - Un), fn = exp2(T[7] - Un);
+#pragma unroll
+          for (int j = 0; j < 7; ++j) Rr[j] = Rr[j] * fo + T[j] * fn;
+          Rr[7] = Un;
+        }
+      }
+      wave_lds_sync();
+    }
+    const int cur = gal;
+    const bool last = ch + 1 == nch;
+    gal = next_gal;
+    ch = next_ch;
+    if (!last) continue;
     // lane j finishes point j: log-sum-exp and gradient in float64
     if (lane < npc) {
       const Point& P = pts_s[lane];
-      const double* T = rec + lane * 8;
+      const double* T = (MULTI ? run : rec) + lane * 8;
       const double S = T[0];
       double ell = -INFINITY, g[5] = {0, 0, 0, 0, 0};
       if (S > 0.0) {
@@ -423,7 +462,7 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
           g[4] = P.inv_se3 * T[6] * iS - P.dlnZ;
         }
       }
-      if (a.per_gal) a.per_gal[(int64_t)(chunk0 + lane) * a.n_gal + gal] = ell;
+      if (a.per_gal) a.per_gal[(int64_t)(chunk0 + lane) * a.n_gal + cur] = ell;
       acc[0] += ell;
 #pragma unroll
       for (int j = 0; j < 5; ++j) acc[1 + j] += g[j];
@@ -668,16 +707,19 @@ hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s) {
   const int chunks = (a.n_pts + kPtsPerChunk - 1) / kPtsPerChunk;
   const dim3 grid(n_blocks, chunks), blk(256);
   const int KL = (a.K + kWave - 1) / kWave;
-  const int ns = KL <= 4 ? 0 : KL <= 8 ? 1 : 2;    // 4, 8 or 16 sample slots per lane
+  // 4, 8 or 16 sample slots per lane; beyond 16 x 64 samples, chunks of 8 x 64
+  const int ns = KL <= 4 ? 0 : KL <= 8 ? 1 : KL <= kMaxPerLane ? 2 : 3;
   const int key = (a.want_grad ? 4 : 0) | (a.size_term ? 2 : 0) | (a.e_kind == 0 ? 0 : 1);
-  switch (key * 3 + ns) {
+  switch (key * 4 + ns) {
 #define BSI_SHEAR_CASE(G, S, E)                                                                     \
-    case ((G) * 4 + (S) * 2 + (E)) * 3 + 0:                                                         \
+    case ((G) * 4 + (S) * 2 + (E)) * 4 + 0:                                                         \
       hipLaunchKernelGGL((shear_kernel<G, S, E, 4>), grid, blk, 0, s, a); break;                    \
-    case ((G) * 4 + (S) * 2 + (E)) * 3 + 1:                                                         \
+    case ((G) * 4 + (S) * 2 + (E)) * 4 + 1:                                                         \
       hipLaunchKernelGGL((shear_kernel<G, S, E, 8>), grid, blk, 0, s, a); break;                    \
-    case ((G) * 4 + (S) * 2 + (E)) * 3 + 2:                                                         \
-      hipLaunchKernelGGL((shear_kernel<G, S, E, 16>), grid, blk, 0, s, a); break;
+    case ((G) * 4 + (S) * 2 + (E)) * 4 + 2:                                                         \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 16>), grid, blk, 0, s, a); break;                   \
+    case ((G) * 4 + (S) * 2 + (E)) * 4 + 3:                                                         \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 8, true>), grid, blk, 0, s, a); break;
     BSI_SHEAR_CASE(false, false, 0) BSI_SHEAR_CASE(false, false, 1)
     BSI_SHEAR_CASE(false, true, 0) BSI_SHEAR_CASE(false, true, 1)
     BSI_SHEAR_CASE(true, false, 0) BSI_SHEAR_CASE(true, false, 1)

@@ -59,11 +59,15 @@ def _pairs(rng, G, K, sig=0.2, emax=0.7, noise=0.05):
     return out
 
 
-def test_galaxy_loglik_parity(bsi):
+@pytest.mark.parametrize("K", [130, 1700])
+def test_galaxy_loglik_parity(bsi, K):
+    """Per-galaxy log-marginals (eq. likelihood-shear, one galaxy at a time)
+    against the oracle; K = 1700 takes the chunked path (512 samples per
+    chunk, a ragged last one) and its per-galaxy output indexing."""
     import torch
-    _log("per-galaxy shear log-marginals")
+    _log(f"per-galaxy shear log-marginals K={K}")
     rng = np.random.default_rng(50)
-    G, K = 37, 130                      # ragged in waves, galaxies and samples
+    G = 37                              # ragged in waves, galaxies and samples
     Sp, _ = _pairs(rng, G, K)
     alpha = (math.log(0.6), 0.3, 0.2)
     gpts, pts = _grid(9, 8, (-0.3, 0.3), (-0.25, 0.35), alpha)   # 72 points: two chunks

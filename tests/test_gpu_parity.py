@@ -483,11 +483,24 @@ def test_shear_posterior_parity(bsi, kind, flux):
     """Log-posterior and gradient against the oracle within the float32 bound of
     tests/f32bound.py (derived from the library's float32 / float64 split),
     at interior points and at every edge of the hyper-prior boxes."""
+    _shear_parity_case(bsi, kind, flux, 40, 300, 30 + kind)
+
+
+@pytest.mark.parametrize("kind,K", [(0, 2500), (1, 1025), (1, 4000)])
+def test_shear_posterior_many_samples(bsi, kind, K):
+    """More samples per galaxy than a wave holds at once (K > 1024): the pass
+    takes them in chunks of 512 and combines the chunks' float64 sums; the
+    same oracle comparison, including the edge points whose weights force the
+    fallback against the exact maximum.  K = 4000 is every draw of a
+    galaxy's four chains in the benchmark's configuration."""
+    _shear_parity_case(bsi, kind, True, 12, K, 60 + K)
+
+
+def _shear_parity_case(bsi, kind, flux, G, K, seed):
     import torch
     from tests import f32bound
-    _log(f"shear parity kind={kind} flux={flux}")
-    rng = np.random.default_rng(30 + kind)
-    G, K = 40, 300
+    _log(f"shear parity kind={kind} flux={flux} G={G} K={K}")
+    rng = np.random.default_rng(seed)
     S = _shear_samples(rng, G, K)
     # e_max = 1 for the truncated Gaussian: its support is the unit disk, so the
     # disk edge of the shear prior can be probed with finite weights
