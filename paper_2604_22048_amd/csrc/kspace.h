@@ -238,6 +238,7 @@ __device__ __forceinline__ LaneCols<PI> lane_cols(const float4* tab) {
 
 // Per-wave LDS tables of one evaluation.
 //   X [ntab+1]: F a(u) exp(-i k_u dx),   u = -h..h  (k_u dx = 2 pi u dx / N), then 0
+//               (u >= 0 only for odd N: entries u < 0 are left unwritten)
 //   Ym[ymax]  : {a(v) exp(-i k_v dy), k_v, k_v^2} for rows v = 0..ymax-1 (row 0
 //               scaled by 1/sqrt 2, rows > hc zero)
 //   Yf[ntab]  : a(v) exp(-i k_v dy),     v = -h..h (even N only, for the Nyquist bins)
@@ -257,7 +258,9 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
   const int lane = chain_lane<H>();
   const float invN = rcp_nr((float)g.N);
   const float rx = dx * invN, ry = dy * invN;   // revolutions per unit frequency
-  for (int t = lane; t < g.ntab; t += LS) {
+  // the pair loop reads X(u) for u >= 0 only (X(-u) = conj X(u) is formed
+  // there); the even-N Nyquist bins also read u = -N/2, so odd N fill half
+  for (int t = ((g.N & 1) ? g.h : 0) + lane; t < g.ntab; t += LS) {
     const float a = F * atab[t];
     const float2 w = cis_neg_rev((float)(t - g.h) * rx);
     X[t] = make_float2(a * w.x, a * w.y);
