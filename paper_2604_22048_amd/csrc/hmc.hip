@@ -17,6 +17,8 @@
 //   support or has a non-finite dH is rejected; during warmup the step is
 //   adapted by dual averaging (Hoffman & Gelman 2014, Algorithm 5) on
 //   alpha = min(1, exp(-dH)).
+#include <algorithm>
+
 #include "bsi_kernels.h"
 #include "kspace.h"
 
@@ -145,12 +147,11 @@ __device__ __forceinline__ double potential(const GalCtx& c, const LaneCols<P * 
     fill_tables<H>(c.g, c.sp, c.atab, c.X, c.Ym, c.Yf, F, dx, dy);
     KSums S;
     if constexpr (H == 4) {
-      // four chains per wave: the lane's 4 P columns are read again from the
-      // column table at each evaluation rather than held in registers for the
-      // whole trajectory
-      const LaneCols<P * H> lr = lane_cols<P * H, H>(c.cols);
-      S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lr, c.dh, c.X, c.Ym, c.Yf, sh,
-                                                        c.red, c.part, xbuf);
+      // four chains per wave: the lane's 4 P columns are read from the column
+      // table block by block at each evaluation rather than held in registers
+      // for the whole trajectory
+      constexpr int CB = (P * H) < 6 ? P * H : 6;
+      S = kspace_sums_blocked<PROF, P, CHI2, NFIX, CB>(c.cols, c.dh, c.X, c.Ym, sh, c.red);
     } else {
       S = kspace_sums<PROF, P, false, CHI2, NFIX, W, H>(c.g, c.sp, lc, c.dh, c.X, c.Ym, c.Yf, sh,
                                                         c.red, c.part, xbuf);
@@ -324,14 +325,27 @@ __host__ __device__ inline int wave_table_len(const Geom& g, const SlotPlan& sp)
   return 2 * sp.ymax + 2 * g.ntab + 2;
 }
 
+// Four chains per wave (odd N only): Ym and X (padded to an even length),
+// no Nyquist table.
+__host__ __device__ inline int quad_table_len(const Geom& g, const SlotPlan& sp) {
+  return (2 * sp.ymax + g.ntab + 3) & ~1;
+}
+
 // LDS: [data spectrum | sqrt-weights | atab | column table | NW chain
 // records | NWV reduction scratches | NW table sets | exchange areas] for NW
 // chain records (one per wave, or per chain with two chains per wave) and NWV
 // waves per block; E exposures of the first three (sqrt-weights only for MX).
 // idx: this lane's chain record and table set (its wave, or its chain with
 // two chains per wave); wave: its reduction scratch.
+//
+// Four chains per wave (quad; odd N, one wave per workgroup, one exposure):
+// [data spectrum | atab | column table | C chain records | C table sets
+// without the Nyquist table], the wave's reduction scratch laid over the
+// table sets (a chain's reduction runs after its pair loop, when the tables
+// of the evaluation are no longer read), no exchange areas: about 20 KiB per
+// wave at N = 53, so that 8 waves fit a CU's LDS.
 __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx, int wave, int C,
-                                     int NWV, int E = 1, bool mx = false) {
+                                     int NWV, int E = 1, bool mx = false, bool quad = false) {
   extern __shared__ float4 smem4[];
   Lds l;
   l.dh = reinterpret_cast<float2*>(smem4);
@@ -340,6 +354,17 @@ __device__ __forceinline__ Lds carve(const Geom& g, const SlotPlan& sp, int idx,
   l.cols = reinterpret_cast<float4*>(l.atab + E * atab_stride(g));
   ChainState* cs0 = reinterpret_cast<ChainState*>(l.cols + sp.P * 64);
   l.cs = cs0 + idx;
+  if (quad) {
+    float2* wt = reinterpret_cast<float2*>(cs0 + C);
+    float2* w0 = wt + quad_table_len(g, sp) * idx;
+    l.Ym = reinterpret_cast<float4*>(w0);
+    l.X = w0 + 2 * sp.ymax;
+    l.Yf = nullptr;
+    l.red = reinterpret_cast<float*>(wt);
+    l.xch0 = l.red;    // unused (one wave per chain group, no split evaluation)
+    l.nuts = nullptr;
+    return l;
+  }
   float* red0 = reinterpret_cast<float*>(cs0 + C);
   l.red = red0 + 512 * wave;
   float2* wt = reinterpret_cast<float2*>(red0 + 512 * NWV);
@@ -1177,7 +1202,7 @@ __global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU))
   const int cw = (H == 1) ? wave / W : H * wave + (int)((threadIdx.x % kWave) / (kWave / H));
   const int part = (H == 1) ? wave % W : 0;
   const int E = MX ? a.n_exp : 1;
-  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H, E, MX);
+  const Lds l = carve(g, sp, H == 1 ? wave : cw, wave, a.C * W, a.C * W / H, E, MX, H == 4);
   build_col_table(g, sp, l.cols);
   const Prior pr{a.lf_lo, a.lf_hi, a.ls_lo, a.ls_hi, a.sigma_d, a.sigma_e,
                  1.0f / (a.sigma_d * a.sigma_d), 1.0f / (a.sigma_e * a.sigma_e)};
@@ -1309,6 +1334,10 @@ size_t hmc_lds_bytes(int N, int C, int P, int W, int H, int E, bool mx, bool nut
   const Geom g = make_geom(N);
   const SlotPlan sp = make_slot_plan_p(N, P);
   const int NW = C * W;
+  if (H == 4)   // the quad layout of carve
+    return sizeof(float2) * dh_stride(sp) + sizeof(float) * atab_stride(g) + sizeof(float4) * sp.P * 64 +
+           sizeof(ChainState) * NW +
+           std::max<size_t>(sizeof(float2) * quad_table_len(g, sp) * NW, sizeof(float) * 512);
   return sizeof(float2) * E * dh_stride(sp) + sizeof(float) * (mx ? E * sw_stride(sp) : 0) +
          sizeof(float) * E * atab_stride(g) +
          sizeof(float4) * sp.P * 64 + sizeof(ChainState) * NW + sizeof(float) * 512 * (NW / H) +
@@ -1366,13 +1395,15 @@ constexpr bool paired_chains_plan(int N, int P) {
 }
 
 // Plans with a four-chains-per-wave kernel (16 lanes per chain; fixed-length
-// trajectories of four chains, one exposure): the small stamps, whose work
-// outside the pair loop (tables, reductions, leapfrog update, random numbers)
-// is per wave and so shared by four chains instead of two.  Not at 53: a
-// wave then holds a whole galaxy, so each wave needs its own 12 KiB data
-// spectrum in LDS (LDS would limit a CU to about 6 waves instead of 8), and
-// the 4 P = 12 columns over 4 super-rows spill inside the step loop.
-constexpr bool quad_chains_plan(int N, int P) { return (N == 25 && P == 3) || (N == 41 && P == 1); }
+// trajectories of four chains, one exposure, odd N): the work outside the
+// pair loop (tables, reductions, leapfrog update, random numbers) is per wave
+// and so shared by four chains instead of two.  A wave then holds a whole
+// galaxy, so each wave needs its own data spectrum in LDS (the quad layout of
+// carve keeps 53 px at about 20 KiB, 8 waves per CU), and the pair loop runs
+// in column blocks (kspace_sums_blocked) so that it stays in registers.
+constexpr bool quad_chains_plan(int N, int P) {
+  return (N == 25 && P == 3) || (N == 41 && P == 1) || (N == 53 && P == 3);
+}
 
 // Chains per wave of an advance launch, the one rule that launch_fixed_w,
 // launch_fixed_nuts, launch_fixed_mx and the LDS size follow.  Several chains

@@ -591,6 +591,90 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   return s;
 }
 
+// Four chains per wave on an odd stamp side (NFIX kernels, one wave per
+// galaxy, no noise weights): the same sums as kspace_sums with H = 4, with the
+// lane's 4 P pair-slot columns taken in blocks of CB.  Each block reads its
+// columns from the column table, runs over every super-row (the next pair's
+// LDS reads issued ahead of the current pair's arithmetic), and folds its
+// per-column sums into the totals before the next block, so only one block's
+// column constants and accumulators are live at a time.
+template <int PROF, int P, bool CHI2, int NFIX, int CB>
+__device__ KSums kspace_sums_blocked(const float4* cols, const float2* __restrict__ dh, const float2* X,
+                                     const float4* Ym, const Shape& sh, float* red) {
+  constexpr int H = 4;
+  constexpr int LS = kWave / H;      // lanes per chain
+  constexpr int PI = P * H;          // pair-slot columns of a lane per super-row
+  constexpr SlotPlan spc = make_slot_plan_p(NFIX, P);
+  constexpr int K = spc.nsr;
+  static_assert((NFIX & 1) && PI % CB == 0, "odd stamp sides, whole column blocks");
+  const int lane = chain_lane<H>();
+  const float4* dp = reinterpret_cast<const float4*>(dh) + lane;
+  double chi2 = 0.0;
+  float sF = 0.f, syy = 0.f, sdy = 0.f, sxx = 0.f, sxy = 0.f, sdx = 0.f;
+#pragma unroll
+  for (int cb = 0; cb < PI; cb += CB) {
+    float kx[CB], kx2[CB], xr[CB], xi[CB], TA[CB], Tc[CB];
+    const float4* yq[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const float4 e = cols[lane + LS * (cb + i)];
+      kx[i] = e.x;
+      kx2[i] = e.y;
+      const float2 x = X[__float_as_int(e.z)];
+      xr[i] = x.x;
+      xi[i] = x.y;
+      TA[i] = fmaf(sh.ta, kx2[i], sh.t0);
+      Tc[i] = sh.tc * kx[i];
+      yq[i] = Ym + __float_as_int(e.w);
+    }
+    float swq[CB], wky[CB], sdc[CB];
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      swq[i] = 0.f;
+      wky[i] = 0.f;
+      sdc[i] = 0.f;
+    }
+    float4 Dn = dp[cb * LS];
+    float4 yn = yq[0][0];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      float c2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < CB; ++i) {
+        const float4 D = Dn;
+        const float4 y = yn;
+        const int b = k * CB + i + 1;          // next pair of this block
+        if (b < K * CB) {
+          Dn = dp[((b / CB) * PI + cb + b % CB) * LS];
+          yn = yq[b % CB][(b / CB) * spc.R];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
+        pair_step<PROF, false>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
+                               sdc[i], sdy, CHI2);
+      }
+      if (CHI2) chi2 += (double)c2;
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      sxx = fmaf(kx2[i], swq[i], sxx);
+      sxy = fmaf(kx[i], wky[i], sxy);
+      sdx = fmaf(kx[i], sdc[i], sdx);
+    }
+  }
+  KSums s;
+  float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
+  s.chi2 = CHI2 ? group_total<H>(chi2) : 0.0;
+  group_total7<H>(v, red);
+  s.sF = v[0];
+  s.sxx = v[1];
+  s.syy = v[2];
+  s.sxy = v[3];
+  s.sdx = v[4];
+  s.sdy = v[5];
+  s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
+  return s;
+}
+
 // Turn the sums into log L and d log L / d(F, s, e1, e2, dx, dy).
 // norm = 1 / (N^2 sigma^2); s_arcsec is the half-light radius.  The X table
 // carried the flux, so sF = sum Re(conj R T) and dT/dF = T / F.
