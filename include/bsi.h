@@ -518,8 +518,8 @@ int bsi_shear_hmc(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p, cons
  * float32 rounding (the order of the sums changes).  The trajectory kernel
  * runs several chains per wave on the plans 25: P 3, 41: P 1, 53: P 3
  * (exponential or Spergel profile, one wave per chain requested, an even
- * number of chains up to 4): four (16 lanes each) for fixed-length
- * trajectories of exactly four chains at 25 and 41 (one exposure, white
+ * number of chains up to 4): four (16 lanes each, one wave per galaxy) for
+ * fixed-length trajectories of exactly four chains (one exposure, white
  * noise), else two (32 lanes each); one chain per wave otherwise.  The choice
  * depends only on the size, plan and configuration, never on the batch. */
 

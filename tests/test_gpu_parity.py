@@ -263,9 +263,9 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi, C, sizes):
     the same Philox momenta; graph replay (sizes in sequence) and direct
     launches (sizes on forked streams) agree bitwise; each galaxy's chains are bitwise
     those of the galaxy alone.  With two chains the 25-, 41- and 53-pixel
-    galaxies run two chains per wave; with four, the 25- and 41-pixel ones
-    run four per wave (16 lanes each), the 53-pixel one two, and the others
-    one wave per chain."""
+    galaxies run two chains per wave; with four, the 25-, 41- and 53-pixel
+    ones run four per wave (16 lanes each, one wave per galaxy), and the
+    others one wave per chain."""
     import torch
     _log(f"hmc mixed sizes {sizes} C={C}")
     G, S = len(sizes), 3
@@ -296,13 +296,14 @@ def test_hmc_mixed_sizes_parity_and_invariance(bsi, C, sizes):
 
 
 @pytest.mark.parametrize("workload,C,sizes", [("tiny", 2, None), ("uniform", 2, None),
-                                               ("uneven", 4, [41, 25, 41])])
+                                               ("uneven", 4, [41, 25, 53])])
 def test_hmc_dual_averaging_parity(bsi, workload, C, sizes):
     """Trajectories agree until the first accept/reject decision that float32
     and float64 potentials take differently; the step-size recursion is then
     checked exactly by replaying the GPU's own acceptance statistics.  The
-    53-pixel case runs the two-chains-per-wave kernel, the 25- and 41-pixel
-    case with four chains the four-chains-per-wave kernel (trace included)."""
+    53-pixel case with two chains runs the two-chains-per-wave kernel, the
+    25-, 41- and 53-pixel case with four chains the four-chains-per-wave
+    kernel (trace included)."""
     import torch
     _log(f"hmc dual averaging parity {workload} C={C} sizes={sizes}")
     G, W, S = 3, 30, 4
@@ -382,12 +383,12 @@ def test_hmc_fisher_metric_parity(bsi):
     assert agree >= G * 4 - 1
 
 
-@pytest.mark.parametrize("workload,C,sizes", [("tiny", 2, None), ("uneven", 4, [41, 25, 41, 25])])
+@pytest.mark.parametrize("workload,C,sizes", [("tiny", 2, None), ("uneven", 4, [41, 53, 41, 25])])
 def test_hmc_forms_and_batch_invariance_bitwise(bsi, workload, C, sizes):
     """Plain form (one galaxy and one leapfrog step per launch), one and three
     iterations per launch, graph and direct launches give the same chains
     bitwise, and a galaxy alone equals its slice of the batch (with four
-    chains at 25 and 41 pixels: the four-chains-per-wave kernel)."""
+    chains at 25, 41 and 53 pixels: the four-chains-per-wave kernel)."""
     import torch
     _log(f"hmc plain/batched/graph/batch-invariance {workload} C={C}")
     G = 4
