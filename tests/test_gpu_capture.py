@@ -70,11 +70,12 @@ def _replays(torch, g, outs, refs, n=3):
             assert torch.equal(o, r), k
 
 
-@pytest.mark.parametrize("sizes", [[25] * 6, [25, 41, 53, 25, 73]])
-def test_hmc_sample_captured_into_caller_graph(mods, sizes):
+@pytest.mark.parametrize("sizes,C", [([25] * 6, 2), ([25, 41, 53, 25, 73], 2), ([25, 41, 53, 25, 73], 4)])
+def test_hmc_sample_captured_into_caller_graph(mods, sizes, C):
+    """With C = 2 the 25/41/53-pixel galaxies run two chains per wave, with
+    C = 4 four chains per wave (one wave per galaxy)."""
     api, torch = mods
-    _log(f"capture hmc_sample sizes {sizes}")
-    C = 2
+    _log(f"capture hmc_sample sizes {sizes} C={C}")
     lib = api.Library(0)
     b, data, ref, init = _inputs(api, torch, sizes, C, seed=31)
     api.reserve(max_stamps=len(sizes), max_n=max(sizes), max_chains=C, lib=lib)
