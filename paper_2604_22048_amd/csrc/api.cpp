@@ -629,12 +629,14 @@ int check_shear_inputs(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p,
 
 // Blocks of one evaluation pass over n_gal galaxies at n_pts points (four
 // waves per block, one galaxy per wave at a time): about one round of
-// resident workgroups over all point chunks (two per compute unit on 256
-// units), so that each wave runs through several galaxies and prefetches the
-// next one's samples while it evaluates the current one.
+// resident workgroups over all point chunks, so that each wave runs through
+// several galaxies and prefetches the next one's samples while it evaluates
+// the current one.  At most 16 points the kernel forms hold 8 samples per
+// lane and fit three blocks on each of the 256 compute units; otherwise two.
 int shear_blocks(int n_gal, int n_pts) {
   const int chunks = (n_pts + 63) / 64;
-  return std::max(1, std::min((n_gal + 3) / 4, std::max(16, 512 / chunks)));
+  const int resident = n_pts <= 16 ? 768 : 512;
+  return std::max(1, std::min((n_gal + 3) / 4, std::max(16, resident / chunks)));
 }
 
 ShearArgs shear_args(int32_t n_gal, int32_t K, const float* e1p, const float* e2p,

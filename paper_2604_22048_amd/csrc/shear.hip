@@ -14,6 +14,7 @@
 #include "bsi.h"
 #include "bsi_kernels.h"
 
+#include <algorithm>
 #include <mutex>
 
 namespace bsi {
@@ -23,6 +24,7 @@ namespace {
 constexpr int kMaxPerLane = 16;    // samples per lane held at once (K <= 1024 in one chunk)
 constexpr int kSampleGroup = 16;   // samples per scheduling group of the weight sums
 constexpr int kPairPoints = 2;     // points evaluated together in the main pass
+constexpr int kFewPoints = 16;     // at most this many points: the chunked form for K > 512
 constexpr int kPtsPerChunk = 64;
 constexpr double kPi = 3.14159265358979323846;
 
@@ -62,6 +64,12 @@ struct Point {
   double c1, c2;          // 4 g / (1 - |g|^2): the Jacobian's |g| derivative
   double inv_sig_s, inv_se3, dlnZ;
 };
+
+// Dynamic LDS of shear_kernel for npa points: the point records (twice for
+// the chunked form) and the points' constants.
+inline size_t shear_dyn_lds(int npa, bool multi) {
+  return sizeof(double) * (multi ? 64 : 32) * npa + sizeof(Point) * npa;
+}
 
 constexpr double kLog2e = 1.44269504088896340736;
 constexpr double kLn2 = 0.69314718055994530942;
@@ -287,20 +295,27 @@ constexpr double kLooseTotal = 0x1p-60;
 // chunk's totals (against the chunk's own bound, with the same fallback) are
 // added in float64 into a running record per point, rescaled to the larger
 // of the two references, and the finish runs after the galaxy's last chunk.
+//
+// LDS: the sample buffers and the reduction scratch are static; the point
+// records (and the running records, MULTI) and the points' constants are
+// dynamic, sized for npa = min(64, n_pts) points (shear_dyn_lds), so that a
+// pass over few points (the shear-level sampler's chains) leaves LDS room for
+// more resident blocks.  NS <= 8 kernels are built for three waves per SIMD.
 template <bool GRAD, bool SZ, int EK, int NS, bool MULTI = false>
-__global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
+__global__ void __launch_bounds__(256, (NS <= 8 ? 3 : 2)) shear_kernel(ShearArgs a) {
   constexpr int CH = NS * kWave;   // samples per chunk
   // per wave: the next chunk's e1', e2', log10 s, loaded straight into LDS
   // while the current one is evaluated (sample k of the chunk at index k)
   __shared__ float pre[4][3][CH];
-  __shared__ Point pts_s[kPtsPerChunk];
   __shared__ __align__(16) float wred[4][64 * 8];       // per-wave transposed-reduction scratch
-  // per-wave point records (7 totals, reference U) of the current chunk; the
-  // block's per-point sums (acc of each wave) at the end
-  __shared__ double fin[4][kPtsPerChunk][8];
-  // per-wave running records of the galaxy over its chunks (MULTI only)
-  __shared__ double run_s[MULTI ? 4 : 1][MULTI ? kPtsPerChunk : 1][8];
-  double (*red)[kPtsPerChunk][6] = reinterpret_cast<double (*)[kPtsPerChunk][6]>(&fin[0][0][0]);
+  // dynamic: per-wave point records [4][npa][8] (7 totals, reference U) of the
+  // current chunk, which also hold the block's per-point sums at the end;
+  // per-wave running records [4][npa][8] of the galaxy over its chunks
+  // (MULTI only); the points' constants [npa]
+  extern __shared__ double dyn_s[];
+  const int npa = min(kPtsPerChunk, a.n_pts);
+  double* fin = dyn_s;
+  Point* pts_s = reinterpret_cast<Point*>(dyn_s + (MULTI ? 64 : 32) * npa);
   const int lane = lane_id(), wave = threadIdx.x / kWave;
   const int chunk0 = blockIdx.y * kPtsPerChunk;
   const int npc = min(kPtsPerChunk, a.n_pts - chunk0);
@@ -330,8 +345,8 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
   const float b0 = a.b0, lz0 = a.lz0;
   const double logK = a.logK;
   const float emax2 = a.e_max * a.e_max;
-  double* rec = &fin[wave][0][0];
-  double* run = &run_s[MULTI ? wave : 0][0][0];
+  double* rec = fin + wave * npa * 8;
+  double* run = dyn_s + 32 * npa + wave * npa * 8;   // MULTI only
   while (gal < a.n_gal) {
     float e1[NS], e2[NS], ep2[NS], ls[NS], c0[NS];
     // this chunk's samples have landed: move them to registers, then start
@@ -470,12 +485,15 @@ __global__ void __launch_bounds__(256, 2) shear_kernel(ShearArgs a) {
     wave_lds_sync();
   }
   __syncthreads();    // every wave is done with its records
+  double* red = fin;   // [4][npa][6]: each wave's per-point sums
+  if (lane < npc)
 #pragma unroll
-  for (int j = 0; j < 6; ++j) red[wave][lane][j] = acc[j];
+    for (int j = 0; j < 6; ++j) red[(wave * npa + lane) * 6 + j] = acc[j];
   __syncthreads();
   for (int t = threadIdx.x; t < npc * 6; t += blockDim.x) {
     const int pj = t / 6, j = t - pj * 6;
-    const double v = red[0][pj][j] + red[1][pj][j] + red[2][pj][j] + red[3][pj][j];
+    const double v = red[pj * 6 + j] + red[(npa + pj) * 6 + j] + red[(2 * npa + pj) * 6 + j] +
+                     red[(3 * npa + pj) * 6 + j];
     a.partial[((int64_t)blockIdx.x * a.n_pts + chunk0 + pj) * 6 + j] = v;
   }
 }
@@ -707,19 +725,23 @@ hipError_t launch_shear(const ShearArgs& a, int n_blocks, hipStream_t s) {
   const int chunks = (a.n_pts + kPtsPerChunk - 1) / kPtsPerChunk;
   const dim3 grid(n_blocks, chunks), blk(256);
   const int KL = (a.K + kWave - 1) / kWave;
-  // 4, 8 or 16 sample slots per lane; beyond 16 x 64 samples, chunks of 8 x 64
-  const int ns = KL <= 4 ? 0 : KL <= 8 ? 1 : KL <= kMaxPerLane ? 2 : 3;
+  const int npa = std::min(kPtsPerChunk, a.n_pts);
+  // 4, 8 or 16 sample slots per lane; beyond 16 x 64 samples, or beyond 8 x 64
+  // with few points (whose records leave LDS room for a third wave per SIMD),
+  // chunks of 8 x 64
+  const int ns = KL <= 4 ? 0 : KL <= 8 ? 1 : (KL <= kMaxPerLane && npa > kFewPoints) ? 2 : 3;
+  const size_t lds = shear_dyn_lds(npa, ns == 3);
   const int key = (a.want_grad ? 4 : 0) | (a.size_term ? 2 : 0) | (a.e_kind == 0 ? 0 : 1);
   switch (key * 4 + ns) {
 #define BSI_SHEAR_CASE(G, S, E)                                                                     \
     case ((G) * 4 + (S) * 2 + (E)) * 4 + 0:                                                         \
-      hipLaunchKernelGGL((shear_kernel<G, S, E, 4>), grid, blk, 0, s, a); break;                    \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 4>), grid, blk, lds, s, a); break;                  \
     case ((G) * 4 + (S) * 2 + (E)) * 4 + 1:                                                         \
-      hipLaunchKernelGGL((shear_kernel<G, S, E, 8>), grid, blk, 0, s, a); break;                    \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 8>), grid, blk, lds, s, a); break;                  \
     case ((G) * 4 + (S) * 2 + (E)) * 4 + 2:                                                         \
-      hipLaunchKernelGGL((shear_kernel<G, S, E, 16>), grid, blk, 0, s, a); break;                   \
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 16>), grid, blk, lds, s, a); break;                 \
     case ((G) * 4 + (S) * 2 + (E)) * 4 + 3:                                                         \
-      hipLaunchKernelGGL((shear_kernel<G, S, E, 8, true>), grid, blk, 0, s, a); break;
+      hipLaunchKernelGGL((shear_kernel<G, S, E, 8, true>), grid, blk, lds, s, a); break;
     BSI_SHEAR_CASE(false, false, 0) BSI_SHEAR_CASE(false, false, 1)
     BSI_SHEAR_CASE(false, true, 0) BSI_SHEAR_CASE(false, true, 1)
     BSI_SHEAR_CASE(true, false, 0) BSI_SHEAR_CASE(true, false, 1)
