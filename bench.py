@@ -112,13 +112,16 @@ def valu_issue_frac(launch_s, profile="hmc_kernel_uniform53.txt", kernel="hmc"):
 
 
 # ---------------------------------------------------------------- CPU baseline
-def _oracle_worker(args):
+def _oracle_chain(args):
+    """One single-threaded float64 oracle chain on one galaxy of a workload:
+    (stamp side, seconds, gradient evaluations)."""
     from threadpoolctl import threadpool_limits
     threadpool_limits(1)            # one BLAS thread per worker process
-    idx, n_iter, L = args
+    name, idx, n_warmup, n_samples, size = args
     from oracle import hmc, render, shear
-    cfg = gen.CONFIGS["uniform"]
-    t = gen.draw_truth(cfg, n_gal=1, seed=gen.data_seed(1) + 1000 + idx)
+    cfg = gen.CONFIGS[name]
+    t = gen.draw_truth(cfg, n_gal=1, seed=gen.data_seed(cfg.index) + 1000 + idx,
+                       size_override=None if size is None else np.array([size]))
     ep = shear.shear_forward(t.e1 + 1j * t.e2, complex(*cfg.g_true))
     prm = np.array([t.flux[0], t.hlr[0], ep.real[0], ep.imag[0], t.dx[0], t.dy[0]])
     rng = np.random.default_rng(idx)
@@ -128,8 +131,13 @@ def _oracle_worker(args):
                      ref_xy=(float(t.dx[0]), float(t.dy[0])))
     th0 = hmc.init_chain(d, 1.0, math.log10(prm[1]), (prm[2], prm[3]), 7, idx)
     t0 = time.perf_counter()
-    hmc.run_chain(hmc.galaxy_potential(gal), th0, 7, idx, L, n_iter, 0, 0.01, adapt=True, jitter=0.2)
-    return time.perf_counter() - t0, n_iter * L
+    if cfg.adapt:
+        hmc.run_chain(hmc.galaxy_potential(gal), th0, 7, idx, cfg.leapfrog, n_warmup, n_samples, 0.01,
+                      adapt=True, jitter=0.2)
+    else:
+        hmc.run_chain(hmc.galaxy_potential(gal), th0, 7, idx, cfg.leapfrog, n_warmup, n_samples,
+                      cfg.step_size, adapt=False)
+    return N, time.perf_counter() - t0, (n_warmup + n_samples) * cfg.leapfrog
 
 
 CPU_ITERS = 600     # per worker: about 15 s of oracle work
@@ -137,20 +145,72 @@ CPU_ITERS = 600     # per worker: about 15 s of oracle work
 # host-CPU share that comes with one GPU on the measurement machines (16
 # cores); the affinity mask there can list the whole host.
 CPU_WORKER_CAP = 16
+UNEVEN_ORACLE_GAL = 16      # oracle chains per size class of the uneven mix
+UNEVEN_ORACLE_ITERS = 20    # warmup iterations each (bounded sample)
 
 
-def cpu_baseline_eval_rate(n_iter=CPU_ITERS, L=20):
-    """Oracle gradient evaluations per second on the host: one single-threaded
-    worker per usable core (capped at CPU_WORKER_CAP)."""
+def oracle_workers() -> int:
+    return min(len(os.sched_getaffinity(0)), CPU_WORKER_CAP)
+
+
+def oracle_pool(tasks):
+    """Oracle chains [(workload, index, warmup, draws, side or None)] on one
+    single-threaded worker process per usable core (CPU_WORKER_CAP at most).
+    Forks, so it runs before the process touches the GPU.  Returns (results,
+    cores, wall seconds)."""
     import multiprocessing as mp
-    cores = min(len(os.sched_getaffinity(0)), CPU_WORKER_CAP)
-    ctx = mp.get_context("fork")
+    cores = oracle_workers()
     t0 = time.perf_counter()
-    with ctx.Pool(cores) as pool:
-        res = pool.map(_oracle_worker, [(i, n_iter, L) for i in range(cores)])
-    wall = time.perf_counter() - t0
-    evals = sum(r[1] for r in res)
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_chain, tasks, chunksize=1)
+    return res, cores, time.perf_counter() - t0
+
+
+def cpu_baseline_eval_rate(n_iter=CPU_ITERS):
+    """Oracle gradient evaluations per second on the host for the uniform
+    workload: one 53-pixel warmup chain of n_iter iterations per worker."""
+    res, cores, wall = oracle_pool([("uniform", i, n_iter, 0, None) for i in range(oracle_workers())])
+    evals = sum(r[2] for r in res)
     return evals / wall, cores, evals, wall
+
+
+def cpu_oracle_per_size(name="uneven", n_gal=UNEVEN_ORACLE_GAL, n_iter=UNEVEN_ORACLE_ITERS):
+    """Oracle seconds per gradient evaluation on one core for each stamp size
+    of the mixed-size workloads: n_gal galaxies of each size from the
+    workload's distributions, n_iter warmup iterations each."""
+    tasks = [(name, 100 * N + i, n_iter, 0, N) for N in gen.SIZE_CLASSES for i in range(n_gal)]
+    res, cores, wall = oracle_pool(tasks)
+    sec = {N: 0.0 for N in gen.SIZE_CLASSES}
+    ev = {N: 0 for N in gen.SIZE_CLASSES}
+    for N, s_, e_ in res:
+        sec[N] += s_
+        ev[N] += e_
+    return {"s_per_eval": {N: sec[N] / ev[N] for N in gen.SIZE_CLASSES}, "evals": sum(ev.values()),
+            "cores": cores, "wall": wall,
+            "sample": f"{n_gal} galaxies per stamp size (25/41/53/73/101 px), one {n_iter}-iteration "
+                      f"warmup chain of {gen.CONFIGS[name].leapfrog} leapfrog steps each"}
+
+
+def cpu_oracle_tiny():
+    """The plain tiny workload in full on the oracle: every galaxy's whole
+    chain (burn-in and draws), one galaxy per worker."""
+    cfg = gen.CONFIGS["tiny"]
+    res, cores, wall = oracle_pool([("tiny", i, cfg.warmup, cfg.samples, None) for i in range(cfg.n_gal)])
+    evals = sum(r[2] for r in res)
+    return {"s_per_eval": sum(r[1] for r in res) / evals, "evals": evals, "cores": cores, "wall": wall}
+
+
+def mix_cpu_baseline(orc, weights, evals_per_gal, note):
+    """cpu_baseline of a mixed-size workload from the oracle's per-size
+    seconds per evaluation: cores / (the mix's mean oracle seconds per
+    galaxy), with evals_per_gal[N] gradient evaluations per galaxy of side N."""
+    tot = sum(weights.values())
+    mean_s = sum(w * evals_per_gal[N] * orc["s_per_eval"][N] for N, w in weights.items()) / tot
+    return {"value": round(orc["cores"] / mean_s, 6), "unit": "galaxies/s", "cores": orc["cores"],
+            "kind": "oracle",
+            "ms_per_eval_by_size": {N: round(v * 1e3, 4) for N, v in orc["s_per_eval"].items()},
+            "s_per_galaxy_by_size": {N: round(evals_per_gal[N] * orc["s_per_eval"][N], 1) for N in weights},
+            "sample": f"{orc['sample']} ({orc['evals']:,} evaluations in {orc['wall']:.1f} s); {note}"}
 
 
 # ---------------------------------------------------------------- GPU workload
@@ -209,18 +269,32 @@ def timed(torch, fn, stream):
     return out, s.elapsed_time(e) * 1e-3
 
 
-def shear_leg(api, torch, stream, smp, G, K, seed):
+def shear_leg(api, torch, stream, smp, G, K, seed, cpu=False):
     """Shear-level HMC over (g1, g2, mu_ln_s, sigma_ln_s, sigma_e) on the
     interim samples of the uniform step (every 4th draw of the 4 chains: K =
     1000 per galaxy, 10^7 in all): 4 chains, 10 leapfrog steps, 500 warmup +
     3000 draws, and the HBM roofline of one evaluation pass."""
     th = smp[:, :, 3::4, :].reshape(G, K, 6)
     e1p, e2p, l10s = th[..., 2].contiguous(), th[..., 3].contiguous(), th[..., 1].contiguous()
-    return shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed)
+    return shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed, cpu)
 
 
-def shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed):
-    """The shear-level HMC leg on interim samples (e1', e2', log10 s) [G, K]."""
+def shear_oracle_point(e1p, e2p, l10s, x):
+    """The oracle's log posterior and gradient at one point x = (g1, g2,
+    mu_ln_s, sigma_ln_s, sigma_e) over all samples, single process: (seconds,
+    log posterior)."""
+    from oracle import shear as oshear
+    h = [v.cpu().numpy() for v in (e1p, e2p, l10s)]
+    tpo = oshear.TruePrior(e_kind=1, e_max=0.7, size_term=True)
+    t0 = time.perf_counter()
+    lp, _ = oshear.log_posterior_grad((h[0], h[1], h[2], h[2]), complex(x[0], x[1]), tuple(x[2:]), tpo,
+                                      oshear.Interim())
+    return time.perf_counter() - t0, lp
+
+
+def shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed, cpu=False):
+    """The shear-level HMC leg on interim samples (e1', e2', log10 s) [G, K];
+    cpu: also time the oracle at one point over all samples."""
     dev = torch.device("cuda:0")
     tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True)
     dcfg = gen.CONFIGS["diff"].extra
@@ -243,21 +317,29 @@ def shear_hmc_run(api, torch, stream, e1p, e2p, l10s, G, K, seed):
     t_pass /= reps
     bytes_pass = G * K * 12.0                  # e1', e2', log10 s as float32
     gbs = bytes_pass / t_pass / 1e9
-    return {"n_gal": G, "K": K, "chains": Cs, "leapfrog": cfg.n_leapfrog, "warmup": cfg.n_warmup,
-            "samples": cfg.n_samples, "t_s": round(t_tot, 4), "n_eval": n_eval,
-            "us_per_eval": round(t_tot / n_eval * 1e6, 2),
-            "g_mean": [round(float(ssn[..., 0].mean()), 5), round(float(ssn[..., 1].mean()), 5)],
-            "g_sd": [round(float(ssn[..., 0].std()), 5), round(float(ssn[..., 1].std()), 5)],
-            "g_true": list(gen.CONFIGS["uniform"].g_true),
-            "ess_g": [round(float(e[0, 0]), 1), round(float(e[0, 1]), 1)],
-            "rhat_max": round(float(rh.max()), 4),
-            "accept_rate": round(float(sst[:, 0].mean()), 4),
-            "eval_pass_us": round(t_pass * 1e6, 2),
-            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
-                         "frac": round(gbs / 8000.0, 4),
-                         "traffic": recorded_traffic("shear_kernel_diff_1e7.txt", "shear"),
-                         "kernel": "shear_kernel + shear_reduce_kernel (4 points, with gradient)",
-                         "alg_bytes_per_pass": bytes_pass}}
+    out = {"n_gal": G, "K": K, "chains": Cs, "leapfrog": cfg.n_leapfrog, "warmup": cfg.n_warmup,
+           "samples": cfg.n_samples, "t_s": round(t_tot, 4), "n_eval": n_eval,
+           "us_per_eval": round(t_tot / n_eval * 1e6, 2),
+           "g_mean": [round(float(ssn[..., 0].mean()), 5), round(float(ssn[..., 1].mean()), 5)],
+           "g_sd": [round(float(ssn[..., 0].std()), 5), round(float(ssn[..., 1].std()), 5)],
+           "g_true": list(gen.CONFIGS["uniform"].g_true),
+           "ess_g": [round(float(e[0, 0]), 1), round(float(e[0, 1]), 1)],
+           "rhat_max": round(float(rh.max()), 4),
+           "accept_rate": round(float(sst[:, 0].mean()), 4),
+           "eval_pass_us": round(t_pass * 1e6, 2),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s",
+                        "frac": round(gbs / 8000.0, 4),
+                        "traffic": recorded_traffic("shear_kernel_diff_1e7.txt", "shear"),
+                        "kernel": "shear_kernel + shear_reduce_kernel (4 points, with gradient)",
+                        "alg_bytes_per_pass": bytes_pass}}
+    if cpu:
+        t_pt, _ = shear_oracle_point(e1p, e2p, l10s, ssn[0, -1, :])
+        out["cpu_baseline"] = {
+            "value": round(t_pt * Cs * n_eval, 1), "unit": "s", "cores": 1, "kind": "oracle",
+            "s_per_point": round(t_pt, 3),
+            "sample": f"one point (g, alpha) with gradient over all {G * K:,} samples on one core "
+                      f"in {t_pt:.2f} s; the run = {n_eval:,} passes x {Cs} points"}
+    return out
 
 
 def render_flops(N):
@@ -335,7 +417,7 @@ def make_request_pool(api, torch, per_size, seed_offset=0):
 
 def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, iters_per_tick=15,
                 budget=4 << 30, extra_rates=(), pace=True, split=4, ess_target=300.0, ess_every=60,
-                log=None):
+                log=None, oracle=None):
     """Poisson request stream at `rate` for `window_s` seconds of arrivals
     (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
     warmup iterations of 20 leapfrog steps, then draws until the request's
@@ -388,6 +470,15 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
            "ess_mean_median": round(float(np.median(em)), 1),
            "frac_ess_ge_300": round(float(np.mean(em >= 300.0)), 4),
            "p50_ms_by_size": by_size(r, sizes)}
+    if oracle:
+        # one request per size on one oracle core: its warmup and the median
+        # number of draws this run needed
+        epr = cfg.leapfrog * (cfg.warmup + out["draws_median"])
+        cb = mix_cpu_baseline(oracle, dict(zip(SERVING_SIZES, w)), {N: epr for N in SERVING_SIZES},
+                              "one request per size = warmup + the run's median draws; galaxies/s "
+                              "= cores / the size-weighted mean request time on one core")
+        cb["request_s_by_size"] = cb.pop("s_per_galaxy_by_size")
+        out["cpu_baseline"] = cb
     if pace:
         rp, sp = run(arr, f"{rate:.0f}/s paced", False, True)
         out["paced_by_size"] = {"galaxies_per_s": round(rp.n_done / rp.wall, 1), **lat_stats(rp),
@@ -417,7 +508,65 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
     return out
 
 
-def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
+def tiny_leg(api, torch, stream, log=None, oracle=None):
+    """The plain tiny workload: 16 galaxies of 32 x 32, 1 chain, 10 leapfrog
+    steps at the fixed step 0.005, 100 burn-in + 500 draws.  Batched (one
+    launch per iteration, graph-replayed) and plain (one galaxy and one
+    leapfrog step per launch, run in full), galaxies/s at 300 ESS for both,
+    then the 41 x 41 shear grid on [-0.25, 0.25]^2 over the draws."""
+    cfg = gen.CONFIGS["tiny"]
+    say = log or (lambda m: None)
+    G, C, L, W, S = cfg.n_gal, cfg.chains, cfg.leapfrog, cfg.warmup, cfg.samples
+    t, b, data, ref, init = make_inputs(api, torch, G, cfg)
+    hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=False,
+                         step_size=cfg.step_size, use_graph=True, seed=gen.chain_seed(cfg.index))
+    wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
+    pcfg = api.HmcConfig(**{**hcfg.__dict__, "form": api.N.FORM_PLAIN, "use_graph": False})
+    api.hmc_sample(b, data, ref, init, hcfg)                               # warm
+    (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
+    _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
+    (psmp, _, _), t_plain = timed(torch, lambda: api.hmc_sample(b, data, ref, init, pcfg), stream)
+    say(f"[tiny] batched {t_hmc:.3f} s, plain {t_plain:.3f} s")
+    e, _ = api.ess(smp)
+    n_eff = float(e.mean(dim=1).mean())
+    t_s = t_hmc - t_w
+    tpg = t_w / G + t_s / (G * n_eff) * TARGET_ESS
+    plain_tpg = t_plain / (G * (W + S)) * (W + S * TARGET_ESS / n_eff)
+    n1 = cfg.extra["grid_n"]
+    gs = np.linspace(cfg.extra["grid_lo"], cfg.extra["grid_hi"], n1)
+    pts = torch.tensor([[a, bb, math.log(0.6), 0.3, 0.2] for bb in gs for a in gs], dtype=torch.float64,
+                       device=data.device)
+    th = smp.reshape(G, C * S, 6)
+    tp = api.TruePriorCfg(e_kind=1, e_max=0.7, size_term=True)
+    grid = lambda: api.shear_posterior(th[..., 2].contiguous(), th[..., 3].contiguous(),
+                                       th[..., 1].contiguous(), None, pts, tp)
+    grid()
+    lp, t_grid = timed(torch, grid, stream)
+    lpn = lp.cpu().numpy().reshape(n1, n1)
+    wgt = np.exp(lpn - lpn.max())
+    G1, G2 = np.meshgrid(gs, gs)
+    out = {"n_gal": G, "stamp": cfg.n_pix, "chains": C, "leapfrog": L, "step_size": cfg.step_size,
+           "burn_in": W, "samples": S, "t_hmc_s": round(t_hmc, 4), "t_burn_in_s": round(t_w, 4),
+           "t_plain_s": round(t_plain, 4), "plain_launches": G * (W + S) * L,
+           "plain_equals_batched": bool(torch.equal(smp, psmp)),
+           "n_eff_mean": round(n_eff, 1), "galaxies_per_s": round(1.0 / tpg, 2),
+           "plain_galaxies_per_s": round(1.0 / plain_tpg, 2),
+           "accept_rate": round(float(st[..., 0].mean()), 4),
+           "grid": f"{n1}x{n1}", "t_grid_s": round(t_grid, 5),
+           "g_mean": [round(float((wgt * G1).sum() / wgt.sum()), 5),
+                      round(float((wgt * G2).sum() / wgt.sum()), 5)]}
+    if oracle:
+        epg = C * L * (W + S * TARGET_ESS / n_eff)
+        out["cpu_baseline"] = {
+            "value": round(oracle["cores"] / (epg * oracle["s_per_eval"]), 6), "unit": "galaxies/s",
+            "cores": oracle["cores"], "kind": "oracle",
+            "sample": f"the whole workload: {G} chains of {W} + {S} iterations, one per galaxy "
+                      f"({oracle['evals']:,} evaluations, {oracle['wall']:.1f} s wall on "
+                      f"{oracle['cores']} cores); galaxies/s with the GPU run's n_eff"}
+    return out
+
+
+def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True, oracle=None):
     """Batched uneven workload: n_gal galaxies, stamp side from the size rule
     (25-101), PSF FWHM ~ U(0.6, 0.9), SNR 10-200, 4 chains, 20 leapfrog
     steps, 300 warmup + 1000 draws; the size classes launch concurrently.
@@ -452,16 +601,23 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True):
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
     del smp, st, e, rh, data
     per_size = uneven_per_size(api, torch, stream, cfg, counts, hcfg, log=say) if per_size_runs else None
-    return {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
-            "t_hmc_s": round(t_hmc, 4),
-            "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
-            "n_eff_mean": round(n_eff, 1),
-            "galaxies_per_s": round(1.0 / tpg, 1),
-            "achieved_tflops": round(flop / t_hmc / 1e12, 3),
-            "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
-            "accept_rate": round(float(acc), 4),
-            "status_nonzero": n_flag,
-            "per_size": per_size}
+    out = {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
+           "t_hmc_s": round(t_hmc, 4),
+           "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
+           "n_eff_mean": round(n_eff, 1),
+           "galaxies_per_s": round(1.0 / tpg, 1),
+           "achieved_tflops": round(flop / t_hmc / 1e12, 3),
+           "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
+           "accept_rate": round(float(acc), 4),
+           "status_nonzero": n_flag,
+           "per_size": per_size}
+    if oracle:
+        epg = C * L * (W + S * TARGET_ESS / n_eff)
+        out["cpu_baseline"] = mix_cpu_baseline(
+            oracle, counts, {N: epg for N in counts},
+            "galaxies/s = cores / the mix's mean oracle seconds per galaxy at 300 ESS with the GPU "
+            "run's n_eff")
+    return out
 
 
 def uneven_per_size(api, torch, stream, cfg, counts, hcfg, n1=20, n2=60, log=None):
@@ -702,7 +858,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory 4 times (calibrates HBM counters)")
     ap.add_argument("--workload", choices=["uniform", "uneven", "serving", "shear-pass", "shear-hmc",
-                                           "spergel", "bias", "exposures", "nuts"],
+                                           "spergel", "bias", "exposures", "nuts", "tiny"],
                     default="uniform",
                     help="uniform: the headline line (with shear-level HMC and serving legs); "
                          "uneven / serving: the mixed-size batch or the extended serving study")
@@ -748,6 +904,19 @@ def main():
         torch.cuda.init()
         print(json.dumps({"transform": transform_leg(api)}), flush=True)
         return
+    # oracle timings fork worker processes, so they run before anything
+    # touches the GPU
+    orc = {}
+    if not args.no_cpu_baseline:
+        legs_on = args.workload == "uniform" and not args.no_legs
+        if args.workload in ("uneven", "serving") or legs_on:
+            orc["sizes"] = cpu_oracle_per_size()
+            log(f"[bench] oracle per size: {orc['sizes']['evals']} evaluations in "
+                f"{orc['sizes']['wall']:.1f} s")
+        if args.workload == "tiny" or legs_on:
+            orc["tiny"] = cpu_oracle_tiny()
+            log(f"[bench] oracle tiny workload: {orc['tiny']['evals']} evaluations in "
+                f"{orc['tiny']['wall']:.1f} s")
     if args.workload != "uniform":
         import torch
         from paper_2604_22048_amd import api
@@ -757,7 +926,8 @@ def main():
             G, K = args.n_gal or 10_000, 1000
             S = [torch.tensor(a, device="cuda:0") for a in gen.draw_interim_samples(G, K, gen.data_seed(3))]
             shear_hmc_run(api, torch, stream, *S, G, K, gen.chain_seed(3))          # warm
-            res = shear_hmc_run(api, torch, stream, *S, G, K, gen.chain_seed(3))
+            res = shear_hmc_run(api, torch, stream, *S, G, K, gen.chain_seed(3),
+                                cpu=not args.no_cpu_baseline)
             out = {"metric": "shear-level HMC (500 warmup + 3000 draws, L = 10, 4 chains)",
                    "value": res["t_s"], "unit": "s", "n_gpus": 1, "higher_is_better": False,
                    "dtype": "f32+f64", "data": "synthetic",
@@ -812,9 +982,18 @@ def main():
                    "config": {"workload": f"model-bias fit: 53-pixel exponential galaxies, Spergel "
                                           f"nu = {args.spergel_nu}, 4 chains, 20 leapfrog steps, "
                                           "300 warmup + 1000 draws"}, **res}
+        elif args.workload == "tiny":
+            res = tiny_leg(api, torch, stream, log, oracle=orc.get("tiny"))
+            out = {"metric": "galaxies/sec at 300 ESS (plain tiny workload), batched vs plain",
+                   "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
+                   "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                   "config": {"workload": "plain tiny: 16 galaxies, 32x32 stamps, PSF FWHM 0.7in, "
+                                          "SNR 15-100, 1 chain, 10 leapfrog steps at step 0.005, "
+                                          "100 burn-in + 500 draws, shear grid 41x41 on "
+                                          "[-0.25, 0.25]^2"}, **res}
         elif args.workload == "uneven":
             G = args.n_gal or gen.CONFIGS["uneven"].n_gal
-            res = uneven_leg(api, torch, stream, G, log)
+            res = uneven_leg(api, torch, stream, G, log, oracle=orc.get("sizes"))
             out = {"metric": "galaxies/sec at 300 ESS (uneven stamps 25-101 px)",
                    "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
                    "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -824,10 +1003,10 @@ def main():
         else:
             if args.serve_requests:
                 res = serving_leg(api, torch, 2000.0, args.serve_requests / 2000.0, 60000, 5, pace=False,
-                                  split=0, log=log)
+                                  split=0, log=log, oracle=orc.get("sizes"))
             else:
                 res = serving_leg(api, torch, 2000.0, args.serve_window, 60000, 5,
-                                  extra_rates=(0.5, 0.9), log=log)
+                                  extra_rates=(0.5, 0.9), log=log, oracle=orc.get("sizes"))
             out = {"metric": "p50/p99 fit latency and galaxies/s, Poisson requests",
                    "value": res["galaxies_per_s"], "unit": "galaxies/s", "n_gpus": 1,
                    "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -932,16 +1111,22 @@ def main():
     peak = FP32_PEAK_TFLOPS
     legs = {}
     if not args.no_legs:
-        legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3))
+        legs["shear_hmc"] = shear_leg(api, torch, stream, r["smp"], G, K, gen.chain_seed(3),
+                                      cpu=cpu is not None)
         log(f"[bench] shear-level HMC: {legs['shear_hmc']['t_s']} s")
         del results, r["smp"]
-        legs["uneven"] = uneven_leg(api, torch, stream, gen.CONFIGS["uneven"].n_gal, log)
+        legs["uneven"] = uneven_leg(api, torch, stream, gen.CONFIGS["uneven"].n_gal, log,
+                                    oracle=orc.get("sizes"))
         log(f"[bench] uneven: {legs['uneven']['galaxies_per_s']} galaxies/s, per size "
             f"{ {N: v['frac_fp32_peak'] for N, v in legs['uneven']['per_size'].items()} }")
         legs["transform"] = transform_leg(api)
         log(f"[bench] render transforms: {legs['transform']}")
+        legs["tiny"] = tiny_leg(api, torch, stream, log, oracle=orc.get("tiny"))
+        log(f"[bench] tiny: {legs['tiny']['galaxies_per_s']} galaxies/s batched, "
+            f"{legs['tiny']['plain_galaxies_per_s']} plain")
         if not args.no_serving:
-            legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log)
+            legs["serving"] = serving_leg(api, torch, 2000.0, args.serve_window, 20000, 5, log=log,
+                                          oracle=orc.get("sizes"))
     out = {
         "metric": "galaxies/sec at 300 ESS (53x53 stamps), batched vs plain; p50/p99 fit latency",
         "value": round(value, 3),
