@@ -73,6 +73,16 @@ __host__ __device__ constexpr SlotPlan make_slot_plan_p(int N, int P) {
 
 __host__ __device__ constexpr bool plan_valid(int N, int P) { return (64 * P) / pair_cols(N) >= 1; }
 
+// Whether pair-iteration j of super-row k holds a bin for any of the LS
+// lanes of a chain (lane l takes the super-row's pair-slots l, l + LS, ...):
+// the last super-row can cover fewer rows, and a super-row's last pair-slots
+// are padding.  A dead iteration would add exact zeros, so kernels that know
+// N at compile time skip it.
+__host__ __device__ constexpr bool pair_iter_live(int N, const SlotPlan& sp, int LS, int k, int j) {
+  const int rows = pair_cols(N) - k * sp.R;
+  return j * LS < (rows < sp.R ? rows : sp.R) * pair_cols(N);
+}
+
 // Default plan: the supported P with the fewest slots (ties: smaller P).
 __host__ __device__ constexpr SlotPlan make_slot_plan(int N) {
   SlotPlan best{0, 0, 0, 1 << 30, 0, 0, 0};
@@ -445,8 +455,9 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
             if constexpr (CORR) wn = wq[b * LS];
           }
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
-          pair_step<PROF, RESID, CORR>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy,
-                                       wky[i], sdc[i], sdy, CHI2, w);
+          if (pair_iter_live(NFIX, spc, LS, k, i))
+            pair_step<PROF, RESID, CORR>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy,
+                                         wky[i], sdc[i], sdy, CHI2, w);
         }
         if (CHI2) chi2 += (double)c2;
       }
@@ -649,8 +660,9 @@ __device__ KSums kspace_sums_blocked(const float4* cols, const float2* __restric
           yn = yq[b % CB][(b / CB) * spc.R];
         }
         __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
-        pair_step<PROF, false>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
-                               sdc[i], sdy, CHI2);
+        if (pair_iter_live(NFIX, spc, LS, k, cb + i))
+          pair_step<PROF, false>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
+                                 sdc[i], sdy, CHI2);
       }
       if (CHI2) chi2 += (double)c2;
     }
