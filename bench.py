@@ -50,23 +50,25 @@ def flops_per_eval(N: int, L: int = 20, chi2_every_step: bool = False, weighted:
     form, counted from the trajectory kernel's pair loop as it executes (an FMA
     counts 2; a reciprocal square root, logarithm or exponential 1).
 
-    One pair of bins (+kx, ky), (-kx, ky) costs 66 operations for the gradient:
+    One pair of bins (+kx, ky), (-kx, ky) costs 62 operations for the gradient:
     the two profile arguments 6, the profile powers G and G/(1 + r0^2 q) 8 (two
     rsqrt and three products each; the Spergel form's log2/exp2 pair costs the
     same), the separable factors X Y and conj(X) Y 10, the residuals 8,
-    conj(R) X Y 12, and the flux, shape and centroid accumulations 22.  Sum
+    conj(R) X Y 12, and the shape and centroid accumulations 18 (the flux sum
+    is not accumulated: it follows from the shape sums after the loop).  Sum
     |R|^2 adds 8 per pair; fixed-length HMC forms it on the last leapfrog step
     of a trajectory only (1 in L evaluations), NUTS on every step.  Stationary
     noise weights scale the two bins' G factors: 4 more per pair.  Per bin
-    that is 33 (+4 for Sum |R|^2, +2 for the weights), counted over the
+    that is 31 (+4 for Sum |R|^2, +2 for the weights), counted over the
     distinct half-plane bins (the lane layout's duplicated column-0 and
     padding slots are not counted).  Per evaluation also: the separable
     PSF-sinc-phase tables (6 per x frequency, 8 per row), the per-column
-    constants and post-loop products (9 per column), and 150 for the shape
-    constants, reductions, gradient assembly, prior and leapfrog update."""
+    constants and post-loop sums and products (10 per column), and 152 for
+    the shape constants, the flux sum, reductions, gradient assembly, prior
+    and leapfrog update."""
     h = N // 2
-    per_bin = 33.0 + (4.0 if chi2_every_step else 4.0 / L) + (2.0 if weighted else 0.0)
-    return per_bin * half_plane_bins(N) + 6.0 * (2 * h + 1) + 8.0 * (h + 1) + 9.0 * (h + 1) + 150.0
+    per_bin = 31.0 + (4.0 if chi2_every_step else 4.0 / L) + (2.0 if weighted else 0.0)
+    return per_bin * half_plane_bins(N) + 6.0 * (2 * h + 1) + 8.0 * (h + 1) + 10.0 * (h + 1) + 152.0
 
 
 KERNEL_SOURCES = {

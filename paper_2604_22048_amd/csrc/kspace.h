@@ -176,6 +176,14 @@ __device__ __forceinline__ Shape make_shape(float rpx, float e1, float e2, float
   return s;
 }
 
+// The flux sum sum G z' from the shape sums: w0 = sum G a^-1 z' and
+// sq = sum G a^-1 z' q, with a = 1 + r0^2 q for the exponential and Spergel
+// profiles and G a^-1 = G for the Gaussian.
+template <int PROF>
+__device__ __forceinline__ float flux_sum(float w0, float sq, const Shape& sh) {
+  return PROF == kProfGauss ? w0 : fmaf(sh.r2, sq, w0);
+}
+
 // Spergel factors from a = 1 + r0^2 q >= 1: G / a = a^gw = 2^(gw log2 a)
 // and G = a (G / a).
 __device__ __forceinline__ void spergel_factor(float gw, float a, float& G, float& Gw) {
@@ -308,7 +316,10 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
 //
 // Per bin, with p = X Y the separable factor and T = G p the model spectrum,
 // R = D - T, and z' = conj(R) p: the sums are sum G z' (flux), sum G a^-1 z'
-// times kx^2, ky^2, kx ky (shape) and sum G Im z' times kx, ky (centroid).
+// times 1, kx^2, ky^2, kx ky (shape) and sum G Im z' times kx, ky (centroid).
+// The flux sum is not accumulated: a = 1 + r0^2 q (exponential and Spergel
+// profiles; for the Gaussian G a^-1 = G), so sum G z' = sum G a^-1 z' +
+// r0^2 sum G a^-1 z' q, and q is linear in kx^2, ky^2, kx ky (flux_sum).
 //
 // One pair-slot holds the bins (+kx, ky) and (-kx, ky).  They share ky, the
 // row factor Y, kx^2 and |X|, and X(-kx) = conj X(kx) (the PSF-sinc factor is
@@ -325,7 +336,7 @@ __device__ __forceinline__ void fill_tables(const Geom& g, const SlotPlan& sp,
 // w-weighted form (Appendix C, eq. covar-pixel-likelihood).
 template <int PROF, bool RESID, bool CORR = false>
 __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, float xr, float xi,
-                                          float TA, float Tc, float& c2, float& sF, float& swq,
+                                          float TA, float Tc, float& c2, float& swq,
                                           float& syy, float& wky, float& sdx, float& sdy, bool chi2,
                                           float2 sw = float2{1.f, 1.f}) {
   const float base = fmaf(sh.tb, y.w, TA);
@@ -363,8 +374,6 @@ __device__ __forceinline__ void pair_step(const Shape& sh, float4 D, float4 y, f
   if (chi2) c2 = fmaf(Rpr, Rpr, fmaf(Rpi, Rpi, fmaf(Rmr, Rmr, fmaf(Rmi, Rmi, c2))));
   const float zrp = fmaf(Rpr, ppr, Rpi * ppi), zip = fmaf(Rpr, ppi, -Rpi * ppr);
   const float zrm = fmaf(Rmr, pmr, Rmi * pmi), zim = fmaf(Rmr, pmi, -Rmi * pmr);
-  sF = fmaf(Gp, zrp, sF);
-  sF = fmaf(Gm, zrm, sF);
   const float wqp = Gwp * zrp;
   const float ws = fmaf(Gwm, zrm, wqp), wd = fmaf(-Gwm, zrm, wqp);
   swq += ws;
@@ -415,7 +424,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
     yp[i] = Ym + lc.yo[i];
   }
   double chi2 = 0.0;
-  float sF = 0.f, syy = 0.f, sdy = 0.f;
+  float syy = 0.f, sdy = 0.f;
   float swq[PI], wky[PI], sdc[PI];    // per column: times kx^2, kx, kx after the loop
 #pragma unroll
   for (int i = 0; i < PI; ++i) {
@@ -456,7 +465,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
           }
           __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
           if (pair_iter_live(NFIX, spc, LS, k, i))
-            pair_step<PROF, RESID, CORR>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy,
+            pair_step<PROF, RESID, CORR>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, swq[i], syy,
                                          wky[i], sdc[i], sdy, CHI2, w);
         }
         if (CHI2) chi2 += (double)c2;
@@ -467,7 +476,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         float c2 = 0.f;
 #pragma unroll
         for (int i = 0; i < P; ++i)
-          pair_step<PROF, RESID>(sh, dq[i * 64], yq[i][0], xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i],
+          pair_step<PROF, RESID>(sh, dq[i * 64], yq[i][0], xr[i], xi[i], TA[i], Tc[i], c2, swq[i],
                                  syy, wky[i], sdc[i], sdy, CHI2);
         if (CHI2) chi2 += (double)c2;
         dq += W * P * 64;
@@ -483,16 +492,17 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
 #pragma unroll
       for (int i = 0; i < P; ++i)
         pair_step<PROF, RESID, CORR>(sh, dp[i * 64], yr[lc.yo[i]], xr[i], xi[i], TA[i], Tc[i], c2,
-                                     sF, swq[i], syy, wky[i], sdc[i], sdy, CHI2,
+                                     swq[i], syy, wky[i], sdc[i], sdy, CHI2,
                                      CORR ? wp[i * 64] : float2{1.f, 1.f});
       if (CHI2) chi2 += (double)c2;
       dp += P * 64;
       if constexpr (CORR) wp += P * 64;
     }
   }
-  float sxx = 0.f, sxy = 0.f, sdx = 0.f;
+  float w0 = 0.f, sxx = 0.f, sxy = 0.f, sdx = 0.f;
 #pragma unroll
   for (int i = 0; i < PI; ++i) {
+    w0 += swq[i];
     sxx = fmaf(lc.kx2[i], swq[i], sxx);
     sxy = fmaf(lc.kx[i], wky[i], sxy);
     sdx = fmaf(lc.kx[i], sdc[i], sdx);
@@ -546,8 +556,8 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
         const float w = cf * cu * cv;
         const float zr = w * fmaf(Rr, Tr, Ri * Ti);
         const float zi = w * fmaf(Rr, Ti, -Ri * Tr);
-        sF += zr;
         const float wq = zr * ia;
+        w0 += wq;
         sxx = fmaf(kx2b, wq, sxx);
         syy = fmaf(ky2b, wq, syy);
         sxy = fmaf(kxy, wq, sxy);
@@ -558,7 +568,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
 
   KSums s;
-  float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
+  float v[7] = {w0, sxx, syy, sxy, sdx, sdy, 0.f};
   if constexpr (H == 1) {
     s.chi2 = CHI2 ? wave_total(chi2) : 0.0;
     wave_total7(v, red);
@@ -599,6 +609,7 @@ __device__ KSums kspace_sums(const Geom& g, const SlotPlan& sp, const LaneCols<P
   }
   // q is linear in (kx^2, ky^2, kx ky), so sum q w = ca Sxx + cb Syy + cc Sxy
   s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
+  s.sF = flux_sum<PROF>(s.sF, s.sq, sh);
   return s;
 }
 
@@ -621,7 +632,7 @@ __device__ KSums kspace_sums_blocked(const float4* cols, const float2* __restric
   const int lane = chain_lane<H>();
   const float4* dp = reinterpret_cast<const float4*>(dh) + lane;
   double chi2 = 0.0;
-  float sF = 0.f, syy = 0.f, sdy = 0.f, sxx = 0.f, sxy = 0.f, sdx = 0.f;
+  float w0 = 0.f, syy = 0.f, sdy = 0.f, sxx = 0.f, sxy = 0.f, sdx = 0.f;
 #pragma unroll
   for (int cb = 0; cb < PI; cb += CB) {
     float kx[CB], kx2[CB], xr[CB], xi[CB], TA[CB], Tc[CB];
@@ -661,20 +672,21 @@ __device__ KSums kspace_sums_blocked(const float4* cols, const float2* __restric
         }
         __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of this pair's arithmetic
         if (pair_iter_live(NFIX, spc, LS, k, cb + i))
-          pair_step<PROF, false>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, sF, swq[i], syy, wky[i],
+          pair_step<PROF, false>(sh, D, y, xr[i], xi[i], TA[i], Tc[i], c2, swq[i], syy, wky[i],
                                  sdc[i], sdy, CHI2);
       }
       if (CHI2) chi2 += (double)c2;
     }
 #pragma unroll
     for (int i = 0; i < CB; ++i) {
+      w0 += swq[i];
       sxx = fmaf(kx2[i], swq[i], sxx);
       sxy = fmaf(kx[i], wky[i], sxy);
       sdx = fmaf(kx[i], sdc[i], sdx);
     }
   }
   KSums s;
-  float v[7] = {sF, sxx, syy, sxy, sdx, sdy, 0.f};
+  float v[7] = {w0, sxx, syy, sxy, sdx, sdy, 0.f};
   s.chi2 = CHI2 ? group_total<H>(chi2) : 0.0;
   group_total7<H>(v, red);
   s.sF = v[0];
@@ -684,6 +696,7 @@ __device__ KSums kspace_sums_blocked(const float4* cols, const float2* __restric
   s.sdx = v[4];
   s.sdy = v[5];
   s.sq = sh.ca * s.sxx + sh.cb * s.syy + sh.cc * s.sxy;
+  s.sF = flux_sum<PROF>(s.sF, s.sq, sh);
   return s;
 }
 
