@@ -14,7 +14,9 @@ from workloads import gen                                    # noqa: E402
 from tests import synth                                      # noqa: E402
 
 PS = gen.PIXEL_SCALE
-PLANS = {25: (3, 1), 53: (3, 4, 6, 2), 101: (4, 5)}
+# every plan with a specialised kernel (the ones the autotuner chooses among),
+# plus one plan per size that runs the generic kernel
+PLANS = {25: (3, 1), 32: (1, 2, 4), 41: (1, 4), 53: (3, 4, 6, 2), 73: (3, 6, 8), 101: (4, 5)}
 
 
 def _log(msg):
