@@ -372,9 +372,10 @@ typedef struct {
  * The log-sum-exp over k and the sum over galaxies are carried in float64.
  *   e1p, e2p, log10s, log10f  [device] float[n_gal][K] interim samples
  *              (structure of arrays; log10f may be NULL when flux_term = 0).
- *              Any K >= 1: up to 1024 samples per galaxy are held at once;
- *              larger K is taken in chunks of 512 whose float64 sums are
- *              combined exactly (a rescaling to the larger reference).
+ *              Any K >= 1: up to 1024 samples per galaxy (512 when
+ *              n_pts <= 16) are held at once; larger K is taken in chunks of
+ *              512 whose float64 sums are combined exactly (a rescaling to
+ *              the larger reference).
  *   pts      [host or device, see pts_on_device] double[n_pts][5].
  *   logpost  [device] double[n_pts].
  *   grad     [device] double[n_pts][5] gradient of ln P, or NULL.
@@ -401,7 +402,8 @@ int bsi_shear_posterior(bsi_handle h, int32_t n_gal, int32_t K, const float* e1p
  *   pts      [device] double[n_pts][5] (host points would need staging memory).
  *   other arguments as for bsi_shear_posterior.
  * The pass needs blocks x n_pts x 48 bytes of scratch for its partial sums,
- * blocks = min(ceil(n_gal / 4), max(16, 512 / ceil(n_pts / 64))); every
+ * blocks = min(ceil(n_gal / 4), max(16, R / ceil(n_pts / 64))), R = 768 for
+ * n_pts <= 16 and 512 otherwise; every
  * n_pts <= 21845 fits, larger counts fail with BSI_EINVAL when they exceed
  * it.  All calls on
  * one device share its scratch, and the array keeps the last call's contents
