@@ -143,9 +143,9 @@ def _oracle_chain(args):
 
 
 CPU_ITERS = 600     # per worker: about 15 s of oracle work
-# Worker processes for the oracle baseline: one per usable core, at most the
-# host-CPU share that comes with one GPU on the measurement machines (16
-# cores); the affinity mask there can list the whole host.
+# Worker processes for the oracle baseline: one per usable core, at most 16,
+# the host cores that come with one GPU when a node's cores are divided among
+# its GPUs (the affinity mask of a process can list the whole host).
 CPU_WORKER_CAP = 16
 UNEVEN_ORACLE_GAL = 16      # oracle chains per size class of the uneven mix
 UNEVEN_ORACLE_ITERS = 20    # warmup iterations each (bounded sample)
@@ -1180,7 +1180,7 @@ def main():
                                "cores": cpu["cores"], "kind": "oracle",
                                "cores_visible": cpu["visible"],
                                "cores_note": f"one worker per usable core, capped at {CPU_WORKER_CAP} "
-                                             "(the host-CPU share of one GPU on the measurement box)",
+                                             "(the host cores that come with one GPU of a shared node)",
                                "sample": f"{cpu['evals']} float64 oracle gradient evaluations (53x53, "
                                          f"one {CPU_ITERS}-iteration warmup chain per core) in "
                                          f"{cpu['wall']:.1f} s; galaxies/s = eval rate / evaluations "
