@@ -9,8 +9,8 @@ samples on a 41x41 grid.  Time per galaxy follows Section 4.1:
     T_warmup / G + T_sampling / (G * n_eff) * 300,
 with T_warmup from a warmup-only call and T_sampling = T_hmc - T_warmup.
 
-Prints one JSON line (rank 0).  `--gpus` above 1 is rejected: this build
-runs on one GPU.
+Prints one JSON line (rank 0).  `--gpus` above 1 is rejected: the benchmark
+runs on one GPU (the sharding across GPUs is a design, not code).
 """
 from __future__ import annotations
 
@@ -896,8 +896,8 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 4}), flush=True)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); multi-GPU runs are not "
-              "part of this build", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the library has no "
+              "multi-GPU path", file=sys.stderr)
         sys.exit(2)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     if args.transform_only:
