@@ -571,8 +571,11 @@ def tiny_leg(api, torch, stream, log=None, oracle=None):
 def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True, oracle=None):
     """Batched uneven workload: n_gal galaxies, stamp side from the size rule
     (25-101), PSF FWHM ~ U(0.6, 0.9), SNR 10-200, 4 chains, 20 leapfrog
-    steps, 300 warmup + 1000 draws; the size classes launch concurrently.
-    per_size_runs: also time each size class alone (uneven_per_size)."""
+    steps, 300 warmup + 1000 draws.  Timed in the direct form (each
+    iteration's per-size launches concurrent on forked streams), and in the
+    graph form (the per-size launches in sequence, replayed from a graph) for
+    comparison.  per_size_runs: also time each size class alone
+    (uneven_per_size)."""
     cfg = gen.CONFIGS["uneven"]
     say = log or (lambda m: None)
     plans = api.autotune(list(gen.SIZE_CLASSES), n_chains=cfg.chains)
@@ -583,33 +586,37 @@ def uneven_leg(api, torch, stream, n_gal, log=None, per_size_runs=True, oracle=N
     hcfg = api.HmcConfig(n_chains=C, n_leapfrog=L, n_warmup=W, n_samples=S, adapt=True,
                          metric=api.N.METRIC_FISHER, step_size=0.5, target_accept=0.8, jitter=0.2,
                          use_graph=True, seed=gen.chain_seed(cfg.index))
-    wcfg = api.HmcConfig(**{**hcfg.__dict__, "n_samples": 0})
-    api.hmc_sample(b, data, ref, init, wcfg, want_samples=False)      # warm
-    # the other launch form (direct, sizes concurrent on forked streams), warmup iterations only
-    dcfg = api.HmcConfig(**{**wcfg.__dict__, "use_graph": False})
-    _, t_w_direct = timed(torch, lambda: api.hmc_sample(b, data, ref, init, dcfg, want_samples=False),
-                          stream)
-    say(f"[uneven] warmup-only direct call {t_w_direct:.3f} s")
-    (smp, st, status), t_hmc = timed(torch, lambda: api.hmc_sample(b, data, ref, init, hcfg), stream)
-    say(f"[uneven] sampler call {t_hmc:.3f} s")
+    dcfg = api.HmcConfig(**{**hcfg.__dict__, "use_graph": False})
+    run = lambda cfg_, n_s, want: api.hmc_sample(b, data, ref, init,
+                                                 api.HmcConfig(**{**cfg_.__dict__, "n_samples": n_s}),
+                                                 want_samples=want)
+    run(hcfg, 0, False)                                                # warm
+    run(dcfg, 0, False)
+    (smp, st, status), t_hmc = timed(torch, lambda: run(dcfg, S, True), stream)
+    say(f"[uneven] sampler call {t_hmc:.3f} s (direct)")
     (e, rh), _ = timed(torch, lambda: api.ess(smp), stream)
-    _, t_w = timed(torch, lambda: api.hmc_sample(b, data, ref, init, wcfg, want_samples=False), stream)
+    _, t_w = timed(torch, lambda: run(dcfg, 0, False), stream)
+    _, t_hmc_g = timed(torch, lambda: run(hcfg, S, True), stream)
+    _, t_w_g = timed(torch, lambda: run(hcfg, 0, False), stream)
+    say(f"[uneven] sampler call {t_hmc_g:.3f} s (graph)")
     n_eff = float(e.mean(dim=1).mean())
     acc = st[..., 0].mean()
     n_flag = int((status != 0).sum())
-    t_s = t_hmc - t_w
-    tpg = t_w / n_gal + t_s / (n_gal * n_eff) * TARGET_ESS
+    tpg = t_w / n_gal + (t_hmc - t_w) / (n_gal * n_eff) * TARGET_ESS
+    tpg_g = t_w_g / n_gal + (t_hmc_g - t_w_g) / (n_gal * n_eff) * TARGET_ESS
     counts = {int(N): int(np.sum(t.n_pix == N)) for N in np.unique(t.n_pix)}
     flop = sum(flops_per_eval(N) * k for N, k in counts.items()) * C * L * (W + S)
     del smp, st, e, rh, data
     per_size = uneven_per_size(api, torch, stream, cfg, counts, hcfg, log=say) if per_size_runs else None
     out = {"n_gal": n_gal, "size_counts": counts, "slot_plans": {N: P for N, (P, _) in plans.items()},
-           "t_hmc_s": round(t_hmc, 4),
-           "t_warmup_s": round(t_w, 4), "t_warmup_direct_forked_s": round(t_w_direct, 4),
+           "launch_form": "direct (per-size launches concurrent on forked streams)",
+           "t_hmc_s": round(t_hmc, 4), "t_warmup_s": round(t_w, 4),
            "n_eff_mean": round(n_eff, 1),
            "galaxies_per_s": round(1.0 / tpg, 1),
            "achieved_tflops": round(flop / t_hmc / 1e12, 3),
            "frac_fp32_peak": round(flop / t_hmc / 1e12 / FP32_PEAK_TFLOPS, 4),
+           "graph_form": {"t_hmc_s": round(t_hmc_g, 4), "t_warmup_s": round(t_w_g, 4),
+                          "galaxies_per_s": round(1.0 / tpg_g, 1)},
            "accept_rate": round(float(acc), 4),
            "status_nonzero": n_flag,
            "per_size": per_size}
