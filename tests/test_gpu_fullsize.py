@@ -116,6 +116,76 @@ def test_uniform_full_hmc_sampled_and_invariant(bsi, uniform):
         assert np.array_equal(s1[0].cpu().numpy(), smp[i]), i
 
 
+@pytest.fixture(scope="module")
+def uneven(bsi):
+    """The batched uneven workload at full size: 100,000 galaxies, stamp side
+    from the size rule (25-101 px), PSF FWHM U(0.6, 0.9) arcsec."""
+    import torch
+    _log("full-size uneven inputs (oracle-rendered)")
+    cfg = gen.CONFIGS["uneven"]
+    t, params, data, off = synth.make_population("uneven")
+    init = synth.init_positions(t, params, data, off, cfg.chains, seed=79)
+    b = bsi.Batch(n=t.n_pix, psf_fwhm=torch.tensor(t.psf_fwhm, dtype=torch.float32).cuda(),
+                  sigma=torch.tensor(t.sigma, dtype=torch.float32).cuda(), pixel_scale=PS)
+    return dict(t=t, params=params, data=data, off=off, init=init, b=b,
+                dev=torch.tensor(data).cuda(),
+                ref=torch.tensor(np.stack([t.dx, t.dy], 1), dtype=torch.float32).cuda())
+
+
+def test_uneven_full_hmc_forms_sampled_and_invariant(bsi, uneven):
+    """All 400,000 chains of the mixed-size batch advanced together for three
+    iterations at a fixed step (Fisher metric, jitter 0.2, L = 20): the direct
+    form (each iteration's per-size launches concurrent on forked streams, as
+    the benchmark times it) equals the graph form (the per-size launches in
+    sequence) bitwise; one sampled galaxy of every size class follows the
+    oracle chain by chain, and run alone reproduces its slice bitwise."""
+    import torch
+    u = uneven
+    G = len(u["t"])
+    assert G == 100_000
+    sizes = u["t"].n_pix
+    assert set(np.unique(sizes)) == set(gen.SIZE_CLASSES)
+    C, L, S = 4, 20, 3
+    base = dict(n_chains=C, n_leapfrog=L, n_warmup=0, n_samples=S, adapt=False, metric=1,
+                step_size=0.3, jitter=0.2, seed=2025)
+    init_t = torch.tensor(u["init"], dtype=torch.float32).cuda()
+    _log("full-size uneven: direct form")
+    smp, _, _ = bsi.hmc_sample(u["b"], u["dev"], u["ref"], init_t,
+                               bsi.HmcConfig(use_graph=False, **base))
+    _log("full-size uneven: graph form")
+    smp_g, _, _ = bsi.hmc_sample(u["b"], u["dev"], u["ref"], init_t,
+                                 bsi.HmcConfig(use_graph=True, **base))
+    smp, smp_g = smp.cpu().numpy(), smp_g.cpu().numpy()
+    assert np.all(np.isfinite(smp))
+    assert np.array_equal(smp, smp_g)
+    picks = [int(np.flatnonzero(sizes == N)[k]) for N in gen.SIZE_CLASSES for k in (0, -1)]
+    agree = 0
+    for i in picks[::2]:
+        gal = synth.oracle_galaxy(u["t"], u["data"], u["off"], i)
+        for c in range(C):
+            th0 = u["init"][i, c].astype(np.float32).astype(np.float64)
+            im = hmc.fisher_inv_mass(gal, th0)
+            r = hmc.run_chain(hmc.galaxy_potential(gal), th0, 2025, i * C + c, L, 0, S, 0.3,
+                              adapt=False, inv_mass=im, jitter=0.2)
+            for k in range(S):
+                d = np.max(np.abs(smp[i, c, k] - r["samples"][k]))
+                if d > 1e-4:
+                    moved_g = k == 0 or np.any(smp[i, c, k] != smp[i, c, k - 1])
+                    moved_o = k == 0 or np.any(r["samples"][k] != r["samples"][k - 1])
+                    assert moved_g != moved_o, (i, int(sizes[i]), c, k, d)
+                    break
+                agree += 1
+    assert agree >= len(picks[::2]) * C * S - 2
+    for i in picks[1::2]:
+        N = int(sizes[i])
+        b1 = bsi.Batch(n=np.array([N]), psf_fwhm=u["b"].psf_fwhm[i:i + 1].clone(),
+                       sigma=u["b"].sigma[i:i + 1].clone(), pixel_scale=PS)
+        one = bsi.HmcConfig(uid_base=i * C, use_graph=False, **base)
+        s1, _, _ = bsi.hmc_sample(b1, u["dev"][u["off"][i]:u["off"][i] + N * N].contiguous(),
+                                  u["ref"][i:i + 1].contiguous(), init_t[i:i + 1].contiguous(), one)
+        assert np.array_equal(s1[0].cpu().numpy(), smp[i]), (i, N)
+
+
 def test_shear_full_size_additivity_and_sampled(bsi):
     """10,000 galaxies x 1,000 interim samples at 4 points with gradient: the
     pass over all galaxies equals the sum of the passes over two halves (ln P
