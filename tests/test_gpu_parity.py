@@ -497,7 +497,16 @@ def test_shear_posterior_many_samples(bsi, kind, K):
     _shear_parity_case(bsi, kind, True, 12, K, 60 + K)
 
 
-def _shear_parity_case(bsi, kind, flux, G, K, seed):
+@pytest.mark.parametrize("K", [700, 1000])
+def test_shear_posterior_few_points(bsi, K):
+    """At most 16 points (the shear-level sampler's chains) with more than
+    512 samples per galaxy: the kernel form that takes samples in chunks of
+    512 at three waves per SIMD.  Log-posterior and gradient against the
+    oracle within the float32 bound."""
+    _shear_parity_case(bsi, 1, False, 24, K, 90 + K, edges=False)
+
+
+def _shear_parity_case(bsi, kind, flux, G, K, seed, edges=True):
     import torch
     from tests import f32bound
     _log(f"shear parity kind={kind} flux={flux} G={G} K={K}")
@@ -511,7 +520,7 @@ def _shear_parity_case(bsi, kind, flux, G, K, seed):
                            mu_ln_f=math.log(1000.0), sigma_ln_f=0.5)
     inner = [((0.02, -0.01, math.log(0.6), 0.3, 0.2), True), ((-0.05, 0.04, -0.4, 0.25, 0.26), True),
              ((0.0, 0.0, -0.6, 0.35, 0.18), True), ((1.2, 0.0, -0.5, 0.3, 0.2), False)]
-    cases = inner + _edge_points()
+    cases = inner + (_edge_points() if edges else [])
     pts = np.array([c[0] for c in cases])
     St = [torch.tensor(a).cuda() for a in S]
     lp, gr = bsi.shear_posterior(St[0], St[1], St[2], St[3], pts, tpg, want_grad=True)
