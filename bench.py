@@ -113,6 +113,16 @@ def valu_issue_frac(launch_s, profile="hmc_kernel_uniform53.txt", kernel="hmc"):
     return None if n is None else round(n / N_CU / (launch_s * CLOCK_HZ), 4)
 
 
+def executed_frac(launch_s, profile="hmc_kernel_uniform53.txt", kernel="hmc"):
+    """FP32 flops the hardware counted per launch (SQ_INSTS_VALU_FLOPS_FP32,
+    in units of 64 lane-flops, from the counter summary) over the live launch
+    duration, as a fraction of the FP32 peak, or None.  It exceeds the
+    algorithmic fraction by the work the count leaves out (padding lanes,
+    per-chain work every lane of a chain repeats)."""
+    n = recorded_counter(profile, kernel, "fp32_flops_executed_per_launch")
+    return None if n is None else round(n / launch_s / 1e12 / FP32_PEAK_TFLOPS, 4)
+
+
 # ---------------------------------------------------------------- CPU baseline
 def _oracle_chain(args):
     """One single-threaded float64 oracle chain on one galaxy of a workload:
@@ -1178,6 +1188,7 @@ def main():
                      "alg_flop_per_eval": flops_per_eval(N, L), "evals_per_launch": G * C * L,
                      "alg_flop_per_launch": alg,
                      "valu_issue_frac": valu_issue_frac(t_launch),
+                     "executed_frac": executed_frac(t_launch),
                      "frac_of_nonpacked_issue_ceiling": round(achieved / VALU_ISSUE_TFLOPS, 4)},
         **legs,
     }
