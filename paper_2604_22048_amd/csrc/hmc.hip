@@ -1171,10 +1171,10 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 }
 
 // Minimum resident waves per SIMD requested from the register allocator for
-// the trajectory kernel (occupancy against instruction-level parallelism).
-#ifndef BSI_HMC_WAVES_PER_EU
-#define BSI_HMC_WAVES_PER_EU 2
-#endif
+// the trajectory kernel (occupancy against instruction-level parallelism;
+// in a sweep on an earlier form of the kernel one wave per SIMD ran 1.7x
+// slower than two, and three or four were slower as well).
+constexpr int kHmcWavesPerEu = 2;
 
 // NFIX > 0: a kernel specialised for stamp side NFIX (a.N == NFIX).
 // W > 1: each chain is evaluated by W waves (split evaluation; advance only).
@@ -1188,7 +1188,7 @@ __device__ void advance_chain_nuts2(const HmcArgs& a, const GalCtx& c, const Lan
 // of the paired plans without MX).
 template <int PROF, bool INIT, int P, int MAXT, int NFIX, int W = 1, int H = 1, bool MX = false,
           bool NUTS = false>
-__global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : BSI_HMC_WAVES_PER_EU)) hmc_kernel(HmcArgs a) {
+__global__ void __launch_bounds__(MAXT, (MAXT > 256 ? 1 : kHmcWavesPerEu)) hmc_kernel(HmcArgs a) {
   static_assert(W == 1 || !INIT, "chain start is evaluated by one wave");
   static_assert(!NUTS || (!INIT && W == 1 && (H == 1 || NFIX > 0)), "NUTS: advance kernels, W = 1");
   static_assert(!MX || (W == 1 && (NFIX == 0 || !INIT)), "exposures and noise weights: no split evaluation");
