@@ -549,7 +549,10 @@ int bsi_hmc_sample(bsi_handle h, const bsi_batch* batch, const float* data, cons
     };
     // direct launches: the sizes run concurrently on forked streams
     auto enqueue = [&](hipStream_t st) -> hipError_t {
-      return fork_join(h, st, (int)p.classes.size(), advance_class);
+      return fork_join(h, st, (int)p.classes.size(), advance_class, [&](int i) {
+        const ClassRange& c = p.classes[i];
+        return (double)c.N * c.N * c.gcount;    // the class's share of the work
+      });
     };
     // any capture (the library's own graph or the caller's): one stream, the
     // sizes' launches in sequence.  Capturing the fork/join has ended in a

@@ -34,6 +34,8 @@ struct DevBuf {
 };
 
 constexpr int kAuxStreams = 4;
+// streams of a forked launch: the caller's and up to kAuxStreams auxiliary
+constexpr int kForkStreams = 4;
 
 // An instantiated graph whose replays were enqueued; destroyed once `done`
 // (recorded after the last replay) has completed.
@@ -281,21 +283,39 @@ inline int stage_upload(bsi_handle h, hipStream_t s, bool cap, std::initializer_
   return BSI_OK;
 }
 
-// Enqueue fn(i, stream) for i = 0..n-1 with item 0 on s and the others on
-// the handle's auxiliary streams, forked from and joined back into s by
-// events, so that the launches of different size classes can run
-// concurrently.  Used outside stream capture only: a capture of the fork
-// (with the executable kept alive until its replays had run) still ended in
-// a host segmentation fault inside the call, so every capture records the
-// launches in sequence on one stream instead.
-template <typename F>
-hipError_t fork_join(bsi_handle h, hipStream_t s, int n, F&& fn) {
+// Enqueue fn(i, stream) for i = 0..n-1 on s and the handle's auxiliary
+// streams (at most kForkStreams streams in all), forked from and joined back
+// into s by events, so that the launches of different size classes run
+// concurrently.  cost(i) estimates item i's duration: the items are enqueued
+// in descending cost, each on the stream with the least estimated cost so
+// far, so the longest runs on s and the shortest share a stream.  Used
+// outside stream capture only: a capture of the fork (with the executable
+// kept alive until its replays had run) still ended in a host segmentation
+// fault inside the call, so every capture records the launches in sequence
+// on one stream instead.
+template <typename F, typename Cost>
+hipError_t fork_join(bsi_handle h, hipStream_t s, int n, F&& fn, Cost&& cost) {
   if (n <= 1) return n == 1 ? fn(0, s) : hipSuccess;
-  const int n_aux = std::min(n - 1, kAuxStreams);
+  const int ns = std::min(n, kForkStreams);
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
+  std::vector<double> load(ns, 0.0);
+  std::vector<int> where(n, 0);
+  for (int c : order) {
+    int b = 0;
+    for (int j = 1; j < ns; ++j)
+      if (load[j] < load[b]) b = j;
+    where[c] = b;
+    load[b] += cost(c);
+  }
   hipError_t e = hipEventRecord(h->ev_fork, s);
-  for (int i = 0; e == hipSuccess && i < n_aux; ++i) e = hipStreamWaitEvent(h->aux[i], h->ev_fork, 0);
-  for (int c = 0; e == hipSuccess && c < n; ++c) e = fn(c, c == 0 ? s : h->aux[(c - 1) % kAuxStreams]);
-  for (int i = 0; e == hipSuccess && i < n_aux; ++i) {
+  for (int i = 0; e == hipSuccess && i < ns - 1; ++i) e = hipStreamWaitEvent(h->aux[i], h->ev_fork, 0);
+  for (int c : order) {
+    if (e != hipSuccess) break;
+    e = fn(c, where[c] == 0 ? s : h->aux[where[c] - 1]);
+  }
+  for (int i = 0; e == hipSuccess && i < ns - 1; ++i) {
     e = hipEventRecord(h->ev_join[i], h->aux[i]);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, h->ev_join[i], 0);
   }

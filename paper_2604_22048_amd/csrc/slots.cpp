@@ -525,6 +525,11 @@ int bsi_slots_advance(bsi_slots sv, int32_t n_iter) {
     x = launch_hmc_advance(a, a.n_gal, st);
     if (x == hipSuccess && sv->cfg.pace) x = hipEventRecord(k.ev_end, st);
     return x;
+  }, [&](int j) {
+    // a launch's duration follows one request's chain (the requests of a
+    // size run side by side): its bins per wave, times its iterations
+    const SizeClass& k = sv->cls[active[j]];
+    return (double)k.N * k.N / k.W * iters[active[j]];
   });
   if (e != hipSuccess) return hip_fail(h, e, "advance launch");
   if (sv->ess) {

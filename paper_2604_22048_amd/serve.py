@@ -17,6 +17,9 @@ import torch
 
 from . import api
 
+# finished requests' draws held on the device for the ESS check before a batch is checked
+ESS_BATCH_BYTES = 1 << 30
+
 
 @dataclass
 class RequestPool:
@@ -68,7 +71,11 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     arrivals: nondecreasing arrival times [s] relative to the start of the
     loop; sizes: stamp side of each request.  Each loop turn admits every
     arrived request that fits (in arrival order), enqueues n_iter iterations
-    for all resident requests, and collects the finished ones."""
+    for all resident requests, and collects the finished ones.  ess: also
+    the ESS of each request's returned draws (mean over the six properties),
+    computed off the requests' critical path: the finished requests' draws are
+    kept on the device and checked in batches (after the loop, or once they
+    pass ESS_BATCH_BYTES)."""
     n = arrivals.shape[0]
     ids = np.arange(n, dtype=np.uint64)
     slot = np.zeros(n, dtype=np.int64)
@@ -80,6 +87,18 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     fin = np.full(n, np.nan)
     ess_out = np.full(n, np.nan) if ess else None
     draws = np.zeros(n, dtype=np.int32)
+    kept = []              # (ids, draws, samples) of finished requests, for the ESS check
+    kept_bytes = 0
+
+    def check_kept():
+        for h, ndh, smp in kept:
+            for v in np.unique(ndh):
+                m = np.nonzero(ndh == v)[0]
+                sel = smp[torch.from_numpy(m).to(smp.device), :, :int(v)].contiguous()
+                e, _ = api.ess(sel)
+                ess_out[h[m]] = e.mean(dim=1).cpu().numpy()
+        kept.clear()
+
     queue_head = 0
     done = 0
     ticks = 0
@@ -116,16 +135,19 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
             ndh = nd.cpu().numpy()
             draws[h] = ndh
             if ess:
-                # requests finished at a check return a prefix of their draws
-                for v in np.unique(ndh):
-                    m = np.nonzero(ndh == v)[0]
-                    sel = smp[torch.from_numpy(m).to(smp.device), :, :int(v)].contiguous()
-                    e, _ = api.ess(sel)
-                    ess_out[h[m]] = e.mean(dim=1).cpu().numpy()
+                # the returned draws are checked after the loop, off the
+                # requests' critical path (a prefix of each request's draws
+                # for requests finished at a check)
+                kept.append((h, ndh, smp[:, :, :int(ndh.max())].clone()))
+                kept_bytes += kept[-1][2].numel() * kept[-1][2].element_size()
+                if kept_bytes > ESS_BATCH_BYTES:
+                    check_kept()
+                    kept_bytes = 0
         if progress and t_done > next_report:
             progress(f"[serve] t={t_done:.1f}s done={done}/{n} resident={resident} "
                      f"queued={arrived - queue_head}")
             next_report = t_done + 5.0
+    check_kept()
     wall = float(np.nanmax(fin) - arrivals[0]) if done else float("nan")
     return ServeResult(latency=lat, finish=fin, wall=wall, n_done=done, ticks=ticks,
                        max_resident=max_res, ess_mean=None if ess_out is None else ess_out,

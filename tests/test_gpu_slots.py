@@ -201,3 +201,49 @@ def test_slots_ess_target(bsi):
         assert np.array_equal(s1[0].cpu().numpy(), smp[:, :nd]), i
         assert np.array_equal(st1[0].cpu().numpy(), st), i
     assert early >= 1
+
+
+def test_serve_loop_ess_batches(bsi):
+    """The request loop's ESS of returned draws: every request completes
+    once, with a draw count at a check or at the cap, a finite mean ESS that
+    reaches the target for requests stopped early, and the same values
+    whether the kept draws are checked after every harvest or once after the
+    loop."""
+    import torch
+    from paper_2604_22048_amd import serve
+    _log("serve loop ESS batches")
+    sizes_srv = [25, 41]
+    n, P, C = 12, 4, 2
+    every, target, cap = 20, 45.0, 120
+    pool = {k: {} for k in ("stamps", "psf", "sigma", "ref", "init")}
+    for N in sizes_srv:
+        t, params, data, off = synth.make_population("uneven", n_gal=P, seed=90 + N,
+                                                     sizes=np.full(P, N))
+        init = synth.init_positions(t, params, data, off, C, seed=91 + N)
+        pool["stamps"][N] = torch.tensor(data).cuda().view(P, N * N)
+        pool["psf"][N] = t.psf_fwhm.astype(np.float32)
+        pool["sigma"][N] = t.sigma.astype(np.float32)
+        pool["ref"][N] = np.ascontiguousarray(params[:, 4:6].astype(np.float32))
+        pool["init"][N] = np.ascontiguousarray(init.astype(np.float32))
+    pool = serve.RequestPool(**pool)
+    sizes = np.random.default_rng(92).choice(np.array(sizes_srv), n)
+    cfg = bsi.HmcConfig(**dict(CFG, n_chains=C, n_samples=cap))
+    out = []
+    for batch_bytes in (1, 1 << 30):
+        old = serve.ESS_BATCH_BYTES
+        serve.ESS_BATCH_BYTES = batch_bytes
+        try:
+            srv = bsi.Slots(sizes_srv, cfg, hbm_budget=64 << 20, max_slots=5, ess_target=target,
+                            ess_every=every)
+            r = serve.serve(srv, pool, np.zeros(n), sizes, 7, time_limit=60.0, ess=True)
+            srv.close()
+        finally:
+            serve.ESS_BATCH_BYTES = old
+        assert r.n_done == n and np.all(np.isfinite(r.latency))
+        assert np.all(r.n_draws % every == 0) and np.all((r.n_draws >= every) & (r.n_draws <= cap))
+        assert np.all(np.isfinite(r.ess_mean))
+        early = r.n_draws < cap
+        assert np.all(r.ess_mean[early] >= target * (1 - 1e-3)), r.ess_mean[early]
+        out.append(r)
+    assert np.array_equal(out[0].n_draws, out[1].n_draws)
+    assert np.array_equal(out[0].ess_mean, out[1].ess_mean)
