@@ -473,6 +473,10 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
     out = {"rate_req_per_s": rate, "window_s": window_s, "n_requests": n_req, "completed": r.n_done,
            "galaxies_per_s": round(r.n_done / r.wall, 1), **lat_stats(r),
            "max_resident": r.max_resident, "ticks": r.ticks, "iters_per_tick": iters_per_tick,
+           "tick_ms": {"p50": round(float(np.percentile(r.tick_s, 50)) * 1e3, 3),
+                       "p99": round(float(np.percentile(r.tick_s, 99)) * 1e3, 3),
+                       "max": round(float(r.tick_s.max()) * 1e3, 1),
+                       "n_over_20ms": int(np.sum(r.tick_s > 0.02))},
            "warmup": cfg.warmup, "ess_target": ess_target, "ess_every": ess_every,
            "max_draws": n_draws, "leapfrog": cfg.leapfrog,
            "draws_median": float(np.median(r.n_draws[r.n_draws > 0])),

@@ -257,6 +257,8 @@ struct SlotArrays {
   int32_t* ndraw;     // [slot] draws returned once finished, 0 while running
   int32_t* done_q;    // [slot] requests finished at checks since the last poll
   int32_t* done_n;    // entries of done_q
+  float* ess6;        // [slot][6] each parameter's ESS at the request's current check
+  int32_t* ess_cnt;   // [slot] parameters whose ESS is in ess6 (reset to 0 by the last)
 };
 // stop0: the first stop of an admitted request (its first check, or W + S).
 hipError_t launch_slots_scatter(const SlotRecord* rec, const float* init_src, int n, int C, int stop0,

@@ -284,7 +284,7 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   auto arrays_bytes = [&](int64_t n) {
     return align_up(n * 8) * 3 + align_up(n * 4) * 2 + align_up(n * 8) + align_up(n * C * 24) +
            align_up(n * C * (int64_t)sizeof(ChainState)) + align_up(n * C * sv->S * 24) +
-           align_up(n * 4) * 3 + align_up(4);
+           align_up(n * 4) * 3 + align_up(4) + align_up(n * 24) + align_up(n * 4);
   };
   if (ms < 1 || arrays_bytes(ms) + max_var > budget) {
     delete sv;
@@ -320,6 +320,8 @@ int bsi_slots_create(bsi_handle h, const bsi_slots_cfg* cfg, bsi_stream stream, 
   sv->arr.ndraw = reinterpret_cast<int32_t*>(take(ms * 4));
   sv->arr.done_q = reinterpret_cast<int32_t*>(take(ms * 4));
   sv->arr.done_n = reinterpret_cast<int32_t*>(take(4));
+  sv->arr.ess6 = reinterpret_cast<float*>(take(ms * 24));
+  sv->arr.ess_cnt = reinterpret_cast<int32_t*>(take(ms * 4));
   sv->arena = p;
   sv->alloc.reset(arena_bytes);
   // upload staging: records, start positions, two slot lists per class, and

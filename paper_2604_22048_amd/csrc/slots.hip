@@ -23,6 +23,7 @@ slots_scatter_kernel(const SlotRecord* __restrict__ rec, const float* __restrict
     sa.uid[r.slot] = r.uid;
     sa.stop[r.slot] = stop0;
     sa.ndraw[r.slot] = 0;
+    sa.ess_cnt[r.slot] = 0;
   }
   const int nin = C * 6;
   for (int i = threadIdx.x; i < nin; i += blockDim.x)
@@ -65,40 +66,52 @@ slots_gather_kernel(const int32_t* __restrict__ list, int C, int S, const ChainS
   }
 }
 
-// One workgroup per listed request.  A request whose chains have reached its
-// stop W + n is checked there: it finishes with n draws when n = S or when
-// the mean over the six parameters of its ESS over draws [0, n) reaches the
-// target; otherwise its stop moves to W + min(n + every, S).  Requests still
-// running towards their stop, and finished ones, are left alone.  The
-// decision depends on the request's own draws only.
+// One workgroup per listed request and parameter.  A request whose chains
+// have reached its stop W + n is checked there: it finishes with n draws when
+// n = S or when the mean over the six parameters of its ESS over draws
+// [0, n) reaches the target; otherwise its stop moves to W + min(n + every,
+// S).  Requests still running towards their stop, and finished ones, are
+// left alone.  The six parameters' ESS are computed by six workgroups; the
+// last of them to finish (a per-request counter) adds them in parameter order
+// and decides.  The decision depends on the request's own draws only.
 __global__ void __launch_bounds__(256)
 slots_check_kernel(const int32_t* __restrict__ list, int C, int W, int S, int every, float target,
                    const ChainState* __restrict__ st, const float* __restrict__ samples, SlotArrays sa) {
   extern __shared__ double xs[];
   __shared__ EssShared es;
-  __shared__ int s_fin;
   const int slot = list[blockIdx.x];
+  const int par = blockIdx.y;
+  // stop, t and ndraw are not changed by this launch before every workgroup
+  // of the request has read them, so the six take the same branch
   const int stop = sa.stop[slot];
   if (st[(int64_t)slot * C].t < stop || sa.ndraw[slot] != 0) return;   // uniform in the block
   const int n = stop - W;
-  if (threadIdx.x == 0) s_fin = n >= S;
-  __syncthreads();
-  if (!s_fin) {
-    double sum = 0.0;                  // thread 0
-    for (int par = 0; par < 6; ++par) {
-      float e = 0.f, r = 0.f;
-      ess_one_param(samples + (int64_t)slot * C * S * 6, C, n, S, 6, par, xs, es, e, r);
-      sum += (double)e;
-    }
-    if (threadIdx.x == 0) s_fin = sum / 6.0 >= (double)target;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (s_fin) {
+  if (n >= S) {
+    // the draw cap: finished without an ESS
+    if (par == 0 && threadIdx.x == 0) {
       sa.ndraw[slot] = n;
       sa.done_q[atomicAdd(sa.done_n, 1)] = slot;
-    } else {
-      sa.stop[slot] = W + min(n + every, S);
+    }
+    return;
+  }
+  float e = 0.f, r = 0.f;
+  ess_one_param(samples + (int64_t)slot * C * S * 6, C, n, S, 6, par, xs, es, e, r);
+  if (threadIdx.x == 0) {
+    sa.ess6[(int64_t)slot * 6 + par] = e;
+    __threadfence();
+    if (atomicAdd(&sa.ess_cnt[slot], 1) == 5) {
+      __threadfence();
+      double sum = 0.0;
+      for (int q = 0; q < 6; ++q)
+        sum += (double)__hip_atomic_load(&sa.ess6[(int64_t)slot * 6 + q], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+      sa.ess_cnt[slot] = 0;
+      if (sum / 6.0 >= (double)target) {
+        sa.ndraw[slot] = n;
+        sa.done_q[atomicAdd(sa.done_n, 1)] = slot;
+      } else {
+        sa.stop[slot] = W + min(n + every, S);
+      }
     }
   }
 }
@@ -130,7 +143,7 @@ hipError_t launch_slots_check(const int32_t* list, int n, int C, int W, int S, i
   const size_t lds = slots_check_lds_bytes(C, S);
   (void)hipFuncSetAttribute((const void*)slots_check_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds);
-  hipLaunchKernelGGL(slots_check_kernel, dim3(n), dim3(256), lds, s, list, C, W, S, every, target, st,
+  hipLaunchKernelGGL(slots_check_kernel, dim3(n, 6), dim3(256), lds, s, list, C, W, S, every, target, st,
                      samples, sa);
   return hipGetLastError();
 }

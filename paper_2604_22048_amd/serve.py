@@ -18,7 +18,7 @@ import torch
 from . import api
 
 # finished requests' draws held on the device for the ESS check before a batch is checked
-ESS_BATCH_BYTES = 1 << 30
+ESS_BATCH_BYTES = 64 << 20
 
 
 @dataclass
@@ -62,6 +62,7 @@ class ServeResult:
     max_resident: int
     ess_mean: np.ndarray | None   # mean over the six properties, per completed request
     n_draws: np.ndarray           # draws per chain returned, per request (0 if not completed)
+    tick_s: np.ndarray | None = None   # duration of each loop turn that advanced, ESS bookkeeping included [s]
 
 
 def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.ndarray,
@@ -74,8 +75,8 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     for all resident requests, and collects the finished ones.  ess: also
     the ESS of each request's returned draws (mean over the six properties),
     computed off the requests' critical path: the finished requests' draws are
-    kept on the device and checked in batches (after the loop, or once they
-    pass ESS_BATCH_BYTES)."""
+    kept on the device and checked in batches (once they pass ESS_BATCH_BYTES,
+    and after the loop) on a side stream that the loop does not wait for."""
     n = arrivals.shape[0]
     ids = np.arange(n, dtype=np.uint64)
     slot = np.zeros(n, dtype=np.int64)
@@ -87,16 +88,25 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     fin = np.full(n, np.nan)
     ess_out = np.full(n, np.nan) if ess else None
     draws = np.zeros(n, dtype=np.int32)
-    kept = []              # (ids, draws, samples) of finished requests, for the ESS check
+    # finished requests' draws for the ESS check, by draw count: count -> [(ids, samples)]
+    kept: dict = {}
     kept_bytes = 0
+    side = torch.cuda.Stream(device=pool.stamps[int(sizes[0])].device) if ess and n else None
+    checked = []       # (ids, device ESS means) of the batches queued so far
+    in_use = []        # inputs of the batch on the side stream, held until it has run
 
     def check_kept():
-        for h, ndh, smp in kept:
-            for v in np.unique(ndh):
-                m = np.nonzero(ndh == v)[0]
-                sel = smp[torch.from_numpy(m).to(smp.device), :, :int(v)].contiguous()
-                e, _ = api.ess(sel)
-                ess_out[h[m]] = e.mean(dim=1).cpu().numpy()
+        # one ESS call per distinct draw count over everything kept, queued on
+        # a side stream so that the loop does not wait for it
+        side.synchronize()
+        in_use.clear()
+        side.wait_stream(torch.cuda.current_stream(side.device))
+        with torch.cuda.stream(side):
+            for v, parts in kept.items():
+                x = torch.cat([x for _, x in parts])
+                e, _ = api.ess(x)
+                checked.append((np.concatenate([h for h, _ in parts]), e.mean(dim=1)))
+        in_use.append(kept.copy())
         kept.clear()
 
     queue_head = 0
@@ -105,6 +115,7 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
     resident = 0
     max_res = 0
     next_report = 5.0
+    tick_s = []
     t0 = time.perf_counter()
     while done < n:
         now = time.perf_counter() - t0
@@ -135,20 +146,28 @@ def serve(srv: api.Slots, pool: RequestPool, arrivals: np.ndarray, sizes: np.nda
             ndh = nd.cpu().numpy()
             draws[h] = ndh
             if ess:
-                # the returned draws are checked after the loop, off the
-                # requests' critical path (a prefix of each request's draws
-                # for requests finished at a check)
-                kept.append((h, ndh, smp[:, :, :int(ndh.max())].clone()))
-                kept_bytes += kept[-1][2].numel() * kept[-1][2].element_size()
+                # the returned draws (a prefix of each request's draws for
+                # requests finished at a check) are checked in batches, off
+                # the requests' critical path
+                for v in np.unique(ndh):
+                    m = np.nonzero(ndh == v)[0]
+                    x = smp[torch.from_numpy(m).to(smp.device), :, :int(v)].contiguous()
+                    kept.setdefault(int(v), []).append((h[m], x))
+                    kept_bytes += x.numel() * x.element_size()
                 if kept_bytes > ESS_BATCH_BYTES:
                     check_kept()
                     kept_bytes = 0
+        tick_s.append(time.perf_counter() - t0 - now)
         if progress and t_done > next_report:
             progress(f"[serve] t={t_done:.1f}s done={done}/{n} resident={resident} "
                      f"queued={arrived - queue_head}")
             next_report = t_done + 5.0
-    check_kept()
+    if side is not None:
+        check_kept()
+        side.synchronize()
+        for h, em in checked:
+            ess_out[h] = em.cpu().numpy()
     wall = float(np.nanmax(fin) - arrivals[0]) if done else float("nan")
     return ServeResult(latency=lat, finish=fin, wall=wall, n_done=done, ticks=ticks,
                        max_resident=max_res, ess_mean=None if ess_out is None else ess_out,
-                       n_draws=draws)
+                       n_draws=draws, tick_s=np.array(tick_s))
