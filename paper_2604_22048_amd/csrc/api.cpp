@@ -271,8 +271,12 @@ int bsi_create(bsi_handle* out, int32_t device, const char* tune_cache) {
             hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_done, hipEventDisableTiming) == hipSuccess &&
             hipEventCreateWithFlags(&h->ev_stage, hipEventDisableTiming) == hipSuccess;
+  // the auxiliary streams do not synchronise implicitly with the null stream:
+  // a forked launch's branches are ordered by its events alone, so a branch
+  // left on a caller's null stream runs beside the others instead of
+  // holding them back until it ends
   for (int i = 0; ok && i < kAuxStreams; ++i)
-    ok = hipStreamCreate(&h->aux[i]) == hipSuccess &&
+    ok = hipStreamCreateWithFlags(&h->aux[i], hipStreamNonBlocking) == hipSuccess &&
          hipEventCreateWithFlags(&h->ev_join[i], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
     (void)hipGetLastError();
