@@ -427,14 +427,16 @@ def make_request_pool(api, torch, per_size, seed_offset=0):
     return serve.RequestPool(**P)
 
 
-def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, iters_per_tick=15,
-                budget=4 << 30, extra_rates=(), pace=True, split=4, ess_target=300.0, ess_every=60,
-                log=None, oracle=None):
+def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, iters_per_tick=60,
+                paced_iters_per_tick=15, budget=4 << 30, extra_rates=(), pace=True, split=4,
+                ess_target=300.0, ess_every=60, log=None, oracle=None):
     """Poisson request stream at `rate` for `window_s` seconds of arrivals
     (sizes 25/41/53/73/101 with weights .3/.3/.2/.15/.05, 1 chain, 300
     warmup iterations of 20 leapfrog steps, then draws until the request's
     ESS reaches ess_target at a check every ess_every draws, at most n_draws),
-    then the capacity: cap_requests requests all present at the start."""
+    then the capacity: cap_requests requests all present at the start.
+    The paced run advances paced_iters_per_tick base iterations per call (its
+    per-size counts are scaled from them), the others iters_per_tick."""
     from paper_2604_22048_amd import serve
     cfg = gen.CONFIGS["serving"]
     hc = api.HmcConfig(n_chains=1, n_leapfrog=cfg.leapfrog, n_warmup=cfg.warmup, n_samples=n_draws,
@@ -450,7 +452,8 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
         hc.waves_per_chain = wpc
         srv = api.Slots(list(SERVING_SIZES), hc, hbm_budget=budget, pace=paced, ess_target=ess_target,
                         ess_every=ess_every)
-        r = serve.serve(srv, pool, arr, sizes, iters_per_tick, ess=ess, progress=log)
+        r = serve.serve(srv, pool, arr, sizes, paced_iters_per_tick if paced else iters_per_tick, ess=ess,
+                        progress=log)
         srv.close()
         if log:
             log(f"[serve] {tag}: {r.n_done} requests in {r.wall:.2f} s")
@@ -498,7 +501,8 @@ def serving_leg(api, torch, rate, window_s, cap_requests, seed, n_draws=1500, it
     if pace:
         rp, sp = run(arr, f"{rate:.0f}/s paced", False, True)
         out["paced_by_size"] = {"galaxies_per_s": round(rp.n_done / rp.wall, 1), **lat_stats(rp),
-                                "ticks": rp.ticks, "p50_ms_by_size": by_size(rp, sp)}
+                                "ticks": rp.ticks, "iters_per_tick": paced_iters_per_tick,
+                                "p50_ms_by_size": by_size(rp, sp)}
     if split:
         # chains split over waves run on the default slot plans
         for N in SERVING_SIZES:
